@@ -1,0 +1,892 @@
+// C ABI of the solver library: context management, argument checks, and the
+// host-side drivers of the Krylov solvers. All arithmetic runs in the HIP
+// kernels of the other translation units; the host only sequences launches on
+// the context's stream, reads back one block of scalars per Krylov step and
+// solves the small triangular systems of GCR.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <exception>
+#include <functional>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace dfl {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess)
+        fail(e == hipErrorOutOfMemory ? DFL_ENOMEM : DFL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+using cd = std::complex<double>;
+
+// device scalar slots (doubles)
+constexpr int S_A1 = 0;      // 64 complex: first Gram-Schmidt pass
+constexpr int S_A2 = 128;    // 64 complex: second pass
+constexpr int S_B = 256;     // ||chi_k||^2
+constexpr int S_C = 258;     // (chi_k, rho)
+constexpr int S_R = 260;     // ||rho||^2
+constexpr int S_DOWN = 264;  // doubles read back per step
+constexpr int S_ALPHA = 512; // 64 complex: GCR solution coefficients
+constexpr int S_TOTAL = 1024;
+
+template <typename T> T* alloc_dev(dfl_ctx* c, size_t n)
+{
+    if (n == 0)
+        return nullptr;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess)
+        fail(DFL_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    c->alloc_bytes += n * sizeof(T);
+    return static_cast<T*>(p);
+}
+
+void free_all(dfl_ctx* c)
+{
+    void* ptrs[] = {c->U64, c->U32,  c->Ubf,  c->Phi, c->Phi32, c->A64, c->A32, c->xi,  c->chi,
+                    c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
+                    c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag};
+    for (void* p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    if (c->hscal)
+        (void)hipHostFree(c->hscal);
+}
+
+void check_blocks(const int dims[4], const int b[4], const char* what)
+{
+    for (int mu = 0; mu < 4; ++mu) {
+        if (b[mu] < 1 || dims[mu] % b[mu] != 0)
+            fail(DFL_EINVAL, std::string(what) + " block does not divide the lattice");
+        int nb = dims[mu] / b[mu];
+        if (nb < 2 || nb % 2 != 0)
+            fail(DFL_EINVAL, std::string(what) + " block count per direction must be even and >= 2");
+    }
+}
+
+void validate(const dfl_params& p)
+{
+    for (int mu = 0; mu < 4; ++mu)
+        if (p.dims[mu] < 2)
+            fail(DFL_EINVAL, "lattice extent must be >= 2 in every direction");
+    double V = (double)p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+    if (V * 12 > 2.0e9)
+        fail(DFL_EINVAL, "lattice too large for one device field");
+    check_blocks(p.dims, p.sap_block, "SAP");
+    check_blocks(p.dims, p.dfl_block, "deflation");
+    int vsb = p.sap_block[0] * p.sap_block[1] * p.sap_block[2] * p.sap_block[3];
+    if (vsb > 512)
+        fail(DFL_EINVAL, "SAP block volume must be <= 512 sites");
+    int vb = p.dfl_block[0] * p.dfl_block[1] * p.dfl_block[2] * p.dfl_block[3];
+    if (p.Ns < 1 || p.Ns > 64 || p.Ns > 12 * vb)
+        fail(DFL_EINVAL, "Ns must be in 1..min(64, 12*|deflation block|)");
+    if (p.ncy < 1 || p.nmr < 1)
+        fail(DFL_EINVAL, "ncy and nmr must be >= 1");
+    if (p.nkv < 1 || p.nkv > kMaxDot || p.little_nkv < 1 || p.little_nkv > kMaxDot)
+        fail(DFL_EINVAL, "nkv and little_nkv must be in 1..64");
+    if (p.n_inviter < 0 || p.maxiter < 1 || p.little_maxiter < 1 || p.nrhs_max < 1)
+        fail(DFL_EINVAL, "n_inviter >= 0, maxiter >= 1, little_maxiter >= 1, nrhs_max >= 1 required");
+    if (!(p.tol > 0.0) || !(p.little_tol_in > 0.0) || !(p.little_tol_out > 0.0))
+        fail(DFL_EINVAL, "tolerances must be positive");
+    if (!std::isfinite(p.m0) || !std::isfinite(p.m0_setup))
+        fail(DFL_EINVAL, "masses must be finite");
+    if (p.link_prec < DFL_F64 || p.link_prec > DFL_BF16)
+        fail(DFL_EINVAL, "link_prec must be F64, F32 or BF16");
+    if (p.sap_prec != DFL_F64 && p.sap_prec != DFL_F32)
+        fail(DFL_EINVAL, "sap_prec must be F64 or F32");
+    if (p.sap_prec == DFL_F64 && p.link_prec != DFL_F64)
+        fail(DFL_EINVAL, "FP64 SAP needs FP64 links");
+    if (p.little_prec != DFL_F64 && p.little_prec != DFL_F32)
+        fail(DFL_EINVAL, "little_prec must be F64 or F32");
+    if (p.solver < DFL_SOLVER_GCR || p.solver > DFL_SOLVER_DFL_SAP_GCR)
+        fail(DFL_EINVAL, "unknown solver");
+}
+
+Links64 links64(const dfl_ctx* c) { return Links64{c->U64, c->V}; }
+Links32 links32(const dfl_ctx* c) { return Links32{c->U32, c->V}; }
+LinksBF16 linksbf(const dfl_ctx* c) { return LinksBF16{c->Ubf, c->V}; }
+
+void need_gauge(const dfl_ctx* c)
+{
+    if (!c->have_gauge)
+        fail(DFL_ESTATE, "no gauge field: call dfl_set_gauge first");
+}
+void need_subspace(const dfl_ctx* c)
+{
+    if (!c->have_subspace)
+        fail(DFL_ESTATE, "no deflation subspace: call dfl_setup first");
+}
+void need_ctx(const dfl_ctx* c)
+{
+    if (!c)
+        fail(DFL_EINVAL, "null context");
+}
+void need_ptr(const void* p, const char* what)
+{
+    if (!p)
+        fail(DFL_EINVAL, std::string("null pointer: ") + what);
+}
+void need_nrhs(const dfl_ctx* c, int nrhs)
+{
+    if (nrhs < 1 || nrhs > c->p.nrhs_max)
+        fail(DFL_EINVAL, "nrhs must be in 1..nrhs_max");
+}
+
+void sync(dfl_ctx* c) { HIPCHECK(hipStreamSynchronize(c->stream)); }
+
+// copy the first n device scalars to the pinned host mirror and wait
+void download(dfl_ctx* c, int n)
+{
+    HIPCHECK(hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+// ||x||^2 to the host (synchronises)
+template <typename T> double host_norm2(dfl_ctx* c, const cpx<T>* x, long n)
+{
+    launch_norm2<T>(x, n, c->red, c->dscal + S_R, c->stream);
+    HIPCHECK(hipMemcpyAsync(c->hscal + S_R, c->dscal + S_R, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return c->hscal[S_R];
+}
+
+// ------------------------------------------------------------ operators
+
+void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0)
+{
+    launch_dirac64(c->g, links64(c), in, out, 1, m0, 0, 0, 0, c->stream);
+}
+
+// psi = M_sap rho (FP64 in and out; block solves in sap_prec)
+void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0)
+{
+    const long n = c->field_elems;
+    if (c->p.sap_prec == DFL_F64) {
+        launch_zero<double>(psi, n, c->stream);
+        for (int cy = 0; cy < c->p.ncy; ++cy)
+            for (int col = 0; col < 2; ++col)
+                launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, c->stream);
+        return;
+    }
+    launch_f64_to_f32(rho, c->s32a, n, c->stream);
+    launch_zero<float>(c->s32b, n, c->stream);
+    for (int cy = 0; cy < c->p.ncy; ++cy)
+        for (int col = 0; col < 2; ++col) {
+            if (c->p.link_prec == DFL_BF16)
+                launch_sap_colour_bf16(c->g, c->sg, linksbf(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col,
+                                       c->stream);
+            else
+                launch_sap_colour32(c->g, c->sg, links32(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, c->stream);
+        }
+    launch_f32_to_f64(c->s32b, psi, n, c->stream);
+}
+
+// ------------------------------------------------------------------ GCR
+//
+// Flexible restarted GCR (section 6.2): xi_k = M rho, chi_k = Op xi_k,
+// orthogonalised against chi_{<k} (classical Gram-Schmidt applied twice),
+// normalised, rho -= (chi_k, rho) chi_k. At the end of a cycle the
+// coefficients alpha solve the triangular system, x += sum alpha_k xi_k and
+// the residue is recomputed from scratch (appendix A.5).
+
+struct GcrVecs {
+    void* xi;    // nkv vectors, stride n
+    void* chi;   // nkv vectors, stride n
+    void* r;     // residue
+    void* x;     // solution accumulator
+};
+
+struct GcrResult {
+    int status;
+    int iters;
+    int restarts;
+    double rel;  // last recomputed relative residual
+};
+
+template <typename T>
+GcrResult gcr_run(dfl_ctx* c, long n, int nkv, int maxiter, double tol, double src_norm, GcrVecs v,
+                  const std::function<void(const cpx<T>*, cpx<T>*)>& precond,
+                  const std::function<void(const cpx<T>*, cpx<T>*)>& op,
+                  const std::function<void(const cpx<T>*, cpx<T>*)>& recompute_residual)
+{
+    cpx<T>* xi = static_cast<cpx<T>*>(v.xi);
+    cpx<T>* chi = static_cast<cpx<T>*>(v.chi);
+    cpx<T>* r = static_cast<cpx<T>*>(v.r);
+    cpx<T>* x = static_cast<cpx<T>*>(v.x);
+    GcrResult res{DFL_OK, 0, 0, 0.0};
+    launch_zero<T>(x, n, c->stream);
+    if (src_norm == 0.0)
+        return res;
+    // the caller has put the initial residue in r
+    double rn = std::sqrt(host_norm2<T>(c, r, n));
+    std::vector<cd> a((size_t)nkv * nkv), cc(nkv), alpha(nkv);
+    std::vector<double> b(nkv);
+    while (true) {
+        res.rel = rn / src_norm;
+        if (!std::isfinite(rn))
+            fail(DFL_ENONFINITE, "non-finite residual in GCR");
+        if (rn <= tol * src_norm)
+            return res;
+        if (res.iters >= maxiter) {
+            res.status = DFL_NOT_CONVERGED;
+            return res;
+        }
+        int k = 0;
+        while (k < nkv && res.iters < maxiter) {
+            cpx<T>* xk = xi + (long)k * n;
+            cpx<T>* ck = chi + (long)k * n;
+            precond(r, xk);
+            op(xk, ck);
+            if (k > 0) {
+                launch_multidot<T>(chi, n, k, ck, n, c->red, c->dscal + S_A1, c->stream);
+                launch_multiaxpy<T>(chi, n, k, c->dscal + S_A1, -1.0, ck, n, c->stream);
+                launch_multidot<T>(chi, n, k, ck, n, c->red, c->dscal + S_A2, c->stream);
+                launch_multiaxpy<T>(chi, n, k, c->dscal + S_A2, -1.0, ck, n, c->stream);
+            }
+            launch_norm2<T>(ck, n, c->red, c->dscal + S_B, c->stream);
+            launch_scale_invsqrt<T>(ck, n, c->dscal + S_B, c->stream);
+            launch_multidot<T>(ck, n, 1, r, n, c->red, c->dscal + S_C, c->stream);
+            launch_multiaxpy<T>(ck, n, 1, c->dscal + S_C, -1.0, r, n, c->stream);
+            launch_norm2<T>(r, n, c->red, c->dscal + S_R, c->stream);
+            download(c, S_DOWN);
+            const double* h = c->hscal;
+            for (int j = 0; j < k; ++j)
+                a[(size_t)j * nkv + k] = cd(h[S_A1 + 2 * j] + h[S_A2 + 2 * j], h[S_A1 + 2 * j + 1] + h[S_A2 + 2 * j + 1]);
+            b[k] = std::sqrt(h[S_B]);
+            cc[k] = cd(h[S_C], h[S_C + 1]);
+            rn = std::sqrt(h[S_R]);
+            if (!(b[k] > 0.0) || !std::isfinite(b[k]))
+                fail(b[k] == 0.0 ? DFL_ESINGULAR : DFL_ENONFINITE, "GCR breakdown: zero or non-finite Krylov image");
+            ++k;
+            ++res.iters;
+            if (rn <= tol * src_norm)
+                break;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            cd s = cc[i];
+            for (int j = i + 1; j < k; ++j)
+                s -= a[(size_t)i * nkv + j] * alpha[j];
+            alpha[i] = s / b[i];
+        }
+        double* up = c->hscal + S_ALPHA;
+        for (int i = 0; i < k; ++i) {
+            up[2 * i] = alpha[i].real();
+            up[2 * i + 1] = alpha[i].imag();
+        }
+        HIPCHECK(hipMemcpyAsync(c->dscal + S_ALPHA, up, sizeof(double) * 2 * k, hipMemcpyHostToDevice, c->stream));
+        launch_multiaxpy<T>(xi, n, k, c->dscal + S_ALPHA, 1.0, x, n, c->stream);
+        recompute_residual(x, r);
+        rn = std::sqrt(host_norm2<T>(c, r, n));
+        ++res.restarts;
+    }
+}
+
+// ---------------------------------------------------------- little solve
+
+// v = A^{-1} w to ||w - A v|| <= tol ||w|| (eq. (6.1)); FP64 in and out.
+int little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec prec, int* iters)
+{
+    const long n = (long)c->g.Nb * c->p.Ns;
+    const Geom& g = c->g;
+    const int Ns = c->p.Ns;
+    GcrResult r;
+    if (prec == DFL_F64) {
+        double wn = std::sqrt(host_norm2<double>(c, w, n));
+        launch_copy<double>(w, static_cast<c64*>(c->lr), n, c->stream);
+        GcrVecs vv{c->lxi, c->lchi, c->lr, v};
+        const c64* A = c->A64;
+        c64* lt = static_cast<c64*>(c->lt);
+        r = gcr_run<double>(
+            c, n, c->p.little_nkv, c->p.little_maxiter, tol, wn, vv,
+            [&](const c64* a, c64* b) { launch_copy<double>(a, b, n, c->stream); },
+            [&](const c64* a, c64* b) { launch_little_apply<double>(g, A, Ns, a, b, c->stream); },
+            [&](const c64* x, c64* rr) {
+                launch_little_apply<double>(g, A, Ns, x, lt, c->stream);
+                launch_sub<double>(w, lt, rr, n, c->stream);
+            });
+    } else {
+        c32* w32 = c->lw32;
+        c32* v32 = c->lx32;
+        launch_f64_to_f32(w, w32, n, c->stream);
+        double wn = std::sqrt(host_norm2<float>(c, w32, n));
+        launch_copy<float>(w32, static_cast<c32*>(c->lr), n, c->stream);
+        GcrVecs vv{c->lxi, c->lchi, c->lr, v32};
+        const c32* A = c->A32;
+        c32* lt = static_cast<c32*>(c->lt);
+        r = gcr_run<float>(
+            c, n, c->p.little_nkv, c->p.little_maxiter, tol, wn, vv,
+            [&](const c32* a, c32* b) { launch_copy<float>(a, b, n, c->stream); },
+            [&](const c32* a, c32* b) { launch_little_apply<float>(g, A, Ns, a, b, c->stream); },
+            [&](const c32* x, c32* rr) {
+                launch_little_apply<float>(g, A, Ns, x, lt, c->stream);
+                launch_sub<float>(w32, lt, rr, n, c->stream);
+            });
+        launch_f32_to_f64(v32, v, n, c->stream);
+    }
+    if (iters)
+        *iters = r.iters;
+    return r.status;
+}
+
+struct SolveStats {
+    int n_little = 0;
+    int n_little_solves = 0;
+};
+
+// out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term); out may not alias in
+void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, SolveStats* st)
+{
+    c64* w = static_cast<c64*>(c->lw);
+    c64* x = static_cast<c64*>(c->lx);
+    launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, c->stream);
+    int it = 0;
+    little_solve_impl(c, w, x, tol, prec, &it);
+    if (st) {
+        st->n_little += it;
+        st->n_little_solves += 1;
+    }
+    launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, c->stream);
+}
+
+// out = P_L in = in - D coarse(in)   (eq. (3.3)); uses t3 and the little buffers
+void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, SolveStats* st, c64* tmpA, c64* tmpB)
+{
+    coarse(c, in, tmpA, tol, prec, st);
+    dirac64(c, tmpA, tmpB, c->p.m0);
+    launch_sub<double>(in, tmpB, out, c->field_elems, c->stream);
+}
+
+}  // namespace
+}  // namespace dfl
+
+using namespace dfl;
+
+#define API_BEGIN try {
+#define API_END                                                                                                    \
+    return DFL_OK;                                                                                                 \
+    }                                                                                                              \
+    catch (const dfl::Error& e)                                                                                    \
+    {                                                                                                              \
+        dfl::g_last_error = e.msg;                                                                                 \
+        return e.code;                                                                                             \
+    }                                                                                                              \
+    catch (const std::bad_alloc&)                                                                                  \
+    {                                                                                                              \
+        dfl::g_last_error = "host allocation failed";                                                             \
+        return DFL_ENOMEM;                                                                                         \
+    }                                                                                                              \
+    catch (...)                                                                                                    \
+    {                                                                                                              \
+        dfl::g_last_error = "unexpected internal error";                                                          \
+        return DFL_EHIP;                                                                                           \
+    }
+
+extern "C" {
+
+void dfl_default_params(dfl_params* p)
+{
+    if (!p)
+        return;
+    std::memset(p, 0, sizeof(*p));
+    for (int mu = 0; mu < 4; ++mu) {
+        p->sap_block[mu] = 4;
+        p->dfl_block[mu] = 4;
+    }
+    p->Ns = 20;
+    p->ncy = 5;
+    p->nmr = 4;
+    p->nkv = 16;
+    p->n_inviter = 3;
+    p->maxiter = 1000;
+    p->nrhs_max = 1;
+    p->little_nkv = 32;
+    p->little_maxiter = 2000;
+    p->solver = DFL_SOLVER_DFL_SAP_GCR;
+    p->m0 = 0.0;
+    p->m0_setup = 0.0;
+    p->tol = 1e-10;
+    p->little_tol_in = 1e-6;
+    p->little_tol_out = 1e-12;
+    p->link_prec = DFL_F64;
+    p->sap_prec = DFL_F64;
+    p->little_prec = DFL_F64;
+}
+
+const char* dfl_last_error(void) { return dfl::g_last_error.c_str(); }
+
+int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
+{
+    dfl_ctx* c = nullptr;
+    API_BEGIN
+    need_ptr(out, "ctx");
+    need_ptr(p, "params");
+    *out = nullptr;
+    validate(*p);
+    c = new dfl_ctx();
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    HIPCHECK(hipGetDevice(&c->device));
+    c->g = make_geom(p->dims, p->dfl_block);
+    c->V = c->g.V;
+    c->field_elems = 12 * c->V;
+    SapGeom& sg = c->sg;
+    for (int mu = 0; mu < 4; ++mu) {
+        sg.sb[mu] = p->sap_block[mu];
+        sg.nsb[mu] = p->dims[mu] / p->sap_block[mu];
+    }
+    sg.lstr[3] = 1;
+    for (int mu = 2; mu >= 0; --mu)
+        sg.lstr[mu] = sg.lstr[mu + 1] * sg.sb[mu + 1];
+    sg.Vsb = sg.sb[0] * sg.sb[1] * sg.sb[2] * sg.sb[3];
+    sg.n_per_colour = sg.nsb[0] * sg.nsb[1] * sg.nsb[2] * sg.nsb[3] / 2;
+
+    const long V = c->V, F = c->field_elems;
+    const long N = (long)c->g.Nb * p->Ns;
+    try {
+        c->U64 = alloc_dev<c64>(c, (size_t)36 * V);
+        c->U32 = alloc_dev<c32>(c, (size_t)24 * V);
+        c->Ubf = alloc_dev<uint32_t>(c, (size_t)24 * V);
+        c->Phi = alloc_dev<c64>(c, (size_t)p->Ns * F);
+        c->A64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
+        c->A32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
+        c->xi = alloc_dev<c64>(c, (size_t)p->nkv * F);
+        c->chi = alloc_dev<c64>(c, (size_t)p->nkv * F);
+        c->rho = alloc_dev<c64>(c, F);
+        c->acc = alloc_dev<c64>(c, F);
+        c->t1 = alloc_dev<c64>(c, F);
+        c->t2 = alloc_dev<c64>(c, F);
+        c->t3 = alloc_dev<c64>(c, F);
+        c->s32a = alloc_dev<c32>(c, F);
+        c->s32b = alloc_dev<c32>(c, F);
+        c->s32c = alloc_dev<c32>(c, F);
+        c->lxi = alloc_dev<c64>(c, (size_t)p->little_nkv * N);
+        c->lchi = alloc_dev<c64>(c, (size_t)p->little_nkv * N);
+        c->lr = alloc_dev<c64>(c, N);
+        c->lx = alloc_dev<c64>(c, N);
+        c->lw = alloc_dev<c64>(c, N);
+        c->lt = alloc_dev<c64>(c, N);
+        c->lw32 = alloc_dev<c32>(c, N);
+        c->lx32 = alloc_dev<c32>(c, N);
+        c->red = alloc_dev<double>(c, (size_t)kMaxDot * kRedBlocks * 2);
+        c->dscal = alloc_dev<double>(c, S_TOTAL);
+        c->dflag = alloc_dev<int>(c, 4);
+        HIPCHECK(hipHostMalloc((void**)&c->hscal, sizeof(double) * S_TOTAL, hipHostMallocDefault));
+        HIPCHECK(hipMemsetAsync(c->dscal, 0, sizeof(double) * S_TOTAL, c->stream));
+        HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
+        sync(c);
+    } catch (...) {
+        free_all(c);
+        delete c;
+        throw;
+    }
+    *out = c;
+    API_END
+}
+
+int dfl_destroy(dfl_ctx* c)
+{
+    API_BEGIN
+    if (!c)
+        return DFL_OK;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    API_END
+}
+
+long long dfl_field_bytes(const dfl_ctx* c, dfl_prec prec)
+{
+    if (!c)
+        return -1;
+    return (long long)c->field_elems * (prec == DFL_F64 ? 16 : 8);
+}
+
+int dfl_num_blocks(const dfl_ctx* c) { return c ? c->g.Nb : -1; }
+
+int dfl_set_mass(dfl_ctx* c, double m0)
+{
+    API_BEGIN
+    need_ctx(c);
+    if (!std::isfinite(m0))
+        fail(DFL_EINVAL, "mass must be finite");
+    c->p.m0 = m0;
+    if (c->have_subspace && m0 != c->m0_A) {
+        // the basis is orthonormal, so A(m0') = A(m0) + (m0' - m0) 1
+        launch_little_shift(c->g, c->A64, c->p.Ns, m0 - c->m0_A, c->stream);
+        launch_c64_to_c32(c->A64, c->A32, (long)c->g.Nb * 9 * c->p.Ns * c->p.Ns, c->stream);
+        c->m0_A = m0;
+    }
+    API_END
+}
+
+int dfl_set_gauge(dfl_ctx* c, const double* U)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(U, "U");
+    launch_pack_gauge(c->g, reinterpret_cast<const c64*>(U), c->U64, c->U32, c->Ubf, c->stream);
+    HIPCHECK(hipGetLastError());
+    c->have_gauge = true;
+    c->have_subspace = false;
+    API_END
+}
+
+int dfl_pack(dfl_ctx* c, const double* canon, void* nat, int nrhs, dfl_prec prec)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(canon, "canon");
+    need_ptr(nat, "native");
+    if (nrhs < 1)
+        fail(DFL_EINVAL, "nrhs must be >= 1");
+    if (prec == DFL_F64)
+        launch_pack_field64(c->g, reinterpret_cast<const c64*>(canon), static_cast<c64*>(nat), nrhs, c->stream);
+    else if (prec == DFL_F32)
+        launch_pack_field32(c->g, reinterpret_cast<const c64*>(canon), static_cast<c32*>(nat), nrhs, c->stream);
+    else
+        fail(DFL_EINVAL, "fields are F64 or F32");
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int dfl_unpack(dfl_ctx* c, const void* nat, double* canon, int nrhs, dfl_prec prec)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(canon, "canon");
+    need_ptr(nat, "native");
+    if (nrhs < 1)
+        fail(DFL_EINVAL, "nrhs must be >= 1");
+    if (prec == DFL_F64)
+        launch_unpack_field64(c->g, static_cast<const c64*>(nat), reinterpret_cast<c64*>(canon), nrhs, c->stream);
+    else if (prec == DFL_F32)
+        launch_unpack_field32(c->g, static_cast<const c32*>(nat), reinterpret_cast<c64*>(canon), nrhs, c->stream);
+    else
+        fail(DFL_EINVAL, "fields are F64 or F32");
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int dirac_apply(dfl_ctx* c, const void* psi, void* out, int nrhs, dfl_prec prec)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(psi, "psi");
+    need_ptr(out, "out");
+    need_gauge(c);
+    need_nrhs(c, nrhs);
+    if (psi == out)
+        fail(DFL_EINVAL, "psi and out must not overlap");
+    if (prec == DFL_F64)
+        launch_dirac64(c->g, links64(c), static_cast<const c64*>(psi), static_cast<c64*>(out), nrhs, c->p.m0, 0, 0,
+                       0, c->stream);
+    else if (prec == DFL_F32 && c->p.link_prec == DFL_BF16)
+        launch_dirac_bf16(c->g, linksbf(c), static_cast<const c32*>(psi), static_cast<c32*>(out), nrhs,
+                          (float)c->p.m0, c->stream);
+    else if (prec == DFL_F32)
+        launch_dirac32(c->g, links32(c), static_cast<const c32*>(psi), static_cast<c32*>(out), nrhs, (float)c->p.m0,
+                       c->stream);
+    else
+        fail(DFL_EINVAL, "dirac_apply precision must be F64 or F32");
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int sap_precond(dfl_ctx* c, const void* rho, void* psi, int nrhs)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(rho, "rho");
+    need_ptr(psi, "psi");
+    need_gauge(c);
+    need_nrhs(c, nrhs);
+    if (rho == psi)
+        fail(DFL_EINVAL, "rho and psi must not overlap");
+    for (int r = 0; r < nrhs; ++r)
+        sap_apply(c, static_cast<const c64*>(rho) + r * c->field_elems, static_cast<c64*>(psi) + r * c->field_elems,
+                  c->p.m0);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int dfl_setup(dfl_ctx* c, const void* init, int n_init)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(init, "init fields (the caller draws the random start fields)");
+    need_gauge(c);
+    if (n_init != c->p.Ns)
+        fail(DFL_EINVAL, "n_init must equal Ns");
+    const long F = c->field_elems;
+    const int Ns = c->p.Ns;
+    c->have_subspace = false;
+    HIPCHECK(hipMemcpyAsync(c->Phi, init, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
+    for (int l = 0; l < Ns; ++l) {
+        c64* f = c->Phi + (long)l * F;
+        launch_finite_check<double>(f, F, c->dflag, c->stream);
+        launch_norm2<double>(f, F, c->red, c->dscal + S_B, c->stream);
+        launch_scale_invsqrt<double>(f, F, c->dscal + S_B, c->stream);
+    }
+    // inverse iteration, eq. (5.1): psi_l <- M_sap psi_l, normalised
+    for (int step = 0; step < c->p.n_inviter; ++step)
+        for (int l = 0; l < Ns; ++l) {
+            c64* f = c->Phi + (long)l * F;
+            sap_apply(c, f, c->t1, c->p.m0_setup);
+            launch_copy<double>(c->t1, f, F, c->stream);
+            launch_norm2<double>(f, F, c->red, c->dscal + S_B, c->stream);
+            launch_scale_invsqrt<double>(f, F, c->dscal + S_B, c->stream);
+        }
+    // block restriction and Gram-Schmidt, eq. (4.2)
+    launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->stream);
+    // little operator, eq. (A.1): block-diagonal part and the eight face hops
+    const long nA = (long)c->g.Nb * 9 * Ns * Ns;
+    for (int l = 0; l < Ns; ++l) {
+        const c64* f = c->Phi + (long)l * F;
+        launch_dirac64(c->g, links64(c), f, c->t1, 1, c->p.m0, 1, 0, 0, c->stream);
+        launch_little_column64(c->g, c->Phi, Ns, c->t1, c->A64, 0, l, c->stream);
+        for (int d = 1; d < 9; ++d) {
+            int mu = (d - 1) / 2;
+            int dir = (d & 1) ? +1 : -1;
+            launch_dirac64(c->g, links64(c), f, c->t1, 1, 0.0, 2, mu, dir, c->stream);
+            launch_little_column64(c->g, c->Phi, Ns, c->t1, c->A64, d, l, c->stream);
+        }
+    }
+    launch_c64_to_c32(c->A64, c->A32, nA, c->stream);
+    c->m0_A = c->p.m0;
+    int flag[4];
+    HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (flag[0] & 1)
+        fail(DFL_ENONFINITE, "non-finite entries in the start fields");
+    if (flag[0] & 2)
+        fail(DFL_ESINGULAR, "block Gram-Schmidt lost rank: the start fields are linearly dependent on a block");
+    c->have_subspace = true;
+    API_END
+}
+
+int dfl_get_basis(dfl_ctx* c, void* phi)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(phi, "phi");
+    need_subspace(c);
+    HIPCHECK(hipMemcpyAsync(phi, c->Phi, sizeof(c64) * c->field_elems * c->p.Ns, hipMemcpyDeviceToDevice,
+                            c->stream));
+    API_END
+}
+
+int dfl_get_little(dfl_ctx* c, double* A)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(A, "A");
+    need_subspace(c);
+    HIPCHECK(hipMemcpyAsync(A, c->A64, sizeof(c64) * c->g.Nb * 9 * c->p.Ns * c->p.Ns, hipMemcpyDeviceToDevice,
+                            c->stream));
+    API_END
+}
+
+int little_dirac_apply(dfl_ctx* c, const void* v, void* w, int nrhs, dfl_prec prec)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(v, "v");
+    need_ptr(w, "w");
+    need_subspace(c);
+    need_nrhs(c, nrhs);
+    if (v == w)
+        fail(DFL_EINVAL, "v and w must not overlap");
+    const long n = (long)c->g.Nb * c->p.Ns;
+    for (int r = 0; r < nrhs; ++r) {
+        if (prec == DFL_F64)
+            launch_little_apply<double>(c->g, c->A64, c->p.Ns, static_cast<const c64*>(v) + r * n,
+                                        static_cast<c64*>(w) + r * n, c->stream);
+        else if (prec == DFL_F32)
+            launch_little_apply<float>(c->g, c->A32, c->p.Ns, static_cast<const c32*>(v) + r * n,
+                                       static_cast<c32*>(w) + r * n, c->stream);
+        else
+            fail(DFL_EINVAL, "little vectors are F64 or F32");
+    }
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int little_solve(dfl_ctx* c, const void* w, void* v, double tol, int* iters)
+{
+    int st = DFL_OK;
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(w, "w");
+    need_ptr(v, "v");
+    need_subspace(c);
+    if (!(tol > 0.0))
+        fail(DFL_EINVAL, "tol must be positive");
+    st = little_solve_impl(c, static_cast<const c64*>(w), static_cast<c64*>(v), tol, DFL_F64, iters);
+    sync(c);
+    if (st != DFL_OK) {
+        g_last_error = "little solve did not converge";
+        return st;
+    }
+    API_END
+}
+
+int deflate_project(dfl_ctx* c, dfl_proj which, const void* in, void* out, int nrhs)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(in, "in");
+    need_ptr(out, "out");
+    need_subspace(c);
+    need_nrhs(c, nrhs);
+    if (in == out)
+        fail(DFL_EINVAL, "in and out must not overlap");
+    const long F = c->field_elems;
+    const double tol = c->p.little_tol_out;
+    for (int r = 0; r < nrhs; ++r) {
+        const c64* x = static_cast<const c64*>(in) + r * F;
+        c64* y = static_cast<c64*>(out) + r * F;
+        switch (which) {
+        case DFL_PROJ_PL:
+            apply_PL(c, x, y, tol, DFL_F64, nullptr, c->t1, c->t2);
+            break;
+        case DFL_PROJ_PR:
+            dirac64(c, x, c->t1, c->p.m0);
+            coarse(c, c->t1, c->t2, tol, DFL_F64, nullptr);
+            launch_sub<double>(x, c->t2, y, F, c->stream);
+            break;
+        case DFL_PROJ_P:
+            launch_restrict64(c->g, c->Phi, c->p.Ns, x, static_cast<c64*>(c->lw), c->stream);
+            launch_prolong64(c->g, c->Phi, c->p.Ns, static_cast<c64*>(c->lw), y, c->stream);
+            break;
+        case DFL_PROJ_COARSE:
+            coarse(c, x, y, tol, DFL_F64, nullptr);
+            break;
+        default:
+            fail(DFL_EINVAL, "unknown projector");
+        }
+    }
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
+{
+    int worst = DFL_OK;
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(eta_v, "eta");
+    need_ptr(psi_v, "psi");
+    need_gauge(c);
+    need_nrhs(c, nrhs);
+    if (eta_v == psi_v)
+        fail(DFL_EINVAL, "eta and psi must not overlap");
+    const bool deflate = c->p.solver == DFL_SOLVER_DFL_SAP_GCR;
+    const bool use_sap = c->p.solver != DFL_SOLVER_GCR;
+    if (deflate)
+        need_subspace(c);
+    const long F = c->field_elems;
+    const double m0 = c->p.m0;
+    for (int rhs = 0; rhs < nrhs; ++rhs) {
+        auto t0 = std::chrono::steady_clock::now();
+        const c64* eta = static_cast<const c64*>(eta_v) + rhs * F;
+        c64* psi = static_cast<c64*>(psi_v) + rhs * F;
+        HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+        launch_finite_check<double>(eta, F, c->dflag, c->stream);
+        int flag = 0;
+        HIPCHECK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        double eta_n = std::sqrt(host_norm2<double>(c, eta, F));
+        if (flag)
+            fail(DFL_ENONFINITE, "non-finite entries in the source");
+        SolveStats st;
+        // initial residue: P_L eta (deflated) or eta
+        if (deflate)
+            apply_PL(c, eta, c->rho, c->p.little_tol_out, DFL_F64, &st, c->t1, c->t2);
+        else
+            launch_copy<double>(eta, c->rho, F, c->stream);
+        GcrVecs v{c->xi, c->chi, c->rho, c->acc};
+        const dfl_prec lp = c->p.little_prec;
+        auto precond = [&](const c64* r, c64* x) {
+            if (use_sap)
+                sap_apply(c, r, x, m0);
+            else
+                launch_copy<double>(r, x, F, c->stream);
+        };
+        auto op = [&](const c64* x, c64* y) {
+            if (deflate) {
+                dirac64(c, x, c->t3, m0);
+                apply_PL(c, c->t3, y, c->p.little_tol_in, lp, &st, c->t1, c->t2);
+            } else {
+                dirac64(c, x, y, m0);
+            }
+        };
+        auto recompute = [&](const c64* x, c64* r) {
+            dirac64(c, x, c->t1, m0);
+            if (deflate) {
+                launch_sub<double>(eta, c->t1, c->t3, F, c->stream);
+                apply_PL(c, c->t3, r, c->p.little_tol_out, DFL_F64, &st, c->t1, c->t2);
+            } else {
+                launch_sub<double>(eta, c->t1, r, F, c->stream);
+            }
+        };
+        GcrResult res = gcr_run<double>(c, F, c->p.nkv, c->p.maxiter, c->p.tol, eta_n, v, precond, op, recompute);
+        // final solution: psi = acc + Phi A^-1 Phi^+ (eta - D acc)   (eq. (3.10) with P_R)
+        if (deflate) {
+            dirac64(c, c->acc, c->t1, m0);
+            launch_sub<double>(eta, c->t1, c->t3, F, c->stream);
+            coarse(c, c->t3, c->t1, c->p.little_tol_out, DFL_F64, &st);
+            launch_copy<double>(c->acc, psi, F, c->stream);
+            // psi += t1 : coefficient 1 from a device scalar
+            c->hscal[S_ALPHA] = 1.0;
+            c->hscal[S_ALPHA + 1] = 0.0;
+            HIPCHECK(hipMemcpyAsync(c->dscal + S_ALPHA, c->hscal + S_ALPHA, sizeof(double) * 2,
+                                    hipMemcpyHostToDevice, c->stream));
+            launch_multiaxpy<double>(c->t1, F, 1, c->dscal + S_ALPHA, 1.0, psi, F, c->stream);
+        } else {
+            launch_copy<double>(c->acc, psi, F, c->stream);
+        }
+        // true residual in FP64
+        dirac64(c, psi, c->t1, m0);
+        launch_sub<double>(eta, c->t1, c->t2, F, c->stream);
+        double rr = std::sqrt(host_norm2<double>(c, c->t2, F));
+        auto t1 = std::chrono::steady_clock::now();
+        int status = res.status;
+        double rel = eta_n > 0.0 ? rr / eta_n : 0.0;
+        if (status == DFL_OK && rel > c->p.tol)
+            status = DFL_NOT_CONVERGED;
+        if (status != DFL_OK)
+            worst = status;
+        if (info) {
+            info->status = status;
+            info->n_gcr = res.iters;
+            info->n_restarts = res.restarts;
+            info->n_little = st.n_little;
+            info->n_little_solves = st.n_little_solves;
+            info->rel_residual = rel;
+            info->t_solve = std::chrono::duration<double>(t1 - t0).count();
+        }
+    }
+    if (worst != DFL_OK) {
+        g_last_error = "solve: tolerance not reached within maxiter";
+        return worst;
+    }
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Vector kernels of the Krylov solvers: copies, fused multi-dot products,
+// multi-axpy with coefficients read from device memory, norms.
+//
+// Reductions are two-pass with a fixed grid (kRedBlocks workgroups, grid-
+// stride loops) and a fixed summation tree, accumulated in FP64, so results
+// are bit-reproducible run to run and independent of stream timing.
+#include "internal.h"
+
+namespace dfl {
+
+namespace {
+
+constexpr int kChunk = 8;  // vectors per pass of the multi-dot
+
+template <typename T> __global__ __launch_bounds__(256) void k_zero(cpx<T>* x, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = cpx<T>{0, 0};
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_copy(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sub(const cpx<T>* __restrict__ x, const cpx<T>* __restrict__ y,
+                                             cpx<T>* __restrict__ z, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        z[i] = cpx<T>{x[i].re - y[i].re, x[i].im - y[i].im};
+}
+
+// partial[(j0 + j)*2*kRedBlocks + 2*blockIdx + {0,1}] = this workgroup's share of (X_j, y)
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_multidot_partial(const cpx<T>* __restrict__ X, long stride, int j0,
+                                                                  int m, const cpx<T>* __restrict__ y, long n,
+                                                                  double* __restrict__ partial)
+{
+    __shared__ double sh[2 * kChunk][kRedThreads / 64];
+    double re[kChunk], im[kChunk];
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j)
+        re[j] = im[j] = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        cpx<T> b = y[i];
+        double br = (double)b.re, bi = (double)b.im;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            if (j < m) {
+                cpx<T> a = X[(long)(j0 + j) * stride + i];
+                double ar = (double)a.re, ai = (double)a.im;
+                re[j] += ar * br + ai * bi;
+                im[j] += ar * bi - ai * br;
+            }
+        }
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+        double a = wave_sum(re[j]);
+        double b = wave_sum(im[j]);
+        if (lane == 0) {
+            sh[2 * j][wid] = a;
+            sh[2 * j + 1][wid] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * m) {
+        double t = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w)
+            t += sh[threadIdx.x][w];
+        int j = threadIdx.x >> 1, c = threadIdx.x & 1;
+        partial[((long)(j0 + j) * kRedBlocks + blockIdx.x) * 2 + c] = t;
+    }
+}
+
+// dst[2j + c] = sum over workgroups of partial for j < m (fixed order)
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int m,
+                                                         double* __restrict__ dst)
+{
+    __shared__ double sh[4];
+    for (int jc = 0; jc < 2 * m; ++jc) {
+        int j = jc >> 1, c = jc & 1;
+        double t = 0.0;
+        for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x)
+            t += partial[((long)j * kRedBlocks + b) * 2 + c];
+        t = block_sum(t, sh);
+        if (threadIdx.x == 0)
+            dst[jc] = t;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_norm2_partial(const cpx<T>* __restrict__ x, long n,
+                                                               double* __restrict__ partial)
+{
+    __shared__ double sh[4];
+    double t = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double a = (double)x[i].re, b = (double)x[i].im;
+        t += a * a + b * b;
+    }
+    t = block_sum(t, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = t;
+        partial[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_multiaxpy(const cpx<T>* __restrict__ X, long stride, int m,
+                                                   const double* __restrict__ coef, double sign,
+                                                   cpx<T>* __restrict__ y, long n)
+{
+    __shared__ double c[2 * kMaxDot];
+    for (int j = threadIdx.x; j < 2 * m; j += blockDim.x)
+        c[j] = sign * coef[j];
+    __syncthreads();
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double yr = (double)y[i].re, yi = (double)y[i].im;
+        for (int j = 0; j < m; ++j) {
+            cpx<T> a = X[(long)j * stride + i];
+            double ar = (double)a.re, ai = (double)a.im;
+            yr += c[2 * j] * ar - c[2 * j + 1] * ai;
+            yi += c[2 * j] * ai + c[2 * j + 1] * ar;
+        }
+        y[i] = cpx<T>{(T)yr, (T)yi};
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_invsqrt(cpx<T>* __restrict__ x, long n, const double* __restrict__ nrm2)
+{
+    double f = 1.0 / sqrt(*nrm2);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        x[i].re = (T)((double)x[i].re * f);
+        x[i].im = (T)((double)x[i].im * f);
+    }
+}
+
+__global__ void k_add_scalars(const double* a, const double* b, double* dst, int m)
+{
+    for (int i = threadIdx.x; i < 2 * m; i += blockDim.x)
+        dst[i] = a[i] + b[i];
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_finite(const cpx<T>* __restrict__ x, long n, int* flag)
+{
+    bool bad = false;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double a = (double)x[i].re, b = (double)x[i].im;
+        bad |= !isfinite(a) || !isfinite(b);
+    }
+    if (bad)
+        atomicOr(flag, 1);
+}
+
+inline unsigned stream_grid(long n)
+{
+    long g = (n + 255) / 256;
+    if (g > 2048)
+        g = 2048;
+    if (g < 1)
+        g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+template <typename T> void launch_zero(cpx<T>* x, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, n);
+}
+template <typename T> void launch_copy(const cpx<T>* x, cpx<T>* y, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, y, n);
+}
+template <typename T> void launch_sub(const cpx<T>* x, const cpx<T>* y, cpx<T>* z, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, y, z, n);
+}
+
+template <typename T>
+void launch_multidot(const cpx<T>* X, long stride, int m, const cpx<T>* y, long n, double* red, double* dst,
+                     hipStream_t s)
+{
+    if (m <= 0)
+        return;
+    for (int j0 = 0; j0 < m; j0 += kChunk) {
+        int mm = m - j0 < kChunk ? m - j0 : kChunk;
+        hipLaunchKernelGGL(k_multidot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, X, stride, j0, mm, y,
+                           n, red);
+    }
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, red, m, dst);
+}
+
+template <typename T> void launch_norm2(const cpx<T>* x, long n, double* red, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norm2_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, n, red);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, red, 1, dst);
+}
+
+template <typename T>
+void launch_multiaxpy(const cpx<T>* X, long stride, int m, const double* coef, double sign, cpx<T>* y, long n,
+                      hipStream_t s)
+{
+    if (m <= 0)
+        return;
+    hipLaunchKernelGGL(k_multiaxpy<T>, dim3(stream_grid(n)), dim3(256), 0, s, X, stride, m, coef, sign, y, n);
+}
+
+template <typename T> void launch_scale_invsqrt(cpx<T>* x, long n, const double* nrm2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_invsqrt<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, n, nrm2);
+}
+
+void launch_add_scalars(const double* a, const double* b, double* dst, int m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_scalars, dim3(1), dim3(128), 0, s, a, b, dst, m);
+}
+
+template <typename T> void launch_finite_check(const cpx<T>* x, long n, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finite<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, n, flag);
+}
+
+#define INST(T)                                                                                                    \
+    template void launch_zero<T>(cpx<T>*, long, hipStream_t);                                                     \
+    template void launch_copy<T>(const cpx<T>*, cpx<T>*, long, hipStream_t);                                      \
+    template void launch_sub<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, long, hipStream_t);                        \
+    template void launch_multidot<T>(const cpx<T>*, long, int, const cpx<T>*, long, double*, double*, hipStream_t); \
+    template void launch_norm2<T>(const cpx<T>*, long, double*, double*, hipStream_t);                            \
+    template void launch_multiaxpy<T>(const cpx<T>*, long, int, const double*, double, cpx<T>*, long, hipStream_t); \
+    template void launch_scale_invsqrt<T>(cpx<T>*, long, const double*, hipStream_t);                            \
+    template void launch_finite_check<T>(const cpx<T>*, long, int*, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace dfl

@@ -1,0 +1,249 @@
+// Device-side building blocks shared by the HIP kernels of the solver:
+// complex numbers, colour vectors and SU(3) links, the block-major native
+// site layout, XCD-aware workgroup numbering and wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfl {
+
+// ------------------------------------------------------------ complex
+
+template <typename T> struct cpx {
+    T re, im;
+};
+
+template <typename T> __host__ __device__ inline cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
+template <typename T> __device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ inline cpx<T> operator-(cpx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __device__ inline cpx<T> operator*(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ inline cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __device__ inline cpx<T>& operator+=(cpx<T>& a, cpx<T> b)
+{
+    a.re += b.re;
+    a.im += b.im;
+    return a;
+}
+template <typename T> __device__ inline cpx<T>& operator-=(cpx<T>& a, cpx<T> b)
+{
+    a.re -= b.re;
+    a.im -= b.im;
+    return a;
+}
+template <typename T> __device__ inline cpx<T> conjg(cpx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename T> __device__ inline cpx<T> cmul_conj(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a and -i * a
+template <typename T> __device__ inline cpx<T> times_i(cpx<T> a) { return {-a.im, a.re}; }
+template <typename T> __device__ inline cpx<T> times_mi(cpx<T> a) { return {a.im, -a.re}; }
+
+template <typename T> struct cvec3 {
+    cpx<T> c[3];
+};
+template <typename T> __device__ inline cvec3<T> operator+(const cvec3<T>& a, const cvec3<T>& b)
+{
+    return {{a.c[0] + b.c[0], a.c[1] + b.c[1], a.c[2] + b.c[2]}};
+}
+template <typename T> __device__ inline cvec3<T> operator-(const cvec3<T>& a, const cvec3<T>& b)
+{
+    return {{a.c[0] - b.c[0], a.c[1] - b.c[1], a.c[2] - b.c[2]}};
+}
+template <typename T> __device__ inline cvec3<T> vi(const cvec3<T>& a)
+{
+    return {{times_i(a.c[0]), times_i(a.c[1]), times_i(a.c[2])}};
+}
+template <typename T> __device__ inline cvec3<T> vmi(const cvec3<T>& a)
+{
+    return {{times_mi(a.c[0]), times_mi(a.c[1]), times_mi(a.c[2])}};
+}
+template <typename T> __device__ inline void operator+=(cvec3<T>& a, const cvec3<T>& b)
+{
+    a.c[0] += b.c[0];
+    a.c[1] += b.c[1];
+    a.c[2] += b.c[2];
+}
+template <typename T> __device__ inline void operator-=(cvec3<T>& a, const cvec3<T>& b)
+{
+    a.c[0] -= b.c[0];
+    a.c[1] -= b.c[1];
+    a.c[2] -= b.c[2];
+}
+
+// SU(3) link as 3x3 complex, m[row][col]
+template <typename T> struct su3 {
+    cpx<T> m[3][3];
+};
+
+// U v
+template <typename T> __device__ inline cvec3<T> mul(const su3<T>& u, const cvec3<T>& v)
+{
+    cvec3<T> r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        r.c[a] = u.m[a][0] * v.c[0] + u.m[a][1] * v.c[1] + u.m[a][2] * v.c[2];
+    return r;
+}
+// U^dagger v
+template <typename T> __device__ inline cvec3<T> mul_dag(const su3<T>& u, const cvec3<T>& v)
+{
+    cvec3<T> r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        r.c[a] = cmul_conj(u.m[0][a], v.c[0]) + cmul_conj(u.m[1][a], v.c[1]) + cmul_conj(u.m[2][a], v.c[2]);
+    return r;
+}
+// third row of an SU(3) matrix from the first two: conj(row0 x row1)
+template <typename T> __device__ inline void complete_third_row(su3<T>& u)
+{
+    u.m[2][0] = conjg(u.m[0][1] * u.m[1][2] - u.m[0][2] * u.m[1][1]);
+    u.m[2][1] = conjg(u.m[0][2] * u.m[1][0] - u.m[0][0] * u.m[1][2]);
+    u.m[2][2] = conjg(u.m[0][0] * u.m[1][1] - u.m[0][1] * u.m[1][0]);
+}
+
+// quark field value at one site: 4 spins x 3 colours
+template <typename T> struct spinor {
+    cvec3<T> s[4];
+};
+
+// ------------------------------------------------------------- layout
+//
+// Native quark field: 12 planes (component c = 3*spin + colour) of V complex
+// values, plane-major: element (c, site) at c*V + site. Sites are numbered
+// block-major over the deflation ("layout") blocks:
+//   site = blk*Vb + ((y0*b1 + y1)*b2 + y2)*b3 + y3,
+//   blk  = ((n0*nb1 + n1)*nb2 + n2)*nb3 + n3,
+// with x_mu = n_mu*b_mu + y_mu. Every block is a contiguous run of Vb sites.
+
+struct Geom {
+    int L[4];     // lattice extent
+    int b[4];     // layout block
+    int nb[4];    // blocks per direction
+    int lstr[4];  // in-block stride of y_mu
+    int bstr[4];  // block-index stride of n_mu
+    int Vb;       // sites per block
+    int Nb;       // number of blocks
+    long V;       // sites
+};
+
+__host__ inline Geom make_geom(const int L[4], const int b[4])
+{
+    Geom g;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.L[mu] = L[mu];
+        g.b[mu] = b[mu];
+        g.nb[mu] = L[mu] / b[mu];
+    }
+    g.lstr[3] = 1;
+    g.bstr[3] = 1;
+    for (int mu = 2; mu >= 0; --mu) {
+        g.lstr[mu] = g.lstr[mu + 1] * b[mu + 1];
+        g.bstr[mu] = g.bstr[mu + 1] * g.nb[mu + 1];
+    }
+    g.Vb = b[0] * b[1] * b[2] * b[3];
+    g.Nb = g.nb[0] * g.nb[1] * g.nb[2] * g.nb[3];
+    g.V = (long)g.Vb * g.Nb;
+    return g;
+}
+
+// block coordinates n and in-block coordinates y of a native site
+__host__ __device__ inline void site_decompose(const Geom& g, long s, int n[4], int y[4])
+{
+    int blk = (int)(s / g.Vb);
+    int loc = (int)(s - (long)blk * g.Vb);
+#pragma unroll
+    for (int mu = 3; mu >= 1; --mu) {
+        int q = loc / g.b[mu];
+        y[mu] = loc - q * g.b[mu];
+        loc = q;
+        int p = blk / g.nb[mu];
+        n[mu] = blk - p * g.nb[mu];
+        blk = p;
+    }
+    y[0] = loc;
+    n[0] = blk;
+}
+
+__host__ __device__ inline long site_compose(const Geom& g, const int n[4], const int y[4])
+{
+    long blk = ((long)(n[0] * g.nb[1] + n[1]) * g.nb[2] + n[2]) * g.nb[3] + n[3];
+    long loc = ((long)(y[0] * g.b[1] + y[1]) * g.b[2] + y[2]) * g.b[3] + y[3];
+    return blk * g.Vb + loc;
+}
+
+// native index of the neighbour s + step*mu (step = +1 or -1), periodic
+__host__ __device__ inline long site_step(const Geom& g, long s, const int n[4], const int y[4], int mu, int step)
+{
+    int yy = y[mu] + step;
+    if (yy >= 0 && yy < g.b[mu])
+        return s + (long)step * g.lstr[mu];
+    // leave the block: wrap y, move the block coordinate with periodic wrap
+    int nn = n[mu] + step;
+    int dn = step;
+    if (nn < 0) {
+        dn += g.nb[mu];
+    } else if (nn >= g.nb[mu]) {
+        dn -= g.nb[mu];
+    }
+    long dy = (step > 0) ? -(long)(g.b[mu] - 1) * g.lstr[mu] : (long)(g.b[mu] - 1) * g.lstr[mu];
+    return s + (long)dn * g.bstr[mu] * g.Vb + dy;
+}
+
+// canonical site index from global coordinates
+__host__ __device__ inline long canon_index(const Geom& g, const int x[4])
+{
+    return (((long)x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
+}
+
+// --------------------------------------------------- XCD-aware numbering
+//
+// Workgroups are handed to the 8 XCDs round robin by id. Renumber so that
+// XCD k works on the contiguous id range [k*per, (k+1)*per): neighbouring
+// sites then share one XCD's L2. The grid must be padded to a multiple of 8;
+// ids >= the real count do nothing.
+constexpr int kNumXcd = 8;
+
+__device__ inline int xcd_remap(int bid, int grid_padded)
+{
+    int per = grid_padded / kNumXcd;
+    return (bid % kNumXcd) * per + bid / kNumXcd;
+}
+
+__host__ inline int pad_grid(long nwg) { return (int)(((nwg + kNumXcd - 1) / kNumXcd) * kNumXcd); }
+
+// --------------------------------------------------------- reductions
+
+template <typename T> __device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of v over the workgroup (blockDim.x a multiple of 64, <= 1024); every
+// thread receives the result. scratch holds >= 16 T. Fixed order: deterministic.
+template <typename T> __device__ inline T block_sum(T v, T* scratch)
+{
+    v = wave_sum(v);
+    int lane = threadIdx.x & 63;
+    int wid = threadIdx.x >> 6;
+    int nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        scratch[wid] = v;
+    __syncthreads();
+    T r = 0;
+    for (int i = 0; i < nw; ++i)
+        r += scratch[i];
+    return r;
+}
+
+}  // namespace dfl

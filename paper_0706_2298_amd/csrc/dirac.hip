@@ -1,0 +1,105 @@
+// The Wilson-Dirac stencil (the operator of eq. (3.9)) on native fields.
+//
+// One thread per site, 256 sites per workgroup, one grid row per right-hand
+// side. Per site the kernel reads the eight neighbour spinors, the four
+// forward links and the four backward links U_mu(x - mu) (owned by the
+// neighbour; they come from L2/MALL, not HBM), and writes one spinor. The
+// workgroup numbering is XCD-aware (common.h): each XCD sweeps a contiguous
+// range of sites so that neighbour reuse stays inside one L2.
+#include "hop.h"
+
+namespace dfl {
+
+namespace {
+
+// MODE 0: full operator; 1: direct sum of the block operators (hops leaving a
+// layout block dropped); 2: only the block-crossing hop (hop_mu, hop_dir),
+// without the mass term. The direction loop is kept rolled so that each
+// direction's loads stay in their own basic block: unrolled, the scheduler
+// hoists all 180 loads of a site and the kernel spills.
+template <int MODE, typename T, typename L>
+__device__ inline void hops_all(const Geom& g, const L& U, const cpx<T>* __restrict__ f, long s, const int n[4],
+                                const int y[4], int hop_mu, int hop_dir, spinor<T>& acc)
+{
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int mu = h >> 1;
+        const int step = (h & 1) ? -1 : +1;
+        bool keep = true;
+        if (MODE == 1) {
+            keep = (step > 0 ? y[mu] + 1 < g.b[mu] : y[mu] > 0) || g.nb[mu] == 1;
+        } else if (MODE == 2) {
+            keep = hop_mu == mu && hop_dir == step && (step > 0 ? y[mu] + 1 == g.b[mu] : y[mu] == 0) &&
+                   g.nb[mu] > 1;
+        }
+        if (!keep)
+            continue;
+        long t = site_step(g, s, n, y, mu, step);
+        spinor<T> p = load_spinor(f, g.V, t);
+        if (step > 0)
+            hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
+        else
+            hop_bwd_rt(mu, load_link(U, mu, t), p, acc);
+    }
+}
+
+template <int MODE, typename T, typename L>
+__global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __restrict__ psi,
+                                               cpx<T>* __restrict__ out, T diag, int hop_mu, int hop_dir,
+                                               int grid_padded)
+{
+    int wg = xcd_remap(blockIdx.x, grid_padded);
+    long s = (long)wg * 256 + threadIdx.x;
+    if (s >= g.V)
+        return;
+    long off = (long)blockIdx.y * 12 * g.V;
+    const cpx<T>* f = psi + off;
+    int n[4], y[4];
+    site_decompose(g, s, n, y);
+    spinor<T> acc;
+    zero(acc);
+    hops_all<MODE>(g, U, f, s, n, y, hop_mu, hop_dir, acc);
+    spinor<T> o;
+    if (MODE == 2) {
+        spinor<T> z;
+        zero(z);
+        o = finish(z, acc, T(0));
+    } else {
+        o = finish(load_spinor(f, g.V, s), acc, diag);
+    }
+    store_spinor(out + off, g.V, s, o);
+}
+
+template <int MODE, typename T, typename L>
+void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, int mu, int dir, hipStream_t s)
+{
+    long nwg = (g.V + 255) / 256;
+    int gp = pad_grid(nwg);
+    hipLaunchKernelGGL((k_dirac<MODE, T, L>), dim3(gp, nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, mu, dir,
+                       gp);
+}
+
+}  // namespace
+
+void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, double m0, int mode, int mu,
+                    int dir, hipStream_t s)
+{
+    if (mode == 0)
+        launch<0>(g, U, psi, out, nrhs, m0, mu, dir, s);
+    else if (mode == 1)
+        launch<1>(g, U, psi, out, nrhs, m0, mu, dir, s);
+    else
+        launch<2>(g, U, psi, out, nrhs, m0, mu, dir, s);
+}
+
+void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s)
+{
+    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s);
+}
+
+void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s)
+{
+    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s);
+}
+
+}  // namespace dfl

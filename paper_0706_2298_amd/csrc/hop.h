@@ -1,0 +1,214 @@
+// Wilson hop terms with spin projection, and link/spinor loads from the
+// native layouts. Shared by the stencil and the Schwarz block kernels.
+//
+// With g_mu = [[0, e_mu], [e_mu^+, 0]] (e_0 = -1, e_k = -i sigma_k) and e_mu
+// unitary, (1 - g_mu) psi = [h; -e_mu^+ h] with h = psi_up - e_mu psi_lo, and
+// (1 + g_mu) psi = [k; e_mu^+ k] with k = psi_up + e_mu psi_lo. A hop thus
+// multiplies two colour vectors by the link instead of four.
+#pragma once
+
+#include "internal.h"
+
+namespace dfl {
+
+__device__ inline float bf16_to_f(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+// Loads take a uniform plane base and a 32-bit byte offset, so the compiler
+// can use the scalar-base + 32-bit vector-offset addressing form instead of
+// one 64-bit address per load. Fields hold fewer than 2^28 sites (checked at
+// context creation), so s * sizeof(element) fits in 32 bits.
+template <typename E> __device__ inline E ld(const E* __restrict__ plane, uint32_t byte_off)
+{
+    return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(plane) + byte_off);
+}
+template <typename E> __device__ inline void st(E* __restrict__ plane, uint32_t byte_off, E v)
+{
+    *reinterpret_cast<E*>(reinterpret_cast<char*>(plane) + byte_off) = v;
+}
+
+__device__ inline su3<double> load_link(const Links64& L, int mu, long s)
+{
+    su3<double> u;
+    const c64* p = L.u + (long)mu * 9 * L.V;
+    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(c64);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            u.m[a][b] = ld(p + (long)(a * 3 + b) * L.V, o);
+    return u;
+}
+
+__device__ inline su3<float> load_link(const Links32& L, int mu, long s)
+{
+    su3<float> u;
+    const c32* p = L.u + (long)mu * 6 * L.V;
+    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(c32);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            u.m[a][b] = ld(p + (long)(a * 3 + b) * L.V, o);
+    complete_third_row(u);
+    return u;
+}
+
+__device__ inline su3<float> load_link(const LinksBF16& L, int mu, long s)
+{
+    su3<float> u;
+    const uint32_t* p = L.u + (long)mu * 6 * L.V;
+    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(uint32_t);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            uint32_t w = ld(p + (long)(a * 3 + b) * L.V, o);
+            u.m[a][b] = c32{bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
+        }
+    complete_third_row(u);
+    return u;
+}
+
+template <typename T> __device__ inline spinor<T> load_spinor(const cpx<T>* __restrict__ f, long V, long s)
+{
+    spinor<T> p;
+    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(cpx<T>);
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            p.s[al].c[a] = ld(f + (long)(3 * al + a) * V, o);
+    return p;
+}
+
+template <typename T> __device__ inline void store_spinor(cpx<T>* __restrict__ f, long V, long s, const spinor<T>& p)
+{
+    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(cpx<T>);
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            st(f + (long)(3 * al + a) * V, o, p.s[al].c[a]);
+}
+
+template <typename T> __device__ inline void zero(spinor<T>& p)
+{
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            p.s[al].c[a] = cpx<T>{0, 0};
+}
+
+// acc += (1 - g_mu) U psi_fwd
+template <int MU, typename T>
+__device__ inline void hop_fwd(const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+{
+    cvec3<T> h0, h1;
+    if (MU == 0) {
+        h0 = p.s[0] + p.s[2];
+        h1 = p.s[1] + p.s[3];
+    } else if (MU == 1) {
+        h0 = p.s[0] + vi(p.s[3]);
+        h1 = p.s[1] + vi(p.s[2]);
+    } else if (MU == 2) {
+        h0 = p.s[0] + p.s[3];
+        h1 = p.s[1] - p.s[2];
+    } else {
+        h0 = p.s[0] + vi(p.s[2]);
+        h1 = p.s[1] - vi(p.s[3]);
+    }
+    cvec3<T> u0 = mul(u, h0);
+    cvec3<T> u1 = mul(u, h1);
+    acc.s[0] += u0;
+    acc.s[1] += u1;
+    if (MU == 0) {
+        acc.s[2] += u0;
+        acc.s[3] += u1;
+    } else if (MU == 1) {
+        acc.s[2] += vmi(u1);
+        acc.s[3] += vmi(u0);
+    } else if (MU == 2) {
+        acc.s[2] -= u1;
+        acc.s[3] += u0;
+    } else {
+        acc.s[2] += vmi(u0);
+        acc.s[3] += vi(u1);
+    }
+}
+
+// acc += (1 + g_mu) U^+ psi_bwd   (u is the link U_mu(x - mu))
+template <int MU, typename T>
+__device__ inline void hop_bwd(const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+{
+    cvec3<T> k0, k1;
+    if (MU == 0) {
+        k0 = p.s[0] - p.s[2];
+        k1 = p.s[1] - p.s[3];
+    } else if (MU == 1) {
+        k0 = p.s[0] + vmi(p.s[3]);
+        k1 = p.s[1] + vmi(p.s[2]);
+    } else if (MU == 2) {
+        k0 = p.s[0] - p.s[3];
+        k1 = p.s[1] + p.s[2];
+    } else {
+        k0 = p.s[0] + vmi(p.s[2]);
+        k1 = p.s[1] + vi(p.s[3]);
+    }
+    cvec3<T> v0 = mul_dag(u, k0);
+    cvec3<T> v1 = mul_dag(u, k1);
+    acc.s[0] += v0;
+    acc.s[1] += v1;
+    if (MU == 0) {
+        acc.s[2] -= v0;
+        acc.s[3] -= v1;
+    } else if (MU == 1) {
+        acc.s[2] += vi(v1);
+        acc.s[3] += vi(v0);
+    } else if (MU == 2) {
+        acc.s[2] += v1;
+        acc.s[3] -= v0;
+    } else {
+        acc.s[2] += vi(v0);
+        acc.s[3] += vmi(v1);
+    }
+}
+
+// runtime-direction forms (uniform branch on mu)
+template <typename T>
+__device__ inline void hop_fwd_rt(int mu, const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+{
+    switch (mu) {
+    case 0: hop_fwd<0>(u, p, acc); break;
+    case 1: hop_fwd<1>(u, p, acc); break;
+    case 2: hop_fwd<2>(u, p, acc); break;
+    default: hop_fwd<3>(u, p, acc); break;
+    }
+}
+template <typename T>
+__device__ inline void hop_bwd_rt(int mu, const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+{
+    switch (mu) {
+    case 0: hop_bwd<0>(u, p, acc); break;
+    case 1: hop_bwd<1>(u, p, acc); break;
+    case 2: hop_bwd<2>(u, p, acc); break;
+    default: hop_bwd<3>(u, p, acc); break;
+    }
+}
+
+// out = diag * p - 1/2 acc
+template <typename T>
+__device__ inline spinor<T> finish(const spinor<T>& p, const spinor<T>& acc, T diag)
+{
+    spinor<T> o;
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o.s[al].c[a].re = diag * p.s[al].c[a].re - T(0.5) * acc.s[al].c[a].re;
+            o.s[al].c[a].im = diag * p.s[al].c[a].im - T(0.5) * acc.s[al].c[a].im;
+        }
+    return o;
+}
+
+}  // namespace dfl

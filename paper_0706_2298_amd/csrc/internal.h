@@ -1,0 +1,177 @@
+// Host-side internals of the solver library: the context, and the launchers
+// each kernel file exports to the solver driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "dfl.h"
+
+namespace dfl {
+
+using c64 = cpx<double>;
+using c32 = cpx<float>;
+
+// error handling: thrown inside the library, caught at the C boundary
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define HIPCHECK(x) ::dfl::hip_check((x), #x)
+
+// Schwarz block grid (independent of the layout blocks)
+struct SapGeom {
+    int sb[4];    // SAP block extent
+    int nsb[4];   // SAP blocks per direction
+    int lstr[4];  // in-block strides (lexicographic, y3 fastest)
+    int Vsb;      // sites per SAP block
+    int n_per_colour;
+};
+
+// links: FP64 full [4][9][V], FP32 two-row [4][6][V], BF16 two-row [4][6][V]
+struct Links64 {
+    const c64* u;
+    long V;
+};
+struct Links32 {
+    const c32* u;
+    long V;
+};
+struct LinksBF16 {
+    const uint32_t* u;
+    long V;
+};
+
+// device scratch for reductions
+constexpr int kRedBlocks = 480;   // fixed grid of the partial-sum kernels (deterministic)
+constexpr int kRedThreads = 256;
+constexpr int kMaxDot = 64;       // most vectors in one multi-dot
+
+}  // namespace dfl
+
+struct dfl_ctx {
+    dfl_params p;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    dfl::Geom g;
+    dfl::SapGeom sg;
+    long V = 0;
+    long field_elems = 0;  // complex entries of one quark field (12 V)
+
+    // gauge field
+    dfl::c64* U64 = nullptr;
+    dfl::c32* U32 = nullptr;
+    uint32_t* Ubf = nullptr;
+    bool have_gauge = false;
+
+    // deflation subspace
+    dfl::c64* Phi = nullptr;   // [Ns][12][V]
+    dfl::c32* Phi32 = nullptr; // FP32 copy (inner projections in mixed precision)
+    dfl::c64* A64 = nullptr;   // [Nb][9][Ns][Ns] at m0_A
+    dfl::c32* A32 = nullptr;
+    double m0_A = 0.0;
+    bool have_subspace = false;
+
+    // FP64 field workspaces
+    dfl::c64* xi = nullptr;    // nkv Krylov directions
+    dfl::c64* chi = nullptr;   // nkv orthonormal images
+    dfl::c64* rho = nullptr;
+    dfl::c64* acc = nullptr;
+    dfl::c64* t1 = nullptr;
+    dfl::c64* t2 = nullptr;
+    dfl::c64* t3 = nullptr;
+    // FP32 SAP workspaces
+    dfl::c32* s32a = nullptr;
+    dfl::c32* s32b = nullptr;
+    dfl::c32* s32c = nullptr;
+    // little-system workspaces (max(FP64) size; reused for FP32)
+    void* lxi = nullptr;
+    void* lchi = nullptr;
+    void* lr = nullptr;
+    void* lx = nullptr;
+    void* lw = nullptr;
+    void* lt = nullptr;
+    dfl::c32* lw32 = nullptr;  // FP32 little source and solution (mixed precision)
+    dfl::c32* lx32 = nullptr;
+    // reductions and scalars
+    double* red = nullptr;       // kRedBlocks * 2 * kMaxDot partials
+    double* dscal = nullptr;     // device scalars
+    double* hscal = nullptr;     // pinned host mirror
+    int* dflag = nullptr;        // device status flag
+    size_t alloc_bytes = 0;
+};
+
+namespace dfl {
+
+// ---------------------------------------------------------------- layout.hip
+void launch_pack_field64(const Geom& g, const c64* canon, c64* nat, int nrhs, hipStream_t s);
+void launch_pack_field32(const Geom& g, const c64* canon, c32* nat, int nrhs, hipStream_t s);
+void launch_unpack_field64(const Geom& g, const c64* nat, c64* canon, int nrhs, hipStream_t s);
+void launch_unpack_field32(const Geom& g, const c32* nat, c64* canon, int nrhs, hipStream_t s);
+void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, hipStream_t s);
+void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s);
+void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s);
+
+// ----------------------------------------------------------------- dirac.hip
+// out = D psi (nrhs fields, each 12 V). mode 0: full D; 1: block-diagonal part
+// (hops leaving a layout block dropped); 2: block-crossing hop in direction
+// mu, orientation dir (no mass term).
+void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, double m0,
+                    int mode, int mu, int dir, hipStream_t s);
+void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s);
+void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s);
+
+// ------------------------------------------------------------------- sap.hip
+void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi,
+                         double m0, int nmr, int colour, hipStream_t s);
+void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi,
+                         float m0, int nmr, int colour, hipStream_t s);
+void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi,
+                            float m0, int nmr, int colour, hipStream_t s);
+
+// ------------------------------------------------------------------ blas.hip
+template <typename T> void launch_zero(cpx<T>* x, long n, hipStream_t s);
+template <typename T> void launch_copy(const cpx<T>* x, cpx<T>* y, long n, hipStream_t s);
+// z = x - y
+template <typename T> void launch_sub(const cpx<T>* x, const cpx<T>* y, cpx<T>* z, long n, hipStream_t s);
+// out[j] = (X_j, y) for j < m, X_j = X + j*stride; complex results to dst (2 doubles each)
+template <typename T>
+void launch_multidot(const cpx<T>* X, long stride, int m, const cpx<T>* y, long n, double* red,
+                     double* dst, hipStream_t s);
+// dst = ||x||^2
+template <typename T> void launch_norm2(const cpx<T>* x, long n, double* red, double* dst, hipStream_t s);
+// y += sign * sum_j coef[j] X_j  (coef: m complex doubles on the device)
+template <typename T>
+void launch_multiaxpy(const cpx<T>* X, long stride, int m, const double* coef, double sign, cpx<T>* y,
+                      long n, hipStream_t s);
+// x *= 1/sqrt(*nrm2)
+template <typename T> void launch_scale_invsqrt(cpx<T>* x, long n, const double* nrm2, hipStream_t s);
+// dst[0..1] = a[0..1] + b[0..1] for m complex
+void launch_add_scalars(const double* a, const double* b, double* dst, int m, hipStream_t s);
+// finite check: flag |= 1 if any entry of x is NaN or Inf
+template <typename T> void launch_finite_check(const cpx<T>* x, long n, int* flag, hipStream_t s);
+
+// ------------------------------------------------------------------- dfl.hip
+// w[blk][k] = (Phi_k, psi) over each layout block, nrhs fields
+void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, hipStream_t s);
+// psi = sum_k Phi_k v[blk][k]
+void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, hipStream_t s);
+// block Gram-Schmidt in place on Ns fields (modified GS, order l = 0..Ns-1)
+void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, hipStream_t s);
+// A[blk][d][k][l] = (Phi_k, Y) over each block; Y given, fixed d and l
+void launch_little_column64(const Geom& g, const c64* Phi, int Ns, const c64* Y, c64* A, int d, int l,
+                            hipStream_t s);
+// w = A v (9-point block stencil)
+template <typename T>
+void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, hipStream_t s);
+// A[blk][0][k][k] += dm  (mass shift)
+void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s);
+void launch_c64_to_c32(const c64* a, c32* b, long n, hipStream_t s);
+
+}  // namespace dfl

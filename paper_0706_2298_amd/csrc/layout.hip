@@ -1,0 +1,143 @@
+// Canonical <-> native conversions of quark fields, and link compression.
+//
+// Canonical quark field: complex128 [V][12] in lexicographic site order.
+// Native quark field: 12 planes of V complex values in block-major site order
+// (common.h). Links: FP64 full 3x3 [4][9][V]; FP32 and BF16 store the first
+// two rows only ([4][6][V]), the third row being rebuilt as conj(row0 x row1).
+#include "internal.h"
+
+namespace dfl {
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_field(Geom g, const c64* __restrict__ canon,
+                                                    cpx<T>* __restrict__ nat, int nrhs)
+{
+    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int r = blockIdx.y;
+    if (s >= g.V || r >= nrhs)
+        return;
+    int n[4], y[4], x[4];
+    site_decompose(g, s, n, y);
+    for (int mu = 0; mu < 4; ++mu)
+        x[mu] = n[mu] * g.b[mu] + y[mu];
+    long c = canon_index(g, x);
+    const c64* src = canon + ((long)r * g.V + c) * 12;
+    cpx<T>* dst = nat + (long)r * 12 * g.V;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        c64 v = src[k];
+        dst[(long)k * g.V + s] = cpx<T>{(T)v.re, (T)v.im};
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack_field(Geom g, const cpx<T>* __restrict__ nat,
+                                                      c64* __restrict__ canon, int nrhs)
+{
+    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int r = blockIdx.y;
+    if (s >= g.V || r >= nrhs)
+        return;
+    int n[4], y[4], x[4];
+    site_decompose(g, s, n, y);
+    for (int mu = 0; mu < 4; ++mu)
+        x[mu] = n[mu] * g.b[mu] + y[mu];
+    long c = canon_index(g, x);
+    c64* dst = canon + ((long)r * g.V + c) * 12;
+    const cpx<T>* src = nat + (long)r * 12 * g.V;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        cpx<T> v = src[(long)k * g.V + s];
+        dst[k] = c64{(double)v.re, (double)v.im};
+    }
+}
+
+// round-to-nearest-even float -> bfloat16 bits (finite inputs)
+__device__ inline uint32_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return u >> 16;
+}
+
+__global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const c64* __restrict__ canon, c64* U64,
+                                                    c32* U32, uint32_t* Ubf)
+{
+    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V)
+        return;
+    int n[4], y[4], x[4];
+    site_decompose(g, s, n, y);
+    for (int mu = 0; mu < 4; ++mu)
+        x[mu] = n[mu] * g.b[mu] + y[mu];
+    long c = canon_index(g, x);
+    for (int mu = 0; mu < 4; ++mu) {
+        const c64* src = canon + (c * 4 + mu) * 9;
+        for (int k = 0; k < 9; ++k) {
+            c64 v = src[k];
+            if (U64)
+                U64[(long)(mu * 9 + k) * g.V + s] = v;
+            if (k < 6) {
+                if (U32)
+                    U32[(long)(mu * 6 + k) * g.V + s] = c32{(float)v.re, (float)v.im};
+                if (Ubf)
+                    Ubf[(long)(mu * 6 + k) * g.V + s] =
+                        bf16_bits((float)v.re) | (bf16_bits((float)v.im) << 16);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_f64_to_f32(const c64* __restrict__ in, c32* __restrict__ out, long n)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = c32{(float)in[i].re, (float)in[i].im};
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_f64(const c32* __restrict__ in, c64* __restrict__ out, long n)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = c64{(double)in[i].re, (double)in[i].im};
+}
+
+inline dim3 site_grid(const Geom& g, int nrhs) { return dim3((unsigned)((g.V + 255) / 256), (unsigned)nrhs); }
+
+}  // namespace
+
+void launch_pack_field64(const Geom& g, const c64* canon, c64* nat, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_field<double>, site_grid(g, nrhs), dim3(256), 0, s, g, canon, nat, nrhs);
+}
+void launch_pack_field32(const Geom& g, const c64* canon, c32* nat, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_field<float>, site_grid(g, nrhs), dim3(256), 0, s, g, canon, nat, nrhs);
+}
+void launch_unpack_field64(const Geom& g, const c64* nat, c64* canon, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack_field<double>, site_grid(g, nrhs), dim3(256), 0, s, g, nat, canon, nrhs);
+}
+void launch_unpack_field32(const Geom& g, const c32* nat, c64* canon, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack_field<float>, site_grid(g, nrhs), dim3(256), 0, s, g, nat, canon, nrhs);
+}
+void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_gauge, site_grid(g, 1), dim3(256), 0, s, g, canon, U64, U32, Ubf);
+}
+void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+}
+void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+}
+
+}  // namespace dfl

@@ -1,0 +1,221 @@
+// One colour sweep of the Schwarz alternating procedure: every Schwarz block
+// of the given colour computes its residual r = (rho - D psi)|_Lambda with the
+// full operator, runs nmr minimal-residual steps on the block operator
+// D_Lambda (Dirichlet walls) and adds the block solution to psi.
+//
+// Mapping: one workgroup per Schwarz block, one thread per site (blockDim =
+// |block| rounded up to a wavefront; spare lanes only join the reductions).
+// The residual reads the neighbour spinors across the block faces directly
+// from global memory; those sites belong to blocks of the other colour, which
+// no workgroup of this launch writes, so there is no race. Inside the MR loop
+// the current residue r is exchanged through LDS (12 planes x |block|), the
+// links come through L1/L2, and the two block reductions per step use
+// wavefront shuffles plus one LDS pass.
+#include "hop.h"
+
+namespace dfl {
+
+namespace {
+
+// D_Lambda hops of one site: neighbours inside the Schwarz block come from
+// the LDS copy of the residue; hops leaving the block are dropped.
+template <typename T, typename L>
+__device__ inline void block_hops(const Geom& g, const SapGeom& sg, const L& U, const cpx<T>* lr, int t,
+                                  const int yl[4], long s, const int n[4], const int y[4], spinor<T>& acc)
+{
+    const int V = sg.Vsb;
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int mu = h >> 1;
+        const int step = (h & 1) ? -1 : +1;
+        if (step > 0 ? yl[mu] + 1 >= sg.sb[mu] : yl[mu] == 0)
+            continue;
+        const int tn = t + step * sg.lstr[mu];
+        spinor<T> p;
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                p.s[al].c[a] = lr[(3 * al + a) * V + tn];
+        if (step > 0)
+            hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
+        else
+            hop_bwd_rt(mu, load_link(U, mu, site_step(g, s, n, y, mu, -1)), p, acc);
+    }
+}
+
+// all eight hops of the full operator at one site, neighbours from global memory
+template <typename T, typename L>
+__device__ inline void full_hops(const Geom& g, const L& U, const cpx<T>* __restrict__ psi, long s, const int n[4],
+                                 const int y[4], spinor<T>& acc)
+{
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int mu = h >> 1;
+        const int step = (h & 1) ? -1 : +1;
+        long tn = site_step(g, s, n, y, mu, step);
+        spinor<T> p = load_spinor(psi, g.V, tn);
+        if (step > 0)
+            hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
+        else
+            hop_bwd_rt(mu, load_link(U, mu, tn), p, acc);
+    }
+}
+
+template <typename T, typename L>
+__global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<T>* __restrict__ rho,
+                                             cpx<T>* __restrict__ psi, T diag, int nmr, int colour)
+{
+    extern __shared__ char smem_raw[];
+    cpx<T>* lr = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[3][8];
+
+    const int t = threadIdx.x;
+    const bool active = t < sg.Vsb;
+    const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+
+    // k-th block of this colour -> block coordinates m
+    int k = blockIdx.x;
+    int half = sg.nsb[3] / 2;
+    int m[4];
+    int j = k % half;
+    int rest = k / half;
+    m[2] = rest % sg.nsb[2];
+    rest /= sg.nsb[2];
+    m[1] = rest % sg.nsb[1];
+    m[0] = rest / sg.nsb[1];
+    m[3] = 2 * j + ((colour + m[0] + m[1] + m[2]) & 1);
+
+    int yl[4] = {0, 0, 0, 0};
+    int n[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
+    long s = 0;
+    if (active) {
+        int tt = t;
+        yl[3] = tt % sg.sb[3];
+        tt /= sg.sb[3];
+        yl[2] = tt % sg.sb[2];
+        tt /= sg.sb[2];
+        yl[1] = tt % sg.sb[1];
+        yl[0] = tt / sg.sb[1];
+        for (int mu = 0; mu < 4; ++mu) {
+            int x = m[mu] * sg.sb[mu] + yl[mu];
+            n[mu] = x / g.b[mu];
+            y[mu] = x - n[mu] * g.b[mu];
+        }
+        s = site_compose(g, n, y);
+    }
+
+    // residual with the full operator
+    spinor<T> r, xs;
+    zero(r);
+    zero(xs);
+    if (active) {
+        spinor<T> acc;
+        zero(acc);
+        full_hops(g, U, psi, s, n, y, acc);
+        spinor<T> d = finish(load_spinor(psi, g.V, s), acc, diag);
+        spinor<T> b = load_spinor(rho, g.V, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+            r.s[al] = b.s[al] - d.s[al];
+    }
+
+    for (int step = 0; step < nmr; ++step) {
+        if (active) {
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    lr[(3 * al + a) * sg.Vsb + t] = r.s[al].c[a];
+        }
+        __syncthreads();
+        spinor<T> q;
+        zero(q);
+        double qr_re = 0.0, qr_im = 0.0, qq = 0.0;
+        if (active) {
+            spinor<T> acc;
+            zero(acc);
+            block_hops(g, sg, U, lr, t, yl, s, n, y, acc);
+            q = finish(r, acc, diag);
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    double qa = (double)q.s[al].c[a].re, qb = (double)q.s[al].c[a].im;
+                    double ra = (double)r.s[al].c[a].re, rb = (double)r.s[al].c[a].im;
+                    qr_re += qa * ra + qb * rb;
+                    qr_im += qa * rb - qb * ra;
+                    qq += qa * qa + qb * qb;
+                }
+        }
+        qr_re = wave_sum(qr_re);
+        qr_im = wave_sum(qr_im);
+        qq = wave_sum(qq);
+        if (lane == 0) {
+            red[0][wid] = qr_re;
+            red[1][wid] = qr_im;
+            red[2][wid] = qq;
+        }
+        __syncthreads();
+        double sre = 0.0, sim = 0.0, sqq = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            sre += red[0][w];
+            sim += red[1][w];
+            sqq += red[2][w];
+        }
+        if (!(sqq > 0.0))
+            break;  // zero residue on this block: uniform across the workgroup
+        cpx<T> alpha{(T)(sre / sqq), (T)(sim / sqq)};
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xs.s[al].c[a] += alpha * r.s[al].c[a];
+                r.s[al].c[a] -= alpha * q.s[al].c[a];
+            }
+    }
+
+    if (active) {
+        spinor<T> p = load_spinor(psi, g.V, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+            p.s[al] += xs.s[al];
+        store_spinor(psi, g.V, s, p);
+    }
+}
+
+template <typename T, typename L>
+void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
+            hipStream_t s)
+{
+    int threads = ((sg.Vsb + 63) / 64) * 64;
+    size_t lds = (size_t)12 * sg.Vsb * sizeof(cpx<T>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap<T, L>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sap<T, L>), dim3(sg.n_per_colour), dim3(threads), lds, s, g, sg, U, rho, psi, T(4) + m0,
+                       nmr, colour);
+}
+
+}  // namespace
+
+void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi, double m0, int nmr,
+                         int colour, hipStream_t s)
+{
+    launch(g, sg, U, rho, psi, m0, nmr, colour, s);
+}
+void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi, float m0, int nmr,
+                         int colour, hipStream_t s)
+{
+    launch(g, sg, U, rho, psi, m0, nmr, colour, s);
+}
+void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi, float m0,
+                            int nmr, int colour, hipStream_t s)
+{
+    launch(g, sg, U, rho, psi, m0, nmr, colour, s);
+}
+
+}  // namespace dfl

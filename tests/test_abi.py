@@ -1,0 +1,69 @@
+"""The C ABI library loads, exports every symbol the header declares, and rejects
+bad parameters on the host (no GPU call is made for these)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0706_2298_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dfl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|long long|char)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_header_symbols():
+    L = binding.load()
+    names = _declared()
+    assert "dirac_apply" in names and "solve" in names and len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), f"libdfl.so does not export {n}"
+    assert sorted(names) == sorted(binding.EXPORTS)
+
+
+def test_default_params():
+    p = binding.default_params(dims=(8, 8, 8, 8))
+    assert list(p.dims) == [8, 8, 8, 8]
+    assert list(p.sap_block) == [4, 4, 4, 4] and list(p.dfl_block) == [4, 4, 4, 4]
+    assert p.Ns == 20 and p.ncy == 5 and p.nmr == 4 and p.nkv == 16
+    assert p.tol == 1e-10 and p.little_tol_in == 1e-6 and p.little_tol_out == 1e-12
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dims=(8, 8, 8, 6)), "block"),                      # 4 does not divide 6
+    (dict(dims=(12, 8, 8, 8)), "even"),                      # 3 blocks along x0
+    (dict(dims=(8, 8, 8, 8), Ns=0), "Ns"),
+    (dict(dims=(8, 8, 8, 8), Ns=65), "Ns"),
+    (dict(dims=(8, 8, 8, 8), nkv=0), "nkv"),
+    (dict(dims=(16, 16, 8, 8), sap_block=(8, 8, 4, 4)), "512"),
+    (dict(dims=(8, 8, 8, 8), tol=0.0), "tolerance"),
+    (dict(dims=(8, 8, 8, 8), link_prec=binding.BF16), "FP64 SAP"),
+    (dict(dims=(8, 8, 8, 8), m0=float("nan")), "finite"),
+])
+def test_create_rejects_bad_params(kw, msg):
+    p = binding.default_params(**kw)
+    with pytest.raises(binding.DflError) as e:
+        binding.dfl_create(p, None)
+    assert e.value.code == -1
+    assert msg in str(e.value)
+
+
+def test_null_context_is_einval():
+    L = binding.load()
+    assert L.dirac_apply(None, None, None, 1, 0) == -1
+    assert L.solve(None, None, None, 1, None) == -1
+    assert L.dfl_destroy(None) == 0
+    assert b"null" in L.dfl_last_error()
+    assert L.dfl_field_bytes(None, 0) == -1
+
+
+def test_params_struct_layout_matches_c():
+    # the ctypes mirror must have the C struct size: 3 int[4] + 10 int + 5 double + 3 enum + padding
+    assert ctypes.sizeof(binding.Params) == 144
+    assert ctypes.sizeof(binding.Info) == 40

@@ -1,0 +1,294 @@
+"""GPU parity: every C-ABI call against the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances (relative to the largest entry of the reference):
+* FP64 stencil 1e-13 (summation order only); FP64 Schwarz 1e-12;
+* FP32 arithmetic with FP32 two-row links 1e-5; BF16 two-row links 1e-2
+  (links carry 2^-9 relative rounding; the stencil output error is a few 1e-3);
+* basis, little operator, projectors: 1e-10 (Gram-Schmidt and little-solve
+  conditioning amplify FP64 rounding);
+* solve: true residual recomputed by the oracle <= tol; solution error against
+  an oracle solve to 1e-12 below 1e-9 when the GPU also solves to 1e-12.
+"""
+import numpy as np
+import pytest
+
+import latgen
+import oracle
+from paper_0706_2298_amd import (BF16, F32, F64, PROJ_COARSE, PROJ_P, PROJ_PL, PROJ_PR, SOLVER_GCR,
+                                 SOLVER_SAP_GCR, DflError, Solver)
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+GEOMS = [
+    # dims, layout/deflation block, SAP block
+    ((8, 8, 8, 8), (4, 4, 4, 4), (4, 4, 4, 4)),
+    ((6, 4, 4, 10), (3, 2, 2, 5), (3, 2, 2, 5)),       # ragged: V = 960, 60-site blocks
+    ((16, 8, 8, 8), (4, 4, 4, 4), (8, 4, 4, 4)),       # SAP blocks span two layout blocks
+    ((4, 4, 2, 2), (2, 2, 1, 1), (2, 2, 1, 1)),
+]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    dims = (8, 8, 8, 8)
+    U = latgen.make_links(dims, 0.4, 1001)
+    eta = latgen.make_source(dims, 1002)
+    init = latgen.make_init_fields(dims, 8, 1003)
+    m0 = -0.2
+    Phi, A = oracle.setup(U, init, m0, dims, (4, 4, 4, 4), (4, 4, 4, 4), 5, 4, 3)
+    return dict(dims=dims, U=U, eta=eta, init=init, m0=m0, Phi=Phi, A=A)
+
+
+def make_solver(dims, b, sb, **kw):
+    kw.setdefault("Ns", 2)
+    kw.setdefault("nkv", 4)
+    return Solver(dims, dfl_block=b, sap_block=sb, **kw)
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+def test_pack_roundtrip(geom):
+    dims, b, sb = geom
+    say(f"pack {dims}")
+    S = make_solver(dims, b, sb, nrhs_max=2)
+    f = latgen.random_field(dims, 5, n=2)
+    nat = S.pack(f)
+    assert np.array_equal(S.unpack(nat), f)
+    nat32 = S.pack(f, prec=F32)
+    assert np.array_equal(S.unpack(nat32, prec=F32), f.astype(np.complex64).astype(np.complex128))
+    S.close()
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+def test_dirac_f64(geom):
+    dims, b, sb = geom
+    say(f"dirac f64 {dims}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.5, 11)
+    psi = latgen.random_field(dims, 12, n=3)
+    S = make_solver(dims, b, sb, m0=m0, nrhs_max=3)
+    S.set_gauge(U)
+    out = S.unpack(S.dirac(S.pack(psi)))
+    for r in range(3):
+        assert rel(out[r], oracle.dirac(U, psi[r], m0, dims)) < 1e-13
+    S.close()
+
+
+@pytest.mark.parametrize("link_prec,tol", [(F32, 1e-5), (BF16, 1e-2)])
+def test_dirac_f32_links(link_prec, tol):
+    dims, b, sb = GEOMS[0]
+    say(f"dirac f32 link_prec={link_prec}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.5, 21)
+    psi = latgen.make_source(dims, 22)
+    S = make_solver(dims, b, sb, m0=m0, link_prec=link_prec, sap_prec=F32)
+    S.set_gauge(U)
+    out = S.unpack(S.dirac(S.pack(psi, prec=F32), prec=F32), prec=F32)[0]
+    e = rel(out, oracle.dirac(U, psi, m0, dims))
+    assert e < tol
+    assert e > 1e-9          # it really ran in reduced precision
+    S.close()
+
+
+def test_dirac_full_size_sampled():
+    # the benchmark's stencil workload, 64 x 32^3, checked on sampled sites
+    dims = (64, 32, 32, 32)
+    say("dirac f64 64x32^3 sampled")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.4, 4101)
+    psi = latgen.make_source(dims, 4102)
+    S = Solver(dims, Ns=1, nkv=1, little_nkv=1, m0=m0)
+    S.set_gauge(U)
+    out = S.unpack(S.dirac(S.pack(psi)))[0]
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(7)
+    sites = np.concatenate([rng.integers(0, V, 3000), [0, V - 1, 32 ** 3 - 1, V - 32 ** 3]])
+    ref = oracle.dirac_sites(U, psi, m0, dims, sites)
+    assert rel(out[sites], ref) < 1e-13
+    S.close()
+
+
+@pytest.mark.parametrize("geom", GEOMS[:3])
+def test_sap_f64(geom):
+    dims, b, sb = geom
+    say(f"sap f64 {dims} sap_block={sb}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.4, 31)
+    rho = latgen.make_source(dims, 32)
+    S = make_solver(dims, b, sb, m0=m0, ncy=3, nmr=4)
+    S.set_gauge(U)
+    got = S.unpack(S.sap(S.pack(rho)))[0]
+    assert rel(got, oracle.sap(U, rho, m0, dims, sb, 3, 4)) < 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("link_prec,tol", [(F32, 1e-4), (BF16, 3e-2)])
+def test_sap_f32(link_prec, tol):
+    dims, b, sb = GEOMS[0]
+    say(f"sap f32 link_prec={link_prec}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.4, 41)
+    rho = latgen.make_source(dims, 42)
+    S = make_solver(dims, b, sb, m0=m0, ncy=5, nmr=4, sap_prec=F32, link_prec=link_prec)
+    S.set_gauge(U)
+    got = S.unpack(S.sap(S.pack(rho)))[0]
+    e = rel(got, oracle.sap(U, rho, m0, dims, sb, 5, 4))
+    assert 1e-9 < e < tol
+    S.close()
+
+
+def _c1_solver(c1, **kw):
+    kw.setdefault("Ns", 8)
+    kw.setdefault("n_inviter", 3)
+    S = Solver(c1["dims"], m0=c1["m0"], m0_setup=c1["m0"], ncy=5, nmr=4, **kw)
+    S.set_gauge(c1["U"])
+    S.setup(S.pack(c1["init"]))
+    return S
+
+
+def test_setup_basis_and_little_operator(c1):
+    say("setup c1")
+    S = _c1_solver(c1)
+    Phi = S.unpack(S.basis())
+    assert rel(Phi, c1["Phi"]) < 1e-10
+    A = S.little_operator()
+    assert rel(A, c1["A"]) < 1e-10
+    # mass shift: the little operator at another mass
+    S.set_mass(-0.3)
+    A2 = S.little_operator()
+    Ao = oracle.little_operator(c1["U"], c1["Phi"], -0.3, c1["dims"], (4, 4, 4, 4))
+    assert rel(A2, Ao) < 1e-10
+    S.close()
+
+
+def test_little_apply_and_solve(c1):
+    say("little apply/solve c1")
+    torch = pytest.importorskip("torch")
+    S = _c1_solver(c1)
+    dims, b = c1["dims"], (4, 4, 4, 4)
+    Nb, Ns = S.Nb, S.Ns
+    v = latgen.random_field((Nb, 1, 1, 1), 51).reshape(-1)[: Nb * Ns].reshape(Nb, Ns)
+    vd = torch.from_numpy(v.reshape(-1).copy()).cuda()
+    w = S.little_apply(vd).cpu().numpy().reshape(Nb, Ns)
+    assert rel(w, oracle.little_apply(c1["A"], v, dims, b)) < 1e-10
+    w32 = S.little_apply(vd.to(torch.complex64), prec=F32).cpu().numpy().reshape(Nb, Ns)
+    assert rel(w32, oracle.little_apply(c1["A"], v, dims, b)) < 1e-5
+    x, code, it = S.little_solve(vd, 1e-12)
+    assert code == 0 and it > 0
+    x = x.cpu().numpy().reshape(Nb, Ns)
+    ref = np.linalg.solve(oracle.little_dense(c1["A"], dims, b), v.reshape(-1)).reshape(Nb, Ns)
+    assert rel(x, ref) < 1e-9
+    S.close()
+
+
+def test_projectors(c1):
+    say("projectors c1")
+    S = _c1_solver(c1)
+    dims, b = c1["dims"], (4, 4, 4, 4)
+    dfl = oracle.Deflation(c1["U"], c1["Phi"], c1["A"], c1["m0"], dims, b)
+    y = latgen.make_source(dims, 61)
+    yd = S.pack(y)
+    for which, ref in [(PROJ_P, dfl.P(y)), (PROJ_COARSE, dfl.coarse(y)), (PROJ_PL, dfl.PL(y)), (PROJ_PR, dfl.PR(y))]:
+        got = S.unpack(S.project(which, yd))[0]
+        assert rel(got, ref) < 1e-9, which
+    S.close()
+
+
+def test_solve_dfl_sap_gcr_c1(c1):
+    say("solve DFL+SAP+GCR c1")
+    dims = c1["dims"]
+    S = _c1_solver(c1, tol=1e-10)
+    psi, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 0, info.as_dict()
+    psi = S.unpack(psi)[0]
+    r = c1["eta"] - oracle.dirac(c1["U"], psi, c1["m0"], dims)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(c1["eta"])
+    assert abs(info.rel_residual - np.linalg.norm(r) / np.linalg.norm(c1["eta"])) < 1e-12
+    S.close()
+    # solution error: GPU and oracle both to 1e-12
+    S = _c1_solver(c1, tol=1e-12)
+    psi, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 0
+    psi = S.unpack(psi)[0]
+    dfl = oracle.Deflation(c1["U"], c1["Phi"], c1["A"], c1["m0"], dims, (4, 4, 4, 4))
+    ref, _, ok = oracle.solve(c1["U"], c1["eta"], c1["m0"], dims, sap_block=(4, 4, 4, 4), dfl=dfl, tol=1e-12)
+    assert ok
+    assert np.linalg.norm(psi - ref) <= 1e-9 * np.linalg.norm(ref)
+    S.close()
+
+
+@pytest.mark.parametrize("solver", [SOLVER_GCR, SOLVER_SAP_GCR])
+def test_solve_undeflated(c1, solver):
+    say(f"solve solver={solver}")
+    dims = c1["dims"]
+    S = Solver(dims, m0=c1["m0"], Ns=2, nkv=32, solver=solver, tol=1e-10)
+    S.set_gauge(c1["U"])
+    psi, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 0
+    psi = S.unpack(psi)[0]
+    r = c1["eta"] - oracle.dirac(c1["U"], psi, c1["m0"], dims)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(c1["eta"])
+    S.close()
+
+
+def test_solve_mixed_precision(c1):
+    say("solve mixed precision c1")
+    dims = c1["dims"]
+    S = _c1_solver(c1, sap_prec=F32, link_prec=BF16, little_prec=F32, tol=1e-10)
+    psi, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 0, info.as_dict()
+    psi = S.unpack(psi)[0]
+    r = c1["eta"] - oracle.dirac(c1["U"], psi, c1["m0"], dims)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(c1["eta"])
+    S.close()
+
+
+def test_edge_cases(c1):
+    say("edge cases")
+    torch = pytest.importorskip("torch")
+    dims = c1["dims"]
+    S = _c1_solver(c1)
+    # zero source: zero solution, converged
+    z = S.field(1)
+    z.zero_()
+    psi, info = S.solve(z)
+    assert info.status == 0 and info.n_gcr == 0
+    assert float(psi.abs().max()) == 0.0
+    # non-finite source
+    bad = S.pack(c1["eta"])
+    bad[5] = complex(float("nan"), 0.0)
+    with pytest.raises(DflError) as e:
+        S.solve(bad)
+    assert e.value.code == -5
+    # too many right-hand sides
+    with pytest.raises(DflError) as e:
+        S.dirac(S.field(2))
+    assert e.value.code == -1
+    S.close()
+    # projection before setup
+    S = Solver(dims, Ns=2, m0=c1["m0"])
+    S.set_gauge(c1["U"])
+    with pytest.raises(DflError) as e:
+        S.project(PROJ_PL, S.pack(c1["eta"]))
+    assert e.value.code == -6
+    # linearly dependent start fields
+    init = np.stack([c1["init"][0], 2j * c1["init"][0]])
+    with pytest.raises(DflError) as e:
+        S.setup(S.pack(init))
+    assert e.value.code == -4
+    S.close()
+    # iteration limit: status NOT_CONVERGED, best iterate written
+    S = Solver(dims, m0=c1["m0"], Ns=2, solver=SOLVER_GCR, maxiter=3)
+    S.set_gauge(c1["U"])
+    psi, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 1 and info.n_gcr == 3 and info.rel_residual > 1e-10
+    S.close()
+    del torch
