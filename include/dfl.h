@@ -86,11 +86,13 @@ typedef struct {
     int Ns;             /* deflation fields per block, 1 <= Ns <= 12*|dfl_block| (and <= 64) */
     int ncy;            /* SAP cycles per application (>= 1) */
     int nmr;            /* minimal-residual steps per block solve (>= 1) */
-    int nkv;            /* Krylov vectors before a GCR restart (1..64) */
+    int nkv;            /* Krylov vectors before a GCR restart (1..64); with inexact
+                           inner projections a cycle also ends once its residue fell
+                           by 10*little_tol_in */
     int n_inviter;      /* inverse-iteration steps in dfl_setup (>= 0) */
     int maxiter;        /* outer GCR iteration limit */
     int nrhs_max;       /* largest nrhs any call will pass (>= 1) */
-    int little_nkv;     /* Krylov vectors of the little GCR (1..64) */
+    int little_nkv;     /* Krylov vectors of the little GCR (1..32) */
     int little_maxiter; /* little GCR iteration limit */
     dfl_solver solver;  /* variant run by solve() */
     double m0;          /* bare mass of D */
@@ -200,6 +202,12 @@ int deflate_project(dfl_ctx *ctx, dfl_proj which, const void *in_dev, void *out_
  * vector is zero). Synchronises; info (may be NULL) receives the statistics
  * of the last right-hand side. Returns DFL_NOT_CONVERGED after maxiter. */
 int solve(dfl_ctx *ctx, const void *eta_dev, void *psi_dev, int nrhs, dfl_info *info);
+
+/* Relative residue norms of the last outer GCR run (the initial one, then one
+ * per Krylov step, as updated by the recursion), the last right-hand side of
+ * the last solve(). Copies min(count, max) values to out (host memory) and
+ * returns count, or -1 for a null context or bad arguments. Host-only. */
+int dfl_residual_history(const dfl_ctx *ctx, double *out, int max);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *dfl_last_error(void);

@@ -55,7 +55,8 @@ _LIB = None
 EXPORTS = [
     "dfl_default_params", "dfl_create", "dfl_destroy", "dfl_set_mass", "dfl_field_bytes", "dfl_num_blocks",
     "dfl_set_gauge", "dfl_pack", "dfl_unpack", "dirac_apply", "sap_precond", "dfl_setup", "dfl_get_basis",
-    "dfl_get_little", "little_dirac_apply", "little_solve", "deflate_project", "solve", "dfl_last_error",
+    "dfl_get_little", "little_dirac_apply", "little_solve", "deflate_project", "solve", "dfl_residual_history",
+    "dfl_last_error",
 ]
 
 
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
         "little_solve": (i, [vp, vp, vp, d, P(i)]),
         "deflate_project": (i, [vp, i, vp, vp, i]),
         "solve": (i, [vp, vp, vp, i, P(Info)]),
+        "dfl_residual_history": (i, [vp, P(d), i]),
         "dfl_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -196,6 +198,16 @@ def little_solve(ctx, w, v, tol):
 
 def deflate_project(ctx, which, inp, out, nrhs=1):
     return _check(load().deflate_project(ctx, which, _ptr(inp), _ptr(out), nrhs))
+
+
+def dfl_residual_history(ctx):
+    L = load()
+    n = L.dfl_residual_history(ctx, None, 0)
+    if n < 0:
+        raise DflError(-1, "bad context")
+    buf = (ctypes.c_double * max(n, 1))()
+    L.dfl_residual_history(ctx, buf, n)
+    return list(buf[:n])
 
 
 def solve(ctx, eta, psi, nrhs=1):

@@ -61,7 +61,8 @@ void free_all(dfl_ctx* c)
 {
     void* ptrs[] = {c->U64, c->U32,  c->Ubf,  c->Phi, c->Phi32, c->A64, c->A32, c->xi,  c->chi,
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
-                    c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag};
+                    c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
+                    c->At64, c->At32, c->lpart, c->lstats};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -98,8 +99,10 @@ void validate(const dfl_params& p)
         fail(DFL_EINVAL, "Ns must be in 1..min(64, 12*|deflation block|)");
     if (p.ncy < 1 || p.nmr < 1)
         fail(DFL_EINVAL, "ncy and nmr must be >= 1");
-    if (p.nkv < 1 || p.nkv > kMaxDot || p.little_nkv < 1 || p.little_nkv > kMaxDot)
-        fail(DFL_EINVAL, "nkv and little_nkv must be in 1..64");
+    if (p.nkv < 1 || p.nkv > kMaxDot)
+        fail(DFL_EINVAL, "nkv must be in 1..64");
+    if (p.little_nkv < 1 || p.little_nkv > kMaxLittleNkv)
+        fail(DFL_EINVAL, "little_nkv must be in 1..32");
     if (p.n_inviter < 0 || p.maxiter < 1 || p.little_maxiter < 1 || p.nrhs_max < 1)
         fail(DFL_EINVAL, "n_inviter >= 0, maxiter >= 1, little_maxiter >= 1, nrhs_max >= 1 required");
     if (!(p.tol > 0.0) || !(p.little_tol_in > 0.0) || !(p.little_tol_out > 0.0))
@@ -223,7 +226,8 @@ template <typename T>
 GcrResult gcr_run(dfl_ctx* c, long n, int nkv, int maxiter, double tol, double src_norm, GcrVecs v,
                   const std::function<void(const cpx<T>*, cpx<T>*)>& precond,
                   const std::function<void(const cpx<T>*, cpx<T>*)>& op,
-                  const std::function<void(const cpx<T>*, cpx<T>*)>& recompute_residual)
+                  const std::function<void(const cpx<T>*, cpx<T>*)>& recompute_residual, double cycle_floor = 0.0,
+                  std::vector<double>* history_ = nullptr)
 {
     cpx<T>* xi = static_cast<cpx<T>*>(v.xi);
     cpx<T>* chi = static_cast<cpx<T>*>(v.chi);
@@ -235,6 +239,8 @@ GcrResult gcr_run(dfl_ctx* c, long n, int nkv, int maxiter, double tol, double s
         return res;
     // the caller has put the initial residue in r
     double rn = std::sqrt(host_norm2<T>(c, r, n));
+    if (history_)
+        history_->push_back(rn / src_norm);
     std::vector<cd> a((size_t)nkv * nkv), cc(nkv), alpha(nkv);
     std::vector<double> b(nkv);
     while (true) {
@@ -248,6 +254,7 @@ GcrResult gcr_run(dfl_ctx* c, long n, int nkv, int maxiter, double tol, double s
             return res;
         }
         int k = 0;
+        const double rn_cycle = rn;
         while (k < nkv && res.iters < maxiter) {
             cpx<T>* xk = xi + (long)k * n;
             cpx<T>* ck = chi + (long)k * n;
@@ -275,7 +282,9 @@ GcrResult gcr_run(dfl_ctx* c, long n, int nkv, int maxiter, double tol, double s
                 fail(b[k] == 0.0 ? DFL_ESINGULAR : DFL_ENONFINITE, "GCR breakdown: zero or non-finite Krylov image");
             ++k;
             ++res.iters;
-            if (rn <= tol * src_norm)
+            if (history_)
+                history_->push_back(rn / src_norm);
+            if (rn <= tol * src_norm || rn <= cycle_floor * rn_cycle)
                 break;
         }
         for (int i = k - 1; i >= 0; --i) {
@@ -300,74 +309,50 @@ GcrResult gcr_run(dfl_ctx* c, long n, int nkv, int maxiter, double tol, double s
 // ---------------------------------------------------------- little solve
 
 // v = A^{-1} w to ||w - A v|| <= tol ||w|| (eq. (6.1)); FP64 in and out.
-int little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec prec, int* iters)
+// One cooperative launch; iteration counts accumulate in c->lstats.
+void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec prec)
 {
     const long n = (long)c->g.Nb * c->p.Ns;
-    const Geom& g = c->g;
-    const int Ns = c->p.Ns;
-    GcrResult r;
     if (prec == DFL_F64) {
-        double wn = std::sqrt(host_norm2<double>(c, w, n));
-        launch_copy<double>(w, static_cast<c64*>(c->lr), n, c->stream);
-        GcrVecs vv{c->lxi, c->lchi, c->lr, v};
-        const c64* A = c->A64;
-        c64* lt = static_cast<c64*>(c->lt);
-        r = gcr_run<double>(
-            c, n, c->p.little_nkv, c->p.little_maxiter, tol, wn, vv,
-            [&](const c64* a, c64* b) { launch_copy<double>(a, b, n, c->stream); },
-            [&](const c64* a, c64* b) { launch_little_apply<double>(g, A, Ns, a, b, c->stream); },
-            [&](const c64* x, c64* rr) {
-                launch_little_apply<double>(g, A, Ns, x, lt, c->stream);
-                launch_sub<double>(w, lt, rr, n, c->stream);
-            });
+        launch_little_gcr<double>(c->g, c->p.Ns, c->p.little_nkv, c->p.little_maxiter, tol, c->At64, w, v,
+                                  static_cast<c64*>(c->lr), static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi),
+                                  c->lpart, c->lstats, c->stream);
     } else {
-        c32* w32 = c->lw32;
-        c32* v32 = c->lx32;
-        launch_f64_to_f32(w, w32, n, c->stream);
-        double wn = std::sqrt(host_norm2<float>(c, w32, n));
-        launch_copy<float>(w32, static_cast<c32*>(c->lr), n, c->stream);
-        GcrVecs vv{c->lxi, c->lchi, c->lr, v32};
-        const c32* A = c->A32;
-        c32* lt = static_cast<c32*>(c->lt);
-        r = gcr_run<float>(
-            c, n, c->p.little_nkv, c->p.little_maxiter, tol, wn, vv,
-            [&](const c32* a, c32* b) { launch_copy<float>(a, b, n, c->stream); },
-            [&](const c32* a, c32* b) { launch_little_apply<float>(g, A, Ns, a, b, c->stream); },
-            [&](const c32* x, c32* rr) {
-                launch_little_apply<float>(g, A, Ns, x, lt, c->stream);
-                launch_sub<float>(w32, lt, rr, n, c->stream);
-            });
-        launch_f32_to_f64(v32, v, n, c->stream);
+        launch_f64_to_f32(w, c->lw32, n, c->stream);
+        launch_little_gcr<float>(c->g, c->p.Ns, c->p.little_nkv, c->p.little_maxiter, tol, c->At32, c->lw32,
+                                 c->lx32, static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
+                                 static_cast<c32*>(c->lchi), c->lpart, c->lstats, c->stream);
+        launch_f32_to_f64(c->lx32, v, n, c->stream);
     }
-    if (iters)
-        *iters = r.iters;
-    return r.status;
 }
 
-struct SolveStats {
-    int n_little = 0;
-    int n_little_solves = 0;
-};
+void reset_little_stats(dfl_ctx* c) { HIPCHECK(hipMemsetAsync(c->lstats, 0, sizeof(int) * 4, c->stream)); }
+
+// [iterations, solves, failed] accumulated since the last reset (synchronises)
+void read_little_stats(dfl_ctx* c, int out[3])
+{
+    int h[4];
+    HIPCHECK(hipMemcpyAsync(h, c->lstats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+}
 
 // out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term); out may not alias in
-void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, SolveStats* st)
+void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec)
 {
     c64* w = static_cast<c64*>(c->lw);
     c64* x = static_cast<c64*>(c->lx);
     launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, c->stream);
-    int it = 0;
-    little_solve_impl(c, w, x, tol, prec, &it);
-    if (st) {
-        st->n_little += it;
-        st->n_little_solves += 1;
-    }
+    little_solve_impl(c, w, x, tol, prec);
     launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, c->stream);
 }
 
 // out = P_L in = in - D coarse(in)   (eq. (3.3)); uses t3 and the little buffers
-void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, SolveStats* st, c64* tmpA, c64* tmpB)
+void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c64* tmpA, c64* tmpB)
 {
-    coarse(c, in, tmpA, tol, prec, st);
+    coarse(c, in, tmpA, tol, prec);
     dirac64(c, tmpA, tmpB, c->p.m0);
     launch_sub<double>(in, tmpB, out, c->field_elems, c->stream);
 }
@@ -430,6 +415,16 @@ void dfl_default_params(dfl_params* p)
 
 const char* dfl_last_error(void) { return dfl::g_last_error.c_str(); }
 
+int dfl_residual_history(const dfl_ctx* c, double* out, int max)
+{
+    if (!c || max < 0 || (max > 0 && !out))
+        return -1;
+    int n = (int)c->history.size();
+    for (int i = 0; i < n && i < max; ++i)
+        out[i] = c->history[(size_t)i];
+    return n;
+}
+
 int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
 {
     dfl_ctx* c = nullptr;
@@ -465,6 +460,8 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->Phi = alloc_dev<c64>(c, (size_t)p->Ns * F);
         c->A64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->A32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
+        c->At64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
+        c->At32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->xi = alloc_dev<c64>(c, (size_t)p->nkv * F);
         c->chi = alloc_dev<c64>(c, (size_t)p->nkv * F);
         c->rho = alloc_dev<c64>(c, F);
@@ -483,12 +480,16 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->lt = alloc_dev<c64>(c, N);
         c->lw32 = alloc_dev<c32>(c, N);
         c->lx32 = alloc_dev<c32>(c, N);
+        c->lgrid = little_gcr_grid(c->g);
+        c->lpart = alloc_dev<double>(c, little_gcr_partial_doubles(c->lgrid));
+        c->lstats = alloc_dev<int>(c, 4);
         c->red = alloc_dev<double>(c, (size_t)kMaxDot * kRedBlocks * 2);
         c->dscal = alloc_dev<double>(c, S_TOTAL);
         c->dflag = alloc_dev<int>(c, 4);
         HIPCHECK(hipHostMalloc((void**)&c->hscal, sizeof(double) * S_TOTAL, hipHostMallocDefault));
         HIPCHECK(hipMemsetAsync(c->dscal, 0, sizeof(double) * S_TOTAL, c->stream));
         HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
+        HIPCHECK(hipMemsetAsync(c->lstats, 0, sizeof(int) * 4, c->stream));
         sync(c);
     } catch (...) {
         free_all(c);
@@ -529,7 +530,7 @@ int dfl_set_mass(dfl_ctx* c, double m0)
     if (c->have_subspace && m0 != c->m0_A) {
         // the basis is orthonormal, so A(m0') = A(m0) + (m0' - m0) 1
         launch_little_shift(c->g, c->A64, c->p.Ns, m0 - c->m0_A, c->stream);
-        launch_c64_to_c32(c->A64, c->A32, (long)c->g.Nb * 9 * c->p.Ns * c->p.Ns, c->stream);
+        launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, c->p.Ns, c->stream);
         c->m0_A = m0;
     }
     API_END
@@ -668,7 +669,8 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
             launch_little_column64(c->g, c->Phi, Ns, c->t1, c->A64, d, l, c->stream);
         }
     }
-    launch_c64_to_c32(c->A64, c->A32, nA, c->stream);
+    launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);
+    (void)nA;
     c->m0_A = c->p.m0;
     int flag[4];
     HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
@@ -730,7 +732,6 @@ int little_dirac_apply(dfl_ctx* c, const void* v, void* w, int nrhs, dfl_prec pr
 
 int little_solve(dfl_ctx* c, const void* w, void* v, double tol, int* iters)
 {
-    int st = DFL_OK;
     API_BEGIN
     need_ctx(c);
     need_ptr(w, "w");
@@ -738,11 +739,17 @@ int little_solve(dfl_ctx* c, const void* w, void* v, double tol, int* iters)
     need_subspace(c);
     if (!(tol > 0.0))
         fail(DFL_EINVAL, "tol must be positive");
-    st = little_solve_impl(c, static_cast<const c64*>(w), static_cast<c64*>(v), tol, DFL_F64, iters);
-    sync(c);
-    if (st != DFL_OK) {
-        g_last_error = "little solve did not converge";
-        return st;
+    if (w == v)
+        fail(DFL_EINVAL, "w and v must not overlap");
+    reset_little_stats(c);
+    little_solve_impl(c, static_cast<const c64*>(w), static_cast<c64*>(v), tol, DFL_F64);
+    int st[3];
+    read_little_stats(c, st);
+    if (iters)
+        *iters = st[0];
+    if (st[2]) {
+        g_last_error = "little solve did not converge within little_maxiter";
+        return DFL_NOT_CONVERGED;
     }
     API_END
 }
@@ -764,11 +771,11 @@ int deflate_project(dfl_ctx* c, dfl_proj which, const void* in, void* out, int n
         c64* y = static_cast<c64*>(out) + r * F;
         switch (which) {
         case DFL_PROJ_PL:
-            apply_PL(c, x, y, tol, DFL_F64, nullptr, c->t1, c->t2);
+            apply_PL(c, x, y, tol, DFL_F64, c->t1, c->t2);
             break;
         case DFL_PROJ_PR:
             dirac64(c, x, c->t1, c->p.m0);
-            coarse(c, c->t1, c->t2, tol, DFL_F64, nullptr);
+            coarse(c, c->t1, c->t2, tol, DFL_F64);
             launch_sub<double>(x, c->t2, y, F, c->stream);
             break;
         case DFL_PROJ_P:
@@ -776,7 +783,7 @@ int deflate_project(dfl_ctx* c, dfl_proj which, const void* in, void* out, int n
             launch_prolong64(c->g, c->Phi, c->p.Ns, static_cast<c64*>(c->lw), y, c->stream);
             break;
         case DFL_PROJ_COARSE:
-            coarse(c, x, y, tol, DFL_F64, nullptr);
+            coarse(c, x, y, tol, DFL_F64);
             break;
         default:
             fail(DFL_EINVAL, "unknown projector");
@@ -814,10 +821,10 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
         double eta_n = std::sqrt(host_norm2<double>(c, eta, F));
         if (flag)
             fail(DFL_ENONFINITE, "non-finite entries in the source");
-        SolveStats st;
+        reset_little_stats(c);
         // initial residue: P_L eta (deflated) or eta
         if (deflate)
-            apply_PL(c, eta, c->rho, c->p.little_tol_out, DFL_F64, &st, c->t1, c->t2);
+            apply_PL(c, eta, c->rho, c->p.little_tol_out, DFL_F64, c->t1, c->t2);
         else
             launch_copy<double>(eta, c->rho, F, c->stream);
         GcrVecs v{c->xi, c->chi, c->rho, c->acc};
@@ -831,7 +838,7 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
         auto op = [&](const c64* x, c64* y) {
             if (deflate) {
                 dirac64(c, x, c->t3, m0);
-                apply_PL(c, c->t3, y, c->p.little_tol_in, lp, &st, c->t1, c->t2);
+                apply_PL(c, c->t3, y, c->p.little_tol_in, lp, c->t1, c->t2);
             } else {
                 dirac64(c, x, y, m0);
             }
@@ -840,17 +847,24 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
             dirac64(c, x, c->t1, m0);
             if (deflate) {
                 launch_sub<double>(eta, c->t1, c->t3, F, c->stream);
-                apply_PL(c, c->t3, r, c->p.little_tol_out, DFL_F64, &st, c->t1, c->t2);
+                apply_PL(c, c->t3, r, c->p.little_tol_out, DFL_F64, c->t1, c->t2);
             } else {
                 launch_sub<double>(eta, c->t1, r, F, c->stream);
             }
         };
-        GcrResult res = gcr_run<double>(c, F, c->p.nkv, c->p.maxiter, c->p.tol, eta_n, v, precond, op, recompute);
+        // With inexact projections inside the cycle (little solves to
+        // little_tol_in), the recursively updated residue stops tracking the
+        // true one once it has fallen by about that factor; the cycle is then
+        // ended early and the residue recomputed (appendix A.5).
+        const double cycle_floor = deflate ? 10.0 * c->p.little_tol_in : 0.0;
+        c->history.clear();
+        GcrResult res = gcr_run<double>(c, F, c->p.nkv, c->p.maxiter, c->p.tol, eta_n, v, precond, op, recompute,
+                                        cycle_floor, &c->history);
         // final solution: psi = acc + Phi A^-1 Phi^+ (eta - D acc)   (eq. (3.10) with P_R)
         if (deflate) {
             dirac64(c, c->acc, c->t1, m0);
             launch_sub<double>(eta, c->t1, c->t3, F, c->stream);
-            coarse(c, c->t3, c->t1, c->p.little_tol_out, DFL_F64, &st);
+            coarse(c, c->t3, c->t1, c->p.little_tol_out, DFL_F64);
             launch_copy<double>(c->acc, psi, F, c->stream);
             // psi += t1 : coefficient 1 from a device scalar
             c->hscal[S_ALPHA] = 1.0;
@@ -876,8 +890,10 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
             info->status = status;
             info->n_gcr = res.iters;
             info->n_restarts = res.restarts;
-            info->n_little = st.n_little;
-            info->n_little_solves = st.n_little_solves;
+            int ls[3];
+            read_little_stats(c, ls);
+            info->n_little = ls[0];
+            info->n_little_solves = ls[1];
             info->rel_residual = rel;
             info->t_solve = std::chrono::duration<double>(t1 - t0).count();
         }

@@ -225,6 +225,23 @@ __global__ void k_little_shift(Geom g, c64* A, int Ns, double dm)
     A[((blk * 9) * Ns + k) * Ns + k].re += dm;
 }
 
+// A32[i] = A[i]; At[blk][d][l][k] = A[blk][d][k][l]
+__global__ void k_little_copies(const c64* __restrict__ A, c32* A32, c64* At64, c32* At32, long nblocks, int Ns)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long n = nblocks * Ns * Ns;
+    if (i >= n)
+        return;
+    long bd = i / ((long)Ns * Ns);
+    int rem = (int)(i - bd * Ns * Ns);
+    int k = rem / Ns, l = rem - k * Ns;
+    c64 v = A[i];
+    A32[i] = c32{(float)v.re, (float)v.im};
+    long j = bd * Ns * Ns + (long)l * Ns + k;
+    At64[j] = v;
+    At32[j] = c32{(float)v.re, (float)v.im};
+}
+
 __global__ void k_c64_to_c32(const c64* a, c32* b, long n)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -263,6 +280,13 @@ void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s
 {
     long n = (long)g.Nb * Ns;
     hipLaunchKernelGGL(k_little_shift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, A, Ns, dm);
+}
+void launch_little_copies(const c64* A, c32* A32, c64* At64, c32* At32, long nblocks, int Ns, hipStream_t s)
+{
+    long n = nblocks * Ns * Ns;
+    if (n > 0)
+        hipLaunchKernelGGL(k_little_copies, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, A32, At64, At32,
+                           nblocks, Ns);
 }
 void launch_c64_to_c32(const c64* a, c32* b, long n, hipStream_t s)
 {

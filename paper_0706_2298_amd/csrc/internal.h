@@ -52,6 +52,8 @@ struct LinksBF16 {
 constexpr int kRedBlocks = 480;   // fixed grid of the partial-sum kernels (deterministic)
 constexpr int kRedThreads = 256;
 constexpr int kMaxDot = 64;       // most vectors in one multi-dot
+constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
+constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
 
 }  // namespace dfl
 
@@ -74,7 +76,9 @@ struct dfl_ctx {
     dfl::c64* Phi = nullptr;   // [Ns][12][V]
     dfl::c32* Phi32 = nullptr; // FP32 copy (inner projections in mixed precision)
     dfl::c64* A64 = nullptr;   // [Nb][9][Ns][Ns] at m0_A
-    dfl::c32* A32 = nullptr;
+    dfl::c32* A32 = nullptr;   // FP32 copy, same layout
+    dfl::c64* At64 = nullptr;  // blocks transposed, [Nb][9][l][k] (little GCR kernel)
+    dfl::c32* At32 = nullptr;
     double m0_A = 0.0;
     bool have_subspace = false;
 
@@ -99,12 +103,16 @@ struct dfl_ctx {
     void* lt = nullptr;
     dfl::c32* lw32 = nullptr;  // FP32 little source and solution (mixed precision)
     dfl::c32* lx32 = nullptr;
+    double* lpart = nullptr;   // partial sums of the cooperative little GCR
+    int* lstats = nullptr;     // [iterations, solves, not-converged flag, spare]
+    int lgrid = 0;             // its grid size
     // reductions and scalars
     double* red = nullptr;       // kRedBlocks * 2 * kMaxDot partials
     double* dscal = nullptr;     // device scalars
     double* hscal = nullptr;     // pinned host mirror
     int* dflag = nullptr;        // device status flag
     size_t alloc_bytes = 0;
+    std::vector<double> history;  // outer GCR residues of the last solve
 };
 
 namespace dfl {
@@ -173,5 +181,16 @@ void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v
 // A[blk][0][k][k] += dm  (mass shift)
 void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s);
 void launch_c64_to_c32(const c64* a, c32* b, long n, hipStream_t s);
+// A32 = A, At64 = At32 = A with every Ns x Ns block transposed
+void launch_little_copies(const c64* A, c32* A32, c64* At64, c32* At32, long nblocks, int Ns, hipStream_t s);
+
+// ---------------------------------------------------------------- little.hip
+int little_gcr_grid(const Geom& g);
+size_t little_gcr_partial_doubles(int grid_size);
+// v = A^{-1} w by GCR to ||w - A v|| <= tol ||w|| in one cooperative launch;
+// r, xi, chi are workspaces; stats accumulates [iterations, solves, failed]
+template <typename T>
+void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
+                       cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, hipStream_t s);
 
 }  // namespace dfl

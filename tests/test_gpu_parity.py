@@ -292,3 +292,44 @@ def test_edge_cases(c1):
     assert info.status == 1 and info.n_gcr == 3 and info.rel_residual > 1e-10
     S.close()
     del torch
+
+
+def test_little_solve_fp32_and_reproducible(c1):
+    say("little solve reproducibility / FP32 inner")
+    torch = pytest.importorskip("torch")
+    S = _c1_solver(c1)
+    dims, b = c1["dims"], (4, 4, 4, 4)
+    Nb, Ns = S.Nb, S.Ns
+    v = latgen.random_field((Nb, 1, 1, 1), 52).reshape(-1)[: Nb * Ns]
+    vd = torch.from_numpy(v.copy()).cuda()
+    x1, code1, it1 = S.little_solve(vd, 1e-12)
+    x2, code2, it2 = S.little_solve(vd, 1e-12)
+    assert code1 == 0 and it1 == it2
+    assert torch.equal(x1, x2)          # fixed reduction order: bit-reproducible
+    ref = np.linalg.solve(oracle.little_dense(c1["A"], dims, b), v)
+    assert rel(x1.cpu().numpy(), ref) < 1e-9
+    # a looser tolerance needs fewer iterations
+    _, _, it6 = S.little_solve(vd, 1e-6)
+    assert 0 < it6 < it1
+    S.close()
+
+
+def test_solve_reproducible_and_history(c1):
+    say("solve reproducibility and residual history")
+    from paper_0706_2298_amd import binding
+    S = _c1_solver(c1, tol=1e-10)
+    eta = S.pack(c1["eta"])
+    p1, i1 = S.solve(eta)
+    h1 = binding.dfl_residual_history(S.ctx)
+    p2, i2 = S.solve(eta)
+    assert i1.n_gcr == i2.n_gcr and p1.equal(p2)
+    assert len(h1) == i1.n_gcr + 1 and h1[0] == pytest.approx(1.0, rel=0.5)
+    S.close()
+    # exact (undeflated) SAP+GCR: the minimal residue never grows
+    S = Solver(c1["dims"], m0=c1["m0"], Ns=2, nkv=32, solver=SOLVER_SAP_GCR, tol=1e-10)
+    S.set_gauge(c1["U"])
+    _, info = S.solve(S.pack(c1["eta"]))
+    h = binding.dfl_residual_history(S.ctx)
+    assert all(h[i + 1] <= h[i] * (1 + 1e-9) for i in range(len(h) - 1))
+    assert h[-1] <= 1e-10
+    S.close()
