@@ -1,27 +1,31 @@
 """Benchmark of the deflated SAP-GCR solver on one MI355X.
 
 Workload (one "step"): the 16^4 lattice at two gauge roughnesses (eps 0.4 and
-0.6, seeds 2001/2002); per gauge field one subspace setup (Ns = 20 fields,
-3 inverse-iteration steps, 4^4 blocks) reused for the three masses
-m0 = -0.2, -0.3, -0.35 (the subspace is generated once per gauge field and
-used at all valence masses), each solved to ||eta - D psi|| <= 1e-10 ||eta||
-with FP64 flexible GCR, FP32 Schwarz block solves (4^4 blocks, 5 cycles,
-4 MR steps) and FP64 little solves. value = solves per second over the
-whole step (setups included).
+0.6, seeds 2001/2002). Per gauge field one subspace setup (Ns = 20 fields,
+3 inverse-iteration steps, 4^4 blocks) is reused for the three masses
+m0 = -0.2, -0.3, -0.35, each solved to ||eta - D psi|| <= 1e-10 ||eta|| with
+FP64 flexible GCR (16 Krylov vectors), FP32 Schwarz block solves (4^4 blocks,
+5 cycles, 4 MR steps, FP32 two-row links) and FP64 little solves (1e-6 inside
+cycles, 1e-12 at restarts). value = solves per second over the whole step,
+setups included; all inputs are resident in HBM before the timed region.
 
-Besides the step the run reports:
+Also reported (outside the timed region):
+* the dominant kernel's roofline: one extra step with the library's event
+  timers on; algorithmic flops or bytes per launch over the measured launch
+  duration;
 * dirac_apply GFLOP/s and algorithmic GB/s on 64 x 32^3 (FP64 full links,
   FP32 and BF16 two-row links), a working set well above the 256 MB MALL;
-* the dominant kernel's roofline, timed with HIP events on the library stream;
-* undeflated SAP+GCR and plain GCR on the same fields (iterations, seconds);
+* undeflated SAP+GCR and plain FP64 GCR on the same fields;
 * the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -33,7 +37,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-FLOPS_PER_SITE = 1368            # Wilson stencil, per site per right-hand side
+FLOPS_PER_SITE = 1368            # Wilson stencil per site per right-hand side (1320 hop + 48 diagonal)
 BYTES_PER_SITE = {"f64": 960, "f32_tworow": 384, "bf16_tworow": 288}
 
 DIMS = (16, 16, 16, 16)
@@ -42,6 +46,14 @@ FIELDS = [(0.4, 2001), (0.6, 2002)]
 MASSES = [-0.2, -0.3, -0.35]
 NS, NCY, NMR, NKV, NINV = 20, 5, 4, 16, 3
 TOL = 1e-10
+V = int(np.prod(DIMS))
+NB = V // int(np.prod(BLOCK))
+
+
+def sap_flops_per_site(nmr):
+    # residual rho - D psi (1368 + 24), nmr MR steps of D_Lambda (1368) plus
+    # (q,r), (q,q), x += a r, r -= a q (96 + 48 + 96 + 96), and psi += x (24)
+    return 1368 + 24 + nmr * (1368 + 336) + 24
 
 
 def log(msg):
@@ -93,12 +105,91 @@ def time_events(torch, fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def profiled_step(ctxs):
+    """One more step with the library's kernel-class timers on."""
+    from paper_0706_2298_amd import binding
+    for c in ctxs:
+        binding.dfl_profile_read(c["S"].ctx)          # reset
+        binding.dfl_profile_enable(c["S"].ctx, True)
+    run_step(ctxs)
+    tot = {k: [0.0, 0] for k in binding.PROF_CLASSES}
+    little_it = 0
+    for c in ctxs:
+        p = binding.dfl_profile_read(c["S"].ctx)
+        binding.dfl_profile_enable(c["S"].ctx, False)
+        for k in binding.PROF_CLASSES:
+            tot[k][0] += p[k][0]
+            tot[k][1] += p[k][1]
+        little_it += p["little_iterations"]
+    return tot, little_it
+
+
+def source_digest(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_0706_2298_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"sap": ("sap.hip", "hop.h", "common.h"), "little": ("little.hip", "common.h"),
+                  "dirac": ("dirac.hip", "hop.h", "common.h"), "project": ("dfl.hip", "common.h")}
+
+
+def counter_traffic(cls, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    kernel, if it was taken on the current source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{cls}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source digest:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm bytes per launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != source_digest(*KERNEL_SOURCES[cls]):
+        return None
+    return float(b.group(1))
+
+
+def roofline(prof, little_it):
+    """Roofline object for the class that took the most time in the profiled step."""
+    cls = max(("sap", "little", "dirac", "project"), key=lambda k: prof[k][0])
+    sec, n = prof[cls]
+    dur = sec / max(n, 1)
+    if cls == "sap":
+        flops = sap_flops_per_site(NMR) * (V // 2)          # one colour sweep visits half the sites
+        ach = flops / dur / 1e12
+        r = dict(kernel="k_sap<float> (Schwarz colour sweep, FP32, 4^4 blocks)", bound="alu", achieved=ach,
+                 peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / FP32_VECTOR_PEAK_TFLOPS,
+                 per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {V // 2} sites")
+    elif cls == "little":
+        per_it = 16 * NB * (9 * NS * NS + 4 * NS)
+        byts = per_it * little_it / max(n, 1)
+        ach = byts / dur / 1e9
+        r = dict(kernel="k_little_gcr<double> (little GCR, one launch per solve)", bound="hbm", achieved=ach,
+                 peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                 per_launch=f"{byts:.4g} B = {little_it / max(n, 1):.1f} iterations x {per_it} B (A + 4 vectors)")
+    elif cls == "dirac":
+        byts = BYTES_PER_SITE["f64"] * V
+        ach = byts / dur / 1e9
+        r = dict(kernel="k_dirac<0,double>", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                 frac=ach / HBM_PEAK_GBS, per_launch=f"{byts} B = 960 B/site x {V}")
+    else:
+        byts = 192 * (NS + 1) * V
+        ach = byts / dur / 1e9
+        r = dict(kernel="k_restrict / k_prolong", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                 frac=ach / HBM_PEAK_GBS, per_launch=f"{byts} B = (Ns + 1) fields x 192 B/site")
+    r["avg_launch_us"] = dur * 1e6
+    r["launches_per_step"] = n
+    r["traffic"] = counter_traffic(cls, None)
+    return r, {k: dict(seconds=v[0], launches=v[1]) for k, v in prof.items()}
+
+
 def dirac_rates(torch):
     """dirac_apply on 64 x 32^3: FP64 full links, FP32 and BF16 two-row links."""
     import latgen
-    from paper_0706_2298_amd import BF16, F32, F64, Solver
+    from paper_0706_2298_amd import BF16, F32, F64, Solver, binding
     dims = (64, 32, 32, 32)
-    V = int(np.prod(dims))
+    vol = int(np.prod(dims))
     U = latgen.make_links(dims, 0.4, 4101)
     psi = latgen.make_source(dims, 4102)
     out = {}
@@ -108,15 +199,13 @@ def dirac_rates(torch):
         S.set_gauge(U)
         x = S.pack(psi, prec=prec)
         y = S.field(1, prec)
-        from paper_0706_2298_amd import binding
         t = time_events(torch, lambda: binding.dirac_apply(S.ctx, x, y, 1, prec), 40)
-        out[name] = dict(ms=t * 1e3, gflops=FLOPS_PER_SITE * V / t / 1e9,
-                         gbs=BYTES_PER_SITE[name] * V / t / 1e9,
-                         frac_hbm=BYTES_PER_SITE[name] * V / t / 1e9 / HBM_PEAK_GBS)
+        gbs = BYTES_PER_SITE[name] * vol / t / 1e9
+        out[name] = dict(ms=t * 1e3, gflops=FLOPS_PER_SITE * vol / t / 1e9, gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
         S.close()
         del x, y
     torch.cuda.empty_cache()
-    return out
+    return dict(lattice=list(dims), bytes_per_site=BYTES_PER_SITE, flops_per_site=FLOPS_PER_SITE, **out)
 
 
 def undeflated(torch, fields):
@@ -142,11 +231,10 @@ def undeflated(torch, fields):
 def cpu_baseline(fields, stats):
     """The FP64 oracle on a bounded sample of the step, scaled to solves/s.
 
-    Sample: for the eps = 0.4 field, one Schwarz application, one inverse-
-    iteration normalisation, the block Gram-Schmidt and little-operator
-    assembly on the 20 start fields (without relaxation), and two iterations
-    of the deflated GCR at m0 = -0.3; the step's cost is then the GPU run's
-    own operation counts (setup SAP applications, GCR iterations, restarts)
+    Sample: for the eps = 0.4 field, two Schwarz applications, the block
+    Gram-Schmidt and little-operator assembly on the 20 start fields, and
+    three iterations of the deflated GCR at m0 = -0.3. The step's cost is the
+    GPU run's own operation counts (setup SAP applications, GCR iterations)
     times these unit costs.
     """
     import oracle
@@ -154,41 +242,29 @@ def cpu_baseline(fields, stats):
     U, eta, init = f["U"], f["eta"], f["init"]
     m0 = -0.3
     t0 = time.perf_counter()
-    oracle.sap(U, eta, m0, DIMS, BLOCK, NCY, NMR)
-    t_sap = time.perf_counter() - t0
+    for _ in range(2):
+        oracle.sap(U, eta, m0, DIMS, BLOCK, NCY, NMR)
+    t_sap = (time.perf_counter() - t0) / 2
     t0 = time.perf_counter()
     Phi = oracle.block_gram_schmidt(init, DIMS, BLOCK)
-    t_gs = time.perf_counter() - t0
-    t0 = time.perf_counter()
     A = oracle.little_operator(U, Phi, m0, DIMS, BLOCK)
-    t_little_op = time.perf_counter() - t0
+    t_subspace = time.perf_counter() - t0
     dfl = oracle.Deflation(U, Phi, A, m0, DIMS, BLOCK)
     t0 = time.perf_counter()
-    _, it, _ = oracle.solve(U, eta, m0, DIMS, sap_block=BLOCK, ncy=NCY, nmr=NMR, dfl=dfl, tol=1e-30, maxiter=2)
-    t_two = time.perf_counter() - t0
-    sample_s = t_sap + t_gs + t_little_op + t_two
-    # per-iteration cost (the two-iteration solve also pays one initial projection, one restart and the final step)
-    t_iter = t_two / 2.0
+    oracle.solve(U, eta, m0, DIMS, sap_block=BLOCK, ncy=NCY, nmr=NMR, dfl=dfl, tol=1e-30, maxiter=3)
+    t_three = time.perf_counter() - t0
+    sample_s = 2 * t_sap + t_subspace + t_three
+    t_iter = t_three / 3.0
     n_setup_sap = len(fields) * NS * NINV
     n_iter = sum(s["n_gcr"] for s in stats)
-    est = n_setup_sap * t_sap + len(fields) * (t_gs + t_little_op) + n_iter * t_iter
+    est = n_setup_sap * t_sap + len(fields) * t_subspace + n_iter * t_iter
     n_solves = len(stats)
     return dict(value=n_solves / est, unit="solves/s", cores=oracle.num_threads(), kind="oracle",
-                sample=(f"16^4 eps=0.4: 1 SAP application ({t_sap:.2f}s), block GS + little operator on 20 fields "
-                        f"({t_gs + t_little_op:.2f}s), 2 deflated GCR iterations ({t_two:.2f}s); scaled by the "
-                        f"step's {n_setup_sap} setup SAP applications and {n_iter} GCR iterations "
-                        f"-> {est:.1f}s per step of {n_solves} solves"),
+                sample=(f"16^4 eps=0.4 field: 2 SAP applications ({t_sap:.2f}s each), block GS + little operator "
+                        f"on 20 fields ({t_subspace:.2f}s), 3 deflated GCR iterations ({t_three:.2f}s); scaled by "
+                        f"the step's {n_setup_sap} setup SAP applications, 2 subspace builds and {n_iter} GCR "
+                        f"iterations -> {est:.1f}s per step of {n_solves} solves"),
                 sample_seconds=sample_s)
-
-
-def dominant_kernel_roofline(torch, ctx_entry):
-    """SAP colour sweep (FP32, 4^4 blocks) timed alone with HIP events."""
-    from paper_0706_2298_amd import binding
-    S = ctx_entry["S"]
-    rho = ctx_entry["eta"]
-    psi = S.field(1)
-    t_sap = time_events(torch, lambda: binding.sap_precond(S.ctx, rho, psi, 1), 20)
-    return t_sap
 
 
 def main():
@@ -199,9 +275,13 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dirac", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (y = 1.0 * x), to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this solver build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not implemented)"}))
         sys.exit(2)
 
     import torch
@@ -210,6 +290,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_read_bytes": x.numel() * 8, "copy_write_bytes": y.numel() * 8, "dispatches": 5}))
+        return
 
     log("generating inputs")
     fields = make_inputs()
@@ -247,14 +335,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "16^4 DFL+SAP+GCR, eps {0.4,0.6}, m0 {-0.2,-0.3,-0.35}, Ns 20, 4^4 blocks, "
-                               "FP64 GCR + FP32 SAP, tol 1e-10",
+        "config": {"workload": "16^4 DFL+SAP+GCR: eps {0.4,0.6} x m0 {-0.2,-0.3,-0.35}, one setup per field "
+                               "(Ns 20, 3 inverse-iteration steps, 4^4 blocks), FP64 GCR + FP32 SAP, tol 1e-10",
                    "lattice": list(DIMS), "Ns": NS, "n_inviter": NINV, "ncy": NCY, "nmr": NMR, "nkv": NKV,
                    "solves_per_step": n_solves},
+        "time_to_solution_s": {f"eps{s['eps']}_m{s['m0']}": s["t_solve"] for s in stats},
         "solves": stats,
     }
-    t_sap = dominant_kernel_roofline(torch, ctxs[0])
-    result["sap_precond_ms"] = t_sap * 1e3
+    if not args.no_profile:
+        log("profiled step")
+        prof, little_it = profiled_step(ctxs)
+        result["roofline"], result["kernel_time_per_step"] = roofline(prof, little_it)
     for c in ctxs:
         c["S"].close()
     ctxs.clear()

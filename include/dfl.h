@@ -209,6 +209,24 @@ int solve(dfl_ctx *ctx, const void *eta_dev, void *psi_dev, int nrhs, dfl_info *
  * returns count, or -1 for a null context or bad arguments. Host-only. */
 int dfl_residual_history(const dfl_ctx *ctx, double *out, int max);
 
+/* Kernel-class timers. When enabled, the context records a pair of HIP
+ * events on its stream around every launch of the classes below (a small
+ * overhead per launch); dfl_profile_read synchronises and returns the summed
+ * seconds and launch counts per class since the last reset, then resets.
+ * Classes: */
+enum {
+    DFL_PROF_SAP = 0,      /* Schwarz colour sweeps (one launch per colour and cycle) */
+    DFL_PROF_DIRAC = 1,    /* full-lattice Dirac operator inside the solvers and dirac_apply */
+    DFL_PROF_LITTLE = 2,   /* little GCR (one cooperative launch per little solve) */
+    DFL_PROF_PROJECT = 3,  /* block restriction and prolongation */
+    DFL_PROF_SETUP = 4,    /* little-operator assembly and block Gram-Schmidt */
+    DFL_PROF_NCLASS = 5
+};
+int dfl_profile_enable(dfl_ctx *ctx, int on);
+/* seconds[DFL_PROF_NCLASS], launches[DFL_PROF_NCLASS] (host memory); little_iters
+ * (may be NULL) receives the little GCR iterations of the same launches. */
+int dfl_profile_read(dfl_ctx *ctx, double *seconds, long long *launches, long long *little_iters);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *dfl_last_error(void);
 

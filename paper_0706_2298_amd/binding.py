@@ -56,8 +56,9 @@ EXPORTS = [
     "dfl_default_params", "dfl_create", "dfl_destroy", "dfl_set_mass", "dfl_field_bytes", "dfl_num_blocks",
     "dfl_set_gauge", "dfl_pack", "dfl_unpack", "dirac_apply", "sap_precond", "dfl_setup", "dfl_get_basis",
     "dfl_get_little", "little_dirac_apply", "little_solve", "deflate_project", "solve", "dfl_residual_history",
-    "dfl_last_error",
+    "dfl_profile_enable", "dfl_profile_read", "dfl_last_error",
 ]
+PROF_CLASSES = ["sap", "dirac", "little", "project", "setup"]
 
 
 def load(path: str = LIB_PATH):
@@ -91,6 +92,8 @@ def load(path: str = LIB_PATH):
         "deflate_project": (i, [vp, i, vp, vp, i]),
         "solve": (i, [vp, vp, vp, i, P(Info)]),
         "dfl_residual_history": (i, [vp, P(d), i]),
+        "dfl_profile_enable": (i, [vp, i]),
+        "dfl_profile_read": (i, [vp, P(d), P(ctypes.c_longlong), P(ctypes.c_longlong)]),
         "dfl_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -208,6 +211,22 @@ def dfl_residual_history(ctx):
     buf = (ctypes.c_double * max(n, 1))()
     L.dfl_residual_history(ctx, buf, n)
     return list(buf[:n])
+
+
+def dfl_profile_enable(ctx, on=True):
+    return _check(load().dfl_profile_enable(ctx, 1 if on else 0))
+
+
+def dfl_profile_read(ctx):
+    """{class: (seconds, launches)}, plus the little GCR iterations, since the last read."""
+    n = len(PROF_CLASSES)
+    t = (ctypes.c_double * n)()
+    k = (ctypes.c_longlong * n)()
+    it = ctypes.c_longlong(0)
+    _check(load().dfl_profile_read(ctx, t, k, ctypes.byref(it)))
+    out = {PROF_CLASSES[j]: (t[j], int(k[j])) for j in range(n)}
+    out["little_iterations"] = int(it.value)
+    return out
 
 
 def solve(ctx, eta, psi, nrhs=1):

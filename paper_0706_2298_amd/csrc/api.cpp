@@ -62,7 +62,7 @@ void free_all(dfl_ctx* c)
     void* ptrs[] = {c->U64, c->U32,  c->Ubf,  c->Phi, c->Phi32, c->A64, c->A32, c->xi,  c->chi,
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
-                    c->At64, c->At32, c->lpart, c->lstats};
+                    c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -153,6 +153,59 @@ void need_nrhs(const dfl_ctx* c, int nrhs)
 
 void sync(dfl_ctx* c) { HIPCHECK(hipStreamSynchronize(c->stream)); }
 
+// ------------------------------------------------------------- profiling
+
+hipEvent_t prof_event(dfl_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    return e;
+}
+
+// records an event pair around the launches in its scope when profiling is on
+struct ProfScope {
+    dfl_ctx* c;
+    int cls;
+    hipEvent_t e0 = nullptr;
+    ProfScope(dfl_ctx* cc, int k) : c(cc), cls(k)
+    {
+        if (c->prof_on) {
+            e0 = prof_event(c);
+            HIPCHECK(hipEventRecord(e0, c->stream));
+        }
+    }
+    ~ProfScope()
+    {
+        if (e0) {
+            hipEvent_t e1 = prof_event(c);
+            if (hipEventRecord(e1, c->stream) == hipSuccess)
+                c->ev_pending.push_back({cls, {e0, e1}});
+        }
+    }
+};
+
+// fold recorded event pairs into the per-class sums (synchronises)
+void prof_collect(dfl_ctx* c)
+{
+    if (c->ev_pending.empty())
+        return;
+    sync(c);
+    for (auto& p : c->ev_pending) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        c->prof_t[p.first] += ms * 1e-3;
+        c->prof_n[p.first] += 1;
+        c->ev_pool.push_back(p.second.first);
+        c->ev_pool.push_back(p.second.second);
+    }
+    c->ev_pending.clear();
+}
+
 // copy the first n device scalars to the pinned host mirror and wait
 void download(dfl_ctx* c, int n)
 {
@@ -173,6 +226,7 @@ template <typename T> double host_norm2(dfl_ctx* c, const cpx<T>* x, long n)
 
 void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0)
 {
+    ProfScope ps(c, DFL_PROF_DIRAC);
     launch_dirac64(c->g, links64(c), in, out, 1, m0, 0, 0, 0, c->stream);
 }
 
@@ -183,14 +237,17 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0)
     if (c->p.sap_prec == DFL_F64) {
         launch_zero<double>(psi, n, c->stream);
         for (int cy = 0; cy < c->p.ncy; ++cy)
-            for (int col = 0; col < 2; ++col)
+            for (int col = 0; col < 2; ++col) {
+                ProfScope ps(c, DFL_PROF_SAP);
                 launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, c->stream);
+            }
         return;
     }
     launch_f64_to_f32(rho, c->s32a, n, c->stream);
     launch_zero<float>(c->s32b, n, c->stream);
     for (int cy = 0; cy < c->p.ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
+            ProfScope ps(c, DFL_PROF_SAP);
             if (c->p.link_prec == DFL_BF16)
                 launch_sap_colour_bf16(c->g, c->sg, linksbf(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col,
                                        c->stream);
@@ -314,14 +371,17 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
 {
     const long n = (long)c->g.Nb * c->p.Ns;
     if (prec == DFL_F64) {
+        ProfScope ps(c, DFL_PROF_LITTLE);
         launch_little_gcr<double>(c->g, c->p.Ns, c->p.little_nkv, c->p.little_maxiter, tol, c->At64, w, v,
                                   static_cast<c64*>(c->lr), static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi),
-                                  c->lpart, c->lstats, c->stream);
+                                  c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->stream);
     } else {
         launch_f64_to_f32(w, c->lw32, n, c->stream);
+        ProfScope ps(c, DFL_PROF_LITTLE);
         launch_little_gcr<float>(c->g, c->p.Ns, c->p.little_nkv, c->p.little_maxiter, tol, c->At32, c->lw32,
                                  c->lx32, static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
-                                 static_cast<c32*>(c->lchi), c->lpart, c->lstats, c->stream);
+                                 static_cast<c32*>(c->lchi), c->lpart, c->lstats, c->lbar_count, c->lbar_gen,
+                                 c->stream);
         launch_f32_to_f64(c->lx32, v, n, c->stream);
     }
 }
@@ -336,7 +396,11 @@ void read_little_stats(dfl_ctx* c, int out[3])
     sync(c);
     out[0] = h[0];
     out[1] = h[1];
-    out[2] = h[2];
+    out[2] = h[2] & 1;
+    if (c->prof_on)
+        c->prof_little_iters += h[0];
+    if (h[2] & 4)
+        fail(DFL_EHIP, "little solver: grid barrier timed out");
 }
 
 // out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term); out may not alias in
@@ -344,8 +408,12 @@ void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec)
 {
     c64* w = static_cast<c64*>(c->lw);
     c64* x = static_cast<c64*>(c->lx);
-    launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, c->stream);
+    {
+        ProfScope ps(c, DFL_PROF_PROJECT);
+        launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, c->stream);
+    }
     little_solve_impl(c, w, x, tol, prec);
+    ProfScope ps(c, DFL_PROF_PROJECT);
     launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, c->stream);
 }
 
@@ -415,6 +483,34 @@ void dfl_default_params(dfl_params* p)
 
 const char* dfl_last_error(void) { return dfl::g_last_error.c_str(); }
 
+int dfl_profile_enable(dfl_ctx* c, int on)
+{
+    API_BEGIN
+    need_ctx(c);
+    prof_collect(c);
+    c->prof_on = on != 0;
+    API_END
+}
+
+int dfl_profile_read(dfl_ctx* c, double* seconds, long long* launches, long long* little_iters)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(seconds, "seconds");
+    need_ptr(launches, "launches");
+    prof_collect(c);
+    for (int k = 0; k < DFL_PROF_NCLASS; ++k) {
+        seconds[k] = c->prof_t[k];
+        launches[k] = c->prof_n[k];
+        c->prof_t[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    if (little_iters)
+        *little_iters = c->prof_little_iters;
+    c->prof_little_iters = 0;
+    API_END
+}
+
 int dfl_residual_history(const dfl_ctx* c, double* out, int max)
 {
     if (!c || max < 0 || (max > 0 && !out))
@@ -483,6 +579,8 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->lgrid = little_gcr_grid(c->g);
         c->lpart = alloc_dev<double>(c, little_gcr_partial_doubles(c->lgrid));
         c->lstats = alloc_dev<int>(c, 4);
+        c->lbar_count = alloc_dev<unsigned>(c, 64);
+        c->lbar_gen = alloc_dev<unsigned long long>(c, 32);
         c->red = alloc_dev<double>(c, (size_t)kMaxDot * kRedBlocks * 2);
         c->dscal = alloc_dev<double>(c, S_TOTAL);
         c->dflag = alloc_dev<int>(c, 4);
@@ -490,6 +588,8 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         HIPCHECK(hipMemsetAsync(c->dscal, 0, sizeof(double) * S_TOTAL, c->stream));
         HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
         HIPCHECK(hipMemsetAsync(c->lstats, 0, sizeof(int) * 4, c->stream));
+        HIPCHECK(hipMemsetAsync(c->lbar_count, 0, sizeof(unsigned) * 64, c->stream));
+        HIPCHECK(hipMemsetAsync(c->lbar_gen, 0, sizeof(unsigned long long) * 32, c->stream));
         sync(c);
     } catch (...) {
         free_all(c);
@@ -506,6 +606,12 @@ int dfl_destroy(dfl_ctx* c)
     if (!c)
         return DFL_OK;
     (void)hipStreamSynchronize(c->stream);
+    for (auto& p : c->ev_pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool)
+        (void)hipEventDestroy(e);
     free_all(c);
     delete c;
     API_END
@@ -594,6 +700,7 @@ int dirac_apply(dfl_ctx* c, const void* psi, void* out, int nrhs, dfl_prec prec)
     need_nrhs(c, nrhs);
     if (psi == out)
         fail(DFL_EINVAL, "psi and out must not overlap");
+    ProfScope ps(c, DFL_PROF_DIRAC);
     if (prec == DFL_F64)
         launch_dirac64(c->g, links64(c), static_cast<const c64*>(psi), static_cast<c64*>(out), nrhs, c->p.m0, 0, 0,
                        0, c->stream);
@@ -655,6 +762,7 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
             launch_scale_invsqrt<double>(f, F, c->dscal + S_B, c->stream);
         }
     // block restriction and Gram-Schmidt, eq. (4.2)
+    ProfScope ps_setup(c, DFL_PROF_SETUP);
     launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->stream);
     // little operator, eq. (A.1): block-diagonal part and the eight face hops
     const long nA = (long)c->g.Nb * 9 * Ns * Ns;

@@ -53,7 +53,7 @@ constexpr int kRedBlocks = 480;   // fixed grid of the partial-sum kernels (dete
 constexpr int kRedThreads = 256;
 constexpr int kMaxDot = 64;       // most vectors in one multi-dot
 constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
-constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
+constexpr int kLittleMaxGrid = 64;   // workgroups of the cooperative little GCR
 
 }  // namespace dfl
 
@@ -104,7 +104,9 @@ struct dfl_ctx {
     dfl::c32* lw32 = nullptr;  // FP32 little source and solution (mixed precision)
     dfl::c32* lx32 = nullptr;
     double* lpart = nullptr;   // partial sums of the cooperative little GCR
-    int* lstats = nullptr;     // [iterations, solves, not-converged flag, spare]
+    int* lstats = nullptr;     // [iterations, solves, failure flags, spare]
+    unsigned* lbar_count = nullptr;         // grid barrier of the little GCR kernel
+    unsigned long long* lbar_gen = nullptr;
     int lgrid = 0;             // its grid size
     // reductions and scalars
     double* red = nullptr;       // kRedBlocks * 2 * kMaxDot partials
@@ -113,6 +115,13 @@ struct dfl_ctx {
     int* dflag = nullptr;        // device status flag
     size_t alloc_bytes = 0;
     std::vector<double> history;  // outer GCR residues of the last solve
+    // kernel-class timers
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;                 // free events
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double prof_t[8] = {0};
+    long long prof_n[8] = {0};
+    long long prof_little_iters = 0;
 };
 
 namespace dfl {
@@ -191,6 +200,7 @@ size_t little_gcr_partial_doubles(int grid_size);
 // r, xi, chi are workspaces; stats accumulates [iterations, solves, failed]
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
-                       cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, hipStream_t s);
+                       cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
+                       unsigned long long* bar_gen, hipStream_t s);
 
 }  // namespace dfl

@@ -3,35 +3,36 @@
 //
 // The little vector has Nb*Ns entries; workgroup g owns the blocks
 // g, g + G, g + 2G, ... (G = grid size) and all entries of those blocks. One
-// GCR step needs three grid-wide barriers:
+// GCR step normally needs two grid-wide barriers:
 //   S1  r is complete: reduce ||r||^2, test convergence, then apply
 //       chi_k = A r (rows of the owned blocks; the nine neighbour blocks'
 //       entries of r are read from global memory);
-//   S2  after the first classical Gram-Schmidt pass: reduce (chi_j, chi_k);
-//   S3  after the second pass: reduce (chi_j, chi_k'), ||chi_k'||^2,
-//       (chi_k', r) and (chi_j, r); the normalised chi_k, its coefficient c_k
-//       and the new residue follow without another reduction.
+//   S2  reduce (chi_j, chi_k), (chi_j, r) for j < k, ||chi_k||^2 and
+//       (chi_k, r) in one pass; classical Gram-Schmidt then gives the
+//       normalised chi_k, its coefficient c_k = (chi_k, r) and the new residue
+//       without another reduction (||chi_k - sum a_j chi_j||^2 =
+//       ||chi_k||^2 - sum |a_j|^2).
+// If that single pass cancels more than 99% of ||chi_k||^2 (orthogonality
+// would suffer), a second pass with its own barrier S3 repeats it.
 // Partial sums are written per workgroup and every workgroup reduces them in
 // the same fixed order, so all workgroups take identical decisions and the
 // result is bit-reproducible. After nkv steps (or convergence) the solution
 // is updated from the triangular system and the residue recomputed as
-// w - A x (two more barriers).
-#include <hip/hip_cooperative_groups.h>
-
+// w - A x (two more barriers). The barriers are this file's own (see
+// grid_barrier); the launch is cooperative so all workgroups are resident.
 #include "internal.h"
-
-namespace cg = cooperative_groups;
 
 namespace dfl {
 
 namespace {
 
-constexpr int LT = 256;
+constexpr int LT = 1024;            // threads per workgroup (16 wavefronts)
+constexpr long kSpinLimit = 1L << 24;  // ~0.5 s of polling before a barrier gives up
 constexpr int NK = kMaxLittleNkv;
 // partial-sum slots
-constexpr int SA = 0;                 // (chi_j, chi_k), j < k
-constexpr int SB = NK;                // (chi_j, chi_k') j<k | (chi_j, r) j<k | ||chi_k'||^2 | (chi_k', r)
-constexpr int SC = NK + 2 * NK + 2;   // ||r||^2 inside a cycle
+constexpr int SA = 0;                 // first pass: (chi_j, chi_k) j<k | (chi_j, r) j<k | ||chi_k||^2 | (chi_k, r)
+constexpr int SB = 2 * NK + 2;        // second pass, same layout
+constexpr int SC = 4 * NK + 4;        // ||r||^2 inside a cycle
 constexpr int SR = SC + 1;            // ||r||^2 after a restart
 constexpr int SW = SC + 2;            // ||w||^2
 constexpr int NSLOT = SC + 3;
@@ -47,8 +48,42 @@ template <typename T> struct LittleArgs {
     cpx<T>* xi;            // nkv * N
     cpx<T>* chi;           // nkv * N
     double* part;          // NSLOT * G complex partial sums
-    int* stats;            // [0] += iterations, [1] += solves, [2] |= 1 on non-convergence
+    int* stats;            // [0] += iterations, [1] += solves, [2] |= 1 not converged, |= 4 barrier timeout
+    unsigned* bar_count;   // grid barrier: arrivals (0 between barriers)
+    unsigned long long* bar_gen;  // grid barrier: generation, increases across launches
 };
+
+// Grid-wide barrier for a cooperative launch (all workgroups co-resident).
+// Thread 0 of each workgroup counts in; the last arrival resets the counter
+// and publishes the next generation, the others poll it. The generation
+// word is never reset, so a launch starts from the value the previous one
+// left (read once at kernel entry). The poll is bounded: on timeout the
+// workgroup records a failure and continues, so every wave reaches the end.
+__device__ inline void grid_barrier(unsigned* count, unsigned long long* gen, unsigned long long& target, int* stats)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ++target;
+        __threadfence();
+        unsigned old = atomicAdd(count, 1u);
+        if (old == gridDim.x - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            __hip_atomic_store(gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spin = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spin > kSpinLimit) {
+                    atomicOr(&stats[2], 4);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
 
 __device__ inline double2 cfma_conj(double2 acc, double ar, double ai, double br, double bi)
 {
@@ -90,44 +125,70 @@ __device__ inline void reduce_slots(const double* __restrict__ part, int G, int 
     __syncthreads();
 }
 
-// y = A v on the rows this workgroup owns
+// y = A v on the rows this workgroup owns. Task (blk, d, k) forms the
+// d-th neighbour term of row k of block blk (Ns multiply-adds over l, reading
+// At[blk][d][l][k] coalesced in k); the nine terms of a row are then summed
+// from LDS in a fixed order. Blocks are processed bpr = max(1, LT / (9 Ns))
+// at a time. lds holds 2 * max(LT, 9 * 64) doubles.
 template <typename T>
-__device__ inline void apply_rows(const LittleCtx<T>& c, const cpx<T>* __restrict__ v, cpx<T>* __restrict__ y)
+__device__ inline void apply_rows(const LittleCtx<T>& c, const cpx<T>* __restrict__ v, cpx<T>* __restrict__ y,
+                                  double* lds)
 {
     const Geom& g = c.a.g;
     const int Ns = c.a.Ns;
-    for (int e = c.t; e < c.R; e += LT) {
-        const int i = e / Ns;
-        const int k = e - i * Ns;
-        const int blk = c.g + i * c.G;
-        int n[4];
-        int rest = blk;
-        for (int mu = 3; mu >= 0; --mu) {
-            n[mu] = rest % g.nb[mu];
-            rest /= g.nb[mu];
-        }
-        double re = 0.0, im = 0.0;
-        for (int d = 0; d < 9; ++d) {
-            int nbr = blk;
-            if (d > 0) {
-                const int mu = (d - 1) >> 1;
-                int nn = n[mu] + ((d & 1) ? 1 : -1);
-                if (nn < 0)
-                    nn += g.nb[mu];
-                if (nn >= g.nb[mu])
-                    nn -= g.nb[mu];
-                nbr = blk + (nn - n[mu]) * g.bstr[mu];
+    const int per = 9 * Ns;
+    const int bpr = per <= LT ? LT / per : 1;
+    for (int i0 = 0; i0 < c.nbg; i0 += bpr) {
+        for (int task0 = 0; task0 < bpr * per; task0 += LT) {
+            const int task = task0 + c.t;
+            const int ib = task / per;
+            const int rem = task - ib * per;
+            const int d = rem / Ns;
+            const int k = rem - d * Ns;
+            if (ib < bpr && i0 + ib < c.nbg) {
+                const int blk = c.g + (i0 + ib) * c.G;
+                int nbr = blk;
+                if (d > 0) {
+                    const int mu = (d - 1) >> 1;
+                    int rest = blk;
+                    for (int nu = 3; nu > mu; --nu)
+                        rest /= g.nb[nu];
+                    const int n_mu = rest % g.nb[mu];
+                    int nn = n_mu + ((d & 1) ? 1 : -1);
+                    if (nn < 0)
+                        nn += g.nb[mu];
+                    if (nn >= g.nb[mu])
+                        nn -= g.nb[mu];
+                    nbr = blk + (nn - n_mu) * g.bstr[mu];
+                }
+                const cpx<T>* At = c.a.At + ((long)blk * 9 + d) * Ns * Ns + k;
+                const cpx<T>* vv = v + (long)nbr * Ns;
+                double re = 0.0, im = 0.0;
+#pragma unroll 4
+                for (int l = 0; l < Ns; ++l) {
+                    cpx<T> p = At[(long)l * Ns];
+                    cpx<T> q = vv[l];
+                    re += (double)p.re * (double)q.re - (double)p.im * (double)q.im;
+                    im += (double)p.re * (double)q.im + (double)p.im * (double)q.re;
+                }
+                lds[2 * task] = re;
+                lds[2 * task + 1] = im;
             }
-            const cpx<T>* At = c.a.At + ((long)blk * 9 + d) * Ns * Ns + k;
-            const cpx<T>* vv = v + (long)nbr * Ns;
-            for (int l = 0; l < Ns; ++l) {
-                cpx<T> p = At[(long)l * Ns];
-                cpx<T> q = vv[l];
-                re += (double)p.re * (double)q.re - (double)p.im * (double)q.im;
-                im += (double)p.re * (double)q.im + (double)p.im * (double)q.re;
+        }
+        __syncthreads();
+        for (int q = c.t; q < bpr * Ns; q += LT) {
+            const int jb = q / Ns, kk = q - jb * Ns;
+            if (i0 + jb < c.nbg) {
+                double sr = 0.0, si = 0.0;
+                for (int dd = 0; dd < 9; ++dd) {
+                    sr += lds[2 * (jb * per + dd * Ns + kk)];
+                    si += lds[2 * (jb * per + dd * Ns + kk) + 1];
+                }
+                const int blk = c.g + (i0 + jb) * c.G;
+                y[(long)blk * Ns + kk] = cpx<T>{(T)sr, (T)si};
             }
         }
-        y[(long)blk * Ns + k] = cpx<T>{(T)re, (T)im};
+        __syncthreads();
     }
 }
 
@@ -147,36 +208,59 @@ __device__ inline void partial_norm2(const LittleCtx<T>& c, const cpx<T>* __rest
     }
 }
 
-// (X_j, y) for j < m over the owned entries, one thread per j -> part[slot0 + j][g]
+// Partial sums of one Gram-Schmidt pass over the owned entries, one wavefront
+// per slot: (chi_j, y) and (chi_j, r) for j < k, ||y||^2 and (y, r), written
+// to part[slot0 ...][g].
 template <typename T>
-__device__ inline void partial_dots(const LittleCtx<T>& c, const cpx<T>* X, int m, const cpx<T>* __restrict__ y,
-                                    int slot0)
+__device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, int k, const cpx<T>* __restrict__ y,
+                                    const cpx<T>* __restrict__ r, int slot0)
 {
-    if (c.t < m) {
-        const cpx<T>* xj = X + (long)c.t * c.N;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int e = 0; e < c.R; ++e) {
-            long i = c.entry(e);
-            cpx<T> a = xj[i], b = y[i];
-            acc = cfma_conj(acc, (double)a.re, (double)a.im, (double)b.re, (double)b.im);
+    const int lane = c.t & 63, w = c.t >> 6;
+    const int ns = 2 * k + 2;
+    for (int s = w; s < ns; s += LT / 64) {
+        const cpx<T>* u;
+        const cpx<T>* v;
+        if (s < k) {
+            u = chi + (long)s * c.N;
+            v = y;
+        } else if (s < 2 * k) {
+            u = chi + (long)(s - k) * c.N;
+            v = r;
+        } else {
+            u = y;
+            v = (s == 2 * k) ? y : r;
         }
-        c.a.part[((long)(slot0 + c.t) * c.G + c.g) * 2] = acc.x;
-        c.a.part[((long)(slot0 + c.t) * c.G + c.g) * 2 + 1] = acc.y;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int e = lane; e < c.R; e += 64) {
+            long i = c.entry(e);
+            cpx<T> p = u[i], q = v[i];
+            acc = cfma_conj(acc, (double)p.re, (double)p.im, (double)q.re, (double)q.im);
+        }
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
+        if (lane == 0) {
+            c.a.part[((long)(slot0 + s) * c.G + c.g) * 2] = acc.x;
+            c.a.part[((long)(slot0 + s) * c.G + c.g) * 2 + 1] = acc.y;
+        }
     }
 }
 
 template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleArgs<T> a)
 {
-    cg::grid_group grid = cg::this_grid();
     __shared__ double red[2 * (2 * NK + 2)];
     __shared__ double acoef[NK][NK][2];
     __shared__ double bcoef[NK];
     __shared__ double ccoef[NK][2];
     __shared__ double alpha[NK][2];
-    __shared__ double sh[8];
+    __shared__ double sh[16];
     __shared__ double wn2_s, rn2_s;
+    __shared__ int second_s;
+    __shared__ double lds[2 * (9 * 64 > LT ? 9 * 64 : LT)];
 
     LittleCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
+    unsigned long long bar_target = 0;
+    if (c.t == 0)
+        bar_target = __hip_atomic_load(a.bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     c.nbg = (a.g.Nb - c.g + c.G - 1) / c.G;
     c.R = c.nbg * a.Ns;
     const long N = c.N;
@@ -188,7 +272,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
         a.r[i] = a.w[i];
     }
     partial_norm2(c, a.w, SW, sh);
-    grid.sync();
+    grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
     reduce_slots(a.part, c.G, SW, 1, red);
     if (c.t == 0)
         wn2_s = red[0];
@@ -211,20 +295,29 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
                 xk[i] = a.r[i];
             }
             partial_norm2(c, a.r, SC, sh);
-            grid.sync();  // S1: r complete everywhere
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S1: r complete everywhere
             reduce_slots(a.part, c.G, SC, 1, red);
             if (c.t == 0)
                 rn2_s = red[0];
             __syncthreads();
             if (k > 0 && rn2_s <= a.tol2 * wn2)
                 break;  // converged with k directions
-            apply_rows(c, xk, ck);
+            apply_rows(c, xk, ck, lds);
+            // one Gram-Schmidt pass: everything needed for chi_k, c_k and the new r
+            partial_pass(c, a.chi, k, ck, a.r, SA);
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
+            reduce_slots(a.part, c.G, SA, 2 * k + 2, red);
+            // red: [0,k) a_j; [k,2k) (chi_j, r); 2k: ||chi_k||^2; 2k+1: (chi_k, r)
+            if (c.t == 0) {
+                double n2 = red[4 * k];
+                double b2 = n2;
+                for (int j = 0; j < k; ++j)
+                    b2 -= red[2 * j] * red[2 * j] + red[2 * j + 1] * red[2 * j + 1];
+                second_s = (k > 0 && !(b2 >= 0.01 * n2)) ? 1 : 0;
+            }
             __syncthreads();
-            if (k > 0)
-                partial_dots(c, a.chi, k, ck, SA);
-            grid.sync();  // S2
-            if (k > 0) {
-                reduce_slots(a.part, c.G, SA, k, red);
+            if (second_s) {
+                // heavy cancellation: subtract the first projections, then a second pass
                 for (int e = c.t; e < c.R; e += LT) {
                     long i = c.entry(e);
                     double yr = (double)ck[i].re, yi = (double)ck[i].im;
@@ -240,26 +333,14 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
                     acoef[c.t][k][1] = red[2 * c.t + 1];
                 }
                 __syncthreads();
+                partial_pass(c, a.chi, k, ck, a.r, SB);
+                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S3
+                reduce_slots(a.part, c.G, SB, 2 * k + 2, red);
+            } else if (c.t < k) {
+                acoef[c.t][k][0] = 0.0;
+                acoef[c.t][k][1] = 0.0;
             }
-            // second pass and the remaining scalars in one reduction
-            partial_dots(c, a.chi, k, ck, SB);
-            partial_dots(c, a.chi, k, a.r, SB + k);
-            if (c.t == 0) {
-                double2 n2 = make_double2(0.0, 0.0), cr = make_double2(0.0, 0.0);
-                for (int e = 0; e < c.R; ++e) {
-                    long i = c.entry(e);
-                    cpx<T> z = ck[i], q = a.r[i];
-                    n2 = cfma_conj(n2, (double)z.re, (double)z.im, (double)z.re, (double)z.im);
-                    cr = cfma_conj(cr, (double)z.re, (double)z.im, (double)q.re, (double)q.im);
-                }
-                a.part[((long)(SB + 2 * k) * c.G + c.g) * 2] = n2.x;
-                a.part[((long)(SB + 2 * k) * c.G + c.g) * 2 + 1] = 0.0;
-                a.part[((long)(SB + 2 * k + 1) * c.G + c.g) * 2] = cr.x;
-                a.part[((long)(SB + 2 * k + 1) * c.G + c.g) * 2 + 1] = cr.y;
-            }
-            grid.sync();  // S3
-            reduce_slots(a.part, c.G, SB, 2 * k + 2, red);
-            // red: [0,k) a2_j; [k,2k) (chi_j, r); 2k: ||chi_k'||^2; 2k+1: (chi_k', r)
+            // red now holds the (last) pass: a_j, (chi_j, r), ||chi||^2, (chi, r)
             if (c.t == 0) {
                 double b2 = red[4 * k];
                 double crr = red[4 * k + 2], cri = red[4 * k + 3];
@@ -267,7 +348,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
                     double ar = red[2 * j], ai = red[2 * j + 1];
                     double qr = red[2 * (k + j)], qi = red[2 * (k + j) + 1];
                     b2 -= ar * ar + ai * ai;
-                    // (chi_k'', r) = (chi_k', r) - sum conj(a2_j) (chi_j, r)
+                    // (chi - sum a_j chi_j, r) = (chi, r) - sum conj(a_j) (chi_j, r)
                     crr -= ar * qr + ai * qi;
                     cri -= ar * qi - ai * qr;
                     acoef[j][k][0] += ar;
@@ -328,15 +409,15 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             a.x[i] = cpx<T>{(T)yr, (T)yi};
         }
         // recompute r = w - A x
-        grid.sync();
-        apply_rows(c, a.x, a.r);
+        grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+        apply_rows(c, a.x, a.r, lds);
         __syncthreads();
         for (int e = c.t; e < c.R; e += LT) {
             long i = c.entry(e);
             a.r[i] = cpx<T>{(T)((double)a.w[i].re - (double)a.r[i].re), (T)((double)a.w[i].im - (double)a.r[i].im)};
         }
         partial_norm2(c, a.r, SR, sh);
-        grid.sync();
+        grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
         reduce_slots(a.part, c.G, SR, 1, red);
         if (c.t == 0)
             rn2_s = red[0];
@@ -353,8 +434,8 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
 
 template <typename T>
 void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
-                 cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, int grid_size,
-                 hipStream_t s)
+                 cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
+                 unsigned long long* bar_gen, int grid_size, hipStream_t s)
 {
     LittleArgs<T> a;
     a.g = g;
@@ -370,6 +451,8 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
     a.chi = chi;
     a.part = part;
     a.stats = stats;
+    a.bar_count = bar_count;
+    a.bar_gen = bar_gen;
     void* args[] = {&a};
     HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_little_gcr<T>), dim3(grid_size), dim3(LT),
                                         args, 0, s));
@@ -377,24 +460,32 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
 
 }  // namespace
 
+// Few, wide workgroups: the barrier cost grows with the workgroup count, so
+// each 1024-thread workgroup owns about eight blocks.
 int little_gcr_grid(const Geom& g)
 {
-    int G = g.Nb < kLittleMaxGrid ? g.Nb : kLittleMaxGrid;
-    return G < 1 ? 1 : G;
+    int G = g.Nb / 8;
+    if (G > kLittleMaxGrid)
+        G = kLittleMaxGrid;
+    if (G < 1)
+        G = 1;
+    return G;
 }
 
 size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * grid_size * 2; }
 
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
-                       cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, hipStream_t s)
+                       cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
+                       unsigned long long* bar_gen, hipStream_t s)
 {
-    launch_impl<T>(g, Ns, nkv, maxiter, tol, At, w, x, r, xi, chi, part, stats, little_gcr_grid(g), s);
+    launch_impl<T>(g, Ns, nkv, maxiter, tol, At, w, x, r, xi, chi, part, stats, bar_count, bar_gen,
+                   little_gcr_grid(g), s);
 }
 
 template void launch_little_gcr<double>(const Geom&, int, int, int, double, const c64*, const c64*, c64*, c64*, c64*,
-                                        c64*, double*, int*, hipStream_t);
+                                        c64*, double*, int*, unsigned*, unsigned long long*, hipStream_t);
 template void launch_little_gcr<float>(const Geom&, int, int, int, double, const c32*, const c32*, c32*, c32*, c32*,
-                                       c32*, double*, int*, hipStream_t);
+                                       c32*, double*, int*, unsigned*, unsigned long long*, hipStream_t);
 
 }  // namespace dfl
