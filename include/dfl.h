@@ -80,7 +80,8 @@ typedef enum {
 } dfl_solver;
 
 typedef struct {
-    int dims[4];        /* L0..L3, x0 slowest; each a multiple of both block shapes */
+    int dims[4];        /* L0..L3, x0 slowest; each a multiple of both block shapes;
+                           volume a multiple of 64 and at most 2^22 sites */
     int sap_block[4];   /* Schwarz blocks; dims[mu]/sap_block[mu] even and >= 2 */
     int dfl_block[4];   /* deflation blocks; dims[mu]/dfl_block[mu] even and >= 2 */
     int Ns;             /* deflation fields per block, 1 <= Ns <= 12*|dfl_block| (and <= 64) */

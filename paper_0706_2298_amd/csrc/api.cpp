@@ -87,8 +87,11 @@ void validate(const dfl_params& p)
         if (p.dims[mu] < 2)
             fail(DFL_EINVAL, "lattice extent must be >= 2 in every direction");
     double V = (double)p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
-    if (V * 12 > 2.0e9)
-        fail(DFL_EINVAL, "lattice too large for one device field");
+    // 64-site tiles; 32-bit byte offsets into the FP64 link array (36 x 16 B per site)
+    if (V > 4194304.0)
+        fail(DFL_EINVAL, "lattice volume must be at most 2^22 sites");
+    if (std::fmod(V, 64.0) != 0.0)
+        fail(DFL_EINVAL, "lattice volume must be a multiple of 64 sites");
     check_blocks(p.dims, p.sap_block, "SAP");
     check_blocks(p.dims, p.dfl_block, "deflation");
     int vsb = p.sap_block[0] * p.sap_block[1] * p.sap_block[2] * p.sap_block[3];

@@ -115,12 +115,25 @@ template <typename T> struct spinor {
 
 // ------------------------------------------------------------- layout
 //
-// Native quark field: 12 planes (component c = 3*spin + colour) of V complex
-// values, plane-major: element (c, site) at c*V + site. Sites are numbered
-// block-major over the deflation ("layout") blocks:
+// Native quark field: sites are grouped in tiles of 64 (one wavefront); inside
+// a tile the 12 components (c = 3*spin + colour) are stored one after the
+// other, each as 64 consecutive complex values: element (s, c) at
+// ((s / 64) * 12 + c) * 64 + s % 64. A wavefront's spinors are thus one
+// contiguous 12 KB (FP64) run, and each component load is a 1 KB line.
+// Links use the same tiling with 36 (FP64, 4 x 3 x 3) or 24 (two-row, 4 x 2 x 3)
+// entries per site. Sites are numbered block-major over the deflation
+// ("layout") blocks:
 //   site = blk*Vb + ((y0*b1 + y1)*b2 + y2)*b3 + y3,
 //   blk  = ((n0*nb1 + n1)*nb2 + n2)*nb3 + n3,
 // with x_mu = n_mu*b_mu + y_mu. Every block is a contiguous run of Vb sites.
+
+constexpr int kTile = 64;
+
+// index of entry c (of ncomp per site) of site s in the tiled layout
+__host__ __device__ inline long tidx(long s, int c, int ncomp)
+{
+    return ((s >> 6) * ncomp + c) * kTile + (s & (kTile - 1));
+}
 
 struct Geom {
     int L[4];     // lattice extent

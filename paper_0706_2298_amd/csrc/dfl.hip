@@ -28,8 +28,8 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
                 long s = base + t;
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
-                    c64 a = ph[(long)c * g.V + s];
-                    c64 b = psi[(long)c * g.V + s];
+                    c64 a = ph[tidx(s, c, 12)];
+                    c64 b = psi[tidx(s, c, 12)];
                     re += a.re * b.re + a.im * b.im;
                     im += a.re * b.im - a.im * b.re;
                 }
@@ -71,11 +71,11 @@ __global__ __launch_bounds__(256) void k_prolong(Geom g, const c64* __restrict__
         const c64* ph = Phi + (long)k * fs;
 #pragma unroll
         for (int c = 0; c < 12; ++c)
-            acc[c] += ph[(long)c * g.V + s] * vk;
+            acc[c] += ph[tidx(s, c, 12)] * vk;
     }
 #pragma unroll
     for (int c = 0; c < 12; ++c)
-        psi[(long)c * g.V + s] = acc[c];
+        psi[tidx(s, c, 12)] = acc[c];
 }
 
 // Modified Gram-Schmidt per block, in place, order l = 0..Ns-1 (eq. (4.2)).
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
         double n0 = 0.0;
         for (int t = threadIdx.x; t < g.Vb; t += kBT)
             for (int c = 0; c < 12; ++c) {
-                c64 a = fl[(long)c * g.V + base + t];
+                c64 a = fl[tidx(base + t, c, 12)];
                 n0 += a.re * a.re + a.im * a.im;
             }
         n0 = block_sum(n0, sh);
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
             double re = 0.0, im = 0.0;
             for (int t = threadIdx.x; t < g.Vb; t += kBT)
                 for (int c = 0; c < 12; ++c) {
-                    long i = (long)c * g.V + base + t;
+                    long i = tidx(base + t, c, 12);
                     c64 a = fk[i], b = fl[i];
                     re += a.re * b.re + a.im * b.im;
                     im += a.re * b.im - a.im * b.re;
@@ -111,14 +111,14 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
             c64 cf{re, im};
             for (int t = threadIdx.x; t < g.Vb; t += kBT)
                 for (int c = 0; c < 12; ++c) {
-                    long i = (long)c * g.V + base + t;
+                    long i = tidx(base + t, c, 12);
                     fl[i] -= cf * fk[i];
                 }
         }
         double nv = 0.0;
         for (int t = threadIdx.x; t < g.Vb; t += kBT)
             for (int c = 0; c < 12; ++c) {
-                c64 a = fl[(long)c * g.V + base + t];
+                c64 a = fl[tidx(base + t, c, 12)];
                 nv += a.re * a.re + a.im * a.im;
             }
         nv = sqrt(block_sum(nv, sh));
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
         double inv = 1.0 / nv;
         for (int t = threadIdx.x; t < g.Vb; t += kBT)
             for (int c = 0; c < 12; ++c) {
-                long i = (long)c * g.V + base + t;
+                long i = tidx(base + t, c, 12);
                 fl[i].re *= inv;
                 fl[i].im *= inv;
             }
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBT) void k_little_column(Geom g, const c64* __rest
         for (int t = threadIdx.x; t < g.Vb; t += kBT)
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                long i = (long)c * g.V + base + t;
+                long i = tidx(base + t, c, 12);
                 c64 a = ph[i], b = Y[i];
                 re += a.re * b.re + a.im * b.im;
                 im += a.re * b.im - a.im * b.re;

@@ -13,10 +13,7 @@ namespace dfl {
 
 __device__ inline float bf16_to_f(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 
-// Loads take a uniform plane base and a 32-bit byte offset, so the compiler
-// can use the scalar-base + 32-bit vector-offset addressing form instead of
-// one 64-bit address per load. Fields hold fewer than 2^28 sites (checked at
-// context creation), so s * sizeof(element) fits in 32 bits.
+// Loads take a uniform base and a 32-bit byte offset (see toff).
 template <typename E> __device__ inline E ld(const E* __restrict__ plane, uint32_t byte_off)
 {
     return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(plane) + byte_off);
@@ -26,29 +23,32 @@ template <typename E> __device__ inline void st(E* __restrict__ plane, uint32_t 
     *reinterpret_cast<E*>(reinterpret_cast<char*>(plane) + byte_off) = v;
 }
 
+// byte offset of entry c (of ncomp per site) of site s; fits 32 bits because
+// fields hold fewer than 2^24 sites (checked at context creation)
+template <typename E> __device__ inline uint32_t toff(long s, int c, int ncomp)
+{
+    return (uint32_t)tidx(s, c, ncomp) * (uint32_t)sizeof(E);
+}
+
 __device__ inline su3<double> load_link(const Links64& L, int mu, long s)
 {
     su3<double> u;
-    const c64* p = L.u + (long)mu * 9 * L.V;
-    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(c64);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            u.m[a][b] = ld(p + (long)(a * 3 + b) * L.V, o);
+            u.m[a][b] = ld(L.u, toff<c64>(s, mu * 9 + a * 3 + b, 36));
     return u;
 }
 
 __device__ inline su3<float> load_link(const Links32& L, int mu, long s)
 {
     su3<float> u;
-    const c32* p = L.u + (long)mu * 6 * L.V;
-    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(c32);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            u.m[a][b] = ld(p + (long)(a * 3 + b) * L.V, o);
+            u.m[a][b] = ld(L.u, toff<c32>(s, mu * 6 + a * 3 + b, 24));
     complete_third_row(u);
     return u;
 }
@@ -56,13 +56,11 @@ __device__ inline su3<float> load_link(const Links32& L, int mu, long s)
 __device__ inline su3<float> load_link(const LinksBF16& L, int mu, long s)
 {
     su3<float> u;
-    const uint32_t* p = L.u + (long)mu * 6 * L.V;
-    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(uint32_t);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            uint32_t w = ld(p + (long)(a * 3 + b) * L.V, o);
+            uint32_t w = ld(L.u, toff<uint32_t>(s, mu * 6 + a * 3 + b, 24));
             u.m[a][b] = c32{bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
         }
     complete_third_row(u);
@@ -71,24 +69,24 @@ __device__ inline su3<float> load_link(const LinksBF16& L, int mu, long s)
 
 template <typename T> __device__ inline spinor<T> load_spinor(const cpx<T>* __restrict__ f, long V, long s)
 {
+    (void)V;
     spinor<T> p;
-    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(cpx<T>);
 #pragma unroll
     for (int al = 0; al < 4; ++al)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            p.s[al].c[a] = ld(f + (long)(3 * al + a) * V, o);
+            p.s[al].c[a] = ld(f, toff<cpx<T>>(s, 3 * al + a, 12));
     return p;
 }
 
 template <typename T> __device__ inline void store_spinor(cpx<T>* __restrict__ f, long V, long s, const spinor<T>& p)
 {
-    const uint32_t o = (uint32_t)s * (uint32_t)sizeof(cpx<T>);
+    (void)V;
 #pragma unroll
     for (int al = 0; al < 4; ++al)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            st(f + (long)(3 * al + a) * V, o, p.s[al].c[a]);
+            st(f, toff<cpx<T>>(s, 3 * al + a, 12), p.s[al].c[a]);
 }
 
 template <typename T> __device__ inline void zero(spinor<T>& p)

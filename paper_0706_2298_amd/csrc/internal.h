@@ -53,7 +53,7 @@ constexpr int kRedBlocks = 480;   // fixed grid of the partial-sum kernels (dete
 constexpr int kRedThreads = 256;
 constexpr int kMaxDot = 64;       // most vectors in one multi-dot
 constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
-constexpr int kLittleMaxGrid = 64;   // workgroups of the cooperative little GCR
+constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
 
 }  // namespace dfl
 

@@ -1,9 +1,10 @@
 // Canonical <-> native conversions of quark fields, and link compression.
 //
 // Canonical quark field: complex128 [V][12] in lexicographic site order.
-// Native quark field: 12 planes of V complex values in block-major site order
-// (common.h). Links: FP64 full 3x3 [4][9][V]; FP32 and BF16 store the first
-// two rows only ([4][6][V]), the third row being rebuilt as conj(row0 x row1).
+// Native quark field: 64-site tiles of 12 components in block-major site
+// order (common.h). Links: FP64 full 3x3 (36 entries per site); FP32 and BF16
+// store the first two rows only (24 entries per site), the third row being
+// rebuilt as conj(row0 x row1).
 #include "internal.h"
 
 namespace dfl {
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(256) void k_pack_field(Geom g, const c64* __restric
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         c64 v = src[k];
-        dst[(long)k * g.V + s] = cpx<T>{(T)v.re, (T)v.im};
+        dst[tidx(s, k, 12)] = cpx<T>{(T)v.re, (T)v.im};
     }
 }
 
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(256) void k_unpack_field(Geom g, const cpx<T>* __re
     const cpx<T>* src = nat + (long)r * 12 * g.V;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        cpx<T> v = src[(long)k * g.V + s];
+        cpx<T> v = src[tidx(s, k, 12)];
         dst[k] = c64{(double)v.re, (double)v.im};
     }
 }
@@ -79,13 +80,12 @@ __global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const c64* __restric
         for (int k = 0; k < 9; ++k) {
             c64 v = src[k];
             if (U64)
-                U64[(long)(mu * 9 + k) * g.V + s] = v;
+                U64[tidx(s, mu * 9 + k, 36)] = v;
             if (k < 6) {
                 if (U32)
-                    U32[(long)(mu * 6 + k) * g.V + s] = c32{(float)v.re, (float)v.im};
+                    U32[tidx(s, mu * 6 + k, 24)] = c32{(float)v.re, (float)v.im};
                 if (Ubf)
-                    Ubf[(long)(mu * 6 + k) * g.V + s] =
-                        bf16_bits((float)v.re) | (bf16_bits((float)v.im) << 16);
+                    Ubf[tidx(s, mu * 6 + k, 24)] = bf16_bits((float)v.re) | (bf16_bits((float)v.im) << 16);
             }
         }
     }

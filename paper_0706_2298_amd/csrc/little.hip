@@ -54,25 +54,30 @@ template <typename T> struct LittleArgs {
 };
 
 // Grid-wide barrier for a cooperative launch (all workgroups co-resident).
-// Thread 0 of each workgroup counts in; the last arrival resets the counter
-// and publishes the next generation, the others poll it. The generation
-// word is never reset, so a launch starts from the value the previous one
-// left (read once at kernel entry). The poll is bounded: on timeout the
-// workgroup records a failure and continues, so every wave reaches the end.
+// Thread 0 of each workgroup publishes the workgroup's writes with one
+// agent-scope release fence, counts in with a relaxed atomic, and (unless it
+// is the last to arrive) polls the generation word with relaxed coherent
+// loads; one agent-scope acquire fence follows. The last arrival resets the
+// counter and publishes the next generation. Acquire/release semantics on
+// every poll would make each poll an L2 invalidation, which serialises
+// across the device; this form costs one cache write-back and one
+// invalidation per workgroup and barrier. The generation word is never
+// reset: a launch continues from the value the previous one left (read once
+// at entry). Polling is bounded; on timeout the workgroup records a failure
+// and continues, so every wave reaches the end.
 __device__ inline void grid_barrier(unsigned* count, unsigned long long* gen, unsigned long long& target, int* stats)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         ++target;
-        __threadfence();
-        unsigned old = atomicAdd(count, 1u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        unsigned old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == gridDim.x - 1) {
             __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
             __hip_atomic_store(gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             long spin = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(1);
                 if (++spin > kSpinLimit) {
                     atomicOr(&stats[2], 4);
@@ -80,7 +85,7 @@ __device__ inline void grid_barrier(unsigned* count, unsigned long long* gen, un
                 }
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -164,7 +169,7 @@ __device__ inline void apply_rows(const LittleCtx<T>& c, const cpx<T>* __restric
                 const cpx<T>* At = c.a.At + ((long)blk * 9 + d) * Ns * Ns + k;
                 const cpx<T>* vv = v + (long)nbr * Ns;
                 double re = 0.0, im = 0.0;
-#pragma unroll 4
+#pragma unroll 20
                 for (int l = 0; l < Ns; ++l) {
                     cpx<T> p = At[(long)l * Ns];
                     cpx<T> q = vv[l];
@@ -231,6 +236,7 @@ __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, in
             v = (s == 2 * k) ? y : r;
         }
         double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
         for (int e = lane; e < c.R; e += 64) {
             long i = c.entry(e);
             cpx<T> p = u[i], q = v[i];
@@ -260,7 +266,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
     LittleCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
     unsigned long long bar_target = 0;
     if (c.t == 0)
-        bar_target = __hip_atomic_load(a.bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        bar_target = __hip_atomic_load(a.bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     c.nbg = (a.g.Nb - c.g + c.G - 1) / c.G;
     c.R = c.nbg * a.Ns;
     const long N = c.N;
@@ -321,6 +327,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
                 for (int e = c.t; e < c.R; e += LT) {
                     long i = c.entry(e);
                     double yr = (double)ck[i].re, yi = (double)ck[i].im;
+#pragma unroll 8
                     for (int j = 0; j < k; ++j) {
                         cpx<T> z = a.chi[(long)j * N + i];
                         yr -= red[2 * j] * (double)z.re - red[2 * j + 1] * (double)z.im;
@@ -369,6 +376,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             for (int e = c.t; e < c.R; e += LT) {
                 long i = c.entry(e);
                 double yr = (double)ck[i].re, yi = (double)ck[i].im;
+#pragma unroll 8
                 for (int j = 0; j < k; ++j) {
                     cpx<T> z = a.chi[(long)j * N + i];
                     yr -= red[2 * j] * (double)z.re - red[2 * j + 1] * (double)z.im;
@@ -401,6 +409,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
         for (int e = c.t; e < c.R; e += LT) {
             long i = c.entry(e);
             double yr = (double)a.x[i].re, yi = (double)a.x[i].im;
+#pragma unroll 8
             for (int j = 0; j < k; ++j) {
                 cpx<T> z = a.xi[(long)j * N + i];
                 yr += alpha[j][0] * (double)z.re - alpha[j][1] * (double)z.im;
@@ -460,11 +469,12 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
 
 }  // namespace
 
-// Few, wide workgroups: the barrier cost grows with the workgroup count, so
-// each 1024-thread workgroup owns about eight blocks.
+// The barrier cost grows with the workgroup count (about 3.4 us at 128 on
+// MI355X), the apply's bandwidth with it: two blocks per workgroup, at most
+// kLittleMaxGrid workgroups.
 int little_gcr_grid(const Geom& g)
 {
-    int G = g.Nb / 8;
+    int G = g.Nb / 2;
     if (G > kLittleMaxGrid)
         G = kLittleMaxGrid;
     if (G < 1)

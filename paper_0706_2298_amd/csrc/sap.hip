@@ -184,6 +184,218 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
     }
 }
 
+// FP32 sweep with the site's eight links in registers (two rows each, 96
+// VGPRs; the third row is rebuilt on use). They are loaded once, during the
+// residual, so the MR steps read only LDS. A block of at most 256 sites runs
+// one wave per SIMD, which leaves the whole register file to that wave.
+template <typename L> struct Link2 {
+    c32 e[6];
+};
+
+template <typename L> __device__ inline Link2<L> load_link2(const L& U, int mu, long s);
+template <> __device__ inline Link2<Links32> load_link2(const Links32& U, int mu, long s)
+{
+    Link2<Links32> r;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        r.e[k] = ld(U.u, toff<c32>(s, mu * 6 + k, 24));
+    return r;
+}
+template <> __device__ inline Link2<LinksBF16> load_link2(const LinksBF16& U, int mu, long s)
+{
+    Link2<LinksBF16> r;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        uint32_t w = ld(U.u, toff<uint32_t>(s, mu * 6 + k, 24));
+        r.e[k] = c32{bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)};
+    }
+    return r;
+}
+template <typename L> __device__ inline su3<float> expand(const Link2<L>& l)
+{
+    su3<float> u;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            u.m[a][b] = l.e[a * 3 + b];
+    complete_third_row(u);
+    return u;
+}
+
+template <typename L>
+__global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
+                                               c32* __restrict__ psi, float diag, int nmr, int colour)
+{
+    extern __shared__ char smem_raw[];
+    c32* lr = reinterpret_cast<c32*>(smem_raw);
+    __shared__ double red[3][8];
+
+    const int t = threadIdx.x;
+    const bool active = t < sg.Vsb;
+    const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+
+    int k = blockIdx.x;
+    int half = sg.nsb[3] / 2;
+    int m[4];
+    int j = k % half;
+    int rest = k / half;
+    m[2] = rest % sg.nsb[2];
+    rest /= sg.nsb[2];
+    m[1] = rest % sg.nsb[1];
+    m[0] = rest / sg.nsb[1];
+    m[3] = 2 * j + ((colour + m[0] + m[1] + m[2]) & 1);
+
+    int yl[4] = {0, 0, 0, 0};
+    int n[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
+    long s = 0;
+    if (active) {
+        int tt = t;
+        yl[3] = tt % sg.sb[3];
+        tt /= sg.sb[3];
+        yl[2] = tt % sg.sb[2];
+        tt /= sg.sb[2];
+        yl[1] = tt % sg.sb[1];
+        yl[0] = tt / sg.sb[1];
+        for (int mu = 0; mu < 4; ++mu) {
+            int x = m[mu] * sg.sb[mu] + yl[mu];
+            n[mu] = x / g.b[mu];
+            y[mu] = x - n[mu] * g.b[mu];
+        }
+        s = site_compose(g, n, y);
+    }
+
+    // residual with the full operator; the links are kept for the MR steps
+    Link2<L> lk[8];
+    spinor<float> r, xs;
+    zero(r);
+    zero(xs);
+    if (active) {
+        spinor<float> acc;
+        zero(acc);
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int mu = h >> 1;
+            const int step = (h & 1) ? -1 : +1;
+            long tn = site_step(g, s, n, y, mu, step);
+            lk[h] = load_link2(U, mu, step > 0 ? s : tn);
+            spinor<float> p = load_spinor(psi, g.V, tn);
+            if (step > 0)
+                hop_fwd_rt(mu, expand(lk[h]), p, acc);
+            else
+                hop_bwd_rt(mu, expand(lk[h]), p, acc);
+            if (h & 1)
+                asm volatile("" ::: "memory");  // two hops' loads in flight at a time
+        }
+        spinor<float> d = finish(load_spinor(psi, g.V, s), acc, diag);
+        spinor<float> b = load_spinor(rho, g.V, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+            r.s[al] = b.s[al] - d.s[al];
+    }
+
+    for (int stp = 0; stp < nmr; ++stp) {
+        if (active) {
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    lr[(3 * al + a) * sg.Vsb + t] = r.s[al].c[a];
+        }
+        __syncthreads();
+        spinor<float> q;
+        zero(q);
+        double qr_re = 0.0, qr_im = 0.0, qq = 0.0;
+        if (active) {
+            spinor<float> acc;
+            zero(acc);
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const int mu = h >> 1;
+                const int step = (h & 1) ? -1 : +1;
+                if (step > 0 ? yl[mu] + 1 < sg.sb[mu] : yl[mu] > 0) {
+                    const int tn = t + step * sg.lstr[mu];
+                    spinor<float> p;
+#pragma unroll
+                    for (int al = 0; al < 4; ++al)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            p.s[al].c[a] = lr[(3 * al + a) * sg.Vsb + tn];
+                    if (step > 0)
+                        hop_fwd_rt(mu, expand(lk[h]), p, acc);
+                    else
+                        hop_bwd_rt(mu, expand(lk[h]), p, acc);
+                }
+                if (h & 1)
+                    asm volatile("" ::: "memory");
+            }
+            q = finish(r, acc, diag);
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    double qa = (double)q.s[al].c[a].re, qb = (double)q.s[al].c[a].im;
+                    double ra = (double)r.s[al].c[a].re, rb = (double)r.s[al].c[a].im;
+                    qr_re += qa * ra + qb * rb;
+                    qr_im += qa * rb - qb * ra;
+                    qq += qa * qa + qb * qb;
+                }
+        }
+        qr_re = wave_sum(qr_re);
+        qr_im = wave_sum(qr_im);
+        qq = wave_sum(qq);
+        if (lane == 0) {
+            red[0][wid] = qr_re;
+            red[1][wid] = qr_im;
+            red[2][wid] = qq;
+        }
+        __syncthreads();
+        double sre = 0.0, sim = 0.0, sqq = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            sre += red[0][w];
+            sim += red[1][w];
+            sqq += red[2][w];
+        }
+        if (!(sqq > 0.0))
+            break;  // zero residue on this block: uniform across the workgroup
+        c32 alpha{(float)(sre / sqq), (float)(sim / sqq)};
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xs.s[al].c[a] += alpha * r.s[al].c[a];
+                r.s[al].c[a] -= alpha * q.s[al].c[a];
+            }
+    }
+
+    if (active) {
+        spinor<float> p = load_spinor(psi, g.V, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+            p.s[al] += xs.s[al];
+        store_spinor(psi, g.V, s, p);
+    }
+}
+
+template <typename T, typename L>
+void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
+            hipStream_t s);
+
+// blocks of up to 256 sites: links in registers; larger blocks: the generic kernel
+template <typename L>
+void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
+               hipStream_t s)
+{
+    if (sg.Vsb > 256) {
+        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, s);
+        return;
+    }
+    int threads = ((sg.Vsb + 63) / 64) * 64;
+    size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
+    hipLaunchKernelGGL((k_sap_rl<L>), dim3(sg.n_per_colour), dim3(threads), lds, s, g, sg, U, rho, psi, 4.0f + m0, nmr,
+                       colour);
+}
+
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
             hipStream_t s)
@@ -210,12 +422,12 @@ void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64*
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi, float m0, int nmr,
                          int colour, hipStream_t s)
 {
-    launch(g, sg, U, rho, psi, m0, nmr, colour, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, s);
 }
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi, float m0,
                             int nmr, int colour, hipStream_t s)
 {
-    launch(g, sg, U, rho, psi, m0, nmr, colour, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, s);
 }
 
 }  // namespace dfl
