@@ -62,7 +62,7 @@ void free_all(dfl_ctx* c)
     void* ptrs[] = {c->U64, c->U32,  c->Ubf,  c->Phi, c->Phi32, c->A64, c->A32, c->xi,  c->chi,
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
-                    c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen};
+                    c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -233,16 +233,17 @@ void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0)
     launch_dirac64(c->g, links64(c), in, out, 1, m0, 0, 0, 0, c->stream);
 }
 
-// psi = M_sap rho (FP64 in and out; block solves in sap_prec)
-void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0)
+// psi = M_sap rho for nrhs fields (FP64 in and out; block solves in sap_prec).
+// One launch per colour sweep covers all nrhs fields.
+void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1)
 {
-    const long n = c->field_elems;
+    const long n = c->field_elems * nrhs;
     if (c->p.sap_prec == DFL_F64) {
         launch_zero<double>(psi, n, c->stream);
         for (int cy = 0; cy < c->p.ncy; ++cy)
             for (int col = 0; col < 2; ++col) {
                 ProfScope ps(c, DFL_PROF_SAP);
-                launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, c->stream);
+                launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, nrhs, c->stream);
             }
         return;
     }
@@ -252,10 +253,11 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0)
         for (int col = 0; col < 2; ++col) {
             ProfScope ps(c, DFL_PROF_SAP);
             if (c->p.link_prec == DFL_BF16)
-                launch_sap_colour_bf16(c->g, c->sg, linksbf(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col,
+                launch_sap_colour_bf16(c->g, c->sg, linksbf(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
                                        c->stream);
             else
-                launch_sap_colour32(c->g, c->sg, links32(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, c->stream);
+                launch_sap_colour32(c->g, c->sg, links32(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
+                                    c->stream);
         }
     launch_f32_to_f64(c->s32b, psi, n, c->stream);
 }
@@ -568,9 +570,12 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->t1 = alloc_dev<c64>(c, F);
         c->t2 = alloc_dev<c64>(c, F);
         c->t3 = alloc_dev<c64>(c, F);
-        c->s32a = alloc_dev<c32>(c, F);
-        c->s32b = alloc_dev<c32>(c, F);
+        const long nf = p->nrhs_max > p->Ns ? p->nrhs_max : p->Ns;  // multi-field Schwarz buffers
+        c->s32a = alloc_dev<c32>(c, (size_t)nf * F);
+        c->s32b = alloc_dev<c32>(c, (size_t)nf * F);
         c->s32c = alloc_dev<c32>(c, F);
+        if (p->sap_prec == DFL_F64)
+            c->tN = alloc_dev<c64>(c, (size_t)p->Ns * F);
         c->lxi = alloc_dev<c64>(c, (size_t)p->little_nkv * N);
         c->lchi = alloc_dev<c64>(c, (size_t)p->little_nkv * N);
         c->lr = alloc_dev<c64>(c, N);
@@ -729,9 +734,7 @@ int sap_precond(dfl_ctx* c, const void* rho, void* psi, int nrhs)
     need_nrhs(c, nrhs);
     if (rho == psi)
         fail(DFL_EINVAL, "rho and psi must not overlap");
-    for (int r = 0; r < nrhs; ++r)
-        sap_apply(c, static_cast<const c64*>(rho) + r * c->field_elems, static_cast<c64*>(psi) + r * c->field_elems,
-                  c->p.m0);
+    sap_apply(c, static_cast<const c64*>(rho), static_cast<c64*>(psi), c->p.m0, nrhs);
     HIPCHECK(hipGetLastError());
     API_END
 }
@@ -755,15 +758,21 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
         launch_norm2<double>(f, F, c->red, c->dscal + S_B, c->stream);
         launch_scale_invsqrt<double>(f, F, c->dscal + S_B, c->stream);
     }
-    // inverse iteration, eq. (5.1): psi_l <- M_sap psi_l, normalised
-    for (int step = 0; step < c->p.n_inviter; ++step)
+    // inverse iteration, eq. (5.1): psi_l <- M_sap psi_l, normalised; the
+    // Schwarz sweeps relax all Ns fields in one launch each
+    for (int step = 0; step < c->p.n_inviter; ++step) {
+        if (c->p.sap_prec == DFL_F64) {
+            sap_apply(c, c->Phi, c->tN, c->p.m0_setup, Ns);
+            launch_copy<double>(c->tN, c->Phi, F * Ns, c->stream);
+        } else {
+            sap_apply(c, c->Phi, c->Phi, c->p.m0_setup, Ns);  // FP32 path: staged through s32a/s32b
+        }
         for (int l = 0; l < Ns; ++l) {
             c64* f = c->Phi + (long)l * F;
-            sap_apply(c, f, c->t1, c->p.m0_setup);
-            launch_copy<double>(c->t1, f, F, c->stream);
             launch_norm2<double>(f, F, c->red, c->dscal + S_B, c->stream);
             launch_scale_invsqrt<double>(f, F, c->dscal + S_B, c->stream);
         }
+    }
     // block restriction and Gram-Schmidt, eq. (4.2)
     ProfScope ps_setup(c, DFL_PROF_SETUP);
     launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->stream);

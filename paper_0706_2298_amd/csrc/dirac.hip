@@ -43,16 +43,22 @@ __device__ inline void hops_all(const Geom& g, const L& U, const cpx<T>* __restr
     }
 }
 
+// Workgroup id -> (site chunk, right-hand side): XCD k sweeps its contiguous
+// range of chunks, and for each chunk all right-hand sides back to back, so
+// the chunk's links are read from HBM once and from L2 for the other RHS.
 template <int MODE, typename T, typename L>
 __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __restrict__ psi,
                                                cpx<T>* __restrict__ out, T diag, int hop_mu, int hop_dir,
-                                               int grid_padded)
+                                               int chunks_padded, int nrhs)
 {
-    int wg = xcd_remap(blockIdx.x, grid_padded);
+    const int per = chunks_padded / kNumXcd;
+    const int local = blockIdx.x / kNumXcd;
+    const int wg = (blockIdx.x % kNumXcd) * per + local / nrhs;
+    const int rhs = local % nrhs;
     long s = (long)wg * 256 + threadIdx.x;
     if (s >= g.V)
         return;
-    long off = (long)blockIdx.y * 12 * g.V;
+    long off = (long)rhs * 12 * g.V;
     const cpx<T>* f = psi + off;
     int n[4], y[4];
     site_decompose(g, s, n, y);
@@ -75,8 +81,8 @@ void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, 
 {
     long nwg = (g.V + 255) / 256;
     int gp = pad_grid(nwg);
-    hipLaunchKernelGGL((k_dirac<MODE, T, L>), dim3(gp, nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, mu, dir,
-                       gp);
+    hipLaunchKernelGGL((k_dirac<MODE, T, L>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, mu, dir,
+                       gp, nrhs);
 }
 
 }  // namespace

@@ -94,6 +94,7 @@ struct dfl_ctx {
     dfl::c32* s32a = nullptr;
     dfl::c32* s32b = nullptr;
     dfl::c32* s32c = nullptr;
+    dfl::c64* tN = nullptr;    // Ns FP64 fields: FP64 inverse-iteration output
     // little-system workspaces (max(FP64) size; reused for FP32)
     void* lxi = nullptr;
     void* lchi = nullptr;
@@ -145,12 +146,13 @@ void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs
 void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s);
 
 // ------------------------------------------------------------------- sap.hip
+// one colour sweep for nrhs fields (each 12 V entries, back to back)
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi,
-                         double m0, int nmr, int colour, hipStream_t s);
+                         double m0, int nmr, int colour, int nrhs, hipStream_t s);
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi,
-                         float m0, int nmr, int colour, hipStream_t s);
+                         float m0, int nmr, int colour, int nrhs, hipStream_t s);
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi,
-                            float m0, int nmr, int colour, hipStream_t s);
+                            float m0, int nmr, int colour, int nrhs, hipStream_t s);
 
 // ------------------------------------------------------------------ blas.hip
 template <typename T> void launch_zero(cpx<T>* x, long n, hipStream_t s);

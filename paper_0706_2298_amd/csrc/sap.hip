@@ -64,8 +64,11 @@ __device__ inline void full_hops(const Geom& g, const L& U, const cpx<T>* __rest
 
 template <typename T, typename L>
 __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<T>* __restrict__ rho,
-                                             cpx<T>* __restrict__ psi, T diag, int nmr, int colour)
+                                             cpx<T>* __restrict__ psi, T diag, int nmr, int colour, int nrhs)
 {
+    // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
+    rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
+    psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
     extern __shared__ char smem_raw[];
     cpx<T>* lr = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[3][8];
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
     const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
 
     // k-th block of this colour -> block coordinates m
-    int k = blockIdx.x;
+    int k = blockIdx.x / nrhs;
     int half = sg.nsb[3] / 2;
     int m[4];
     int j = k % half;
@@ -225,8 +228,11 @@ template <typename L> __device__ inline su3<float> expand(const Link2<L>& l)
 
 template <typename L>
 __global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
-                                               c32* __restrict__ psi, float diag, int nmr, int colour)
+                                               c32* __restrict__ psi, float diag, int nmr, int colour, int nrhs)
 {
+    // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
+    rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
+    psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
     extern __shared__ char smem_raw[];
     c32* lr = reinterpret_cast<c32*>(smem_raw);
     __shared__ double red[3][8];
@@ -235,7 +241,7 @@ __global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c
     const bool active = t < sg.Vsb;
     const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
 
-    int k = blockIdx.x;
+    int k = blockIdx.x / nrhs;
     int half = sg.nsb[3] / 2;
     int m[4];
     int j = k % half;
@@ -379,26 +385,26 @@ __global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c
 
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            hipStream_t s);
+            int nrhs, hipStream_t s);
 
 // blocks of up to 256 sites: links in registers; larger blocks: the generic kernel
 template <typename L>
 void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
-               hipStream_t s)
+               int nrhs, hipStream_t s)
 {
     if (sg.Vsb > 256) {
-        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, s);
+        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
         return;
     }
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
-    hipLaunchKernelGGL((k_sap_rl<L>), dim3(sg.n_per_colour), dim3(threads), lds, s, g, sg, U, rho, psi, 4.0f + m0, nmr,
-                       colour);
+    hipLaunchKernelGGL((k_sap_rl<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
+                       4.0f + m0, nmr, colour, nrhs);
 }
 
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            hipStream_t s)
+            int nrhs, hipStream_t s)
 {
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(cpx<T>);
@@ -408,26 +414,26 @@ void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* ps
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sap<T, L>), dim3(sg.n_per_colour), dim3(threads), lds, s, g, sg, U, rho, psi, T(4) + m0,
-                       nmr, colour);
+    hipLaunchKernelGGL((k_sap<T, L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
+                       T(4) + m0, nmr, colour, nrhs);
 }
 
 }  // namespace
 
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi, double m0, int nmr,
-                         int colour, hipStream_t s)
+                         int colour, int nrhs, hipStream_t s)
 {
-    launch(g, sg, U, rho, psi, m0, nmr, colour, s);
+    launch(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
 }
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi, float m0, int nmr,
-                         int colour, hipStream_t s)
+                         int colour, int nrhs, hipStream_t s)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
 }
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi, float m0,
-                            int nmr, int colour, hipStream_t s)
+                            int nmr, int colour, int nrhs, hipStream_t s)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
 }
 
 }  // namespace dfl

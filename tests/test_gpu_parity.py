@@ -333,3 +333,20 @@ def test_solve_reproducible_and_history(c1):
     assert all(h[i + 1] <= h[i] * (1 + 1e-9) for i in range(len(h) - 1))
     assert h[-1] <= 1e-10
     S.close()
+
+
+@pytest.mark.parametrize("sap_prec,tol", [(F64, 1e-12), (F32, 1e-4)])
+def test_sap_multi_rhs(sap_prec, tol):
+    # one Schwarz launch per sweep for three fields equals the per-field oracle
+    dims, b, sb = GEOMS[0]
+    say(f"sap multi-rhs prec={sap_prec}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.4, 71)
+    rho = latgen.random_field(dims, 72, n=3)
+    S = make_solver(dims, b, sb, m0=m0, ncy=2, nmr=3, nrhs_max=3, sap_prec=sap_prec,
+                    link_prec=F64 if sap_prec == F64 else F32)
+    S.set_gauge(U)
+    got = S.unpack(S.sap(S.pack(rho)))
+    for r in range(3):
+        assert rel(got[r], oracle.sap(U, rho[r], m0, dims, sb, 2, 3)) < tol
+    S.close()
