@@ -92,7 +92,8 @@ typedef struct {
                            by 10*little_tol_in */
     int n_inviter;      /* inverse-iteration steps in dfl_setup (>= 0) */
     int maxiter;        /* outer GCR iteration limit */
-    int nrhs_max;       /* largest nrhs any call will pass (>= 1) */
+    int nrhs_max;       /* largest nrhs any call will pass (1..16); field workspaces
+                           scale with it */
     int little_nkv;     /* Krylov vectors of the little GCR (1..32) */
     int little_maxiter; /* little GCR iteration limit */
     dfl_solver solver;  /* variant run by solve() */
@@ -184,7 +185,9 @@ int dfl_get_basis(dfl_ctx *ctx, void *phi_dev);
 int dfl_get_little(dfl_ctx *ctx, double *A_dev);
 
 /* w = A v with the little Dirac operator (eqs. (3.2)/(A.1)) for nrhs native
- * little vectors of precision prec (F64 or F32). */
+ * little vectors of precision prec (F64 or F32), back to back. One launch for
+ * all nrhs; F32 with nrhs > 1 runs as a batched complex GEMM on the matrix
+ * cores (16 right-hand sides per pass). */
 int little_dirac_apply(dfl_ctx *ctx, const void *v_dev, void *w_dev, int nrhs, dfl_prec prec);
 
 /* Solve A v = w (eq. (6.1)) by GCR to ||w - A v|| <= tol ||w|| in FP64
@@ -200,8 +203,12 @@ int deflate_project(dfl_ctx *ctx, dfl_proj which, const void *in_dev, void *out_
  * with the solver chosen in the parameters (section 6 for DFL_SAP_GCR:
  * flexible GCR on eq. (6.2), restarts recomputing the residual in FP64
  * (appendix A.5), final solution by eq. (3.10)). psi is overwritten (the start
- * vector is zero). Synchronises; info (may be NULL) receives the statistics
- * of the last right-hand side. Returns DFL_NOT_CONVERGED after maxiter. */
+ * vector is zero). The nrhs sources are solved together: every stencil,
+ * Schwarz, projection and little-solve launch covers all of them, while each
+ * keeps its own Krylov coefficients and stops on its own residual.
+ * Synchronises; info (may be NULL) points to nrhs records, one per source
+ * (little-solve counts and t_solve are those of the whole call). Returns
+ * DFL_NOT_CONVERGED if some source reached maxiter. */
 int solve(dfl_ctx *ctx, const void *eta_dev, void *psi_dev, int nrhs, dfl_info *info);
 
 /* Relative residue norms of the last outer GCR run (the initial one, then one

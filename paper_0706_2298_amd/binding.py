@@ -230,7 +230,8 @@ def dfl_profile_read(ctx):
 
 
 def solve(ctx, eta, psi, nrhs=1):
-    info = Info()
-    code = load().solve(ctx, _ptr(eta), _ptr(psi), nrhs, ctypes.byref(info))
+    """Returns one Info for nrhs == 1, else a list of nrhs Info records."""
+    infos = (Info * nrhs)()
+    code = load().solve(ctx, _ptr(eta), _ptr(psi), nrhs, infos)
     _check(code, allow_not_converged=True)
-    return info
+    return infos[0] if nrhs == 1 else list(infos)

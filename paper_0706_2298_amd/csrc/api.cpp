@@ -62,12 +62,15 @@ void free_all(dfl_ctx* c)
     void* ptrs[] = {c->U64, c->U32,  c->Ubf,  c->Phi, c->Phi32, c->A64, c->A32, c->xi,  c->chi,
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
-                    c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN};
+                    c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
+                    c->lfin, c->lacoef, c->dact};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
     if (c->hscal)
         (void)hipHostFree(c->hscal);
+    if (c->hact)
+        (void)hipHostFree(c->hact);
 }
 
 void check_blocks(const int dims[4], const int b[4], const char* what)
@@ -108,6 +111,8 @@ void validate(const dfl_params& p)
         fail(DFL_EINVAL, "little_nkv must be in 1..32");
     if (p.n_inviter < 0 || p.maxiter < 1 || p.little_maxiter < 1 || p.nrhs_max < 1)
         fail(DFL_EINVAL, "n_inviter >= 0, maxiter >= 1, little_maxiter >= 1, nrhs_max >= 1 required");
+    if (p.nrhs_max > kMaxLittleRhs)
+        fail(DFL_EINVAL, "nrhs_max must be at most " + std::to_string(kMaxLittleRhs));
     if (!(p.tol > 0.0) || !(p.little_tol_in > 0.0) || !(p.little_tol_out > 0.0))
         fail(DFL_EINVAL, "tolerances must be positive");
     if (!std::isfinite(p.m0) || !std::isfinite(p.m0_setup))
@@ -216,6 +221,36 @@ void download(dfl_ctx* c, int n)
     sync(c);
 }
 
+// the first n scalars of each of nb right-hand sides (stride S_TOTAL) to the host
+void download_b(dfl_ctx* c, int n, int nb)
+{
+    HIPCHECK(hipMemcpy2DAsync(c->hscal, sizeof(double) * S_TOTAL, c->dscal, sizeof(double) * S_TOTAL,
+                              sizeof(double) * n, nb, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+// per-RHS active mask to the device (host mirror is pinned; the previous copy
+// has completed because every GCR step synchronises before the mask changes)
+void upload_mask(dfl_ctx* c, const std::vector<int>& m)
+{
+    for (size_t b = 0; b < m.size(); ++b)
+        c->hact[b] = m[b];
+    HIPCHECK(hipMemcpyAsync(c->dact, c->hact, sizeof(int) * m.size(), hipMemcpyHostToDevice, c->stream));
+}
+
+// ||x_b||^2 of nb fields of n entries to the host (synchronises)
+std::vector<double> host_norm2_b(dfl_ctx* c, const c64* x, long n, int nb)
+{
+    launch_norm2_b<double>(x, n, nb, n, c->red, c->dscal + S_R, S_TOTAL, nullptr, c->stream);
+    HIPCHECK(hipMemcpy2DAsync(c->hscal + S_R, sizeof(double) * S_TOTAL, c->dscal + S_R, sizeof(double) * S_TOTAL,
+                              sizeof(double), nb, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    std::vector<double> out(nb);
+    for (int b = 0; b < nb; ++b)
+        out[b] = c->hscal[(long)b * S_TOTAL + S_R];
+    return out;
+}
+
 // ||x||^2 to the host (synchronises)
 template <typename T> double host_norm2(dfl_ctx* c, const cpx<T>* x, long n)
 {
@@ -227,10 +262,10 @@ template <typename T> double host_norm2(dfl_ctx* c, const cpx<T>* x, long n)
 
 // ------------------------------------------------------------ operators
 
-void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0)
+void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0, int nb = 1)
 {
     ProfScope ps(c, DFL_PROF_DIRAC);
-    launch_dirac64(c->g, links64(c), in, out, 1, m0, 0, 0, 0, c->stream);
+    launch_dirac64(c->g, links64(c), in, out, nb, m0, 0, 0, 0, c->stream);
 }
 
 // psi = M_sap rho for nrhs fields (FP64 in and out; block solves in sap_prec).
@@ -264,17 +299,22 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1)
 
 // ------------------------------------------------------------------ GCR
 //
-// Flexible restarted GCR (section 6.2): xi_k = M rho, chi_k = Op xi_k,
-// orthogonalised against chi_{<k} (classical Gram-Schmidt applied twice),
-// normalised, rho -= (chi_k, rho) chi_k. At the end of a cycle the
-// coefficients alpha solve the triangular system, x += sum alpha_k xi_k and
-// the residue is recomputed from scratch (appendix A.5).
+// Flexible restarted GCR (section 6.2) for nb right-hand sides in lockstep:
+// xi_k = M rho, chi_k = Op xi_k, orthogonalised against chi_{<k} (classical
+// Gram-Schmidt applied twice), normalised, rho -= (chi_k, rho) chi_k. Every
+// step is one batched launch sequence over all sources; each source has its
+// own coefficients and leaves the cycle when it converges. At the end of a
+// cycle the coefficients alpha solve the triangular system, x += sum alpha_k
+// xi_k and the residue is recomputed from scratch (appendix A.5).
+//
+// Layout: residue and solution of source b at b*n; Krylov slot k of source b
+// at (k*nb + b)*n. Scalars of source b at dscal + b*S_TOTAL.
 
 struct GcrVecs {
-    void* xi;    // nkv vectors, stride n
-    void* chi;   // nkv vectors, stride n
-    void* r;     // residue
-    void* x;     // solution accumulator
+    c64* xi;   // nkv * nb vectors
+    c64* chi;  // nkv * nb vectors
+    c64* r;    // nb residues
+    c64* x;    // nb solution accumulators
 };
 
 struct GcrResult {
@@ -284,110 +324,172 @@ struct GcrResult {
     double rel;  // last recomputed relative residual
 };
 
-template <typename T>
-GcrResult gcr_run(dfl_ctx* c, long n, int nkv, int maxiter, double tol, double src_norm, GcrVecs v,
-                  const std::function<void(const cpx<T>*, cpx<T>*)>& precond,
-                  const std::function<void(const cpx<T>*, cpx<T>*)>& op,
-                  const std::function<void(const cpx<T>*, cpx<T>*)>& recompute_residual, double cycle_floor = 0.0,
-                  std::vector<double>* history_ = nullptr)
+using BatchOp = std::function<void(const c64*, c64*, int)>;
+
+std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter, double tol,
+                               const std::vector<double>& src_norm, GcrVecs v, const BatchOp& precond,
+                               const BatchOp& op, const BatchOp& recompute_residual, double cycle_floor = 0.0,
+                               std::vector<double>* history_ = nullptr)
 {
-    cpx<T>* xi = static_cast<cpx<T>*>(v.xi);
-    cpx<T>* chi = static_cast<cpx<T>*>(v.chi);
-    cpx<T>* r = static_cast<cpx<T>*>(v.r);
-    cpx<T>* x = static_cast<cpx<T>*>(v.x);
-    GcrResult res{DFL_OK, 0, 0, 0.0};
-    launch_zero<T>(x, n, c->stream);
-    if (src_norm == 0.0)
-        return res;
-    // the caller has put the initial residue in r
-    double rn = std::sqrt(host_norm2<T>(c, r, n));
+    std::vector<GcrResult> res(nb, GcrResult{DFL_OK, 0, 0, 0.0});
+    launch_zero<double>(v.x, n * nb, c->stream);
+    // the caller has put the initial residues in r
+    std::vector<double> rn = host_norm2_b(c, v.r, n, nb);
+    for (auto& q : rn)
+        q = std::sqrt(q);
     if (history_)
-        history_->push_back(rn / src_norm);
-    std::vector<cd> a((size_t)nkv * nkv), cc(nkv), alpha(nkv);
-    std::vector<double> b(nkv);
+        history_->push_back(src_norm[0] > 0.0 ? rn[0] / src_norm[0] : 0.0);
+    std::vector<int> done(nb, 0), act(nb, 0), kb(nb, 0);
+    std::vector<cd> a((size_t)nb * nkv * nkv), cc((size_t)nb * nkv), alpha((size_t)nb * nkv);
+    std::vector<double> bb((size_t)nb * nkv), rn_cycle(nb);
+    const long ks = n * nb;  // stride of the Krylov slots
+    const int* mask = nb > 1 ? c->dact : nullptr;
     while (true) {
-        res.rel = rn / src_norm;
-        if (!std::isfinite(rn))
-            fail(DFL_ENONFINITE, "non-finite residual in GCR");
-        if (rn <= tol * src_norm)
-            return res;
-        if (res.iters >= maxiter) {
-            res.status = DFL_NOT_CONVERGED;
-            return res;
-        }
-        int k = 0;
-        const double rn_cycle = rn;
-        while (k < nkv && res.iters < maxiter) {
-            cpx<T>* xk = xi + (long)k * n;
-            cpx<T>* ck = chi + (long)k * n;
-            precond(r, xk);
-            op(xk, ck);
-            if (k > 0) {
-                launch_multidot<T>(chi, n, k, ck, n, c->red, c->dscal + S_A1, c->stream);
-                launch_multiaxpy<T>(chi, n, k, c->dscal + S_A1, -1.0, ck, n, c->stream);
-                launch_multidot<T>(chi, n, k, ck, n, c->red, c->dscal + S_A2, c->stream);
-                launch_multiaxpy<T>(chi, n, k, c->dscal + S_A2, -1.0, ck, n, c->stream);
+        int n_act = 0;
+        for (int b = 0; b < nb; ++b) {
+            if (done[b])
+                continue;
+            res[b].rel = src_norm[b] > 0.0 ? rn[b] / src_norm[b] : 0.0;
+            if (!std::isfinite(rn[b]))
+                fail(DFL_ENONFINITE, "non-finite residual in GCR");
+            if (src_norm[b] == 0.0 || rn[b] <= tol * src_norm[b]) {
+                done[b] = 1;
+            } else if (res[b].iters >= maxiter) {
+                res[b].status = DFL_NOT_CONVERGED;
+                done[b] = 1;
             }
-            launch_norm2<T>(ck, n, c->red, c->dscal + S_B, c->stream);
-            launch_scale_invsqrt<T>(ck, n, c->dscal + S_B, c->stream);
-            launch_multidot<T>(ck, n, 1, r, n, c->red, c->dscal + S_C, c->stream);
-            launch_multiaxpy<T>(ck, n, 1, c->dscal + S_C, -1.0, r, n, c->stream);
-            launch_norm2<T>(r, n, c->red, c->dscal + S_R, c->stream);
-            download(c, S_DOWN);
-            const double* h = c->hscal;
-            for (int j = 0; j < k; ++j)
-                a[(size_t)j * nkv + k] = cd(h[S_A1 + 2 * j] + h[S_A2 + 2 * j], h[S_A1 + 2 * j + 1] + h[S_A2 + 2 * j + 1]);
-            b[k] = std::sqrt(h[S_B]);
-            cc[k] = cd(h[S_C], h[S_C + 1]);
-            rn = std::sqrt(h[S_R]);
-            if (!(b[k] > 0.0) || !std::isfinite(b[k]))
-                fail(b[k] == 0.0 ? DFL_ESINGULAR : DFL_ENONFINITE, "GCR breakdown: zero or non-finite Krylov image");
+        }
+        for (int b = 0; b < nb; ++b) {
+            act[b] = !done[b];
+            kb[b] = 0;
+            rn_cycle[b] = rn[b];
+            n_act += act[b];
+        }
+        if (n_act == 0)
+            return res;
+        if (mask)
+            upload_mask(c, act);
+        int k = 0;
+        while (k < nkv && n_act > 0) {
+            c64* xk = v.xi + (long)k * ks;
+            c64* ck = v.chi + (long)k * ks;
+            precond(v.r, xk, nb);
+            op(xk, ck, nb);
+            if (k > 0) {
+                launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A1, S_TOTAL, mask,
+                                          c->stream);
+                launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A1, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
+                                           c->stream);
+                launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A2, S_TOTAL, mask,
+                                          c->stream);
+                launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A2, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
+                                           c->stream);
+            }
+            launch_norm2_b<double>(ck, n, nb, n, c->red, c->dscal + S_B, S_TOTAL, mask, c->stream);
+            launch_scale_invsqrt_b<double>(ck, n, nb, n, c->dscal + S_B, S_TOTAL, mask, c->stream);
+            launch_multidot_b<double>(ck, 0, 1, v.r, n, nb, n, n, c->red, c->dscal + S_C, S_TOTAL, mask, c->stream);
+            launch_multiaxpy_b<double>(ck, 0, 1, c->dscal + S_C, S_TOTAL, -1.0, v.r, n, nb, n, n, mask, c->stream);
+            launch_norm2_b<double>(v.r, n, nb, n, c->red, c->dscal + S_R, S_TOTAL, mask, c->stream);
+            download_b(c, S_DOWN, nb);
+            bool changed = false;
+            for (int b = 0; b < nb; ++b) {
+                if (!act[b])
+                    continue;
+                const double* h = c->hscal + (long)b * S_TOTAL;
+                cd* ab = &a[(size_t)b * nkv * nkv];
+                for (int j = 0; j < k; ++j)
+                    ab[(size_t)j * nkv + k] = cd(h[S_A1 + 2 * j] + h[S_A2 + 2 * j], h[S_A1 + 2 * j + 1] + h[S_A2 + 2 * j + 1]);
+                const double bk = std::sqrt(h[S_B]);
+                bb[(size_t)b * nkv + k] = bk;
+                cc[(size_t)b * nkv + k] = cd(h[S_C], h[S_C + 1]);
+                rn[b] = std::sqrt(h[S_R]);
+                if (!(bk > 0.0) || !std::isfinite(bk))
+                    fail(bk == 0.0 ? DFL_ESINGULAR : DFL_ENONFINITE, "GCR breakdown: zero or non-finite Krylov image");
+                kb[b] = k + 1;
+                ++res[b].iters;
+                if (history_ && b == 0)
+                    history_->push_back(rn[0] / src_norm[0]);
+                if (rn[b] <= tol * src_norm[b] || rn[b] <= cycle_floor * rn_cycle[b] || res[b].iters >= maxiter) {
+                    act[b] = 0;
+                    --n_act;
+                    changed = true;
+                }
+            }
             ++k;
-            ++res.iters;
-            if (history_)
-                history_->push_back(rn / src_norm);
-            if (rn <= tol * src_norm || rn <= cycle_floor * rn_cycle)
-                break;
+            if (changed && mask && n_act > 0 && k < nkv)
+                upload_mask(c, act);
         }
-        for (int i = k - 1; i >= 0; --i) {
-            cd s = cc[i];
-            for (int j = i + 1; j < k; ++j)
-                s -= a[(size_t)i * nkv + j] * alpha[j];
-            alpha[i] = s / b[i];
+        int kmax = 0;
+        for (int b = 0; b < nb; ++b) {
+            const cd* ab = &a[(size_t)b * nkv * nkv];
+            cd* al = &alpha[(size_t)b * nkv];
+            for (int i = kb[b] - 1; i >= 0; --i) {
+                cd t = cc[(size_t)b * nkv + i];
+                for (int j = i + 1; j < kb[b]; ++j)
+                    t -= ab[(size_t)i * nkv + j] * al[j];
+                al[i] = t / bb[(size_t)b * nkv + i];
+            }
+            double* up = c->hscal + (long)b * S_TOTAL + S_ALPHA;
+            for (int i = 0; i < nkv; ++i) {
+                up[2 * i] = i < kb[b] ? al[i].real() : 0.0;
+                up[2 * i + 1] = i < kb[b] ? al[i].imag() : 0.0;
+            }
+            kmax = std::max(kmax, kb[b]);
+            act[b] = kb[b] > 0;
         }
-        double* up = c->hscal + S_ALPHA;
-        for (int i = 0; i < k; ++i) {
-            up[2 * i] = alpha[i].real();
-            up[2 * i + 1] = alpha[i].imag();
+        HIPCHECK(hipMemcpy2DAsync(c->dscal + S_ALPHA, sizeof(double) * S_TOTAL, c->hscal + S_ALPHA,
+                                  sizeof(double) * S_TOTAL, sizeof(double) * 2 * nkv, nb, hipMemcpyHostToDevice,
+                                  c->stream));
+        if (mask)
+            upload_mask(c, act);
+        launch_multiaxpy_b<double>(v.xi, ks, kmax, c->dscal + S_ALPHA, S_TOTAL, 1.0, v.x, n, nb, n, n, mask,
+                                   c->stream);
+        recompute_residual(v.x, v.r, nb);
+        rn = host_norm2_b(c, v.r, n, nb);
+        for (int b = 0; b < nb; ++b) {
+            rn[b] = std::sqrt(rn[b]);
+            if (kb[b] > 0)
+                ++res[b].restarts;
+            if (done[b])
+                res[b].rel = src_norm[b] > 0.0 ? rn[b] / src_norm[b] : 0.0;
         }
-        HIPCHECK(hipMemcpyAsync(c->dscal + S_ALPHA, up, sizeof(double) * 2 * k, hipMemcpyHostToDevice, c->stream));
-        launch_multiaxpy<T>(xi, n, k, c->dscal + S_ALPHA, 1.0, x, n, c->stream);
-        recompute_residual(x, r);
-        rn = std::sqrt(host_norm2<T>(c, r, n));
-        ++res.restarts;
     }
 }
 
 // ---------------------------------------------------------- little solve
 
-// v = A^{-1} w to ||w - A v|| <= tol ||w|| (eq. (6.1)); FP64 in and out.
-// One cooperative launch; iteration counts accumulate in c->lstats.
-void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec prec)
+// v_b = A^{-1} w_b to ||w_b - A v_b|| <= tol ||w_b|| (eq. (6.1)) for nb little
+// vectors back to back; FP64 in and out. One cooperative launch; iteration
+// counts accumulate in c->lstats.
+void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec prec, int nb = 1)
 {
     const long n = (long)c->g.Nb * c->p.Ns;
+    const int Ns = c->p.Ns, nkv = c->p.little_nkv, mi = c->p.little_maxiter;
     if (prec == DFL_F64) {
         ProfScope ps(c, DFL_PROF_LITTLE);
-        launch_little_gcr<double>(c->g, c->p.Ns, c->p.little_nkv, c->p.little_maxiter, tol, c->At64, w, v,
-                                  static_cast<c64*>(c->lr), static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi),
-                                  c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->stream);
+        if (nb == 1)
+            launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, c->At64, w, v, static_cast<c64*>(c->lr),
+                                      static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lstats,
+                                      c->lbar_count, c->lbar_gen, c->stream);
+        else
+            launch_little_gcr_multi<double>(c->g, Ns, nkv, mi, tol, nb, c->At64, w, v, static_cast<c64*>(c->lr),
+                                            static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lfin,
+                                            c->lacoef, c->lstats, c->lbar_count, c->lbar_gen, c->stream);
     } else {
-        launch_f64_to_f32(w, c->lw32, n, c->stream);
-        ProfScope ps(c, DFL_PROF_LITTLE);
-        launch_little_gcr<float>(c->g, c->p.Ns, c->p.little_nkv, c->p.little_maxiter, tol, c->At32, c->lw32,
-                                 c->lx32, static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
-                                 static_cast<c32*>(c->lchi), c->lpart, c->lstats, c->lbar_count, c->lbar_gen,
-                                 c->stream);
-        launch_f32_to_f64(c->lx32, v, n, c->stream);
+        launch_f64_to_f32(w, c->lw32, n * nb, c->stream);
+        {
+            ProfScope ps(c, DFL_PROF_LITTLE);
+            if (nb == 1)
+                launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, c->At32, c->lw32, c->lx32, static_cast<c32*>(c->lr),
+                                         static_cast<c32*>(c->lxi), static_cast<c32*>(c->lchi), c->lpart, c->lstats,
+                                         c->lbar_count, c->lbar_gen, c->stream);
+            else
+                launch_little_gcr_multi<float>(c->g, Ns, nkv, mi, tol, nb, c->At32, c->lw32, c->lx32,
+                                               static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
+                                               static_cast<c32*>(c->lchi), c->lpart, c->lfin, c->lacoef, c->lstats,
+                                               c->lbar_count, c->lbar_gen, c->stream);
+        }
+        launch_f32_to_f64(c->lx32, v, n * nb, c->stream);
     }
 }
 
@@ -408,26 +510,26 @@ void read_little_stats(dfl_ctx* c, int out[3])
         fail(DFL_EHIP, "little solver: grid barrier timed out");
 }
 
-// out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term); out may not alias in
-void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec)
+// out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term) for nb fields; out may not alias in
+void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, int nb = 1)
 {
     c64* w = static_cast<c64*>(c->lw);
     c64* x = static_cast<c64*>(c->lx);
     {
         ProfScope ps(c, DFL_PROF_PROJECT);
-        launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, c->stream);
+        launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, nb, c->stream);
     }
-    little_solve_impl(c, w, x, tol, prec);
+    little_solve_impl(c, w, x, tol, prec, nb);
     ProfScope ps(c, DFL_PROF_PROJECT);
-    launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, c->stream);
+    launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, nb, c->stream);
 }
 
-// out = P_L in = in - D coarse(in)   (eq. (3.3)); uses t3 and the little buffers
-void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c64* tmpA, c64* tmpB)
+// out = P_L in = in - D coarse(in)   (eq. (3.3)) for nb fields
+void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c64* tmpA, c64* tmpB, int nb = 1)
 {
-    coarse(c, in, tmpA, tol, prec);
-    dirac64(c, tmpA, tmpB, c->p.m0);
-    launch_sub<double>(in, tmpB, out, c->field_elems, c->stream);
+    coarse(c, in, tmpA, tol, prec, nb);
+    dirac64(c, tmpA, tmpB, c->p.m0, nb);
+    launch_sub<double>(in, tmpB, out, c->field_elems * nb, c->stream);
 }
 
 }  // namespace
@@ -563,37 +665,48 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->A32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->At64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->At32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
-        c->xi = alloc_dev<c64>(c, (size_t)p->nkv * F);
-        c->chi = alloc_dev<c64>(c, (size_t)p->nkv * F);
-        c->rho = alloc_dev<c64>(c, F);
-        c->acc = alloc_dev<c64>(c, F);
-        c->t1 = alloc_dev<c64>(c, F);
-        c->t2 = alloc_dev<c64>(c, F);
-        c->t3 = alloc_dev<c64>(c, F);
+        const long R = p->nrhs_max;
+        c->xi = alloc_dev<c64>(c, (size_t)p->nkv * R * F);
+        c->chi = alloc_dev<c64>(c, (size_t)p->nkv * R * F);
+        c->rho = alloc_dev<c64>(c, R * F);
+        c->acc = alloc_dev<c64>(c, R * F);
+        c->t1 = alloc_dev<c64>(c, R * F);
+        c->t2 = alloc_dev<c64>(c, R * F);
+        c->t3 = alloc_dev<c64>(c, R * F);
         const long nf = p->nrhs_max > p->Ns ? p->nrhs_max : p->Ns;  // multi-field Schwarz buffers
         c->s32a = alloc_dev<c32>(c, (size_t)nf * F);
         c->s32b = alloc_dev<c32>(c, (size_t)nf * F);
         c->s32c = alloc_dev<c32>(c, F);
         if (p->sap_prec == DFL_F64)
             c->tN = alloc_dev<c64>(c, (size_t)p->Ns * F);
-        c->lxi = alloc_dev<c64>(c, (size_t)p->little_nkv * N);
-        c->lchi = alloc_dev<c64>(c, (size_t)p->little_nkv * N);
-        c->lr = alloc_dev<c64>(c, N);
-        c->lx = alloc_dev<c64>(c, N);
-        c->lw = alloc_dev<c64>(c, N);
+        c->lxi = alloc_dev<c64>(c, (size_t)p->little_nkv * R * N);
+        c->lchi = alloc_dev<c64>(c, (size_t)p->little_nkv * R * N);
+        c->lr = alloc_dev<c64>(c, R * N);
+        c->lx = alloc_dev<c64>(c, R * N);
+        c->lw = alloc_dev<c64>(c, R * N);
         c->lt = alloc_dev<c64>(c, N);
-        c->lw32 = alloc_dev<c32>(c, N);
-        c->lx32 = alloc_dev<c32>(c, N);
+        c->lw32 = alloc_dev<c32>(c, R * N);
+        c->lx32 = alloc_dev<c32>(c, R * N);
         c->lgrid = little_gcr_grid(c->g);
-        c->lpart = alloc_dev<double>(c, little_gcr_partial_doubles(c->lgrid));
+        size_t part = little_gcr_partial_doubles(c->lgrid);
+        if (R > 1) {
+            size_t nfin = 0, nac = 0;
+            part = std::max(part, little_gcr_multi_doubles(c->lgrid, (int)R, &nfin, &nac));
+            c->lfin = alloc_dev<double>(c, nfin);
+            c->lacoef = alloc_dev<double>(c, nac);
+        }
+        c->lpart = alloc_dev<double>(c, part);
         c->lstats = alloc_dev<int>(c, 4);
         c->lbar_count = alloc_dev<unsigned>(c, 64);
         c->lbar_gen = alloc_dev<unsigned long long>(c, 32);
-        c->red = alloc_dev<double>(c, (size_t)kMaxDot * kRedBlocks * 2);
-        c->dscal = alloc_dev<double>(c, S_TOTAL);
+        c->red = alloc_dev<double>(c, (size_t)kMaxDot * kRedBlocks * 2 * R);
+        c->dscal = alloc_dev<double>(c, S_TOTAL * R);
         c->dflag = alloc_dev<int>(c, 4);
-        HIPCHECK(hipHostMalloc((void**)&c->hscal, sizeof(double) * S_TOTAL, hipHostMallocDefault));
-        HIPCHECK(hipMemsetAsync(c->dscal, 0, sizeof(double) * S_TOTAL, c->stream));
+        c->dact = alloc_dev<int>(c, kMaxLittleRhs);
+        HIPCHECK(hipHostMalloc((void**)&c->hscal, sizeof(double) * S_TOTAL * R, hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&c->hact, sizeof(int) * kMaxLittleRhs, hipHostMallocDefault));
+        HIPCHECK(hipMemsetAsync(c->dscal, 0, sizeof(double) * S_TOTAL * R, c->stream));
+        HIPCHECK(hipMemsetAsync(c->dact, 0, sizeof(int) * kMaxLittleRhs, c->stream));
         HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
         HIPCHECK(hipMemsetAsync(c->lstats, 0, sizeof(int) * 4, c->stream));
         HIPCHECK(hipMemsetAsync(c->lbar_count, 0, sizeof(unsigned) * 64, c->stream));
@@ -835,17 +948,17 @@ int little_dirac_apply(dfl_ctx* c, const void* v, void* w, int nrhs, dfl_prec pr
     need_nrhs(c, nrhs);
     if (v == w)
         fail(DFL_EINVAL, "v and w must not overlap");
-    const long n = (long)c->g.Nb * c->p.Ns;
-    for (int r = 0; r < nrhs; ++r) {
-        if (prec == DFL_F64)
-            launch_little_apply<double>(c->g, c->A64, c->p.Ns, static_cast<const c64*>(v) + r * n,
-                                        static_cast<c64*>(w) + r * n, c->stream);
-        else if (prec == DFL_F32)
-            launch_little_apply<float>(c->g, c->A32, c->p.Ns, static_cast<const c32*>(v) + r * n,
-                                       static_cast<c32*>(w) + r * n, c->stream);
-        else
-            fail(DFL_EINVAL, "little vectors are F64 or F32");
-    }
+    if (prec == DFL_F64)
+        launch_little_apply<double>(c->g, c->A64, c->p.Ns, static_cast<const c64*>(v), static_cast<c64*>(w), nrhs,
+                                    c->stream);
+    else if (prec == DFL_F32 && nrhs == 1)
+        launch_little_apply<float>(c->g, c->A32, c->p.Ns, static_cast<const c32*>(v), static_cast<c32*>(w), 1,
+                                   c->stream);
+    else if (prec == DFL_F32)
+        launch_little_apply_mfma(c->g, c->At32, c->p.Ns, static_cast<const c32*>(v), static_cast<c32*>(w), nrhs,
+                                 c->stream);
+    else
+        fail(DFL_EINVAL, "little vectors are F64 or F32");
     HIPCHECK(hipGetLastError());
     API_END
 }
@@ -886,28 +999,26 @@ int deflate_project(dfl_ctx* c, dfl_proj which, const void* in, void* out, int n
         fail(DFL_EINVAL, "in and out must not overlap");
     const long F = c->field_elems;
     const double tol = c->p.little_tol_out;
-    for (int r = 0; r < nrhs; ++r) {
-        const c64* x = static_cast<const c64*>(in) + r * F;
-        c64* y = static_cast<c64*>(out) + r * F;
-        switch (which) {
-        case DFL_PROJ_PL:
-            apply_PL(c, x, y, tol, DFL_F64, c->t1, c->t2);
-            break;
-        case DFL_PROJ_PR:
-            dirac64(c, x, c->t1, c->p.m0);
-            coarse(c, c->t1, c->t2, tol, DFL_F64);
-            launch_sub<double>(x, c->t2, y, F, c->stream);
-            break;
-        case DFL_PROJ_P:
-            launch_restrict64(c->g, c->Phi, c->p.Ns, x, static_cast<c64*>(c->lw), c->stream);
-            launch_prolong64(c->g, c->Phi, c->p.Ns, static_cast<c64*>(c->lw), y, c->stream);
-            break;
-        case DFL_PROJ_COARSE:
-            coarse(c, x, y, tol, DFL_F64);
-            break;
-        default:
-            fail(DFL_EINVAL, "unknown projector");
-        }
+    const c64* x = static_cast<const c64*>(in);
+    c64* y = static_cast<c64*>(out);
+    switch (which) {
+    case DFL_PROJ_PL:
+        apply_PL(c, x, y, tol, DFL_F64, c->t1, c->t2, nrhs);
+        break;
+    case DFL_PROJ_PR:
+        dirac64(c, x, c->t1, c->p.m0, nrhs);
+        coarse(c, c->t1, c->t2, tol, DFL_F64, nrhs);
+        launch_sub<double>(x, c->t2, y, F * nrhs, c->stream);
+        break;
+    case DFL_PROJ_P:
+        launch_restrict64(c->g, c->Phi, c->p.Ns, x, static_cast<c64*>(c->lw), nrhs, c->stream);
+        launch_prolong64(c->g, c->Phi, c->p.Ns, static_cast<c64*>(c->lw), y, nrhs, c->stream);
+        break;
+    case DFL_PROJ_COARSE:
+        coarse(c, x, y, tol, DFL_F64, nrhs);
+        break;
+    default:
+        fail(DFL_EINVAL, "unknown projector");
     }
     HIPCHECK(hipGetLastError());
     API_END
@@ -930,92 +1041,90 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
         need_subspace(c);
     const long F = c->field_elems;
     const double m0 = c->p.m0;
-    for (int rhs = 0; rhs < nrhs; ++rhs) {
-        auto t0 = std::chrono::steady_clock::now();
-        const c64* eta = static_cast<const c64*>(eta_v) + rhs * F;
-        c64* psi = static_cast<c64*>(psi_v) + rhs * F;
-        HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
-        launch_finite_check<double>(eta, F, c->dflag, c->stream);
-        int flag = 0;
-        HIPCHECK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        double eta_n = std::sqrt(host_norm2<double>(c, eta, F));
-        if (flag)
-            fail(DFL_ENONFINITE, "non-finite entries in the source");
-        reset_little_stats(c);
-        // initial residue: P_L eta (deflated) or eta
-        if (deflate)
-            apply_PL(c, eta, c->rho, c->p.little_tol_out, DFL_F64, c->t1, c->t2);
+    const int nb = nrhs;
+    auto t0 = std::chrono::steady_clock::now();
+    const c64* eta = static_cast<const c64*>(eta_v);
+    c64* psi = static_cast<c64*>(psi_v);
+    HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+    launch_finite_check<double>(eta, F * nb, c->dflag, c->stream);
+    int flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> eta_n = host_norm2_b(c, eta, F, nb);
+    for (auto& q : eta_n)
+        q = std::sqrt(q);
+    if (flag)
+        fail(DFL_ENONFINITE, "non-finite entries in the source");
+    reset_little_stats(c);
+    // initial residues: P_L eta (deflated) or eta
+    if (deflate)
+        apply_PL(c, eta, c->rho, c->p.little_tol_out, DFL_F64, c->t1, c->t2, nb);
+    else
+        launch_copy<double>(eta, c->rho, F * nb, c->stream);
+    GcrVecs v{c->xi, c->chi, c->rho, c->acc};
+    const dfl_prec lp = c->p.little_prec;
+    auto precond = [&](const c64* r, c64* x, int n_b) {
+        if (use_sap)
+            sap_apply(c, r, x, m0, n_b);
         else
-            launch_copy<double>(eta, c->rho, F, c->stream);
-        GcrVecs v{c->xi, c->chi, c->rho, c->acc};
-        const dfl_prec lp = c->p.little_prec;
-        auto precond = [&](const c64* r, c64* x) {
-            if (use_sap)
-                sap_apply(c, r, x, m0);
-            else
-                launch_copy<double>(r, x, F, c->stream);
-        };
-        auto op = [&](const c64* x, c64* y) {
-            if (deflate) {
-                dirac64(c, x, c->t3, m0);
-                apply_PL(c, c->t3, y, c->p.little_tol_in, lp, c->t1, c->t2);
-            } else {
-                dirac64(c, x, y, m0);
-            }
-        };
-        auto recompute = [&](const c64* x, c64* r) {
-            dirac64(c, x, c->t1, m0);
-            if (deflate) {
-                launch_sub<double>(eta, c->t1, c->t3, F, c->stream);
-                apply_PL(c, c->t3, r, c->p.little_tol_out, DFL_F64, c->t1, c->t2);
-            } else {
-                launch_sub<double>(eta, c->t1, r, F, c->stream);
-            }
-        };
-        // With inexact projections inside the cycle (little solves to
-        // little_tol_in), the recursively updated residue stops tracking the
-        // true one once it has fallen by about that factor; the cycle is then
-        // ended early and the residue recomputed (appendix A.5).
-        const double cycle_floor = deflate ? 10.0 * c->p.little_tol_in : 0.0;
-        c->history.clear();
-        GcrResult res = gcr_run<double>(c, F, c->p.nkv, c->p.maxiter, c->p.tol, eta_n, v, precond, op, recompute,
-                                        cycle_floor, &c->history);
-        // final solution: psi = acc + Phi A^-1 Phi^+ (eta - D acc)   (eq. (3.10) with P_R)
+            launch_copy<double>(r, x, F * n_b, c->stream);
+    };
+    auto op = [&](const c64* x, c64* y, int n_b) {
         if (deflate) {
-            dirac64(c, c->acc, c->t1, m0);
-            launch_sub<double>(eta, c->t1, c->t3, F, c->stream);
-            coarse(c, c->t3, c->t1, c->p.little_tol_out, DFL_F64);
-            launch_copy<double>(c->acc, psi, F, c->stream);
-            // psi += t1 : coefficient 1 from a device scalar
-            c->hscal[S_ALPHA] = 1.0;
-            c->hscal[S_ALPHA + 1] = 0.0;
-            HIPCHECK(hipMemcpyAsync(c->dscal + S_ALPHA, c->hscal + S_ALPHA, sizeof(double) * 2,
-                                    hipMemcpyHostToDevice, c->stream));
-            launch_multiaxpy<double>(c->t1, F, 1, c->dscal + S_ALPHA, 1.0, psi, F, c->stream);
+            dirac64(c, x, c->t3, m0, n_b);
+            apply_PL(c, c->t3, y, c->p.little_tol_in, lp, c->t1, c->t2, n_b);
         } else {
-            launch_copy<double>(c->acc, psi, F, c->stream);
+            dirac64(c, x, y, m0, n_b);
         }
-        // true residual in FP64
-        dirac64(c, psi, c->t1, m0);
-        launch_sub<double>(eta, c->t1, c->t2, F, c->stream);
-        double rr = std::sqrt(host_norm2<double>(c, c->t2, F));
-        auto t1 = std::chrono::steady_clock::now();
-        int status = res.status;
-        double rel = eta_n > 0.0 ? rr / eta_n : 0.0;
+    };
+    auto recompute = [&](const c64* x, c64* r, int n_b) {
+        dirac64(c, x, c->t1, m0, n_b);
+        if (deflate) {
+            launch_sub<double>(eta, c->t1, c->t3, F * n_b, c->stream);
+            apply_PL(c, c->t3, r, c->p.little_tol_out, DFL_F64, c->t1, c->t2, n_b);
+        } else {
+            launch_sub<double>(eta, c->t1, r, F * n_b, c->stream);
+        }
+    };
+    // With inexact projections inside the cycle (little solves to
+    // little_tol_in), the recursively updated residue stops tracking the
+    // true one once it has fallen by about that factor; the cycle is then
+    // ended early and the residue recomputed (appendix A.5).
+    const double cycle_floor = deflate ? 10.0 * c->p.little_tol_in : 0.0;
+    c->history.clear();
+    std::vector<GcrResult> res = gcr_run(c, F, nb, c->p.nkv, c->p.maxiter, c->p.tol, eta_n, v, precond, op,
+                                         recompute, cycle_floor, &c->history);
+    // final solutions: psi = acc + Phi A^-1 Phi^+ (eta - D acc)   (eq. (3.10) with P_R)
+    if (deflate) {
+        dirac64(c, c->acc, c->t1, m0, nb);
+        launch_sub<double>(eta, c->t1, c->t3, F * nb, c->stream);
+        coarse(c, c->t3, c->t1, c->p.little_tol_out, DFL_F64, nb);
+        launch_add<double>(c->acc, c->t1, psi, F * nb, c->stream);
+    } else {
+        launch_copy<double>(c->acc, psi, F * nb, c->stream);
+    }
+    // true residuals in FP64
+    dirac64(c, psi, c->t1, m0, nb);
+    launch_sub<double>(eta, c->t1, c->t2, F * nb, c->stream);
+    std::vector<double> rr = host_norm2_b(c, c->t2, F, nb);
+    auto t1 = std::chrono::steady_clock::now();
+    int ls[3] = {0, 0, 0};
+    read_little_stats(c, ls);
+    for (int b = 0; b < nb; ++b) {
+        int status = res[b].status;
+        double rel = eta_n[b] > 0.0 ? std::sqrt(rr[b]) / eta_n[b] : 0.0;
         if (status == DFL_OK && rel > c->p.tol)
             status = DFL_NOT_CONVERGED;
         if (status != DFL_OK)
             worst = status;
         if (info) {
-            info->status = status;
-            info->n_gcr = res.iters;
-            info->n_restarts = res.restarts;
-            int ls[3];
-            read_little_stats(c, ls);
-            info->n_little = ls[0];
-            info->n_little_solves = ls[1];
-            info->rel_residual = rel;
-            info->t_solve = std::chrono::duration<double>(t1 - t0).count();
+            dfl_info& q = info[b];
+            q.status = status;
+            q.n_gcr = res[b].iters;
+            q.n_restarts = res[b].restarts;
+            q.n_little = ls[0];
+            q.n_little_solves = ls[1];
+            q.rel_residual = rel;
+            q.t_solve = std::chrono::duration<double>(t1 - t0).count();
         }
     }
     if (worst != DFL_OK) {

@@ -32,20 +32,40 @@ __global__ __launch_bounds__(256) void k_sub(const cpx<T>* __restrict__ x, const
         z[i] = cpx<T>{x[i].re - y[i].re, x[i].im - y[i].im};
 }
 
-// partial[(j0 + j)*2*kRedBlocks + 2*blockIdx + {0,1}] = this workgroup's share of (X_j, y)
+template <typename T>
+__global__ __launch_bounds__(256) void k_add(const cpx<T>* __restrict__ x, const cpx<T>* __restrict__ y,
+                                             cpx<T>* __restrict__ z, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        z[i] = cpx<T>{x[i].re + y[i].re, x[i].im + y[i].im};
+}
+
+// Batched forms: blockIdx.y is the right-hand side b; vectors of RHS b sit
+// at a fixed offset (xb, yb) from those of RHS 0, its partial sums at
+// b * kMaxDot * kRedBlocks * 2, its results at dst + b * dstride. A non-null
+// mask skips every RHS b with active[b] == 0 (nothing is read or written).
+
+// partial[(b*kMaxDot + j0 + j)*kRedBlocks + blockIdx)*2 + {0,1}] = this workgroup's share of (X_j, y)
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_multidot_partial(const cpx<T>* __restrict__ X, long stride, int j0,
                                                                   int m, const cpx<T>* __restrict__ y, long n,
+                                                                  long xb, long yb, const int* __restrict__ active,
                                                                   double* __restrict__ partial)
 {
+    const int b = blockIdx.y;
+    if (active && !active[b])
+        return;
+    X += b * xb;
+    y += b * yb;
+    partial += (long)b * kMaxDot * kRedBlocks * 2;
     __shared__ double sh[2 * kChunk][kRedThreads / 64];
     double re[kChunk], im[kChunk];
 #pragma unroll
     for (int j = 0; j < kChunk; ++j)
         re[j] = im[j] = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        cpx<T> b = y[i];
-        double br = (double)b.re, bi = (double)b.im;
+        cpx<T> bv = y[i];
+        double br = (double)bv.re, bi = (double)bv.im;
 #pragma unroll
         for (int j = 0; j < kChunk; ++j) {
             if (j < m) {
@@ -60,10 +80,10 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot_partial(const cpx<T>* 
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
         double a = wave_sum(re[j]);
-        double b = wave_sum(im[j]);
+        double c = wave_sum(im[j]);
         if (lane == 0) {
             sh[2 * j][wid] = a;
-            sh[2 * j + 1][wid] = b;
+            sh[2 * j + 1][wid] = c;
         }
     }
     __syncthreads();
@@ -76,16 +96,22 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot_partial(const cpx<T>* 
     }
 }
 
-// dst[2j + c] = sum over workgroups of partial for j < m (fixed order)
+// dst[b*dstride + 2j + c] = sum over workgroups of RHS b's partials, j < m (fixed order)
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int m,
-                                                         double* __restrict__ dst)
+                                                         double* __restrict__ dst, int dstride,
+                                                         const int* __restrict__ active)
 {
+    const int b = blockIdx.x;
+    if (active && !active[b])
+        return;
+    partial += (long)b * kMaxDot * kRedBlocks * 2;
+    dst += (long)b * dstride;
     __shared__ double sh[4];
     for (int jc = 0; jc < 2 * m; ++jc) {
         int j = jc >> 1, c = jc & 1;
         double t = 0.0;
-        for (int b = threadIdx.x; b < kRedBlocks; b += blockDim.x)
-            t += partial[((long)j * kRedBlocks + b) * 2 + c];
+        for (int q = threadIdx.x; q < kRedBlocks; q += blockDim.x)
+            t += partial[((long)j * kRedBlocks + q) * 2 + c];
         t = block_sum(t, sh);
         if (threadIdx.x == 0)
             dst[jc] = t;
@@ -94,14 +120,20 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
 }
 
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_norm2_partial(const cpx<T>* __restrict__ x, long n,
+__global__ __launch_bounds__(kRedThreads) void k_norm2_partial(const cpx<T>* __restrict__ x, long n, long xb,
+                                                               const int* __restrict__ active,
                                                                double* __restrict__ partial)
 {
+    const int b = blockIdx.y;
+    if (active && !active[b])
+        return;
+    x += b * xb;
+    partial += (long)b * kMaxDot * kRedBlocks * 2;
     __shared__ double sh[4];
     double t = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        double a = (double)x[i].re, b = (double)x[i].im;
-        t += a * a + b * b;
+        double a = (double)x[i].re, c = (double)x[i].im;
+        t += a * a + c * c;
     }
     t = block_sum(t, sh);
     if (threadIdx.x == 0) {
@@ -112,9 +144,16 @@ __global__ __launch_bounds__(kRedThreads) void k_norm2_partial(const cpx<T>* __r
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_multiaxpy(const cpx<T>* __restrict__ X, long stride, int m,
-                                                   const double* __restrict__ coef, double sign,
-                                                   cpx<T>* __restrict__ y, long n)
+                                                   const double* __restrict__ coef, int cstride, double sign,
+                                                   cpx<T>* __restrict__ y, long n, long xb, long yb,
+                                                   const int* __restrict__ active)
 {
+    const int b = blockIdx.y;
+    if (active && !active[b])
+        return;
+    X += b * xb;
+    y += b * yb;
+    coef += (long)b * cstride;
     __shared__ double c[2 * kMaxDot];
     for (int j = threadIdx.x; j < 2 * m; j += blockDim.x)
         c[j] = sign * coef[j];
@@ -132,9 +171,16 @@ __global__ __launch_bounds__(256) void k_multiaxpy(const cpx<T>* __restrict__ X,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_scale_invsqrt(cpx<T>* __restrict__ x, long n, const double* __restrict__ nrm2)
+__global__ __launch_bounds__(256) void k_scale_invsqrt(cpx<T>* __restrict__ x, long n, long xb,
+                                                       const double* __restrict__ nrm2, int cstride,
+                                                       const int* __restrict__ active)
 {
-    double f = 1.0 / sqrt(*nrm2);
+    const int b = blockIdx.y;
+    if (active && !active[b])
+        return;
+    x += b * xb;
+    const double q = nrm2[(long)b * cstride];
+    const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         x[i].re = (T)((double)x[i].re * f);
         x[i].im = (T)((double)x[i].im * f);
@@ -183,38 +229,77 @@ template <typename T> void launch_sub(const cpx<T>* x, const cpx<T>* y, cpx<T>* 
     hipLaunchKernelGGL(k_sub<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, y, z, n);
 }
 
+template <typename T> void launch_add(const cpx<T>* x, const cpx<T>* y, cpx<T>* z, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, y, z, n);
+}
+
+template <typename T>
+void launch_multidot_b(const cpx<T>* X, long stride, int m, const cpx<T>* y, long n, int nb, long xb, long yb,
+                       double* red, double* dst, int dstride, const int* active, hipStream_t s)
+{
+    if (m <= 0 || nb <= 0)
+        return;
+    for (int j0 = 0; j0 < m; j0 += kChunk) {
+        int mm = m - j0 < kChunk ? m - j0 : kChunk;
+        hipLaunchKernelGGL(k_multidot_partial<T>, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, s, X, stride, j0, mm,
+                           y, n, xb, yb, active, red);
+    }
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, s, red, m, dst, dstride, active);
+}
+
+template <typename T>
+void launch_norm2_b(const cpx<T>* x, long n, int nb, long xb, double* red, double* dst, int dstride,
+                    const int* active, hipStream_t s)
+{
+    if (nb <= 0)
+        return;
+    hipLaunchKernelGGL(k_norm2_partial<T>, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, s, x, n, xb, active, red);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, s, red, 1, dst, dstride, active);
+}
+
+template <typename T>
+void launch_multiaxpy_b(const cpx<T>* X, long stride, int m, const double* coef, int cstride, double sign, cpx<T>* y,
+                        long n, int nb, long xb, long yb, const int* active, hipStream_t s)
+{
+    if (m <= 0 || nb <= 0)
+        return;
+    hipLaunchKernelGGL(k_multiaxpy<T>, dim3(stream_grid(n), nb), dim3(256), 0, s, X, stride, m, coef, cstride, sign,
+                       y, n, xb, yb, active);
+}
+
+template <typename T>
+void launch_scale_invsqrt_b(cpx<T>* x, long n, int nb, long xb, const double* nrm2, int cstride, const int* active,
+                            hipStream_t s)
+{
+    if (nb <= 0)
+        return;
+    hipLaunchKernelGGL(k_scale_invsqrt<T>, dim3(stream_grid(n), nb), dim3(256), 0, s, x, n, xb, nrm2, cstride,
+                       active);
+}
+
 template <typename T>
 void launch_multidot(const cpx<T>* X, long stride, int m, const cpx<T>* y, long n, double* red, double* dst,
                      hipStream_t s)
 {
-    if (m <= 0)
-        return;
-    for (int j0 = 0; j0 < m; j0 += kChunk) {
-        int mm = m - j0 < kChunk ? m - j0 : kChunk;
-        hipLaunchKernelGGL(k_multidot_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, X, stride, j0, mm, y,
-                           n, red);
-    }
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, red, m, dst);
+    launch_multidot_b<T>(X, stride, m, y, n, 1, 0, 0, red, dst, 0, nullptr, s);
 }
 
 template <typename T> void launch_norm2(const cpx<T>* x, long n, double* red, double* dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_norm2_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, x, n, red);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, red, 1, dst);
+    launch_norm2_b<T>(x, n, 1, 0, red, dst, 0, nullptr, s);
 }
 
 template <typename T>
 void launch_multiaxpy(const cpx<T>* X, long stride, int m, const double* coef, double sign, cpx<T>* y, long n,
                       hipStream_t s)
 {
-    if (m <= 0)
-        return;
-    hipLaunchKernelGGL(k_multiaxpy<T>, dim3(stream_grid(n)), dim3(256), 0, s, X, stride, m, coef, sign, y, n);
+    launch_multiaxpy_b<T>(X, stride, m, coef, 0, sign, y, n, 1, 0, 0, nullptr, s);
 }
 
 template <typename T> void launch_scale_invsqrt(cpx<T>* x, long n, const double* nrm2, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scale_invsqrt<T>, dim3(stream_grid(n)), dim3(256), 0, s, x, n, nrm2);
+    launch_scale_invsqrt_b<T>(x, n, 1, 0, nrm2, 0, nullptr, s);
 }
 
 void launch_add_scalars(const double* a, const double* b, double* dst, int m, hipStream_t s)
@@ -231,11 +316,18 @@ template <typename T> void launch_finite_check(const cpx<T>* x, long n, int* fla
     template void launch_zero<T>(cpx<T>*, long, hipStream_t);                                                     \
     template void launch_copy<T>(const cpx<T>*, cpx<T>*, long, hipStream_t);                                      \
     template void launch_sub<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, long, hipStream_t);                        \
+    template void launch_add<T>(const cpx<T>*, const cpx<T>*, cpx<T>*, long, hipStream_t);                        \
     template void launch_multidot<T>(const cpx<T>*, long, int, const cpx<T>*, long, double*, double*, hipStream_t); \
     template void launch_norm2<T>(const cpx<T>*, long, double*, double*, hipStream_t);                            \
     template void launch_multiaxpy<T>(const cpx<T>*, long, int, const double*, double, cpx<T>*, long, hipStream_t); \
     template void launch_scale_invsqrt<T>(cpx<T>*, long, const double*, hipStream_t);                            \
-    template void launch_finite_check<T>(const cpx<T>*, long, int*, hipStream_t);
+    template void launch_finite_check<T>(const cpx<T>*, long, int*, hipStream_t);                                 \
+    template void launch_multidot_b<T>(const cpx<T>*, long, int, const cpx<T>*, long, int, long, long, double*,    \
+                                       double*, int, const int*, hipStream_t);                                    \
+    template void launch_norm2_b<T>(const cpx<T>*, long, int, long, double*, double*, int, const int*, hipStream_t); \
+    template void launch_multiaxpy_b<T>(const cpx<T>*, long, int, const double*, int, double, cpx<T>*, long, int,  \
+                                        long, long, const int*, hipStream_t);                                     \
+    template void launch_scale_invsqrt_b<T>(cpx<T>*, long, int, long, const double*, int, const int*, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

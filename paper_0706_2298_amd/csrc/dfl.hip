@@ -10,72 +10,100 @@ namespace {
 
 constexpr int kBT = 256;  // threads per block-kernel workgroup
 
-// w[blk*Ns + k] = sum_{x in blk} sum_c conj(Phi_k(x,c)) psi(x,c)   (eq. (4.1))
-__global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict__ Phi, int Ns,
-                                                  const c64* __restrict__ psi, c64* __restrict__ w)
+constexpr int kRB = 8;  // right-hand sides per pass of the batched projections
+
+// Address of the e-th of the 12*Vb entries of block blk in a native field.
+// When Vb is a multiple of the 64-site tile, a block is one contiguous run.
+__device__ inline long block_elem(const Geom& g, int blk, int e)
 {
-    __shared__ double part[2 * 64][kBT / 64];
-    const int blk = blockIdx.x;
-    const long base = (long)blk * g.Vb;
+    if ((g.Vb & (kTile - 1)) == 0)
+        return (long)blk * 12 * g.Vb + e;
+    const int t = e % g.Vb, c = e / g.Vb;
+    return tidx((long)blk * g.Vb + t, c, 12);
+}
+
+// w_b[blk*Ns + k] = sum_{x in blk} sum_c conj(Phi_k(x,c)) psi_b(x,c)   (eq. (4.1))
+// One workgroup per (block, k); the Ns workgroups of a block are adjacent in
+// the XCD-remapped order, so the block of psi_b is fetched into one L2. The
+// Phi_k entries are read once per chunk of kRB right-hand sides.
+__global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict__ Phi, int Ns,
+                                                  const c64* __restrict__ psi, c64* __restrict__ w, int nrhs,
+                                                  int grid_padded)
+{
+    __shared__ double part[2 * kRB][kBT / 64];
+    const int q = xcd_remap(blockIdx.x, grid_padded);
+    if (q >= g.Nb * Ns)
+        return;
+    const int blk = q / Ns, k = q - blk * Ns;
     const long fs = 12 * g.V;
+    const long nw = (long)g.Nb * Ns;
+    const c64* ph = Phi + (long)k * fs;
+    const int ne = 12 * g.Vb;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k0 = 0; k0 < Ns; k0 += 64) {
-        int kn = Ns - k0 < 64 ? Ns - k0 : 64;
-        for (int kk = 0; kk < kn; ++kk) {
-            const c64* ph = Phi + (long)(k0 + kk) * fs;
-            double re = 0.0, im = 0.0;
-            for (int t = threadIdx.x; t < g.Vb; t += kBT) {
-                long s = base + t;
+    for (int b0 = 0; b0 < nrhs; b0 += kRB) {
+        double re[kRB], im[kRB];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) {
-                    c64 a = ph[tidx(s, c, 12)];
-                    c64 b = psi[tidx(s, c, 12)];
-                    re += a.re * b.re + a.im * b.im;
-                    im += a.re * b.im - a.im * b.re;
+        for (int j = 0; j < kRB; ++j)
+            re[j] = im[j] = 0.0;
+        for (int e = threadIdx.x; e < ne; e += kBT) {
+            const long i = block_elem(g, blk, e);
+            const c64 a = ph[i];
+#pragma unroll
+            for (int j = 0; j < kRB; ++j)
+                if (b0 + j < nrhs) {
+                    const c64 b = psi[(long)(b0 + j) * fs + i];
+                    re[j] += a.re * b.re + a.im * b.im;
+                    im[j] += a.re * b.im - a.im * b.re;
                 }
-            }
-            re = wave_sum(re);
-            im = wave_sum(im);
+        }
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) {
+            double x = wave_sum(re[j]), y = wave_sum(im[j]);
             if (lane == 0) {
-                part[2 * kk][wid] = re;
-                part[2 * kk + 1][wid] = im;
+                part[2 * j][wid] = x;
+                part[2 * j + 1][wid] = y;
             }
         }
         __syncthreads();
-        if (threadIdx.x < 2 * kn) {
+        if (threadIdx.x < 2 * kRB && b0 + (threadIdx.x >> 1) < nrhs) {
             double t = 0.0;
-            for (int q = 0; q < kBT / 64; ++q)
-                t += part[threadIdx.x][q];
-            double* dst = reinterpret_cast<double*>(w + (long)blk * Ns + k0);
-            dst[threadIdx.x] = t;
+            for (int u = 0; u < kBT / 64; ++u)
+                t += part[threadIdx.x][u];
+            double* dst = reinterpret_cast<double*>(w + (long)(b0 + (threadIdx.x >> 1)) * nw + q);
+            dst[threadIdx.x & 1] = t;
         }
         __syncthreads();
     }
 }
 
-// psi(x) = sum_k Phi_k(x) v[blk*Ns + k]
+// psi_b(i) = sum_k Phi_k(i) v_b[blk(i)*Ns + k], one thread per field entry
 __global__ __launch_bounds__(256) void k_prolong(Geom g, const c64* __restrict__ Phi, int Ns,
-                                                 const c64* __restrict__ v, c64* __restrict__ psi)
+                                                 const c64* __restrict__ v, c64* __restrict__ psi, int nrhs)
 {
-    long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.V)
-        return;
-    long blk = s / g.Vb;
     const long fs = 12 * g.V;
-    c64 acc[12];
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= fs)
+        return;
+    const long s = (i / (12 * kTile)) * kTile + (i & (kTile - 1));
+    const long blk = s / g.Vb;
+    const long nw = (long)g.Nb * Ns;
+    for (int b0 = 0; b0 < nrhs; b0 += kRB) {
+        c64 acc[kRB];
 #pragma unroll
-    for (int c = 0; c < 12; ++c)
-        acc[c] = c64{0.0, 0.0};
-    for (int k = 0; k < Ns; ++k) {
-        c64 vk = v[blk * Ns + k];
-        const c64* ph = Phi + (long)k * fs;
+        for (int j = 0; j < kRB; ++j)
+            acc[j] = c64{0.0, 0.0};
+        for (int k = 0; k < Ns; ++k) {
+            const c64 a = Phi[(long)k * fs + i];
 #pragma unroll
-        for (int c = 0; c < 12; ++c)
-            acc[c] += ph[tidx(s, c, 12)] * vk;
+            for (int j = 0; j < kRB; ++j)
+                if (b0 + j < nrhs)
+                    acc[j] += a * v[(long)(b0 + j) * nw + blk * Ns + k];
+        }
+#pragma unroll
+        for (int j = 0; j < kRB; ++j)
+            if (b0 + j < nrhs)
+                psi[(long)(b0 + j) * fs + i] = acc[j];
     }
-#pragma unroll
-    for (int c = 0; c < 12; ++c)
-        psi[tidx(s, c, 12)] = acc[c];
 }
 
 // Modified Gram-Schmidt per block, in place, order l = 0..Ns-1 (eq. (4.2)).
@@ -176,35 +204,40 @@ __global__ __launch_bounds__(kBT) void k_little_column(Geom g, const c64* __rest
     }
 }
 
-// w[blk] = sum_d A[blk][d] v[nbr_d(blk)], one thread per (blk, k) row
+__device__ inline int block_nbr(const Geom& g, int blk, int d)
+{
+    if (d == 0)
+        return blk;
+    const int mu = (d - 1) >> 1;
+    int rest = blk;
+    for (int nu = 3; nu > mu; --nu)
+        rest /= g.nb[nu];
+    const int n_mu = rest % g.nb[mu];
+    int nn = n_mu + ((d & 1) ? 1 : -1);
+    if (nn < 0)
+        nn += g.nb[mu];
+    if (nn >= g.nb[mu])
+        nn -= g.nb[mu];
+    return blk + (nn - n_mu) * g.bstr[mu];
+}
+
+// w_b[blk] = sum_d A[blk][d] v_b[nbr_d(blk)], one thread per (blk, k) row,
+// blockIdx.y = right-hand side b (little vectors of Nb*Ns entries, back to back)
 template <typename T>
 __global__ __launch_bounds__(256) void k_little_apply(Geom g, const cpx<T>* __restrict__ A, int Ns,
                                                       const cpx<T>* __restrict__ v, cpx<T>* __restrict__ w)
 {
+    const long nw = (long)g.Nb * Ns;
     long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= (long)g.Nb * Ns)
+    if (row >= nw)
         return;
+    v += blockIdx.y * nw;
+    w += blockIdx.y * nw;
     int blk = (int)(row / Ns);
     int k = (int)(row - (long)blk * Ns);
-    int n[4];
-    int rest = blk;
-    for (int mu = 3; mu >= 0; --mu) {
-        n[mu] = rest % g.nb[mu];
-        rest /= g.nb[mu];
-    }
     double re = 0.0, im = 0.0;
     for (int d = 0; d < 9; ++d) {
-        int nbr = blk;
-        if (d > 0) {
-            int mu = (d - 1) >> 1;
-            int step = (d & 1) ? +1 : -1;
-            int nn = n[mu] + step;
-            if (nn < 0)
-                nn += g.nb[mu];
-            if (nn >= g.nb[mu])
-                nn -= g.nb[mu];
-            nbr = blk + (nn - n[mu]) * g.bstr[mu];
-        }
+        const int nbr = block_nbr(g, blk, d);
         const cpx<T>* a = A + (((long)blk * 9 + d) * Ns + k) * Ns;
         const cpx<T>* x = v + (long)nbr * Ns;
         for (int l = 0; l < Ns; ++l) {
@@ -214,6 +247,75 @@ __global__ __launch_bounds__(256) void k_little_apply(Geom g, const cpx<T>* __re
         }
     }
     w[row] = cpx<T>{(T)re, (T)im};
+}
+
+// Batched FP32 little apply on the matrix cores. For one block the complex
+// product Y = sum_d A_d V_d (A_d: Ns x Ns, V_d: Ns x nrhs, the right-hand
+// sides' entries on the d-th neighbour block) is the real product of the
+// 2Ns x 18Ns matrix with entries Re/Im of A_d arranged as [[ar, -ai],[ai, ar]]
+// per complex entry (rows and columns interleaved re/im) and the 18Ns x nrhs
+// matrix of the V_d entries read as reals. It runs as 16x16x4 FP32 MFMA
+// tiles: wave t of the workgroup owns rows [16t, 16t + 16) of the real
+// product, 16 right-hand sides per pass. The V_d entries of the pass are
+// staged in LDS as [d][l][b] complex.
+constexpr int kMfmaRhs = 16;
+
+__global__ __launch_bounds__(256) void k_little_apply_mfma(Geom g, const c32* __restrict__ At, int Ns,
+                                                           const c32* __restrict__ v, c32* __restrict__ w, int nrhs)
+{
+    extern __shared__ c32 vs[];  // [9][Ns][kMfmaRhs]
+    const long nw = (long)g.Nb * Ns;
+    const int blk = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m_tiles = (2 * Ns + 15) / 16;
+    const int n = lane & 15, kq = lane >> 4;
+    const c32* Ab = At + (long)blk * 9 * Ns * Ns;  // [d][l][k] = A[d][k][l]
+    for (int b0 = 0; b0 < nrhs; b0 += kMfmaRhs) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 9 * Ns * kMfmaRhs; e += blockDim.x) {
+            const int b = e % kMfmaRhs;
+            const int dl = e / kMfmaRhs;
+            const int d = dl / Ns, l = dl - d * Ns;
+            c32 x{0.f, 0.f};
+            if (b0 + b < nrhs)
+                x = v[(long)(b0 + b) * nw + (long)block_nbr(g, blk, d) * Ns + l];
+            vs[e] = x;
+        }
+        __syncthreads();
+        for (int t = wave; t < m_tiles; t += blockDim.x / 64) {
+            const int rr = 16 * t + n;  // real row of the A operand held by this lane
+            const int m = rr >> 1, cr = rr & 1;
+            __attribute__((ext_vector_type(4))) float acc = {0.f, 0.f, 0.f, 0.f};
+            for (int d = 0; d < 9; ++d) {
+                const c32* Ad = Ab + (long)d * Ns * Ns;
+                for (int kc = 0; kc < 2 * Ns; kc += 4) {
+                    const int kk = kc + kq;  // real column index of the contraction
+                    const int l = kk >> 1, ck = kk & 1;
+                    float a = 0.f, bv = 0.f;
+                    if (kk < 2 * Ns) {
+                        if (m < Ns) {
+                            const c32 z = Ad[(long)l * Ns + m];
+                            a = cr == 0 ? (ck == 0 ? z.re : -z.im) : (ck == 0 ? z.im : z.re);
+                        }
+                        const c32 y = vs[(d * Ns + l) * kMfmaRhs + n];
+                        bv = ck == 0 ? y.re : y.im;
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+                }
+            }
+            // lane holds rows 16t + 4*(lane/16) + i, column n
+            if (b0 + n < nrhs) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int ro = 16 * t + 4 * kq + i;
+                    if (ro < 2 * Ns) {
+                        float* dst = reinterpret_cast<float*>(w + (long)(b0 + n) * nw + (long)blk * Ns + (ro >> 1));
+                        dst[ro & 1] = acc[i];
+                    }
+                }
+            }
+        }
+    }
 }
 
 __global__ void k_little_shift(Geom g, c64* A, int Ns, double dm)
@@ -251,13 +353,15 @@ __global__ void k_c64_to_c32(const c64* a, c32* b, long n)
 
 }  // namespace
 
-void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, hipStream_t s)
+void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_restrict, dim3(g.Nb), dim3(kBT), 0, s, g, Phi, Ns, psi, w);
+    const int gp = pad_grid((long)g.Nb * Ns);
+    hipLaunchKernelGGL(k_restrict, dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
 }
-void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, hipStream_t s)
+void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prolong, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi);
+    const long n = 12 * g.V;
+    hipLaunchKernelGGL(k_prolong, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi, nrhs);
 }
 void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, hipStream_t s)
 {
@@ -268,13 +372,20 @@ void launch_little_column64(const Geom& g, const c64* Phi, int Ns, const c64* Y,
     hipLaunchKernelGGL(k_little_column, dim3(g.Nb), dim3(kBT), 0, s, g, Phi, Ns, Y, A, d, l);
 }
 template <typename T>
-void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, hipStream_t s)
+void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, int nrhs, hipStream_t s)
 {
     long rows = (long)g.Nb * Ns;
-    hipLaunchKernelGGL(k_little_apply<T>, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, g, A, Ns, v, w);
+    hipLaunchKernelGGL(k_little_apply<T>, dim3((unsigned)((rows + 255) / 256), nrhs), dim3(256), 0, s, g, A, Ns, v,
+                       w);
 }
-template void launch_little_apply<double>(const Geom&, const c64*, int, const c64*, c64*, hipStream_t);
-template void launch_little_apply<float>(const Geom&, const c32*, int, const c32*, c32*, hipStream_t);
+template void launch_little_apply<double>(const Geom&, const c64*, int, const c64*, c64*, int, hipStream_t);
+template void launch_little_apply<float>(const Geom&, const c32*, int, const c32*, c32*, int, hipStream_t);
+
+void launch_little_apply_mfma(const Geom& g, const c32* At, int Ns, const c32* v, c32* w, int nrhs, hipStream_t s)
+{
+    const size_t lds = sizeof(c32) * 9 * Ns * kMfmaRhs;
+    hipLaunchKernelGGL(k_little_apply_mfma, dim3(g.Nb), dim3(256), lds, s, g, At, Ns, v, w, nrhs);
+}
 
 void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s)
 {

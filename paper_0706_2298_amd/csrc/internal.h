@@ -54,6 +54,16 @@ constexpr int kRedThreads = 256;
 constexpr int kMaxDot = 64;       // most vectors in one multi-dot
 constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
 constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
+constexpr int kMaxLittleRhs = 16;    // right-hand sides of one batched little solve
+
+// The same for nrhs systems at once (nrhs <= kMaxLittleRhs): w, x, r hold
+// nrhs little vectors back to back, xi and chi nkv * nrhs. Sizes of part,
+// fin and acoef (doubles) come from little_gcr_multi_doubles.
+size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef);
+template <typename T>
+void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
+                             const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
+                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s);
 
 }  // namespace dfl
 
@@ -109,11 +119,15 @@ struct dfl_ctx {
     unsigned* lbar_count = nullptr;         // grid barrier of the little GCR kernel
     unsigned long long* lbar_gen = nullptr;
     int lgrid = 0;             // its grid size
+    double* lfin = nullptr;    // batched little GCR: reduced sums and per-workgroup coefficients
+    double* lacoef = nullptr;
     // reductions and scalars
     double* red = nullptr;       // kRedBlocks * 2 * kMaxDot partials
     double* dscal = nullptr;     // device scalars
     double* hscal = nullptr;     // pinned host mirror
     int* dflag = nullptr;        // device status flag
+    int* dact = nullptr;         // per-RHS active mask of the batched GCR
+    int* hact = nullptr;         // pinned host mirror
     size_t alloc_bytes = 0;
     std::vector<double> history;  // outer GCR residues of the last solve
     // kernel-class timers
@@ -157,6 +171,8 @@ void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const
 // ------------------------------------------------------------------ blas.hip
 template <typename T> void launch_zero(cpx<T>* x, long n, hipStream_t s);
 template <typename T> void launch_copy(const cpx<T>* x, cpx<T>* y, long n, hipStream_t s);
+// z = x + y
+template <typename T> void launch_add(const cpx<T>* x, const cpx<T>* y, cpx<T>* z, long n, hipStream_t s);
 // z = x - y
 template <typename T> void launch_sub(const cpx<T>* x, const cpx<T>* y, cpx<T>* z, long n, hipStream_t s);
 // out[j] = (X_j, y) for j < m, X_j = X + j*stride; complex results to dst (2 doubles each)
@@ -171,24 +187,43 @@ void launch_multiaxpy(const cpx<T>* X, long stride, int m, const double* coef, d
                       long n, hipStream_t s);
 // x *= 1/sqrt(*nrm2)
 template <typename T> void launch_scale_invsqrt(cpx<T>* x, long n, const double* nrm2, hipStream_t s);
+// Batched forms over nb right-hand sides: RHS b's vectors at offsets b*xb
+// (X, x) and b*yb (y), its scalars at b*cstride / b*dstride; RHS with
+// active[b] == 0 are skipped when active is non-null. red holds kMaxDot *
+// kRedBlocks * 2 doubles per RHS.
+template <typename T>
+void launch_multidot_b(const cpx<T>* X, long stride, int m, const cpx<T>* y, long n, int nb, long xb, long yb,
+                       double* red, double* dst, int dstride, const int* active, hipStream_t s);
+template <typename T>
+void launch_norm2_b(const cpx<T>* x, long n, int nb, long xb, double* red, double* dst, int dstride,
+                    const int* active, hipStream_t s);
+template <typename T>
+void launch_multiaxpy_b(const cpx<T>* X, long stride, int m, const double* coef, int cstride, double sign, cpx<T>* y,
+                        long n, int nb, long xb, long yb, const int* active, hipStream_t s);
+template <typename T>
+void launch_scale_invsqrt_b(cpx<T>* x, long n, int nb, long xb, const double* nrm2, int cstride, const int* active,
+                            hipStream_t s);
 // dst[0..1] = a[0..1] + b[0..1] for m complex
 void launch_add_scalars(const double* a, const double* b, double* dst, int m, hipStream_t s);
 // finite check: flag |= 1 if any entry of x is NaN or Inf
 template <typename T> void launch_finite_check(const cpx<T>* x, long n, int* flag, hipStream_t s);
 
 // ------------------------------------------------------------------- dfl.hip
-// w[blk][k] = (Phi_k, psi) over each layout block, nrhs fields
-void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, hipStream_t s);
-// psi = sum_k Phi_k v[blk][k]
-void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, hipStream_t s);
+// w_b[blk][k] = (Phi_k, psi_b) over each layout block, nrhs fields (little
+// vectors of Nb*Ns entries back to back)
+void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s);
+// psi_b = sum_k Phi_k v_b[blk][k]
+void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s);
 // block Gram-Schmidt in place on Ns fields (modified GS, order l = 0..Ns-1)
 void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, hipStream_t s);
 // A[blk][d][k][l] = (Phi_k, Y) over each block; Y given, fixed d and l
 void launch_little_column64(const Geom& g, const c64* Phi, int Ns, const c64* Y, c64* A, int d, int l,
                             hipStream_t s);
-// w = A v (9-point block stencil)
+// w_b = A v_b (9-point block stencil) for nrhs little vectors
 template <typename T>
-void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, hipStream_t s);
+void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, int nrhs, hipStream_t s);
+// the same in FP32 on the matrix cores, from the transposed blocks At
+void launch_little_apply_mfma(const Geom& g, const c32* At, int Ns, const c32* v, c32* w, int nrhs, hipStream_t s);
 // A[blk][0][k][k] += dm  (mass shift)
 void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s);
 void launch_c64_to_c32(const c64* a, c32* b, long n, hipStream_t s);
@@ -204,5 +239,14 @@ template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                        unsigned long long* bar_gen, hipStream_t s);
+
+// The same for nrhs systems at once (nrhs <= kMaxLittleRhs): w, x, r hold
+// nrhs little vectors back to back, xi and chi nkv * nrhs. Sizes of part,
+// fin and acoef (doubles) come from little_gcr_multi_doubles.
+size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef);
+template <typename T>
+void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
+                             const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
+                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s);
 
 }  // namespace dfl

@@ -441,6 +441,520 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
     }
 }
 
+// ------------------------------------------------------------ many sources
+//
+// The same GCR for nrhs little systems A v_b = w_b at once: the right-hand
+// sides share the launch, the grid barriers and the reads of A, and each has
+// its own Krylov space, coefficients and convergence test. Vectors of RHS b
+// sit at b * N (w, x, r) and at (k * nrhs + b) * N (xi_k, chi_k).
+// Reductions over the workgroups are two-level: partial sums, a barrier,
+// workgroup g sums the slots t = g mod G into fin, a barrier, everyone reads
+// fin. A RHS leaves the cycle when it converges or its new direction falls
+// in the span; the cycle ends when no RHS is left in it.
+
+constexpr int RS = 2 * NK + 2;  // slots of one pass per RHS
+
+template <typename T> struct LittleMultiArgs {
+    Geom g;
+    int Ns, nkv, maxiter, nrhs;
+    double tol2;
+    const cpx<T>* At;
+    const cpx<T>* w;
+    cpx<T>* x;
+    cpx<T>* r;
+    cpx<T>* xi;
+    cpx<T>* chi;
+    double* part;   // [NSLOT][nrhs][G] complex
+    double* fin;    // [nrhs][RS] complex
+    double* acoef;  // [G][nrhs][NK][NK] complex (each workgroup's own copy)
+    int* stats;
+    unsigned* bar_count;
+    unsigned long long* bar_gen;
+};
+
+template <typename T> struct MultiCtx {
+    const LittleMultiArgs<T>& a;
+    int G, g, t, nbg, R;
+    long N;
+    __device__ long entry(int e) const
+    {
+        int i = e / a.Ns;
+        int k = e - i * a.Ns;
+        return (long)(g + i * G) * a.Ns + k;
+    }
+    __device__ double* pslot(int slot, int b) const { return a.part + (((long)slot * a.nrhs + b) * G + g) * 2; }
+};
+
+// y_b = A v_b on the owned rows for the listed right-hand sides. A unit is
+// (owned block, RHS); a round covers LT / (9 Ns) units, task (unit, d, k)
+// forms one neighbour term as in apply_rows.
+template <typename T>
+__device__ inline void apply_multi(const MultiCtx<T>& c, const cpx<T>* __restrict__ v, long vstride,
+                                   cpx<T>* __restrict__ y, long ystride, const int* list, int nlist, double* lds)
+{
+    const Geom& g = c.a.g;
+    const int Ns = c.a.Ns;
+    const int per = 9 * Ns;
+    const int upr = per <= LT ? LT / per : 1;
+    const long nu = (long)c.nbg * nlist;
+    for (long u0 = 0; u0 < nu; u0 += upr) {
+        for (int task0 = 0; task0 < upr * per; task0 += LT) {
+            const int task = task0 + c.t;
+            const int iu = task / per;
+            const int rem = task - iu * per;
+            const int d = rem / Ns;
+            const int k = rem - d * Ns;
+            if (iu < upr && u0 + iu < nu && task < 2 * LT / 2) {
+                const long u = u0 + iu;
+                const int ib = (int)(u / nlist);
+                const int b = list[u - (long)ib * nlist];
+                const int blk = c.g + ib * c.G;
+                int nbr = blk;
+                if (d > 0) {
+                    const int mu = (d - 1) >> 1;
+                    int rest = blk;
+                    for (int nu2 = 3; nu2 > mu; --nu2)
+                        rest /= g.nb[nu2];
+                    const int n_mu = rest % g.nb[mu];
+                    int nn = n_mu + ((d & 1) ? 1 : -1);
+                    if (nn < 0)
+                        nn += g.nb[mu];
+                    if (nn >= g.nb[mu])
+                        nn -= g.nb[mu];
+                    nbr = blk + (nn - n_mu) * g.bstr[mu];
+                }
+                const cpx<T>* At = c.a.At + ((long)blk * 9 + d) * Ns * Ns + k;
+                const cpx<T>* vv = v + b * vstride + (long)nbr * Ns;
+                double re = 0.0, im = 0.0;
+#pragma unroll 8
+                for (int l = 0; l < Ns; ++l) {
+                    cpx<T> p = At[(long)l * Ns];
+                    cpx<T> q = vv[l];
+                    re += (double)p.re * (double)q.re - (double)p.im * (double)q.im;
+                    im += (double)p.re * (double)q.im + (double)p.im * (double)q.re;
+                }
+                lds[2 * task] = re;
+                lds[2 * task + 1] = im;
+            }
+        }
+        __syncthreads();
+        for (int q = c.t; q < upr * Ns; q += LT) {
+            const int ju = q / Ns, kk = q - ju * Ns;
+            if (u0 + ju < nu) {
+                double sr = 0.0, si = 0.0;
+                for (int dd = 0; dd < 9; ++dd) {
+                    sr += lds[2 * (ju * per + dd * Ns + kk)];
+                    si += lds[2 * (ju * per + dd * Ns + kk) + 1];
+                }
+                const long u = u0 + ju;
+                const int ib = (int)(u / nlist);
+                const int b = list[u - (long)ib * nlist];
+                const int blk = c.g + ib * c.G;
+                y[b * ystride + (long)blk * Ns + kk] = cpx<T>{(T)sr, (T)si};
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// part[slot][b][g] = ||v_b||^2 over the owned entries, one wavefront per listed RHS
+template <typename T>
+__device__ inline void multi_norm2(const MultiCtx<T>& c, const cpx<T>* v, const int* list, int nlist, int slot)
+{
+    const int lane = c.t & 63, wv = c.t >> 6;
+    for (int bi = wv; bi < nlist; bi += LT / 64) {
+        const int b = list[bi];
+        const cpx<T>* vb = v + b * c.N;
+        double s = 0.0;
+        for (int e = lane; e < c.R; e += 64) {
+            cpx<T> z = vb[c.entry(e)];
+            s += (double)z.re * (double)z.re + (double)z.im * (double)z.im;
+        }
+        s = wave_sum(s);
+        if (lane == 0) {
+            double* p = c.pslot(slot, b);
+            p[0] = s;
+            p[1] = 0.0;
+        }
+    }
+}
+
+// every workgroup: out[b] = sum over workgroups of part[slot][b] (real part), listed RHS
+__device__ inline void multi_reduce_real(const double* part, int nrhs, int G, int slot, const int* list, int nlist,
+                                         double* out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int bi = wv; bi < nlist; bi += LT / 64) {
+        const int b = list[bi];
+        double s = 0.0;
+        for (int q = lane; q < G; q += 64)
+            s += part[(((long)slot * nrhs + b) * G + q) * 2];
+        s = wave_sum(s);
+        if (lane == 0)
+            out[b] = s;
+    }
+    __syncthreads();
+}
+
+// Gram-Schmidt partial sums for the listed RHS into slots slot0 + s, s < 2k+2
+// (same layout as partial_pass); 16-lane groups per (RHS, slot).
+template <typename T>
+__device__ inline void multi_pass(const MultiCtx<T>& c, int k, const int* list, int nlist, int slot0)
+{
+    const int ns = 2 * k + 2;
+    const int l16 = c.t & 15, grp = c.t >> 4;
+    const long N = c.N;
+    const int nr = c.a.nrhs;
+    for (int task = grp; task < nlist * ns; task += LT / 16) {
+        const int bi = task / ns, s = task - bi * ns;
+        const int b = list[bi];
+        const cpx<T>* y = c.a.chi + ((long)k * nr + b) * N;
+        const cpx<T>* r = c.a.r + b * N;
+        const cpx<T>* u;
+        const cpx<T>* v;
+        if (s < k) {
+            u = c.a.chi + ((long)s * nr + b) * N;
+            v = y;
+        } else if (s < 2 * k) {
+            u = c.a.chi + ((long)(s - k) * nr + b) * N;
+            v = r;
+        } else {
+            u = y;
+            v = (s == 2 * k) ? y : r;
+        }
+        double2 acc = make_double2(0.0, 0.0);
+        for (int e = l16; e < c.R; e += 16) {
+            long i = c.entry(e);
+            cpx<T> p = u[i], q = v[i];
+            acc = cfma_conj(acc, (double)p.re, (double)p.im, (double)q.re, (double)q.im);
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) {
+            acc.x += __shfl_xor(acc.x, off, 16);
+            acc.y += __shfl_xor(acc.y, off, 16);
+        }
+        if (l16 == 0) {
+            double* p = c.pslot(slot0 + s, b);
+            p[0] = acc.x;
+            p[1] = acc.y;
+        }
+    }
+}
+
+// workgroup g: fin[b][s] = sum over workgroups of part[slot0 + s][b], for the
+// (listed RHS, s < ns) tasks t with t mod G == g
+__device__ inline void multi_fin(const double* part, double* fin, int nrhs, int G, int g, int slot0, int ns,
+                                 const int* list, int nlist)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ntask = nlist * ns;
+    int j = 0;
+    for (int task = g; task < ntask; task += G, ++j) {
+        if ((j % (LT / 64)) != wv)
+            continue;
+        const int bi = task / ns, s = task - bi * ns;
+        const int b = list[bi];
+        double re = 0.0, im = 0.0;
+        for (int q = lane; q < G; q += 64) {
+            re += part[((((long)slot0 + s) * nrhs + b) * G + q) * 2];
+            im += part[((((long)slot0 + s) * nrhs + b) * G + q) * 2 + 1];
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            fin[((long)b * RS + s) * 2] = re;
+            fin[((long)b * RS + s) * 2 + 1] = im;
+        }
+    }
+}
+
+template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(LittleMultiArgs<T> a)
+{
+    __shared__ double red[kMaxLittleRhs][2 * RS];
+    __shared__ double bcoef[kMaxLittleRhs][NK];
+    __shared__ double ccoef[kMaxLittleRhs][NK][2];
+    __shared__ double alpha[kMaxLittleRhs][NK][2];
+    __shared__ double wn2[kMaxLittleRhs], rn2[kMaxLittleRhs];
+    __shared__ int act[kMaxLittleRhs], stop[kMaxLittleRhs], conv[kMaxLittleRhs], kb[kMaxLittleRhs];
+    __shared__ int second[kMaxLittleRhs];
+    __shared__ int list[kMaxLittleRhs], nlist_s, list2[kMaxLittleRhs], nlist2_s;
+    __shared__ double lds[2 * LT];
+
+    MultiCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
+    const int nr = a.nrhs;
+    const long N = c.N;
+    unsigned long long bar_target = 0;
+    if (c.t == 0)
+        bar_target = __hip_atomic_load(a.bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.nbg = (a.g.Nb - c.g + c.G - 1) / c.G;
+    c.R = c.nbg * a.Ns;
+    double* acoef = a.acoef + (long)c.g * nr * NK * NK * 2;
+    auto AC = [&](int b, int i, int j) -> double* { return acoef + (((long)b * NK + i) * NK + j) * 2; };
+
+    // x = 0, r = w, ||w_b||^2
+    for (long q = c.t; q < (long)c.R * nr; q += LT) {
+        const int b = (int)(q / c.R), e = (int)(q - (long)b * c.R);
+        const long i = c.entry(e) + b * N;
+        a.x[i] = cpx<T>{0, 0};
+        a.r[i] = a.w[i];
+    }
+    if (c.t < nr)
+        list[c.t] = c.t;
+    if (c.t == 0)
+        nlist_s = nr;
+    __syncthreads();
+    multi_norm2(c, a.w, list, nr, SW);
+    grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+    multi_reduce_real(a.part, nr, c.G, SW, list, nr, wn2);
+    if (c.t < nr) {
+        conv[c.t] = !(wn2[c.t] > 0.0);
+        stop[c.t] = conv[c.t];
+    }
+    __syncthreads();
+    int iters = 0;
+
+    // every branch depends on values all workgroups reduce identically
+    while (iters < a.maxiter) {
+        if (c.t == 0) {
+            int n = 0;
+            for (int b = 0; b < nr; ++b) {
+                act[b] = !stop[b];
+                kb[b] = 0;
+                if (act[b])
+                    list[n++] = b;
+            }
+            nlist_s = n;
+        }
+        __syncthreads();
+        if (nlist_s == 0)
+            break;
+        int k = 0;
+        for (; k < a.nkv && iters < a.maxiter; ++k) {
+            const int nl = nlist_s;
+            // xi_k = r and the partial ||r||^2 for the RHS still in the cycle
+            for (long q = c.t; q < (long)c.R * nl; q += LT) {
+                const int bi = (int)(q / c.R), e = (int)(q - (long)bi * c.R);
+                const int b = list[bi];
+                const long i = c.entry(e);
+                a.xi[((long)k * nr + b) * N + i] = a.r[b * N + i];
+            }
+            multi_norm2(c, a.r, list, nl, SC);
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S1
+            multi_reduce_real(a.part, nr, c.G, SC, list, nl, rn2);
+            if (c.t == 0) {
+                int n = 0;
+                for (int bi = 0; bi < nl; ++bi) {
+                    const int b = list[bi];
+                    if (k > 0 && rn2[b] <= a.tol2 * wn2[b])
+                        act[b] = 0;  // converged with k directions
+                    else
+                        list[n++] = b;
+                }
+                nlist_s = n;
+            }
+            __syncthreads();
+            const int na = nlist_s;
+            if (na == 0)
+                break;
+            apply_multi(c, a.xi + (long)k * nr * N, N, a.chi + (long)k * nr * N, N, list, na, lds);
+            multi_pass(c, k, list, na, SA);
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
+            multi_fin(a.part, a.fin, nr, c.G, c.g, SA, 2 * k + 2, list, na);
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2b
+            for (int q = c.t; q < na * (2 * k + 2) * 2; q += LT) {
+                const int bi = q / ((2 * k + 2) * 2), rem = q - bi * (2 * k + 2) * 2;
+                const int b = list[bi];
+                red[b][rem] = a.fin[(long)b * RS * 2 + rem];
+            }
+            __syncthreads();
+            if (c.t < na) {
+                const int b = list[c.t];
+                double n2 = red[b][4 * k];
+                double b2 = n2;
+                for (int j = 0; j < k; ++j)
+                    b2 -= red[b][2 * j] * red[b][2 * j] + red[b][2 * j + 1] * red[b][2 * j + 1];
+                second[b] = (k > 0 && !(b2 >= 0.01 * n2)) ? 1 : 0;
+                for (int j = 0; j < k; ++j) {
+                    double* p = AC(b, j, k);
+                    p[0] = 0.0;
+                    p[1] = 0.0;
+                }
+            }
+            __syncthreads();
+            if (c.t == 0) {
+                int n = 0;
+                for (int bi = 0; bi < na; ++bi)
+                    if (second[list[bi]])
+                        list2[n++] = list[bi];
+                nlist2_s = n;
+            }
+            __syncthreads();
+            const int n2l = nlist2_s;
+            if (n2l > 0) {
+                // heavy cancellation for some RHS: subtract the first projections, then a second pass
+                for (long q = c.t; q < (long)c.R * n2l; q += LT) {
+                    const int bi = (int)(q / c.R), e = (int)(q - (long)bi * c.R);
+                    const int b = list2[bi];
+                    const long i = c.entry(e);
+                    cpx<T>* ck = a.chi + ((long)k * nr + b) * N;
+                    double yr = (double)ck[i].re, yi = (double)ck[i].im;
+                    for (int j = 0; j < k; ++j) {
+                        cpx<T> z = a.chi[((long)j * nr + b) * N + i];
+                        yr -= red[b][2 * j] * (double)z.re - red[b][2 * j + 1] * (double)z.im;
+                        yi -= red[b][2 * j] * (double)z.im + red[b][2 * j + 1] * (double)z.re;
+                    }
+                    ck[i] = cpx<T>{(T)yr, (T)yi};
+                }
+                if (c.t < n2l) {
+                    const int b = list2[c.t];
+                    for (int j = 0; j < k; ++j) {
+                        double* p = AC(b, j, k);
+                        p[0] = red[b][2 * j];
+                        p[1] = red[b][2 * j + 1];
+                    }
+                }
+                __syncthreads();
+                multi_pass(c, k, list2, n2l, SB);
+                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S3
+                multi_fin(a.part, a.fin, nr, c.G, c.g, SB, 2 * k + 2, list2, n2l);
+                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S3b
+                for (int q = c.t; q < n2l * (2 * k + 2) * 2; q += LT) {
+                    const int bi = q / ((2 * k + 2) * 2), rem = q - bi * (2 * k + 2) * 2;
+                    const int b = list2[bi];
+                    red[b][rem] = a.fin[(long)b * RS * 2 + rem];
+                }
+                __syncthreads();
+            }
+            if (c.t < na) {
+                const int b = list[c.t];
+                double b2 = red[b][4 * k];
+                double crr = red[b][4 * k + 2], cri = red[b][4 * k + 3];
+                for (int j = 0; j < k; ++j) {
+                    double ar = red[b][2 * j], ai = red[b][2 * j + 1];
+                    double qr = red[b][2 * (k + j)], qi = red[b][2 * (k + j) + 1];
+                    b2 -= ar * ar + ai * ai;
+                    crr -= ar * qr + ai * qi;
+                    cri -= ar * qi - ai * qr;
+                    double* p = AC(b, j, k);
+                    p[0] += ar;
+                    p[1] += ai;
+                }
+                double bb = b2 > 0.0 ? sqrt(b2) : 0.0;
+                bcoef[b][k] = bb;
+                ccoef[b][k][0] = bb > 0.0 ? crr / bb : 0.0;
+                ccoef[b][k][1] = bb > 0.0 ? cri / bb : 0.0;
+            }
+            __syncthreads();
+            if (c.t == 0) {
+                int n = 0;
+                for (int bi = 0; bi < na; ++bi) {
+                    const int b = list[bi];
+                    if (!(bcoef[b][k] > 0.0)) {
+                        act[b] = 0;  // new direction in the span: the RHS ends its cycle without it
+                        stop[b] = 1;
+                    } else {
+                        kb[b] = k + 1;
+                        list[n++] = b;
+                    }
+                }
+                nlist_s = n;
+            }
+            __syncthreads();
+            const int nu = nlist_s;
+            for (long q = c.t; q < (long)c.R * nu; q += LT) {
+                const int bi = (int)(q / c.R), e = (int)(q - (long)bi * c.R);
+                const int b = list[bi];
+                const long i = c.entry(e);
+                cpx<T>* ck = a.chi + ((long)k * nr + b) * N;
+                const double inv = 1.0 / bcoef[b][k], cr0 = ccoef[b][k][0], ci0 = ccoef[b][k][1];
+                double yr = (double)ck[i].re, yi = (double)ck[i].im;
+                for (int j = 0; j < k; ++j) {
+                    cpx<T> z = a.chi[((long)j * nr + b) * N + i];
+                    yr -= red[b][2 * j] * (double)z.re - red[b][2 * j + 1] * (double)z.im;
+                    yi -= red[b][2 * j] * (double)z.im + red[b][2 * j + 1] * (double)z.re;
+                }
+                yr *= inv;
+                yi *= inv;
+                ck[i] = cpx<T>{(T)yr, (T)yi};
+                cpx<T>* rb = a.r + b * N;
+                double rr = (double)rb[i].re - (cr0 * yr - ci0 * yi);
+                double ri = (double)rb[i].im - (cr0 * yi + ci0 * yr);
+                rb[i] = cpx<T>{(T)rr, (T)ri};
+            }
+            ++iters;
+            __syncthreads();
+            if (nu == 0)
+                break;
+        }
+        // x_b += sum alpha_j xi_j for the RHS that took directions in this cycle
+        if (c.t < nr) {
+            const int b = c.t;
+            for (int i = kb[b] - 1; i >= 0; --i) {
+                double sr = ccoef[b][i][0], si = ccoef[b][i][1];
+                for (int j = i + 1; j < kb[b]; ++j) {
+                    const double* p = AC(b, i, j);
+                    sr -= p[0] * alpha[b][j][0] - p[1] * alpha[b][j][1];
+                    si -= p[0] * alpha[b][j][1] + p[1] * alpha[b][j][0];
+                }
+                alpha[b][i][0] = sr / bcoef[b][i];
+                alpha[b][i][1] = si / bcoef[b][i];
+            }
+        }
+        if (c.t == 0) {
+            int n = 0;
+            for (int b = 0; b < nr; ++b)
+                if (kb[b] > 0)
+                    list[n++] = b;
+            nlist_s = n;
+        }
+        __syncthreads();
+        const int nx = nlist_s;
+        for (long q = c.t; q < (long)c.R * nx; q += LT) {
+            const int bi = (int)(q / c.R), e = (int)(q - (long)bi * c.R);
+            const int b = list[bi];
+            const long i = c.entry(e);
+            double yr = (double)a.x[b * N + i].re, yi = (double)a.x[b * N + i].im;
+            for (int j = 0; j < kb[b]; ++j) {
+                cpx<T> z = a.xi[((long)j * nr + b) * N + i];
+                yr += alpha[b][j][0] * (double)z.re - alpha[b][j][1] * (double)z.im;
+                yi += alpha[b][j][0] * (double)z.im + alpha[b][j][1] * (double)z.re;
+            }
+            a.x[b * N + i] = cpx<T>{(T)yr, (T)yi};
+        }
+        // recompute r_b = w_b - A x_b for those RHS
+        grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+        apply_multi(c, a.x, N, a.r, N, list, nx, lds);
+        for (long q = c.t; q < (long)c.R * nx; q += LT) {
+            const int bi = (int)(q / c.R), e = (int)(q - (long)bi * c.R);
+            const int b = list[bi];
+            const long i = c.entry(e) + b * N;
+            a.r[i] = cpx<T>{(T)((double)a.w[i].re - (double)a.r[i].re), (T)((double)a.w[i].im - (double)a.r[i].im)};
+        }
+        __syncthreads();
+        multi_norm2(c, a.r, list, nx, SR);
+        grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+        multi_reduce_real(a.part, nr, c.G, SR, list, nx, rn2);
+        if (c.t < nx) {
+            const int b = list[c.t];
+            conv[b] = rn2[b] <= a.tol2 * wn2[b];
+            if (conv[b])
+                stop[b] = 1;
+        }
+        __syncthreads();
+        if (nx == 0)
+            break;  // no RHS made progress: all stopped
+    }
+    if (c.g == 0 && c.t == 0) {
+        int nc = 0;
+        for (int b = 0; b < nr; ++b)
+            nc += conv[b] ? 0 : 1;
+        atomicAdd(&a.stats[0], iters);
+        atomicAdd(&a.stats[1], nr);
+        if (nc)
+            atomicOr(&a.stats[2], 1);
+    }
+}
+
 template <typename T>
 void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
                  cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
@@ -492,6 +1006,50 @@ void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, 
     launch_impl<T>(g, Ns, nkv, maxiter, tol, At, w, x, r, xi, chi, part, stats, bar_count, bar_gen,
                    little_gcr_grid(g), s);
 }
+
+template <typename T>
+void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
+                             const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
+                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s)
+{
+    LittleMultiArgs<T> a;
+    a.g = g;
+    a.Ns = Ns;
+    a.nkv = nkv;
+    a.maxiter = maxiter;
+    a.nrhs = nrhs;
+    a.tol2 = tol * tol;
+    a.At = At;
+    a.w = w;
+    a.x = x;
+    a.r = r;
+    a.xi = xi;
+    a.chi = chi;
+    a.part = part;
+    a.fin = fin;
+    a.acoef = acoef;
+    a.stats = stats;
+    a.bar_count = bar_count;
+    a.bar_gen = bar_gen;
+    void* args[] = {&a};
+    HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_little_gcr_multi<T>),
+                                        dim3(little_gcr_grid(g)), dim3(LT), args, 0, s));
+}
+
+size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef)
+{
+    *fin = (size_t)nrhs * RS * 2;
+    *acoef = (size_t)grid_size * nrhs * NK * NK * 2;
+    return (size_t)NSLOT * nrhs * grid_size * 2;
+}
+
+#define INST_MULTI(T)                                                                                               \
+    template void launch_little_gcr_multi<T>(const Geom&, int, int, int, double, int, const cpx<T>*, const cpx<T>*, \
+                                             cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*, double*, double*, double*, int*,    \
+                                             unsigned*, unsigned long long*, hipStream_t);
+INST_MULTI(double)
+INST_MULTI(float)
+#undef INST_MULTI
 
 template void launch_little_gcr<double>(const Geom&, int, int, int, double, const c64*, const c64*, c64*, c64*, c64*,
                                         c64*, double*, int*, unsigned*, unsigned long long*, hipStream_t);

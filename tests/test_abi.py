@@ -47,6 +47,7 @@ def test_default_params():
     (dict(dims=(8, 8, 8, 8), m0=float("nan")), "finite"),
     (dict(dims=(2, 2, 2, 2), sap_block=(1, 1, 1, 1), dfl_block=(1, 1, 1, 1), Ns=4), "multiple of 64"),
     (dict(dims=(128, 64, 32, 32)), "2^22"),
+    (dict(dims=(8, 8, 8, 8), nrhs_max=17), "nrhs_max"),
 ])
 def test_create_rejects_bad_params(kw, msg):
     p = binding.default_params(**kw)

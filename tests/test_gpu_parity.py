@@ -350,3 +350,70 @@ def test_sap_multi_rhs(sap_prec, tol):
     for r in range(3):
         assert rel(got[r], oracle.sap(U, rho[r], m0, dims, sb, 2, 3)) < tol
     S.close()
+
+
+def test_little_apply_multi_rhs(c1):
+    # one launch for several little vectors: FP64 vector kernel and the FP32
+    # matrix-core kernel (5 sources: a partial 16-column tile; 16: a full one)
+    say("little apply multi-rhs c1")
+    torch = pytest.importorskip("torch")
+    dims, b = c1["dims"], (4, 4, 4, 4)
+    S = _c1_solver(c1, nrhs_max=16)
+    Nb, Ns = S.Nb, S.Ns
+    for n in (5, 16):
+        v = latgen.random_field((Nb, 1, 1, 1), 70 + n, n=n).reshape(n, -1)[:, : Nb * Ns].reshape(n, Nb, Ns)
+        ref = [oracle.little_apply(c1["A"], v[j], dims, b) for j in range(n)]
+        vd = torch.from_numpy(v.reshape(-1).copy()).cuda()
+        w = S.little_apply(vd).cpu().numpy().reshape(n, Nb, Ns)
+        w32 = S.little_apply(vd.to(torch.complex64), prec=F32).cpu().numpy().reshape(n, Nb, Ns)
+        for j in range(n):
+            assert rel(w[j], ref[j]) < 1e-12
+            assert rel(w32[j], ref[j]) < 1e-5, (n, j)
+    S.close()
+
+
+def test_projectors_multi_rhs(c1):
+    # batched restriction, little solve (one cooperative launch for all
+    # sources) and prolongation against the oracle field by field
+    say("projectors multi-rhs c1")
+    S = _c1_solver(c1, nrhs_max=3)
+    dims, b = c1["dims"], (4, 4, 4, 4)
+    dfl = oracle.Deflation(c1["U"], c1["Phi"], c1["A"], c1["m0"], dims, b)
+    y = latgen.random_field(dims, 62, n=3)
+    yd = S.pack(y)
+    for which, fn in [(PROJ_P, dfl.P), (PROJ_COARSE, dfl.coarse), (PROJ_PL, dfl.PL), (PROJ_PR, dfl.PR)]:
+        got = S.unpack(S.project(which, yd))
+        for j in range(3):
+            assert rel(got[j], fn(y[j])) < 1e-9, (which, j)
+    S.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_solve_multi_rhs(c1, mixed):
+    # sources solved together: every one reaches the FP64 true residual, its
+    # solution agrees with the single-source solve, and a zero source among
+    # them gives zero
+    say(f"solve multi-rhs mixed={mixed}")
+    dims = c1["dims"]
+    kw = dict(sap_prec=F32, link_prec=BF16, little_prec=F32) if mixed else {}
+    S = _c1_solver(c1, nrhs_max=4, tol=1e-10, **kw)
+    eta = np.stack([c1["eta"], latgen.make_source(dims, 81), np.zeros_like(c1["eta"]),
+                    latgen.point_sources(dims, [0])[0]])
+    psi, infos = S.solve(S.pack(eta))
+    psi = S.unpack(psi)
+    assert len(infos) == 4
+    for j in range(4):
+        assert infos[j].status == 0, (j, infos[j].as_dict())
+        if j == 2:
+            assert np.all(psi[j] == 0) and infos[j].n_gcr == 0
+            continue
+        r = eta[j] - oracle.dirac(c1["U"], psi[j], c1["m0"], dims)
+        rr = np.linalg.norm(r) / np.linalg.norm(eta[j])
+        assert rr <= 1e-10, j
+        assert abs(infos[j].rel_residual - rr) < 1e-12
+    for j in (0, 3):
+        one, info1 = S.solve(S.pack(eta[j]))
+        one = S.unpack(one)[0]
+        assert np.linalg.norm(one - psi[j]) <= 1e-7 * np.linalg.norm(one)
+        assert abs(info1.n_gcr - infos[j].n_gcr) <= 2
+    S.close()
