@@ -199,6 +199,21 @@ int little_solve(dfl_ctx *ctx, const void *w_dev, void *v_dev, double tol, int *
  * solves run to little_tol_out in FP64. in and out must not overlap. */
 int deflate_project(dfl_ctx *ctx, dfl_proj which, const void *in_dev, void *out_dev, int nrhs);
 
+/* Run the GCR steps of solve() as HIP graphs (on != 0) or as direct
+ * launches (0, the default). With graphs on, the launch sequence of each
+ * Krylov step (Schwarz preconditioner, stencil, deflation projector with its
+ * little solve, Gram-Schmidt) is captured once per step index and number of
+ * sources and replayed on later steps and solves; results are identical to
+ * direct launches. The captured little solve is an ordinary kernel node whose
+ * grid of at most one workgroup per compute unit is resident when nothing
+ * else runs on the device. Graphs are dropped when the mass changes. Capture
+ * and replay run on a stream the context creates, ordered against the
+ * context's stream by events. Synchronises. */
+int dfl_use_graphs(dfl_ctx *ctx, int on);
+
+/* Number of graph replays since the context was created (-1 for NULL). */
+long long dfl_graph_replays(const dfl_ctx *ctx);
+
 /* Solve D psi = eta for nrhs native FP64 sources to ||eta - D psi|| <= tol ||eta||
  * with the solver chosen in the parameters (section 6 for DFL_SAP_GCR:
  * flexible GCR on eq. (6.2), restarts recomputing the residual in FP64

@@ -144,6 +144,9 @@ class Solver:
         binding.deflate_project(self.ctx, which, y, out, nrhs)
         return out
 
+    def use_graphs(self, on=True):
+        binding.dfl_use_graphs(self.ctx, on)
+
     def solve(self, eta):
         nrhs = eta.numel() // (12 * self.V)
         psi = self.field(nrhs, F64)

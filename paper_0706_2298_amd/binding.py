@@ -56,7 +56,7 @@ EXPORTS = [
     "dfl_default_params", "dfl_create", "dfl_destroy", "dfl_set_mass", "dfl_field_bytes", "dfl_num_blocks",
     "dfl_set_gauge", "dfl_pack", "dfl_unpack", "dirac_apply", "sap_precond", "dfl_setup", "dfl_get_basis",
     "dfl_get_little", "little_dirac_apply", "little_solve", "deflate_project", "solve", "dfl_residual_history",
-    "dfl_profile_enable", "dfl_profile_read", "dfl_last_error",
+    "dfl_profile_enable", "dfl_profile_read", "dfl_last_error", "dfl_use_graphs", "dfl_graph_replays",
 ]
 PROF_CLASSES = ["sap", "dirac", "little", "project", "setup"]
 
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
         "dfl_profile_enable": (i, [vp, i]),
         "dfl_profile_read": (i, [vp, P(d), P(ctypes.c_longlong), P(ctypes.c_longlong)]),
         "dfl_last_error": (ctypes.c_char_p, []),
+        "dfl_use_graphs": (i, [vp, i]),
+        "dfl_graph_replays": (ctypes.c_longlong, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -211,6 +213,14 @@ def dfl_residual_history(ctx):
     buf = (ctypes.c_double * max(n, 1))()
     L.dfl_residual_history(ctx, buf, n)
     return list(buf[:n])
+
+
+def dfl_use_graphs(ctx, on=True):
+    _check(load().dfl_use_graphs(ctx, 1 if on else 0))
+
+
+def dfl_graph_replays(ctx):
+    return load().dfl_graph_replays(ctx)
 
 
 def dfl_profile_enable(ctx, on=True):

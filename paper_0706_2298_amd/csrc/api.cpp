@@ -182,7 +182,7 @@ struct ProfScope {
     hipEvent_t e0 = nullptr;
     ProfScope(dfl_ctx* cc, int k) : c(cc), cls(k)
     {
-        if (c->prof_on) {
+        if (c->prof_on && !c->capturing) {
             e0 = prof_event(c);
             HIPCHECK(hipEventRecord(e0, c->stream));
         }
@@ -258,6 +258,63 @@ template <typename T> double host_norm2(dfl_ctx* c, const cpx<T>* x, long n)
     HIPCHECK(hipMemcpyAsync(c->hscal + S_R, c->dscal + S_R, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     sync(c);
     return c->hscal[S_R];
+}
+
+// ---------------------------------------------------------------- graphs
+
+void drop_graphs(dfl_ctx* c)
+{
+    for (auto& g : c->graphs)
+        (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+}
+
+// Run body on the context's stream: directly, or (graphs on) as the replay of
+// a graph captured from it the first time this key is seen. Capture and
+// replay use the context's own stream gstream, ordered after the work already
+// queued on `stream` and before the work queued after it by a pair of events,
+// so the caller's stream may be any stream (the null stream included).
+// Captured launch sequences must not contain memsets or host synchronisation.
+void run_step(dfl_ctx* c, long key, const std::function<void()>& body)
+{
+    if (!c->use_graph) {
+        body();
+        return;
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : c->graphs)
+        if (g.first == key)
+            exec = g.second;
+    HIPCHECK(hipEventRecord(c->gev[0], c->stream));
+    HIPCHECK(hipStreamWaitEvent(c->gstream, c->gev[0], 0));
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        hipStream_t user = c->stream;
+        HIPCHECK(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
+        c->stream = c->gstream;
+        try {
+            body();
+        } catch (...) {
+            c->capturing = false;
+            c->stream = user;
+            (void)hipStreamEndCapture(c->gstream, &graph);
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            throw;
+        }
+        c->capturing = false;
+        c->stream = user;
+        HIPCHECK(hipStreamEndCapture(c->gstream, &graph));
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHECK(e);
+        c->graphs.push_back({key, exec});
+    }
+    HIPCHECK(hipGraphLaunch(exec, c->gstream));
+    HIPCHECK(hipEventRecord(c->gev[1], c->gstream));
+    HIPCHECK(hipStreamWaitEvent(c->stream, c->gev[1], 0));
+    ++c->graph_replays;
 }
 
 // ------------------------------------------------------------ operators
@@ -373,23 +430,27 @@ std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter,
         while (k < nkv && n_act > 0) {
             c64* xk = v.xi + (long)k * ks;
             c64* ck = v.chi + (long)k * ks;
-            precond(v.r, xk, nb);
-            op(xk, ck, nb);
-            if (k > 0) {
-                launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A1, S_TOTAL, mask,
+            run_step(c, (long)k * 64 + nb, [&]() {
+                precond(v.r, xk, nb);
+                op(xk, ck, nb);
+                if (k > 0) {
+                    launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A1, S_TOTAL, mask,
+                                              c->stream);
+                    launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A1, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
+                                               c->stream);
+                    launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A2, S_TOTAL, mask,
+                                              c->stream);
+                    launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A2, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
+                                               c->stream);
+                }
+                launch_norm2_b<double>(ck, n, nb, n, c->red, c->dscal + S_B, S_TOTAL, mask, c->stream);
+                launch_scale_invsqrt_b<double>(ck, n, nb, n, c->dscal + S_B, S_TOTAL, mask, c->stream);
+                launch_multidot_b<double>(ck, 0, 1, v.r, n, nb, n, n, c->red, c->dscal + S_C, S_TOTAL, mask,
                                           c->stream);
-                launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A1, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
+                launch_multiaxpy_b<double>(ck, 0, 1, c->dscal + S_C, S_TOTAL, -1.0, v.r, n, nb, n, n, mask,
                                            c->stream);
-                launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A2, S_TOTAL, mask,
-                                          c->stream);
-                launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A2, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
-                                           c->stream);
-            }
-            launch_norm2_b<double>(ck, n, nb, n, c->red, c->dscal + S_B, S_TOTAL, mask, c->stream);
-            launch_scale_invsqrt_b<double>(ck, n, nb, n, c->dscal + S_B, S_TOTAL, mask, c->stream);
-            launch_multidot_b<double>(ck, 0, 1, v.r, n, nb, n, n, c->red, c->dscal + S_C, S_TOTAL, mask, c->stream);
-            launch_multiaxpy_b<double>(ck, 0, 1, c->dscal + S_C, S_TOTAL, -1.0, v.r, n, nb, n, n, mask, c->stream);
-            launch_norm2_b<double>(v.r, n, nb, n, c->red, c->dscal + S_R, S_TOTAL, mask, c->stream);
+                launch_norm2_b<double>(v.r, n, nb, n, c->red, c->dscal + S_R, S_TOTAL, mask, c->stream);
+            });
             download_b(c, S_DOWN, nb);
             bool changed = false;
             for (int b = 0; b < nb; ++b) {
@@ -470,11 +531,12 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
         if (nb == 1)
             launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, c->At64, w, v, static_cast<c64*>(c->lr),
                                       static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lstats,
-                                      c->lbar_count, c->lbar_gen, c->stream);
+                                      c->lbar_count, c->lbar_gen, c->stream, !c->capturing);
         else
             launch_little_gcr_multi<double>(c->g, Ns, nkv, mi, tol, nb, c->At64, w, v, static_cast<c64*>(c->lr),
                                             static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lfin,
-                                            c->lacoef, c->lstats, c->lbar_count, c->lbar_gen, c->stream);
+                                            c->lacoef, c->lstats, c->lbar_count, c->lbar_gen, c->stream,
+                                            !c->capturing);
     } else {
         launch_f64_to_f32(w, c->lw32, n * nb, c->stream);
         {
@@ -482,12 +544,12 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
             if (nb == 1)
                 launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, c->At32, c->lw32, c->lx32, static_cast<c32*>(c->lr),
                                          static_cast<c32*>(c->lxi), static_cast<c32*>(c->lchi), c->lpart, c->lstats,
-                                         c->lbar_count, c->lbar_gen, c->stream);
+                                         c->lbar_count, c->lbar_gen, c->stream, !c->capturing);
             else
                 launch_little_gcr_multi<float>(c->g, Ns, nkv, mi, tol, nb, c->At32, c->lw32, c->lx32,
                                                static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
                                                static_cast<c32*>(c->lchi), c->lpart, c->lfin, c->lacoef, c->lstats,
-                                               c->lbar_count, c->lbar_gen, c->stream);
+                                               c->lbar_count, c->lbar_gen, c->stream, !c->capturing);
         }
         launch_f32_to_f64(c->lx32, v, n * nb, c->stream);
     }
@@ -727,6 +789,14 @@ int dfl_destroy(dfl_ctx* c)
     if (!c)
         return DFL_OK;
     (void)hipStreamSynchronize(c->stream);
+    if (c->gstream)
+        (void)hipStreamSynchronize(c->gstream);
+    drop_graphs(c);
+    for (hipEvent_t e : c->gev)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (c->gstream)
+        (void)hipStreamDestroy(c->gstream);
     for (auto& p : c->ev_pending) {
         (void)hipEventDestroy(p.second.first);
         (void)hipEventDestroy(p.second.second);
@@ -745,6 +815,24 @@ long long dfl_field_bytes(const dfl_ctx* c, dfl_prec prec)
     return (long long)c->field_elems * (prec == DFL_F64 ? 16 : 8);
 }
 
+int dfl_use_graphs(dfl_ctx* c, int on)
+{
+    API_BEGIN
+    need_ctx(c);
+    sync(c);
+    if (!on)
+        drop_graphs(c);
+    if (on && !c->gstream) {
+        HIPCHECK(hipStreamCreate(&c->gstream));
+        HIPCHECK(hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming));
+    }
+    c->use_graph = on != 0;
+    API_END
+}
+
+long long dfl_graph_replays(const dfl_ctx* c) { return c ? c->graph_replays : -1; }
+
 int dfl_num_blocks(const dfl_ctx* c) { return c ? c->g.Nb : -1; }
 
 int dfl_set_mass(dfl_ctx* c, double m0)
@@ -753,6 +841,8 @@ int dfl_set_mass(dfl_ctx* c, double m0)
     need_ctx(c);
     if (!std::isfinite(m0))
         fail(DFL_EINVAL, "mass must be finite");
+    if (m0 != c->p.m0)
+        drop_graphs(c);  // the mass is a kernel argument of the captured steps
     c->p.m0 = m0;
     if (c->have_subspace && m0 != c->m0_A) {
         // the basis is orthonormal, so A(m0') = A(m0) + (m0' - m0) 1

@@ -384,6 +384,12 @@ template void launch_little_apply<float>(const Geom&, const c32*, int, const c32
 void launch_little_apply_mfma(const Geom& g, const c32* At, int Ns, const c32* v, c32* w, int nrhs, hipStream_t s)
 {
     const size_t lds = sizeof(c32) * 9 * Ns * kMfmaRhs;
+    static bool attr_set = false;
+    if (!attr_set && lds > 65536) {
+        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_little_apply_mfma),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 9 * 64 * kMfmaRhs * sizeof(c32)));
+        attr_set = true;
+    }
     hipLaunchKernelGGL(k_little_apply_mfma, dim3(g.Nb), dim3(256), lds, s, g, At, Ns, v, w, nrhs);
 }
 

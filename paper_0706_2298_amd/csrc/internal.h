@@ -56,15 +56,6 @@ constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
 constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
 constexpr int kMaxLittleRhs = 16;    // right-hand sides of one batched little solve
 
-// The same for nrhs systems at once (nrhs <= kMaxLittleRhs): w, x, r hold
-// nrhs little vectors back to back, xi and chi nkv * nrhs. Sizes of part,
-// fin and acoef (doubles) come from little_gcr_multi_doubles.
-size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef);
-template <typename T>
-void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
-                             const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
-                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s);
-
 }  // namespace dfl
 
 struct dfl_ctx {
@@ -130,6 +121,13 @@ struct dfl_ctx {
     int* hact = nullptr;         // pinned host mirror
     size_t alloc_bytes = 0;
     std::vector<double> history;  // outer GCR residues of the last solve
+    // HIP graphs of the GCR steps, keyed by (step index, number of sources)
+    bool use_graph = false;
+    bool capturing = false;
+    hipStream_t gstream = nullptr;     // capture and replay stream, fenced to `stream` by events
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    std::vector<std::pair<long, hipGraphExec_t>> graphs;
+    long graph_replays = 0;
     // kernel-class timers
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;                 // free events
@@ -235,10 +233,14 @@ int little_gcr_grid(const Geom& g);
 size_t little_gcr_partial_doubles(int grid_size);
 // v = A^{-1} w by GCR to ||w - A v|| <= tol ||w|| in one cooperative launch;
 // r, xi, chi are workspaces; stats accumulates [iterations, solves, failed]
+// cooperative = false launches it as an ordinary kernel (for graph capture):
+// the grid (at most kLittleMaxGrid workgroups, one per compute unit) is then
+// resident by construction when nothing else runs on the device, and the
+// barriers' bounded polling reports a failure rather than hang otherwise.
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
-                       unsigned long long* bar_gen, hipStream_t s);
+                       unsigned long long* bar_gen, hipStream_t s, bool cooperative = true);
 
 // The same for nrhs systems at once (nrhs <= kMaxLittleRhs): w, x, r hold
 // nrhs little vectors back to back, xi and chi nkv * nrhs. Sizes of part,
@@ -247,6 +249,7 @@ size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* ac
 template <typename T>
 void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
                              const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
-                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s);
+                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s,
+                             bool cooperative = true);
 
 }  // namespace dfl

@@ -958,7 +958,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
 template <typename T>
 void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
                  cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
-                 unsigned long long* bar_gen, int grid_size, hipStream_t s)
+                 unsigned long long* bar_gen, int grid_size, hipStream_t s, bool cooperative)
 {
     LittleArgs<T> a;
     a.g = g;
@@ -976,6 +976,11 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
     a.stats = stats;
     a.bar_count = bar_count;
     a.bar_gen = bar_gen;
+    if (!cooperative) {
+        hipLaunchKernelGGL(k_little_gcr<T>, dim3(grid_size), dim3(LT), 0, s, a);
+        HIPCHECK(hipGetLastError());
+        return;
+    }
     void* args[] = {&a};
     HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_little_gcr<T>), dim3(grid_size), dim3(LT),
                                         args, 0, s));
@@ -1001,16 +1006,17 @@ size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * grid_s
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
-                       unsigned long long* bar_gen, hipStream_t s)
+                       unsigned long long* bar_gen, hipStream_t s, bool cooperative)
 {
     launch_impl<T>(g, Ns, nkv, maxiter, tol, At, w, x, r, xi, chi, part, stats, bar_count, bar_gen,
-                   little_gcr_grid(g), s);
+                   little_gcr_grid(g), s, cooperative);
 }
 
 template <typename T>
 void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
                              const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
-                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s)
+                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s,
+                             bool cooperative)
 {
     LittleMultiArgs<T> a;
     a.g = g;
@@ -1031,6 +1037,11 @@ void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double
     a.stats = stats;
     a.bar_count = bar_count;
     a.bar_gen = bar_gen;
+    if (!cooperative) {
+        hipLaunchKernelGGL(k_little_gcr_multi<T>, dim3(little_gcr_grid(g)), dim3(LT), 0, s, a);
+        HIPCHECK(hipGetLastError());
+        return;
+    }
     void* args[] = {&a};
     HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_little_gcr_multi<T>),
                                         dim3(little_gcr_grid(g)), dim3(LT), args, 0, s));
@@ -1046,14 +1057,14 @@ size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* ac
 #define INST_MULTI(T)                                                                                               \
     template void launch_little_gcr_multi<T>(const Geom&, int, int, int, double, int, const cpx<T>*, const cpx<T>*, \
                                              cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*, double*, double*, double*, int*,    \
-                                             unsigned*, unsigned long long*, hipStream_t);
+                                             unsigned*, unsigned long long*, hipStream_t, bool);
 INST_MULTI(double)
 INST_MULTI(float)
 #undef INST_MULTI
 
 template void launch_little_gcr<double>(const Geom&, int, int, int, double, const c64*, const c64*, c64*, c64*, c64*,
-                                        c64*, double*, int*, unsigned*, unsigned long long*, hipStream_t);
+                                        c64*, double*, int*, unsigned*, unsigned long long*, hipStream_t, bool);
 template void launch_little_gcr<float>(const Geom&, int, int, int, double, const c32*, const c32*, c32*, c32*, c32*,
-                                       c32*, double*, int*, unsigned*, unsigned long long*, hipStream_t);
+                                       c32*, double*, int*, unsigned*, unsigned long long*, hipStream_t, bool);
 
 }  // namespace dfl

@@ -417,3 +417,37 @@ def test_solve_multi_rhs(c1, mixed):
         assert np.linalg.norm(one - psi[j]) <= 1e-7 * np.linalg.norm(one)
         assert abs(info1.n_gcr - infos[j].n_gcr) <= 2
     S.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_graph_solve_equals_direct(c1, nrhs):
+    # captured GCR steps replayed many times (several cycles, two solves, with
+    # direct solves in between) give bit-identical results to direct launches
+    say(f"graph solve nrhs={nrhs}")
+    dims = c1["dims"]
+    S = _c1_solver(c1, nrhs_max=3, tol=1e-10, sap_prec=F32, link_prec=F32, little_prec=F32, nkv=6)
+    eta = np.stack([c1["eta"], latgen.make_source(dims, 91), latgen.make_source(dims, 92)])[:nrhs]
+    ed = S.pack(eta)
+    ref, info_ref = S.solve(ed)
+    ref = S.unpack(ref)
+    S.use_graphs(True)
+    for rep in range(2):
+        got, info = S.solve(ed)
+        got = S.unpack(got)
+        assert np.array_equal(got, ref), rep
+        a = info if nrhs == 1 else info[0]
+        b = info_ref if nrhs == 1 else info_ref[0]
+        assert a.n_gcr == b.n_gcr and a.n_little == b.n_little
+        S.use_graphs(False)
+        again, _ = S.solve(ed)
+        assert np.array_equal(S.unpack(again), ref)
+        S.use_graphs(True)
+    from paper_0706_2298_amd import binding
+    assert binding.dfl_graph_replays(S.ctx) > 6
+    # a mass change drops the graphs; the next graph solve recaptures
+    S.set_mass(c1["m0"] - 0.05)
+    S.use_graphs(False)
+    ref2 = S.unpack(S.solve(ed)[0])
+    S.use_graphs(True)
+    assert np.array_equal(S.unpack(S.solve(ed)[0]), ref2)
+    S.close()
