@@ -16,6 +16,12 @@ Also reported (outside the timed region):
 * dirac_apply GFLOP/s and algorithmic GB/s on 64 x 32^3 (FP64 full links,
   FP32 and BF16 two-row links), a working set well above the 256 MB MALL;
 * undeflated SAP+GCR and plain FP64 GCR on the same fields;
+* 32 x 16^3 in mixed precision (BF16 two-row links, FP32 Schwarz and inner
+  little solves, Schwarz block shape picked by the autotuner) with the error
+  of each result against FP64 references;
+* 12 point sources on 48 x 24^3 and 6 on 32 x 16^3 (Ns = 24) solved as one
+  batch per lattice with graph replay, against one-by-one solves, and the
+  12-source dirac_apply rate;
 * the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -228,6 +234,117 @@ def undeflated(torch, fields):
     return rows
 
 
+def timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def mixed_precision_32x16(torch):
+    """32 x 16^3, eps 0.4 (seed 3001), m0 = -0.3, Gaussian source (seed 3002):
+    BF16 two-row links, FP32 Schwarz and inner little solves, FP64 GCR and
+    projector; Schwarz block 4^4 or 8 x 4^3 chosen by the autotuner on
+    setup + solve time. Errors: dirac_apply and one Schwarz application against
+    the FP64 oracle; the solution against an all-FP64 solve to 1e-12 on the
+    GPU, and its true residual recomputed by the oracle's D."""
+    import latgen
+    import oracle
+    from paper_0706_2298_amd import BF16, F32, F64, Solver, autotune, binding
+    dims, m0 = (32, 16, 16, 16), -0.3
+    U = latgen.make_links(dims, 0.4, 3001)
+    eta = latgen.make_source(dims, 3002)
+    init = latgen.make_init_fields(dims, NS, 3003)
+    base = solver_params(m0=m0, m0_setup=m0, link_prec=BF16, sap_prec=F32, little_prec=F32)
+    base.pop("sap_block")
+    cands = [dict(sap_block=sb, nmr=NMR, graph=False) for sb in [(4, 4, 4, 4), (8, 4, 4, 4)]]
+    tuned = autotune.tune(dims, U, eta[None], init=init, params=base, cands=cands, cache=None, solves_per_setup=1,
+                          reps=1)
+    S = Solver(dims, sap_block=tuned["sap_block"], **base)
+    S.set_gauge(U)
+    ed, initd = S.pack(eta), S.pack(init)
+    _, t_setup = timed(torch, lambda: S.setup(initd))
+    (psi, info), t_solve = timed(torch, lambda: S.solve(ed))
+    psi = S.unpack(psi)[0]
+    # stencil and one Schwarz application in reduced precision against the oracle
+    x = S.pack(eta, prec=F32)
+    y = S.field(1, F32)
+    binding.dirac_apply(S.ctx, x, y, 1, F32)
+    d_err = float(np.linalg.norm(S.unpack(y, prec=F32)[0] - oracle.dirac(U, eta, m0, dims)) /
+                  np.linalg.norm(oracle.dirac(U, eta, m0, dims)))
+    sap_gpu = S.unpack(S.sap(ed))[0]
+    sap_ref = oracle.sap(U, eta, m0, dims, tuple(tuned["sap_block"]), NCY, NMR)
+    s_err = float(np.linalg.norm(sap_gpu - sap_ref) / np.linalg.norm(sap_ref))
+    S.close()
+    R = Solver(dims, **solver_params(m0=m0, m0_setup=m0, sap_prec=F64, link_prec=F64, little_prec=F64, tol=1e-12,
+                                     sap_block=tuned["sap_block"]))
+    R.set_gauge(U)
+    R.setup(R.pack(init))
+    ref, _ = R.solve(R.pack(eta))
+    ref = R.unpack(ref)[0]
+    R.close()
+    torch.cuda.empty_cache()
+    res = float(np.linalg.norm(eta - oracle.dirac(U, psi, m0, dims)) / np.linalg.norm(eta))
+    return dict(lattice=list(dims), m0=m0, autotune=dict(sap_block=list(tuned["sap_block"]),
+                                                         seconds=tuned["seconds"]),
+                t_setup=t_setup, t_solve=t_solve, n_gcr=info.n_gcr, n_little=info.n_little,
+                rel_residual_oracle_D=res,
+                err_solution_vs_fp64_solve=float(np.linalg.norm(psi - ref) / np.linalg.norm(ref)),
+                err_dirac_bf16_links_vs_oracle=d_err, err_sap_fp32_bf16_vs_oracle=s_err)
+
+
+def multi_rhs(torch):
+    """12 point sources (x = 0, spin-colour 0..11) on 48 x 24^3 (seed 4001) and
+    6 (spin-colour 0..5) on 32 x 16^3 (seed 4002), eps 0.4, m0 = -0.3, Ns = 24:
+    one batched solve per lattice with graph replay against one-by-one solves
+    on the same subspace; plus dirac_apply on the 12 sources in one launch."""
+    import latgen
+    from paper_0706_2298_amd import F64, Solver, binding
+    out = {}
+    for dims, seed, n in [((48, 24, 24, 24), 4001, 12), ((32, 16, 16, 16), 4002, 6)]:
+        key = "x".join(map(str, dims))
+        U = latgen.make_links(dims, 0.4, seed)
+        src = latgen.point_sources(dims, range(n))
+        init = latgen.make_init_fields(dims, 24, seed + 200)
+        S = Solver(dims, **solver_params(Ns=24, m0=-0.3, m0_setup=-0.3, nrhs_max=n))
+        S.set_gauge(U)
+        ed = S.pack(src)
+        _, t_setup = timed(torch, lambda: S.setup(S.pack(init)))
+        row = dict(nrhs=n, t_setup=t_setup)
+        S.use_graphs(True)
+        S.solve(ed)  # captures the step graphs
+        (psi, infos), row["t_batched_graph"] = timed(torch, lambda: S.solve(ed))
+        row["n_gcr_batched"] = [i.n_gcr for i in infos]
+        row["max_rel_residual"] = max(i.rel_residual for i in infos)
+        S.use_graphs(False)
+        _, row["t_batched_direct"] = timed(torch, lambda: S.solve(ed))
+        singles = []
+        t_single = 0.0
+        for j in range(n):
+            ej = S.pack(src[j])
+            (_, inf1), dt = timed(torch, lambda: S.solve(ej))
+            t_single += dt
+            singles.append(inf1.n_gcr)
+        row["t_one_by_one"] = t_single
+        row["n_gcr_single"] = singles
+        row["speedup_batched_graph"] = t_single / row["t_batched_graph"]
+        if n == 12:
+            y = S.field(n, F64)
+            t = time_events(torch, lambda: binding.dirac_apply(S.ctx, ed, y, n, F64), 10)
+            vol = int(np.prod(dims))
+            byts = (2 * 192 * n + 576) * vol  # spinors in and out per source, links once
+            row["dirac_nrhs12"] = dict(ms=t * 1e3, gflops=FLOPS_PER_SITE * vol * n / t / 1e9,
+                                       gbs=byts / t / 1e9, frac_hbm=byts / t / 1e9 / HBM_PEAK_GBS,
+                                       bytes_per_site_per_rhs=byts / vol / n)
+            del y
+        S.close()
+        del ed
+        torch.cuda.empty_cache()
+        out[key] = row
+    return out
+
+
 def cpu_baseline(fields, stats):
     """The FP64 oracle on a bounded sample of the step, scaled to solves/s.
 
@@ -276,6 +393,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dirac", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 32x16^3 mixed-precision and multi-source runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (y = 1.0 * x), to scale HBM byte counters")
     args = ap.parse_args()
@@ -357,6 +475,11 @@ def main():
     if not args.no_compare:
         log("undeflated comparisons")
         result["undeflated"] = undeflated(torch, fields)
+    if not args.no_extras:
+        log("mixed precision on 32x16^3")
+        result["mixed_precision_32x16^3"] = mixed_precision_32x16(torch)
+        log("multi-source batches")
+        result["multi_rhs"] = multi_rhs(torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(fields, stats)
