@@ -24,7 +24,10 @@ available; these generators stand in for them with fields of the same shapes:
 * Gaussian sources with real and imaginary parts i.i.d. N(0, 1);
 * point sources ``delta_{x,0} delta_{c,j}``;
 * Gaussian random start fields for the inverse-iteration setup (section 5.3);
-  the random numbers the method draws are generated here and passed in.
+  the random numbers the method draws are generated here and passed in;
+* the noise channels and the initial weights of the start-field network
+  (per-site Gaussian noise; weights Gaussian with variance 1/(81 C_in), zero
+  biases).
 
 All draws use ``numpy.random.default_rng(seed)`` (PCG64) in the order stated in
 each function, so a seed fixes the array bit for bit.
@@ -34,6 +37,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
+    "NET_CHANNELS", "net_noise", "net_init",
     "gell_mann",
     "volume",
     "make_links",
@@ -146,3 +150,27 @@ def random_gauge_transform(dims, seed: int) -> np.ndarray:
     h = rng.standard_normal((V, 8))
     H = np.einsum("sa,aij->sij", h, gell_mann() / 2.0)
     return _expi_hermitian(H, 1.0)
+
+
+NET_CHANNELS = (96, 32, 32, 32, 576)  # 72 link + 24 noise inputs; Ns = 24 complex-12 outputs
+
+
+def net_noise(dims, seed: int, n: int = 24) -> np.ndarray:
+    """Per-site Gaussian noise channels of the start-field network: (V, n) float64,
+    drawn as standard_normal((V, n))."""
+    return np.random.default_rng(seed).standard_normal((volume(dims), n))
+
+
+def net_init(channels, seed: int) -> list:
+    """Initial weights of the 3^4 convolutions: [(W (3,3,3,3,Cin,Cout), b (Cout,)), ...].
+
+    W is drawn layer by layer as standard_normal((3,3,3,3,Cin,Cout)) times
+    sqrt(1/(81*Cin)); biases are zero.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        W = rng.standard_normal((3, 3, 3, 3, cin, cout)) * np.sqrt(1.0 / (81 * cin))
+        out.append((W, np.zeros(cout)))
+    return out
+

@@ -21,13 +21,19 @@ quark modes in lattice QCD":
 * ``gcr`` / ``solve`` -- the flexible GCR of section 6.2 on eq. (6.2), with
   restarts recomputing the residual (appendix A.5) and the final solution of
   eq. (3.10), stopping at ||eta - D psi|| <= tol ||eta|| (section 6.3);
-* ``inverse_iteration`` / ``setup`` -- the subspace generation of eq. (5.1).
+* ``inverse_iteration`` / ``setup`` -- the subspace generation of eq. (5.1);
+* ``oracle.net`` -- the start-field network (periodic 3^4 convolutions, SiLU),
+  its backward pass, the block deficit loss built on eq. (3.15) with its
+  gradient, and the Adam update (the paper has no network; the definitions
+  are stated in that module).
 
 Pins (tests/test_oracle_*.py): free-field spectrum and plane waves, the
 Clifford algebra, gamma5-hermiticity, gauge covariance, dense LAPACK solves
 and eigenvalues, the projector identities (3.5)-(3.8), the Schur inverse
 (3.14), the determinant factorisation (6.3), the free-field deficit of
-eq. (4.4) in closed form, and the block sparsity of fig. 4.
+eq. (4.4) in closed form, and the block sparsity of fig. 4; for the network,
+a brute-force convolution, finite differences of every forward map, the
+deficit through the Gram-Schmidt projector, and Adam's first step.
 """
 from .dfl import *  # noqa: F401,F403
 from .dfl import __all__  # noqa: F401
