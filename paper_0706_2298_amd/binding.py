@@ -1,4 +1,4 @@
-"""ctypes binding of libdfl.so (the C ABI of include/dfl.h).
+"""ctypes binding of libdfl.so (the C ABI of include/dfl.h and include/dfl_net.h).
 
 Argument marshalling only: every step of the solver runs in the HIP library.
 Functions keep the C names; tensor arguments are torch CUDA tensors (their
@@ -57,6 +57,8 @@ EXPORTS = [
     "dfl_set_gauge", "dfl_pack", "dfl_unpack", "dirac_apply", "sap_precond", "dfl_setup", "dfl_get_basis",
     "dfl_get_little", "little_dirac_apply", "little_solve", "deflate_project", "solve", "dfl_residual_history",
     "dfl_profile_enable", "dfl_profile_read", "dfl_last_error", "dfl_use_graphs", "dfl_graph_replays",
+    "dfl_inverse_iteration", "net_features", "conv4d_forward", "conv4d_backward", "net_outputs_to_fields",
+    "net_fields_grad_to_outputs", "deficit_loss", "adam_update",
 ]
 PROF_CLASSES = ["sap", "dirac", "little", "project", "setup"]
 
@@ -97,6 +99,14 @@ def load(path: str = LIB_PATH):
         "dfl_last_error": (ctypes.c_char_p, []),
         "dfl_use_graphs": (i, [vp, i]),
         "dfl_graph_replays": (ctypes.c_longlong, [vp]),
+        "dfl_inverse_iteration": (i, [vp, vp, i, i]),
+        "net_features": (i, [vp, vp, vp]),
+        "conv4d_forward": (i, [vp, vp, i, vp, vp, i, vp, vp]),
+        "conv4d_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp, vp]),
+        "net_outputs_to_fields": (i, [vp, vp, i, vp]),
+        "net_fields_grad_to_outputs": (i, [vp, vp, i, vp]),
+        "deficit_loss": (i, [vp, vp, i, vp, i, P(d), vp]),
+        "adam_update": (i, [vp, vp, vp, vp, vp, ctypes.c_longlong, i, d, d, d, d]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -213,6 +223,41 @@ def dfl_residual_history(ctx):
     buf = (ctypes.c_double * max(n, 1))()
     L.dfl_residual_history(ctx, buf, n)
     return list(buf[:n])
+
+
+def dfl_inverse_iteration(ctx, fields, n, steps):
+    _check(load().dfl_inverse_iteration(ctx, _ptr(fields), n, steps))
+
+
+def net_features(ctx, noise, x):
+    _check(load().net_features(ctx, _ptr(noise), _ptr(x)))
+
+
+def conv4d_forward(ctx, x, cin, W, b, cout, z, a=None):
+    _check(load().conv4d_forward(ctx, _ptr(x), cin, _ptr(W), _ptr(b), cout, _ptr(z), _ptr(a)))
+
+
+def conv4d_backward(ctx, x, cin, W, cout, g, dW, db, din=None, z_in=None):
+    _check(load().conv4d_backward(ctx, _ptr(x), cin, _ptr(W), cout, _ptr(g), _ptr(dW), _ptr(db), _ptr(din),
+                                  _ptr(z_in)))
+
+
+def net_outputs_to_fields(ctx, out, Ns, fields):
+    _check(load().net_outputs_to_fields(ctx, _ptr(out), Ns, _ptr(fields)))
+
+
+def net_fields_grad_to_outputs(ctx, grad, Ns, dout):
+    _check(load().net_fields_grad_to_outputs(ctx, _ptr(grad), Ns, _ptr(dout)))
+
+
+def deficit_loss(ctx, fields, Ns, targets, K, grad=None):
+    loss = ctypes.c_double()
+    _check(load().deficit_loss(ctx, _ptr(fields), Ns, _ptr(targets), K, ctypes.byref(loss), _ptr(grad)))
+    return loss.value
+
+
+def adam_update(ctx, theta, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    _check(load().adam_update(ctx, _ptr(theta), _ptr(g), _ptr(m), _ptr(v), theta.numel(), t, lr, b1, b2, eps))
 
 
 def dfl_use_graphs(ctx, on=True):

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdfl.so")
-SOURCES = ["api.cpp", "layout.hip", "dirac.hip", "blas.hip", "sap.hip", "dfl.hip", "little.hip"]
+SOURCES = ["api.cpp", "layout.hip", "dirac.hip", "blas.hip", "sap.hip", "dfl.hip", "little.hip", "net.hip"]
 ARCH = os.environ.get("DFL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -5,6 +5,7 @@
 // solves the small triangular systems of GCR.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -16,6 +17,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "dfl_net.h"
 
 namespace dfl {
 
@@ -63,7 +65,7 @@ void free_all(dfl_ctx* c)
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
                     c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
-                    c->lfin, c->lacoef, c->dact};
+                    c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -71,6 +73,8 @@ void free_all(dfl_ctx* c)
         (void)hipHostFree(c->hscal);
     if (c->hact)
         (void)hipHostFree(c->hact);
+    if (c->loss_host)
+        (void)hipHostFree(c->loss_host);
 }
 
 void check_blocks(const int dims[4], const int b[4], const char* what)
@@ -594,6 +598,49 @@ void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c6
     launch_sub<double>(in, tmpB, out, c->field_elems * nb, c->stream);
 }
 
+// Relaxed inverse iteration of eq. (5.1) on n native FP64 fields in place:
+// normalise, then `steps` times psi <- M_sap psi at m0_setup and normalise.
+// Sets c->dflag bit 0 on non-finite input.
+void inverse_iterate(dfl_ctx* c, c64* f, int n, int steps)
+{
+    const long F = c->field_elems;
+    for (int l = 0; l < n; ++l) {
+        launch_finite_check<double>(f + (long)l * F, F, c->dflag, c->stream);
+        launch_norm2<double>(f + (long)l * F, F, c->red, c->dscal + S_B, c->stream);
+        launch_scale_invsqrt<double>(f + (long)l * F, F, c->dscal + S_B, c->stream);
+    }
+    for (int step = 0; step < steps; ++step) {
+        if (c->p.sap_prec == DFL_F64) {
+            sap_apply(c, f, c->tN, c->p.m0_setup, n);
+            launch_copy<double>(c->tN, f, F * n, c->stream);
+        } else {
+            sap_apply(c, f, f, c->p.m0_setup, n);  // FP32 path: staged through s32a/s32b
+        }
+        for (int l = 0; l < n; ++l) {
+            launch_norm2<double>(f + (long)l * F, F, c->red, c->dscal + S_B, c->stream);
+            launch_scale_invsqrt<double>(f + (long)l * F, F, c->dscal + S_B, c->stream);
+        }
+    }
+}
+
+int max_multi_fields(const dfl_ctx* c)
+{
+    return c->p.sap_prec == DFL_F64 ? c->p.Ns : std::max(c->p.Ns, c->p.nrhs_max);
+}
+
+template <typename T> T* grow(dfl_ctx* c, T* p, size_t& have, size_t need)
+{
+    if (need <= have)
+        return p;
+    sync(c);
+    if (p)
+        HIPCHECK(hipFree(p));
+    have = 0;
+    T* q = alloc_dev<T>(c, need);
+    have = need;
+    return q;
+}
+
 }  // namespace
 }  // namespace dfl
 
@@ -955,27 +1002,9 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     c->have_subspace = false;
     HIPCHECK(hipMemcpyAsync(c->Phi, init, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
-    for (int l = 0; l < Ns; ++l) {
-        c64* f = c->Phi + (long)l * F;
-        launch_finite_check<double>(f, F, c->dflag, c->stream);
-        launch_norm2<double>(f, F, c->red, c->dscal + S_B, c->stream);
-        launch_scale_invsqrt<double>(f, F, c->dscal + S_B, c->stream);
-    }
     // inverse iteration, eq. (5.1): psi_l <- M_sap psi_l, normalised; the
     // Schwarz sweeps relax all Ns fields in one launch each
-    for (int step = 0; step < c->p.n_inviter; ++step) {
-        if (c->p.sap_prec == DFL_F64) {
-            sap_apply(c, c->Phi, c->tN, c->p.m0_setup, Ns);
-            launch_copy<double>(c->tN, c->Phi, F * Ns, c->stream);
-        } else {
-            sap_apply(c, c->Phi, c->Phi, c->p.m0_setup, Ns);  // FP32 path: staged through s32a/s32b
-        }
-        for (int l = 0; l < Ns; ++l) {
-            c64* f = c->Phi + (long)l * F;
-            launch_norm2<double>(f, F, c->red, c->dscal + S_B, c->stream);
-            launch_scale_invsqrt<double>(f, F, c->dscal + S_B, c->stream);
-        }
-    }
+    inverse_iterate(c, c->Phi, Ns, c->p.n_inviter);
     // block restriction and Gram-Schmidt, eq. (4.2)
     ProfScope ps_setup(c, DFL_PROF_SETUP);
     launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->stream);
@@ -1221,6 +1250,195 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
         g_last_error = "solve: tolerance not reached within maxiter";
         return worst;
     }
+    API_END
+}
+
+// ------------------------------------------------------ start-field network
+
+int dfl_inverse_iteration(dfl_ctx* c, void* fields, int n, int steps)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(fields, "fields");
+    need_gauge(c);
+    if (n < 1 || n > max_multi_fields(c))
+        fail(DFL_EINVAL, "n must be in 1..Ns (FP64 Schwarz) or 1..max(Ns, nrhs_max)");
+    if (steps < 0)
+        fail(DFL_EINVAL, "steps must be >= 0");
+    HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
+    inverse_iterate(c, static_cast<c64*>(fields), n, steps);
+    int flag[4];
+    HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (flag[0] & 1)
+        fail(DFL_ENONFINITE, "non-finite entries in the fields");
+    API_END
+}
+
+int net_features(dfl_ctx* c, const float* noise, float* x)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(noise, "noise");
+    need_ptr(x, "x");
+    need_gauge(c);
+    launch_net_features(c->g, c->U64, noise, x, c->stream);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int conv4d_forward(dfl_ctx* c, const float* in, int cin, const float* W, const float* b, int cout, float* z, float* a)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(in, "in");
+    need_ptr(W, "W");
+    need_ptr(z, "z");
+    if (cin < 1 || cin > kNetMaxCin || cout < 1 || cout > kNetMaxCout)
+        fail(DFL_EINVAL, "channels: 1 <= cin <= 96, 1 <= cout <= 576");
+    if (z == in || a == in)
+        fail(DFL_EINVAL, "outputs must not overlap the input");
+    launch_conv_forward(c->g, in, cin, W, b, cout, z, a, c->stream);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int conv4d_backward(dfl_ctx* c, const float* in, int cin, const float* W, int cout, const float* g, float* dW,
+                    float* db, float* din, const float* z_in)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(in, "in");
+    need_ptr(W, "W");
+    need_ptr(g, "g");
+    need_ptr(dW, "dW");
+    need_ptr(db, "db");
+    if (cin < 1 || cin > kNetMaxCin || cout < 1 || cout > kNetMaxCout)
+        fail(DFL_EINVAL, "channels: 1 <= cin <= 96, 1 <= cout <= 576");
+    if (din && (din == g || din == in))
+        fail(DFL_EINVAL, "din must not overlap g or in");
+    long chunk = 0;
+    int nchunk = 0;
+    const size_t need = conv_wgrad_chunk_floats(c->g, cin, cout, &chunk, &nchunk);
+    c->net_part = grow<float>(c, c->net_part, c->net_part_n, need);
+    launch_conv_backward(c->g, in, cin, W, cout, g, dW, db, din, z_in, c->net_part, chunk, nchunk, c->stream);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int net_outputs_to_fields(dfl_ctx* c, const float* out, int Ns, void* fields)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(out, "out");
+    need_ptr(fields, "fields");
+    if (Ns < 1 || 24 * Ns > kNetMaxCout)
+        fail(DFL_EINVAL, "Ns must be in 1..24");
+    launch_out_to_fields(c->g, out, Ns, static_cast<c64*>(fields), c->stream);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int net_fields_grad_to_outputs(dfl_ctx* c, const void* grad, int Ns, float* dout)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(grad, "grad");
+    need_ptr(dout, "dout");
+    if (Ns < 1 || 24 * Ns > kNetMaxCout)
+        fail(DFL_EINVAL, "Ns must be in 1..24");
+    launch_fields_to_out(c->g, static_cast<const c64*>(grad), Ns, dout, c->stream);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int deficit_loss(dfl_ctx* c, const void* fields, int Ns, const void* targets, int K, double* loss, void* grad)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(fields, "fields");
+    need_ptr(targets, "targets");
+    need_ptr(loss, "loss");
+    if (Ns < 1 || Ns > kLossMaxN || K < 1 || K > kLossMaxN)
+        fail(DFL_EINVAL, "Ns and K must be in 1..32");
+    if (Ns > 12 * c->g.Vb)
+        fail(DFL_EINVAL, "Ns exceeds the dimension of a block");
+    const long Nb = c->g.Nb;
+    const size_t nY = (size_t)Nb * Ns * K;
+    const size_t nbuf = (size_t)Nb * K * 2 + K;
+    if (nY > c->loss_n || !c->loss_buf) {
+        sync(c);
+        if (c->loss_Y)
+            HIPCHECK(hipFree(c->loss_Y));
+        if (c->loss_buf)
+            HIPCHECK(hipFree(c->loss_buf));
+        if (c->loss_host)
+            HIPCHECK(hipHostFree(c->loss_host));
+        c->loss_Y = nullptr;
+        c->loss_buf = nullptr;
+        c->loss_host = nullptr;
+        c->loss_n = 0;
+        const size_t cap_Y = (size_t)Nb * kLossMaxN * kLossMaxN;
+        const size_t cap_b = (size_t)Nb * kLossMaxN * 2 + kLossMaxN;
+        c->loss_Y = alloc_dev<c64>(c, cap_Y);
+        c->loss_buf = alloc_dev<double>(c, cap_b);
+        HIPCHECK(hipHostMalloc((void**)&c->loss_host, sizeof(double) * cap_b, hipHostMallocDefault));
+        c->loss_n = cap_Y;
+    }
+    double* tb2 = c->loss_buf;
+    double* proj = tb2 + Nb * K;
+    double* wk = proj + Nb * K;
+    HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
+    launch_deficit_block(c->g, static_cast<const c64*>(fields), Ns, static_cast<const c64*>(targets), K, c->loss_Y,
+                         tb2, proj, c->dflag, c->stream);
+    HIPCHECK(hipGetLastError());
+    int flag[4];
+    HIPCHECK(hipMemcpyAsync(c->loss_host, tb2, sizeof(double) * Nb * K * 2, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (flag[0] & 1)
+        fail(DFL_ESINGULAR, "deficit loss: the fields are linearly dependent on a block");
+    const double* h_tb2 = c->loss_host;
+    const double* h_proj = h_tb2 + Nb * K;
+    double* h_wk = c->loss_host + Nb * K * 2;
+    double total = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double tn2 = 0.0, pr = 0.0;
+        for (long b = 0; b < Nb; ++b) {
+            tn2 += h_tb2[b * K + k];
+            pr += h_proj[b * K + k];
+        }
+        if (!(tn2 > 0.0))
+            fail(DFL_EINVAL, "deficit loss: a target field is zero");
+        total += (tn2 - pr) / tn2;
+        h_wk[k] = 1.0 / (K * tn2);
+    }
+    *loss = total / K;
+    if (grad) {
+        HIPCHECK(hipMemcpyAsync(wk, h_wk, sizeof(double) * K, hipMemcpyHostToDevice, c->stream));
+        launch_deficit_grad(c->g, static_cast<const c64*>(fields), Ns, static_cast<const c64*>(targets), K,
+                            c->loss_Y, wk, static_cast<c64*>(grad), c->stream);
+        HIPCHECK(hipGetLastError());
+        sync(c);  // the weights live in the pinned mirror until the copy has run
+    }
+    API_END
+}
+
+int adam_update(dfl_ctx* c, float* theta, const float* g, float* m, float* v, long long n, int t, double lr, double b1,
+                double b2, double eps)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(theta, "theta");
+    need_ptr(g, "g");
+    need_ptr(m, "m");
+    need_ptr(v, "v");
+    if (t < 1 || n < 0 || !(lr > 0.0) || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) || !(eps > 0.0))
+        fail(DFL_EINVAL, "adam: t >= 1, n >= 0, lr > 0, 0 <= b1, b2 < 1, eps > 0");
+    const double c1 = 1.0 - std::pow(b1, t), c2 = 1.0 - std::pow(b2, t);
+    launch_adam(theta, g, m, v, (long)n, (float)lr, (float)b1, (float)b2, (float)eps, (float)c1, (float)c2,
+                c->stream);
+    HIPCHECK(hipGetLastError());
     API_END
 }
 

@@ -121,6 +121,13 @@ struct dfl_ctx {
     int* hact = nullptr;         // pinned host mirror
     size_t alloc_bytes = 0;
     std::vector<double> history;  // outer GCR residues of the last solve
+    // start-field network scratch (grown on demand)
+    float* net_part = nullptr;   // weight-gradient partial sums
+    size_t net_part_n = 0;
+    dfl::c64* loss_Y = nullptr;  // deficit loss: per-block G^-1 Psi^+ T
+    double* loss_buf = nullptr;  // [Nb][K] block norms, [Nb][K] projections, [K] weights
+    double* loss_host = nullptr;
+    size_t loss_n = 0;
     // HIP graphs of the GCR steps, keyed by (step index, number of sources)
     bool use_graph = false;
     bool capturing = false;
@@ -227,6 +234,27 @@ void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s
 void launch_c64_to_c32(const c64* a, c32* b, long n, hipStream_t s);
 // A32 = A, At64 = At32 = A with every Ns x Ns block transposed
 void launch_little_copies(const c64* A, c32* A32, c64* At64, c32* At32, long nblocks, int Ns, hipStream_t s);
+
+// ------------------------------------------------------------------- net.hip
+// Start-field network: FP32 planes [C][V] in canonical site order.
+void launch_net_features(const Geom& g, const c64* U64, const float* noise, float* x, hipStream_t s);
+void launch_conv_forward(const Geom& g, const float* in, int cin, const float* W, const float* b, int cout, float* z,
+                         float* a, hipStream_t s);
+size_t conv_wgrad_chunk_floats(const Geom& g, int cin, int cout, long* chunk, int* nchunk);
+void launch_conv_backward(const Geom& g, const float* in, int cin, const float* W, int cout, const float* gr,
+                          float* dW, float* db, float* din, const float* zprev, float* part, long chunk, int nchunk,
+                          hipStream_t s);
+void launch_out_to_fields(const Geom& g, const float* out, int Ns, c64* f, hipStream_t s);
+void launch_fields_to_out(const Geom& g, const c64* gr, int Ns, float* dout, hipStream_t s);
+void launch_deficit_block(const Geom& g, const c64* Psi, int Ns, const c64* T, int K, c64* Y, double* tb2,
+                          double* proj, int* flag, hipStream_t s);
+void launch_deficit_grad(const Geom& g, const c64* Psi, int Ns, const c64* T, int K, const c64* Y, const double* wk,
+                         c64* grad, hipStream_t s);
+void launch_adam(float* th, const float* gr, float* m, float* v, long n, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t s);
+constexpr int kNetMaxCin = 96;     // input channels of a convolution (weight gradient bound)
+constexpr int kNetMaxCout = 576;   // output channels (input-gradient staging bound)
+constexpr int kLossMaxN = 32;      // fields and targets of the deficit loss
 
 // ---------------------------------------------------------------- little.hip
 int little_gcr_grid(const Geom& g);

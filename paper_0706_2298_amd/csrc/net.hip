@@ -1,0 +1,599 @@
+// Kernels of the start-field network and its training: periodic 3^4
+// convolutions (forward, backward to the input, backward to the weights),
+// the maps between output channels and quark fields, the block deficit loss
+// of eq. (3.15) with its gradient, and the Adam update.
+//
+// Activations are FP32 planes [C][V] in canonical site order (x0 slowest),
+// so a tap's neighbour is a fixed shift of the site index up to the periodic
+// wrap. Weights are [81][Cin][Cout], tap t = sum_mu (o_mu + 1) 3^(3 - mu) for
+// the offset o in {-1,0,1}^4. Quark fields are native FP64 fields (common.h).
+#include "internal.h"
+
+namespace dfl {
+
+namespace {
+
+constexpr int kCO = 16;        // output channels per workgroup of the convolution
+constexpr int kWT = 64;        // output channels per workgroup of the weight gradient
+constexpr int kWS = 64;        // sites per LDS tile of the weight gradient
+constexpr int kMaxCin = 96;
+
+struct Lat {
+    int L[4];
+    long str[4];  // canonical strides (x3 fastest)
+    long V;
+};
+
+// delta[mu][o+1]: index shift of the neighbour x + o mu_hat of site i
+__device__ inline void tap_shifts(const Lat& lt, long i, int sign, long delta[4][3])
+{
+    long rest = i;
+    int x[4];
+    for (int mu = 3; mu >= 0; --mu) {
+        x[mu] = (int)(rest % lt.L[mu]);
+        rest /= lt.L[mu];
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+        for (int o = -1; o <= 1; ++o) {
+            int y = x[mu] + sign * o;
+            if (y < 0)
+                y += lt.L[mu];
+            if (y >= lt.L[mu])
+                y -= lt.L[mu];
+            delta[mu][o + 1] = (long)(y - x[mu]) * lt.str[mu];
+        }
+    }
+}
+
+__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float silu_grad_f(float z)
+{
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// out[oc][i] = bias[oc] + sum_t sum_ic Wt(t, ic, oc) in[ic][i + s*o_t]
+//   forward (TRANS = false, s = +1): Wt(t, ic, oc) = W[t][ic][oc], nic = Cin
+//   input gradient (TRANS = true, s = -1): Wt(t, ic, oc) = W[t][oc][ic], nic = Cout of W
+// Epilogue: forward stores z and optionally a = silu(z); the input gradient
+// is optionally multiplied by silu'(zprev[oc][i]).
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_conv(Lat lt, const float* __restrict__ in, int nic,
+                                              const float* __restrict__ W, int w_cin, int w_cout,
+                                              const float* __restrict__ bias, int noc, float* __restrict__ out,
+                                              float* __restrict__ act, const float* __restrict__ zprev)
+{
+    __shared__ float4 ws[kMaxCin * kCO / 4 > 576 * kCO / 4 ? kMaxCin * kCO / 4 : 576 * kCO / 4];
+    const long V = lt.V;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int oc0 = blockIdx.y * kCO;
+    long dl[4][3];
+    if (i < V)
+        tap_shifts(lt, i, TRANS ? -1 : 1, dl);
+    float acc[kCO];
+#pragma unroll
+    for (int j = 0; j < kCO; ++j)
+        acc[j] = (bias && oc0 + j < noc) ? bias[oc0 + j] : 0.f;
+    float* wsf = reinterpret_cast<float*>(ws);
+    for (int t = 0; t < 81; ++t) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < nic * kCO; e += blockDim.x) {
+            int ic, j;
+            if (TRANS) {
+                ic = e % nic;
+                j = e / nic;
+            } else {
+                ic = e / kCO;
+                j = e % kCO;
+            }
+            float w = 0.f;
+            if (oc0 + j < noc)
+                w = TRANS ? W[((long)t * w_cin + oc0 + j) * w_cout + ic] : W[((long)t * w_cin + ic) * w_cout + oc0 + j];
+            wsf[ic * kCO + j] = w;
+        }
+        __syncthreads();
+        if (i < V) {
+            const int o0 = t / 27, o1 = (t / 9) % 3, o2 = (t / 3) % 3, o3 = t % 3;
+            const long nb = i + dl[0][o0] + dl[1][o1] + dl[2][o2] + dl[3][o3];
+            const float* src = in + nb;
+            for (int ic = 0; ic < nic; ++ic) {
+                const float x = src[(long)ic * V];
+#pragma unroll
+                for (int q = 0; q < kCO / 4; ++q) {
+                    const float4 w = ws[ic * (kCO / 4) + q];
+                    acc[4 * q] += x * w.x;
+                    acc[4 * q + 1] += x * w.y;
+                    acc[4 * q + 2] += x * w.z;
+                    acc[4 * q + 3] += x * w.w;
+                }
+            }
+        }
+    }
+    if (i >= V)
+        return;
+#pragma unroll
+    for (int j = 0; j < kCO; ++j) {
+        if (oc0 + j >= noc)
+            continue;
+        float v = acc[j];
+        if (TRANS && zprev)
+            v *= silu_grad_f(zprev[(long)(oc0 + j) * V + i]);
+        out[(long)(oc0 + j) * V + i] = v;
+        if (!TRANS && act)
+            act[(long)(oc0 + j) * V + i] = silu_f(v);
+    }
+}
+
+// Weight gradient, partial over a chunk of sites:
+// part[chunk][t][ci][co] = sum_{y in chunk} in[ci][y + o_t] g[co][y].
+// Workgroup (t, co tile of kWT, site chunk); thread (ci group, co), the
+// tiles of g and of the shifted input staged in LDS kWS sites at a time.
+__global__ __launch_bounds__(256) void k_conv_wgrad(Lat lt, const float* __restrict__ in, int cin,
+                                                    const float* __restrict__ g, int cout, long chunk,
+                                                    float* __restrict__ part)
+{
+    __shared__ float gs[kWS][kWT + 1];
+    __shared__ float xs[kWS][kMaxCin + 1];
+    const long V = lt.V;
+    const int t = blockIdx.x;
+    const int co0 = blockIdx.y * kWT;
+    const long y0 = (long)blockIdx.z * chunk;
+    const long y1 = y0 + chunk < V ? y0 + chunk : V;
+    const int col = threadIdx.x % kWT, cg = threadIdx.x / kWT;  // 4 groups of ci
+    const int cpt = (cin + 3) / 4;
+    const int o0 = t / 27, o1 = (t / 9) % 3, o2 = (t / 3) % 3, o3 = t % 3;
+    float acc[kMaxCin / 4];
+#pragma unroll
+    for (int c = 0; c < kMaxCin / 4; ++c)
+        acc[c] = 0.f;
+    for (long ys = y0; ys < y1; ys += kWS) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kWS * kWT; e += blockDim.x) {
+            const int yy = e % kWS, cc = e / kWS;
+            const long y = ys + yy;
+            gs[yy][cc] = (y < y1 && co0 + cc < cout) ? g[(long)(co0 + cc) * V + y] : 0.f;
+        }
+        for (int e = threadIdx.x; e < kWS * cin; e += blockDim.x) {
+            const int yy = e % kWS, ci = e / kWS;
+            const long y = ys + yy;
+            float v = 0.f;
+            if (y < y1) {
+                long dl[4][3];
+                tap_shifts(lt, y, 1, dl);
+                v = in[(long)ci * V + y + dl[0][o0] + dl[1][o1] + dl[2][o2] + dl[3][o3]];
+            }
+            xs[yy][ci] = v;
+        }
+        __syncthreads();
+        for (int yy = 0; yy < kWS; ++yy) {
+            const float gv = gs[yy][col];
+#pragma unroll
+            for (int c = 0; c < kMaxCin / 4; ++c)
+                if (c < cpt && cg * cpt + c < cin)
+                    acc[c] += xs[yy][cg * cpt + c] * gv;
+        }
+    }
+    if (co0 + col >= cout)
+        return;
+    float* dst = part + ((long)blockIdx.z * 81 + t) * cin * cout;
+#pragma unroll
+    for (int c = 0; c < kMaxCin / 4; ++c) {
+        const int ci = cg * cpt + c;
+        if (c < cpt && ci < cin)
+            dst[(long)ci * cout + co0 + col] = acc[c];
+    }
+}
+
+// dW[e] = sum over chunks of part[chunk][e] (fixed order)
+__global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ part, long n, int nchunk,
+                                                    float* __restrict__ dW)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n)
+        return;
+    float s = 0.f;
+    for (int q = 0; q < nchunk; ++q)
+        s += part[(long)q * n + e];
+    dW[e] = s;
+}
+
+// db[co] = sum_y g[co][y], one workgroup per channel
+__global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ g, long V, float* __restrict__ db)
+{
+    __shared__ float sh[16];
+    const float* gc = g + (long)blockIdx.x * V;
+    float s = 0.f;
+    for (long y = threadIdx.x; y < V; y += blockDim.x)
+        s += gc[y];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0)
+        db[blockIdx.x] = s;
+}
+
+// canonical site index of native site s
+__device__ inline long canon_of(const Geom& g, long s)
+{
+    int n[4], y[4], x[4];
+    site_decompose(g, s, n, y);
+    for (int mu = 0; mu < 4; ++mu)
+        x[mu] = n[mu] * g.b[mu] + y[mu];
+    return canon_index(g, x);
+}
+
+// x[c][i]: Re/Im of U_mu(x)[a][b] at channel ((mu*3 + a)*3 + b)*2 + r, then
+// the 24 noise channels (noise [V][24], canonical)
+__global__ __launch_bounds__(256) void k_features(Geom g, const c64* __restrict__ U64, const float* __restrict__ noise,
+                                                  float* __restrict__ x)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V)
+        return;
+    const long i = canon_of(g, s);
+    for (int k = 0; k < 36; ++k) {
+        const c64 u = U64[tidx(s, k, 36)];
+        x[(long)(2 * k) * g.V + i] = (float)u.re;
+        x[(long)(2 * k + 1) * g.V + i] = (float)u.im;
+    }
+    for (int k = 0; k < 24; ++k)
+        x[(long)(72 + k) * g.V + i] = noise[i * 24 + k];
+}
+
+// field_l(x)[c] = out[(l*12 + c)*2][i] + i out[(l*12 + c)*2 + 1][i]
+__global__ __launch_bounds__(256) void k_out_to_fields(Geom g, const float* __restrict__ out, int Ns,
+                                                       c64* __restrict__ f)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V)
+        return;
+    const long i = canon_of(g, s);
+    const long F = 12 * g.V;
+    for (int l = 0; l < Ns; ++l)
+        for (int c = 0; c < 12; ++c) {
+            const long ch = (long)(l * 12 + c) * 2;
+            f[l * F + tidx(s, c, 12)] = c64{(double)out[ch * g.V + i], (double)out[(ch + 1) * g.V + i]};
+        }
+}
+
+// dout[(l*12 + c)*2 + r][i] = 2 Re / 2 Im of grad_l(x)[c]  (real gradient of a
+// real loss from its derivative with respect to conj(field))
+__global__ __launch_bounds__(256) void k_fields_to_out(Geom g, const c64* __restrict__ gr, int Ns,
+                                                       float* __restrict__ dout)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V)
+        return;
+    const long i = canon_of(g, s);
+    const long F = 12 * g.V;
+    for (int l = 0; l < Ns; ++l)
+        for (int c = 0; c < 12; ++c) {
+            const long ch = (long)(l * 12 + c) * 2;
+            const c64 v = gr[l * F + tidx(s, c, 12)];
+            dout[ch * g.V + i] = (float)(2.0 * v.re);
+            dout[(ch + 1) * g.V + i] = (float)(2.0 * v.im);
+        }
+}
+
+// Per deflation block: G = Psi^+ Psi, C = Psi^+ T, Cholesky G = L L^+,
+// Y = G^-1 C; writes Y[blk][l][k], tb2[blk][k] = ||t_k on the block||^2 and
+// proj[blk][k] = Re(c_k^+ y_k). Entries are staged through LDS 64 at a time.
+constexpr int kMaxLossN = 32;
+constexpr int kLT = 64;  // staged entries
+
+__global__ __launch_bounds__(256) void k_deficit_block(Geom g, const c64* __restrict__ Psi, int Ns,
+                                                       const c64* __restrict__ T, int K, c64* __restrict__ Y,
+                                                       double* __restrict__ tb2, double* __restrict__ proj,
+                                                       int* __restrict__ flag)
+{
+    extern __shared__ double dyn[];
+    c64* ps = reinterpret_cast<c64*>(dyn);              // [Ns][kLT + 1]
+    c64* ts = ps + Ns * (kLT + 1);                      // [K][kLT + 1]
+    c64* Gm = ts + K * (kLT + 1);                       // [Ns][Ns]
+    c64* Cm = Gm + Ns * Ns;                             // [Ns][K]
+    double* tn = reinterpret_cast<double*>(Cm + Ns * K);  // [K]
+    const int blk = blockIdx.x;
+    const long F = 12 * g.V;
+    const int ne = 12 * g.Vb;
+    // products: G (l <= m), C (l, k), ||t_k||^2
+    const int nG = Ns * (Ns + 1) / 2, nC = Ns * K, np = nG + nC + K;
+    c64 acc[8];
+    int pid[8];
+    int nmine = 0;
+    for (int p = threadIdx.x; p < np && nmine < 8; p += blockDim.x)
+        pid[nmine++] = p;
+    for (int q = 0; q < 8; ++q)
+        acc[q] = c64{0.0, 0.0};
+    for (int e0 = 0; e0 < ne; e0 += kLT) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < (Ns + K) * kLT; q += blockDim.x) {
+            const int r = q / kLT, e = q % kLT;
+            c64 v{0.0, 0.0};
+            if (e0 + e < ne) {
+                long idx;
+                if ((g.Vb & (kTile - 1)) == 0)
+                    idx = (long)blk * ne + e0 + e;
+                else
+                    idx = tidx((long)blk * g.Vb + (e0 + e) % g.Vb, (e0 + e) / g.Vb, 12);
+                v = r < Ns ? Psi[(long)r * F + idx] : T[(long)(r - Ns) * F + idx];
+            }
+            if (r < Ns)
+                ps[r * (kLT + 1) + e] = v;
+            else
+                ts[(r - Ns) * (kLT + 1) + e] = v;
+        }
+        __syncthreads();
+        for (int q = 0; q < nmine; ++q) {
+            const int p = pid[q];
+            const c64 *u, *v;
+            if (p < nG) {
+                int l = 0, rem = p;
+                while (rem >= Ns - l) {
+                    rem -= Ns - l;
+                    ++l;
+                }
+                u = ps + l * (kLT + 1);
+                v = ps + (l + rem) * (kLT + 1);
+            } else if (p < nG + nC) {
+                const int l = (p - nG) / K, k = (p - nG) % K;
+                u = ps + l * (kLT + 1);
+                v = ts + k * (kLT + 1);
+            } else {
+                u = ts + (p - nG - nC) * (kLT + 1);
+                v = u;
+            }
+            double re = acc[q].re, im = acc[q].im;
+            for (int e = 0; e < kLT; ++e) {
+                const c64 a = u[e], b = v[e];
+                re += a.re * b.re + a.im * b.im;
+                im += a.re * b.im - a.im * b.re;
+            }
+            acc[q] = c64{re, im};
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < nmine; ++q) {
+        const int p = pid[q];
+        if (p < nG) {
+            int l = 0, rem = p;
+            while (rem >= Ns - l) {
+                rem -= Ns - l;
+                ++l;
+            }
+            const int m = l + rem;
+            Gm[l * Ns + m] = acc[q];
+            Gm[m * Ns + l] = c64{acc[q].re, -acc[q].im};
+        } else if (p < nG + nC) {
+            Cm[p - nG] = acc[q];
+        } else {
+            tn[p - nG - nC] = acc[q].re;
+        }
+    }
+    __syncthreads();
+    // Cholesky in place (lower triangle): G = L L^+
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < Ns; ++j) {
+            double d = Gm[j * Ns + j].re;
+            for (int k = 0; k < j; ++k)
+                d -= Gm[j * Ns + k].re * Gm[j * Ns + k].re + Gm[j * Ns + k].im * Gm[j * Ns + k].im;
+            if (!(d > 0.0)) {
+                atomicOr(flag, 1);
+                d = 1.0;
+            }
+            const double ljj = sqrt(d);
+            Gm[j * Ns + j] = c64{ljj, 0.0};
+            for (int i = j + 1; i < Ns; ++i) {
+                c64 s = Gm[i * Ns + j];
+                for (int k = 0; k < j; ++k) {
+                    const c64 a = Gm[i * Ns + k], b = Gm[j * Ns + k];  // s -= L_ik conj(L_jk)
+                    s.re -= a.re * b.re + a.im * b.im;
+                    s.im -= a.im * b.re - a.re * b.im;
+                }
+                Gm[i * Ns + j] = c64{s.re / ljj, s.im / ljj};
+            }
+        }
+    }
+    __syncthreads();
+    // columns of Y: L z = c, L^+ y = z
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        c64 z[kMaxLossN];
+        for (int i = 0; i < Ns; ++i) {
+            c64 s = Cm[i * K + k];
+            for (int j = 0; j < i; ++j) {
+                const c64 a = Gm[i * Ns + j];
+                s.re -= a.re * z[j].re - a.im * z[j].im;
+                s.im -= a.re * z[j].im + a.im * z[j].re;
+            }
+            const double d = Gm[i * Ns + i].re;
+            z[i] = c64{s.re / d, s.im / d};
+        }
+        for (int i = Ns - 1; i >= 0; --i) {
+            c64 s = z[i];
+            for (int j = i + 1; j < Ns; ++j) {
+                const c64 a = Gm[j * Ns + i];  // (L^+)_ij = conj(L_ji)
+                s.re -= a.re * z[j].re + a.im * z[j].im;
+                s.im -= a.re * z[j].im - a.im * z[j].re;
+            }
+            const double d = Gm[i * Ns + i].re;
+            z[i] = c64{s.re / d, s.im / d};
+        }
+        double pr = 0.0;
+        for (int i = 0; i < Ns; ++i) {
+            const c64 cc = Cm[i * K + k];
+            pr += cc.re * z[i].re + cc.im * z[i].im;
+            Y[((long)blk * Ns + i) * K + k] = z[i];
+        }
+        tb2[(long)blk * K + k] = tn[k];
+        proj[(long)blk * K + k] = pr;
+    }
+}
+
+// grad_l(x) = -sum_k (t_k(x) - sum_m Psi_m(x) Y_mk) conj(Y_lk) wk[k]
+// (wk = 1 / (K ||t_k||^2)). Workgroup = kLT entries of one block: first the
+// residuals r_k(x) into LDS (task (k, x)), then the gradient (task (l, x)).
+__global__ __launch_bounds__(256) void k_deficit_grad(Geom g, const c64* __restrict__ Psi, int Ns,
+                                                      const c64* __restrict__ T, int K, const c64* __restrict__ Y,
+                                                      const double* __restrict__ wk, c64* __restrict__ grad)
+{
+    __shared__ c64 ys[kMaxLossN * kMaxLossN];
+    __shared__ c64 rs[kMaxLossN * kLT];
+    __shared__ double ws[kMaxLossN];
+    const int blk = blockIdx.y;
+    const long F = 12 * g.V;
+    const int ne = 12 * g.Vb;
+    const int e0 = blockIdx.x * kLT;
+    for (int q = threadIdx.x; q < Ns * K; q += blockDim.x)
+        ys[q] = Y[(long)blk * Ns * K + q];
+    for (int q = threadIdx.x; q < K; q += blockDim.x)
+        ws[q] = wk[q];
+    __syncthreads();
+    auto index = [&](int e) -> long {
+        if ((g.Vb & (kTile - 1)) == 0)
+            return (long)blk * ne + e;
+        return tidx((long)blk * g.Vb + e % g.Vb, e / g.Vb, 12);
+    };
+    for (int q = threadIdx.x; q < K * kLT; q += blockDim.x) {
+        const int k = q / kLT, e = q % kLT;
+        c64 r{0.0, 0.0};
+        if (e0 + e < ne) {
+            const long idx = index(e0 + e);
+            r = T[(long)k * F + idx];
+            for (int m = 0; m < Ns; ++m) {
+                const c64 p = Psi[(long)m * F + idx], y = ys[m * K + k];
+                r.re -= p.re * y.re - p.im * y.im;
+                r.im -= p.re * y.im + p.im * y.re;
+            }
+        }
+        rs[k * kLT + e] = r;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < Ns * kLT; q += blockDim.x) {
+        const int l = q / kLT, e = q % kLT;
+        if (e0 + e >= ne)
+            continue;
+        double gr = 0.0, gi = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const c64 r = rs[k * kLT + e], y = ys[l * K + k];  // r conj(y)
+            gr -= ws[k] * (r.re * y.re + r.im * y.im);
+            gi -= ws[k] * (r.im * y.re - r.re * y.im);
+        }
+        grad[(long)l * F + index(e0 + e)] = c64{gr, gi};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ th, const float* __restrict__ gr,
+                                              float* __restrict__ m, float* __restrict__ v, long n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float gi = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+Lat make_lat(const Geom& g)
+{
+    Lat lt;
+    for (int mu = 0; mu < 4; ++mu)
+        lt.L[mu] = g.L[mu];
+    lt.str[3] = 1;
+    for (int mu = 2; mu >= 0; --mu)
+        lt.str[mu] = lt.str[mu + 1] * lt.L[mu + 1];
+    lt.V = g.V;
+    return lt;
+}
+
+inline unsigned site_blocks(long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+size_t conv_wgrad_chunk_floats(const Geom& g, int cin, int cout, long* chunk, int* nchunk)
+{
+    // about 64 workgroups' worth of sites per chunk, at most 32 chunks
+    long c = (g.V + 31) / 32;
+    c = ((c + kWS - 1) / kWS) * kWS;
+    if (c < 4096)
+        c = 4096;
+    *chunk = c;
+    *nchunk = (int)((g.V + c - 1) / c);
+    return (size_t)(*nchunk) * 81 * cin * cout;
+}
+
+void launch_net_features(const Geom& g, const c64* U64, const float* noise, float* x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_features, dim3(site_blocks(g.V)), dim3(256), 0, s, g, U64, noise, x);
+}
+
+void launch_conv_forward(const Geom& g, const float* in, int cin, const float* W, const float* b, int cout, float* z,
+                         float* a, hipStream_t s)
+{
+    const Lat lt = make_lat(g);
+    hipLaunchKernelGGL(k_conv<false>, dim3(site_blocks(g.V), (cout + kCO - 1) / kCO), dim3(256), 0, s, lt, in, cin,
+                       W, cin, cout, b, cout, z, a, nullptr);
+}
+
+void launch_conv_backward(const Geom& g, const float* in, int cin, const float* W, int cout, const float* gr,
+                          float* dW, float* db, float* din, const float* zprev, float* part, long chunk, int nchunk,
+                          hipStream_t s)
+{
+    const Lat lt = make_lat(g);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(81, (cout + kWT - 1) / kWT, nchunk), dim3(256), 0, s, lt, in, cin, gr,
+                       cout, chunk, part);
+    const long n = 81L * cin * cout;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(site_blocks(n)), dim3(256), 0, s, part, n, nchunk, dW);
+    hipLaunchKernelGGL(k_bias_grad, dim3(cout), dim3(256), 0, s, gr, g.V, db);
+    if (din)
+        hipLaunchKernelGGL(k_conv<true>, dim3(site_blocks(g.V), (cin + kCO - 1) / kCO), dim3(256), 0, s, lt, gr,
+                           cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
+}
+
+void launch_out_to_fields(const Geom& g, const float* out, int Ns, c64* f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_out_to_fields, dim3(site_blocks(g.V)), dim3(256), 0, s, g, out, Ns, f);
+}
+
+void launch_fields_to_out(const Geom& g, const c64* gr, int Ns, float* dout, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fields_to_out, dim3(site_blocks(g.V)), dim3(256), 0, s, g, gr, Ns, dout);
+}
+
+size_t deficit_lds_bytes(int Ns, int K)
+{
+    return sizeof(c64) * ((size_t)(Ns + K) * (kLT + 1) + (size_t)Ns * Ns + (size_t)Ns * K) + sizeof(double) * K;
+}
+
+void launch_deficit_block(const Geom& g, const c64* Psi, int Ns, const c64* T, int K, c64* Y, double* tb2,
+                          double* proj, int* flag, hipStream_t s)
+{
+    const size_t lds = deficit_lds_bytes(Ns, K);
+    static bool attr = false;
+    if (!attr) {
+        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deficit_block),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)deficit_lds_bytes(kMaxLossN, kMaxLossN)));
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_deficit_block, dim3(g.Nb), dim3(256), lds, s, g, Psi, Ns, T, K, Y, tb2, proj, flag);
+}
+
+void launch_deficit_grad(const Geom& g, const c64* Psi, int Ns, const c64* T, int K, const c64* Y, const double* wk,
+                         c64* grad, hipStream_t s)
+{
+    const int ne = 12 * (int)g.Vb;
+    hipLaunchKernelGGL(k_deficit_grad, dim3((ne + kLT - 1) / kLT, g.Nb), dim3(256), 0, s, g, Psi, Ns, T, K, Y, wk,
+                       grad);
+}
+
+void launch_adam(float* th, const float* gr, float* m, float* v, long n, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_adam, dim3(site_blocks(n)), dim3(256), 0, s, th, gr, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+}  // namespace dfl
