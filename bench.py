@@ -19,6 +19,10 @@ Also reported (outside the timed region):
 * 32 x 16^3 in mixed precision (BF16 two-row links, FP32 Schwarz and inner
   little solves, Schwarz block shape picked by the autotuner) with the error
   of each result against FP64 references;
+* the learned start fields: the network trained on 16^4 fields (eps 0.5),
+  then on held-out 64 x 32^3 fields the GCR iterations and times of the
+  deflated solve with network start fields against random ones at equal
+  inverse-iteration steps;
 * 12 point sources on 48 x 24^3 and 6 on 32 x 16^3 (Ns = 24) solved as one
   batch per lattice with graph replay, against one-by-one solves, and the
   12-source dirac_apply rate;
@@ -345,6 +349,80 @@ def multi_rhs(torch):
     return out
 
 
+def learned_subspace(torch, n_train=20, n_test=2, train_steps=300, m0=-0.56):
+    """Start-field network: trained on 20 seeded 16^4 gauge fields (eps 0.5,
+    seeds 5000..5019; targets = 24 inverse-iteration low modes, 3 steps, from
+    seeded random fields), tested on held-out 64 x 32^3 fields (seeds 5100..)
+    at m0 = -0.56 (near the critical mass of eps 0.5): deflated SAP-GCR
+    iterations and times with the subspace grown from (a) random fields and
+    (b) network fields, both with 3 inverse-iteration steps (equal setup
+    D-applications), and (c) network fields with 1 step. The network is local
+    (receptive field 9^4) and the links are i.i.d. per site, so a 16^4 lattice
+    has the local statistics of a 64 x 32^3 one."""
+    import latgen
+    from paper_0706_2298_amd import F32, Solver, binding
+    from paper_0706_2298_amd.learned import CHANNELS, StartFieldNet, make_targets
+    tdims, xdims, eps, K = (16, 16, 16, 16), (64, 32, 32, 32), 0.5, 24
+    prm = dict(Ns=24, m0=m0, m0_setup=m0, n_inviter=0, sap_prec=F32, link_prec=F32, little_prec=F32, maxiter=4000)
+    S = Solver(tdims, **solver_params(**prm))
+    links, targets = [], []
+    t0 = time.perf_counter()
+    for j in range(n_train):
+        U = latgen.make_links(tdims, eps, 5000 + j)
+        S.set_gauge(U)
+        targets.append(make_targets(S, S.pack(latgen.make_init_fields(tdims, K, 5300 + j)), 3))
+        links.append(U)
+    t_targets = time.perf_counter() - t0
+    net = StartFieldNet(S, latgen.net_init(CHANNELS, 5500))
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(train_steps):
+        j = i % n_train
+        S.set_gauge(links[j])
+        losses.append(net.train_step(latgen.net_noise(tdims, 8000 + i), targets[j], K, lr=3e-3))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    weights = net.weights_numpy()
+    S.close()
+    del targets, net
+    torch.cuda.empty_cache()
+    T = Solver(xdims, **solver_params(**prm))
+    net = StartFieldNet(T, weights)
+    rows = []
+    for j in range(n_test):
+        seed = 5100 + j
+        U = latgen.make_links(xdims, eps, seed)
+        eta = latgen.make_source(xdims, seed + 100)
+        T.set_gauge(U)
+        ed = T.pack(eta)
+        row = dict(seed=seed)
+        for name, steps in [("random_k3", 3), ("learned_k3", 3), ("learned_k1", 1)]:
+            if name.startswith("random"):
+                f = T.pack(latgen.make_init_fields(xdims, K, seed + 200))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            else:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f = net.forward(latgen.net_noise(xdims, seed + 400))
+            make_targets(T, f, steps)
+            T.setup(f)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            (_, info), t_solve = timed(torch, lambda: T.solve(ed))
+            row[name] = dict(n_gcr=info.n_gcr, t_setup=t_setup, t_solve=t_solve, status=info.status,
+                             rel_residual=info.rel_residual, n_little=info.n_little)
+            del f
+        rows.append(row)
+        log(f"learned: field {seed}: " + ", ".join(f"{k} {row[k]['n_gcr']} it" for k in row if k != "seed"))
+    T.close()
+    torch.cuda.empty_cache()
+    return dict(train_lattice=list(tdims), test_lattice=list(xdims), eps=eps, m0=m0, channels=list(CHANNELS),
+                n_train_fields=n_train, train_steps=train_steps, t_targets=t_targets, t_train=t_train,
+                loss_first10=float(np.mean(losses[:10])), loss_last10=float(np.mean(losses[-10:])), tests=rows)
+
+
 def cpu_baseline(fields, stats):
     """The FP64 oracle on a bounded sample of the step, scaled to solves/s.
 
@@ -394,6 +472,8 @@ def main():
     ap.add_argument("--no-dirac", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the 32x16^3 mixed-precision and multi-source runs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the start-field network training and tests")
+    ap.add_argument("--learned-tests", type=int, default=2, help="held-out 64x32^3 fields for the network")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (y = 1.0 * x), to scale HBM byte counters")
     args = ap.parse_args()
@@ -480,6 +560,9 @@ def main():
         result["mixed_precision_32x16^3"] = mixed_precision_32x16(torch)
         log("multi-source batches")
         result["multi_rhs"] = multi_rhs(torch)
+    if not args.no_learned:
+        log("learned start fields")
+        result["learned_subspace"] = learned_subspace(torch, n_test=args.learned_tests)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(fields, stats)
