@@ -1008,17 +1008,23 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     // block restriction and Gram-Schmidt, eq. (4.2)
     ProfScope ps_setup(c, DFL_PROF_SETUP);
     launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->stream);
-    // little operator, eq. (A.1): block-diagonal part and the eight face hops
+    // little operator, eq. (A.1): block-diagonal part and the eight face
+    // hops, applied to a chunk of basis fields per launch (the Krylov
+    // buffer is free during the setup), then the block products with Phi
     const long nA = (long)c->g.Nb * 9 * Ns * Ns;
-    for (int l = 0; l < Ns; ++l) {
-        const c64* f = c->Phi + (long)l * F;
-        launch_dirac64(c->g, links64(c), f, c->t1, 1, c->p.m0, 1, 0, 0, c->stream);
-        launch_little_column64(c->g, c->Phi, Ns, c->t1, c->A64, 0, l, c->stream);
-        for (int d = 1; d < 9; ++d) {
-            int mu = (d - 1) / 2;
-            int dir = (d & 1) ? +1 : -1;
-            launch_dirac64(c->g, links64(c), f, c->t1, 1, 0.0, 2, mu, dir, c->stream);
-            launch_little_column64(c->g, c->Phi, Ns, c->t1, c->A64, d, l, c->stream);
+    const int chunk = std::min({Ns, little_columns_max(Ns), c->p.nkv * c->p.nrhs_max, 128 - Ns});
+    for (int l0 = 0; l0 < Ns; l0 += chunk) {
+        const int nc = std::min(chunk, Ns - l0);
+        const c64* f = c->Phi + (long)l0 * F;
+        for (int d = 0; d < 9; ++d) {
+            if (d == 0) {
+                launch_dirac64(c->g, links64(c), f, c->xi, nc, c->p.m0, 1, 0, 0, c->stream);
+            } else {
+                const int mu = (d - 1) / 2;
+                const int dir = (d & 1) ? +1 : -1;
+                launch_dirac64(c->g, links64(c), f, c->xi, nc, 0.0, 2, mu, dir, c->stream);
+            }
+            launch_little_columns64(c->g, c->Phi, Ns, c->xi, nc, l0, d, c->A64, c->stream);
         }
     }
     launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);

@@ -166,44 +166,7 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
     }
 }
 
-// A[blk][d][k][l] = sum_{x in blk} conj(Phi_k(x)) Y(x) for all k, fixed d, l
-__global__ __launch_bounds__(kBT) void k_little_column(Geom g, const c64* __restrict__ Phi, int Ns,
-                                                       const c64* __restrict__ Y, c64* __restrict__ A, int d, int l)
-{
-    __shared__ double part[2][kBT / 64];
-    const long base = (long)blockIdx.x * g.Vb;
-    const long fs = 12 * g.V;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = 0; k < Ns; ++k) {
-        const c64* ph = Phi + (long)k * fs;
-        double re = 0.0, im = 0.0;
-        for (int t = threadIdx.x; t < g.Vb; t += kBT)
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                long i = tidx(base + t, c, 12);
-                c64 a = ph[i], b = Y[i];
-                re += a.re * b.re + a.im * b.im;
-                im += a.re * b.im - a.im * b.re;
-            }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        __syncthreads();
-        if (lane == 0) {
-            part[0][wid] = re;
-            part[1][wid] = im;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double a = 0.0, b = 0.0;
-            for (int q = 0; q < kBT / 64; ++q) {
-                a += part[0][q];
-                b += part[1][q];
-            }
-            A[(((long)blockIdx.x * 9 + d) * Ns + k) * Ns + l] = c64{a, b};
-        }
-    }
-}
-
+// index of the d-th neighbour of block blk (d = 0 itself, 1 + 2mu: +mu, 2 + 2mu: -mu)
 __device__ inline int block_nbr(const Geom& g, int blk, int d)
 {
     if (d == 0)
@@ -219,6 +182,65 @@ __device__ inline int block_nbr(const Geom& g, int blk, int d)
     if (nn >= g.nb[mu])
         nn -= g.nb[mu];
     return blk + (nn - n_mu) * g.bstr[mu];
+}
+
+// A[blk][d][k][l0 + j] = sum_{x in blk} conj(Phi_k(x)) Y_j(x) for k < Ns, j < nc:
+// the block products Phi_blk^+ Y_blk of eq. (A.1) for nc columns at once. One
+// workgroup per block; entries staged through LDS kCE at a time, each thread
+// accumulating up to kMaxPairs of the Ns*nc products.
+constexpr int kCE = 32;
+constexpr int kMaxPairs = 16;
+
+__global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __restrict__ Phi, int Ns,
+                                                        const c64* __restrict__ Y, int nc, int l0, int d,
+                                                        c64* __restrict__ A)
+{
+    extern __shared__ c64 st[];  // [Ns + nc][kCE + 1]
+    const int blk = blockIdx.x;
+    const long F = 12 * g.V;
+    const int ne = 12 * g.Vb;
+    const int np = Ns * nc;
+    c64 acc[kMaxPairs];
+#pragma unroll
+    for (int q = 0; q < kMaxPairs; ++q)
+        acc[q] = c64{0.0, 0.0};
+    for (int e0 = 0; e0 < ne; e0 += kCE) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < (Ns + nc) * kCE; q += blockDim.x) {
+            const int r = q / kCE, e = q % kCE;
+            c64 v{0.0, 0.0};
+            if (e0 + e < ne) {
+                const long i = block_elem(g, blk, e0 + e);
+                v = r < Ns ? Phi[(long)r * F + i] : Y[(long)(r - Ns) * F + i];
+            }
+            st[r * (kCE + 1) + e] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kMaxPairs; ++q) {
+            const int p = threadIdx.x + q * blockDim.x;
+            if (p < np) {
+                const int k = p / nc, j = p - k * nc;
+                const c64* u = st + k * (kCE + 1);
+                const c64* v = st + (Ns + j) * (kCE + 1);
+                double re = acc[q].re, im = acc[q].im;
+                for (int e = 0; e < kCE; ++e) {
+                    const c64 a = u[e], b = v[e];
+                    re += a.re * b.re + a.im * b.im;
+                    im += a.re * b.im - a.im * b.re;
+                }
+                acc[q] = c64{re, im};
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxPairs; ++q) {
+        const int p = threadIdx.x + q * blockDim.x;
+        if (p < np) {
+            const int k = p / nc, j = p - k * nc;
+            A[(((long)blk * 9 + d) * Ns + k) * Ns + l0 + j] = acc[q];
+        }
+    }
 }
 
 // w_b[blk] = sum_d A[blk][d] v_b[nbr_d(blk)], one thread per (blk, k) row,
@@ -367,10 +389,26 @@ void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag
 {
     hipLaunchKernelGGL(k_block_gs, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag);
 }
-void launch_little_column64(const Geom& g, const c64* Phi, int Ns, const c64* Y, c64* A, int d, int l, hipStream_t s)
+int little_columns_max(int Ns)
 {
-    hipLaunchKernelGGL(k_little_column, dim3(g.Nb), dim3(kBT), 0, s, g, Phi, Ns, Y, A, d, l);
+    int nc = kMaxPairs * 256 / Ns;
+    return nc < 1 ? 1 : nc;
 }
+
+void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y, int nc, int l0, int d, c64* A,
+                             hipStream_t s)
+{
+    const size_t lds = sizeof(c64) * (Ns + nc) * (kCE + 1);
+    static bool attr = false;
+    if (!attr) {
+        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_little_columns),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(c64) * (64 + 64) * (kCE + 1))));
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_little_columns, dim3(g.Nb), dim3(256), lds, s, g, Phi, Ns, Y, nc, l0, d, A);
+}
+
 template <typename T>
 void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, int nrhs, hipStream_t s)
 {
