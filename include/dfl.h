@@ -105,6 +105,10 @@ typedef struct {
     dfl_prec link_prec;    /* link storage of the SAP block solves: F64, F32 or BF16 two-row */
     dfl_prec sap_prec;     /* arithmetic of the SAP block solves: F64 or F32 */
     dfl_prec little_prec;  /* arithmetic of the little solves inside cycles: F64 or F32 */
+    int little_grid;       /* workgroups of the little solver (0: a quarter of the block
+                              count; at most 128 and the block count) */
+    int little_adapt;      /* 1: inside a cycle, relax the little-solve tolerance in
+                              proportion to the fall of the residue (appendix A.5) */
 } dfl_params;
 
 typedef struct {
@@ -118,8 +122,9 @@ typedef struct {
 } dfl_info;
 
 /* Fill *p with defaults: 4^4 blocks, Ns = 20, ncy = 5, nmr = 4, nkv = 16,
- * n_inviter = 3, maxiter = 1000, tol = 1e-10, little tolerances 1e-6/1e-12,
- * all precisions F64, solver DFL_SAP_GCR; dims are left zero. */
+ * n_inviter = 3, maxiter = 1000, tol = 1e-10, little tolerances 1e-6/1e-12
+ * with adapted precision on, all precisions F64, solver DFL_SAP_GCR; dims are
+ * left zero. */
 void dfl_default_params(dfl_params *p);
 
 /* Create a context for the lattice and parameters in *p on the current HIP

@@ -65,7 +65,7 @@ void free_all(dfl_ctx* c)
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
                     c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
-                    c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf};
+                    c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -75,6 +75,8 @@ void free_all(dfl_ctx* c)
         (void)hipHostFree(c->hact);
     if (c->loss_host)
         (void)hipHostFree(c->loss_host);
+    if (c->htol)
+        (void)hipHostFree(c->htol);
 }
 
 void check_blocks(const int dims[4], const int b[4], const char* what)
@@ -115,6 +117,8 @@ void validate(const dfl_params& p)
         fail(DFL_EINVAL, "little_nkv must be in 1..32");
     if (p.n_inviter < 0 || p.maxiter < 1 || p.little_maxiter < 1 || p.nrhs_max < 1)
         fail(DFL_EINVAL, "n_inviter >= 0, maxiter >= 1, little_maxiter >= 1, nrhs_max >= 1 required");
+    if (p.little_grid < 0)
+        fail(DFL_EINVAL, "little_grid must be >= 0");
     if (p.nrhs_max > kMaxLittleRhs)
         fail(DFL_EINVAL, "nrhs_max must be at most " + std::to_string(kMaxLittleRhs));
     if (!(p.tol > 0.0) || !(p.little_tol_in > 0.0) || !(p.little_tol_out > 0.0))
@@ -387,10 +391,15 @@ struct GcrResult {
 
 using BatchOp = std::function<void(const c64*, c64*, int)>;
 
+// inner_tol(ratio) gives the relative tolerance of the inner little solves
+// for the step when the residues have fallen by `ratio` (the smallest
+// rho_k / rho_cycle-start over the sources still in the cycle) within the
+// cycle; it is written to c->dtol before the step runs.
 std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter, double tol,
                                const std::vector<double>& src_norm, GcrVecs v, const BatchOp& precond,
                                const BatchOp& op, const BatchOp& recompute_residual, double cycle_floor = 0.0,
-                               std::vector<double>* history_ = nullptr)
+                               std::vector<double>* history_ = nullptr,
+                               const std::function<double(double)>& inner_tol = nullptr)
 {
     std::vector<GcrResult> res(nb, GcrResult{DFL_OK, 0, 0, 0.0});
     launch_zero<double>(v.x, n * nb, c->stream);
@@ -434,6 +443,14 @@ std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter,
         while (k < nkv && n_act > 0) {
             c64* xk = v.xi + (long)k * ks;
             c64* ck = v.chi + (long)k * ks;
+            if (inner_tol) {
+                double ratio = 1.0;
+                for (int b = 0; b < nb; ++b)
+                    if (act[b] && rn_cycle[b] > 0.0)
+                        ratio = std::min(ratio, rn[b] / rn_cycle[b]);
+                *c->htol = inner_tol(ratio);
+                HIPCHECK(hipMemcpyAsync(c->dtol, c->htol, sizeof(double), hipMemcpyHostToDevice, c->stream));
+            }
             run_step(c, (long)k * 64 + nb, [&]() {
                 precond(v.r, xk, nb);
                 op(xk, ck, nb);
@@ -526,34 +543,35 @@ std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter,
 // v_b = A^{-1} w_b to ||w_b - A v_b|| <= tol ||w_b|| (eq. (6.1)) for nb little
 // vectors back to back; FP64 in and out. One cooperative launch; iteration
 // counts accumulate in c->lstats.
-void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec prec, int nb = 1)
+void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec prec, int nb = 1,
+                       const double* tol_dev = nullptr)
 {
     const long n = (long)c->g.Nb * c->p.Ns;
     const int Ns = c->p.Ns, nkv = c->p.little_nkv, mi = c->p.little_maxiter;
     if (prec == DFL_F64) {
         ProfScope ps(c, DFL_PROF_LITTLE);
         if (nb == 1)
-            launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, c->At64, w, v, static_cast<c64*>(c->lr),
+            launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, tol_dev, c->At64, w, v, static_cast<c64*>(c->lr),
                                       static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lstats,
-                                      c->lbar_count, c->lbar_gen, c->stream, !c->capturing);
+                                      c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
         else
-            launch_little_gcr_multi<double>(c->g, Ns, nkv, mi, tol, nb, c->At64, w, v, static_cast<c64*>(c->lr),
+            launch_little_gcr_multi<double>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At64, w, v, static_cast<c64*>(c->lr),
                                             static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lfin,
-                                            c->lacoef, c->lstats, c->lbar_count, c->lbar_gen, c->stream,
-                                            !c->capturing);
+                                            c->lacoef, c->lstats, c->lbar_count, c->lbar_gen, c->lgrid,
+                                            c->stream, !c->capturing);
     } else {
         launch_f64_to_f32(w, c->lw32, n * nb, c->stream);
         {
             ProfScope ps(c, DFL_PROF_LITTLE);
             if (nb == 1)
-                launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, c->At32, c->lw32, c->lx32, static_cast<c32*>(c->lr),
+                launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, tol_dev, c->At32, c->lw32, c->lx32, static_cast<c32*>(c->lr),
                                          static_cast<c32*>(c->lxi), static_cast<c32*>(c->lchi), c->lpart, c->lstats,
-                                         c->lbar_count, c->lbar_gen, c->stream, !c->capturing);
+                                         c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
             else
-                launch_little_gcr_multi<float>(c->g, Ns, nkv, mi, tol, nb, c->At32, c->lw32, c->lx32,
+                launch_little_gcr_multi<float>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At32, c->lw32, c->lx32,
                                                static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
                                                static_cast<c32*>(c->lchi), c->lpart, c->lfin, c->lacoef, c->lstats,
-                                               c->lbar_count, c->lbar_gen, c->stream, !c->capturing);
+                                               c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
         }
         launch_f32_to_f64(c->lx32, v, n * nb, c->stream);
     }
@@ -577,7 +595,8 @@ void read_little_stats(dfl_ctx* c, int out[3])
 }
 
 // out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term) for nb fields; out may not alias in
-void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, int nb = 1)
+void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, int nb = 1,
+            const double* tol_dev = nullptr)
 {
     c64* w = static_cast<c64*>(c->lw);
     c64* x = static_cast<c64*>(c->lx);
@@ -585,15 +604,16 @@ void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, int 
         ProfScope ps(c, DFL_PROF_PROJECT);
         launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, nb, c->stream);
     }
-    little_solve_impl(c, w, x, tol, prec, nb);
+    little_solve_impl(c, w, x, tol, prec, nb, tol_dev);
     ProfScope ps(c, DFL_PROF_PROJECT);
     launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, nb, c->stream);
 }
 
 // out = P_L in = in - D coarse(in)   (eq. (3.3)) for nb fields
-void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c64* tmpA, c64* tmpB, int nb = 1)
+void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c64* tmpA, c64* tmpB, int nb = 1,
+              const double* tol_dev = nullptr)
 {
-    coarse(c, in, tmpA, tol, prec, nb);
+    coarse(c, in, tmpA, tol, prec, nb, tol_dev);
     dirac64(c, tmpA, tmpB, c->p.m0, nb);
     launch_sub<double>(in, tmpB, out, c->field_elems * nb, c->stream);
 }
@@ -695,6 +715,8 @@ void dfl_default_params(dfl_params* p)
     p->link_prec = DFL_F64;
     p->sap_prec = DFL_F64;
     p->little_prec = DFL_F64;
+    p->little_grid = 0;
+    p->little_adapt = 1;
 }
 
 const char* dfl_last_error(void) { return dfl::g_last_error.c_str(); }
@@ -796,7 +818,7 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->lt = alloc_dev<c64>(c, N);
         c->lw32 = alloc_dev<c32>(c, R * N);
         c->lx32 = alloc_dev<c32>(c, R * N);
-        c->lgrid = little_gcr_grid(c->g);
+        c->lgrid = little_gcr_grid(c->g, p->little_grid);
         size_t part = little_gcr_partial_doubles(c->lgrid);
         if (R > 1) {
             size_t nfin = 0, nac = 0;
@@ -812,6 +834,8 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->dscal = alloc_dev<double>(c, S_TOTAL * R);
         c->dflag = alloc_dev<int>(c, 4);
         c->dact = alloc_dev<int>(c, kMaxLittleRhs);
+        c->dtol = alloc_dev<double>(c, 2);
+        HIPCHECK(hipHostMalloc((void**)&c->htol, sizeof(double) * 2, hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&c->hscal, sizeof(double) * S_TOTAL * R, hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&c->hact, sizeof(int) * kMaxLittleRhs, hipHostMallocDefault));
         HIPCHECK(hipMemsetAsync(c->dscal, 0, sizeof(double) * S_TOTAL * R, c->stream));
@@ -1193,10 +1217,11 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
         else
             launch_copy<double>(r, x, F * n_b, c->stream);
     };
+    const bool adapt = deflate && c->p.little_adapt;
     auto op = [&](const c64* x, c64* y, int n_b) {
         if (deflate) {
             dirac64(c, x, c->t3, m0, n_b);
-            apply_PL(c, c->t3, y, c->p.little_tol_in, lp, c->t1, c->t2, n_b);
+            apply_PL(c, c->t3, y, c->p.little_tol_in, lp, c->t1, c->t2, n_b, adapt ? c->dtol : nullptr);
         } else {
             dirac64(c, x, y, m0, n_b);
         }
@@ -1216,8 +1241,14 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
     // ended early and the residue recomputed (appendix A.5).
     const double cycle_floor = deflate ? 10.0 * c->p.little_tol_in : 0.0;
     c->history.clear();
+    // Adapted precision inside a cycle (appendix A.5): the residue, hence the
+    // field the projector acts on, has fallen by `ratio` since the cycle
+    // began, so a relative little-solve tolerance little_tol_in / ratio keeps
+    // the absolute error of the projection fixed (capped at 1e-2).
+    auto inner_tol = [&](double ratio) { return std::min(1e-2, c->p.little_tol_in / std::max(ratio, 1e-300)); };
     std::vector<GcrResult> res = gcr_run(c, F, nb, c->p.nkv, c->p.maxiter, c->p.tol, eta_n, v, precond, op,
-                                         recompute, cycle_floor, &c->history);
+                                         recompute, cycle_floor, &c->history,
+                                         adapt ? std::function<double(double)>(inner_tol) : nullptr);
     // final solutions: psi = acc + Phi A^-1 Phi^+ (eta - D acc)   (eq. (3.10) with P_R)
     if (deflate) {
         dirac64(c, c->acc, c->t1, m0, nb);

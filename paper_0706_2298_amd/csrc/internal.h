@@ -118,6 +118,8 @@ struct dfl_ctx {
     double* hscal = nullptr;     // pinned host mirror
     int* dflag = nullptr;        // device status flag
     int* dact = nullptr;         // per-RHS active mask of the batched GCR
+    double* dtol = nullptr;      // relative tolerance of the inner little solves (device)
+    double* htol = nullptr;      // pinned host mirror
     int* hact = nullptr;         // pinned host mirror
     size_t alloc_bytes = 0;
     std::vector<double> history;  // outer GCR residues of the last solve
@@ -259,27 +261,31 @@ constexpr int kNetMaxCout = 576;   // output channels (input-gradient staging bo
 constexpr int kLossMaxN = 32;      // fields and targets of the deficit loss
 
 // ---------------------------------------------------------------- little.hip
-int little_gcr_grid(const Geom& g);
+// workgroups of the little GCR: requested (0: Nb / 4), clamped to 1..min(Nb, kLittleMaxGrid)
+int little_gcr_grid(const Geom& g, int requested);
 size_t little_gcr_partial_doubles(int grid_size);
-// v = A^{-1} w by GCR to ||w - A v|| <= tol ||w|| in one cooperative launch;
+// v = A^{-1} w by GCR to ||w - A v|| <= tol ||w|| in one cooperative launch
+// (tol read from device memory at tol_dev when that is not null);
 // r, xi, chi are workspaces; stats accumulates [iterations, solves, failed]
 // cooperative = false launches it as an ordinary kernel (for graph capture):
 // the grid (at most kLittleMaxGrid workgroups, one per compute unit) is then
 // resident by construction when nothing else runs on the device, and the
 // barriers' bounded polling reports a failure rather than hang otherwise.
 template <typename T>
-void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
+void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev,
+                       const cpx<T>* At, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
-                       unsigned long long* bar_gen, hipStream_t s, bool cooperative = true);
+                       unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative = true);
 
 // The same for nrhs systems at once (nrhs <= kMaxLittleRhs): w, x, r hold
 // nrhs little vectors back to back, xi and chi nkv * nrhs. Sizes of part,
 // fin and acoef (doubles) come from little_gcr_multi_doubles.
 size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef);
 template <typename T>
-void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
+void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, int nrhs,
+                             const cpx<T>* At,
                              const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
-                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s,
-                             bool cooperative = true);
+                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, int grid,
+                             hipStream_t s, bool cooperative = true);
 
 }  // namespace dfl

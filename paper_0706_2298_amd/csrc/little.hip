@@ -41,6 +41,7 @@ template <typename T> struct LittleArgs {
     Geom g;
     int Ns, nkv, maxiter;
     double tol2;           // stop at ||r||^2 <= tol2 * ||w||^2
+    const double* tol_dev; // if set: the relative tolerance is read from here at entry
     const cpx<T>* At;      // [Nb][9][Ns(l)][Ns(k)]: transposed blocks
     const cpx<T>* w;
     cpx<T>* x;
@@ -264,6 +265,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
     __shared__ double lds[2 * (9 * 64 > LT ? 9 * 64 : LT)];
 
     LittleCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
+    const double tol2 = a.tol_dev ? (*a.tol_dev) * (*a.tol_dev) : a.tol2;
     unsigned long long bar_target = 0;
     if (c.t == 0)
         bar_target = __hip_atomic_load(a.bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -306,7 +308,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             if (c.t == 0)
                 rn2_s = red[0];
             __syncthreads();
-            if (k > 0 && rn2_s <= a.tol2 * wn2)
+            if (k > 0 && rn2_s <= tol2 * wn2)
                 break;  // converged with k directions
             apply_rows(c, xk, ck, lds);
             // one Gram-Schmidt pass: everything needed for chi_k, c_k and the new r
@@ -431,7 +433,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
         if (c.t == 0)
             rn2_s = red[0];
         __syncthreads();
-        converged = rn2_s <= a.tol2 * wn2;
+        converged = rn2_s <= tol2 * wn2;
     }
     if (c.g == 0 && c.t == 0) {
         atomicAdd(&a.stats[0], iters);
@@ -458,6 +460,7 @@ template <typename T> struct LittleMultiArgs {
     Geom g;
     int Ns, nkv, maxiter, nrhs;
     double tol2;
+    const double* tol_dev;
     const cpx<T>* At;
     const cpx<T>* w;
     cpx<T>* x;
@@ -681,6 +684,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
     __shared__ double lds[2 * LT];
 
     MultiCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
+    const double tol2 = a.tol_dev ? (*a.tol_dev) * (*a.tol_dev) : a.tol2;
     const int nr = a.nrhs;
     const long N = c.N;
     unsigned long long bar_target = 0;
@@ -745,7 +749,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
                 int n = 0;
                 for (int bi = 0; bi < nl; ++bi) {
                     const int b = list[bi];
-                    if (k > 0 && rn2[b] <= a.tol2 * wn2[b])
+                    if (k > 0 && rn2[b] <= tol2 * wn2[b])
                         act[b] = 0;  // converged with k directions
                     else
                         list[n++] = b;
@@ -936,7 +940,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
         multi_reduce_real(a.part, nr, c.G, SR, list, nx, rn2);
         if (c.t < nx) {
             const int b = list[c.t];
-            conv[b] = rn2[b] <= a.tol2 * wn2[b];
+            conv[b] = rn2[b] <= tol2 * wn2[b];
             if (conv[b])
                 stop[b] = 1;
         }
@@ -956,7 +960,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
 }
 
 template <typename T>
-void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
+void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At, const cpx<T>* w,
                  cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                  unsigned long long* bar_gen, int grid_size, hipStream_t s, bool cooperative)
 {
@@ -966,6 +970,7 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
     a.nkv = nkv;
     a.maxiter = maxiter;
     a.tol2 = tol * tol;
+    a.tol_dev = tol_dev;
     a.At = At;
     a.w = w;
     a.x = x;
@@ -988,14 +993,17 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
 
 }  // namespace
 
-// The barrier cost grows with the workgroup count (about 3.4 us at 128 on
-// MI355X), the apply's bandwidth with it: two blocks per workgroup, at most
-// kLittleMaxGrid workgroups.
-int little_gcr_grid(const Geom& g)
+// The barrier and reduction costs grow with the workgroup count (a barrier
+// takes about 3.4 us at 128 workgroups on MI355X), the apply's bandwidth with
+// it. Default four blocks per workgroup (one round of the 1024 threads in the
+// apply for Ns up to 28), at most kLittleMaxGrid workgroups.
+int little_gcr_grid(const Geom& g, int requested)
 {
-    int G = g.Nb / 2;
+    int G = requested > 0 ? requested : g.Nb / 4;
     if (G > kLittleMaxGrid)
         G = kLittleMaxGrid;
+    if (G > g.Nb)
+        G = g.Nb;
     if (G < 1)
         G = 1;
     return G;
@@ -1004,19 +1012,21 @@ int little_gcr_grid(const Geom& g)
 size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * grid_size * 2; }
 
 template <typename T>
-void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const cpx<T>* At, const cpx<T>* w,
+void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,
+                       const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
-                       unsigned long long* bar_gen, hipStream_t s, bool cooperative)
+                       unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative)
 {
-    launch_impl<T>(g, Ns, nkv, maxiter, tol, At, w, x, r, xi, chi, part, stats, bar_count, bar_gen,
-                   little_gcr_grid(g), s, cooperative);
+    launch_impl<T>(g, Ns, nkv, maxiter, tol, tol_dev, At, w, x, r, xi, chi, part, stats, bar_count, bar_gen, grid, s,
+                   cooperative);
 }
 
 template <typename T>
-void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, int nrhs, const cpx<T>* At,
+void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, int nrhs,
+                             const cpx<T>* At,
                              const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
-                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, hipStream_t s,
-                             bool cooperative)
+                             double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, int grid,
+                             hipStream_t s, bool cooperative)
 {
     LittleMultiArgs<T> a;
     a.g = g;
@@ -1025,6 +1035,7 @@ void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double
     a.maxiter = maxiter;
     a.nrhs = nrhs;
     a.tol2 = tol * tol;
+    a.tol_dev = tol_dev;
     a.At = At;
     a.w = w;
     a.x = x;
@@ -1038,13 +1049,13 @@ void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double
     a.bar_count = bar_count;
     a.bar_gen = bar_gen;
     if (!cooperative) {
-        hipLaunchKernelGGL(k_little_gcr_multi<T>, dim3(little_gcr_grid(g)), dim3(LT), 0, s, a);
+        hipLaunchKernelGGL(k_little_gcr_multi<T>, dim3(grid), dim3(LT), 0, s, a);
         HIPCHECK(hipGetLastError());
         return;
     }
     void* args[] = {&a};
     HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_little_gcr_multi<T>),
-                                        dim3(little_gcr_grid(g)), dim3(LT), args, 0, s));
+                                        dim3(grid), dim3(LT), args, 0, s));
 }
 
 size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef)
@@ -1055,16 +1066,17 @@ size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* ac
 }
 
 #define INST_MULTI(T)                                                                                               \
-    template void launch_little_gcr_multi<T>(const Geom&, int, int, int, double, int, const cpx<T>*, const cpx<T>*, \
+    template void launch_little_gcr_multi<T>(const Geom&, int, int, int, double, const double*, int, const cpx<T>*,  \
+                                             const cpx<T>*,                                                         \
                                              cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*, double*, double*, double*, int*,    \
-                                             unsigned*, unsigned long long*, hipStream_t, bool);
+                                             unsigned*, unsigned long long*, int, hipStream_t, bool);
 INST_MULTI(double)
 INST_MULTI(float)
 #undef INST_MULTI
 
-template void launch_little_gcr<double>(const Geom&, int, int, int, double, const c64*, const c64*, c64*, c64*, c64*,
-                                        c64*, double*, int*, unsigned*, unsigned long long*, hipStream_t, bool);
-template void launch_little_gcr<float>(const Geom&, int, int, int, double, const c32*, const c32*, c32*, c32*, c32*,
-                                       c32*, double*, int*, unsigned*, unsigned long long*, hipStream_t, bool);
+template void launch_little_gcr<double>(const Geom&, int, int, int, double, const double*, const c64*, const c64*, c64*, c64*, c64*,
+                                        c64*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
+template void launch_little_gcr<float>(const Geom&, int, int, int, double, const double*, const c32*, const c32*, c32*, c32*, c32*,
+                                       c32*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
 
 }  // namespace dfl
