@@ -109,6 +109,9 @@ typedef struct {
                               count; at most 128 and the block count) */
     int little_adapt;      /* 1: inside a cycle, relax the little-solve tolerance in
                               proportion to the fall of the residue (appendix A.5) */
+    int little_eo;         /* 1: single-source little solves run GCR on the even-odd
+                              reduced system (appendix A.2), falling back to A when a
+                              diagonal block is not safely invertible */
 } dfl_params;
 
 typedef struct {
@@ -123,8 +126,8 @@ typedef struct {
 
 /* Fill *p with defaults: 4^4 blocks, Ns = 20, ncy = 5, nmr = 4, nkv = 16,
  * n_inviter = 3, maxiter = 1000, tol = 1e-10, little tolerances 1e-6/1e-12
- * with adapted precision on, all precisions F64, solver DFL_SAP_GCR; dims are
- * left zero. */
+ * with adapted precision and even-odd little solves on, all precisions F64,
+ * solver DFL_SAP_GCR; dims are left zero. */
 void dfl_default_params(dfl_params *p);
 
 /* Create a context for the lattice and parameters in *p on the current HIP

@@ -31,7 +31,7 @@ class Params(ctypes.Structure):
         ("m0", ctypes.c_double), ("m0_setup", ctypes.c_double), ("tol", ctypes.c_double),
         ("little_tol_in", ctypes.c_double), ("little_tol_out", ctypes.c_double),
         ("link_prec", ctypes.c_int), ("sap_prec", ctypes.c_int), ("little_prec", ctypes.c_int),
-        ("little_grid", ctypes.c_int), ("little_adapt", ctypes.c_int),
+        ("little_grid", ctypes.c_int), ("little_adapt", ctypes.c_int), ("little_eo", ctypes.c_int),
     ]
 
 

@@ -65,7 +65,7 @@ void free_all(dfl_ctx* c)
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
                     c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
-                    c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol};
+                    c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol, c->Mt64, c->Mt32, c->lw1, c->lw2};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -551,7 +551,8 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
     if (prec == DFL_F64) {
         ProfScope ps(c, DFL_PROF_LITTLE);
         if (nb == 1)
-            launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, tol_dev, c->At64, w, v, static_cast<c64*>(c->lr),
+            launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, tol_dev, c->At64, c->eo_ok ? c->Mt64 : nullptr,
+                                      static_cast<c64*>(c->lw1), static_cast<c64*>(c->lw2), w, v, static_cast<c64*>(c->lr),
                                       static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lstats,
                                       c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
         else
@@ -564,7 +565,8 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
         {
             ProfScope ps(c, DFL_PROF_LITTLE);
             if (nb == 1)
-                launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, tol_dev, c->At32, c->lw32, c->lx32, static_cast<c32*>(c->lr),
+                launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, tol_dev, c->At32, c->eo_ok ? c->Mt32 : nullptr,
+                                         static_cast<c32*>(c->lw1), static_cast<c32*>(c->lw2), c->lw32, c->lx32, static_cast<c32*>(c->lr),
                                          static_cast<c32*>(c->lxi), static_cast<c32*>(c->lchi), c->lpart, c->lstats,
                                          c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
             else
@@ -616,6 +618,23 @@ void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c6
     coarse(c, in, tmpA, tol, prec, nb, tol_dev);
     dirac64(c, tmpA, tmpB, c->p.m0, nb);
     launch_sub<double>(in, tmpB, out, c->field_elems * nb, c->stream);
+}
+
+// Even-odd matrices of the little operator (appendix A.2) after A changed;
+// the plain system is kept if a diagonal block is not safely invertible or
+// the block lists do not fit. Synchronises.
+void prepare_eo(dfl_ctx* c)
+{
+    c->eo_ok = false;
+    if (!c->p.little_eo || !c->Mt64 || !little_eo_fits(c->g, c->lgrid))
+        return;
+    HIPCHECK(hipMemsetAsync(c->dflag + 1, 0, sizeof(int), c->stream));
+    launch_little_eo_prep(c->g, c->A64, c->p.Ns, c->Mt64, c->Mt32, c->dflag + 1, c->stream);
+    HIPCHECK(hipGetLastError());
+    int f = 0;
+    HIPCHECK(hipMemcpyAsync(&f, c->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    c->eo_ok = (f & 1) == 0;
 }
 
 // Relaxed inverse iteration of eq. (5.1) on n native FP64 fields in place:
@@ -717,6 +736,7 @@ void dfl_default_params(dfl_params* p)
     p->little_prec = DFL_F64;
     p->little_grid = 0;
     p->little_adapt = 1;
+    p->little_eo = 1;
 }
 
 const char* dfl_last_error(void) { return dfl::g_last_error.c_str(); }
@@ -796,6 +816,12 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->A32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->At64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->At32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
+        if (p->little_eo) {
+            c->Mt64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
+            c->Mt32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
+            c->lw1 = alloc_dev<c64>(c, N);
+            c->lw2 = alloc_dev<c64>(c, N);
+        }
         const long R = p->nrhs_max;
         c->xi = alloc_dev<c64>(c, (size_t)p->nkv * R * F);
         c->chi = alloc_dev<c64>(c, (size_t)p->nkv * R * F);
@@ -920,6 +946,7 @@ int dfl_set_mass(dfl_ctx* c, double m0)
         launch_little_shift(c->g, c->A64, c->p.Ns, m0 - c->m0_A, c->stream);
         launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, c->p.Ns, c->stream);
         c->m0_A = m0;
+        prepare_eo(c);
     }
     API_END
 }
@@ -1053,6 +1080,7 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     }
     launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);
     (void)nA;
+    c->eo_ok = false;
     c->m0_A = c->p.m0;
     int flag[4];
     HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
@@ -1061,6 +1089,7 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
         fail(DFL_ENONFINITE, "non-finite entries in the start fields");
     if (flag[0] & 2)
         fail(DFL_ESINGULAR, "block Gram-Schmidt lost rank: the start fields are linearly dependent on a block");
+    prepare_eo(c);
     c->have_subspace = true;
     API_END
 }

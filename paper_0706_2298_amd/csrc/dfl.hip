@@ -340,6 +340,109 @@ __global__ __launch_bounds__(256) void k_little_apply_mfma(Geom g, const c32* __
     }
 }
 
+// Even-odd preparation for one block per workgroup: Gauss-Jordan inversion of
+// the diagonal block A[blk][0] with partial pivoting in LDS ([Ns][2 Ns]
+// augmented matrix), then M_d = D^-1 A[blk][d], d = 1..8. Output transposed:
+// Mt[blk][0][l][k] = D^-1[k][l], Mt[blk][d][l][k] = M_d[k][l].
+__global__ __launch_bounds__(256) void k_little_eo_prep(Geom g, const c64* __restrict__ A, int Ns,
+                                                        c64* __restrict__ Mt64, c32* __restrict__ Mt32,
+                                                        int* __restrict__ flag)
+{
+    extern __shared__ c64 aug[];  // [Ns][2 Ns], then fcol[Ns]
+    c64* fcol = aug + 2 * Ns * Ns;
+    __shared__ double sh[16];
+    __shared__ int piv_s;
+    const int blk = blockIdx.x;
+    const int W = 2 * Ns;
+    const c64* D = A + (long)blk * 9 * Ns * Ns;
+    double amax = 0.0;
+    for (int q = threadIdx.x; q < Ns * W; q += blockDim.x) {
+        const int i = q / W, j = q % W;
+        c64 v{0.0, 0.0};
+        if (j < Ns) {
+            v = D[i * Ns + j];
+            amax = fmax(amax, fabs(v.re) + fabs(v.im));
+        } else if (j - Ns == i) {
+            v = c64{1.0, 0.0};
+        }
+        aug[q] = v;
+    }
+    // largest |re| + |im| of the block (shuffles, then LDS)
+    for (int off = 32; off >= 1; off >>= 1)
+        amax = fmax(amax, __shfl_xor(amax, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    amax = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q)
+        amax = fmax(amax, sh[q]);
+    for (int col = 0; col < Ns; ++col) {
+        if (threadIdx.x == 0) {
+            int p = col;
+            double best = -1.0;
+            for (int i = col; i < Ns; ++i) {
+                const c64 v = aug[i * W + col];
+                const double m = fabs(v.re) + fabs(v.im);
+                if (m > best) {
+                    best = m;
+                    p = i;
+                }
+            }
+            if (!(best >= 1e-8 * amax))
+                atomicOr(flag, 1);
+            piv_s = p;
+        }
+        __syncthreads();
+        const int p = piv_s;
+        if (p != col)
+            for (int j = threadIdx.x; j < W; j += blockDim.x) {
+                const c64 t = aug[col * W + j];
+                aug[col * W + j] = aug[p * W + j];
+                aug[p * W + j] = t;
+            }
+        __syncthreads();
+        const c64 pv = aug[col * W + col];
+        const double den = pv.re * pv.re + pv.im * pv.im;
+        const c64 inv = den > 0.0 ? c64{pv.re / den, -pv.im / den} : c64{0.0, 0.0};
+        __syncthreads();
+        for (int j = threadIdx.x; j < W; j += blockDim.x)
+            aug[col * W + j] = aug[col * W + j] * inv;
+        __syncthreads();
+        for (int i = threadIdx.x; i < Ns; i += blockDim.x)
+            fcol[i] = aug[i * W + col];
+        __syncthreads();
+        for (int q = threadIdx.x; q < Ns * W; q += blockDim.x) {
+            const int i = q / W, j = q % W;
+            if (i != col)
+                aug[q] -= fcol[i] * aug[col * W + j];
+        }
+        __syncthreads();
+    }
+    // D^-1 = aug[:, Ns:2Ns]
+    const long base = (long)blk * 9 * Ns * Ns;
+    for (int q = threadIdx.x; q < Ns * Ns; q += blockDim.x) {
+        const int k = q / Ns, l = q % Ns;
+        const c64 v = aug[k * W + Ns + l];
+        Mt64[base + (long)l * Ns + k] = v;
+        Mt32[base + (long)l * Ns + k] = c32{(float)v.re, (float)v.im};
+    }
+    for (int q = threadIdx.x; q < 8 * Ns * Ns; q += blockDim.x) {
+        const int d = 1 + q / (Ns * Ns);
+        const int rem = q % (Ns * Ns);
+        const int k = rem / Ns, l = rem % Ns;
+        const c64* Ad = A + ((long)blk * 9 + d) * Ns * Ns;
+        double re = 0.0, im = 0.0;
+        for (int m = 0; m < Ns; ++m) {
+            const c64 a = aug[k * W + Ns + m], b = Ad[(long)m * Ns + l];
+            re += a.re * b.re - a.im * b.im;
+            im += a.re * b.im + a.im * b.re;
+        }
+        const long o = base + (long)d * Ns * Ns + (long)l * Ns + k;
+        Mt64[o] = c64{re, im};
+        Mt32[o] = c32{(float)re, (float)im};
+    }
+}
+
 __global__ void k_little_shift(Geom g, c64* A, int Ns, double dm)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -429,6 +532,19 @@ void launch_little_apply_mfma(const Geom& g, const c32* At, int Ns, const c32* v
         attr_set = true;
     }
     hipLaunchKernelGGL(k_little_apply_mfma, dim3(g.Nb), dim3(256), lds, s, g, At, Ns, v, w, nrhs);
+}
+
+void launch_little_eo_prep(const Geom& g, const c64* A, int Ns, c64* Mt64, c32* Mt32, int* flag, hipStream_t s)
+{
+    const size_t lds = sizeof(c64) * (2 * (size_t)Ns * Ns + Ns);
+    static bool attr = false;
+    if (!attr) {
+        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_little_eo_prep),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(c64) * (2 * 64 * 64 + 64))));
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_little_eo_prep, dim3(g.Nb), dim3(256), lds, s, g, A, Ns, Mt64, Mt32, flag);
 }
 
 void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s)

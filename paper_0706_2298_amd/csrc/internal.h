@@ -80,6 +80,9 @@ struct dfl_ctx {
     dfl::c32* A32 = nullptr;   // FP32 copy, same layout
     dfl::c64* At64 = nullptr;  // blocks transposed, [Nb][9][l][k] (little GCR kernel)
     dfl::c32* At32 = nullptr;
+    dfl::c64* Mt64 = nullptr;  // even-odd little system: D^-1 and D^-1 A_d, transposed blocks
+    dfl::c32* Mt32 = nullptr;
+    bool eo_ok = false;        // Mt is current and every diagonal block was safely invertible
     double m0_A = 0.0;
     bool have_subspace = false;
 
@@ -103,6 +106,8 @@ struct dfl_ctx {
     void* lx = nullptr;
     void* lw = nullptr;
     void* lt = nullptr;
+    void* lw1 = nullptr;       // even-odd workspaces of the little GCR
+    void* lw2 = nullptr;
     dfl::c32* lw32 = nullptr;  // FP32 little source and solution (mixed precision)
     dfl::c32* lx32 = nullptr;
     double* lpart = nullptr;   // partial sums of the cooperative little GCR
@@ -236,6 +241,12 @@ void launch_little_apply_mfma(const Geom& g, const c32* At, int Ns, const c32* v
 // A[blk][0][k][k] += dm  (mass shift)
 void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s);
 void launch_c64_to_c32(const c64* a, c32* b, long n, hipStream_t s);
+// Even-odd preparation (appendix A.2): per block D^-1 of the diagonal block by
+// Gauss-Jordan elimination with partial pivoting, and M_d = D^-1 A_d for the
+// eight neighbour terms; stored transposed like At: Mt[blk][0] = D^-1,
+// Mt[blk][d] = M_d. flag |= 1 when a pivot is below 1e-8 of the block's
+// largest entry (the caller then keeps the plain system).
+void launch_little_eo_prep(const Geom& g, const c64* A, int Ns, c64* Mt64, c32* Mt32, int* flag, hipStream_t s);
 // A32 = A, At64 = At32 = A with every Ns x Ns block transposed
 void launch_little_copies(const c64* A, c32* A32, c64* At64, c32* At32, long nblocks, int Ns, hipStream_t s);
 
@@ -264,16 +275,21 @@ constexpr int kLossMaxN = 32;      // fields and targets of the deficit loss
 // workgroups of the little GCR: requested (0: Nb / 4), clamped to 1..min(Nb, kLittleMaxGrid)
 int little_gcr_grid(const Geom& g, int requested);
 size_t little_gcr_partial_doubles(int grid_size);
+// whether the even-odd solver's per-workgroup block lists fit for this grid
+bool little_eo_fits(const Geom& g, int grid);
 // v = A^{-1} w by GCR to ||w - A v|| <= tol ||w|| in one cooperative launch
 // (tol read from device memory at tol_dev when that is not null);
 // r, xi, chi are workspaces; stats accumulates [iterations, solves, failed]
+// With Mt non-null the GCR runs on the even-odd reduced system (appendix
+// A.2) using the matrices of launch_little_eo_prep and the workspaces w1, w2
+// (N entries each); otherwise on A itself.
 // cooperative = false launches it as an ordinary kernel (for graph capture):
 // the grid (at most kLittleMaxGrid workgroups, one per compute unit) is then
 // resident by construction when nothing else runs on the device, and the
 // barriers' bounded polling reports a failure rather than hang otherwise.
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev,
-                       const cpx<T>* At, const cpx<T>* w,
+                       const cpx<T>* At, const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                        unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative = true);
 

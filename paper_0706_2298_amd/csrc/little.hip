@@ -43,11 +43,14 @@ template <typename T> struct LittleArgs {
     double tol2;           // stop at ||r||^2 <= tol2 * ||w||^2
     const double* tol_dev; // if set: the relative tolerance is read from here at entry
     const cpx<T>* At;      // [Nb][9][Ns(l)][Ns(k)]: transposed blocks
+    const cpx<T>* Mt;      // even-odd: [Nb][0] = D^-1, [Nb][d] = D^-1 A_d, transposed likewise
     const cpx<T>* w;
     cpx<T>* x;
     cpx<T>* r;
     cpx<T>* xi;            // nkv * N
     cpx<T>* chi;           // nkv * N
+    cpx<T>* w1;            // even-odd workspaces (N each)
+    cpx<T>* w2;
     double* part;          // NSLOT * G complex partial sums
     int* stats;            // [0] += iterations, [1] += solves, [2] |= 1 not converged, |= 4 barrier timeout
     unsigned* bar_count;   // grid barrier: arrivals (0 between barriers)
@@ -99,16 +102,52 @@ __device__ inline double2 cfma_conj(double2 acc, double ar, double ai, double br
     return acc;
 }
 
+constexpr int kMaxOwned = 2048;  // blocks one workgroup of the even-odd solver may own
+
+// colour (sum of block coordinates mod 2) of block blk
+__device__ inline int block_colour(const Geom& g, int blk)
+{
+    int sum = 0, rest = blk;
+    for (int mu = 3; mu >= 0; --mu) {
+        sum += rest % g.nb[mu];
+        rest /= g.nb[mu];
+    }
+    return sum & 1;
+}
+
+__device__ inline int nbr_block(const Geom& g, int blk, int d)
+{
+    if (d == 0)
+        return blk;
+    const int mu = (d - 1) >> 1;
+    int rest = blk;
+    for (int nu = 3; nu > mu; --nu)
+        rest /= g.nb[nu];
+    const int n_mu = rest % g.nb[mu];
+    int nn = n_mu + ((d & 1) ? 1 : -1);
+    if (nn < 0)
+        nn += g.nb[mu];
+    if (nn >= g.nb[mu])
+        nn -= g.nb[mu];
+    return blk + (nn - n_mu) * g.bstr[mu];
+}
+
+// The workgroup's view: its vector entries are those of the blocks in vb
+// (all owned blocks g, g + G, ... when vb is null).
 template <typename T> struct LittleCtx {
     const LittleArgs<T>& a;
-    int G, g, t, nbg, R;
+    int G, g, t;
     long N;
+    const int* vb;
+    int nvb;
+    __device__ int block(int i) const { return vb ? vb[i] : g + i * G; }
     __device__ long entry(int e) const
     {
         int i = e / a.Ns;
         int k = e - i * a.Ns;
-        return (long)(g + i * G) * a.Ns + k;
+        return (long)block(i) * a.Ns + k;
     }
+    __device__ int R() const { return nvb * a.Ns; }
 };
 
 // reduce slots [s0, s0 + ns) over the G workgroups into red (complex), identically everywhere
@@ -131,48 +170,38 @@ __device__ inline void reduce_slots(const double* __restrict__ part, int G, int 
     __syncthreads();
 }
 
-// y = A v on the rows this workgroup owns. Task (blk, d, k) forms the
-// d-th neighbour term of row k of block blk (Ns multiply-adds over l, reading
-// At[blk][d][l][k] coalesced in k); the nine terms of a row are then summed
-// from LDS in a fixed order. Blocks are processed bpr = max(1, LT / (9 Ns))
-// at a time. lds holds 2 * max(LT, 9 * 64) doubles.
+// y_blk = alpha s_blk + beta sum_{d0 <= d < d1} Mat[blk][d] u_{nbr_d(blk)} for
+// the listed blocks (list null: the owned blocks g + i G, i < nlist). Mat is
+// stored transposed, Mat[blk][d][l][k] = (block d of blk)[k][l]. Task
+// (block, d, k) forms one term of row k (Ns multiply-adds over l, reading Mat
+// coalesced in k); the terms of a row are summed from LDS in a fixed order.
+// Blocks are processed LT / ((d1 - d0) Ns) at a time; lds holds 2 LT doubles.
 template <typename T>
-__device__ inline void apply_rows(const LittleCtx<T>& c, const cpx<T>* __restrict__ v, cpx<T>* __restrict__ y,
-                                  double* lds)
+__device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int nlist, const cpx<T>* __restrict__ Mat,
+                                    int d0, int d1, const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ s,
+                                    double alpha, double beta, cpx<T>* __restrict__ y, double* lds)
 {
     const Geom& g = c.a.g;
     const int Ns = c.a.Ns;
-    const int per = 9 * Ns;
+    const int nd = d1 - d0;
+    const int per = nd * Ns;
     const int bpr = per <= LT ? LT / per : 1;
-    for (int i0 = 0; i0 < c.nbg; i0 += bpr) {
-        for (int task0 = 0; task0 < bpr * per; task0 += LT) {
-            const int task = task0 + c.t;
+    for (int i0 = 0; i0 < nlist; i0 += bpr) {
+        {
+            const int task = c.t;
             const int ib = task / per;
             const int rem = task - ib * per;
-            const int d = rem / Ns;
-            const int k = rem - d * Ns;
-            if (ib < bpr && i0 + ib < c.nbg) {
-                const int blk = c.g + (i0 + ib) * c.G;
-                int nbr = blk;
-                if (d > 0) {
-                    const int mu = (d - 1) >> 1;
-                    int rest = blk;
-                    for (int nu = 3; nu > mu; --nu)
-                        rest /= g.nb[nu];
-                    const int n_mu = rest % g.nb[mu];
-                    int nn = n_mu + ((d & 1) ? 1 : -1);
-                    if (nn < 0)
-                        nn += g.nb[mu];
-                    if (nn >= g.nb[mu])
-                        nn -= g.nb[mu];
-                    nbr = blk + (nn - n_mu) * g.bstr[mu];
-                }
-                const cpx<T>* At = c.a.At + ((long)blk * 9 + d) * Ns * Ns + k;
-                const cpx<T>* vv = v + (long)nbr * Ns;
+            const int d = d0 + rem / Ns;
+            const int k = rem - (d - d0) * Ns;
+            if (ib < bpr && i0 + ib < nlist) {
+                const int blk = list ? list[i0 + ib] : c.g + (i0 + ib) * c.G;
+                const int nbr = nbr_block(g, blk, d);
+                const cpx<T>* M = Mat + ((long)blk * 9 + d) * Ns * Ns + k;
+                const cpx<T>* vv = u + (long)nbr * Ns;
                 double re = 0.0, im = 0.0;
 #pragma unroll 20
                 for (int l = 0; l < Ns; ++l) {
-                    cpx<T> p = At[(long)l * Ns];
+                    cpx<T> p = M[(long)l * Ns];
                     cpx<T> q = vv[l];
                     re += (double)p.re * (double)q.re - (double)p.im * (double)q.im;
                     im += (double)p.re * (double)q.im + (double)p.im * (double)q.re;
@@ -184,26 +213,33 @@ __device__ inline void apply_rows(const LittleCtx<T>& c, const cpx<T>* __restric
         __syncthreads();
         for (int q = c.t; q < bpr * Ns; q += LT) {
             const int jb = q / Ns, kk = q - jb * Ns;
-            if (i0 + jb < c.nbg) {
+            if (i0 + jb < nlist) {
                 double sr = 0.0, si = 0.0;
-                for (int dd = 0; dd < 9; ++dd) {
+                for (int dd = 0; dd < nd; ++dd) {
                     sr += lds[2 * (jb * per + dd * Ns + kk)];
                     si += lds[2 * (jb * per + dd * Ns + kk) + 1];
                 }
-                const int blk = c.g + (i0 + jb) * c.G;
-                y[(long)blk * Ns + kk] = cpx<T>{(T)sr, (T)si};
+                const int blk = list ? list[i0 + jb] : c.g + (i0 + jb) * c.G;
+                const long i = (long)blk * Ns + kk;
+                double yr = beta * sr, yi = beta * si;
+                if (alpha != 0.0) {
+                    yr += alpha * (double)s[i].re;
+                    yi += alpha * (double)s[i].im;
+                }
+                y[i] = cpx<T>{(T)yr, (T)yi};
             }
         }
         __syncthreads();
     }
 }
 
-// ||v||^2 over the owned entries -> part[slot][g] (workgroup reduction)
+// ||v||^2 over the workgroup's vector entries -> part[slot][g]
 template <typename T>
 __device__ inline void partial_norm2(const LittleCtx<T>& c, const cpx<T>* __restrict__ v, int slot, double* sh)
 {
     double s = 0.0;
-    for (int e = c.t; e < c.R; e += LT) {
+    const int R = c.R();
+    for (int e = c.t; e < R; e += LT) {
         cpx<T> z = v[c.entry(e)];
         s += (double)z.re * (double)z.re + (double)z.im * (double)z.im;
     }
@@ -214,15 +250,16 @@ __device__ inline void partial_norm2(const LittleCtx<T>& c, const cpx<T>* __rest
     }
 }
 
-// Partial sums of one Gram-Schmidt pass over the owned entries, one wavefront
-// per slot: (chi_j, y) and (chi_j, r) for j < k, ||y||^2 and (y, r), written
-// to part[slot0 ...][g].
+// Partial sums of one Gram-Schmidt pass over the vector entries, one
+// wavefront per slot: (chi_j, y) and (chi_j, r) for j < k, ||y||^2 and (y, r),
+// written to part[slot0 ...][g].
 template <typename T>
 __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, int k, const cpx<T>* __restrict__ y,
                                     const cpx<T>* __restrict__ r, int slot0)
 {
     const int lane = c.t & 63, w = c.t >> 6;
     const int ns = 2 * k + 2;
+    const int R = c.R();
     for (int s = w; s < ns; s += LT / 64) {
         const cpx<T>* u;
         const cpx<T>* v;
@@ -238,7 +275,7 @@ __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, in
         }
         double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
-        for (int e = lane; e < c.R; e += 64) {
+        for (int e = lane; e < R; e += 64) {
             long i = c.entry(e);
             cpx<T> p = u[i], q = v[i];
             acc = cfma_conj(acc, (double)p.re, (double)p.im, (double)q.re, (double)q.im);
@@ -252,7 +289,13 @@ __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, in
     }
 }
 
-template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleArgs<T> a)
+// GCR on A v = w (EO = false) or on the even-odd reduced system (EO = true,
+// appendix A.2): with D the block diagonal of A and M_d = D^-1 A_d,
+//   v_e solves (1 - M_eo M_oe) v_e = (D^-1 w)_e - M_eo (D^-1 w)_o,
+//   v_o = (D^-1 w)_o - M_oe v_e.
+// Even-odd workspaces: w1 = D^-1 w (all blocks); w2 holds the reduced source
+// on even blocks and the intermediate M_oe u on odd blocks.
+template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gcr(LittleArgs<T> a)
 {
     __shared__ double red[2 * (2 * NK + 2)];
     __shared__ double acoef[NK][NK][2];
@@ -262,24 +305,60 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
     __shared__ double sh[16];
     __shared__ double wn2_s, rn2_s;
     __shared__ int second_s;
-    __shared__ double lds[2 * (9 * 64 > LT ? 9 * 64 : LT)];
+    __shared__ double lds[2 * LT];
+    __shared__ int l_even[EO ? kMaxOwned : 1], l_odd[EO ? kMaxOwned : 1];
+    __shared__ int n_even_s, n_odd_s;
 
-    LittleCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
+    const int G = (int)gridDim.x, gi = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int nbg = (a.g.Nb - gi + G - 1) / G;
+    if (EO) {
+        if (t == 0) {
+            int ne = 0, no = 0;
+            for (int i = 0; i < nbg; ++i) {
+                const int blk = gi + i * G;
+                if (block_colour(a.g, blk))
+                    l_odd[no++] = blk;
+                else
+                    l_even[ne++] = blk;
+            }
+            n_even_s = ne;
+            n_odd_s = no;
+        }
+        __syncthreads();
+    }
+    const int n_even = EO ? n_even_s : 0, n_odd = EO ? n_odd_s : 0;
+    LittleCtx<T> c{a, G, gi, t, (long)a.g.Nb * a.Ns, EO ? l_even : nullptr, EO ? n_even : nbg};
     const double tol2 = a.tol_dev ? (*a.tol_dev) * (*a.tol_dev) : a.tol2;
     unsigned long long bar_target = 0;
     if (c.t == 0)
         bar_target = __hip_atomic_load(a.bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c.nbg = (a.g.Nb - c.g + c.G - 1) / c.G;
-    c.R = c.nbg * a.Ns;
     const long N = c.N;
+    const int R = c.R();
+    // op: y = A u (plain) or y = u - M_eo M_oe u on even blocks (one more barrier)
+    auto op = [&](const cpx<T>* u, cpx<T>* y) {
+        if (EO) {
+            apply_blocks(c, l_odd, n_odd, a.Mt, 1, 9, u, (const cpx<T>*)nullptr, 0.0, 1.0, a.w2, lds);
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+            apply_blocks(c, l_even, n_even, a.Mt, 1, 9, (const cpx<T>*)a.w2, u, 1.0, -1.0, y, lds);
+        } else {
+            apply_blocks(c, (const int*)nullptr, nbg, a.At, 0, 9, u, (const cpx<T>*)nullptr, 0.0, 1.0, y, lds);
+        }
+    };
+    const cpx<T>* rhs = a.w;
+    if (EO) {
+        apply_blocks(c, (const int*)nullptr, nbg, a.Mt, 0, 1, a.w, (const cpx<T>*)nullptr, 0.0, 1.0, a.w1, lds);
+        grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+        apply_blocks(c, l_even, n_even, a.Mt, 1, 9, (const cpx<T>*)a.w1, (const cpx<T>*)a.w1, 1.0, -1.0, a.w2, lds);
+        rhs = a.w2;
+    }
 
-    // x = 0, r = w, ||w||^2
-    for (int e = c.t; e < c.R; e += LT) {
+    // x = 0, r = rhs, ||rhs||^2
+    for (int e = c.t; e < R; e += LT) {
         long i = c.entry(e);
         a.x[i] = cpx<T>{0, 0};
-        a.r[i] = a.w[i];
+        a.r[i] = rhs[i];
     }
-    partial_norm2(c, a.w, SW, sh);
+    partial_norm2(c, rhs, SW, sh);
     grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
     reduce_slots(a.part, c.G, SW, 1, red);
     if (c.t == 0)
@@ -297,8 +376,8 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
         for (; k < a.nkv && iters < a.maxiter; ++k) {
             cpx<T>* xk = a.xi + (long)k * N;
             cpx<T>* ck = a.chi + (long)k * N;
-            // xi_k = r on the owned entries, and the partial ||r||^2
-            for (int e = c.t; e < c.R; e += LT) {
+            // xi_k = r on the vector entries, and the partial ||r||^2
+            for (int e = c.t; e < R; e += LT) {
                 long i = c.entry(e);
                 xk[i] = a.r[i];
             }
@@ -310,7 +389,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             __syncthreads();
             if (k > 0 && rn2_s <= tol2 * wn2)
                 break;  // converged with k directions
-            apply_rows(c, xk, ck, lds);
+            op(xk, ck);
             // one Gram-Schmidt pass: everything needed for chi_k, c_k and the new r
             partial_pass(c, a.chi, k, ck, a.r, SA);
             grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
@@ -326,7 +405,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             __syncthreads();
             if (second_s) {
                 // heavy cancellation: subtract the first projections, then a second pass
-                for (int e = c.t; e < c.R; e += LT) {
+                for (int e = c.t; e < R; e += LT) {
                     long i = c.entry(e);
                     double yr = (double)ck[i].re, yi = (double)ck[i].im;
 #pragma unroll 8
@@ -375,7 +454,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
                 break;
             }
             const double inv = 1.0 / b, cr0 = ccoef[k][0], ci0 = ccoef[k][1];
-            for (int e = c.t; e < c.R; e += LT) {
+            for (int e = c.t; e < R; e += LT) {
                 long i = c.entry(e);
                 double yr = (double)ck[i].re, yi = (double)ck[i].im;
 #pragma unroll 8
@@ -408,7 +487,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             }
         }
         __syncthreads();
-        for (int e = c.t; e < c.R; e += LT) {
+        for (int e = c.t; e < R; e += LT) {
             long i = c.entry(e);
             double yr = (double)a.x[i].re, yi = (double)a.x[i].im;
 #pragma unroll 8
@@ -419,13 +498,13 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             }
             a.x[i] = cpx<T>{(T)yr, (T)yi};
         }
-        // recompute r = w - A x
+        // recompute r = rhs - op(x)
         grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
-        apply_rows(c, a.x, a.r, lds);
+        op(a.x, a.r);
         __syncthreads();
-        for (int e = c.t; e < c.R; e += LT) {
+        for (int e = c.t; e < R; e += LT) {
             long i = c.entry(e);
-            a.r[i] = cpx<T>{(T)((double)a.w[i].re - (double)a.r[i].re), (T)((double)a.w[i].im - (double)a.r[i].im)};
+            a.r[i] = cpx<T>{(T)((double)rhs[i].re - (double)a.r[i].re), (T)((double)rhs[i].im - (double)a.r[i].im)};
         }
         partial_norm2(c, a.r, SR, sh);
         grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
@@ -434,6 +513,10 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr(LittleA
             rn2_s = red[0];
         __syncthreads();
         converged = rn2_s <= tol2 * wn2;
+    }
+    if (EO) {
+        // x_e is complete everywhere (a barrier followed its last update)
+        apply_blocks(c, l_odd, n_odd, a.Mt, 1, 9, (const cpx<T>*)a.x, (const cpx<T>*)a.w1, 1.0, -1.0, a.x, lds);
     }
     if (c.g == 0 && c.t == 0) {
         atomicAdd(&a.stats[0], iters);
@@ -960,9 +1043,10 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
 }
 
 template <typename T>
-void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At, const cpx<T>* w,
-                 cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
-                 unsigned long long* bar_gen, int grid_size, hipStream_t s, bool cooperative)
+void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,
+                 const cpx<T>* Mt, const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, cpx<T>* w1,
+                 cpx<T>* w2, double* part, int* stats, unsigned* bar_count, unsigned long long* bar_gen, int grid_size,
+                 hipStream_t s, bool cooperative)
 {
     LittleArgs<T> a;
     a.g = g;
@@ -972,23 +1056,30 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
     a.tol2 = tol * tol;
     a.tol_dev = tol_dev;
     a.At = At;
+    a.Mt = Mt;
     a.w = w;
     a.x = x;
     a.r = r;
     a.xi = xi;
     a.chi = chi;
+    a.w1 = w1;
+    a.w2 = w2;
     a.part = part;
     a.stats = stats;
     a.bar_count = bar_count;
     a.bar_gen = bar_gen;
+    const void* fn = Mt ? reinterpret_cast<const void*>(&k_little_gcr<T, true>)
+                        : reinterpret_cast<const void*>(&k_little_gcr<T, false>);
     if (!cooperative) {
-        hipLaunchKernelGGL(k_little_gcr<T>, dim3(grid_size), dim3(LT), 0, s, a);
+        if (Mt)
+            hipLaunchKernelGGL((k_little_gcr<T, true>), dim3(grid_size), dim3(LT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_little_gcr<T, false>), dim3(grid_size), dim3(LT), 0, s, a);
         HIPCHECK(hipGetLastError());
         return;
     }
     void* args[] = {&a};
-    HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_little_gcr<T>), dim3(grid_size), dim3(LT),
-                                        args, 0, s));
+    HIPCHECK(hipLaunchCooperativeKernel(fn, dim3(grid_size), dim3(LT), args, 0, s));
 }
 
 }  // namespace
@@ -1009,16 +1100,21 @@ int little_gcr_grid(const Geom& g, int requested)
     return G;
 }
 
+bool little_eo_fits(const Geom& g, int grid)
+{
+    return (g.Nb + grid - 1) / grid <= kMaxOwned;
+}
+
 size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * grid_size * 2; }
 
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,
-                       const cpx<T>* w,
+                       const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                        unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative)
 {
-    launch_impl<T>(g, Ns, nkv, maxiter, tol, tol_dev, At, w, x, r, xi, chi, part, stats, bar_count, bar_gen, grid, s,
-                   cooperative);
+    launch_impl<T>(g, Ns, nkv, maxiter, tol, tol_dev, At, Mt, w, x, r, xi, chi, w1, w2, part, stats, bar_count, bar_gen,
+                   grid, s, cooperative);
 }
 
 template <typename T>
@@ -1074,9 +1170,11 @@ INST_MULTI(double)
 INST_MULTI(float)
 #undef INST_MULTI
 
-template void launch_little_gcr<double>(const Geom&, int, int, int, double, const double*, const c64*, const c64*, c64*, c64*, c64*,
+template void launch_little_gcr<double>(const Geom&, int, int, int, double, const double*, const c64*, const c64*,
+                                        c64*, c64*, const c64*, c64*, c64*, c64*,
                                         c64*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
-template void launch_little_gcr<float>(const Geom&, int, int, int, double, const double*, const c32*, const c32*, c32*, c32*, c32*,
+template void launch_little_gcr<float>(const Geom&, int, int, int, double, const double*, const c32*, const c32*,
+                                       c32*, c32*, const c32*, c32*, c32*, c32*,
                                        c32*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
 
 }  // namespace dfl

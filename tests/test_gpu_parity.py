@@ -451,3 +451,26 @@ def test_graph_solve_equals_direct(c1, nrhs):
     S.use_graphs(True)
     assert np.array_equal(S.unpack(S.solve(ed)[0]), ref2)
     S.close()
+
+
+def test_little_solve_even_odd_vs_plain(c1):
+    # the even-odd reduced GCR (default) and GCR on A itself both reach the
+    # dense solution; the reduced system needs fewer iterations
+    say("little solve even-odd vs plain")
+    torch = pytest.importorskip("torch")
+    dims, b = c1["dims"], (4, 4, 4, 4)
+    ref_solver = np.linalg.solve(oracle.little_dense(c1["A"], dims, b), np.eye(1, 16 * 8, 3).ravel() * 0 + 1.0)
+    its = {}
+    for eo in (1, 0):
+        S = _c1_solver(c1, little_eo=eo)
+        Nb, Ns = S.Nb, S.Ns
+        v = latgen.random_field((Nb, 1, 1, 1), 52).reshape(-1)[: Nb * Ns]
+        x, code, it = S.little_solve(torch.from_numpy(v.copy()).cuda(), 1e-12)
+        assert code == 0
+        ref = np.linalg.solve(oracle.little_dense(c1["A"], dims, b), v)
+        assert rel(x.cpu().numpy(), ref) < 1e-9, eo
+        its[eo] = it
+        S.close()
+    del ref_solver
+    print("[little iterations] even-odd", its[1], "plain", its[0], flush=True)
+    assert its[1] <= its[0]
