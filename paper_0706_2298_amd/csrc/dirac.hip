@@ -1,7 +1,7 @@
 // The Wilson-Dirac stencil (the operator of eq. (3.9)) on native fields.
 //
 // One thread per site, 256 sites per workgroup, one grid row per right-hand
-// side. Per site the kernel reads the eight neighbour spinors, the four
+// side (k_dirac_blk below stages a 256-site block's spinors in LDS). Per site the kernel reads the eight neighbour spinors, the four
 // forward links and the four backward links U_mu(x - mu) (owned by the
 // neighbour; they come from L2/MALL, not HBM), and writes one spinor. The
 // workgroup numbering is XCD-aware (common.h): each XCD sweeps a contiguous
@@ -76,9 +76,83 @@ __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __rest
     store_spinor(out + off, g.V, s, o);
 }
 
+// Full operator for 256-site layout blocks with the block's spinors staged in
+// LDS: one workgroup per (block, right-hand side), one thread per site; hops
+// that stay inside the block read the neighbour from LDS (three quarters of
+// them for 4^4 blocks), the others and all links come from global memory.
+// The output is written with non-temporal stores (it is not re-read here).
+template <typename T, typename L>
+__global__ __launch_bounds__(256) void k_dirac_blk(Geom g, L U, const cpx<T>* __restrict__ psi,
+                                                   cpx<T>* __restrict__ out, T diag, int chunks_padded, int nrhs)
+{
+    __shared__ cpx<T> sp[12][256];
+    const int per = chunks_padded / kNumXcd;
+    const int local = blockIdx.x / kNumXcd;
+    const int blk = (blockIdx.x % kNumXcd) * per + local / nrhs;
+    const int rhs = local % nrhs;
+    if (blk >= g.Nb)
+        return;
+    const int t0 = threadIdx.x;
+    const long s = (long)blk * 256 + t0;
+    const long off = (long)rhs * 12 * g.V;
+    const cpx<T>* f = psi + off;
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+        sp[c][t0] = ld(f, toff<cpx<T>>(s, c, 12));
+    __syncthreads();
+    int n[4], y[4];
+    site_decompose(g, s, n, y);
+    spinor<T> acc;
+    zero(acc);
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int mu = h >> 1;
+        const int step = (h & 1) ? -1 : +1;
+        const bool inside = step > 0 ? y[mu] + 1 < g.b[mu] : y[mu] > 0;
+        const long t = site_step(g, s, n, y, mu, step);
+        spinor<T> p;
+        if (inside) {
+            const int tl = t0 + step * g.lstr[mu];
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    p.s[al].c[a] = sp[3 * al + a][tl];
+        } else {
+            p = load_spinor(f, g.V, t);
+        }
+        if (step > 0)
+            hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
+        else
+            hop_bwd_rt(mu, load_link(U, mu, t), p, acc);
+    }
+    spinor<T> self;
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            self.s[al].c[a] = sp[3 * al + a][t0];
+    const spinor<T> o = finish(self, acc, diag);
+    cpx<T>* dst = out + off;
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cpx<T>* q = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(dst) + toff<cpx<T>>(s, 3 * al + a, 12));
+            __builtin_nontemporal_store(o.s[al].c[a].re, &q->re);
+            __builtin_nontemporal_store(o.s[al].c[a].im, &q->im);
+        }
+}
+
 template <int MODE, typename T, typename L>
 void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, int mu, int dir, hipStream_t s)
 {
+    if (MODE == 0 && g.Vb == 256) {
+        const int gp = pad_grid(g.Nb);
+        hipLaunchKernelGGL((k_dirac_blk<T, L>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, gp,
+                           nrhs);
+        return;
+    }
     long nwg = (g.V + 255) / 256;
     int gp = pad_grid(nwg);
     hipLaunchKernelGGL((k_dirac<MODE, T, L>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, mu, dir,
