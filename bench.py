@@ -323,6 +323,13 @@ def multi_rhs(torch):
         row["max_rel_residual"] = max(i.rel_residual for i in infos)
         S.use_graphs(False)
         _, row["t_batched_direct"] = timed(torch, lambda: S.solve(ed))
+        binding.dfl_profile_read(S.ctx)
+        binding.dfl_profile_enable(S.ctx, True)
+        S.solve(ed)
+        prof = binding.dfl_profile_read(S.ctx)
+        binding.dfl_profile_enable(S.ctx, False)
+        row["kernel_time_batched"] = {k: dict(seconds=prof[k][0], launches=prof[k][1]) for k in binding.PROF_CLASSES}
+        row["little_iterations_batched"] = prof["little_iterations"]
         singles = []
         t_single = 0.0
         for j in range(n):

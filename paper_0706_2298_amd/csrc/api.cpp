@@ -558,8 +558,8 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
         else
             launch_little_gcr_multi<double>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At64, w, v, static_cast<c64*>(c->lr),
                                             static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lfin,
-                                            c->lacoef, c->lstats, c->lbar_count, c->lbar_gen, c->lgrid,
-                                            c->stream, !c->capturing);
+                                            c->lacoef, c->lstats, c->lbar_count, c->lbar_gen,
+                                            c->lgrid_multi, c->stream, !c->capturing);
     } else {
         launch_f64_to_f32(w, c->lw32, n * nb, c->stream);
         {
@@ -573,7 +573,7 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
                 launch_little_gcr_multi<float>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At32, c->lw32, c->lx32,
                                                static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
                                                static_cast<c32*>(c->lchi), c->lpart, c->lfin, c->lacoef, c->lstats,
-                                               c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
+                                               c->lbar_count, c->lbar_gen, c->lgrid_multi, c->stream, !c->capturing);
         }
         launch_f32_to_f64(c->lx32, v, n * nb, c->stream);
     }
@@ -845,10 +845,11 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->lw32 = alloc_dev<c32>(c, R * N);
         c->lx32 = alloc_dev<c32>(c, R * N);
         c->lgrid = little_gcr_grid(c->g, p->little_grid);
+        c->lgrid_multi = little_gcr_multi_grid(c->g, p->little_grid);
         size_t part = little_gcr_partial_doubles(c->lgrid);
         if (R > 1) {
             size_t nfin = 0, nac = 0;
-            part = std::max(part, little_gcr_multi_doubles(c->lgrid, (int)R, &nfin, &nac));
+            part = std::max(part, little_gcr_multi_doubles(c->lgrid_multi, (int)R, &nfin, &nac));
             c->lfin = alloc_dev<double>(c, nfin);
             c->lacoef = alloc_dev<double>(c, nac);
         }

@@ -55,6 +55,7 @@ constexpr int kMaxDot = 64;       // most vectors in one multi-dot
 constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
 constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
 constexpr int kMaxLittleRhs = 16;    // right-hand sides of one batched little solve
+constexpr int kLittleMaxGridMulti = 256;  // workgroups of the batched little GCR (one per CU)
 
 }  // namespace dfl
 
@@ -115,6 +116,7 @@ struct dfl_ctx {
     unsigned* lbar_count = nullptr;         // grid barrier of the little GCR kernel
     unsigned long long* lbar_gen = nullptr;
     int lgrid = 0;             // its grid size
+    int lgrid_multi = 0;       // grid of the batched little GCR
     double* lfin = nullptr;    // batched little GCR: reduced sums and per-workgroup coefficients
     double* lacoef = nullptr;
     // reductions and scalars
@@ -275,6 +277,9 @@ constexpr int kLossMaxN = 32;      // fields and targets of the deficit loss
 // workgroups of the little GCR: requested (0: Nb / 4), clamped to 1..min(Nb, kLittleMaxGrid)
 int little_gcr_grid(const Geom& g, int requested);
 size_t little_gcr_partial_doubles(int grid_size);
+// workgroups of the batched little GCR: twice the requested single-source
+// grid (0: Nb / 4), at most one per compute unit and the block count
+int little_gcr_multi_grid(const Geom& g, int requested);
 // whether the even-odd solver's per-workgroup block lists fit for this grid
 bool little_eo_fits(const Geom& g, int grid);
 // v = A^{-1} w by GCR to ||w - A v|| <= tol ||w|| in one cooperative launch

@@ -571,76 +571,77 @@ template <typename T> struct MultiCtx {
     __device__ double* pslot(int slot, int b) const { return a.part + (((long)slot * a.nrhs + b) * G + g) * 2; }
 };
 
-// y_b = A v_b on the owned rows for the listed right-hand sides. A unit is
-// (owned block, RHS); a round covers LT / (9 Ns) units, task (unit, d, k)
-// forms one neighbour term as in apply_rows.
+// y_b = A v_b on the owned rows for the listed sources, on the matrix cores:
+// for an owned block the nine terms
+// sum_d A_d V_d (V_d: the listed sources' entries on the d-th neighbour, Ns x
+// nlist) form one real GEMM of the 2Ns x 18Ns matrix [[ar, -ai], [ai, ar]]
+// (rows and columns interleaved re/im) with the 18Ns x nlist matrix of the
+// V_d entries read as reals, in 16x16x4 tiles (FP32 or FP64 MFMA). Wave w
+// takes (block, row tile) tasks w, w + 16, ...; the sources (<= 16) are the
+// 16 columns. A is read from the transposed blocks At, coalesced in the row.
+template <typename T> struct Mfma;
+// Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result
+// element i of lane l is D[row(l / 16, i)][l % 16], with the row order of
+// the FP32 and FP64 instructions differing.
+template <> struct Mfma<float> {
+    using acc_t = __attribute__((ext_vector_type(4))) float;
+    static __device__ inline acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int kq, int i) { return 4 * kq + i; }
+};
+template <> struct Mfma<double> {
+    using acc_t = __attribute__((ext_vector_type(4))) double;
+    static __device__ inline acc_t step(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int kq, int i) { return 4 * i + kq; }
+};
+
 template <typename T>
-__device__ inline void apply_multi(const MultiCtx<T>& c, const cpx<T>* __restrict__ v, long vstride,
-                                   cpx<T>* __restrict__ y, long ystride, const int* list, int nlist, double* lds)
+__device__ inline void apply_multi_mfma(const MultiCtx<T>& c, const cpx<T>* __restrict__ v, long vstride,
+                                        cpx<T>* __restrict__ y, long ystride, const int* list, int nlist)
 {
     const Geom& g = c.a.g;
     const int Ns = c.a.Ns;
-    const int per = 9 * Ns;
-    const int upr = per <= LT ? LT / per : 1;
-    const long nu = (long)c.nbg * nlist;
-    for (long u0 = 0; u0 < nu; u0 += upr) {
-        for (int task0 = 0; task0 < upr * per; task0 += LT) {
-            const int task = task0 + c.t;
-            const int iu = task / per;
-            const int rem = task - iu * per;
-            const int d = rem / Ns;
-            const int k = rem - d * Ns;
-            if (iu < upr && u0 + iu < nu && task < 2 * LT / 2) {
-                const long u = u0 + iu;
-                const int ib = (int)(u / nlist);
-                const int b = list[u - (long)ib * nlist];
-                const int blk = c.g + ib * c.G;
-                int nbr = blk;
-                if (d > 0) {
-                    const int mu = (d - 1) >> 1;
-                    int rest = blk;
-                    for (int nu2 = 3; nu2 > mu; --nu2)
-                        rest /= g.nb[nu2];
-                    const int n_mu = rest % g.nb[mu];
-                    int nn = n_mu + ((d & 1) ? 1 : -1);
-                    if (nn < 0)
-                        nn += g.nb[mu];
-                    if (nn >= g.nb[mu])
-                        nn -= g.nb[mu];
-                    nbr = blk + (nn - n_mu) * g.bstr[mu];
+    const int mt = (2 * Ns + 15) / 16;
+    const int lane = c.t & 63, wave = c.t >> 6;
+    const int n = lane & 15, kq = lane >> 4;
+    const int b_n = n < nlist ? list[n] : 0;
+    for (int task = wave; task < c.nbg * mt; task += LT / 64) {
+        const int ib = task / mt, tt = task - ib * mt;
+        const int blk = c.g + ib * c.G;
+        const int rr = 16 * tt + n;
+        const int m = rr >> 1, cr = rr & 1;
+        typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+        for (int d = 0; d < 9; ++d) {
+            const int nbr = nbr_block(g, blk, d);
+            const cpx<T>* Ad = c.a.At + ((long)blk * 9 + d) * Ns * Ns;
+            const cpx<T>* vb = v + b_n * vstride + (long)nbr * Ns;
+            for (int kc = 0; kc < 2 * Ns; kc += 4) {
+                const int kk = kc + kq;
+                const int l = kk >> 1, ck = kk & 1;
+                T a = 0, bv = 0;
+                if (kk < 2 * Ns) {
+                    if (m < Ns) {
+                        const cpx<T> z = Ad[(long)l * Ns + m];
+                        a = cr == 0 ? (ck == 0 ? z.re : -z.im) : (ck == 0 ? z.im : z.re);
+                    }
+                    if (n < nlist) {
+                        const cpx<T> q = vb[l];
+                        bv = ck == 0 ? q.re : q.im;
+                    }
                 }
-                const cpx<T>* At = c.a.At + ((long)blk * 9 + d) * Ns * Ns + k;
-                const cpx<T>* vv = v + b * vstride + (long)nbr * Ns;
-                double re = 0.0, im = 0.0;
-#pragma unroll 8
-                for (int l = 0; l < Ns; ++l) {
-                    cpx<T> p = At[(long)l * Ns];
-                    cpx<T> q = vv[l];
-                    re += (double)p.re * (double)q.re - (double)p.im * (double)q.im;
-                    im += (double)p.re * (double)q.im + (double)p.im * (double)q.re;
-                }
-                lds[2 * task] = re;
-                lds[2 * task + 1] = im;
+                acc = Mfma<T>::step(a, bv, acc);
             }
         }
-        __syncthreads();
-        for (int q = c.t; q < upr * Ns; q += LT) {
-            const int ju = q / Ns, kk = q - ju * Ns;
-            if (u0 + ju < nu) {
-                double sr = 0.0, si = 0.0;
-                for (int dd = 0; dd < 9; ++dd) {
-                    sr += lds[2 * (ju * per + dd * Ns + kk)];
-                    si += lds[2 * (ju * per + dd * Ns + kk) + 1];
-                }
-                const long u = u0 + ju;
-                const int ib = (int)(u / nlist);
-                const int b = list[u - (long)ib * nlist];
-                const int blk = c.g + ib * c.G;
-                y[b * ystride + (long)blk * Ns + kk] = cpx<T>{(T)sr, (T)si};
+        if (n < nlist) {
+            T* yb = reinterpret_cast<T*>(y + b_n * ystride + (long)blk * Ns);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ro = 16 * tt + Mfma<T>::row(kq, i);
+                if (ro < 2 * Ns)
+                    yb[ro] = acc[i];
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 // part[slot][b][g] = ||v_b||^2 over the owned entries, one wavefront per listed RHS
@@ -683,46 +684,57 @@ __device__ inline void multi_reduce_real(const double* part, int nrhs, int G, in
 }
 
 // Gram-Schmidt partial sums for the listed RHS into slots slot0 + s, s < 2k+2
-// (same layout as partial_pass); 16-lane groups per (RHS, slot).
+// (same layout as partial_pass). One wavefront per (RHS, group of 8 slots):
+// the lanes run over the workgroup's entries, y and r are read once for the
+// group, and the 8 complex sums are reduced across the wavefront at the end.
+constexpr int kSlotGroup = 8;
+
 template <typename T>
 __device__ inline void multi_pass(const MultiCtx<T>& c, int k, const int* list, int nlist, int slot0)
 {
     const int ns = 2 * k + 2;
-    const int l16 = c.t & 15, grp = c.t >> 4;
+    const int ngrp = (ns + kSlotGroup - 1) / kSlotGroup;
+    const int lane = c.t & 63, wv = c.t >> 6;
     const long N = c.N;
     const int nr = c.a.nrhs;
-    for (int task = grp; task < nlist * ns; task += LT / 16) {
-        const int bi = task / ns, s = task - bi * ns;
+    for (int task = wv; task < nlist * ngrp; task += LT / 64) {
+        const int bi = task / ngrp, s0 = (task - bi * ngrp) * kSlotGroup;
         const int b = list[bi];
         const cpx<T>* y = c.a.chi + ((long)k * nr + b) * N;
         const cpx<T>* r = c.a.r + b * N;
-        const cpx<T>* u;
-        const cpx<T>* v;
-        if (s < k) {
-            u = c.a.chi + ((long)s * nr + b) * N;
-            v = y;
-        } else if (s < 2 * k) {
-            u = c.a.chi + ((long)(s - k) * nr + b) * N;
-            v = r;
-        } else {
-            u = y;
-            v = (s == 2 * k) ? y : r;
-        }
-        double2 acc = make_double2(0.0, 0.0);
-        for (int e = l16; e < c.R; e += 16) {
-            long i = c.entry(e);
-            cpx<T> p = u[i], q = v[i];
-            acc = cfma_conj(acc, (double)p.re, (double)p.im, (double)q.re, (double)q.im);
+        double2 acc[kSlotGroup];
+#pragma unroll
+        for (int q = 0; q < kSlotGroup; ++q)
+            acc[q] = make_double2(0.0, 0.0);
+        for (int e = lane; e < c.R; e += 64) {
+            const long i = c.entry(e);
+            const cpx<T> yv = y[i], rv = r[i];
+#pragma unroll
+            for (int q = 0; q < kSlotGroup; ++q) {
+                const int sl = s0 + q;
+                if (sl < ns) {
+                    cpx<T> u, v;
+                    if (sl < 2 * k) {
+                        u = c.a.chi[((long)(sl < k ? sl : sl - k) * nr + b) * N + i];
+                        v = sl < k ? yv : rv;
+                    } else {
+                        u = yv;
+                        v = sl == 2 * k ? yv : rv;
+                    }
+                    acc[q] = cfma_conj(acc[q], (double)u.re, (double)u.im, (double)v.re, (double)v.im);
+                }
+            }
         }
 #pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-            acc.x += __shfl_xor(acc.x, off, 16);
-            acc.y += __shfl_xor(acc.y, off, 16);
-        }
-        if (l16 == 0) {
-            double* p = c.pslot(slot0 + s, b);
-            p[0] = acc.x;
-            p[1] = acc.y;
+        for (int q = 0; q < kSlotGroup; ++q) {
+            if (s0 + q >= ns)
+                break;
+            const double re = wave_sum(acc[q].x), im = wave_sum(acc[q].y);
+            if (lane == 0) {
+                double* p = c.pslot(slot0 + s0 + q, b);
+                p[0] = re;
+                p[1] = im;
+            }
         }
     }
 }
@@ -764,7 +776,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
     __shared__ int act[kMaxLittleRhs], stop[kMaxLittleRhs], conv[kMaxLittleRhs], kb[kMaxLittleRhs];
     __shared__ int second[kMaxLittleRhs];
     __shared__ int list[kMaxLittleRhs], nlist_s, list2[kMaxLittleRhs], nlist2_s;
-    __shared__ double lds[2 * LT];
+    
 
     MultiCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
     const double tol2 = a.tol_dev ? (*a.tol_dev) * (*a.tol_dev) : a.tol2;
@@ -843,7 +855,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
             const int na = nlist_s;
             if (na == 0)
                 break;
-            apply_multi(c, a.xi + (long)k * nr * N, N, a.chi + (long)k * nr * N, N, list, na, lds);
+            apply_multi_mfma(c, a.xi + (long)k * nr * N, N, a.chi + (long)k * nr * N, N, list, na);
             multi_pass(c, k, list, na, SA);
             grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
             multi_fin(a.part, a.fin, nr, c.G, c.g, SA, 2 * k + 2, list, na);
@@ -1010,7 +1022,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
         }
         // recompute r_b = w_b - A x_b for those RHS
         grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
-        apply_multi(c, a.x, N, a.r, N, list, nx, lds);
+        apply_multi_mfma(c, a.x, N, a.r, N, list, nx);
         for (long q = c.t; q < (long)c.R * nx; q += LT) {
             const int bi = (int)(q / c.R), e = (int)(q - (long)bi * c.R);
             const int b = list[bi];
@@ -1093,6 +1105,18 @@ int little_gcr_grid(const Geom& g, int requested)
     int G = requested > 0 ? requested : g.Nb / 4;
     if (G > kLittleMaxGrid)
         G = kLittleMaxGrid;
+    if (G > g.Nb)
+        G = g.Nb;
+    if (G < 1)
+        G = 1;
+    return G;
+}
+
+int little_gcr_multi_grid(const Geom& g, int requested)
+{
+    int G = requested > 0 ? 2 * requested : g.Nb / 4;
+    if (G > kLittleMaxGridMulti)
+        G = kLittleMaxGridMulti;
     if (G > g.Nb)
         G = g.Nb;
     if (G < 1)
