@@ -1064,7 +1064,12 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     // hops, applied to a chunk of basis fields per launch (the Krylov
     // buffer is free during the setup), then the block products with Phi
     const long nA = (long)c->g.Nb * 9 * Ns * Ns;
-    const int chunk = std::min({Ns, little_columns_max(Ns), c->p.nkv * c->p.nrhs_max, 128 - Ns});
+    // chunk of basis fields per launch: bounded by the Krylov buffer (the
+    // stencil output) and by t1 (the split partial sums, Nb*Ns*chunk entries)
+    const long part_cap = F * c->p.nrhs_max;
+    const int chunk = (int)std::max(1L, std::min({(long)Ns, (long)little_columns_max(Ns),
+                                                  (long)c->p.nkv * c->p.nrhs_max, (long)(128 - Ns),
+                                                  part_cap / ((long)c->g.Nb * Ns)}));
     for (int l0 = 0; l0 < Ns; l0 += chunk) {
         const int nc = std::min(chunk, Ns - l0);
         const c64* f = c->Phi + (long)l0 * F;
@@ -1076,7 +1081,7 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
                 const int dir = (d & 1) ? +1 : -1;
                 launch_dirac64(c->g, links64(c), f, c->xi, nc, 0.0, 2, mu, dir, c->stream);
             }
-            launch_little_columns64(c->g, c->Phi, Ns, c->xi, nc, l0, d, c->A64, c->stream);
+            launch_little_columns64(c->g, c->Phi, Ns, c->xi, nc, l0, d, c->A64, c->t1, part_cap, c->stream);
         }
     }
     launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);

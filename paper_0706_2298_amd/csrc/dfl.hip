@@ -184,32 +184,36 @@ __device__ inline int block_nbr(const Geom& g, int blk, int d)
     return blk + (nn - n_mu) * g.bstr[mu];
 }
 
-// A[blk][d][k][l0 + j] = sum_{x in blk} conj(Phi_k(x)) Y_j(x) for k < Ns, j < nc:
-// the block products Phi_blk^+ Y_blk of eq. (A.1) for nc columns at once. One
-// workgroup per block; entries staged through LDS kCE at a time, each thread
-// accumulating up to kMaxPairs of the Ns*nc products.
+// Block products Phi_blk^+ Y_blk of eq. (A.1) for nc columns at once, the
+// 12 Vb entries of a block split over nsplit workgroups:
+// part[split][blk][k][j] = sum over the split's entries of conj(Phi_k) Y_j.
+// Entries are staged through LDS kCE at a time, each thread accumulating up
+// to kMaxPairs of the Ns*nc products.
 constexpr int kCE = 32;
 constexpr int kMaxPairs = 16;
 
 __global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __restrict__ Phi, int Ns,
-                                                        const c64* __restrict__ Y, int nc, int l0, int d,
-                                                        c64* __restrict__ A)
+                                                        const c64* __restrict__ Y, int nc, int nsplit,
+                                                        c64* __restrict__ part)
 {
     extern __shared__ c64 st[];  // [Ns + nc][kCE + 1]
-    const int blk = blockIdx.x;
+    const int blk = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
     const long F = 12 * g.V;
     const int ne = 12 * g.Vb;
+    const int per = ((ne + nsplit - 1) / nsplit + kCE - 1) / kCE * kCE;
+    const int e_lo = split * per;
+    const int e_hi = e_lo + per < ne ? e_lo + per : ne;
     const int np = Ns * nc;
     c64 acc[kMaxPairs];
 #pragma unroll
     for (int q = 0; q < kMaxPairs; ++q)
         acc[q] = c64{0.0, 0.0};
-    for (int e0 = 0; e0 < ne; e0 += kCE) {
+    for (int e0 = e_lo; e0 < e_hi; e0 += kCE) {
         __syncthreads();
         for (int q = threadIdx.x; q < (Ns + nc) * kCE; q += blockDim.x) {
             const int r = q / kCE, e = q % kCE;
             c64 v{0.0, 0.0};
-            if (e0 + e < ne) {
+            if (e0 + e < e_hi) {
                 const long i = block_elem(g, blk, e0 + e);
                 v = r < Ns ? Phi[(long)r * F + i] : Y[(long)(r - Ns) * F + i];
             }
@@ -236,11 +240,25 @@ __global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __res
 #pragma unroll
     for (int q = 0; q < kMaxPairs; ++q) {
         const int p = threadIdx.x + q * blockDim.x;
-        if (p < np) {
-            const int k = p / nc, j = p - k * nc;
-            A[(((long)blk * 9 + d) * Ns + k) * Ns + l0 + j] = acc[q];
-        }
+        if (p < np)
+            part[((long)split * g.Nb + blk) * np + p] = acc[q];
     }
+}
+
+// A[blk][d][k][l0 + j] = sum over splits of part (fixed order)
+__global__ __launch_bounds__(256) void k_little_columns_sum(Geom g, const c64* __restrict__ part, int Ns, int nc,
+                                                            int nsplit, int l0, int d, c64* __restrict__ A)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int np = Ns * nc;
+    if (q >= (long)g.Nb * np)
+        return;
+    const int blk = (int)(q / np), p = (int)(q - (long)blk * np);
+    const int k = p / nc, j = p - k * nc;
+    c64 s{0.0, 0.0};
+    for (int sp = 0; sp < nsplit; ++sp)
+        s += part[((long)sp * g.Nb + blk) * np + p];
+    A[(((long)blk * 9 + d) * Ns + k) * Ns + l0 + j] = s;
 }
 
 // w_b[blk] = sum_d A[blk][d] v_b[nbr_d(blk)], one thread per (blk, k) row,
@@ -499,9 +517,18 @@ int little_columns_max(int Ns)
 }
 
 void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y, int nc, int l0, int d, c64* A,
-                             hipStream_t s)
+                             c64* part, long part_cap, hipStream_t s)
 {
     const size_t lds = sizeof(c64) * (Ns + nc) * (kCE + 1);
+    int nsplit = (12 * g.Vb) / (8 * kCE);  // at least 8 staged tiles per workgroup
+    if (nsplit > 8)
+        nsplit = 8;
+    while (nsplit > 1 && (long)nsplit * g.Nb * Ns * nc > part_cap)
+        --nsplit;
+    if (nsplit < 1)
+        nsplit = 1;
+    if ((long)nsplit * g.Nb * Ns * nc > part_cap)
+        fail(DFL_EINVAL, "little-operator assembly: scratch too small for the column chunk");
     static bool attr = false;
     if (!attr) {
         HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_little_columns),
@@ -509,7 +536,10 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
                                      (int)(sizeof(c64) * (64 + 64) * (kCE + 1))));
         attr = true;
     }
-    hipLaunchKernelGGL(k_little_columns, dim3(g.Nb), dim3(256), lds, s, g, Phi, Ns, Y, nc, l0, d, A);
+    hipLaunchKernelGGL(k_little_columns, dim3(g.Nb * nsplit), dim3(256), lds, s, g, Phi, Ns, Y, nc, nsplit, part);
+    const long n = (long)g.Nb * Ns * nc;
+    hipLaunchKernelGGL(k_little_columns_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, part, Ns, nc,
+                       nsplit, l0, d, A);
 }
 
 template <typename T>

@@ -231,10 +231,11 @@ void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* 
 // block Gram-Schmidt in place on Ns fields (modified GS, order l = 0..Ns-1)
 void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, hipStream_t s);
 // A[blk][d][k][l0 + j] = (Phi_k, Y_j) over each block for k < Ns, j < nc
-// (nc <= little_columns_max(Ns), nc + Ns <= 128)
+// (nc <= little_columns_max(Ns), nc + Ns <= 128); part: scratch of part_cap
+// complex entries for the split partial sums (at least Nb*Ns*nc)
 int little_columns_max(int Ns);
 void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y, int nc, int l0, int d, c64* A,
-                             hipStream_t s);
+                             c64* part, long part_cap, hipStream_t s);
 // w_b = A v_b (9-point block stencil) for nrhs little vectors
 template <typename T>
 void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, int nrhs, hipStream_t s);
