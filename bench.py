@@ -13,8 +13,8 @@ Also reported (outside the timed region):
 * the dominant kernel's roofline: one extra step with the library's event
   timers on; algorithmic flops or bytes per launch over the measured launch
   duration;
-* dirac_apply GFLOP/s and algorithmic GB/s on 64 x 32^3 (FP64 full links,
-  FP32 and BF16 two-row links), a working set well above the 256 MB MALL;
+* dirac_apply GFLOP/s and algorithmic GB/s on 64 x 32^3 (FP64, FP32 and
+  BF16 two-row links), a working set well above the 256 MB MALL;
 * undeflated SAP+GCR and plain FP64 GCR on the same fields;
 * 32 x 16^3 in mixed precision (BF16 two-row links, FP32 Schwarz and inner
   little solves, Schwarz block shape picked by the autotuner) with the error
@@ -48,7 +48,8 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FLOPS_PER_SITE = 1368            # Wilson stencil per site per right-hand side (1320 hop + 48 diagonal)
-BYTES_PER_SITE = {"f64": 960, "f32_tworow": 384, "bf16_tworow": 288}
+# links are stored as two rows of the SU(3) matrix in every precision (the third row is rebuilt)
+BYTES_PER_SITE = {"f64_tworow": 768, "f32_tworow": 384, "bf16_tworow": 288}
 
 DIMS = (16, 16, 16, 16)
 BLOCK = (4, 4, 4, 4)
@@ -179,10 +180,10 @@ def roofline(prof, little_it):
                  peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                  per_launch=f"{byts:.4g} B = {little_it / max(n, 1):.1f} iterations x {per_it} B (A + 4 vectors)")
     elif cls == "dirac":
-        byts = BYTES_PER_SITE["f64"] * V
+        byts = BYTES_PER_SITE["f64_tworow"] * V
         ach = byts / dur / 1e9
-        r = dict(kernel="k_dirac<0,double>", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                 frac=ach / HBM_PEAK_GBS, per_launch=f"{byts} B = 960 B/site x {V}")
+        r = dict(kernel="k_dirac_blk<double>", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                 frac=ach / HBM_PEAK_GBS, per_launch=f"{byts} B = 768 B/site x {V}")
     else:
         byts = 192 * (NS + 1) * V
         ach = byts / dur / 1e9
@@ -195,7 +196,7 @@ def roofline(prof, little_it):
 
 
 def dirac_rates(torch):
-    """dirac_apply on 64 x 32^3: FP64 full links, FP32 and BF16 two-row links."""
+    """dirac_apply on 64 x 32^3: FP64 arithmetic with FP64 two-row links, FP32 with FP32 and BF16 two-row links."""
     import latgen
     from paper_0706_2298_amd import BF16, F32, F64, Solver, binding
     dims = (64, 32, 32, 32)
@@ -203,7 +204,7 @@ def dirac_rates(torch):
     U = latgen.make_links(dims, 0.4, 4101)
     psi = latgen.make_source(dims, 4102)
     out = {}
-    for name, lp, prec in [("f64", F64, F64), ("f32_tworow", F32, F32), ("bf16_tworow", BF16, F32)]:
+    for name, lp, prec in [("f64_tworow", F64, F64), ("f32_tworow", F32, F32), ("bf16_tworow", BF16, F32)]:
         sp = F64 if lp == F64 else F32
         S = Solver(dims, Ns=1, nkv=1, little_nkv=1, m0=-0.2, link_prec=lp, sap_prec=sp)
         S.set_gauge(U)

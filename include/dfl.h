@@ -150,9 +150,12 @@ long long dfl_field_bytes(const dfl_ctx *ctx, dfl_prec prec);
 int dfl_num_blocks(const dfl_ctx *ctx);
 
 /* Load the gauge field U (canonical complex128 [V][4][3][3], device) and
- * derive the internal copies: FP64 full links for D, and the two-row
- * FP32/BF16 links of the SAP block solves when link_prec asks for them.
- * Invalidates a previously built deflation subspace. */
+ * derive the internal copies, two rows per SU(3) matrix (the third is
+ * rebuilt as conj(row0 x row1) where a link is used): FP64 for D, FP32 and
+ * BF16 for the SAP block solves. Synchronises. DFL_EINVAL (and no gauge
+ * field) if some link's third row differs from conj(row0 x row1) by more than
+ * 1e-12 relative, i.e. the links are not SU(3). Invalidates a previously
+ * built deflation subspace. */
 int dfl_set_gauge(dfl_ctx *ctx, const double *U_canon_dev);
 
 /* Canonical complex128 [nrhs][V][12] (device) <-> native fields of precision

@@ -808,7 +808,7 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
     const long V = c->V, F = c->field_elems;
     const long N = (long)c->g.Nb * p->Ns;
     try {
-        c->U64 = alloc_dev<c64>(c, (size_t)36 * V);
+        c->U64 = alloc_dev<c64>(c, (size_t)24 * V);
         c->U32 = alloc_dev<c32>(c, (size_t)24 * V);
         c->Ubf = alloc_dev<uint32_t>(c, (size_t)24 * V);
         c->Phi = alloc_dev<c64>(c, (size_t)p->Ns * F);
@@ -957,10 +957,17 @@ int dfl_set_gauge(dfl_ctx* c, const double* U)
     API_BEGIN
     need_ctx(c);
     need_ptr(U, "U");
-    launch_pack_gauge(c->g, reinterpret_cast<const c64*>(U), c->U64, c->U32, c->Ubf, c->stream);
-    HIPCHECK(hipGetLastError());
-    c->have_gauge = true;
+    c->have_gauge = false;
     c->have_subspace = false;
+    HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+    launch_pack_gauge(c->g, reinterpret_cast<const c64*>(U), c->U64, c->U32, c->Ubf, c->dflag, c->stream);
+    HIPCHECK(hipGetLastError());
+    int flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (flag)
+        fail(DFL_EINVAL, "gauge field: every link must be SU(3) (third row = conj(row0 x row1) to 1e-12)");
+    c->have_gauge = true;
     API_END
 }
 

@@ -34,10 +34,11 @@ __device__ inline su3<double> load_link(const Links64& L, int mu, long s)
 {
     su3<double> u;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            u.m[a][b] = ld(L.u, toff<c64>(s, mu * 9 + a * 3 + b, 36));
+            u.m[a][b] = ld(L.u, toff<c64>(s, mu * 6 + a * 3 + b, 24));
+    complete_third_row(u);
     return u;
 }
 

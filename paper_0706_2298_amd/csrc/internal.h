@@ -34,7 +34,8 @@ struct SapGeom {
     int n_per_colour;
 };
 
-// links: FP64 full [4][9][V], FP32 two-row [4][6][V], BF16 two-row [4][6][V]
+// links, two rows per matrix (the third is conj(row0 x row1)): FP64, FP32 and
+// BF16 [4][6] entries per site in 64-site tiles
 struct Links64 {
     const c64* u;
     long V;
@@ -160,7 +161,8 @@ void launch_pack_field64(const Geom& g, const c64* canon, c64* nat, int nrhs, hi
 void launch_pack_field32(const Geom& g, const c64* canon, c32* nat, int nrhs, hipStream_t s);
 void launch_unpack_field64(const Geom& g, const c64* nat, c64* canon, int nrhs, hipStream_t s);
 void launch_unpack_field32(const Geom& g, const c32* nat, c64* canon, int nrhs, hipStream_t s);
-void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, hipStream_t s);
+// flag |= 1 if some link's third row is not conj(row0 x row1)
+void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, int* flag, hipStream_t s);
 void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s);
 void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s);
 

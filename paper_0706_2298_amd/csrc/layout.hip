@@ -2,9 +2,9 @@
 //
 // Canonical quark field: complex128 [V][12] in lexicographic site order.
 // Native quark field: 64-site tiles of 12 components in block-major site
-// order (common.h). Links: FP64 full 3x3 (36 entries per site); FP32 and BF16
-// store the first two rows only (24 entries per site), the third row being
-// rebuilt as conj(row0 x row1).
+// order (common.h). Links: FP64, FP32 and BF16 store the first two rows only
+// (24 entries per site), the third row being rebuilt as conj(row0 x row1),
+// which is exact for SU(3) matrices.
 #include "internal.h"
 
 namespace dfl {
@@ -64,8 +64,11 @@ __device__ inline uint32_t bf16_bits(float f)
     return u >> 16;
 }
 
-__global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const c64* __restrict__ canon, c64* U64,
-                                                    c32* U32, uint32_t* Ubf)
+// Links in two-row form ([4][6] entries per site) in FP64, FP32 and BF16; the
+// third row is rebuilt as conj(row0 x row1) wherever a link is used. flag |= 1
+// where the given third row differs from that (the link is not SU(3)).
+__global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const c64* __restrict__ canon, c64* U64, c32* U32,
+                                                    uint32_t* Ubf, int* flag)
 {
     long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V)
@@ -75,20 +78,32 @@ __global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const c64* __restric
     for (int mu = 0; mu < 4; ++mu)
         x[mu] = n[mu] * g.b[mu] + y[mu];
     long c = canon_index(g, x);
+    bool bad = false;
     for (int mu = 0; mu < 4; ++mu) {
         const c64* src = canon + (c * 4 + mu) * 9;
-        for (int k = 0; k < 9; ++k) {
-            c64 v = src[k];
+        c64 u[9];
+        for (int k = 0; k < 9; ++k)
+            u[k] = src[k];
+        double scale = 0.0;
+        for (int k = 0; k < 6; ++k) {
+            const c64 v = u[k];
+            scale += v.re * v.re + v.im * v.im;
             if (U64)
-                U64[tidx(s, mu * 9 + k, 36)] = v;
-            if (k < 6) {
-                if (U32)
-                    U32[tidx(s, mu * 6 + k, 24)] = c32{(float)v.re, (float)v.im};
-                if (Ubf)
-                    Ubf[tidx(s, mu * 6 + k, 24)] = bf16_bits((float)v.re) | (bf16_bits((float)v.im) << 16);
-            }
+                U64[tidx(s, mu * 6 + k, 24)] = v;
+            if (U32)
+                U32[tidx(s, mu * 6 + k, 24)] = c32{(float)v.re, (float)v.im};
+            if (Ubf)
+                Ubf[tidx(s, mu * 6 + k, 24)] = bf16_bits((float)v.re) | (bf16_bits((float)v.im) << 16);
+        }
+        for (int b = 0; b < 3; ++b) {
+            const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+            const c64 r = conjg(u[b1] * u[3 + b2] - u[b2] * u[3 + b1]);
+            const double dr = r.re - u[6 + b].re, di = r.im - u[6 + b].im;
+            bad |= !(dr * dr + di * di <= 1e-24 * (1.0 + scale * scale));
         }
     }
+    if (bad)
+        atomicOr(flag, 1);
 }
 
 __global__ __launch_bounds__(256) void k_f64_to_f32(const c64* __restrict__ in, c32* __restrict__ out, long n)
@@ -125,9 +140,9 @@ void launch_unpack_field32(const Geom& g, const c32* nat, c64* canon, int nrhs, 
 {
     hipLaunchKernelGGL(k_unpack_field<float>, site_grid(g, nrhs), dim3(256), 0, s, g, nat, canon, nrhs);
 }
-void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, hipStream_t s)
+void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, int* flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pack_gauge, site_grid(g, 1), dim3(256), 0, s, g, canon, U64, U32, Ubf);
+    hipLaunchKernelGGL(k_pack_gauge, site_grid(g, 1), dim3(256), 0, s, g, canon, U64, U32, Ubf, flag);
 }
 void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s)
 {

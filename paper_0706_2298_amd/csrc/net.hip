@@ -231,10 +231,17 @@ __global__ __launch_bounds__(256) void k_features(Geom g, const c64* __restrict_
     if (s >= g.V)
         return;
     const long i = canon_of(g, s);
-    for (int k = 0; k < 36; ++k) {
-        const c64 u = U64[tidx(s, k, 36)];
-        x[(long)(2 * k) * g.V + i] = (float)u.re;
-        x[(long)(2 * k + 1) * g.V + i] = (float)u.im;
+    for (int mu = 0; mu < 4; ++mu) {
+        c64 u[9];
+        for (int k = 0; k < 6; ++k)
+            u[k] = U64[tidx(s, mu * 6 + k, 24)];
+        for (int b = 0; b < 3; ++b)
+            u[6 + b] = conjg(u[(b + 1) % 3] * u[3 + (b + 2) % 3] - u[(b + 2) % 3] * u[3 + (b + 1) % 3]);
+        for (int k = 0; k < 9; ++k) {
+            const int ch = 2 * (mu * 9 + k);
+            x[(long)ch * g.V + i] = (float)u[k].re;
+            x[(long)(ch + 1) * g.V + i] = (float)u[k].im;
+        }
     }
     for (int k = 0; k < 24; ++k)
         x[(long)(72 + k) * g.V + i] = noise[i * 24 + k];

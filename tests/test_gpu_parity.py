@@ -474,3 +474,20 @@ def test_little_solve_even_odd_vs_plain(c1):
     del ref_solver
     print("[little iterations] even-odd", its[1], "plain", its[0], flush=True)
     assert its[1] <= its[0]
+
+
+def test_set_gauge_requires_su3():
+    # links are stored as two rows; a link whose third row is not conj(row0 x row1) is refused
+    say("set_gauge SU(3) check")
+    dims = (8, 8, 8, 8)
+    U = latgen.make_links(dims, 0.4, 17)
+    S = make_solver(dims, (4, 4, 4, 4), (4, 4, 4, 4))
+    S.set_gauge(U)
+    bad = U.copy()
+    bad[123, 2] *= np.exp(0.3j)   # unitary but det != 1
+    with pytest.raises(DflError) as e:
+        S.set_gauge(bad)
+    assert "SU(3)" in str(e.value)
+    with pytest.raises(DflError):
+        S.dirac(S.field(1))        # the gauge field is unset after the refusal
+    S.close()
