@@ -112,6 +112,8 @@ typedef struct {
     int little_eo;         /* 1: single-source little solves run GCR on the even-odd
                               reduced system (appendix A.2), falling back to A when a
                               diagonal block is not safely invertible */
+    int little_gdefl;      /* 1 (with little_eo and Ns <= 32): deflate the even-odd little
+                              system by the start fields' global modes (appendix A.3) */
 } dfl_params;
 
 typedef struct {
@@ -126,7 +128,8 @@ typedef struct {
 
 /* Fill *p with defaults: 4^4 blocks, Ns = 20, ncy = 5, nmr = 4, nkv = 16,
  * n_inviter = 3, maxiter = 1000, tol = 1e-10, little tolerances 1e-6/1e-12
- * with adapted precision and even-odd little solves on, all precisions F64,
+ * with adapted precision, even-odd little solves and their global-mode
+ * deflation on, all precisions F64,
  * solver DFL_SAP_GCR; dims are left zero. */
 void dfl_default_params(dfl_params *p);
 

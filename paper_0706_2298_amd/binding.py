@@ -32,6 +32,7 @@ class Params(ctypes.Structure):
         ("little_tol_in", ctypes.c_double), ("little_tol_out", ctypes.c_double),
         ("link_prec", ctypes.c_int), ("sap_prec", ctypes.c_int), ("little_prec", ctypes.c_int),
         ("little_grid", ctypes.c_int), ("little_adapt", ctypes.c_int), ("little_eo", ctypes.c_int),
+        ("little_gdefl", ctypes.c_int),
     ]
 
 

@@ -65,7 +65,8 @@ void free_all(dfl_ctx* c)
                     c->rho, c->acc,  c->t1,   c->t2,  c->t3,    c->s32a, c->s32b, c->s32c, c->lxi,
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
                     c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
-                    c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol, c->Mt64, c->Mt32, c->lw1, c->lw2};
+                    c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol, c->Mt64, c->Mt32, c->lw1, c->lw2,
+                    c->gsR, c->gU, c->gW, c->gQ, c->gZ, c->gQ32, c->gZ32, c->gC};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -552,7 +553,8 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
         ProfScope ps(c, DFL_PROF_LITTLE);
         if (nb == 1)
             launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, tol_dev, c->At64, c->eo_ok ? c->Mt64 : nullptr,
-                                      static_cast<c64*>(c->lw1), static_cast<c64*>(c->lw2), w, v, static_cast<c64*>(c->lr),
+                                      static_cast<c64*>(c->lw1), static_cast<c64*>(c->lw2), c->gQ, c->gZ,
+                                      c->eo_ok ? c->gdefl_n : 0, w, v, static_cast<c64*>(c->lr),
                                       static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lstats,
                                       c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
         else
@@ -566,7 +568,8 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
             ProfScope ps(c, DFL_PROF_LITTLE);
             if (nb == 1)
                 launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, tol_dev, c->At32, c->eo_ok ? c->Mt32 : nullptr,
-                                         static_cast<c32*>(c->lw1), static_cast<c32*>(c->lw2), c->lw32, c->lx32, static_cast<c32*>(c->lr),
+                                         static_cast<c32*>(c->lw1), static_cast<c32*>(c->lw2), c->gQ32, c->gZ32,
+                                         c->eo_ok ? c->gdefl_n : 0, c->lw32, c->lx32, static_cast<c32*>(c->lr),
                                          static_cast<c32*>(c->lxi), static_cast<c32*>(c->lchi), c->lpart, c->lstats,
                                          c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
             else
@@ -635,6 +638,106 @@ void prepare_eo(dfl_ctx* c)
     HIPCHECK(hipMemcpyAsync(&f, c->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     sync(c);
     c->eo_ok = (f & 1) == 0;
+}
+
+// Global-mode deflation of the even-odd little system (appendix A.3): the
+// start fields in the block basis on even blocks, u_l, their images
+// W = A_hat U, and Q = W C, Z = U C with C from Cholesky-QR applied twice so
+// that Q is orthonormal and Q = A_hat Z. The little GCR then keeps its
+// residue orthogonal to span Q. Off (gdefl_n = 0) if the even-odd system is
+// off or W is numerically rank deficient. Synchronises.
+// G = R^H R with R upper triangular, computed for the leading n' <= n columns
+// whose pivots stay above 1e-12 of the largest diagonal entry (the later
+// columns are numerically dependent on them). On return G holds R^-1 for
+// those n' columns, zero elsewhere; returns n'.
+int cholesky_inverse(std::vector<cd>& G, int n)
+{
+    std::vector<cd> R((size_t)n * n, cd(0.0, 0.0));
+    double scale = 0.0;
+    for (int i = 0; i < n; ++i)
+        scale = std::max(scale, G[(size_t)i * n + i].real());
+    int m = 0;
+    for (int j = 0; j < n; ++j) {
+        double d = G[(size_t)j * n + j].real();
+        for (int k = 0; k < j; ++k)
+            d -= std::norm(R[(size_t)k * n + j]);
+        if (!(d > 1e-12 * scale))
+            break;
+        const double rjj = std::sqrt(d);
+        R[(size_t)j * n + j] = rjj;
+        for (int i = j + 1; i < n; ++i) {
+            cd t = G[(size_t)j * n + i];
+            for (int k = 0; k < j; ++k)
+                t -= std::conj(R[(size_t)k * n + j]) * R[(size_t)k * n + i];
+            R[(size_t)j * n + i] = t / rjj;
+        }
+        m = j + 1;
+    }
+    std::vector<cd> Inv((size_t)n * n, cd(0.0, 0.0));
+    for (int col = 0; col < m; ++col)
+        for (int i = col; i >= 0; --i) {
+            cd t = (i == col) ? cd(1.0, 0.0) : cd(0.0, 0.0);
+            for (int k = i + 1; k <= col; ++k)
+                t -= R[(size_t)i * n + k] * Inv[(size_t)k * n + col];
+            Inv[(size_t)i * n + col] = t / R[(size_t)i * n + i];
+        }
+    G = Inv;
+    return m;
+}
+
+void prepare_gdefl(dfl_ctx* c)
+{
+    c->gdefl_n = 0;
+    if (!c->p.little_gdefl || !c->eo_ok || !c->gU)
+        return;
+    const int Ns = c->p.Ns;
+    const long N = (long)c->g.Nb * Ns;
+    launch_global_modes(c->g, c->gsR, Ns, c->gU, c->stream);
+    launch_zero<double>(c->gW, N * Ns, c->stream);
+    launch_zero<double>(c->gQ, N * Ns, c->stream);
+    launch_eo_hop(c->g, c->Mt64, Ns, c->gU, nullptr, c->gQ, Ns, 1, 0.0, 1.0, c->stream);  // odd: M_oe u
+    launch_eo_hop(c->g, c->Mt64, Ns, c->gQ, c->gU, c->gW, Ns, 0, 1.0, -1.0, c->stream);   // even: u - M_eo (M_oe u)
+    std::vector<cd> G((size_t)Ns * Ns);
+    int nq = Ns;
+    for (int pass = 0; pass < 2; ++pass) {
+        c64* X = pass == 0 ? c->gW : c->gQ;
+        c64* Zin = pass == 0 ? c->gU : c->gZ;
+        c64* Xout = pass == 0 ? c->gQ : c->gW;
+        c64* Zout = pass == 0 ? c->gZ : c->gU;
+        launch_gram(X, N, nq, c->gC, c->stream);
+        G.assign((size_t)nq * nq, cd(0.0, 0.0));
+        HIPCHECK(hipMemcpyAsync(G.data(), c->gC, sizeof(c64) * nq * nq, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        const int m = cholesky_inverse(G, nq);
+        if (m == 0)
+            return;
+        // keep the leading m directions: C is nq x m (the first m columns of R^-1)
+        std::vector<cd> C((size_t)nq * m);
+        for (int k = 0; k < nq; ++k)
+            for (int l = 0; l < m; ++l)
+                C[(size_t)k * m + l] = G[(size_t)k * nq + l];
+        HIPCHECK(hipMemcpyAsync(c->gC, C.data(), sizeof(c64) * nq * m, hipMemcpyHostToDevice, c->stream));
+        launch_combine(X, N, nq, m, c->gC, Xout, c->stream);
+        launch_combine(Zin, N, nq, m, c->gC, Zout, c->stream);
+        sync(c);  // C is host memory read by the copy
+        nq = m;
+    }
+    // after two passes Q, Z sit in gW, gU: swap the roles
+    std::swap(c->gQ, c->gW);
+    std::swap(c->gZ, c->gU);
+    // accept only an orthonormal Q
+    launch_gram(c->gQ, N, nq, c->gC, c->stream);
+    G.assign((size_t)nq * nq, cd(0.0, 0.0));
+    HIPCHECK(hipMemcpyAsync(G.data(), c->gC, sizeof(c64) * nq * nq, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    for (int k = 0; k < nq; ++k)
+        for (int l = 0; l < nq; ++l)
+            if (std::abs(G[(size_t)k * nq + l] - cd(k == l ? 1.0 : 0.0, 0.0)) > 1e-8)
+                return;
+    launch_c64_to_c32(c->gQ, c->gQ32, N * Ns, c->stream);
+    launch_c64_to_c32(c->gZ, c->gZ32, N * Ns, c->stream);
+    HIPCHECK(hipGetLastError());
+    c->gdefl_n = nq;
 }
 
 // Relaxed inverse iteration of eq. (5.1) on n native FP64 fields in place:
@@ -737,6 +840,7 @@ void dfl_default_params(dfl_params* p)
     p->little_grid = 0;
     p->little_adapt = 1;
     p->little_eo = 1;
+    p->little_gdefl = 1;
 }
 
 const char* dfl_last_error(void) { return dfl::g_last_error.c_str(); }
@@ -821,6 +925,16 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
             c->Mt32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
             c->lw1 = alloc_dev<c64>(c, N);
             c->lw2 = alloc_dev<c64>(c, N);
+            if (p->little_gdefl && p->Ns <= kMaxLittleDefl) {
+                c->gsR = alloc_dev<c64>(c, (size_t)c->g.Nb * p->Ns * p->Ns);
+                c->gU = alloc_dev<c64>(c, (size_t)p->Ns * N);
+                c->gW = alloc_dev<c64>(c, (size_t)p->Ns * N);
+                c->gQ = alloc_dev<c64>(c, (size_t)p->Ns * N);
+                c->gZ = alloc_dev<c64>(c, (size_t)p->Ns * N);
+                c->gQ32 = alloc_dev<c32>(c, (size_t)p->Ns * N);
+                c->gZ32 = alloc_dev<c32>(c, (size_t)p->Ns * N);
+                c->gC = alloc_dev<c64>(c, (size_t)p->Ns * p->Ns);
+            }
         }
         const long R = p->nrhs_max;
         c->xi = alloc_dev<c64>(c, (size_t)p->nkv * R * F);
@@ -948,6 +1062,7 @@ int dfl_set_mass(dfl_ctx* c, double m0)
         launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, c->p.Ns, c->stream);
         c->m0_A = m0;
         prepare_eo(c);
+        prepare_gdefl(c);
     }
     API_END
 }
@@ -1066,7 +1181,7 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     inverse_iterate(c, c->Phi, Ns, c->p.n_inviter);
     // block restriction and Gram-Schmidt, eq. (4.2)
     ProfScope ps_setup(c, DFL_PROF_SETUP);
-    launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->stream);
+    launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->gsR, c->stream);
     // little operator, eq. (A.1): block-diagonal part and the eight face
     // hops, applied to a chunk of basis fields per launch (the Krylov
     // buffer is free during the setup), then the block products with Phi
@@ -1103,6 +1218,7 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     if (flag[0] & 2)
         fail(DFL_ESINGULAR, "block Gram-Schmidt lost rank: the start fields are linearly dependent on a block");
     prepare_eo(c);
+    prepare_gdefl(c);
     c->have_subspace = true;
     API_END
 }

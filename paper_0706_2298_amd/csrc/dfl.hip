@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geom g, const c64* __restrict__
 // Modified Gram-Schmidt per block, in place, order l = 0..Ns-1 (eq. (4.2)).
 // flag is set to 1 if a block loses rank.
 __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
-                                                  int* __restrict__ flag)
+                                                  int* __restrict__ flag, c64* __restrict__ R)
 {
     __shared__ double sh[8];
     const long base = (long)blockIdx.x * g.Vb;
@@ -137,6 +137,8 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
             re = block_sum(re, sh);
             im = block_sum(im, sh);
             c64 cf{re, im};
+            if (R && threadIdx.x == 0)
+                R[((long)blockIdx.x * Ns + k) * Ns + l] = cf;
             for (int t = threadIdx.x; t < g.Vb; t += kBT)
                 for (int c = 0; c < 12; ++c) {
                     long i = tidx(base + t, c, 12);
@@ -151,6 +153,11 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
             }
         nv = sqrt(block_sum(nv, sh));
         n0 = sqrt(n0);
+        if (R && threadIdx.x == 0) {
+            R[((long)blockIdx.x * Ns + l) * Ns + l] = c64{nv, 0.0};
+            for (int k = l + 1; k < Ns; ++k)
+                R[((long)blockIdx.x * Ns + k) * Ns + l] = c64{0.0, 0.0};
+        }
         if (!(nv > rank_tol * n0) || !(n0 > 0.0)) {
             if (threadIdx.x == 0)
                 atomicOr(flag, 2);
@@ -461,6 +468,102 @@ __global__ __launch_bounds__(256) void k_little_eo_prep(Geom g, const c64* __res
     }
 }
 
+// Global modes of the little system (appendix A.3): u_l = the l-th start
+// field in the block basis, kept on even blocks: u_l[blk][k] = R[blk][k][l]
+// (the block Gram-Schmidt coefficients, psi_l = sum_k R_kl phi_k on each
+// block), zero on odd blocks.
+__global__ void k_global_modes(Geom g, const c64* __restrict__ R, int Ns, c64* __restrict__ U)
+{
+    const long N = (long)g.Nb * Ns;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N * Ns)
+        return;
+    const int l = (int)(q / N);
+    const long i = q - (long)l * N;
+    const int blk = (int)(i / Ns), k = (int)(i - (long)blk * Ns);
+    int sum = 0, rest = blk;
+    for (int mu = 3; mu >= 0; --mu) {
+        sum += rest % g.nb[mu];
+        rest /= g.nb[mu];
+    }
+    U[q] = (sum & 1) ? c64{0.0, 0.0} : R[((long)blk * Ns + k) * Ns + l];
+}
+
+// One even-odd hop for nv little vectors (stride N): on the blocks of the
+// given parity, out = alpha s + beta sum_{d=1..8} M_d in_{nbr_d} with the
+// transposed matrices Mt of the even-odd preparation; other blocks untouched.
+__global__ void k_eo_hop(Geom g, const c64* __restrict__ Mt, int Ns, const c64* __restrict__ in,
+                         const c64* __restrict__ sv, c64* __restrict__ out, int parity, double alpha, double beta)
+{
+    const long N = (long)g.Nb * Ns;
+    const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= N)
+        return;
+    in += blockIdx.y * N;
+    out += blockIdx.y * N;
+    if (sv)
+        sv += blockIdx.y * N;
+    const int blk = (int)(row / Ns), k = (int)(row - (long)blk * Ns);
+    int n[4], rest = blk, sum = 0;
+    for (int mu = 3; mu >= 0; --mu) {
+        n[mu] = rest % g.nb[mu];
+        rest /= g.nb[mu];
+        sum += n[mu];
+    }
+    if ((sum & 1) != parity)
+        return;
+    double re = 0.0, im = 0.0;
+    for (int d = 1; d < 9; ++d) {
+        const int nbr = block_nbr(g, blk, d);
+        const c64* M = Mt + ((long)blk * 9 + d) * Ns * Ns + k;
+        const c64* x = in + (long)nbr * Ns;
+        for (int l = 0; l < Ns; ++l) {
+            const c64 p = M[(long)l * Ns], q = x[l];
+            re += p.re * q.re - p.im * q.im;
+            im += p.re * q.im + p.im * q.re;
+        }
+    }
+    double yr = beta * re, yi = beta * im;
+    if (sv) {
+        yr += alpha * sv[row].re;
+        yi += alpha * sv[row].im;
+    }
+    out[row] = c64{yr, yi};
+}
+
+// G[k][l] = (X_k, X_l) for nv vectors of n entries, one workgroup per pair (fixed order)
+__global__ __launch_bounds__(256) void k_gram(const c64* __restrict__ X, long n, int nv, c64* __restrict__ G)
+{
+    __shared__ double sh[16];
+    const int k = blockIdx.x / nv, l = blockIdx.x % nv;
+    const c64* a = X + (long)k * n;
+    const c64* b = X + (long)l * n;
+    double re = 0.0, im = 0.0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) {
+        const c64 u = a[i], v = b[i];
+        re += u.re * v.re + u.im * v.im;
+        im += u.re * v.im - u.im * v.re;
+    }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (threadIdx.x == 0)
+        G[blockIdx.x] = c64{re, im};
+}
+
+// Y_l = sum_k X_k C[k][l], l < m, for nv vectors of n entries (C complex nv x m, device)
+__global__ void k_combine(const c64* __restrict__ X, long n, int nv, int m, const c64* __restrict__ C,
+                          c64* __restrict__ Y)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int l = blockIdx.y;
+    c64 s{0.0, 0.0};
+    for (int k = 0; k < nv; ++k)
+        s += X[(long)k * n + i] * C[(long)k * m + l];
+    Y[(long)l * n + i] = s;
+}
+
 __global__ void k_little_shift(Geom g, c64* A, int Ns, double dm)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -506,9 +609,9 @@ void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* 
     const long n = 12 * g.V;
     hipLaunchKernelGGL(k_prolong, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi, nrhs);
 }
-void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, hipStream_t s)
+void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_block_gs, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag);
+    hipLaunchKernelGGL(k_block_gs, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
 }
 int little_columns_max(int Ns)
 {
@@ -575,6 +678,28 @@ void launch_little_eo_prep(const Geom& g, const c64* A, int Ns, c64* Mt64, c32* 
         attr = true;
     }
     hipLaunchKernelGGL(k_little_eo_prep, dim3(g.Nb), dim3(256), lds, s, g, A, Ns, Mt64, Mt32, flag);
+}
+
+void launch_global_modes(const Geom& g, const c64* R, int Ns, c64* U, hipStream_t s)
+{
+    const long n = (long)g.Nb * Ns * Ns;
+    hipLaunchKernelGGL(k_global_modes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, R, Ns, U);
+}
+void launch_eo_hop(const Geom& g, const c64* Mt, int Ns, const c64* in, const c64* sv, c64* out, int nv, int parity,
+                   double alpha, double beta, hipStream_t s)
+{
+    const long N = (long)g.Nb * Ns;
+    hipLaunchKernelGGL(k_eo_hop, dim3((unsigned)((N + 255) / 256), nv), dim3(256), 0, s, g, Mt, Ns, in, sv, out,
+                       parity, alpha, beta);
+}
+void launch_gram(const c64* X, long n, int nv, c64* G, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gram, dim3(nv * nv), dim3(256), 0, s, X, n, nv, G);
+}
+void launch_combine(const c64* X, long n, int nv, int m, const c64* C, c64* Y, hipStream_t s)
+{
+    if (m > 0)
+        hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256), m), dim3(256), 0, s, X, n, nv, m, C, Y);
 }
 
 void launch_little_shift(const Geom& g, c64* A, int Ns, double dm, hipStream_t s)

@@ -56,6 +56,7 @@ constexpr int kMaxDot = 64;       // most vectors in one multi-dot
 constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
 constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
 constexpr int kMaxLittleRhs = 16;    // right-hand sides of one batched little solve
+constexpr int kMaxLittleDefl = 32;   // global deflation directions of the little system
 constexpr int kLittleMaxGridMulti = 256;  // workgroups of the batched little GCR (one per CU)
 
 }  // namespace dfl
@@ -85,6 +86,15 @@ struct dfl_ctx {
     dfl::c64* Mt64 = nullptr;  // even-odd little system: D^-1 and D^-1 A_d, transposed blocks
     dfl::c32* Mt32 = nullptr;
     bool eo_ok = false;        // Mt is current and every diagonal block was safely invertible
+    dfl::c64* gsR = nullptr;   // block Gram-Schmidt coefficients [Nb][Ns][Ns]
+    dfl::c64* gU = nullptr;    // global deflation of the little system: Ns vectors each
+    dfl::c64* gW = nullptr;
+    dfl::c64* gQ = nullptr;
+    dfl::c64* gZ = nullptr;
+    dfl::c32* gQ32 = nullptr;
+    dfl::c32* gZ32 = nullptr;
+    dfl::c64* gC = nullptr;    // Ns x Ns scratch (Gram matrix, transform)
+    int gdefl_n = 0;           // deflation directions in use (0: none)
     double m0_A = 0.0;
     bool have_subspace = false;
 
@@ -230,8 +240,17 @@ template <typename T> void launch_finite_check(const cpx<T>* x, long n, int* fla
 void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s);
 // psi_b = sum_k Phi_k v_b[blk][k]
 void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s);
-// block Gram-Schmidt in place on Ns fields (modified GS, order l = 0..Ns-1)
-void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, hipStream_t s);
+// block Gram-Schmidt in place on Ns fields (modified GS, order l = 0..Ns-1);
+// R (may be null): [Nb][Ns][Ns] coefficients, field l = sum_k R[k][l] basis k
+void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s);
+// global modes of the little system from R: Ns little vectors, even blocks only
+void launch_global_modes(const Geom& g, const c64* R, int Ns, c64* U, hipStream_t s);
+// on blocks of the given parity: out = alpha sv + beta sum_{d>=1} (D^-1 A_d) in_{nbr} (nv vectors)
+void launch_eo_hop(const Geom& g, const c64* Mt, int Ns, const c64* in, const c64* sv, c64* out, int nv, int parity,
+                   double alpha, double beta, hipStream_t s);
+// G[k][l] = (X_k, X_l); Y_l = sum_k X_k C[k][l] for l < m (C is nv x m)
+void launch_gram(const c64* X, long n, int nv, c64* G, hipStream_t s);
+void launch_combine(const c64* X, long n, int nv, int m, const c64* C, c64* Y, hipStream_t s);
 // A[blk][d][k][l0 + j] = (Phi_k, Y_j) over each block for k < Ns, j < nc
 // (nc <= little_columns_max(Ns), nc + Ns <= 128); part: scratch of part_cap
 // complex entries for the split partial sums (at least Nb*Ns*nc)
@@ -290,14 +309,16 @@ bool little_eo_fits(const Geom& g, int grid);
 // r, xi, chi are workspaces; stats accumulates [iterations, solves, failed]
 // With Mt non-null the GCR runs on the even-odd reduced system (appendix
 // A.2) using the matrices of launch_little_eo_prep and the workspaces w1, w2
-// (N entries each); otherwise on A itself.
+// (N entries each); otherwise on A itself. With nq > 0 (even-odd only) it is
+// deflated by the nq orthonormal little vectors Q = A_hat Z (appendix A.3).
 // cooperative = false launches it as an ordinary kernel (for graph capture):
 // the grid (at most kLittleMaxGrid workgroups, one per compute unit) is then
 // resident by construction when nothing else runs on the device, and the
 // barriers' bounded polling reports a failure rather than hang otherwise.
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev,
-                       const cpx<T>* At, const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* w,
+                       const cpx<T>* At, const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* Q, const cpx<T>* Z,
+                       int nq, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                        unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative = true);
 

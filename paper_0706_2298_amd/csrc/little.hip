@@ -30,12 +30,14 @@ constexpr int LT = 1024;            // threads per workgroup (16 wavefronts)
 constexpr long kSpinLimit = 1L << 24;  // ~0.5 s of polling before a barrier gives up
 constexpr int NK = kMaxLittleNkv;
 // partial-sum slots
-constexpr int SA = 0;                 // first pass: (chi_j, chi_k) j<k | (chi_j, r) j<k | ||chi_k||^2 | (chi_k, r)
-constexpr int SB = 2 * NK + 2;        // second pass, same layout
-constexpr int SC = 4 * NK + 4;        // ||r||^2 inside a cycle
+constexpr int NQ = kMaxLittleDefl;   // most global deflation directions of the little system
+constexpr int SA = 0;                 // first pass: (chi_j, chi_k) j<k | (chi_j, r) j<k | ||chi_k||^2 | (chi_k, r) | (Q_l, chi_k)
+constexpr int SB = 2 * NK + 2 + NQ;   // second pass, same layout
+constexpr int SC = 2 * SB;            // ||r||^2 inside a cycle
 constexpr int SR = SC + 1;            // ||r||^2 after a restart
 constexpr int SW = SC + 2;            // ||w||^2
-constexpr int NSLOT = SC + 3;
+constexpr int SQ = SC + 3;            // (Q_l, r) at the start and after a restart
+constexpr int NSLOT = SQ + NQ;
 
 template <typename T> struct LittleArgs {
     Geom g;
@@ -51,6 +53,9 @@ template <typename T> struct LittleArgs {
     cpx<T>* chi;           // nkv * N
     cpx<T>* w1;            // even-odd workspaces (N each)
     cpx<T>* w2;
+    const cpx<T>* Q;       // global deflation (appendix A.3): nq orthonormal images Q = A_hat Z
+    const cpx<T>* Z;       //   and their preimages, little vectors (even blocks)
+    int nq;
     double* part;          // NSLOT * G complex partial sums
     int* stats;            // [0] += iterations, [1] += solves, [2] |= 1 not converged, |= 4 barrier timeout
     unsigned* bar_count;   // grid barrier: arrivals (0 between barriers)
@@ -102,7 +107,7 @@ __device__ inline double2 cfma_conj(double2 acc, double ar, double ai, double br
     return acc;
 }
 
-constexpr int kMaxOwned = 2048;  // blocks one workgroup of the even-odd solver may own
+constexpr int kMaxOwned = 1024;  // blocks one workgroup of the even-odd solver may own
 
 // colour (sum of block coordinates mod 2) of block blk
 __device__ inline int block_colour(const Geom& g, int blk)
@@ -251,14 +256,15 @@ __device__ inline void partial_norm2(const LittleCtx<T>& c, const cpx<T>* __rest
 }
 
 // Partial sums of one Gram-Schmidt pass over the vector entries, one
-// wavefront per slot: (chi_j, y) and (chi_j, r) for j < k, ||y||^2 and (y, r),
-// written to part[slot0 ...][g].
+// wavefront per slot: (chi_j, y) and (chi_j, r) for j < k, ||y||^2, (y, r)
+// and (Q_l, y) for the nq global deflation directions, written to
+// part[slot0 ...][g].
 template <typename T>
 __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, int k, const cpx<T>* __restrict__ y,
                                     const cpx<T>* __restrict__ r, int slot0)
 {
     const int lane = c.t & 63, w = c.t >> 6;
-    const int ns = 2 * k + 2;
+    const int ns = 2 * k + 2 + c.a.nq;
     const int R = c.R();
     for (int s = w; s < ns; s += LT / 64) {
         const cpx<T>* u;
@@ -269,9 +275,12 @@ __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, in
         } else if (s < 2 * k) {
             u = chi + (long)(s - k) * c.N;
             v = r;
-        } else {
+        } else if (s < 2 * k + 2) {
             u = y;
             v = (s == 2 * k) ? y : r;
+        } else {
+            u = c.a.Q + (long)(s - 2 * k - 2) * c.N;
+            v = y;
         }
         double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
@@ -289,6 +298,30 @@ __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, in
     }
 }
 
+// ||v||^2 into slot sn and (Q_l, v), l < nq, into slots SQ + l (one wavefront per slot)
+template <typename T>
+__device__ inline void partial_norm2_q(const LittleCtx<T>& c, const cpx<T>* __restrict__ v, int sn)
+{
+    const int lane = c.t & 63, w = c.t >> 6;
+    const int R = c.R();
+    for (int s = w; s < 1 + c.a.nq; s += LT / 64) {
+        const cpx<T>* u = s == 0 ? v : c.a.Q + (long)(s - 1) * c.N;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int e = lane; e < R; e += 64) {
+            long i = c.entry(e);
+            cpx<T> p = u[i], q = v[i];
+            acc = cfma_conj(acc, (double)p.re, (double)p.im, (double)q.re, (double)q.im);
+        }
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
+        if (lane == 0) {
+            const int slot = s == 0 ? sn : SQ + s - 1;
+            c.a.part[((long)slot * c.G + c.g) * 2] = acc.x;
+            c.a.part[((long)slot * c.G + c.g) * 2 + 1] = acc.y;
+        }
+    }
+}
+
 // GCR on A v = w (EO = false) or on the even-odd reduced system (EO = true,
 // appendix A.2): with D the block diagonal of A and M_d = D^-1 A_d,
 //   v_e solves (1 - M_eo M_oe) v_e = (D^-1 w)_e - M_eo (D^-1 w)_o,
@@ -297,8 +330,10 @@ __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, in
 // on even blocks and the intermediate M_oe u on odd blocks.
 template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gcr(LittleArgs<T> a)
 {
-    __shared__ double red[2 * (2 * NK + 2)];
+    __shared__ double red[2 * (2 * NK + 2 + NQ)];
     __shared__ double acoef[NK][NK][2];
+    __shared__ double qcoef[NQ][NK][2];  // components of each direction's image along Q
+    __shared__ double zc[NQ][2];
     __shared__ double bcoef[NK];
     __shared__ double ccoef[NK][2];
     __shared__ double alpha[NK][2];
@@ -352,19 +387,43 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
         rhs = a.w2;
     }
 
-    // x = 0, r = rhs, ||rhs||^2
+    const int nq = a.nq;
+    // r -= Q c, x += Z c with c = red[0..2nq) (the residue leaves span Q: global deflation)
+    auto project_q = [&]() {
+        for (int e = c.t; e < R; e += LT) {
+            const long i = c.entry(e);
+            double rr = (double)a.r[i].re, ri = (double)a.r[i].im;
+            double xr = (double)a.x[i].re, xi_ = (double)a.x[i].im;
+            for (int l = 0; l < nq; ++l) {
+                const double cr = red[2 * l], ci = red[2 * l + 1];
+                const cpx<T> q = a.Q[(long)l * N + i], z = a.Z[(long)l * N + i];
+                rr -= cr * (double)q.re - ci * (double)q.im;
+                ri -= cr * (double)q.im + ci * (double)q.re;
+                xr += cr * (double)z.re - ci * (double)z.im;
+                xi_ += cr * (double)z.im + ci * (double)z.re;
+            }
+            a.r[i] = cpx<T>{(T)rr, (T)ri};
+            a.x[i] = cpx<T>{(T)xr, (T)xi_};
+        }
+    };
+
+    // x = 0, r = rhs, ||rhs||^2 and (Q, rhs); then r leaves span Q
     for (int e = c.t; e < R; e += LT) {
         long i = c.entry(e);
         a.x[i] = cpx<T>{0, 0};
         a.r[i] = rhs[i];
     }
-    partial_norm2(c, rhs, SW, sh);
+    partial_norm2_q(c, rhs, SW);
     grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
     reduce_slots(a.part, c.G, SW, 1, red);
     if (c.t == 0)
         wn2_s = red[0];
     __syncthreads();
     const double wn2 = wn2_s;
+    if (nq > 0) {
+        reduce_slots(a.part, c.G, SQ, nq, red);
+        project_q();
+    }
     int iters = 0;
     bool converged = !(wn2 > 0.0);
     bool broke = false;
@@ -393,14 +452,17 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
             // one Gram-Schmidt pass: everything needed for chi_k, c_k and the new r
             partial_pass(c, a.chi, k, ck, a.r, SA);
             grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
-            reduce_slots(a.part, c.G, SA, 2 * k + 2, red);
-            // red: [0,k) a_j; [k,2k) (chi_j, r); 2k: ||chi_k||^2; 2k+1: (chi_k, r)
+            reduce_slots(a.part, c.G, SA, 2 * k + 2 + nq, red);
+            // red: [0,k) a_j; [k,2k) (chi_j, r); 2k: ||chi_k||^2; 2k+1: (chi_k, r); [2k+2, 2k+2+nq) (Q_l, chi_k)
+            const int q0 = 2 * k + 2;
             if (c.t == 0) {
                 double n2 = red[4 * k];
                 double b2 = n2;
                 for (int j = 0; j < k; ++j)
                     b2 -= red[2 * j] * red[2 * j] + red[2 * j + 1] * red[2 * j + 1];
-                second_s = (k > 0 && !(b2 >= 0.01 * n2)) ? 1 : 0;
+                for (int l = 0; l < nq; ++l)
+                    b2 -= red[2 * (q0 + l)] * red[2 * (q0 + l)] + red[2 * (q0 + l) + 1] * red[2 * (q0 + l) + 1];
+                second_s = ((k > 0 || nq > 0) && !(b2 >= 0.01 * n2)) ? 1 : 0;
             }
             __syncthreads();
             if (second_s) {
@@ -414,19 +476,35 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
                         yr -= red[2 * j] * (double)z.re - red[2 * j + 1] * (double)z.im;
                         yi -= red[2 * j] * (double)z.im + red[2 * j + 1] * (double)z.re;
                     }
+                    for (int l = 0; l < nq; ++l) {
+                        const double qr = red[2 * (q0 + l)], qi = red[2 * (q0 + l) + 1];
+                        const cpx<T> z = a.Q[(long)l * N + i];
+                        yr -= qr * (double)z.re - qi * (double)z.im;
+                        yi -= qr * (double)z.im + qi * (double)z.re;
+                    }
                     ck[i] = cpx<T>{(T)yr, (T)yi};
                 }
                 if (c.t < k) {
                     acoef[c.t][k][0] = red[2 * c.t];
                     acoef[c.t][k][1] = red[2 * c.t + 1];
                 }
+                if (c.t < nq) {
+                    qcoef[c.t][k][0] = red[2 * (q0 + c.t)];
+                    qcoef[c.t][k][1] = red[2 * (q0 + c.t) + 1];
+                }
                 __syncthreads();
                 partial_pass(c, a.chi, k, ck, a.r, SB);
                 grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S3
-                reduce_slots(a.part, c.G, SB, 2 * k + 2, red);
-            } else if (c.t < k) {
-                acoef[c.t][k][0] = 0.0;
-                acoef[c.t][k][1] = 0.0;
+                reduce_slots(a.part, c.G, SB, 2 * k + 2 + nq, red);
+            } else {
+                if (c.t < k) {
+                    acoef[c.t][k][0] = 0.0;
+                    acoef[c.t][k][1] = 0.0;
+                }
+                if (c.t < nq) {
+                    qcoef[c.t][k][0] = 0.0;
+                    qcoef[c.t][k][1] = 0.0;
+                }
             }
             // red now holds the (last) pass: a_j, (chi_j, r), ||chi||^2, (chi, r)
             if (c.t == 0) {
@@ -441,6 +519,12 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
                     cri -= ar * qi - ai * qr;
                     acoef[j][k][0] += ar;
                     acoef[j][k][1] += ai;
+                }
+                for (int l = 0; l < nq; ++l) {
+                    const double qr = red[2 * (q0 + l)], qi = red[2 * (q0 + l) + 1];
+                    b2 -= qr * qr + qi * qi;
+                    qcoef[l][k][0] += qr;
+                    qcoef[l][k][1] += qi;
                 }
                 double b = b2 > 0.0 ? sqrt(b2) : 0.0;
                 bcoef[k] = b;
@@ -462,6 +546,12 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
                     cpx<T> z = a.chi[(long)j * N + i];
                     yr -= red[2 * j] * (double)z.re - red[2 * j + 1] * (double)z.im;
                     yi -= red[2 * j] * (double)z.im + red[2 * j + 1] * (double)z.re;
+                }
+                for (int l = 0; l < nq; ++l) {
+                    const double qr = red[2 * (q0 + l)], qi = red[2 * (q0 + l) + 1];
+                    const cpx<T> z = a.Q[(long)l * N + i];
+                    yr -= qr * (double)z.re - qi * (double)z.im;
+                    yi -= qr * (double)z.im + qi * (double)z.re;
                 }
                 yr *= inv;
                 yi *= inv;
@@ -487,6 +577,17 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
             }
         }
         __syncthreads();
+        // the direction preimages are xi_k - Z q_k: zc = sum_k q_k alpha_k
+        if (c.t < nq) {
+            double zr = 0.0, zi = 0.0;
+            for (int j = 0; j < k; ++j) {
+                zr += qcoef[c.t][j][0] * alpha[j][0] - qcoef[c.t][j][1] * alpha[j][1];
+                zi += qcoef[c.t][j][0] * alpha[j][1] + qcoef[c.t][j][1] * alpha[j][0];
+            }
+            zc[c.t][0] = zr;
+            zc[c.t][1] = zi;
+        }
+        __syncthreads();
         for (int e = c.t; e < R; e += LT) {
             long i = c.entry(e);
             double yr = (double)a.x[i].re, yi = (double)a.x[i].im;
@@ -495,6 +596,11 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
                 cpx<T> z = a.xi[(long)j * N + i];
                 yr += alpha[j][0] * (double)z.re - alpha[j][1] * (double)z.im;
                 yi += alpha[j][0] * (double)z.im + alpha[j][1] * (double)z.re;
+            }
+            for (int l = 0; l < nq; ++l) {
+                const cpx<T> z = a.Z[(long)l * N + i];
+                yr -= zc[l][0] * (double)z.re - zc[l][1] * (double)z.im;
+                yi -= zc[l][0] * (double)z.im + zc[l][1] * (double)z.re;
             }
             a.x[i] = cpx<T>{(T)yr, (T)yi};
         }
@@ -506,16 +612,30 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
             long i = c.entry(e);
             a.r[i] = cpx<T>{(T)((double)rhs[i].re - (double)a.r[i].re), (T)((double)rhs[i].im - (double)a.r[i].im)};
         }
-        partial_norm2(c, a.r, SR, sh);
+        // partial_norm2_q reads each entry from another thread than the one that wrote it
+        __syncthreads();
+        partial_norm2_q(c, a.r, SR);
         grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
         reduce_slots(a.part, c.G, SR, 1, red);
         if (c.t == 0)
             rn2_s = red[0];
         __syncthreads();
-        converged = rn2_s <= tol2 * wn2;
+        double rn2 = rn2_s;
+        if (nq > 0) {
+            // remove the residue's component in span Q (x moves along Z): ||r||^2 drops by |c|^2
+            reduce_slots(a.part, c.G, SQ, nq, red);
+            for (int l = 0; l < nq; ++l)
+                rn2 -= red[2 * l] * red[2 * l] + red[2 * l + 1] * red[2 * l + 1];
+            project_q();
+            __syncthreads();
+        }
+        converged = rn2 <= tol2 * wn2;
     }
     if (EO) {
-        // x_e is complete everywhere (a barrier followed its last update)
+        // x_e must be complete everywhere: a barrier followed its last GCR
+        // update, but not the projection along Z that may come after it
+        if (nq > 0)
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
         apply_blocks(c, l_odd, n_odd, a.Mt, 1, 9, (const cpx<T>*)a.x, (const cpx<T>*)a.w1, 1.0, -1.0, a.x, lds);
     }
     if (c.g == 0 && c.t == 0) {
@@ -1056,9 +1176,9 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
 
 template <typename T>
 void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,
-                 const cpx<T>* Mt, const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, cpx<T>* w1,
-                 cpx<T>* w2, double* part, int* stats, unsigned* bar_count, unsigned long long* bar_gen, int grid_size,
-                 hipStream_t s, bool cooperative)
+                 const cpx<T>* Mt, const cpx<T>* Q, const cpx<T>* Z, int nq, const cpx<T>* w, cpx<T>* x, cpx<T>* r,
+                 cpx<T>* xi, cpx<T>* chi, cpx<T>* w1, cpx<T>* w2, double* part, int* stats, unsigned* bar_count,
+                 unsigned long long* bar_gen, int grid_size, hipStream_t s, bool cooperative)
 {
     LittleArgs<T> a;
     a.g = g;
@@ -1076,6 +1196,9 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
     a.chi = chi;
     a.w1 = w1;
     a.w2 = w2;
+    a.Q = Mt ? Q : nullptr;
+    a.Z = Mt ? Z : nullptr;
+    a.nq = (Mt && Q && Z) ? nq : 0;
     a.part = part;
     a.stats = stats;
     a.bar_count = bar_count;
@@ -1133,12 +1256,12 @@ size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * grid_s
 
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,
-                       const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* w,
+                       const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* Q, const cpx<T>* Z, int nq, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                        unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative)
 {
-    launch_impl<T>(g, Ns, nkv, maxiter, tol, tol_dev, At, Mt, w, x, r, xi, chi, w1, w2, part, stats, bar_count, bar_gen,
-                   grid, s, cooperative);
+    launch_impl<T>(g, Ns, nkv, maxiter, tol, tol_dev, At, Mt, Q, Z, nq, w, x, r, xi, chi, w1, w2, part, stats, bar_count,
+                   bar_gen, grid, s, cooperative);
 }
 
 template <typename T>
@@ -1195,10 +1318,10 @@ INST_MULTI(float)
 #undef INST_MULTI
 
 template void launch_little_gcr<double>(const Geom&, int, int, int, double, const double*, const c64*, const c64*,
-                                        c64*, c64*, const c64*, c64*, c64*, c64*,
+                                        c64*, c64*, const c64*, const c64*, int, const c64*, c64*, c64*, c64*,
                                         c64*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
 template void launch_little_gcr<float>(const Geom&, int, int, int, double, const double*, const c32*, const c32*,
-                                       c32*, c32*, const c32*, c32*, c32*, c32*,
+                                       c32*, c32*, const c32*, const c32*, int, const c32*, c32*, c32*, c32*,
                                        c32*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
 
 }  // namespace dfl

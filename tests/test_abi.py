@@ -71,6 +71,6 @@ def test_null_context_is_einval():
 
 
 def test_params_struct_layout_matches_c():
-    # the ctypes mirror must have the C struct size: 3 int[4] + 10 int + 5 double + 3 enum + 3 int
-    assert ctypes.sizeof(binding.Params) == 152
+    # the ctypes mirror must have the C struct size: 3 int[4] + 10 int + 5 double + 3 enum + 4 int + padding
+    assert ctypes.sizeof(binding.Params) == 160
     assert ctypes.sizeof(binding.Info) == 40

@@ -454,26 +454,28 @@ def test_graph_solve_equals_direct(c1, nrhs):
 
 
 def test_little_solve_even_odd_vs_plain(c1):
-    # the even-odd reduced GCR (default) and GCR on A itself both reach the
-    # dense solution; the reduced system needs fewer iterations
-    say("little solve even-odd vs plain")
+    # GCR on the even-odd reduced system with global-mode deflation (default),
+    # without the deflation, and on A itself all reach the dense solution; each
+    # refinement needs no more iterations than the plainer form
+    say("little solve: deflated even-odd, even-odd, plain")
     torch = pytest.importorskip("torch")
     dims, b = c1["dims"], (4, 4, 4, 4)
-    ref_solver = np.linalg.solve(oracle.little_dense(c1["A"], dims, b), np.eye(1, 16 * 8, 3).ravel() * 0 + 1.0)
     its = {}
-    for eo in (1, 0):
-        S = _c1_solver(c1, little_eo=eo)
+    for eo, gd in [(1, 1), (1, 0), (0, 0)]:
+        S = _c1_solver(c1, little_eo=eo, little_gdefl=gd)
         Nb, Ns = S.Nb, S.Ns
         v = latgen.random_field((Nb, 1, 1, 1), 52).reshape(-1)[: Nb * Ns]
-        x, code, it = S.little_solve(torch.from_numpy(v.copy()).cuda(), 1e-12)
-        assert code == 0
         ref = np.linalg.solve(oracle.little_dense(c1["A"], dims, b), v)
-        assert rel(x.cpu().numpy(), ref) < 1e-9, eo
-        its[eo] = it
+        for tol in (1e-12, 1e-6):
+            x, code, it = S.little_solve(torch.from_numpy(v.copy()).cuda(), tol)
+            assert code == 0
+            err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+            assert err < (1e-9 if tol == 1e-12 else 1e-3), (eo, gd, tol, err)
+            its[(eo, gd, tol)] = it
         S.close()
-    del ref_solver
-    print("[little iterations] even-odd", its[1], "plain", its[0], flush=True)
-    assert its[1] <= its[0]
+    print("[little iterations]", its, flush=True)
+    for tol in (1e-12, 1e-6):
+        assert its[(1, 1, tol)] <= its[(1, 0, tol)] <= its[(0, 0, tol)]
 
 
 def test_set_gauge_requires_su3():
