@@ -26,7 +26,9 @@ namespace dfl {
 
 namespace {
 
-constexpr int LT = 1024;            // threads per workgroup (16 wavefronts)
+constexpr int LT = 1024;            // threads per workgroup of the many-source solver (16 wavefronts)
+constexpr int LT1 = 512;            // threads per workgroup of the single-source solver: a few blocks per
+                                    // workgroup need no more, and 512 threads leave 256 VGPRs per lane
 constexpr long kSpinLimit = 1L << 24;  // ~0.5 s of polling before a barrier gives up
 constexpr int NK = kMaxLittleNkv;
 // partial-sum slots
@@ -38,6 +40,7 @@ constexpr int SR = SC + 1;            // ||r||^2 after a restart
 constexpr int SW = SC + 2;            // ||w||^2
 constexpr int SQ = SC + 3;            // (Q_l, r) at the start and after a restart
 constexpr int NSLOT = SQ + NQ;
+static_assert(NK + NQ <= 64, "the coefficient step gives each projection one lane of a wavefront");
 
 template <typename T> struct LittleArgs {
     Geom g;
@@ -156,20 +159,44 @@ template <typename T> struct LittleCtx {
 };
 
 // reduce slots [s0, s0 + ns) over the G workgroups into red (complex), identically everywhere
+// Each wavefront reduces kSlotUnroll slots at a time so that their loads are
+// in flight together (the partial sums were written by other workgroups and
+// come from beyond the local L2).
+constexpr int kSlotUnroll = 4;
 __device__ inline void reduce_slots(const double* __restrict__ part, int G, int s0, int ns, double* red)
 {
+    constexpr int NW = LT1 / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int s = w; s < ns; s += LT / 64) {
-        double re = 0.0, im = 0.0;
-        for (int q = lane; q < G; q += 64) {
-            re += part[((long)(s0 + s) * G + q) * 2];
-            im += part[((long)(s0 + s) * G + q) * 2 + 1];
+    for (int sb = w; sb < ns; sb += NW * kSlotUnroll) {
+        double re[kSlotUnroll], im[kSlotUnroll];
+#pragma unroll
+        for (int u = 0; u < kSlotUnroll; ++u) {
+            re[u] = 0.0;
+            im[u] = 0.0;
         }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        if (lane == 0) {
-            red[2 * s] = re;
-            red[2 * s + 1] = im;
+        // slots past ns read slot ns - 1 (valid memory, result dropped): no
+        // branch separates the loads of the kSlotUnroll slots
+        for (int q = lane; q < G; q += 64) {
+            double2 v[kSlotUnroll];
+#pragma unroll
+            for (int u = 0; u < kSlotUnroll; ++u) {
+                const int s = min(sb + u * NW, ns - 1);
+                v[u] = *reinterpret_cast<const double2*>(part + ((long)(s0 + s) * G + q) * 2);
+            }
+#pragma unroll
+            for (int u = 0; u < kSlotUnroll; ++u) {
+                re[u] += v[u].x;
+                im[u] += v[u].y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSlotUnroll; ++u) {
+            const int s = sb + u * NW;
+            const double sr = wave_sum(re[u]), si = wave_sum(im[u]);
+            if (s < ns && lane == 0) {
+                red[2 * s] = sr;
+                red[2 * s + 1] = si;
+            }
         }
     }
     __syncthreads();
@@ -180,7 +207,8 @@ __device__ inline void reduce_slots(const double* __restrict__ part, int G, int 
 // stored transposed, Mat[blk][d][l][k] = (block d of blk)[k][l]. Task
 // (block, d, k) forms one term of row k (Ns multiply-adds over l, reading Mat
 // coalesced in k); the terms of a row are summed from LDS in a fixed order.
-// Blocks are processed LT / ((d1 - d0) Ns) at a time; lds holds 2 LT doubles.
+// Blocks are processed LT1 / ((d1 - d0) Ns) at a time; lds holds 2 LT1 doubles.
+constexpr int kApplyChunk = 10;
 template <typename T>
 __device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int nlist, const cpx<T>* __restrict__ Mat,
                                     int d0, int d1, const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ s,
@@ -190,7 +218,7 @@ __device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int 
     const int Ns = c.a.Ns;
     const int nd = d1 - d0;
     const int per = nd * Ns;
-    const int bpr = per <= LT ? LT / per : 1;
+    const int bpr = per <= LT1 ? LT1 / per : 1;
     for (int i0 = 0; i0 < nlist; i0 += bpr) {
         {
             const int task = c.t;
@@ -204,19 +232,30 @@ __device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int 
                 const cpx<T>* M = Mat + ((long)blk * 9 + d) * Ns * Ns + k;
                 const cpx<T>* vv = u + (long)nbr * Ns;
                 double re = 0.0, im = 0.0;
-#pragma unroll 20
-                for (int l = 0; l < Ns; ++l) {
-                    cpx<T> p = M[(long)l * Ns];
-                    cpx<T> q = vv[l];
-                    re += (double)p.re * (double)q.re - (double)p.im * (double)q.im;
-                    im += (double)p.re * (double)q.im + (double)p.im * (double)q.re;
+                // kApplyChunk loads of M and of u are issued before their
+                // multiply-adds, so the chunk costs one memory round trip
+                for (int l0 = 0; l0 < Ns; l0 += kApplyChunk) {
+                    cpx<T> mv[kApplyChunk], uv[kApplyChunk];
+#pragma unroll
+                    for (int q = 0; q < kApplyChunk; ++q)
+                        if (l0 + q < Ns) {
+                            mv[q] = M[(long)(l0 + q) * Ns];
+                            uv[q] = vv[l0 + q];
+                        }
+#pragma unroll
+                    for (int q = 0; q < kApplyChunk; ++q)
+                        if (l0 + q < Ns) {
+                            const cpx<T> p = mv[q], w = uv[q];
+                            re += (double)p.re * (double)w.re - (double)p.im * (double)w.im;
+                            im += (double)p.re * (double)w.im + (double)p.im * (double)w.re;
+                        }
                 }
                 lds[2 * task] = re;
                 lds[2 * task + 1] = im;
             }
         }
         __syncthreads();
-        for (int q = c.t; q < bpr * Ns; q += LT) {
+        for (int q = c.t; q < bpr * Ns; q += LT1) {
             const int jb = q / Ns, kk = q - jb * Ns;
             if (i0 + jb < nlist) {
                 double sr = 0.0, si = 0.0;
@@ -244,7 +283,7 @@ __device__ inline void partial_norm2(const LittleCtx<T>& c, const cpx<T>* __rest
 {
     double s = 0.0;
     const int R = c.R();
-    for (int e = c.t; e < R; e += LT) {
+    for (int e = c.t; e < R; e += LT1) {
         cpx<T> z = v[c.entry(e)];
         s += (double)z.re * (double)z.re + (double)z.im * (double)z.im;
     }
@@ -263,37 +302,56 @@ template <typename T>
 __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, int k, const cpx<T>* __restrict__ y,
                                     const cpx<T>* __restrict__ r, int slot0)
 {
+    constexpr int NW = LT1 / 64;
     const int lane = c.t & 63, w = c.t >> 6;
     const int ns = 2 * k + 2 + c.a.nq;
     const int R = c.R();
-    for (int s = w; s < ns; s += LT / 64) {
-        const cpx<T>* u;
-        const cpx<T>* v;
-        if (s < k) {
-            u = chi + (long)s * c.N;
-            v = y;
-        } else if (s < 2 * k) {
-            u = chi + (long)(s - k) * c.N;
-            v = r;
-        } else if (s < 2 * k + 2) {
-            u = y;
-            v = (s == 2 * k) ? y : r;
-        } else {
-            u = c.a.Q + (long)(s - 2 * k - 2) * c.N;
-            v = y;
+    // kSlotUnroll slots per wavefront at a time, their loads in flight together
+    for (int sb = w; sb < ns; sb += NW * kSlotUnroll) {
+        double2 acc[kSlotUnroll];
+        const cpx<T>* p[kSlotUnroll];
+        const cpx<T>* q[kSlotUnroll];
+#pragma unroll
+        for (int u = 0; u < kSlotUnroll; ++u) {
+            acc[u] = make_double2(0.0, 0.0);
+            const int s = sb + u * NW;  // slots past ns read y (result dropped)
+            if (s < k) {
+                p[u] = chi + (long)s * c.N;
+                q[u] = y;
+            } else if (s < 2 * k) {
+                p[u] = chi + (long)(s - k) * c.N;
+                q[u] = r;
+            } else if (s < 2 * k + 2) {
+                p[u] = y;
+                q[u] = (s == 2 * k) ? y : r;
+            } else if (s < ns) {
+                p[u] = c.a.Q + (long)(s - 2 * k - 2) * c.N;
+                q[u] = y;
+            } else {
+                p[u] = y;
+                q[u] = y;
+            }
         }
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
         for (int e = lane; e < R; e += 64) {
-            long i = c.entry(e);
-            cpx<T> p = u[i], q = v[i];
-            acc = cfma_conj(acc, (double)p.re, (double)p.im, (double)q.re, (double)q.im);
+            const long i = c.entry(e);
+            cpx<T> pv[kSlotUnroll], qv[kSlotUnroll];
+#pragma unroll
+            for (int u = 0; u < kSlotUnroll; ++u) {
+                pv[u] = p[u][i];
+                qv[u] = q[u][i];
+            }
+#pragma unroll
+            for (int u = 0; u < kSlotUnroll; ++u)
+                acc[u] = cfma_conj(acc[u], (double)pv[u].re, (double)pv[u].im, (double)qv[u].re, (double)qv[u].im);
         }
-        acc.x = wave_sum(acc.x);
-        acc.y = wave_sum(acc.y);
-        if (lane == 0) {
-            c.a.part[((long)(slot0 + s) * c.G + c.g) * 2] = acc.x;
-            c.a.part[((long)(slot0 + s) * c.G + c.g) * 2 + 1] = acc.y;
+#pragma unroll
+        for (int u = 0; u < kSlotUnroll; ++u) {
+            const int s = sb + u * NW;
+            const double sr = wave_sum(acc[u].x), si = wave_sum(acc[u].y);
+            if (s < ns && lane == 0) {
+                c.a.part[((long)(slot0 + s) * c.G + c.g) * 2] = sr;
+                c.a.part[((long)(slot0 + s) * c.G + c.g) * 2 + 1] = si;
+            }
         }
     }
 }
@@ -304,7 +362,7 @@ __device__ inline void partial_norm2_q(const LittleCtx<T>& c, const cpx<T>* __re
 {
     const int lane = c.t & 63, w = c.t >> 6;
     const int R = c.R();
-    for (int s = w; s < 1 + c.a.nq; s += LT / 64) {
+    for (int s = w; s < 1 + c.a.nq; s += LT1 / 64) {
         const cpx<T>* u = s == 0 ? v : c.a.Q + (long)(s - 1) * c.N;
         double2 acc = make_double2(0.0, 0.0);
         for (int e = lane; e < R; e += 64) {
@@ -322,13 +380,67 @@ __device__ inline void partial_norm2_q(const LittleCtx<T>& c, const cpx<T>* __re
     }
 }
 
+// For each of the workgroup's entries e (entry index i): out(e, i, sr, si)
+// with sr + i si = sum_{j < nterm} cf(j) v(j)[i], cf(j) a complex coefficient
+// (double2) and v(j) a little vector. When the workgroup has few entries the
+// terms of an entry are split over thread groups whose partial sums meet in
+// lds (2 LT1 doubles, summed in a fixed order); loads are issued four terms
+// at a time. Ends with a workgroup barrier.
+constexpr int kTermChunk = 4;
+template <typename T, typename CF, typename VF, typename OUT>
+__device__ inline void combine_terms(const LittleCtx<T>& c, int nterm, CF cf, VF vf, double* lds, OUT out)
+{
+    const int R = c.R();
+    const int ng = R > 0 ? max(1, min(LT1 / R, (nterm + kTermChunk - 1) / kTermChunk)) : 1;
+    const int per = (nterm + ng - 1) / ng;
+    for (int t = c.t; t < ng * R; t += LT1) {
+        const int gq = t / R, e = t - gq * R;
+        const long i = c.entry(e);
+        double sr = 0.0, si = 0.0;
+        const int ja = gq * per, jz = min(nterm, ja + per);
+        for (int jb = ja; jb < jz; jb += kTermChunk) {
+            cpx<T> zv[kTermChunk];
+            double2 cv[kTermChunk];
+#pragma unroll
+            for (int u = 0; u < kTermChunk; ++u) {
+                const int j = min(jb + u, jz - 1);  // past jz: a valid term with coefficient 0
+                cv[u] = jb + u < jz ? cf(j) : make_double2(0.0, 0.0);
+                zv[u] = vf(j)[i];
+            }
+#pragma unroll
+            for (int u = 0; u < kTermChunk; ++u) {
+                sr += cv[u].x * (double)zv[u].re - cv[u].y * (double)zv[u].im;
+                si += cv[u].x * (double)zv[u].im + cv[u].y * (double)zv[u].re;
+            }
+        }
+        if (ng > 1) {
+            lds[2 * t] = sr;
+            lds[2 * t + 1] = si;
+        } else {
+            out(e, i, sr, si);
+        }
+    }
+    if (ng > 1) {
+        __syncthreads();
+        for (int e = c.t; e < R; e += LT1) {
+            double sr = 0.0, si = 0.0;
+            for (int gq = 0; gq < ng; ++gq) {
+                sr += lds[2 * (gq * R + e)];
+                si += lds[2 * (gq * R + e) + 1];
+            }
+            out(e, c.entry(e), sr, si);
+        }
+    }
+    __syncthreads();
+}
+
 // GCR on A v = w (EO = false) or on the even-odd reduced system (EO = true,
 // appendix A.2): with D the block diagonal of A and M_d = D^-1 A_d,
 //   v_e solves (1 - M_eo M_oe) v_e = (D^-1 w)_e - M_eo (D^-1 w)_o,
 //   v_o = (D^-1 w)_o - M_oe v_e.
 // Even-odd workspaces: w1 = D^-1 w (all blocks); w2 holds the reduced source
 // on even blocks and the intermediate M_oe u on odd blocks.
-template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gcr(LittleArgs<T> a)
+template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_gcr(LittleArgs<T> a)
 {
     __shared__ double red[2 * (2 * NK + 2 + NQ)];
     __shared__ double acoef[NK][NK][2];
@@ -340,7 +452,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
     __shared__ double sh[16];
     __shared__ double wn2_s, rn2_s;
     __shared__ int second_s;
-    __shared__ double lds[2 * LT];
+    __shared__ double lds[2 * LT1];
     __shared__ int l_even[EO ? kMaxOwned : 1], l_odd[EO ? kMaxOwned : 1];
     __shared__ int n_even_s, n_odd_s;
 
@@ -390,25 +502,17 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
     const int nq = a.nq;
     // r -= Q c, x += Z c with c = red[0..2nq) (the residue leaves span Q: global deflation)
     auto project_q = [&]() {
-        for (int e = c.t; e < R; e += LT) {
-            const long i = c.entry(e);
-            double rr = (double)a.r[i].re, ri = (double)a.r[i].im;
-            double xr = (double)a.x[i].re, xi_ = (double)a.x[i].im;
-            for (int l = 0; l < nq; ++l) {
-                const double cr = red[2 * l], ci = red[2 * l + 1];
-                const cpx<T> q = a.Q[(long)l * N + i], z = a.Z[(long)l * N + i];
-                rr -= cr * (double)q.re - ci * (double)q.im;
-                ri -= cr * (double)q.im + ci * (double)q.re;
-                xr += cr * (double)z.re - ci * (double)z.im;
-                xi_ += cr * (double)z.im + ci * (double)z.re;
-            }
-            a.r[i] = cpx<T>{(T)rr, (T)ri};
-            a.x[i] = cpx<T>{(T)xr, (T)xi_};
-        }
+        auto cq = [&](int l) { return make_double2(red[2 * l], red[2 * l + 1]); };
+        combine_terms(c, nq, cq, [&](int l) { return a.Q + (long)l * N; }, lds, [&](int, long i, double sr, double si) {
+            a.r[i] = cpx<T>{(T)((double)a.r[i].re - sr), (T)((double)a.r[i].im - si)};
+        });
+        combine_terms(c, nq, cq, [&](int l) { return a.Z + (long)l * N; }, lds, [&](int, long i, double sr, double si) {
+            a.x[i] = cpx<T>{(T)((double)a.x[i].re + sr), (T)((double)a.x[i].im + si)};
+        });
     };
 
     // x = 0, r = rhs, ||rhs||^2 and (Q, rhs); then r leaves span Q
-    for (int e = c.t; e < R; e += LT) {
+    for (int e = c.t; e < R; e += LT1) {
         long i = c.entry(e);
         a.x[i] = cpx<T>{0, 0};
         a.r[i] = rhs[i];
@@ -436,7 +540,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
             cpx<T>* xk = a.xi + (long)k * N;
             cpx<T>* ck = a.chi + (long)k * N;
             // xi_k = r on the vector entries, and the partial ||r||^2
-            for (int e = c.t; e < R; e += LT) {
+            for (int e = c.t; e < R; e += LT1) {
                 long i = c.entry(e);
                 xk[i] = a.r[i];
             }
@@ -455,19 +559,20 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
             reduce_slots(a.part, c.G, SA, 2 * k + 2 + nq, red);
             // red: [0,k) a_j; [k,2k) (chi_j, r); 2k: ||chi_k||^2; 2k+1: (chi_k, r); [2k+2, 2k+2+nq) (Q_l, chi_k)
             const int q0 = 2 * k + 2;
-            if (c.t == 0) {
-                double n2 = red[4 * k];
-                double b2 = n2;
-                for (int j = 0; j < k; ++j)
-                    b2 -= red[2 * j] * red[2 * j] + red[2 * j + 1] * red[2 * j + 1];
-                for (int l = 0; l < nq; ++l)
-                    b2 -= red[2 * (q0 + l)] * red[2 * (q0 + l)] + red[2 * (q0 + l) + 1] * red[2 * (q0 + l) + 1];
-                second_s = ((k > 0 || nq > 0) && !(b2 >= 0.01 * n2)) ? 1 : 0;
+            // the k + nq <= 64 projections are spread over the lanes of wavefront 0
+            if (c.t < 64) {
+                const int ri = c.t < k ? 2 * c.t : 2 * (q0 + c.t - k);
+                const double m2 = c.t < k + nq ? red[ri] * red[ri] + red[ri + 1] * red[ri + 1] : 0.0;
+                const double p2 = wave_sum(m2);
+                if (c.t == 0) {
+                    const double n2 = red[4 * k];
+                    second_s = ((k > 0 || nq > 0) && !(n2 - p2 >= 0.01 * n2)) ? 1 : 0;
+                }
             }
             __syncthreads();
             if (second_s) {
                 // heavy cancellation: subtract the first projections, then a second pass
-                for (int e = c.t; e < R; e += LT) {
+                for (int e = c.t; e < R; e += LT1) {
                     long i = c.entry(e);
                     double yr = (double)ck[i].re, yi = (double)ck[i].im;
 #pragma unroll 8
@@ -507,29 +612,37 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
                 }
             }
             // red now holds the (last) pass: a_j, (chi_j, r), ||chi||^2, (chi, r)
-            if (c.t == 0) {
-                double b2 = red[4 * k];
-                double crr = red[4 * k + 2], cri = red[4 * k + 3];
-                for (int j = 0; j < k; ++j) {
-                    double ar = red[2 * j], ai = red[2 * j + 1];
-                    double qr = red[2 * (k + j)], qi = red[2 * (k + j) + 1];
-                    b2 -= ar * ar + ai * ai;
+            if (c.t < 64) {
+                // lane j < k: chi_j; lane k + l: Q_l
+                double m2 = 0.0, dr = 0.0, di = 0.0;
+                if (c.t < k) {
+                    const int j = c.t;
+                    const double ar = red[2 * j], ai = red[2 * j + 1];
+                    const double qr = red[2 * (k + j)], qi = red[2 * (k + j) + 1];
+                    m2 = ar * ar + ai * ai;
                     // (chi - sum a_j chi_j, r) = (chi, r) - sum conj(a_j) (chi_j, r)
-                    crr -= ar * qr + ai * qi;
-                    cri -= ar * qi - ai * qr;
+                    dr = ar * qr + ai * qi;
+                    di = ar * qi - ai * qr;
                     acoef[j][k][0] += ar;
                     acoef[j][k][1] += ai;
-                }
-                for (int l = 0; l < nq; ++l) {
+                } else if (c.t < k + nq) {
+                    const int l = c.t - k;
                     const double qr = red[2 * (q0 + l)], qi = red[2 * (q0 + l) + 1];
-                    b2 -= qr * qr + qi * qi;
+                    m2 = qr * qr + qi * qi;
                     qcoef[l][k][0] += qr;
                     qcoef[l][k][1] += qi;
                 }
-                double b = b2 > 0.0 ? sqrt(b2) : 0.0;
-                bcoef[k] = b;
-                ccoef[k][0] = b > 0.0 ? crr / b : 0.0;
-                ccoef[k][1] = b > 0.0 ? cri / b : 0.0;
+                m2 = wave_sum(m2);
+                dr = wave_sum(dr);
+                di = wave_sum(di);
+                if (c.t == 0) {
+                    const double b2 = red[4 * k] - m2;
+                    const double crr = red[4 * k + 2] - dr, cri = red[4 * k + 3] - di;
+                    const double b = b2 > 0.0 ? sqrt(b2) : 0.0;
+                    bcoef[k] = b;
+                    ccoef[k][0] = b > 0.0 ? crr / b : 0.0;
+                    ccoef[k][1] = b > 0.0 ? cri / b : 0.0;
+                }
             }
             __syncthreads();
             const double b = bcoef[k];
@@ -538,28 +651,21 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
                 break;
             }
             const double inv = 1.0 / b, cr0 = ccoef[k][0], ci0 = ccoef[k][1];
-            for (int e = c.t; e < R; e += LT) {
-                long i = c.entry(e);
-                double yr = (double)ck[i].re, yi = (double)ck[i].im;
-#pragma unroll 8
-                for (int j = 0; j < k; ++j) {
-                    cpx<T> z = a.chi[(long)j * N + i];
-                    yr -= red[2 * j] * (double)z.re - red[2 * j + 1] * (double)z.im;
-                    yi -= red[2 * j] * (double)z.im + red[2 * j + 1] * (double)z.re;
-                }
-                for (int l = 0; l < nq; ++l) {
-                    const double qr = red[2 * (q0 + l)], qi = red[2 * (q0 + l) + 1];
-                    const cpx<T> z = a.Q[(long)l * N + i];
-                    yr -= qr * (double)z.re - qi * (double)z.im;
-                    yi -= qr * (double)z.im + qi * (double)z.re;
-                }
-                yr *= inv;
-                yi *= inv;
-                ck[i] = cpx<T>{(T)yr, (T)yi};
-                double rr = (double)a.r[i].re - (cr0 * yr - ci0 * yi);
-                double ri = (double)a.r[i].im - (cr0 * yi + ci0 * yr);
-                a.r[i] = cpx<T>{(T)rr, (T)ri};
-            }
+            // chi_k -= sum_j a_j chi_j + sum_l q_l Q_l, then normalise; r -= c_k chi_k
+            combine_terms(
+                c, k + nq,
+                [&](int j) {
+                    const int ri = j < k ? 2 * j : 2 * (q0 + j - k);
+                    return make_double2(red[ri], red[ri + 1]);
+                },
+                [&](int j) { return j < k ? a.chi + (long)j * N : a.Q + (long)(j - k) * N; }, lds,
+                [&](int, long i, double sr, double si) {
+                    double yr = ((double)ck[i].re - sr) * inv, yi = ((double)ck[i].im - si) * inv;
+                    ck[i] = cpx<T>{(T)yr, (T)yi};
+                    double rr = (double)a.r[i].re - (cr0 * yr - ci0 * yi);
+                    double ri = (double)a.r[i].im - (cr0 * yi + ci0 * yr);
+                    a.r[i] = cpx<T>{(T)rr, (T)ri};
+                });
             ++iters;
             __syncthreads();
         }
@@ -588,27 +694,21 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gc
             zc[c.t][1] = zi;
         }
         __syncthreads();
-        for (int e = c.t; e < R; e += LT) {
-            long i = c.entry(e);
-            double yr = (double)a.x[i].re, yi = (double)a.x[i].im;
-#pragma unroll 8
-            for (int j = 0; j < k; ++j) {
-                cpx<T> z = a.xi[(long)j * N + i];
-                yr += alpha[j][0] * (double)z.re - alpha[j][1] * (double)z.im;
-                yi += alpha[j][0] * (double)z.im + alpha[j][1] * (double)z.re;
-            }
-            for (int l = 0; l < nq; ++l) {
-                const cpx<T> z = a.Z[(long)l * N + i];
-                yr -= zc[l][0] * (double)z.re - zc[l][1] * (double)z.im;
-                yi -= zc[l][0] * (double)z.im + zc[l][1] * (double)z.re;
-            }
-            a.x[i] = cpx<T>{(T)yr, (T)yi};
-        }
+        // x += sum_j alpha_j xi_j - sum_l zc_l Z_l
+        combine_terms(
+            c, k + nq,
+            [&](int j) {
+                return j < k ? make_double2(alpha[j][0], alpha[j][1]) : make_double2(-zc[j - k][0], -zc[j - k][1]);
+            },
+            [&](int j) { return j < k ? a.xi + (long)j * N : a.Z + (long)(j - k) * N; }, lds,
+            [&](int, long i, double sr, double si) {
+                a.x[i] = cpx<T>{(T)((double)a.x[i].re + sr), (T)((double)a.x[i].im + si)};
+            });
         // recompute r = rhs - op(x)
         grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
         op(a.x, a.r);
         __syncthreads();
-        for (int e = c.t; e < R; e += LT) {
+        for (int e = c.t; e < R; e += LT1) {
             long i = c.entry(e);
             a.r[i] = cpx<T>{(T)((double)rhs[i].re - (double)a.r[i].re), (T)((double)rhs[i].im - (double)a.r[i].im)};
         }
@@ -1207,14 +1307,14 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
                         : reinterpret_cast<const void*>(&k_little_gcr<T, false>);
     if (!cooperative) {
         if (Mt)
-            hipLaunchKernelGGL((k_little_gcr<T, true>), dim3(grid_size), dim3(LT), 0, s, a);
+            hipLaunchKernelGGL((k_little_gcr<T, true>), dim3(grid_size), dim3(LT1), 0, s, a);
         else
-            hipLaunchKernelGGL((k_little_gcr<T, false>), dim3(grid_size), dim3(LT), 0, s, a);
+            hipLaunchKernelGGL((k_little_gcr<T, false>), dim3(grid_size), dim3(LT1), 0, s, a);
         HIPCHECK(hipGetLastError());
         return;
     }
     void* args[] = {&a};
-    HIPCHECK(hipLaunchCooperativeKernel(fn, dim3(grid_size), dim3(LT), args, 0, s));
+    HIPCHECK(hipLaunchCooperativeKernel(fn, dim3(grid_size), dim3(LT1), args, 0, s));
 }
 
 }  // namespace
