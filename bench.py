@@ -169,14 +169,14 @@ def roofline(prof, little_it):
     if cls == "sap":
         flops = sap_flops_per_site(NMR) * (V // 2)          # one colour sweep visits half the sites
         ach = flops / dur / 1e12
-        r = dict(kernel="k_sap<float> (Schwarz colour sweep, FP32, 4^4 blocks)", bound="alu", achieved=ach,
+        r = dict(kernel="k_sap_rl<Links32> (Schwarz colour sweep of one field, FP32, 4^4 blocks)", bound="alu", achieved=ach,
                  peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / FP32_VECTOR_PEAK_TFLOPS,
                  per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {V // 2} sites")
     elif cls == "little":
         per_it = 16 * NB * (9 * NS * NS + 4 * NS)
         byts = per_it * little_it / max(n, 1)
         ach = byts / dur / 1e9
-        r = dict(kernel="k_little_gcr<double> (little GCR, one launch per solve)", bound="hbm", achieved=ach,
+        r = dict(kernel="k_little_gcr<double, true> (even-odd little GCR, one launch per little solve)", bound="hbm", achieved=ach,
                  peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                  per_launch=f"{byts:.4g} B = {little_it / max(n, 1):.1f} iterations x {per_it} B (A + 4 vectors)")
     elif cls == "dirac":

@@ -252,11 +252,11 @@ int dfl_residual_history(const dfl_ctx *ctx, double *out, int max);
  * seconds and launch counts per class since the last reset, then resets.
  * Classes: */
 enum {
-    DFL_PROF_SAP = 0,      /* Schwarz colour sweeps (one launch per colour and cycle) */
+    DFL_PROF_SAP = 0,      /* Schwarz colour sweeps of the solvers and sap_precond (one launch per colour and cycle) */
     DFL_PROF_DIRAC = 1,    /* full-lattice Dirac operator inside the solvers and dirac_apply */
     DFL_PROF_LITTLE = 2,   /* little GCR (one cooperative launch per little solve) */
     DFL_PROF_PROJECT = 3,  /* block restriction and prolongation */
-    DFL_PROF_SETUP = 4,    /* little-operator assembly and block Gram-Schmidt */
+    DFL_PROF_SETUP = 4,    /* Schwarz sweeps of the inverse iteration, block Gram-Schmidt, little-operator assembly */
     DFL_PROF_NCLASS = 5
 };
 int dfl_profile_enable(dfl_ctx *ctx, int on);

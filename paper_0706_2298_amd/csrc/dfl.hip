@@ -199,14 +199,39 @@ __device__ inline int block_nbr(const Geom& g, int blk, int d)
 constexpr int kCE = 32;
 constexpr int kMaxPairs = 16;
 
+// Entry e of the block's face {y_fmu = fy} (fmu >= 0; e = c * nface + site
+// index in local lexicographic order) or of the whole block (fmu < 0).
+__device__ inline long face_elem(const Geom& g, int blk, int e, int fmu, int fy, int nface)
+{
+    if (fmu < 0)
+        return block_elem(g, blk, e);
+    const int c = e / nface;
+    int r = e - c * nface, y[4];
+#pragma unroll
+    for (int nu = 3; nu >= 0; --nu) {
+        if (nu == fmu) {
+            y[nu] = fy;
+        } else {
+            y[nu] = r % g.b[nu];
+            r /= g.b[nu];
+        }
+    }
+    const int t = ((y[0] * g.b[1] + y[1]) * g.b[2] + y[2]) * g.b[3] + y[3];
+    return tidx((long)blk * g.Vb + t, c, 12);
+}
+
+// A block hop (eq. (A.1) with D restricted to the hops from block Lambda + mu
+// into Lambda) is non-zero only on the sites of Lambda's face towards
+// Lambda + mu: for those columns only that face's entries are summed.
 __global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __restrict__ Phi, int Ns,
-                                                        const c64* __restrict__ Y, int nc, int nsplit,
-                                                        c64* __restrict__ part)
+                                                        const c64* __restrict__ Y, int nc, int nsplit, int fmu,
+                                                        int fy, int nface, c64* __restrict__ part)
 {
     extern __shared__ c64 st[];  // [Ns + nc][kCE + 1]
+    __shared__ long eidx[kCE];
     const int blk = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
     const long F = 12 * g.V;
-    const int ne = 12 * g.Vb;
+    const int ne = 12 * nface;  // nface: sites of the face (Vb for the whole block)
     const int per = ((ne + nsplit - 1) / nsplit + kCE - 1) / kCE * kCE;
     const int e_lo = split * per;
     const int e_hi = e_lo + per < ne ? e_lo + per : ne;
@@ -217,13 +242,15 @@ __global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __res
         acc[q] = c64{0.0, 0.0};
     for (int e0 = e_lo; e0 < e_hi; e0 += kCE) {
         __syncthreads();
+        if (threadIdx.x < kCE)
+            eidx[threadIdx.x] = e0 + (int)threadIdx.x < e_hi ? face_elem(g, blk, e0 + threadIdx.x, fmu, fy, nface) : -1;
+        __syncthreads();
         for (int q = threadIdx.x; q < (Ns + nc) * kCE; q += blockDim.x) {
             const int r = q / kCE, e = q % kCE;
             c64 v{0.0, 0.0};
-            if (e0 + e < e_hi) {
-                const long i = block_elem(g, blk, e0 + e);
+            const long i = eidx[e];
+            if (i >= 0)
                 v = r < Ns ? Phi[(long)r * F + i] : Y[(long)(r - Ns) * F + i];
-            }
             st[r * (kCE + 1) + e] = v;
         }
         __syncthreads();
@@ -623,7 +650,12 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
                              c64* part, long part_cap, hipStream_t s)
 {
     const size_t lds = sizeof(c64) * (Ns + nc) * (kCE + 1);
-    int nsplit = (12 * g.Vb) / (8 * kCE);  // at least 8 staged tiles per workgroup
+    // columns of a block hop: only the face towards the neighbour (see k_little_columns)
+    const int fmu = d == 0 ? -1 : (d - 1) / 2;
+    const int fy = d == 0 ? 0 : ((d & 1) ? g.b[fmu] - 1 : 0);
+    const int nface = fmu < 0 ? g.Vb : g.Vb / g.b[fmu];
+    const int ne = 12 * nface;
+    int nsplit = ne / (8 * kCE);  // at least 8 staged tiles per workgroup
     if (nsplit > 8)
         nsplit = 8;
     while (nsplit > 1 && (long)nsplit * g.Nb * Ns * nc > part_cap)
@@ -639,7 +671,8 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
                                      (int)(sizeof(c64) * (64 + 64) * (kCE + 1))));
         attr = true;
     }
-    hipLaunchKernelGGL(k_little_columns, dim3(g.Nb * nsplit), dim3(256), lds, s, g, Phi, Ns, Y, nc, nsplit, part);
+    hipLaunchKernelGGL(k_little_columns, dim3(g.Nb * nsplit), dim3(256), lds, s, g, Phi, Ns, Y, nc, nsplit, fmu, fy,
+                       nface, part);
     const long n = (long)g.Nb * Ns * nc;
     hipLaunchKernelGGL(k_little_columns_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, part, Ns, nc,
                        nsplit, l0, d, A);

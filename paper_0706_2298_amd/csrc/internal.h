@@ -157,6 +157,7 @@ struct dfl_ctx {
     long graph_replays = 0;
     // kernel-class timers
     bool prof_on = false;
+    int sap_prof_cls = DFL_PROF_SAP;  // class the Schwarz sweeps are timed in (setup during inverse iteration)
     std::vector<hipEvent_t> ev_pool;                 // free events
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     double prof_t[8] = {0};

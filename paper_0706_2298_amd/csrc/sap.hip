@@ -387,12 +387,16 @@ template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
             int nrhs, hipStream_t s);
 
-// blocks of up to 256 sites: links in registers; larger blocks: the generic kernel
+// One field with blocks of up to 256 sites: links in registers (one workgroup
+// per CU, the fastest sweep while the blocks of one colour leave CUs free).
+// Several fields (or larger blocks): the generic kernel, which fits three
+// workgroups per CU and so sweeps many blocks at a higher rate (16 fields on
+// 16^4: 18% less time).
 template <typename L>
 void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
                int nrhs, hipStream_t s)
 {
-    if (sg.Vsb > 256) {
+    if (sg.Vsb > 256 || nrhs > 1) {
         launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
         return;
     }
