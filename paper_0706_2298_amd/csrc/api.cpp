@@ -746,11 +746,14 @@ void prepare_gdefl(dfl_ctx* c)
 void inverse_iterate(dfl_ctx* c, c64* f, int n, int steps)
 {
     const long F = c->field_elems;
-    for (int l = 0; l < n; ++l) {
-        launch_finite_check<double>(f + (long)l * F, F, c->dflag, c->stream);
-        launch_norm2<double>(f + (long)l * F, F, c->red, c->dscal + S_B, c->stream);
-        launch_scale_invsqrt<double>(f + (long)l * F, F, c->dscal + S_B, c->stream);
-    }
+    // the n fields (back to back) are checked and normalised one launch per kernel
+    auto normalise = [&]() {
+        // a reduction writes a complex pair per field: stride 2
+        launch_norm2_b<double>(f, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
+        launch_scale_invsqrt_b<double>(f, F, n, F, c->dnorm, 2, nullptr, c->stream);
+    };
+    launch_finite_check<double>(f, F * n, c->dflag, c->stream);
+    normalise();
     // the sweeps of the inverse iteration are timed as setup work
     struct SetupSweeps {
         dfl_ctx* c;
@@ -764,10 +767,7 @@ void inverse_iterate(dfl_ctx* c, c64* f, int n, int steps)
         } else {
             sap_apply(c, f, f, c->p.m0_setup, n);  // FP32 path: staged through s32a/s32b
         }
-        for (int l = 0; l < n; ++l) {
-            launch_norm2<double>(f + (long)l * F, F, c->red, c->dscal + S_B, c->stream);
-            launch_scale_invsqrt<double>(f + (long)l * F, F, c->dscal + S_B, c->stream);
-        }
+        normalise();
     }
 }
 
@@ -977,7 +977,9 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->lstats = alloc_dev<int>(c, 4);
         c->lbar_count = alloc_dev<unsigned>(c, 64);
         c->lbar_gen = alloc_dev<unsigned long long>(c, 32);
-        c->red = alloc_dev<double>(c, (size_t)kMaxDot * kRedBlocks * 2 * R);
+        const long RM = std::max<long>(R, max_multi_fields(c));  // fields normalised in one launch
+        c->red = alloc_dev<double>(c, (size_t)kMaxDot * kRedBlocks * 2 * RM);
+        c->dnorm = alloc_dev<double>(c, (size_t)2 * RM);
         c->dscal = alloc_dev<double>(c, S_TOTAL * R);
         c->dflag = alloc_dev<int>(c, 4);
         c->dact = alloc_dev<int>(c, kMaxLittleRhs);

@@ -26,11 +26,15 @@ __device__ inline long block_elem(const Geom& g, int blk, int e)
 // One workgroup per (block, k); the Ns workgroups of a block are adjacent in
 // the XCD-remapped order, so the block of psi_b is fetched into one L2. The
 // Phi_k entries are read once per chunk of kRB right-hand sides.
+// RU entries per thread have their loads issued together (one pass over eight
+// right-hand sides already has nine loads per entry in flight)
+// RB: right-hand sides per pass (1 for a single field, else kRB)
+template <int RB, int RU = (RB == 1 ? 4 : 1)>
 __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict__ Phi, int Ns,
                                                   const c64* __restrict__ psi, c64* __restrict__ w, int nrhs,
                                                   int grid_padded)
 {
-    __shared__ double part[2 * kRB][kBT / 64];
+    __shared__ double part[2 * RB][kBT / 64];
     const int q = xcd_remap(blockIdx.x, grid_padded);
     if (q >= g.Nb * Ns)
         return;
@@ -40,24 +44,51 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
     const c64* ph = Phi + (long)k * fs;
     const int ne = 12 * g.Vb;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int b0 = 0; b0 < nrhs; b0 += kRB) {
-        double re[kRB], im[kRB];
+    for (int b0 = 0; b0 < nrhs; b0 += RB) {
+        double re[RB], im[RB];
 #pragma unroll
-        for (int j = 0; j < kRB; ++j)
+        for (int j = 0; j < RB; ++j)
             re[j] = im[j] = 0.0;
-        for (int e = threadIdx.x; e < ne; e += kBT) {
-            const long i = block_elem(g, blk, e);
-            const c64 a = ph[i];
+        if constexpr (RU == 1) {
+            for (int e = threadIdx.x; e < ne; e += kBT) {
+                const long i = block_elem(g, blk, e);
+                const c64 a = ph[i];
 #pragma unroll
-            for (int j = 0; j < kRB; ++j)
-                if (b0 + j < nrhs) {
-                    const c64 b = psi[(long)(b0 + j) * fs + i];
-                    re[j] += a.re * b.re + a.im * b.im;
-                    im[j] += a.re * b.im - a.im * b.re;
+                for (int j = 0; j < RB; ++j)
+                    if (b0 + j < nrhs) {
+                        const c64 b = psi[(long)(b0 + j) * fs + i];
+                        re[j] += a.re * b.re + a.im * b.im;
+                        im[j] += a.re * b.im - a.im * b.re;
+                    }
+            }
+        } else {
+            // RU entries per thread at a time, their loads issued together
+            // (entry indices clamped to valid memory; the extra terms are dropped)
+            for (int e0 = threadIdx.x; e0 < ne; e0 += RU * kBT) {
+                c64 av[RU], bv[RU][RB];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const long i = block_elem(g, blk, min(e0 + u * kBT, ne - 1));
+                    av[u] = ph[i];
+#pragma unroll
+                    for (int j = 0; j < RB; ++j)
+                        bv[u][j] = b0 + j < nrhs ? psi[(long)(b0 + j) * fs + i] : c64{0.0, 0.0};
                 }
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+                    if (e0 + u * kBT < ne) {
+#pragma unroll
+                        for (int j = 0; j < RB; ++j)
+                            if (b0 + j < nrhs) {
+                                const c64 a = av[u], b = bv[u][j];
+                                re[j] += a.re * b.re + a.im * b.im;
+                                im[j] += a.re * b.im - a.im * b.re;
+                            }
+                    }
+            }
         }
 #pragma unroll
-        for (int j = 0; j < kRB; ++j) {
+        for (int j = 0; j < RB; ++j) {
             double x = wave_sum(re[j]), y = wave_sum(im[j]);
             if (lane == 0) {
                 part[2 * j][wid] = x;
@@ -65,7 +96,7 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
             }
         }
         __syncthreads();
-        if (threadIdx.x < 2 * kRB && b0 + (threadIdx.x >> 1) < nrhs) {
+        if (threadIdx.x < 2 * RB && b0 + (threadIdx.x >> 1) < nrhs) {
             double t = 0.0;
             for (int u = 0; u < kBT / 64; ++u)
                 t += part[threadIdx.x][u];
@@ -629,7 +660,10 @@ __global__ void k_c64_to_c32(const c64* a, c32* b, long n)
 void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
 {
     const int gp = pad_grid((long)g.Nb * Ns);
-    hipLaunchKernelGGL(k_restrict, dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
+    if (nrhs == 1)
+        hipLaunchKernelGGL(k_restrict<1>, dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
+    else
+        hipLaunchKernelGGL(k_restrict<kRB>, dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
 }
 void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s)
 {

@@ -131,7 +131,8 @@ struct dfl_ctx {
     double* lfin = nullptr;    // batched little GCR: reduced sums and per-workgroup coefficients
     double* lacoef = nullptr;
     // reductions and scalars
-    double* red = nullptr;       // kRedBlocks * 2 * kMaxDot partials
+    double* red = nullptr;       // kRedBlocks * 2 * kMaxDot partials per field (max(nrhs_max, multi-field count))
+    double* dnorm = nullptr;     // squared norms (complex pairs) of the fields of a multi-field normalisation
     double* dscal = nullptr;     // device scalars
     double* hscal = nullptr;     // pinned host mirror
     int* dflag = nullptr;        // device status flag
