@@ -3,10 +3,12 @@
 //
 // The little vector has Nb*Ns entries; workgroup g owns the blocks
 // g, g + G, g + 2G, ... (G = grid size) and all entries of those blocks. One
-// GCR step normally needs two grid-wide barriers:
-//   S1  r is complete: reduce ||r||^2, test convergence, then apply
-//       chi_k = A r (rows of the owned blocks; the nine neighbour blocks'
-//       entries of r are read from global memory);
+// GCR step normally needs two grid-wide barriers (one more inside the
+// even-odd operator):
+//   S1  xi_k = r is complete everywhere: apply chi_k = A xi_k (rows of the
+//       owned blocks; the nine neighbour blocks' entries are read from global
+//       memory). Convergence is tested before it on ||r_k||^2 =
+//       ||r_{k-1}||^2 - |c_k|^2, which needs no reduction;
 //   S2  reduce (chi_j, chi_k), (chi_j, r) for j < k, ||chi_k||^2 and
 //       (chi_k, r) in one pass; classical Gram-Schmidt then gives the
 //       normalised chi_k, its coefficient c_k = (chi_k, r) and the new residue
@@ -18,7 +20,7 @@
 // the same fixed order, so all workgroups take identical decisions and the
 // result is bit-reproducible. After nkv steps (or convergence) the solution
 // is updated from the triangular system and the residue recomputed as
-// w - A x (two more barriers). The barriers are this file's own (see
+// w - A x (two more barriers); convergence is decided on that true residue. The barriers are this file's own (see
 // grid_barrier); the launch is cooperative so all workgroups are resident.
 #include "internal.h"
 
@@ -442,6 +444,10 @@ __device__ inline void combine_terms(const LittleCtx<T>& c, int nterm, CF cf, VF
 // on even blocks and the intermediate M_oe u on odd blocks.
 template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_gcr(LittleArgs<T> a)
 {
+    // FP64: the residue norm inside a cycle follows from the coefficients
+    // while it is more than kNormFloor ||w||^2 above the tolerance
+    constexpr bool kTrackNorm = sizeof(T) == sizeof(double);
+    constexpr double kNormFloor = 1e-12;
     __shared__ double red[2 * (2 * NK + 2 + NQ)];
     __shared__ double acoef[NK][NK][2];
     __shared__ double qcoef[NQ][NK][2];  // components of each direction's image along Q
@@ -524,10 +530,16 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
         wn2_s = red[0];
     __syncthreads();
     const double wn2 = wn2_s;
+    double rn2_0 = wn2;  // ||r||^2 after the projection below (Q orthonormal)
     if (nq > 0) {
         reduce_slots(a.part, c.G, SQ, nq, red);
+        for (int l = 0; l < nq; ++l)
+            rn2_0 -= red[2 * l] * red[2 * l] + red[2 * l + 1] * red[2 * l + 1];
         project_q();
     }
+    if (c.t == 0)
+        rn2_s = rn2_0;
+    __syncthreads();
     int iters = 0;
     bool converged = !(wn2 > 0.0);
     bool broke = false;
@@ -539,19 +551,37 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
         for (; k < a.nkv && iters < a.maxiter; ++k) {
             cpx<T>* xk = a.xi + (long)k * N;
             cpx<T>* ck = a.chi + (long)k * N;
-            // xi_k = r on the vector entries, and the partial ||r||^2
-            for (int e = c.t; e < R; e += LT1) {
-                long i = c.entry(e);
-                xk[i] = a.r[i];
+            cpx<T>* xnext = a.xi + (long)(k + 1) * N;  // used only while k + 1 < nkv
+            // ||r||^2 inside a cycle: in FP64 it follows from the coefficients
+            // (||r_k||^2 = ||r_{k-1}||^2 - |c_k|^2, chi_k a unit vector
+            // orthogonal to r_k), but that difference carries an absolute
+            // error of a few ulp of ||w||^2. While the estimate lies well
+            // above the tolerance it only says "not converged" and the
+            // reduction is skipped; near the tolerance, and always in single
+            // precision, ||r||^2 is measured. The true residue is recomputed
+            // and tested at every restart.
+            const bool far = k > 0 && kTrackNorm && rn2_s > (tol2 + kNormFloor) * wn2;
+            if (k == 0 || far) {
+                if (k == 0)
+                    for (int e = c.t; e < R; e += LT1) {
+                        long i = c.entry(e);
+                        xk[i] = a.r[i];  // xi_k = r (else written by the previous step's update)
+                    }
+                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S1: xi_k complete everywhere
+            } else {
+                for (int e = c.t; e < R; e += LT1) {
+                    long i = c.entry(e);
+                    xk[i] = a.r[i];
+                }
+                partial_norm2(c, a.r, SC, sh);
+                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S1: r complete everywhere
+                reduce_slots(a.part, c.G, SC, 1, red);
+                if (c.t == 0)
+                    rn2_s = red[0];
+                __syncthreads();
+                if (rn2_s <= tol2 * wn2)
+                    break;  // converged with k directions
             }
-            partial_norm2(c, a.r, SC, sh);
-            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S1: r complete everywhere
-            reduce_slots(a.part, c.G, SC, 1, red);
-            if (c.t == 0)
-                rn2_s = red[0];
-            __syncthreads();
-            if (k > 0 && rn2_s <= tol2 * wn2)
-                break;  // converged with k directions
             op(xk, ck);
             // one Gram-Schmidt pass: everything needed for chi_k, c_k and the new r
             partial_pass(c, a.chi, k, ck, a.r, SA);
@@ -642,6 +672,8 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                     bcoef[k] = b;
                     ccoef[k][0] = b > 0.0 ? crr / b : 0.0;
                     ccoef[k][1] = b > 0.0 ? cri / b : 0.0;
+                    if (kTrackNorm)
+                        rn2_s -= ccoef[k][0] * ccoef[k][0] + ccoef[k][1] * ccoef[k][1];
                 }
             }
             __syncthreads();
@@ -665,6 +697,8 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                     double rr = (double)a.r[i].re - (cr0 * yr - ci0 * yi);
                     double ri = (double)a.r[i].im - (cr0 * yi + ci0 * yr);
                     a.r[i] = cpx<T>{(T)rr, (T)ri};
+                    if (kTrackNorm && k + 1 < a.nkv)
+                        xnext[i] = cpx<T>{(T)rr, (T)ri};  // xi_{k+1} = r
                 });
             ++iters;
             __syncthreads();
@@ -730,6 +764,10 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
             __syncthreads();
         }
         converged = rn2 <= tol2 * wn2;
+        __syncthreads();  // every thread has read rn2_s
+        if (c.t == 0)
+            rn2_s = rn2;  // start of the next cycle's norm updates
+        __syncthreads();
     }
     if (EO) {
         // x_e must be complete everywhere: a barrier followed its last GCR
