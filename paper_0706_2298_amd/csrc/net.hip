@@ -47,6 +47,9 @@ __device__ inline void tap_shifts(const Lat& lt, long i, int sign, long delta[4]
     }
 }
 
+// canonical index of site x3 on the x3 line `line` = (x0 L1 + x1) L2 + x2
+__device__ inline long base_site(const Lat& lt, long line, int x3) { return line * lt.L[3] + x3; }
+
 __device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
 __device__ inline float silu_grad_f(float z)
 {
@@ -123,6 +126,115 @@ __global__ __launch_bounds__(256) void k_conv(Lat lt, const float* __restrict__ 
         out[(long)(oc0 + j) * V + i] = v;
         if (!TRANS && act)
             act[(long)(oc0 + j) * V + i] = silu_f(v);
+    }
+}
+
+// The same map on the matrix cores (v_mfma_f32_16x16x4f32, FP32 products
+// and sums), as a GEMM per tap: out[oc][x] += sum_ic Wt(t, ic, oc) in[ic][x + s o_t].
+// Workgroup: TS consecutive sites along x3 (TS = 16 or 32, L3 % TS == 0) and
+// OCT = OPW * 1024 / TS output channels; wavefront w computes OPW 16 x 16
+// tiles (channels (OPW * (w / (TS / 16)) + j) * 16.., sites (w % (TS / 16)) *
+// 16..; OPW = 2 when there are enough channels, halving the staging per
+// matrix-core instruction). For each of
+// the 27 neighbour lines (o0, o1, o2) and each chunk of kMC input channels,
+// the line segment with its +-1 halo along x3 and the weights of the three
+// taps o3 = -1, 0, 1 are staged in LDS; the three taps then read the segment
+// at shifts of one site. Operand layout of the 16x16x4 instruction: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// C[4 (l / 16) + i][l % 16], i < 4.
+constexpr int kMC = 32;          // input channels per LDS chunk
+constexpr int kXS = 48;          // LDS row stride of the staged segment (TS + 2 <= 34; 48 = 16 mod 32 banks)
+template <bool TRANS, int TS, int OPW>
+__global__ __launch_bounds__(256) void k_conv_mfma(Lat lt, const float* __restrict__ in, int nic,
+                                                   const float* __restrict__ W, int w_cin, int w_cout,
+                                                   const float* __restrict__ bias, int noc, float* __restrict__ out,
+                                                   float* __restrict__ act, const float* __restrict__ zprev)
+{
+    constexpr int OCT = OPW * 1024 / TS;  // output channels per workgroup
+    constexpr int WS = OCT + 16;        // LDS row stride of the weights (16 mod 32 banks)
+    constexpr int NST = TS / 16;        // site tiles per workgroup
+    __shared__ float xs[kMC][kXS];
+    __shared__ float ws[3][kMC][WS];
+    const int sgn = TRANS ? -1 : 1;
+    const long V = lt.V;
+    const int L3 = lt.L[3];
+    const long seg = blockIdx.x;                          // segment of TS sites of one x3 line
+    const long line = seg / (L3 / TS);
+    const int x3_0 = (int)(seg - line * (L3 / TS)) * TS;
+    int x[3];
+    {
+        long r = line;
+        x[2] = (int)(r % lt.L[2]);
+        r /= lt.L[2];
+        x[1] = (int)(r % lt.L[1]);
+        x[0] = (int)(r / lt.L[1]);
+    }
+    const int oc0 = blockIdx.y * OCT;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ot = w / NST, st = w % NST;
+    const int kr = lane >> 4, kc = lane & 15;             // k row and column of this lane's operands
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 acc[OPW];
+#pragma unroll
+    for (int j = 0; j < OPW; ++j)
+        acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int l = 0; l < 27; ++l) {
+        const int o[3] = {l / 9 - 1, (l / 3) % 3 - 1, l % 3 - 1};
+        long base = 0;  // canonical index of (y0, y1, y2, 0)
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            int y = x[mu] + sgn * o[mu];
+            y = y < 0 ? y + lt.L[mu] : (y >= lt.L[mu] ? y - lt.L[mu] : y);
+            base += (long)y * lt.str[mu];
+        }
+        for (int c0 = 0; c0 < nic; c0 += kMC) {
+            __syncthreads();  // the previous chunk's operands are consumed
+            for (int e = threadIdx.x; e < kMC * (TS + 2); e += 256) {
+                const int ic = e / (TS + 2), j = e - ic * (TS + 2);
+                int y3 = x3_0 - 1 + j;
+                y3 = y3 < 0 ? y3 + L3 : (y3 >= L3 ? y3 - L3 : y3);
+                xs[ic][j] = c0 + ic < nic ? in[(long)(c0 + ic) * V + base + y3] : 0.f;
+            }
+            for (int e = threadIdx.x; e < 3 * kMC * OCT; e += 256) {
+                const int q = e / (kMC * OCT), r = e - q * (kMC * OCT);
+                const int ic = r / OCT, c = r - ic * OCT;
+                const int t = l * 3 + q;  // tap of (o0, o1, o2, o3 = q - 1)
+                const int ci = c0 + ic, co = oc0 + c;
+                float v = 0.f;
+                if (ci < nic && co < noc)
+                    v = TRANS ? W[((long)t * w_cin + co) * w_cout + ci] : W[((long)t * w_cin + ci) * w_cout + co];
+                ws[q][ic][c] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int sh = 1 + sgn * (q - 1);  // segment column of site 0 for o3 = q - 1
+#pragma unroll
+                for (int k0 = 0; k0 < kMC; k0 += 4) {
+                    const float b = xs[k0 + kr][st * 16 + kc + sh];
+#pragma unroll
+                    for (int j = 0; j < OPW; ++j) {
+                        const float a = ws[q][k0 + kr][(OPW * ot + j) * 16 + kc];
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    const long site = base_site(lt, line, x3_0 + st * 16 + kc);
+#pragma unroll
+    for (int j = 0; j < OPW; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int oc = oc0 + (OPW * ot + j) * 16 + 4 * kr + i;
+        if (oc >= noc)
+            continue;
+        float v = acc[j][i] + (bias ? bias[oc] : 0.f);
+        if (TRANS && zprev)
+            v *= silu_grad_f(zprev[(long)oc * V + site]);
+        out[(long)oc * V + site] = v;
+        if (!TRANS && act)
+            act[(long)oc * V + site] = silu_f(v);
     }
 }
 
@@ -540,8 +652,21 @@ void launch_conv_forward(const Geom& g, const float* in, int cin, const float* W
                          float* a, hipStream_t s)
 {
     const Lat lt = make_lat(g);
-    hipLaunchKernelGGL(k_conv<false>, dim3(site_blocks(g.V), (cout + kCO - 1) / kCO), dim3(256), 0, s, lt, in, cin,
-                       W, cin, cout, b, cout, z, a, nullptr);
+    if (g.L[3] % 32 == 0 && cout >= 64)
+        hipLaunchKernelGGL((k_conv_mfma<false, 32, 2>), dim3((unsigned)(g.V / 32), (cout + 63) / 64), dim3(256), 0, s,
+                           lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
+    else if (g.L[3] % 32 == 0)
+        hipLaunchKernelGGL((k_conv_mfma<false, 32, 1>), dim3((unsigned)(g.V / 32), (cout + 31) / 32), dim3(256), 0, s,
+                           lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
+    else if (g.L[3] % 16 == 0 && cout >= 128)
+        hipLaunchKernelGGL((k_conv_mfma<false, 16, 2>), dim3((unsigned)(g.V / 16), (cout + 127) / 128), dim3(256), 0,
+                           s, lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
+    else if (g.L[3] % 16 == 0)
+        hipLaunchKernelGGL((k_conv_mfma<false, 16, 1>), dim3((unsigned)(g.V / 16), (cout + 63) / 64), dim3(256), 0, s,
+                           lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
+    else
+        hipLaunchKernelGGL(k_conv<false>, dim3(site_blocks(g.V), (cout + kCO - 1) / kCO), dim3(256), 0, s, lt, in,
+                           cin, W, cin, cout, b, cout, z, a, nullptr);
 }
 
 void launch_conv_backward(const Geom& g, const float* in, int cin, const float* W, int cout, const float* gr,
@@ -554,7 +679,15 @@ void launch_conv_backward(const Geom& g, const float* in, int cin, const float* 
     const long n = 81L * cin * cout;
     hipLaunchKernelGGL(k_sum_chunks, dim3(site_blocks(n)), dim3(256), 0, s, part, n, nchunk, dW);
     hipLaunchKernelGGL(k_bias_grad, dim3(cout), dim3(256), 0, s, gr, g.V, db);
-    if (din)
+    if (!din)
+        return;
+    if (g.L[3] % 32 == 0)
+        hipLaunchKernelGGL((k_conv_mfma<true, 32, 1>), dim3((unsigned)(g.V / 32), (cin + 31) / 32), dim3(256), 0, s,
+                           lt, gr, cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
+    else if (g.L[3] % 16 == 0)
+        hipLaunchKernelGGL((k_conv_mfma<true, 16, 1>), dim3((unsigned)(g.V / 16), (cin + 63) / 64), dim3(256), 0, s,
+                           lt, gr, cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
+    else
         hipLaunchKernelGGL(k_conv<true>, dim3(site_blocks(g.V), (cin + kCO - 1) / kCO), dim3(256), 0, s, lt, gr,
                            cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
 }

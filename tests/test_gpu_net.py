@@ -196,3 +196,36 @@ def test_trained_network_beats_random_start(S):
     assert res[("trained", 0)] < res[("random", 0)]
     assert res[("trained", 0)] < res[("untrained", 0)]
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dims,blk", [((8, 8, 8, 16), (4, 4, 4, 4)), ((4, 4, 8, 32), (2, 2, 2, 4))])
+@pytest.mark.parametrize("cin,cout", [(5, 7), (96, 37), (32, 576)])
+def test_conv_matrix_core_paths(dims, blk, cin, cout):
+    # lattices whose x3 extent is a multiple of 16 (32) run the convolutions
+    # on the matrix cores with 16 (32) sites per workgroup: forward, activation
+    # and the input gradient against the oracle, same tolerance as above
+    say(f"conv mfma {dims} {cin}->{cout}")
+    s = Solver(dims, dfl_block=blk, sap_block=blk, Ns=2, nkv=2, little_nkv=2, m0=-0.2, nrhs_max=1)
+    s.set_gauge(latgen.make_links(dims, 0.4, 6011))
+    torch = s.torch
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(cin * 7 + cout + dims[3])
+    x = rng.standard_normal((V, cin))
+    W = rng.standard_normal((3, 3, 3, 3, cin, cout)) / np.sqrt(81 * cin)
+    b = rng.standard_normal(cout)
+    g = rng.standard_normal((V, cout))
+    zin = rng.standard_normal((V, cin))
+    xd, Wd, bd = dev(x.T, torch), dev(W.reshape(81, cin, cout), torch), dev(b, torch)
+    z = torch.empty(cout * V, dtype=torch.float32, device="cuda")
+    a = torch.empty_like(z)
+    binding.conv4d_forward(s.ctx, xd, cin, Wd, bd, cout, z, a)
+    zr = onet.conv4d(x, W, b, dims)
+    assert rel(z.cpu().numpy().reshape(cout, V).T, zr) < 2e-5
+    assert rel(a.cpu().numpy().reshape(cout, V).T, onet.silu(zr)) < 2e-5
+    dW = torch.empty_like(Wd)
+    db = torch.empty_like(bd)
+    din = torch.empty_like(xd)
+    binding.conv4d_backward(s.ctx, xd, cin, Wd, cout, dev(g.T, torch), dW, db, din, dev(zin.T, torch))
+    dxr, _, _ = onet.conv4d_backward(x, W, g, dims)
+    assert rel(din.cpu().numpy().reshape(cin, V).T, dxr * onet.silu_grad(zin)) < 2e-5
+    s.close()
