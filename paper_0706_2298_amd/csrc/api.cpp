@@ -1209,7 +1209,7 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
             } else {
                 const int mu = (d - 1) / 2;
                 const int dir = (d & 1) ? +1 : -1;
-                launch_dirac64(c->g, links64(c), f, c->xi, nc, 0.0, 2, mu, dir, c->stream);
+                launch_dirac64_face(c->g, links64(c), f, c->xi, nc, mu, dir, c->stream);
             }
             launch_little_columns64(c->g, c->Phi, Ns, c->xi, nc, l0, d, c->A64, c->t1, part_cap, c->stream);
         }

@@ -144,6 +144,49 @@ __global__ __launch_bounds__(256) void k_dirac_blk(Geom g, L U, const cpx<T>* __
         }
 }
 
+// The block-crossing hop (hop_mu, hop_dir) of MODE 2 on the sites it reaches
+// only: one thread per site of the face {y_mu = b_mu - 1} (dir = +1) or
+// {y_mu = 0} (dir = -1) of every layout block, blockIdx.y = right-hand side.
+// The other sites of out are left untouched (the little-operator assembly
+// reads the face only).
+template <typename T, typename L>
+__global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* __restrict__ psi,
+                                                    cpx<T>* __restrict__ out, int mu, int dir, int nface)
+{
+    const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= (long)g.Nb * nface)
+        return;
+    const int blk = (int)(f / nface);
+    int r = (int)(f - (long)blk * nface), rb = blk;
+    int n[4], y[4];
+#pragma unroll
+    for (int nu = 3; nu >= 0; --nu) {
+        n[nu] = rb % g.nb[nu];
+        rb /= g.nb[nu];
+        if (nu == mu) {
+            y[nu] = dir > 0 ? g.b[nu] - 1 : 0;
+        } else {
+            y[nu] = r % g.b[nu];
+            r /= g.b[nu];
+        }
+    }
+    const long s = site_compose(g, n, y);
+    const long off = (long)blockIdx.y * 12 * g.V;
+    spinor<T> acc;
+    zero(acc);
+    if (g.nb[mu] > 1) {
+        const long t = site_step(g, s, n, y, mu, dir);
+        spinor<T> p = load_spinor(psi + off, g.V, t);
+        if (dir > 0)
+            hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
+        else
+            hop_bwd_rt(mu, load_link(U, mu, t), p, acc);
+    }
+    spinor<T> z;
+    zero(z);
+    store_spinor(out + off, g.V, s, finish(z, acc, T(0)));
+}
+
 template <int MODE, typename T, typename L>
 void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, int mu, int dir, hipStream_t s)
 {
@@ -170,6 +213,14 @@ void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs
         launch<1>(g, U, psi, out, nrhs, m0, mu, dir, s);
     else
         launch<2>(g, U, psi, out, nrhs, m0, mu, dir, s);
+}
+
+void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s)
+{
+    const int nface = (int)(g.Vb / g.b[mu]);
+    const long n = (long)g.Nb * nface;
+    hipLaunchKernelGGL((k_dirac_face<double, Links64>), dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, g,
+                       U, psi, out, mu, dir, nface);
 }
 
 void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s)
