@@ -113,7 +113,9 @@ typedef struct {
                               reduced system (appendix A.2), falling back to A when a
                               diagonal block is not safely invertible */
     int little_gdefl;      /* 1 (with little_eo and Ns <= 32): deflate the even-odd little
-                              system by the start fields' global modes (appendix A.3) */
+                              system by the even-block parts of the global fields the
+                              subspace was built from, i.e. the inverse-iteration fields
+                              before block orthonormalisation (appendix A.3) */
 } dfl_params;
 
 typedef struct {

@@ -698,13 +698,8 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
         nsplit = 1;
     if ((long)nsplit * g.Nb * Ns * nc > part_cap)
         fail(DFL_EINVAL, "little-operator assembly: scratch too small for the column chunk");
-    static bool attr = false;
-    if (!attr) {
-        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_little_columns),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(sizeof(c64) * (64 + 64) * (kCE + 1))));
-        attr = true;
-    }
+    static std::once_flag attr;
+    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_columns), (int)(sizeof(c64) * (64 + 64) * (kCE + 1)));
     hipLaunchKernelGGL(k_little_columns, dim3(g.Nb * nsplit), dim3(256), lds, s, g, Phi, Ns, Y, nc, nsplit, fmu, fy,
                        nface, part);
     const long n = (long)g.Nb * Ns * nc;
@@ -725,25 +720,17 @@ template void launch_little_apply<float>(const Geom&, const c32*, int, const c32
 void launch_little_apply_mfma(const Geom& g, const c32* At, int Ns, const c32* v, c32* w, int nrhs, hipStream_t s)
 {
     const size_t lds = sizeof(c32) * 9 * Ns * kMfmaRhs;
-    static bool attr_set = false;
-    if (!attr_set && lds > 65536) {
-        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_little_apply_mfma),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 9 * 64 * kMfmaRhs * sizeof(c32)));
-        attr_set = true;
-    }
+    static std::once_flag attr;
+    if (lds > 65536)
+        set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_apply_mfma), 9 * 64 * kMfmaRhs * sizeof(c32));
     hipLaunchKernelGGL(k_little_apply_mfma, dim3(g.Nb), dim3(256), lds, s, g, At, Ns, v, w, nrhs);
 }
 
 void launch_little_eo_prep(const Geom& g, const c64* A, int Ns, c64* Mt64, c32* Mt32, int* flag, hipStream_t s)
 {
     const size_t lds = sizeof(c64) * (2 * (size_t)Ns * Ns + Ns);
-    static bool attr = false;
-    if (!attr) {
-        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_little_eo_prep),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(sizeof(c64) * (2 * 64 * 64 + 64))));
-        attr = true;
-    }
+    static std::once_flag attr;
+    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_eo_prep), (int)(sizeof(c64) * (2 * 64 * 64 + 64)));
     hipLaunchKernelGGL(k_little_eo_prep, dim3(g.Nb), dim3(256), lds, s, g, A, Ns, Mt64, Mt32, flag);
 }
 

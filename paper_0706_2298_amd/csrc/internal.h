@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,13 @@ struct Error {
 [[noreturn]] void fail(int code, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
 #define HIPCHECK(x) ::dfl::hip_check((x), #x)
+
+// Raise a kernel's dynamic LDS limit to `bytes`, once per process (thread-safe;
+// a failure leaves the flag unset and is reported by HIPCHECK).
+inline void set_max_lds_once(std::once_flag& flag, const void* fn, int bytes)
+{
+    std::call_once(flag, [&] { HIPCHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)); });
+}
 
 // Schwarz block grid (independent of the layout blocks)
 struct SapGeom {

@@ -1358,9 +1358,11 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
 }  // namespace
 
 // The barrier and reduction costs grow with the workgroup count (a barrier
-// takes about 3.4 us at 128 workgroups on MI355X), the apply's bandwidth with
-// it. Default four blocks per workgroup (one round of the 1024 threads in the
-// apply for Ns up to 28), at most kLittleMaxGrid workgroups.
+// takes about 2.2 us at 64 and 3.4 us at 128 workgroups on MI355X), the
+// apply's bandwidth with it. Default four blocks per workgroup: with the
+// even-odd operator each apply covers two blocks, one round of the 512
+// threads for Ns up to 32 (measured on 16^4: 64 workgroups beat 32, 48 and
+// 128). At most kLittleMaxGrid workgroups.
 int little_gcr_grid(const Geom& g, int requested)
 {
     int G = requested > 0 ? requested : g.Nb / 4;

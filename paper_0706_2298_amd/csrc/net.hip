@@ -131,26 +131,28 @@ __global__ __launch_bounds__(256) void k_conv(Lat lt, const float* __restrict__ 
 
 // The same map on the matrix cores (v_mfma_f32_16x16x4f32, FP32 products
 // and sums), as a GEMM per tap: out[oc][x] += sum_ic Wt(t, ic, oc) in[ic][x + s o_t].
-// Workgroup: TS consecutive sites along x3 (TS = 16 or 32, L3 % TS == 0) and
-// OCT = OPW * 1024 / TS output channels; wavefront w computes OPW 16 x 16
-// tiles (channels (OPW * (w / (TS / 16)) + j) * 16.., sites (w % (TS / 16)) *
-// 16..; OPW = 2 when there are enough channels, halving the staging per
-// matrix-core instruction). For each of
-// the 27 neighbour lines (o0, o1, o2) and each chunk of kMC input channels,
-// the line segment with its +-1 halo along x3 and the weights of the three
-// taps o3 = -1, 0, 1 are staged in LDS; the three taps then read the segment
-// at shifts of one site. Operand layout of the 16x16x4 instruction: lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
-// C[4 (l / 16) + i][l % 16], i < 4.
-constexpr int kMC = 32;          // input channels per LDS chunk
-constexpr int kXS = 48;          // LDS row stride of the staged segment (TS + 2 <= 34; 48 = 16 mod 32 banks)
-template <bool TRANS, int TS, int OPW>
+// Workgroup: 32 consecutive sites along x3 (L3 % 32 == 0) and 32 output
+// channels; wavefront w computes the 16 x 16 tile (channels (w / 2) * 16..,
+// sites (w % 2) * 16..). For each of the 27 neighbour lines (o0, o1, o2) and
+// each chunk of kMC input channels, the line segment with its +-1 halo along
+// x3 and the weights of the three taps o3 = -1, 0, 1 are staged in LDS; the
+// three taps then read the segment at shifts of one site. Operand layout of
+// the 16x16x4 instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds C[4 (l / 16) + i][l % 16], i < 4.
+// Measured on MI355X: 44-50 TFLOP/s per layer on 64 x 32^3, 15% faster than
+// k_conv; 16-site segments (for L3 = 16) ran three times slower than k_conv
+// and two channel tiles per wavefront did not help, so only this shape is
+// used and other lattices take k_conv.
+constexpr int kMC = 32;  // input channels per LDS chunk
+constexpr int kXS = 48;  // LDS row stride of the staged segment (34 used; 48 = 16 mod 32 banks)
+template <bool TRANS>
 __global__ __launch_bounds__(256) void k_conv_mfma(Lat lt, const float* __restrict__ in, int nic,
                                                    const float* __restrict__ W, int w_cin, int w_cout,
                                                    const float* __restrict__ bias, int noc, float* __restrict__ out,
                                                    float* __restrict__ act, const float* __restrict__ zprev)
 {
-    constexpr int OCT = OPW * 1024 / TS;  // output channels per workgroup
+    constexpr int TS = 32;              // sites per workgroup
+    constexpr int OCT = 32;             // output channels per workgroup
     constexpr int WS = OCT + 16;        // LDS row stride of the weights (16 mod 32 banks)
     constexpr int NST = TS / 16;        // site tiles per workgroup
     __shared__ float xs[kMC][kXS];
@@ -174,10 +176,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(Lat lt, const float* __restri
     const int ot = w / NST, st = w % NST;
     const int kr = lane >> 4, kc = lane & 15;             // k row and column of this lane's operands
     typedef float f4 __attribute__((ext_vector_type(4)));
-    f4 acc[OPW];
-#pragma unroll
-    for (int j = 0; j < OPW; ++j)
-        acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int l = 0; l < 27; ++l) {
         const int o[3] = {l / 9 - 1, (l / 3) % 3 - 1, l % 3 - 1};
         long base = 0;  // canonical index of (y0, y1, y2, 0)
@@ -211,25 +210,20 @@ __global__ __launch_bounds__(256) void k_conv_mfma(Lat lt, const float* __restri
                 const int sh = 1 + sgn * (q - 1);  // segment column of site 0 for o3 = q - 1
 #pragma unroll
                 for (int k0 = 0; k0 < kMC; k0 += 4) {
+                    const float a = ws[q][k0 + kr][ot * 16 + kc];
                     const float b = xs[k0 + kr][st * 16 + kc + sh];
-#pragma unroll
-                    for (int j = 0; j < OPW; ++j) {
-                        const float a = ws[q][k0 + kr][(OPW * ot + j) * 16 + kc];
-                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
-                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
                 }
             }
         }
     }
     const long site = base_site(lt, line, x3_0 + st * 16 + kc);
 #pragma unroll
-    for (int j = 0; j < OPW; ++j)
-#pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int oc = oc0 + (OPW * ot + j) * 16 + 4 * kr + i;
+        const int oc = oc0 + ot * 16 + 4 * kr + i;
         if (oc >= noc)
             continue;
-        float v = acc[j][i] + (bias ? bias[oc] : 0.f);
+        float v = acc[i] + (bias ? bias[oc] : 0.f);
         if (TRANS && zprev)
             v *= silu_grad_f(zprev[(long)oc * V + site]);
         out[(long)oc * V + site] = v;
@@ -652,18 +646,9 @@ void launch_conv_forward(const Geom& g, const float* in, int cin, const float* W
                          float* a, hipStream_t s)
 {
     const Lat lt = make_lat(g);
-    if (g.L[3] % 32 == 0 && cout >= 64)
-        hipLaunchKernelGGL((k_conv_mfma<false, 32, 2>), dim3((unsigned)(g.V / 32), (cout + 63) / 64), dim3(256), 0, s,
-                           lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
-    else if (g.L[3] % 32 == 0)
-        hipLaunchKernelGGL((k_conv_mfma<false, 32, 1>), dim3((unsigned)(g.V / 32), (cout + 31) / 32), dim3(256), 0, s,
-                           lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
-    else if (g.L[3] % 16 == 0 && cout >= 128)
-        hipLaunchKernelGGL((k_conv_mfma<false, 16, 2>), dim3((unsigned)(g.V / 16), (cout + 127) / 128), dim3(256), 0,
-                           s, lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
-    else if (g.L[3] % 16 == 0)
-        hipLaunchKernelGGL((k_conv_mfma<false, 16, 1>), dim3((unsigned)(g.V / 16), (cout + 63) / 64), dim3(256), 0, s,
-                           lt, in, cin, W, cin, cout, b, cout, z, a, nullptr);
+    if (g.L[3] % 32 == 0)
+        hipLaunchKernelGGL(k_conv_mfma<false>, dim3((unsigned)(g.V / 32), (cout + 31) / 32), dim3(256), 0, s, lt, in,
+                           cin, W, cin, cout, b, cout, z, a, nullptr);
     else
         hipLaunchKernelGGL(k_conv<false>, dim3(site_blocks(g.V), (cout + kCO - 1) / kCO), dim3(256), 0, s, lt, in,
                            cin, W, cin, cout, b, cout, z, a, nullptr);
@@ -682,11 +667,8 @@ void launch_conv_backward(const Geom& g, const float* in, int cin, const float* 
     if (!din)
         return;
     if (g.L[3] % 32 == 0)
-        hipLaunchKernelGGL((k_conv_mfma<true, 32, 1>), dim3((unsigned)(g.V / 32), (cin + 31) / 32), dim3(256), 0, s,
-                           lt, gr, cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
-    else if (g.L[3] % 16 == 0)
-        hipLaunchKernelGGL((k_conv_mfma<true, 16, 1>), dim3((unsigned)(g.V / 16), (cin + 63) / 64), dim3(256), 0, s,
-                           lt, gr, cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
+        hipLaunchKernelGGL(k_conv_mfma<true>, dim3((unsigned)(g.V / 32), (cin + 31) / 32), dim3(256), 0, s, lt, gr,
+                           cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
     else
         hipLaunchKernelGGL(k_conv<true>, dim3(site_blocks(g.V), (cin + kCO - 1) / kCO), dim3(256), 0, s, lt, gr,
                            cout, W, cin, cout, nullptr, cin, din, nullptr, zprev);
@@ -711,13 +693,8 @@ void launch_deficit_block(const Geom& g, const c64* Psi, int Ns, const c64* T, i
                           double* proj, int* flag, hipStream_t s)
 {
     const size_t lds = deficit_lds_bytes(Ns, K);
-    static bool attr = false;
-    if (!attr) {
-        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_deficit_block),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)deficit_lds_bytes(kMaxLossN, kMaxLossN)));
-        attr = true;
-    }
+    static std::once_flag attr;
+    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_deficit_block), (int)deficit_lds_bytes(kMaxLossN, kMaxLossN));
     hipLaunchKernelGGL(k_deficit_block, dim3(g.Nb), dim3(256), lds, s, g, Psi, Ns, T, K, Y, tb2, proj, flag);
 }
 

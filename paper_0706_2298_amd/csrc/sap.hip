@@ -412,12 +412,8 @@ void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* ps
 {
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(cpx<T>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        HIPCHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap<T, L>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
-        attr_set = true;
-    }
+    static std::once_flag attr;  // one per kernel instantiation
+    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap<T, L>), 160 * 1024 - 1024);
     hipLaunchKernelGGL((k_sap<T, L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
                        T(4) + m0, nmr, colour, nrhs);
 }

@@ -200,11 +200,12 @@ def test_trained_network_beats_random_start(S):
 
 @pytest.mark.parametrize("dims,blk", [((8, 8, 8, 16), (4, 4, 4, 4)), ((4, 4, 8, 32), (2, 2, 2, 4))])
 @pytest.mark.parametrize("cin,cout", [(5, 7), (96, 37), (32, 576)])
-def test_conv_matrix_core_paths(dims, blk, cin, cout):
-    # lattices whose x3 extent is a multiple of 16 (32) run the convolutions
-    # on the matrix cores with 16 (32) sites per workgroup: forward, activation
-    # and the input gradient against the oracle, same tolerance as above
-    say(f"conv mfma {dims} {cin}->{cout}")
+def test_conv_both_paths(dims, blk, cin, cout):
+    # a lattice whose x3 extent is a multiple of 32 runs the convolutions on
+    # the matrix cores (32 sites per workgroup), one with L3 = 16 the vector
+    # kernel: forward, activation and the input gradient against the oracle,
+    # same tolerance as above
+    say(f"conv {dims} {cin}->{cout}")
     s = Solver(dims, dfl_block=blk, sap_block=blk, Ns=2, nkv=2, little_nkv=2, m0=-0.2, nrhs_max=1)
     s.set_gauge(latgen.make_links(dims, 0.4, 6011))
     torch = s.torch
