@@ -456,14 +456,19 @@ std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter,
                 precond(v.r, xk, nb);
                 op(xk, ck, nb);
                 if (k > 0) {
-                    launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A1, S_TOTAL, mask,
-                                              c->stream);
+                    // classical Gram-Schmidt; the first pass also yields ||chi_k||^2 (slot k, as chi_k
+                    // follows the earlier images at stride ks), and a second pass runs only for the
+                    // sources whose first pass cancelled more than 99% of it
+                    launch_multidot_b<double>(v.chi, ks, k + 1, ck, n, nb, n, n, c->red, c->dscal + S_A1, S_TOTAL,
+                                              mask, c->stream);
                     launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A1, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
                                                c->stream);
-                    launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A2, S_TOTAL, mask,
-                                              c->stream);
-                    launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A2, S_TOTAL, -1.0, ck, n, nb, n, n, mask,
-                                               c->stream);
+                    launch_second_pass_mask(c->dscal + S_A1, c->dscal + S_A2, k, S_TOTAL, mask, nb, c->dact2,
+                                            c->stream);
+                    launch_multidot_b<double>(v.chi, ks, k, ck, n, nb, n, n, c->red, c->dscal + S_A2, S_TOTAL,
+                                              c->dact2, c->stream);
+                    launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A2, S_TOTAL, -1.0, ck, n, nb, n, n,
+                                               c->dact2, c->stream);
                 }
                 launch_norm2_b<double>(ck, n, nb, n, c->red, c->dscal + S_B, S_TOTAL, mask, c->stream);
                 launch_scale_invsqrt_b<double>(ck, n, nb, n, c->dscal + S_B, S_TOTAL, mask, c->stream);
@@ -983,6 +988,7 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->dscal = alloc_dev<double>(c, S_TOTAL * R);
         c->dflag = alloc_dev<int>(c, 4);
         c->dact = alloc_dev<int>(c, kMaxLittleRhs);
+        c->dact2 = alloc_dev<int>(c, kMaxLittleRhs);
         c->dtol = alloc_dev<double>(c, 2);
         HIPCHECK(hipHostMalloc((void**)&c->htol, sizeof(double) * 2, hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&c->hscal, sizeof(double) * S_TOTAL * R, hipHostMallocDefault));

@@ -302,6 +302,36 @@ template <typename T> void launch_scale_invsqrt(cpx<T>* x, long n, const double*
     launch_scale_invsqrt_b<T>(x, n, 1, 0, nrm2, 0, nullptr, s);
 }
 
+namespace {
+// Gram-Schmidt re-orthogonalisation test per source b: the first pass left
+// (x_j, y) for j < k and (y, y) at a1[b*stride + 2j] (j <= k). A second pass
+// is needed only if the first cancelled more than 99% of ||y||^2; sources that
+// skip it get zero second-pass coefficients (a2) and act2[b] = 0.
+__global__ void k_second_pass_mask(const double* __restrict__ a1, double* __restrict__ a2, int k, int stride,
+                                   const int* __restrict__ active, int nb, int* __restrict__ act2)
+{
+    const int b = threadIdx.x;
+    if (b >= nb)
+        return;
+    const double* p = a1 + (long)b * stride;
+    double q = 0.0;
+    for (int j = 0; j < k; ++j)
+        q += p[2 * j] * p[2 * j] + p[2 * j + 1] * p[2 * j + 1];
+    const double n2 = p[2 * k];
+    const int need = (!active || active[b]) && !(n2 - q >= 0.01 * n2);
+    act2[b] = need;
+    if (!need)
+        for (int j = 0; j < 2 * k; ++j)
+            a2[(long)b * stride + j] = 0.0;
+}
+}  // namespace
+
+void launch_second_pass_mask(const double* a1, double* a2, int k, int stride, const int* active, int nb, int* act2,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_second_pass_mask, dim3(1), dim3(64), 0, s, a1, a2, k, stride, active, nb, act2);
+}
+
 void launch_add_scalars(const double* a, const double* b, double* dst, int m, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_scalars, dim3(1), dim3(128), 0, s, a, b, dst, m);

@@ -145,6 +145,7 @@ struct dfl_ctx {
     double* hscal = nullptr;     // pinned host mirror
     int* dflag = nullptr;        // device status flag
     int* dact = nullptr;         // per-RHS active mask of the batched GCR
+    int* dact2 = nullptr;        // per-RHS mask of the outer GCR's second Gram-Schmidt pass
     double* dtol = nullptr;      // relative tolerance of the inner little solves (device)
     double* htol = nullptr;      // pinned host mirror
     int* hact = nullptr;         // pinned host mirror
@@ -241,6 +242,10 @@ void launch_multiaxpy_b(const cpx<T>* X, long stride, int m, const double* coef,
 template <typename T>
 void launch_scale_invsqrt_b(cpx<T>* x, long n, int nb, long xb, const double* nrm2, int cstride, const int* active,
                             hipStream_t s);
+// second Gram-Schmidt pass only where the first cancelled > 99% of ||y||^2:
+// act2[b] set accordingly, a2 zeroed for the sources that skip it (nb <= 64)
+void launch_second_pass_mask(const double* a1, double* a2, int k, int stride, const int* active, int nb, int* act2,
+                             hipStream_t s);
 // dst[0..1] = a[0..1] + b[0..1] for m complex
 void launch_add_scalars(const double* a, const double* b, double* dst, int m, hipStream_t s);
 // finite check: flag |= 1 if any entry of x is NaN or Inf
