@@ -339,28 +339,33 @@ void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0, int nb = 1)
 void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1)
 {
     const long n = c->field_elems * nrhs;
+    const int ncy = c->p.ncy;
+    // psi starts at zero: the first cycle's colour-0 sweep sees zero
+    // everywhere, its colour-1 sweep zero on its own blocks (no fill pass)
+    auto init_of = [](int cy, int col) { return cy > 0 ? 0 : (col == 0 ? 2 : 1); };
     if (c->p.sap_prec == DFL_F64) {
-        launch_zero<double>(psi, n, c->stream);
-        for (int cy = 0; cy < c->p.ncy; ++cy)
+        for (int cy = 0; cy < ncy; ++cy)
             for (int col = 0; col < 2; ++col) {
                 ProfScope ps(c, c->sap_prof_cls);
-                launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, nrhs, c->stream);
+                launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, nrhs, init_of(cy, col),
+                                    c->stream);
             }
         return;
     }
+    // FP32 block solves on FP32 copies; the last cycle's sweeps also write
+    // their blocks' result to psi in FP64 (every block has one of the colours)
     launch_f64_to_f32(rho, c->s32a, n, c->stream);
-    launch_zero<float>(c->s32b, n, c->stream);
-    for (int cy = 0; cy < c->p.ncy; ++cy)
+    for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             ProfScope ps(c, c->sap_prof_cls);
+            c64* out64 = cy == ncy - 1 ? psi : nullptr;
             if (c->p.link_prec == DFL_BF16)
                 launch_sap_colour_bf16(c->g, c->sg, linksbf(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
-                                       c->stream);
+                                       init_of(cy, col), out64, c->stream);
             else
                 launch_sap_colour32(c->g, c->sg, links32(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
-                                    c->stream);
+                                    init_of(cy, col), out64, c->stream);
         }
-    launch_f32_to_f64(c->s32b, psi, n, c->stream);
 }
 
 // ------------------------------------------------------------------ GCR

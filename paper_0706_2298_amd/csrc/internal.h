@@ -200,12 +200,15 @@ void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int
 
 // ------------------------------------------------------------------- sap.hip
 // one colour sweep for nrhs fields (each 12 V entries, back to back)
+// init: 0 = general psi, 1 = psi zero on the sweep's own blocks, 2 = psi
+// zero everywhere (the two sweeps of the first cycle); out64 (FP32 sweeps,
+// may be null): the blocks' new psi also written there in FP64
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi,
-                         double m0, int nmr, int colour, int nrhs, hipStream_t s);
+                         double m0, int nmr, int colour, int nrhs, int init, hipStream_t s);
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi,
-                         float m0, int nmr, int colour, int nrhs, hipStream_t s);
+                         float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s);
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi,
-                            float m0, int nmr, int colour, int nrhs, hipStream_t s);
+                            float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s);
 
 // ------------------------------------------------------------------ blas.hip
 template <typename T> void launch_zero(cpx<T>* x, long n, hipStream_t s);

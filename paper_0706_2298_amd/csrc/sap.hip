@@ -11,11 +11,28 @@
 // the current residue r is exchanged through LDS (12 planes x |block|), the
 // links come through L1/L2, and the two block reductions per step use
 // wavefront shuffles plus one LDS pass.
+//
+// init (first cycle, where psi starts at zero): 2 = psi is zero everywhere
+// (colour 0: the residue is rho, no hops, no reads of psi), 1 = psi is zero on
+// the sweep's own blocks (colour 1: only the neighbours' values are read).
+// out64 (optional, last cycle of an FP32 sweep): the block's new psi is also
+// written in FP64 there, so no conversion pass follows.
 #include "hop.h"
 
 namespace dfl {
 
 namespace {
+
+template <typename T> __device__ inline void store_spinor_f64(c64* __restrict__ f, long V, long s, const spinor<T>& p)
+{
+    spinor<double> d;
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            d.s[al].c[a] = c64{(double)p.s[al].c[a].re, (double)p.s[al].c[a].im};
+    store_spinor(f, V, s, d);
+}
 
 // D_Lambda hops of one site: neighbours inside the Schwarz block come from
 // the LDS copy of the residue; hops leaving the block are dropped.
@@ -44,15 +61,19 @@ __device__ inline void block_hops(const Geom& g, const SapGeom& sg, const L& U, 
     }
 }
 
-// all eight hops of the full operator at one site, neighbours from global memory
+// the eight hops of the full operator at one site, neighbours from global
+// memory; with outside_only, only the hops that leave the Schwarz block (the
+// block's own psi is zero in the first cycle's colour-1 sweep)
 template <typename T, typename L>
-__device__ inline void full_hops(const Geom& g, const L& U, const cpx<T>* __restrict__ psi, long s, const int n[4],
-                                 const int y[4], spinor<T>& acc)
+__device__ inline void full_hops(const Geom& g, const SapGeom& sg, const L& U, const cpx<T>* __restrict__ psi, long s,
+                                 const int n[4], const int y[4], const int yl[4], bool outside_only, spinor<T>& acc)
 {
 #pragma unroll 1
     for (int h = 0; h < 8; ++h) {
         const int mu = h >> 1;
         const int step = (h & 1) ? -1 : +1;
+        if (outside_only && (step > 0 ? yl[mu] + 1 < sg.sb[mu] : yl[mu] > 0))
+            continue;
         long tn = site_step(g, s, n, y, mu, step);
         spinor<T> p = load_spinor(psi, g.V, tn);
         if (step > 0)
@@ -64,11 +85,14 @@ __device__ inline void full_hops(const Geom& g, const L& U, const cpx<T>* __rest
 
 template <typename T, typename L>
 __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<T>* __restrict__ rho,
-                                             cpx<T>* __restrict__ psi, T diag, int nmr, int colour, int nrhs)
+                                             cpx<T>* __restrict__ psi, T diag, int nmr, int colour, int nrhs, int init,
+                                             c64* __restrict__ out64)
 {
     // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
     rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
     psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
+    if (out64)
+        out64 += (long)(blockIdx.x % nrhs) * 12 * g.V;
     extern __shared__ char smem_raw[];
     cpx<T>* lr = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[3][8];
@@ -113,10 +137,14 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
     zero(r);
     zero(xs);
     if (active) {
-        spinor<T> acc;
+        spinor<T> acc, self;
         zero(acc);
-        full_hops(g, U, psi, s, n, y, acc);
-        spinor<T> d = finish(load_spinor(psi, g.V, s), acc, diag);
+        zero(self);
+        if (init < 2)
+            full_hops(g, sg, U, psi, s, n, y, yl, init == 1, acc);
+        if (init == 0)
+            self = load_spinor(psi, g.V, s);
+        spinor<T> d = finish(self, acc, diag);
         spinor<T> b = load_spinor(rho, g.V, s);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
@@ -179,11 +207,16 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
     }
 
     if (active) {
-        spinor<T> p = load_spinor(psi, g.V, s);
+        spinor<T> p;
+        zero(p);
+        if (init == 0)
+            p = load_spinor(psi, g.V, s);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
             p.s[al] += xs.s[al];
         store_spinor(psi, g.V, s, p);
+        if (out64)
+            store_spinor_f64(out64, g.V, s, p);
     }
 }
 
@@ -228,11 +261,14 @@ template <typename L> __device__ inline su3<float> expand(const Link2<L>& l)
 
 template <typename L>
 __global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
-                                               c32* __restrict__ psi, float diag, int nmr, int colour, int nrhs)
+                                               c32* __restrict__ psi, float diag, int nmr, int colour, int nrhs,
+                                               int init, c64* __restrict__ out64)
 {
     // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
     rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
     psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
+    if (out64)
+        out64 += (long)(blockIdx.x % nrhs) * 12 * g.V;
     extern __shared__ char smem_raw[];
     c32* lr = reinterpret_cast<c32*>(smem_raw);
     __shared__ double red[3][8];
@@ -277,23 +313,29 @@ __global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c
     zero(r);
     zero(xs);
     if (active) {
-        spinor<float> acc;
+        spinor<float> acc, self;
         zero(acc);
+        zero(self);
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
             const int mu = h >> 1;
             const int step = (h & 1) ? -1 : +1;
             long tn = site_step(g, s, n, y, mu, step);
             lk[h] = load_link2(U, mu, step > 0 ? s : tn);
-            spinor<float> p = load_spinor(psi, g.V, tn);
-            if (step > 0)
-                hop_fwd_rt(mu, expand(lk[h]), p, acc);
-            else
-                hop_bwd_rt(mu, expand(lk[h]), p, acc);
+            const bool inside = step > 0 ? yl[mu] + 1 < sg.sb[mu] : yl[mu] > 0;
+            if (init == 0 || (init == 1 && !inside)) {
+                spinor<float> p = load_spinor(psi, g.V, tn);
+                if (step > 0)
+                    hop_fwd_rt(mu, expand(lk[h]), p, acc);
+                else
+                    hop_bwd_rt(mu, expand(lk[h]), p, acc);
+            }
             if (h & 1)
                 asm volatile("" ::: "memory");  // two hops' loads in flight at a time
         }
-        spinor<float> d = finish(load_spinor(psi, g.V, s), acc, diag);
+        if (init == 0)
+            self = load_spinor(psi, g.V, s);
+        spinor<float> d = finish(self, acc, diag);
         spinor<float> b = load_spinor(rho, g.V, s);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
@@ -375,17 +417,22 @@ __global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c
     }
 
     if (active) {
-        spinor<float> p = load_spinor(psi, g.V, s);
+        spinor<float> p;
+        zero(p);
+        if (init == 0)
+            p = load_spinor(psi, g.V, s);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
             p.s[al] += xs.s[al];
         store_spinor(psi, g.V, s, p);
+        if (out64)
+            store_spinor_f64(out64, g.V, s, p);
     }
 }
 
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            int nrhs, hipStream_t s);
+            int nrhs, int init, c64* out64, hipStream_t s);
 
 // One field with blocks of up to 256 sites: links in registers (one workgroup
 // per CU, the fastest sweep while the blocks of one colour leave CUs free).
@@ -394,46 +441,46 @@ void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* ps
 // 16^4: 18% less time).
 template <typename L>
 void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
-               int nrhs, hipStream_t s)
+               int nrhs, int init, c64* out64, hipStream_t s)
 {
     if (sg.Vsb > 256 || nrhs > 1) {
-        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
+        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
         return;
     }
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
     hipLaunchKernelGGL((k_sap_rl<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
-                       4.0f + m0, nmr, colour, nrhs);
+                       4.0f + m0, nmr, colour, nrhs, init, out64);
 }
 
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            int nrhs, hipStream_t s)
+            int nrhs, int init, c64* out64, hipStream_t s)
 {
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(cpx<T>);
     static std::once_flag attr;  // one per kernel instantiation
     set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap<T, L>), 160 * 1024 - 1024);
     hipLaunchKernelGGL((k_sap<T, L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
-                       T(4) + m0, nmr, colour, nrhs);
+                       T(4) + m0, nmr, colour, nrhs, init, out64);
 }
 
 }  // namespace
 
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi, double m0, int nmr,
-                         int colour, int nrhs, hipStream_t s)
+                         int colour, int nrhs, int init, hipStream_t s)
 {
-    launch(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
+    launch(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, (c64*)nullptr, s);
 }
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi, float m0, int nmr,
-                         int colour, int nrhs, hipStream_t s)
+                         int colour, int nrhs, int init, c64* out64, hipStream_t s)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
 }
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi, float m0,
-                            int nmr, int colour, int nrhs, hipStream_t s)
+                            int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
 }
 
 }  // namespace dfl
