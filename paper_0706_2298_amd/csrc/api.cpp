@@ -372,7 +372,8 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1)
 //
 // Flexible restarted GCR (section 6.2) for nb right-hand sides in lockstep:
 // xi_k = M rho, chi_k = Op xi_k, orthogonalised against chi_{<k} (classical
-// Gram-Schmidt applied twice), normalised, rho -= (chi_k, rho) chi_k. Every
+// Gram-Schmidt, a second pass where the first cancelled more than 99% of
+// ||chi_k||^2), normalised, rho -= (chi_k, rho) chi_k. Every
 // step is one batched launch sequence over all sources; each source has its
 // own coefficients and leaves the cycle when it converges. At the end of a
 // cycle the coefficients alpha solve the triangular system, x += sum alpha_k
