@@ -142,15 +142,18 @@ __device__ inline int nbr_block(const Geom& g, int blk, int d)
     return blk + (nn - n_mu) * g.bstr[mu];
 }
 
-// The workgroup's view: its vector entries are those of the blocks in vb
-// (all owned blocks g, g + G, ... when vb is null).
+// The workgroup's view: it owns the blocks g + i G (i = owned position); its
+// vector entries are those of the owned positions listed in vb (all of them
+// when vb is null). nbr (LDS, may be null): nbr[8 i + d - 1] = neighbour d of
+// owned position i.
 template <typename T> struct LittleCtx {
     const LittleArgs<T>& a;
     int G, g, t;
     long N;
     const int* vb;
     int nvb;
-    __device__ int block(int i) const { return vb ? vb[i] : g + i * G; }
+    const int* nbr;
+    __device__ int block(int i) const { return g + (vb ? vb[i] : i) * G; }
     __device__ long entry(int e) const
     {
         int i = e / a.Ns;
@@ -205,7 +208,7 @@ __device__ inline void reduce_slots(const double* __restrict__ part, int G, int 
 }
 
 // y_blk = alpha s_blk + beta sum_{d0 <= d < d1} Mat[blk][d] u_{nbr_d(blk)} for
-// the listed blocks (list null: the owned blocks g + i G, i < nlist). Mat is
+// the blocks at the listed owned positions (list null: positions 0..nlist-1). Mat is
 // stored transposed, Mat[blk][d][l][k] = (block d of blk)[k][l]. Task
 // (block, d, k) forms one term of row k (Ns multiply-adds over l, reading Mat
 // coalesced in k); the terms of a row are summed from LDS in a fixed order.
@@ -229,8 +232,9 @@ __device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int 
             const int d = d0 + rem / Ns;
             const int k = rem - (d - d0) * Ns;
             if (ib < bpr && i0 + ib < nlist) {
-                const int blk = list ? list[i0 + ib] : c.g + (i0 + ib) * c.G;
-                const int nbr = nbr_block(g, blk, d);
+                const int own = list ? list[i0 + ib] : i0 + ib;
+                const int blk = c.g + own * c.G;
+                const int nbr = d == 0 ? blk : (c.nbr ? c.nbr[8 * own + d - 1] : nbr_block(g, blk, d));
                 const cpx<T>* M = Mat + ((long)blk * 9 + d) * Ns * Ns + k;
                 const cpx<T>* vv = u + (long)nbr * Ns;
                 double re = 0.0, im = 0.0;
@@ -265,7 +269,7 @@ __device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int 
                     sr += lds[2 * (jb * per + dd * Ns + kk)];
                     si += lds[2 * (jb * per + dd * Ns + kk) + 1];
                 }
-                const int blk = list ? list[i0 + jb] : c.g + (i0 + jb) * c.G;
+                const int blk = c.g + (list ? list[i0 + jb] : i0 + jb) * c.G;
                 const long i = (long)blk * Ns + kk;
                 double yr = beta * sr, yi = beta * si;
                 if (alpha != 0.0) {
@@ -459,28 +463,30 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
     __shared__ double wn2_s, rn2_s;
     __shared__ int second_s;
     __shared__ double lds[2 * LT1];
-    __shared__ int l_even[EO ? kMaxOwned : 1], l_odd[EO ? kMaxOwned : 1];
+    __shared__ int l_even[EO ? kMaxOwned : 1], l_odd[EO ? kMaxOwned : 1];  // owned positions by colour
     __shared__ int n_even_s, n_odd_s;
+    __shared__ int nbr_tab[8 * kMaxOwned];  // neighbours of the owned blocks, computed once
 
     const int G = (int)gridDim.x, gi = (int)blockIdx.x, t = (int)threadIdx.x;
     const int nbg = (a.g.Nb - gi + G - 1) / G;
-    if (EO) {
-        if (t == 0) {
-            int ne = 0, no = 0;
-            for (int i = 0; i < nbg; ++i) {
-                const int blk = gi + i * G;
-                if (block_colour(a.g, blk))
-                    l_odd[no++] = blk;
-                else
-                    l_even[ne++] = blk;
-            }
-            n_even_s = ne;
-            n_odd_s = no;
+    const bool tab = nbg <= kMaxOwned;
+    if (tab)
+        for (int q = t; q < 8 * nbg; q += LT1)
+            nbr_tab[q] = nbr_block(a.g, gi + (q >> 3) * G, 1 + (q & 7));
+    if (EO && t == 0) {
+        int ne = 0, no = 0;
+        for (int i = 0; i < nbg; ++i) {
+            if (block_colour(a.g, gi + i * G))
+                l_odd[no++] = i;
+            else
+                l_even[ne++] = i;
         }
-        __syncthreads();
+        n_even_s = ne;
+        n_odd_s = no;
     }
+    __syncthreads();
     const int n_even = EO ? n_even_s : 0, n_odd = EO ? n_odd_s : 0;
-    LittleCtx<T> c{a, G, gi, t, (long)a.g.Nb * a.Ns, EO ? l_even : nullptr, EO ? n_even : nbg};
+    LittleCtx<T> c{a, G, gi, t, (long)a.g.Nb * a.Ns, EO ? l_even : nullptr, EO ? n_even : nbg, tab ? nbr_tab : nullptr};
     const double tol2 = a.tol_dev ? (*a.tol_dev) * (*a.tol_dev) : a.tol2;
     unsigned long long bar_target = 0;
     if (c.t == 0)
