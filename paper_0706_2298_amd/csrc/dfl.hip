@@ -138,8 +138,98 @@ __global__ __launch_bounds__(256) void k_prolong(Geom g, const c64* __restrict__
 }
 
 // Modified Gram-Schmidt per block, in place, order l = 0..Ns-1 (eq. (4.2)).
-// flag is set to 1 if a block loses rank.
+// flag is set to 1 if a block loses rank; R (may be null) receives the
+// triangular factor. One workgroup per block; the field being orthogonalised
+// is held in registers (E entries per thread, 12 Vb <= E kBT), so each
+// projection reads only the earlier basis field and needs one reduction.
+// Blocks of more than 512 sites use k_block_gs_stream, which streams both
+// fields through memory.
+
+// sum over the workgroup of a complex value, the same in every thread (fixed order)
+__device__ inline double2 block_sum2(double2 v, double2* sh)
+{
+    v.x = wave_sum(v.x);
+    v.y = wave_sum(v.y);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0)
+        sh[wid] = v;
+    __syncthreads();
+    double2 t = make_double2(0.0, 0.0);
+    for (int q = 0; q < nw; ++q) {
+        t.x += sh[q].x;
+        t.y += sh[q].y;
+    }
+    __syncthreads();
+    return t;
+}
+
+template <int E>
 __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
+                                                  int* __restrict__ flag, c64* __restrict__ R)
+{
+    __shared__ double2 sh[kBT / 64];
+    const int blk = blockIdx.x;
+    const long fs = 12 * g.V;
+    const int ne = 12 * g.Vb;
+    for (int l = 0; l < Ns; ++l) {
+        c64* fl = F + (long)l * fs;
+        c64 v[E];
+        double n0 = 0.0;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int e = threadIdx.x + j * kBT;
+            v[j] = e < ne ? fl[block_elem(g, blk, e)] : c64{0.0, 0.0};
+            n0 += v[j].re * v[j].re + v[j].im * v[j].im;
+        }
+        // norm of the restricted input field (for the rank test)
+        n0 = block_sum2(make_double2(n0, 0.0), sh).x;
+        for (int k = 0; k < l; ++k) {
+            const c64* fk = F + (long)k * fs;
+            c64 u[E];
+            double2 d = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int e = threadIdx.x + j * kBT;
+                u[j] = e < ne ? fk[block_elem(g, blk, e)] : c64{0.0, 0.0};
+                d.x += u[j].re * v[j].re + u[j].im * v[j].im;
+                d.y += u[j].re * v[j].im - u[j].im * v[j].re;
+            }
+            d = block_sum2(d, sh);
+            const c64 cf{d.x, d.y};
+            if (R && threadIdx.x == 0)
+                R[((long)blk * Ns + k) * Ns + l] = cf;
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+                v[j] -= cf * u[j];
+        }
+        double nv = 0.0;
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            nv += v[j].re * v[j].re + v[j].im * v[j].im;
+        nv = sqrt(block_sum2(make_double2(nv, 0.0), sh).x);
+        n0 = sqrt(n0);
+        if (R && threadIdx.x == 0) {
+            R[((long)blk * Ns + l) * Ns + l] = c64{nv, 0.0};
+            for (int k = l + 1; k < Ns; ++k)
+                R[((long)blk * Ns + k) * Ns + l] = c64{0.0, 0.0};
+        }
+        if (!(nv > rank_tol * n0) || !(n0 > 0.0)) {
+            if (threadIdx.x == 0)
+                atomicOr(flag, 2);
+            nv = 1.0;
+        }
+        const double inv = 1.0 / nv;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int e = threadIdx.x + j * kBT;
+            if (e < ne)
+                fl[block_elem(g, blk, e)] = c64{v[j].re * inv, v[j].im * inv};
+        }
+    }
+}
+
+// The same Gram-Schmidt for blocks of any size, both fields streamed through memory.
+__global__ __launch_bounds__(kBT) void k_block_gs_stream(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
                                                   int* __restrict__ flag, c64* __restrict__ R)
 {
     __shared__ double sh[8];
@@ -672,7 +762,15 @@ void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* 
 }
 void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_block_gs, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
+    const int e = (12 * (int)g.Vb + kBT - 1) / kBT;  // entries per thread
+    if (e <= 6)
+        hipLaunchKernelGGL(k_block_gs<6>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
+    else if (e <= 12)
+        hipLaunchKernelGGL(k_block_gs<12>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
+    else if (e <= 24)
+        hipLaunchKernelGGL(k_block_gs<24>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
+    else
+        hipLaunchKernelGGL(k_block_gs_stream, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
 }
 int little_columns_max(int Ns)
 {

@@ -528,3 +528,19 @@ def test_bench_workload_16x4():
         assert true_rel <= bench.TOL, (m0, info.as_dict())
         assert abs(info.rel_residual - true_rel) < 1e-12
     S.close()
+
+
+@pytest.mark.parametrize("dims,b", [((8, 8, 8, 8), (2, 2, 2, 4)), ((8, 8, 8, 16), (4, 4, 4, 8)),
+                                    ((16, 8, 8, 16), (8, 4, 4, 8))])
+def test_block_gram_schmidt_block_sizes(dims, b):
+    # without inverse-iteration steps the basis is the block Gram-Schmidt of
+    # the start fields (eq. (4.2)); block volumes 32, 512 and 1024 run the
+    # register kernel with 6 and 24 entries per thread and the streaming one
+    say(f"block GS {dims} blocks {b}")
+    U = latgen.make_links(dims, 0.4, 71)
+    init = latgen.make_init_fields(dims, 6, 72)
+    S = Solver(dims, dfl_block=b, sap_block=(4, 4, 4, 4), Ns=6, n_inviter=0, m0=-0.2, m0_setup=-0.2)
+    S.set_gauge(U)
+    S.setup(S.pack(init))
+    assert rel(S.unpack(S.basis()), oracle.block_gram_schmidt(init, dims, b)) < 1e-12
+    S.close()
