@@ -334,6 +334,14 @@ void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0, int nb = 1)
     launch_dirac64(c->g, links64(c), in, out, nb, m0, 0, 0, 0, c->stream);
 }
 
+// out = s - D in for nb fields (the subtraction fused into the stencil); out
+// must alias neither s nor in
+void dirac64_sub(dfl_ctx* c, const c64* s, const c64* in, c64* out, double m0, int nb = 1)
+{
+    ProfScope ps(c, DFL_PROF_DIRAC);
+    launch_dirac64_sub(c->g, links64(c), s, in, out, nb, m0, c->stream);
+}
+
 // psi = M_sap rho for nrhs fields (FP64 in and out; block solves in sap_prec).
 // One launch per colour sweep covers all nrhs fields.
 void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1)
@@ -630,8 +638,12 @@ void apply_PL(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, c6
               const double* tol_dev = nullptr)
 {
     coarse(c, in, tmpA, tol, prec, nb, tol_dev);
-    dirac64(c, tmpA, tmpB, c->p.m0, nb);
-    launch_sub<double>(in, tmpB, out, c->field_elems * nb, c->stream);
+    if (out != in) {
+        dirac64_sub(c, in, tmpA, out, c->p.m0, nb);
+    } else {
+        dirac64(c, tmpA, tmpB, c->p.m0, nb);
+        launch_sub<double>(in, tmpB, out, c->field_elems * nb, c->stream);
+    }
 }
 
 // Even-odd matrices of the little operator (appendix A.2) after A changed;
@@ -1405,12 +1417,11 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
         }
     };
     auto recompute = [&](const c64* x, c64* r, int n_b) {
-        dirac64(c, x, c->t1, m0, n_b);
         if (deflate) {
-            launch_sub<double>(eta, c->t1, c->t3, F * n_b, c->stream);
+            dirac64_sub(c, eta, x, c->t3, m0, n_b);
             apply_PL(c, c->t3, r, c->p.little_tol_out, DFL_F64, c->t1, c->t2, n_b);
         } else {
-            launch_sub<double>(eta, c->t1, r, F * n_b, c->stream);
+            dirac64_sub(c, eta, x, r, m0, n_b);
         }
     };
     // With inexact projections inside the cycle (little solves to
@@ -1429,16 +1440,14 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
                                          adapt ? std::function<double(double)>(inner_tol) : nullptr);
     // final solutions: psi = acc + Phi A^-1 Phi^+ (eta - D acc)   (eq. (3.10) with P_R)
     if (deflate) {
-        dirac64(c, c->acc, c->t1, m0, nb);
-        launch_sub<double>(eta, c->t1, c->t3, F * nb, c->stream);
+        dirac64_sub(c, eta, c->acc, c->t3, m0, nb);
         coarse(c, c->t3, c->t1, c->p.little_tol_out, DFL_F64, nb);
         launch_add<double>(c->acc, c->t1, psi, F * nb, c->stream);
     } else {
         launch_copy<double>(c->acc, psi, F * nb, c->stream);
     }
     // true residuals in FP64
-    dirac64(c, psi, c->t1, m0, nb);
-    launch_sub<double>(eta, c->t1, c->t2, F * nb, c->stream);
+    dirac64_sub(c, eta, psi, c->t2, m0, nb);
     std::vector<double> rr = host_norm2_b(c, c->t2, F, nb);
     auto t1 = std::chrono::steady_clock::now();
     int ls[3] = {0, 0, 0};

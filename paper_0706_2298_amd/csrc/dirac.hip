@@ -49,7 +49,7 @@ __device__ inline void hops_all(const Geom& g, const L& U, const cpx<T>* __restr
 template <int MODE, typename T, typename L>
 __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __restrict__ psi,
                                                cpx<T>* __restrict__ out, T diag, int hop_mu, int hop_dir,
-                                               int chunks_padded, int nrhs)
+                                               int chunks_padded, int nrhs, const cpx<T>* __restrict__ sub)
 {
     const int per = chunks_padded / kNumXcd;
     const int local = blockIdx.x / kNumXcd;
@@ -73,6 +73,12 @@ __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __rest
     } else {
         o = finish(load_spinor(f, g.V, s), acc, diag);
     }
+    if (sub) {
+        const spinor<T> a = load_spinor(sub + off, g.V, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+            o.s[al] = a.s[al] - o.s[al];
+    }
     store_spinor(out + off, g.V, s, o);
 }
 
@@ -83,7 +89,8 @@ __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __rest
 // The output is written with non-temporal stores (it is not re-read here).
 template <typename T, typename L>
 __global__ __launch_bounds__(256) void k_dirac_blk(Geom g, L U, const cpx<T>* __restrict__ psi,
-                                                   cpx<T>* __restrict__ out, T diag, int chunks_padded, int nrhs)
+                                                   cpx<T>* __restrict__ out, T diag, int chunks_padded, int nrhs,
+                                                   const cpx<T>* __restrict__ sub)
 {
     __shared__ cpx<T> sp[12][256];
     const int per = chunks_padded / kNumXcd;
@@ -132,7 +139,13 @@ __global__ __launch_bounds__(256) void k_dirac_blk(Geom g, L U, const cpx<T>* __
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             self.s[al].c[a] = sp[3 * al + a][t0];
-    const spinor<T> o = finish(self, acc, diag);
+    spinor<T> o = finish(self, acc, diag);
+    if (sub) {
+        const spinor<T> a = load_spinor(sub + off, g.V, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+            o.s[al] = a.s[al] - o.s[al];
+    }
     cpx<T>* dst = out + off;
 #pragma unroll
     for (int al = 0; al < 4; ++al)
@@ -187,19 +200,21 @@ __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* _
     store_spinor(out + off, g.V, s, finish(z, acc, T(0)));
 }
 
+// sub (MODE 0, may be null): out = sub - D psi
 template <int MODE, typename T, typename L>
-void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, int mu, int dir, hipStream_t s)
+void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, int mu, int dir, hipStream_t s,
+            const cpx<T>* sub = nullptr)
 {
     if (MODE == 0 && g.Vb == 256) {
         const int gp = pad_grid(g.Nb);
         hipLaunchKernelGGL((k_dirac_blk<T, L>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, gp,
-                           nrhs);
+                           nrhs, sub);
         return;
     }
     long nwg = (g.V + 255) / 256;
     int gp = pad_grid(nwg);
     hipLaunchKernelGGL((k_dirac<MODE, T, L>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, mu, dir,
-                       gp, nrhs);
+                       gp, nrhs, MODE == 0 ? sub : nullptr);
 }
 
 }  // namespace
@@ -213,6 +228,12 @@ void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs
         launch<1>(g, U, psi, out, nrhs, m0, mu, dir, s);
     else
         launch<2>(g, U, psi, out, nrhs, m0, mu, dir, s);
+}
+
+void launch_dirac64_sub(const Geom& g, Links64 U, const c64* sub, const c64* psi, c64* out, int nrhs, double m0,
+                        hipStream_t s)
+{
+    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s, sub);
 }
 
 void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s)

@@ -193,6 +193,9 @@ void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s);
 // mu, orientation dir (no mass term).
 void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, double m0,
                     int mode, int mu, int dir, hipStream_t s);
+// out = sub - D psi (full operator, FP64) for nrhs fields; out aliases neither sub nor psi
+void launch_dirac64_sub(const Geom& g, Links64 U, const c64* sub, const c64* psi, c64* out, int nrhs, double m0,
+                        hipStream_t s);
 // MODE 2 on the face sites only (other sites of out untouched)
 void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s);
 void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s);
