@@ -259,8 +259,11 @@ template <typename L> __device__ inline su3<float> expand(const Link2<L>& l)
     return u;
 }
 
-template <typename L>
-__global__ __launch_bounds__(256) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
+// W: wavefronts per SIMD the register budget must allow (1: one block per CU,
+// no spills; 2: two blocks per CU at a few spilled registers, the faster
+// choice once the blocks of all fields outnumber the CUs)
+template <typename L, int W>
+__global__ __launch_bounds__(256, W) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
                                                c32* __restrict__ psi, float diag, int nmr, int colour, int nrhs,
                                                int init, c64* __restrict__ out64)
 {
@@ -434,23 +437,27 @@ template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
             int nrhs, int init, c64* out64, hipStream_t s);
 
-// One field with blocks of up to 256 sites: links in registers (one workgroup
-// per CU, the fastest sweep while the blocks of one colour leave CUs free).
-// Several fields (or larger blocks): the generic kernel, which fits three
-// workgroups per CU and so sweeps many blocks at a higher rate (16 fields on
-// 16^4: 18% less time).
+// Blocks of up to 256 sites: links in registers. One field: one block per CU
+// (the fastest sweep while the blocks of one colour leave CUs free); several
+// fields: two blocks per CU (16 fields on 16^4: 12% faster than the generic
+// kernel at three blocks per CU, which re-reads the links every MR step).
+// Larger blocks: the generic kernel.
 template <typename L>
 void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
                int nrhs, int init, c64* out64, hipStream_t s)
 {
-    if (sg.Vsb > 256 || nrhs > 1) {
+    if (sg.Vsb > 256) {
         launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
         return;
     }
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
-    hipLaunchKernelGGL((k_sap_rl<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
-                       4.0f + m0, nmr, colour, nrhs, init, out64);
+    if (nrhs > 1)
+        hipLaunchKernelGGL((k_sap_rl<L, 2>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
+                           4.0f + m0, nmr, colour, nrhs, init, out64);
+    else
+        hipLaunchKernelGGL((k_sap_rl<L, 1>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
+                           4.0f + m0, nmr, colour, nrhs, init, out64);
 }
 
 template <typename T, typename L>
