@@ -233,12 +233,46 @@ __host__ inline int pad_grid(long nwg) { return (int)(((nwg + kNumXcd - 1) / kNu
 
 // --------------------------------------------------------- reductions
 
+// Sum over the 64 lanes of a wavefront, the same value in every lane; every
+// lane must be active. Cross-lane moves go through DPP: swaps inside quads,
+// the half-row and row mirrors (16-lane sums in every lane), then row 0's and
+// row 2's last lanes are broadcast into rows 1 and 3, and lane 31 into rows 2
+// and 3, which leaves the total in lane 63; a readlane hands it to all.
+namespace wave_detail {
+template <int CTRL, int ROWS> __device__ inline int dpp(int v)
+{
+    // lanes of rows outside ROWS (and lanes without a source) receive 0
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS> __device__ inline double dpp(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp<CTRL, ROWS>((int)b), hi = dpp<CTRL, ROWS>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROWS> __device__ inline float dpp(float v)
+{
+    return __int_as_float(dpp<CTRL, ROWS>(__float_as_int(v)));
+}
+__device__ inline double lane63(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+}  // namespace wave_detail
+
 template <typename T> __device__ inline T wave_sum(T v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off, 64);
-    return v;
+    using namespace wave_detail;
+    v += dpp<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp<0x140, 0xF>(v);  // row_mirror
+    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return lane63(v);
 }
 
 // Sum of v over the workgroup (blockDim.x a multiple of 64, <= 1024); every

@@ -433,14 +433,277 @@ __global__ __launch_bounds__(256, W) void k_sap_rl(Geom g, SapGeom sg, L U, cons
     }
 }
 
+// ---------------------------------------------------------------- lane pairs
+//
+// FP32 sweep with two lanes per site (adjacent lanes 2i, 2i+1). The even lane
+// takes the four forward hops, (1 - g_mu) U_mu(x) psi(x + mu), the odd lane
+// the four backward ones, (1 + g_mu) U_mu(x - mu)^+ psi(x - mu). The odd lane
+// holds the adjoint of its link, and its spin projection and reconstruction
+// equal the forward ones with the sign of every e_mu term flipped (see the
+// projector identities in hop.h), so both lanes run one instruction stream
+// with the sign as an FMA operand. The pair's partial sums are combined by
+// one cross-lane add per real, and each lane owns two of the site's four spin
+// components of the residue, the MR direction and the block solution
+// (even: spins 0 and 1, odd: 2 and 3). Four links of 3x3 per lane (72 VGPRs)
+// leave room for two wavefronts per SIMD.
+
+// x + s*y, x + s*i*y and x - s*i*y with the lane's sign s
+__device__ inline c32 add_s(c32 x, float sg, c32 y) { return {fmaf(sg, y.re, x.re), fmaf(sg, y.im, x.im)}; }
+__device__ inline c32 add_si(c32 x, float sg, c32 y) { return {fmaf(-sg, y.im, x.re), fmaf(sg, y.re, x.im)}; }
+__device__ inline c32 add_smi(c32 x, float sg, c32 y) { return {fmaf(sg, y.im, x.re), fmaf(-sg, y.re, x.im)}; }
+
+// acc += forward (sg = +1, w = U_mu(x)) or backward (sg = -1, w = U_mu(x-mu)^+) hop of p
+template <int MU>
+__device__ inline void hop_pair(const su3<float>& w, const spinor<float>& p, float sg, spinor<float>& acc)
+{
+    cvec3<float> h0, h1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (MU == 0) {
+            h0.c[a] = add_s(p.s[0].c[a], sg, p.s[2].c[a]);
+            h1.c[a] = add_s(p.s[1].c[a], sg, p.s[3].c[a]);
+        } else if (MU == 1) {
+            h0.c[a] = add_si(p.s[0].c[a], sg, p.s[3].c[a]);
+            h1.c[a] = add_si(p.s[1].c[a], sg, p.s[2].c[a]);
+        } else if (MU == 2) {
+            h0.c[a] = add_s(p.s[0].c[a], sg, p.s[3].c[a]);
+            h1.c[a] = add_s(p.s[1].c[a], -sg, p.s[2].c[a]);
+        } else {
+            h0.c[a] = add_si(p.s[0].c[a], sg, p.s[2].c[a]);
+            h1.c[a] = add_smi(p.s[1].c[a], sg, p.s[3].c[a]);
+        }
+    }
+    cvec3<float> w0 = mul(w, h0);
+    cvec3<float> w1 = mul(w, h1);
+    acc.s[0] += w0;
+    acc.s[1] += w1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (MU == 0) {
+            acc.s[2].c[a] = add_s(acc.s[2].c[a], sg, w0.c[a]);
+            acc.s[3].c[a] = add_s(acc.s[3].c[a], sg, w1.c[a]);
+        } else if (MU == 1) {
+            acc.s[2].c[a] = add_smi(acc.s[2].c[a], sg, w1.c[a]);
+            acc.s[3].c[a] = add_smi(acc.s[3].c[a], sg, w0.c[a]);
+        } else if (MU == 2) {
+            acc.s[2].c[a] = add_s(acc.s[2].c[a], -sg, w1.c[a]);
+            acc.s[3].c[a] = add_s(acc.s[3].c[a], sg, w0.c[a]);
+        } else {
+            acc.s[2].c[a] = add_smi(acc.s[2].c[a], sg, w0.c[a]);
+            acc.s[3].c[a] = add_si(acc.s[3].c[a], sg, w1.c[a]);
+        }
+    }
+}
+
+// v + (v of the other lane of the pair); every lane of the wavefront must take part
+__device__ inline float pair_sum(float v)
+{
+    // DPP quad_perm [1, 0, 3, 2]: swap adjacent lanes
+    int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false);
+    return v + __int_as_float(o);
+}
+
+// the lane's link for direction mu: U_mu(x) (forward lane) or U_mu(x - mu)^+ (backward lane)
+template <typename L> __device__ inline su3<float> pair_link(const L& U, int mu, long site, bool bwd)
+{
+    su3<float> u = expand(load_link2(U, mu, site));
+    su3<float> w;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const c32 x = u.m[a][b], y = u.m[b][a];
+            w.m[a][b] = bwd ? c32{y.re, -y.im} : x;
+        }
+    return w;
+}
+
+template <typename L>
+__global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
+                                                     c32* __restrict__ psi, float diag, int nmr, int colour,
+                                                     int nrhs, int init, c64* __restrict__ out64)
+{
+    rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
+    psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
+    if (out64)
+        out64 += (long)(blockIdx.x % nrhs) * 12 * g.V;
+    extern __shared__ char smem_raw[];
+    c32* lr = reinterpret_cast<c32*>(smem_raw);
+    __shared__ double red[3][8];
+
+    const int t = threadIdx.x;
+    const int ts = t >> 1;           // site in the block
+    const int hb = t & 1;            // 0: forward hops, spins 0-1; 1: backward hops, spins 2-3
+    const float sgn = hb ? -1.0f : 1.0f;
+    const bool active = ts < sg.Vsb;  // both lanes of a pair agree
+    const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+
+    int k = blockIdx.x / nrhs;
+    int half = sg.nsb[3] / 2;
+    int m[4];
+    int j = k % half;
+    int rest = k / half;
+    m[2] = rest % sg.nsb[2];
+    rest /= sg.nsb[2];
+    m[1] = rest % sg.nsb[1];
+    m[0] = rest / sg.nsb[1];
+    m[3] = 2 * j + ((colour + m[0] + m[1] + m[2]) & 1);
+
+    int yl[4] = {0, 0, 0, 0};
+    int n[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
+    long s = 0;
+    if (active) {
+        int tt = ts;
+        yl[3] = tt % sg.sb[3];
+        tt /= sg.sb[3];
+        yl[2] = tt % sg.sb[2];
+        tt /= sg.sb[2];
+        yl[1] = tt % sg.sb[1];
+        yl[0] = tt / sg.sb[1];
+        for (int mu = 0; mu < 4; ++mu) {
+            int x = m[mu] * sg.sb[mu] + yl[mu];
+            n[mu] = x / g.b[mu];
+            y[mu] = x - n[mu] * g.b[mu];
+        }
+        s = site_compose(g, n, y);
+    }
+    // neighbour of this lane's hop inside the block
+    bool inside[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+        inside[mu] = hb ? yl[mu] > 0 : yl[mu] + 1 < sg.sb[mu];
+    const int c0 = 6 * hb;  // first owned component (3 * spin + colour)
+
+    // residual with the full operator; the links are kept for the MR steps
+    su3<float> lk[4];
+    spinor<float> acc;
+    zero(acc);
+    if (active) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            long tn = site_step(g, s, n, y, mu, hb ? -1 : +1);
+            lk[mu] = pair_link(U, mu, hb ? tn : s, hb != 0);
+            if (init == 0 || (init == 1 && !inside[mu])) {
+                spinor<float> p = load_spinor(psi, g.V, tn);
+                if (mu == 0) hop_pair<0>(lk[0], p, sgn, acc);
+                else if (mu == 1) hop_pair<1>(lk[1], p, sgn, acc);
+                else if (mu == 2) hop_pair<2>(lk[2], p, sgn, acc);
+                else hop_pair<3>(lk[3], p, sgn, acc);
+            }
+            if (mu & 1)
+                asm volatile("" ::: "memory");  // two hops' loads in flight at a time
+        }
+    }
+    c32 r[6], xs[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        // pair sum, then the owned half (spins 0-1 or 2-3)
+        const int al = i / 3, a = i % 3;
+        c32 lo{pair_sum(acc.s[al].c[a].re), pair_sum(acc.s[al].c[a].im)};
+        c32 hi{pair_sum(acc.s[al + 2].c[a].re), pair_sum(acc.s[al + 2].c[a].im)};
+        c32 ao = hb ? hi : lo;
+        r[i] = c32{0.0f, 0.0f};
+        xs[i] = c32{0.0f, 0.0f};
+        if (active) {
+            c32 self = c32{0.0f, 0.0f};
+            if (init == 0)
+                self = ld(psi, toff<c32>(s, c0 + i, 12));
+            const c32 b = ld(rho, toff<c32>(s, c0 + i, 12));
+            r[i] = c32{b.re - (diag * self.re - 0.5f * ao.re), b.im - (diag * self.im - 0.5f * ao.im)};
+        }
+    }
+
+    for (int stp = 0; stp < nmr; ++stp) {
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+                lr[(c0 + i) * sg.Vsb + ts] = r[i];
+        }
+        __syncthreads();
+        zero(acc);
+        if (active) {
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                if (inside[mu]) {
+                    const int tn = ts + (hb ? -sg.lstr[mu] : sg.lstr[mu]);
+                    spinor<float> p;
+#pragma unroll
+                    for (int al = 0; al < 4; ++al)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            p.s[al].c[a] = lr[(3 * al + a) * sg.Vsb + tn];
+                    if (mu == 0) hop_pair<0>(lk[0], p, sgn, acc);
+                    else if (mu == 1) hop_pair<1>(lk[1], p, sgn, acc);
+                    else if (mu == 2) hop_pair<2>(lk[2], p, sgn, acc);
+                    else hop_pair<3>(lk[3], p, sgn, acc);
+                }
+                if (mu & 1)
+                    asm volatile("" ::: "memory");
+            }
+        }
+        c32 q[6];
+        double qr_re = 0.0, qr_im = 0.0, qq = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const int al = i / 3, a = i % 3;
+            c32 lo{pair_sum(acc.s[al].c[a].re), pair_sum(acc.s[al].c[a].im)};
+            c32 hi{pair_sum(acc.s[al + 2].c[a].re), pair_sum(acc.s[al + 2].c[a].im)};
+            c32 ao = hb ? hi : lo;
+            q[i] = c32{diag * r[i].re - 0.5f * ao.re, diag * r[i].im - 0.5f * ao.im};
+            double qa = (double)q[i].re, qb = (double)q[i].im;
+            double ra = (double)r[i].re, rb = (double)r[i].im;
+            qr_re += qa * ra + qb * rb;
+            qr_im += qa * rb - qb * ra;
+            qq += qa * qa + qb * qb;
+        }
+        qr_re = wave_sum(qr_re);
+        qr_im = wave_sum(qr_im);
+        qq = wave_sum(qq);
+        if (lane == 0) {
+            red[0][wid] = qr_re;
+            red[1][wid] = qr_im;
+            red[2][wid] = qq;
+        }
+        __syncthreads();
+        double sre = 0.0, sim = 0.0, sqq = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            sre += red[0][w];
+            sim += red[1][w];
+            sqq += red[2][w];
+        }
+        if (!(sqq > 0.0))
+            break;  // zero residue on this block: uniform across the workgroup
+        c32 alpha{(float)(sre / sqq), (float)(sim / sqq)};
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            xs[i] += alpha * r[i];
+            r[i] -= alpha * q[i];
+        }
+    }
+
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            c32 p = xs[i];
+            if (init == 0)
+                p += ld(psi, toff<c32>(s, c0 + i, 12));
+            st(psi, toff<c32>(s, c0 + i, 12), p);
+            if (out64)
+                st(out64, toff<c64>(s, c0 + i, 12), c64{(double)p.re, (double)p.im});
+        }
+    }
+}
+
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
             int nrhs, int init, c64* out64, hipStream_t s);
 
-// Blocks of up to 256 sites: links in registers. One field: one block per CU
-// (the fastest sweep while the blocks of one colour leave CUs free); several
-// fields: two blocks per CU (16 fields on 16^4: 12% faster than the generic
-// kernel at three blocks per CU, which re-reads the links every MR step).
+// Blocks of up to 256 sites: links in registers. One field: lane pairs, one
+// block per CU at two wavefronts per SIMD (the blocks of one colour leave CUs
+// free; 16^4 with 4^4 blocks: 5% faster than one lane per site); several
+// fields: one lane per site, two blocks per CU (16 fields on 16^4: 12% faster
+// than the generic kernel at three blocks per CU, which re-reads the links
+// every MR step, and 28% faster than lane pairs at one block per CU).
 // Larger blocks: the generic kernel.
 template <typename L>
 void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
@@ -450,8 +713,14 @@ void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, 
         launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
         return;
     }
-    int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
+    if (nrhs == 1) {
+        int threads = ((2 * sg.Vsb + 63) / 64) * 64;
+        hipLaunchKernelGGL((k_sap_pair<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
+                           4.0f + m0, nmr, colour, nrhs, init, out64);
+        return;
+    }
+    int threads = ((sg.Vsb + 63) / 64) * 64;
     if (nrhs > 1)
         hipLaunchKernelGGL((k_sap_rl<L, 2>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
                            4.0f + m0, nmr, colour, nrhs, init, out64);
