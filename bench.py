@@ -169,7 +169,7 @@ def roofline(prof, little_it):
     if cls == "sap":
         flops = sap_flops_per_site(NMR) * (V // 2)          # one colour sweep visits half the sites
         ach = flops / dur / 1e12
-        r = dict(kernel="k_sap_rl<Links32, 1> (Schwarz colour sweep of one field, FP32, 4^4 blocks)", bound="alu", achieved=ach,
+        r = dict(kernel="k_sap_pair<Links32> (Schwarz colour sweep of one field, FP32, 4^4 blocks, two lanes per site)", bound="alu", achieved=ach,
                  peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / FP32_VECTOR_PEAK_TFLOPS,
                  per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {V // 2} sites")
     elif cls == "little":

@@ -96,27 +96,28 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot_partial(const cpx<T>* 
     }
 }
 
-// dst[b*dstride + 2j + c] = sum over workgroups of RHS b's partials, j < m (fixed order)
+// dst[b*dstride + jc] = sum over workgroups of RHS b's partials, jc < 2m
+// (jc = 2j + {0: re, 1: im}); one wavefront per value, a fixed lane-strided
+// order and wavefront tree. Grid: (ceil(2m / 4), nrhs) workgroups of 256.
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int m,
                                                          double* __restrict__ dst, int dstride,
                                                          const int* __restrict__ active)
 {
-    const int b = blockIdx.x;
+    const int b = blockIdx.y;
     if (active && !active[b])
         return;
+    const int lane = threadIdx.x & 63;
+    const int jc = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (jc >= 2 * m)
+        return;  // whole wavefronts
     partial += (long)b * kMaxDot * kRedBlocks * 2;
-    dst += (long)b * dstride;
-    __shared__ double sh[4];
-    for (int jc = 0; jc < 2 * m; ++jc) {
-        int j = jc >> 1, c = jc & 1;
-        double t = 0.0;
-        for (int q = threadIdx.x; q < kRedBlocks; q += blockDim.x)
-            t += partial[((long)j * kRedBlocks + q) * 2 + c];
-        t = block_sum(t, sh);
-        if (threadIdx.x == 0)
-            dst[jc] = t;
-        __syncthreads();
-    }
+    const int j = jc >> 1, c = jc & 1;
+    double t = 0.0;
+    for (int q = lane; q < kRedBlocks; q += 64)
+        t += partial[((long)j * kRedBlocks + q) * 2 + c];
+    t = wave_sum(t);
+    if (lane == 0)
+        dst[(long)b * dstride + jc] = t;
 }
 
 template <typename T>
@@ -245,7 +246,7 @@ void launch_multidot_b(const cpx<T>* X, long stride, int m, const cpx<T>* y, lon
         hipLaunchKernelGGL(k_multidot_partial<T>, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, s, X, stride, j0, mm,
                            y, n, xb, yb, active, red);
     }
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, s, red, m, dst, dstride, active);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((2 * m + 3) / 4, nb), dim3(256), 0, s, red, m, dst, dstride, active);
 }
 
 template <typename T>
@@ -255,7 +256,7 @@ void launch_norm2_b(const cpx<T>* x, long n, int nb, long xb, double* red, doubl
     if (nb <= 0)
         return;
     hipLaunchKernelGGL(k_norm2_partial<T>, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, s, x, n, xb, active, red);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, s, red, 1, dst, dstride, active);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1, nb), dim3(256), 0, s, red, 1, dst, dstride, active);
 }
 
 template <typename T>

@@ -25,11 +25,10 @@ __device__ inline long block_elem(const Geom& g, int blk, int e)
 // w_b[blk*Ns + k] = sum_{x in blk} sum_c conj(Phi_k(x,c)) psi_b(x,c)   (eq. (4.1))
 // One workgroup per (block, k); the Ns workgroups of a block are adjacent in
 // the XCD-remapped order, so the block of psi_b is fetched into one L2. The
-// Phi_k entries are read once per chunk of kRB right-hand sides.
-// RU entries per thread have their loads issued together (one pass over eight
-// right-hand sides already has nine loads per entry in flight)
-// RB: right-hand sides per pass (1 for a single field, else kRB)
-template <int RB, int RU = (RB == 1 ? 4 : 1)>
+// Phi_k entries are read once per chunk of RB right-hand sides (one pass
+// over eight right-hand sides has nine loads per entry in flight). A single
+// field uses k_restrict_kg below.
+template <int RB>
 __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict__ Phi, int Ns,
                                                   const c64* __restrict__ psi, c64* __restrict__ w, int nrhs,
                                                   int grid_padded)
@@ -49,43 +48,16 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
 #pragma unroll
         for (int j = 0; j < RB; ++j)
             re[j] = im[j] = 0.0;
-        if constexpr (RU == 1) {
-            for (int e = threadIdx.x; e < ne; e += kBT) {
-                const long i = block_elem(g, blk, e);
-                const c64 a = ph[i];
+        for (int e = threadIdx.x; e < ne; e += kBT) {
+            const long i = block_elem(g, blk, e);
+            const c64 a = ph[i];
 #pragma unroll
-                for (int j = 0; j < RB; ++j)
-                    if (b0 + j < nrhs) {
-                        const c64 b = psi[(long)(b0 + j) * fs + i];
-                        re[j] += a.re * b.re + a.im * b.im;
-                        im[j] += a.re * b.im - a.im * b.re;
-                    }
-            }
-        } else {
-            // RU entries per thread at a time, their loads issued together
-            // (entry indices clamped to valid memory; the extra terms are dropped)
-            for (int e0 = threadIdx.x; e0 < ne; e0 += RU * kBT) {
-                c64 av[RU], bv[RU][RB];
-#pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const long i = block_elem(g, blk, min(e0 + u * kBT, ne - 1));
-                    av[u] = ph[i];
-#pragma unroll
-                    for (int j = 0; j < RB; ++j)
-                        bv[u][j] = b0 + j < nrhs ? psi[(long)(b0 + j) * fs + i] : c64{0.0, 0.0};
+            for (int j = 0; j < RB; ++j)
+                if (b0 + j < nrhs) {
+                    const c64 b = psi[(long)(b0 + j) * fs + i];
+                    re[j] += a.re * b.re + a.im * b.im;
+                    im[j] += a.re * b.im - a.im * b.re;
                 }
-#pragma unroll
-                for (int u = 0; u < RU; ++u)
-                    if (e0 + u * kBT < ne) {
-#pragma unroll
-                        for (int j = 0; j < RB; ++j)
-                            if (b0 + j < nrhs) {
-                                const c64 a = av[u], b = bv[u][j];
-                                re[j] += a.re * b.re + a.im * b.im;
-                                im[j] += a.re * b.im - a.im * b.re;
-                            }
-                    }
-            }
         }
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
@@ -104,6 +76,66 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
             dst[threadIdx.x & 1] = t;
         }
         __syncthreads();
+    }
+}
+
+// Single field, KG basis fields per workgroup: one workgroup per (block,
+// group of KG consecutive k); each entry of psi is loaded once for the KG
+// products (the block of psi is fetched Ns / KG times instead of Ns).
+template <int KG>
+__global__ __launch_bounds__(kBT) void k_restrict_kg(Geom g, const c64* __restrict__ Phi, int Ns,
+                                                     const c64* __restrict__ psi, c64* __restrict__ w, int ngrp,
+                                                     int grid_padded)
+{
+    __shared__ double part[2 * KG][kBT / 64];
+    const int q = xcd_remap(blockIdx.x, grid_padded);
+    if (q >= g.Nb * ngrp)
+        return;
+    const int blk = q / ngrp, k0 = (q - blk * ngrp) * KG;
+    const long fs = 12 * g.V;
+    const int ne = 12 * g.Vb;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double re[KG], im[KG];
+#pragma unroll
+    for (int j = 0; j < KG; ++j)
+        re[j] = im[j] = 0.0;
+    constexpr int RU = 4;
+    for (int e0 = threadIdx.x; e0 < ne; e0 += RU * kBT) {
+        c64 bv[RU], av[RU][KG];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const long i = block_elem(g, blk, min(e0 + u * kBT, ne - 1));
+            bv[u] = psi[i];
+#pragma unroll
+            for (int j = 0; j < KG; ++j)
+                av[u][j] = Phi[(long)min(k0 + j, Ns - 1) * fs + i];
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (e0 + u * kBT < ne) {
+#pragma unroll
+                for (int j = 0; j < KG; ++j) {
+                    const c64 a = av[u][j], b = bv[u];
+                    re[j] += a.re * b.re + a.im * b.im;
+                    im[j] += a.re * b.im - a.im * b.re;
+                }
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < KG; ++j) {
+        const double x = wave_sum(re[j]), y = wave_sum(im[j]);
+        if (lane == 0) {
+            part[2 * j][wid] = x;
+            part[2 * j + 1][wid] = y;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * KG && k0 + (threadIdx.x >> 1) < Ns) {
+        double t = 0.0;
+        for (int u = 0; u < kBT / 64; ++u)
+            t += part[threadIdx.x][u];
+        double* dst = reinterpret_cast<double*>(w + (long)blk * Ns + k0 + (threadIdx.x >> 1));
+        dst[threadIdx.x & 1] = t;
     }
 }
 
@@ -398,6 +430,86 @@ __global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __res
         if (p < np)
             part[((long)split * g.Nb + blk) * np + p] = acc[q];
     }
+}
+
+// Register-tiled form for Ns <= 20 and nc <= 16: the (k, j) pairs form 16
+// tiles of 5 x 4, one per 16-lane row of the workgroup; the 16 lanes of a
+// row take every 16th staged entry, read 5 + 4 values from LDS per entry for
+// 20 products (the kernel above reads 2 per product), and combine their sums
+// with in-row DPP moves at the end. Same partial-sum layout as above.
+constexpr int kRtK = 5, kRtJ = 4, kRtCE = 64;
+
+__device__ inline double row16_sum(double v)
+{
+    using namespace wave_detail;
+    v += dpp<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp<0x140, 0xF>(v);  // row_mirror
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __restrict__ Phi, int Ns,
+                                                           const c64* __restrict__ Y, int nc, int nsplit, int fmu,
+                                                           int fy, int nface, c64* __restrict__ part)
+{
+    extern __shared__ c64 st[];  // [Ns + nc][kRtCE]
+    __shared__ long eidx[kRtCE];
+    const int blk = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+    const long F = 12 * g.V;
+    const int ne = 12 * nface;
+    const int per = ((ne + nsplit - 1) / nsplit + kRtCE - 1) / kRtCE * kRtCE;
+    const int e_lo = split * per;
+    const int e_hi = e_lo + per < ne ? e_lo + per : ne;
+    const int nr = Ns + nc;
+    const int lane16 = threadIdx.x & 15, tile = threadIdx.x >> 4;
+    const int k0 = (tile >> 2) * kRtK, j0 = (tile & 3) * kRtJ;
+    double acc[kRtK][kRtJ][2];
+#pragma unroll
+    for (int i = 0; i < kRtK; ++i)
+#pragma unroll
+        for (int j = 0; j < kRtJ; ++j)
+            acc[i][j][0] = acc[i][j][1] = 0.0;
+    for (int e0 = e_lo; e0 < e_hi; e0 += kRtCE) {
+        __syncthreads();
+        if (threadIdx.x < kRtCE)
+            eidx[threadIdx.x] = e0 + (int)threadIdx.x < e_hi ? face_elem(g, blk, e0 + threadIdx.x, fmu, fy, nface) : -1;
+        __syncthreads();
+        for (int q = threadIdx.x; q < nr * kRtCE; q += blockDim.x) {
+            const int r = q / kRtCE, e = q % kRtCE;
+            c64 v{0.0, 0.0};
+            const long i = eidx[e];
+            if (i >= 0)
+                v = r < Ns ? Phi[(long)r * F + i] : Y[(long)(r - Ns) * F + i];
+            st[r * kRtCE + e] = v;
+        }
+        __syncthreads();
+        for (int e = lane16; e < kRtCE; e += 16) {
+            c64 a[kRtK], b[kRtJ];
+#pragma unroll
+            for (int i = 0; i < kRtK; ++i)
+                a[i] = k0 + i < Ns ? st[(k0 + i) * kRtCE + e] : c64{0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < kRtJ; ++j)
+                b[j] = j0 + j < nc ? st[(Ns + j0 + j) * kRtCE + e] : c64{0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < kRtK; ++i)
+#pragma unroll
+                for (int j = 0; j < kRtJ; ++j) {
+                    acc[i][j][0] += a[i].re * b[j].re + a[i].im * b[j].im;
+                    acc[i][j][1] += a[i].re * b[j].im - a[i].im * b[j].re;
+                }
+        }
+    }
+    const int np = Ns * nc;
+#pragma unroll
+    for (int i = 0; i < kRtK; ++i)
+#pragma unroll
+        for (int j = 0; j < kRtJ; ++j) {
+            const double re = row16_sum(acc[i][j][0]), im = row16_sum(acc[i][j][1]);
+            if (lane16 == 0 && k0 + i < Ns && j0 + j < nc)
+                part[((long)split * g.Nb + blk) * np + (k0 + i) * nc + j0 + j] = c64{re, im};
+        }
 }
 
 // A[blk][d][k][l0 + j] = sum over splits of part (fixed order)
@@ -750,8 +862,12 @@ __global__ void k_c64_to_c32(const c64* a, c32* b, long n)
 void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
 {
     const int gp = pad_grid((long)g.Nb * Ns);
-    if (nrhs == 1)
-        hipLaunchKernelGGL(k_restrict<1>, dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
+    if (nrhs == 1) {
+        constexpr int KG = 4;
+        const int ngrp = (Ns + KG - 1) / KG;
+        const int gk = pad_grid((long)g.Nb * ngrp);
+        hipLaunchKernelGGL(k_restrict_kg<KG>, dim3(gk), dim3(kBT), 0, s, g, Phi, Ns, psi, w, ngrp, gk);
+    }
     else
         hipLaunchKernelGGL(k_restrict<kRB>, dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
 }
@@ -796,10 +912,16 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
         nsplit = 1;
     if ((long)nsplit * g.Nb * Ns * nc > part_cap)
         fail(DFL_EINVAL, "little-operator assembly: scratch too small for the column chunk");
-    static std::once_flag attr;
-    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_columns), (int)(sizeof(c64) * (64 + 64) * (kCE + 1)));
-    hipLaunchKernelGGL(k_little_columns, dim3(g.Nb * nsplit), dim3(256), lds, s, g, Phi, Ns, Y, nc, nsplit, fmu, fy,
-                       nface, part);
+    if (Ns <= 4 * kRtK && nc <= 4 * kRtJ) {
+        hipLaunchKernelGGL(k_little_columns_rt, dim3(g.Nb * nsplit), dim3(256), sizeof(c64) * (Ns + nc) * kRtCE, s, g,
+                           Phi, Ns, Y, nc, nsplit, fmu, fy, nface, part);
+    } else {
+        static std::once_flag attr;
+        set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_columns),
+                         (int)(sizeof(c64) * (64 + 64) * (kCE + 1)));
+        hipLaunchKernelGGL(k_little_columns, dim3(g.Nb * nsplit), dim3(256), lds, s, g, Phi, Ns, Y, nc, nsplit, fmu,
+                           fy, nface, part);
+    }
     const long n = (long)g.Nb * Ns * nc;
     hipLaunchKernelGGL(k_little_columns_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, part, Ns, nc,
                        nsplit, l0, d, A);

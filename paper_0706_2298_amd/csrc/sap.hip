@@ -220,10 +220,10 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
     }
 }
 
-// FP32 sweep with the site's eight links in registers (two rows each, 96
-// VGPRs; the third row is rebuilt on use). They are loaded once, during the
-// residual, so the MR steps read only LDS. A block of at most 256 sites runs
-// one wave per SIMD, which leaves the whole register file to that wave.
+// FP32 sweep for several fields with the site's eight links kept for the MR
+// steps: the first two rows in registers (96 VGPRs), the third row, formed
+// once during the residual, in LDS (24 planes x block). The MR steps then read
+// only LDS, and two blocks of up to 256 sites share a CU (2 x 72 KB of LDS).
 template <typename L> struct Link2 {
     c32 e[6];
 };
@@ -259,11 +259,23 @@ template <typename L> __device__ inline su3<float> expand(const Link2<L>& l)
     return u;
 }
 
-// W: wavefronts per SIMD the register budget must allow (1: one block per CU,
-// no spills; 2: two blocks per CU at a few spilled registers, the faster
-// choice once the blocks of all fields outnumber the CUs)
-template <typename L, int W>
-__global__ __launch_bounds__(256, W) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
+// the link from its two register rows and its third row in LDS (entry b at l3[b * stride])
+template <typename L> __device__ inline su3<float> expand_lds(const Link2<L>& l, const c32* l3, int stride)
+{
+    su3<float> u;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            u.m[a][b] = l.e[a * 3 + b];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        u.m[2][b] = l3[b * stride];
+    return u;
+}
+
+template <typename L>
+__global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
                                                c32* __restrict__ psi, float diag, int nmr, int colour, int nrhs,
                                                int init, c64* __restrict__ out64)
 {
@@ -274,6 +286,7 @@ __global__ __launch_bounds__(256, W) void k_sap_rl(Geom g, SapGeom sg, L U, cons
         out64 += (long)(blockIdx.x % nrhs) * 12 * g.V;
     extern __shared__ char smem_raw[];
     c32* lr = reinterpret_cast<c32*>(smem_raw);
+    c32* l3 = lr + 12 * sg.Vsb;  // third link rows: entry (3 h + b) * Vsb + site
     __shared__ double red[3][8];
 
     const int t = threadIdx.x;
@@ -325,13 +338,17 @@ __global__ __launch_bounds__(256, W) void k_sap_rl(Geom g, SapGeom sg, L U, cons
             const int step = (h & 1) ? -1 : +1;
             long tn = site_step(g, s, n, y, mu, step);
             lk[h] = load_link2(U, mu, step > 0 ? s : tn);
+            const su3<float> u = expand(lk[h]);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                l3[(3 * h + b) * sg.Vsb + t] = u.m[2][b];
             const bool inside = step > 0 ? yl[mu] + 1 < sg.sb[mu] : yl[mu] > 0;
             if (init == 0 || (init == 1 && !inside)) {
                 spinor<float> p = load_spinor(psi, g.V, tn);
                 if (step > 0)
-                    hop_fwd_rt(mu, expand(lk[h]), p, acc);
+                    hop_fwd_rt(mu, u, p, acc);
                 else
-                    hop_bwd_rt(mu, expand(lk[h]), p, acc);
+                    hop_bwd_rt(mu, u, p, acc);
             }
             if (h & 1)
                 asm volatile("" ::: "memory");  // two hops' loads in flight at a time
@@ -372,10 +389,11 @@ __global__ __launch_bounds__(256, W) void k_sap_rl(Geom g, SapGeom sg, L U, cons
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
                             p.s[al].c[a] = lr[(3 * al + a) * sg.Vsb + tn];
+                    const su3<float> u = expand_lds(lk[h], l3 + 3 * h * sg.Vsb + t, sg.Vsb);
                     if (step > 0)
-                        hop_fwd_rt(mu, expand(lk[h]), p, acc);
+                        hop_fwd_rt(mu, u, p, acc);
                     else
-                        hop_bwd_rt(mu, expand(lk[h]), p, acc);
+                        hop_bwd_rt(mu, u, p, acc);
                 }
                 if (h & 1)
                     asm volatile("" ::: "memory");
@@ -721,12 +739,11 @@ void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, 
         return;
     }
     int threads = ((sg.Vsb + 63) / 64) * 64;
-    if (nrhs > 1)
-        hipLaunchKernelGGL((k_sap_rl<L, 2>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
-                           4.0f + m0, nmr, colour, nrhs, init, out64);
-    else
-        hipLaunchKernelGGL((k_sap_rl<L, 1>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
-                           4.0f + m0, nmr, colour, nrhs, init, out64);
+    size_t lds_rl = (size_t)36 * sg.Vsb * sizeof(c32);
+    static std::once_flag attr;  // one per link type
+    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap_rl<L>), 80 * 1024);
+    hipLaunchKernelGGL((k_sap_rl<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds_rl, s, g, sg, U, rho, psi,
+                       4.0f + m0, nmr, colour, nrhs, init, out64);
 }
 
 template <typename T, typename L>
