@@ -438,6 +438,7 @@ __global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __res
 // 20 products (the kernel above reads 2 per product), and combine their sums
 // with in-row DPP moves at the end. Same partial-sum layout as above.
 constexpr int kRtK = 5, kRtJ = 4, kRtCE = 64;
+constexpr int kRtLd = (4 * kRtK + 4 * kRtJ + 3) / 4;  // staged rows per thread (Ns + nc <= 36 rows / 4 waves)
 
 __device__ inline double row16_sum(double v)
 {
@@ -454,7 +455,6 @@ __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __
                                                            int fy, int nface, c64* __restrict__ part)
 {
     extern __shared__ c64 st[];  // [Ns + nc][kRtCE]
-    __shared__ long eidx[kRtCE];
     const int blk = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
     const long F = 12 * g.V;
     const int ne = 12 * nface;
@@ -462,6 +462,7 @@ __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __
     const int e_lo = split * per;
     const int e_hi = e_lo + per < ne ? e_lo + per : ne;
     const int nr = Ns + nc;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int lane16 = threadIdx.x & 15, tile = threadIdx.x >> 4;
     const int k0 = (tile >> 2) * kRtK, j0 = (tile & 3) * kRtJ;
     double acc[kRtK][kRtJ][2];
@@ -470,20 +471,33 @@ __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __
 #pragma unroll
         for (int j = 0; j < kRtJ; ++j)
             acc[i][j][0] = acc[i][j][1] = 0.0;
+    // staging: entry e0 + lane of rows wid, wid + 4, ... (kRtCE = 64 entries,
+    // 256 threads), all loads of a stage issued together, the next stage's
+    // during the current stage's products
+    c64 v[kRtLd];
+    auto load = [&](int e0) {
+        const long i = e0 + lane < e_hi ? face_elem(g, blk, e0 + lane, fmu, fy, nface) : -1;
+#pragma unroll
+        for (int m = 0; m < kRtLd; ++m) {
+            const int r = wid + 4 * m;
+            v[m] = c64{0.0, 0.0};
+            if (i >= 0 && r < nr)
+                v[m] = r < Ns ? Phi[(long)r * F + i] : Y[(long)(r - Ns) * F + i];
+        }
+    };
+    if (e_lo < e_hi)
+        load(e_lo);
     for (int e0 = e_lo; e0 < e_hi; e0 += kRtCE) {
         __syncthreads();
-        if (threadIdx.x < kRtCE)
-            eidx[threadIdx.x] = e0 + (int)threadIdx.x < e_hi ? face_elem(g, blk, e0 + threadIdx.x, fmu, fy, nface) : -1;
-        __syncthreads();
-        for (int q = threadIdx.x; q < nr * kRtCE; q += blockDim.x) {
-            const int r = q / kRtCE, e = q % kRtCE;
-            c64 v{0.0, 0.0};
-            const long i = eidx[e];
-            if (i >= 0)
-                v = r < Ns ? Phi[(long)r * F + i] : Y[(long)(r - Ns) * F + i];
-            st[r * kRtCE + e] = v;
+#pragma unroll
+        for (int m = 0; m < kRtLd; ++m) {
+            const int r = wid + 4 * m;
+            if (r < nr)
+                st[r * kRtCE + lane] = v[m];
         }
         __syncthreads();
+        if (e0 + kRtCE < e_hi)
+            load(e0 + kRtCE);
         for (int e = lane16; e < kRtCE; e += 16) {
             c64 a[kRtK], b[kRtJ];
 #pragma unroll
