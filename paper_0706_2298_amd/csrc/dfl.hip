@@ -215,14 +215,28 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
         }
         // norm of the restricted input field (for the rank test)
         n0 = block_sum2(make_double2(n0, 0.0), sh).x;
-        for (int k = 0; k < l; ++k) {
+        // the next earlier field's entries are loaded before this projection's reduction
+        c64 un[E];
+        auto load = [&](int k) {
             const c64* fk = F + (long)k * fs;
-            c64 u[E];
-            double2 d = make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < E; ++j) {
                 const int e = threadIdx.x + j * kBT;
-                u[j] = e < ne ? fk[block_elem(g, blk, e)] : c64{0.0, 0.0};
+                un[j] = e < ne ? fk[block_elem(g, blk, e)] : c64{0.0, 0.0};
+            }
+        };
+        if (l > 0)
+            load(0);
+        for (int k = 0; k < l; ++k) {
+            c64 u[E];
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+                u[j] = un[j];
+            if (k + 1 < l)
+                load(k + 1);
+            double2 d = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
                 d.x += u[j].re * v[j].re + u[j].im * v[j].im;
                 d.y += u[j].re * v[j].im - u[j].im * v[j].re;
             }
@@ -877,7 +891,7 @@ void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c6
 {
     const int gp = pad_grid((long)g.Nb * Ns);
     if (nrhs == 1) {
-        constexpr int KG = 4;
+        constexpr int KG = 4;  // measured: five fields per workgroup are no faster
         const int ngrp = (Ns + KG - 1) / KG;
         const int gk = pad_grid((long)g.Nb * ngrp);
         hipLaunchKernelGGL(k_restrict_kg<KG>, dim3(gk), dim3(kBT), 0, s, g, Phi, Ns, psi, w, ngrp, gk);

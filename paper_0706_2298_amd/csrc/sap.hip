@@ -373,7 +373,8 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
         __syncthreads();
         spinor<float> q;
         zero(q);
-        double qr_re = 0.0, qr_im = 0.0, qq = 0.0;
+        // the lane's products summed in FP32, the block sums in FP64
+        float fr_re = 0.0f, fr_im = 0.0f, fqq = 0.0f;
         if (active) {
             spinor<float> acc;
             zero(acc);
@@ -403,16 +404,16 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
             for (int al = 0; al < 4; ++al)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    double qa = (double)q.s[al].c[a].re, qb = (double)q.s[al].c[a].im;
-                    double ra = (double)r.s[al].c[a].re, rb = (double)r.s[al].c[a].im;
-                    qr_re += qa * ra + qb * rb;
-                    qr_im += qa * rb - qb * ra;
-                    qq += qa * qa + qb * qb;
+                    const float qa = q.s[al].c[a].re, qb = q.s[al].c[a].im;
+                    const float ra = r.s[al].c[a].re, rb = r.s[al].c[a].im;
+                    fr_re += qa * ra + qb * rb;
+                    fr_im += qa * rb - qb * ra;
+                    fqq += qa * qa + qb * qb;
                 }
         }
-        qr_re = wave_sum(qr_re);
-        qr_im = wave_sum(qr_im);
-        qq = wave_sum(qq);
+        const double qr_re = wave_sum((double)fr_re);
+        const double qr_im = wave_sum((double)fr_im);
+        const double qq = wave_sum((double)fqq);
         if (lane == 0) {
             red[0][wid] = qr_re;
             red[1][wid] = qr_im;
@@ -660,7 +661,8 @@ __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, co
             }
         }
         c32 q[6];
-        double qr_re = 0.0, qr_im = 0.0, qq = 0.0;
+        // the lane's products summed in FP32, the block sums in FP64
+        float fr_re = 0.0f, fr_im = 0.0f, fqq = 0.0f;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             const int al = i / 3, a = i % 3;
@@ -668,15 +670,15 @@ __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, co
             c32 hi{pair_sum(acc.s[al + 2].c[a].re), pair_sum(acc.s[al + 2].c[a].im)};
             c32 ao = hb ? hi : lo;
             q[i] = c32{diag * r[i].re - 0.5f * ao.re, diag * r[i].im - 0.5f * ao.im};
-            double qa = (double)q[i].re, qb = (double)q[i].im;
-            double ra = (double)r[i].re, rb = (double)r[i].im;
-            qr_re += qa * ra + qb * rb;
-            qr_im += qa * rb - qb * ra;
-            qq += qa * qa + qb * qb;
+            const float qa = q[i].re, qb = q[i].im;
+            const float ra = r[i].re, rb = r[i].im;
+            fr_re += qa * ra + qb * rb;
+            fr_im += qa * rb - qb * ra;
+            fqq += qa * qa + qb * qb;
         }
-        qr_re = wave_sum(qr_re);
-        qr_im = wave_sum(qr_im);
-        qq = wave_sum(qq);
+        const double qr_re = wave_sum((double)fr_re);
+        const double qr_im = wave_sum((double)fr_im);
+        const double qq = wave_sum((double)fqq);
         if (lane == 0) {
             red[0][wid] = qr_re;
             red[1][wid] = qr_im;
