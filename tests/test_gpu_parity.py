@@ -544,3 +544,23 @@ def test_block_gram_schmidt_block_sizes(dims, b):
     S.setup(S.pack(init))
     assert rel(S.unpack(S.basis()), oracle.block_gram_schmidt(init, dims, b)) < 1e-12
     S.close()
+
+
+@pytest.mark.parametrize("Ns,nkv", [(24, 8), (20, 16), (12, 5)])
+def test_little_operator_column_kernels(Ns, nkv):
+    # eq. (A.1) assembled over chunks of min(Ns, nkv) basis fields: Ns <= 20
+    # with chunks <= 16 runs the register-tiled block products (chunks 16 + 4
+    # and 5 + 5 + 2 here), Ns = 24 the one-pair-per-thread kernel; without
+    # inverse-iteration steps the basis is the block Gram-Schmidt of the start
+    # fields, so the oracle needs no solver
+    say(f"little operator Ns={Ns} chunk={min(Ns, nkv)}")
+    dims, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    U = latgen.make_links(dims, 0.4, 81)
+    init = latgen.make_init_fields(dims, Ns, 82)
+    S = Solver(dims, dfl_block=b, sap_block=b, Ns=Ns, nkv=nkv, n_inviter=0, m0=-0.2, m0_setup=-0.2)
+    S.set_gauge(U)
+    S.setup(S.pack(init))
+    Phi = oracle.block_gram_schmidt(init, dims, b)
+    assert rel(S.unpack(S.basis()), Phi) < 1e-12
+    assert rel(S.little_operator(), oracle.little_operator(U, Phi, -0.2, dims, b)) < 1e-10
+    S.close()
