@@ -3,14 +3,18 @@
 // full operator, runs nmr minimal-residual steps on the block operator
 // D_Lambda (Dirichlet walls) and adds the block solution to psi.
 //
-// Mapping: one workgroup per Schwarz block, one thread per site (blockDim =
-// |block| rounded up to a wavefront; spare lanes only join the reductions).
-// The residual reads the neighbour spinors across the block faces directly
-// from global memory; those sites belong to blocks of the other colour, which
-// no workgroup of this launch writes, so there is no race. Inside the MR loop
-// the current residue r is exchanged through LDS (12 planes x |block|), the
-// links come through L1/L2, and the two block reductions per step use
-// wavefront shuffles plus one LDS pass.
+// Mapping: one workgroup per Schwarz block. The generic kernel (k_sap, any
+// block size, FP64 or FP32) and the several-field kernel (k_sap_rl, blocks of
+// at most 256 sites) run one thread per site (blockDim = |block| rounded up to
+// a wavefront; spare lanes only join the reductions); the one-field kernel
+// (k_sap_pair) runs two lanes per site. The residual reads the neighbour
+// spinors across the block faces directly from global memory; those sites
+// belong to blocks of the other colour, which no workgroup of this launch
+// writes, so there is no race. Inside the MR loop the current residue r is
+// exchanged through LDS (12 planes x |block|), and the two block reductions
+// per step use DPP wavefront sums plus one LDS pass. k_sap reads the links
+// through L1/L2 at every MR step; k_sap_rl and k_sap_pair keep them from the
+// residual on.
 //
 // init (first cycle, where psi starts at zero): 2 = psi is zero everywhere
 // (colour 0: the residue is rho, no hops, no reads of psi), 1 = psi is zero on
