@@ -805,6 +805,8 @@ __global__ void k_eo_hop(Geom g, const c64* __restrict__ Mt, int Ns, const c64* 
         const int nbr = block_nbr(g, blk, d);
         const c64* M = Mt + ((long)blk * 9 + d) * Ns * Ns + k;
         const c64* x = in + (long)nbr * Ns;
+        // ten terms' loads issued together
+#pragma unroll 10
         for (int l = 0; l < Ns; ++l) {
             const c64 p = M[(long)l * Ns], q = x[l];
             re += p.re * q.re - p.im * q.im;
