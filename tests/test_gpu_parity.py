@@ -130,10 +130,12 @@ def test_sap_f64(geom):
     S.close()
 
 
-@pytest.mark.parametrize("link_prec,tol", [(F32, 1e-4), (BF16, 3e-2)])
-def test_sap_f32(link_prec, tol):
-    dims, b, sb = GEOMS[0]
-    say(f"sap f32 link_prec={link_prec}")
+@pytest.mark.parametrize("gi,link_prec,tol", [(0, F32, 1e-4), (0, BF16, 3e-2), (1, F32, 1e-4), (3, F32, 1e-4),
+                                               (1, BF16, 3e-2)])
+def test_sap_f32(gi, link_prec, tol):
+    # one field: the lane-pair kernel on 256-, 60- and 4-site blocks
+    dims, b, sb = GEOMS[gi]
+    say(f"sap f32 {dims} sap_block={sb} link_prec={link_prec}")
     m0 = -0.2
     U = latgen.make_links(dims, 0.4, 41)
     rho = latgen.make_source(dims, 42)
@@ -335,16 +337,18 @@ def test_solve_reproducible_and_history(c1):
     S.close()
 
 
-@pytest.mark.parametrize("sap_prec,tol", [(F64, 1e-12), (F32, 1e-4)])
-def test_sap_multi_rhs(sap_prec, tol):
-    # one Schwarz launch per sweep for three fields equals the per-field oracle
-    dims, b, sb = GEOMS[0]
-    say(f"sap multi-rhs prec={sap_prec}")
+@pytest.mark.parametrize("gi,sap_prec,link_prec,tol", [(0, F64, F64, 1e-12), (0, F32, F32, 1e-4), (1, F32, F32, 1e-4),
+                                                        (3, F32, F32, 1e-4), (1, F32, BF16, 3e-2)])
+def test_sap_multi_rhs(gi, sap_prec, link_prec, tol):
+    # one Schwarz launch per sweep for three fields equals the per-field oracle;
+    # in FP32 the several-field kernel (third link rows in LDS) on 256-, 60-
+    # and 4-site blocks
+    dims, b, sb = GEOMS[gi]
+    say(f"sap multi-rhs {dims} sap_block={sb} prec={sap_prec} links={link_prec}")
     m0 = -0.2
     U = latgen.make_links(dims, 0.4, 71)
     rho = latgen.random_field(dims, 72, n=3)
-    S = make_solver(dims, b, sb, m0=m0, ncy=2, nmr=3, nrhs_max=3, sap_prec=sap_prec,
-                    link_prec=F64 if sap_prec == F64 else F32)
+    S = make_solver(dims, b, sb, m0=m0, ncy=2, nmr=3, nrhs_max=3, sap_prec=sap_prec, link_prec=link_prec)
     S.set_gauge(U)
     got = S.unpack(S.sap(S.pack(rho)))
     for r in range(3):
