@@ -41,7 +41,7 @@ using cd = std::complex<double>;
 constexpr int S_A1 = 0;      // 64 complex: first Gram-Schmidt pass
 constexpr int S_A2 = 128;    // 64 complex: second pass
 constexpr int S_B = 256;     // ||chi_k||^2
-constexpr int S_C = 258;     // (chi_k, rho)
+constexpr int S_C = 258;     // (chi_k, rho) with chi_k before its normalisation
 constexpr int S_R = 260;     // ||rho||^2
 constexpr int S_DOWN = 264;  // doubles read back per step
 constexpr int S_ALPHA = 512; // 64 complex: GCR solution coefficients
@@ -484,13 +484,12 @@ std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter,
                     launch_multiaxpy_b<double>(v.chi, ks, k, c->dscal + S_A2, S_TOTAL, -1.0, ck, n, nb, n, n,
                                                c->dact2, c->stream);
                 }
-                launch_norm2_b<double>(ck, n, nb, n, c->red, c->dscal + S_B, S_TOTAL, mask, c->stream);
-                launch_scale_invsqrt_b<double>(ck, n, nb, n, c->dscal + S_B, S_TOTAL, mask, c->stream);
-                launch_multidot_b<double>(ck, 0, 1, v.r, n, nb, n, n, c->red, c->dscal + S_C, S_TOTAL, mask,
-                                          c->stream);
-                launch_multiaxpy_b<double>(ck, 0, 1, c->dscal + S_C, S_TOTAL, -1.0, v.r, n, nb, n, n, mask,
-                                           c->stream);
-                launch_norm2_b<double>(v.r, n, nb, n, c->red, c->dscal + S_R, S_TOTAL, mask, c->stream);
+                // ||chi||^2 and (chi, r) in one pass (S_B, S_C), then chi /= ||chi||,
+                // r -= ((chi, r) / ||chi||^2) chi and ||r||^2 (S_R) in another
+                static_assert(S_C == S_B + 2, "the norm and the product are reduced together");
+                launch_norm_dot_b(ck, v.r, n, nb, n, c->red, c->dscal + S_B, S_TOTAL, mask, c->stream);
+                launch_scale_update_b(ck, v.r, n, nb, n, c->dscal + S_B, S_TOTAL, c->red, c->dscal + S_R, S_TOTAL,
+                                      mask, c->stream);
             });
             download_b(c, S_DOWN, nb);
             bool changed = false;
@@ -503,7 +502,8 @@ std::vector<GcrResult> gcr_run(dfl_ctx* c, long n, int nb, int nkv, int maxiter,
                     ab[(size_t)j * nkv + k] = cd(h[S_A1 + 2 * j] + h[S_A2 + 2 * j], h[S_A1 + 2 * j + 1] + h[S_A2 + 2 * j + 1]);
                 const double bk = std::sqrt(h[S_B]);
                 bb[(size_t)b * nkv + k] = bk;
-                cc[(size_t)b * nkv + k] = cd(h[S_C], h[S_C + 1]);
+                // (chi_k, r) for the unit chi_k: S_C holds the product before the scaling
+                cc[(size_t)b * nkv + k] = bk > 0.0 ? cd(h[S_C], h[S_C + 1]) / bk : cd(0.0, 0.0);
                 rn[b] = std::sqrt(h[S_R]);
                 if (!(bk > 0.0) || !std::isfinite(bk))
                     fail(bk == 0.0 ? DFL_ESINGULAR : DFL_ENONFINITE, "GCR breakdown: zero or non-finite Krylov image");

@@ -188,6 +188,73 @@ __global__ __launch_bounds__(256) void k_scale_invsqrt(cpx<T>* __restrict__ x, l
     }
 }
 
+// The closing steps of a GCR step on source b (vectors at offset b * xb):
+// partials of ||x||^2 (slot 0, imaginary part 0) and of (x, y) (slot 1) in
+// one pass over x and y.
+__global__ __launch_bounds__(kRedThreads) void k_norm_dot_partial(const c64* __restrict__ x, const c64* __restrict__ y,
+                                                                  long n, long xb, const int* __restrict__ active,
+                                                                  double* __restrict__ partial)
+{
+    const int b = blockIdx.y;
+    if (active && !active[b])
+        return;
+    x += b * xb;
+    y += b * xb;
+    partial += (long)b * kMaxDot * kRedBlocks * 2;
+    __shared__ double sh[16];
+    double nn = 0.0, dr = 0.0, di = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const c64 a = x[i], c = y[i];
+        nn += a.re * a.re + a.im * a.im;
+        dr += a.re * c.re + a.im * c.im;
+        di += a.re * c.im - a.im * c.re;
+    }
+    nn = block_sum(nn, sh);
+    dr = block_sum(dr, sh);
+    di = block_sum(di, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = nn;
+        partial[2 * blockIdx.x + 1] = 0.0;
+        partial[(kRedBlocks + blockIdx.x) * 2] = dr;
+        partial[(kRedBlocks + blockIdx.x) * 2 + 1] = di;
+    }
+}
+
+// With sc = {||x||^2, 0, Re (x, y), Im (x, y)} of source b (at b * cstride):
+// y <- y - ((x, y) / ||x||^2) x, x <- x / ||x||, and partials of the new
+// ||y||^2 (slot 0), in one pass.
+__global__ __launch_bounds__(kRedThreads) void k_scale_update_partial(c64* __restrict__ x, c64* __restrict__ y, long n,
+                                                                      long xb, const double* __restrict__ sc,
+                                                                      int cstride, const int* __restrict__ active,
+                                                                      double* __restrict__ partial)
+{
+    const int b = blockIdx.y;
+    if (active && !active[b])
+        return;
+    x += b * xb;
+    y += b * xb;
+    sc += (long)b * cstride;
+    partial += (long)b * kMaxDot * kRedBlocks * 2;
+    __shared__ double sh[16];
+    const double q = sc[0];
+    const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    const double cr = q > 0.0 ? sc[2] / q : 0.0, ci = q > 0.0 ? sc[3] / q : 0.0;
+    double t = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const c64 a = x[i], c = y[i];
+        const double yr = c.re - (cr * a.re - ci * a.im);
+        const double yi = c.im - (cr * a.im + ci * a.re);
+        y[i] = c64{yr, yi};
+        x[i] = c64{a.re * f, a.im * f};
+        t += yr * yr + yi * yi;
+    }
+    t = block_sum(t, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = t;
+        partial[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
 __global__ void k_add_scalars(const double* a, const double* b, double* dst, int m)
 {
     for (int i = threadIdx.x; i < 2 * m; i += blockDim.x)
@@ -267,6 +334,25 @@ void launch_multiaxpy_b(const cpx<T>* X, long stride, int m, const double* coef,
         return;
     hipLaunchKernelGGL(k_multiaxpy<T>, dim3(stream_grid(n), nb), dim3(256), 0, s, X, stride, m, coef, cstride, sign,
                        y, n, xb, yb, active);
+}
+
+void launch_norm_dot_b(const c64* x, const c64* y, long n, int nb, long xb, double* red, double* dst, int dstride,
+                       const int* active, hipStream_t s)
+{
+    if (nb <= 0)
+        return;
+    hipLaunchKernelGGL(k_norm_dot_partial, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, s, x, y, n, xb, active, red);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1, nb), dim3(256), 0, s, red, 2, dst, dstride, active);
+}
+
+void launch_scale_update_b(c64* x, c64* y, long n, int nb, long xb, const double* sc, int cstride, double* red,
+                           double* dst, int dstride, const int* active, hipStream_t s)
+{
+    if (nb <= 0)
+        return;
+    hipLaunchKernelGGL(k_scale_update_partial, dim3(kRedBlocks, nb), dim3(kRedThreads), 0, s, x, y, n, xb, sc, cstride,
+                       active, red);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1, nb), dim3(256), 0, s, red, 1, dst, dstride, active);
 }
 
 template <typename T>

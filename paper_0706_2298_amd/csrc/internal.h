@@ -245,6 +245,13 @@ void launch_norm2_b(const cpx<T>* x, long n, int nb, long xb, double* red, doubl
 template <typename T>
 void launch_multiaxpy_b(const cpx<T>* X, long stride, int m, const double* coef, int cstride, double sign, cpx<T>* y,
                         long n, int nb, long xb, long yb, const int* active, hipStream_t s);
+// GCR closing steps (FP64): dst[b*dstride + 0..3] = {||x_b||^2, 0, (x_b, y_b)};
+// then y_b -= ((x_b, y_b) / ||x_b||^2) x_b, x_b /= ||x_b|| with those sums (sc),
+// and dst[b*dstride + 0..1] = {||y_b||^2, 0}. red: partial-sum scratch.
+void launch_norm_dot_b(const c64* x, const c64* y, long n, int nb, long xb, double* red, double* dst, int dstride,
+                       const int* active, hipStream_t s);
+void launch_scale_update_b(c64* x, c64* y, long n, int nb, long xb, const double* sc, int cstride, double* red,
+                           double* dst, int dstride, const int* active, hipStream_t s);
 template <typename T>
 void launch_scale_invsqrt_b(cpx<T>* x, long n, int nb, long xb, const double* nrm2, int cstride, const int* active,
                             hipStream_t s);
