@@ -614,8 +614,14 @@ void read_little_stats(dfl_ctx* c, int out[3])
     out[2] = h[2] & 1;
     if (c->prof_on)
         c->prof_little_iters += h[0];
-    if (h[2] & 4)
+    if (h[2] & 4) {
+        // a timed-out barrier leaves its arrival count behind: clear it so
+        // that later solves start from a clean barrier
+        HIPCHECK(hipMemsetAsync(c->lbar_count, 0, sizeof(unsigned) * 64, c->stream));
+        HIPCHECK(hipMemsetAsync(c->lstats, 0, sizeof(int) * 4, c->stream));
+        sync(c);
         fail(DFL_EHIP, "little solver: grid barrier timed out");
+    }
 }
 
 // out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term) for nb fields; out may not alias in
@@ -989,6 +995,12 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->lx32 = alloc_dev<c32>(c, R * N);
         c->lgrid = little_gcr_grid(c->g, p->little_grid);
         c->lgrid_multi = little_gcr_multi_grid(c->g, p->little_grid);
+        // every workgroup of the grid-barrier kernels must be resident at
+        // once (graph replays launch them as ordinary kernels)
+        c->lgrid = std::min(c->lgrid, little_gcr_resident_limit(false));
+        c->lgrid_multi = std::min(c->lgrid_multi, little_gcr_resident_limit(true));
+        if (c->lgrid < 1 || c->lgrid_multi < 1)
+            fail(DFL_EHIP, "the little GCR kernels cannot be resident on this device");
         size_t part = little_gcr_partial_doubles(c->lgrid);
         if (R > 1) {
             size_t nfin = 0, nac = 0;
@@ -1104,6 +1116,8 @@ int dfl_set_gauge(dfl_ctx* c, const double* U)
     API_BEGIN
     need_ctx(c);
     need_ptr(U, "U");
+    sync(c);
+    drop_graphs(c);  // captured steps hold the subspace state they were recorded with
     c->have_gauge = false;
     c->have_subspace = false;
     HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
@@ -1205,6 +1219,10 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
         fail(DFL_EINVAL, "n_init must equal Ns");
     const long F = c->field_elems;
     const int Ns = c->p.Ns;
+    // captured GCR steps keep the even-odd and global-deflation state (and
+    // the buffers of Q and Z) of the subspace they were recorded with
+    sync(c);
+    drop_graphs(c);
     c->have_subspace = false;
     HIPCHECK(hipMemcpyAsync(c->Phi, init, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));

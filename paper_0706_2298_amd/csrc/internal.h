@@ -332,6 +332,10 @@ size_t little_gcr_partial_doubles(int grid_size);
 // workgroups of the batched little GCR: twice the requested single-source
 // grid (0: Nb / 4), at most one per compute unit and the block count
 int little_gcr_multi_grid(const Geom& g, int requested);
+// workgroups of the (batched) little GCR kernels that can be resident at once
+// on the current device (occupancy x compute units); the grid barrier needs
+// the whole grid resident, also when the kernel is a graph node
+int little_gcr_resident_limit(bool multi);
 // whether the even-odd solver's per-workgroup block lists fit for this grid
 bool little_eo_fits(const Geom& g, int grid);
 // v = A^{-1} w by GCR to ||w - A v|| <= tol ||w|| in one cooperative launch

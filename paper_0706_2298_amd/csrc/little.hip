@@ -1408,6 +1408,29 @@ int little_gcr_multi_grid(const Geom& g, int requested)
     return G;
 }
 
+int little_gcr_resident_limit(bool multi)
+{
+    int dev = 0, cus = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = 1 << 30;
+    auto occ = [&](const void* fn, int threads) {
+        int n = 0;
+        HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0));
+        per_cu = n < per_cu ? n : per_cu;
+    };
+    if (multi) {
+        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<double>), LT);
+        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<float>), LT);
+    } else {
+        occ(reinterpret_cast<const void*>(&k_little_gcr<double, true>), LT1);
+        occ(reinterpret_cast<const void*>(&k_little_gcr<double, false>), LT1);
+        occ(reinterpret_cast<const void*>(&k_little_gcr<float, true>), LT1);
+        occ(reinterpret_cast<const void*>(&k_little_gcr<float, false>), LT1);
+    }
+    return per_cu * cus;
+}
+
 bool little_eo_fits(const Geom& g, int grid)
 {
     return (g.Nb + grid - 1) / grid <= kMaxOwned;

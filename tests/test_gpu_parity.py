@@ -131,9 +131,10 @@ def test_sap_f64(geom):
 
 
 @pytest.mark.parametrize("gi,link_prec,tol", [(0, F32, 1e-4), (0, BF16, 3e-2), (1, F32, 1e-4), (3, F32, 1e-4),
-                                               (1, BF16, 3e-2)])
+                                               (1, BF16, 3e-2), (2, F32, 1e-4), (2, BF16, 3e-2)])
 def test_sap_f32(gi, link_prec, tol):
-    # one field: the lane-pair kernel on 256-, 60- and 4-site blocks
+    # one field: the lane-pair kernel on 256-, 60- and 4-site blocks; the
+    # generic kernel on the 512-site 8 x 4^3 blocks of section 6.3
     dims, b, sb = GEOMS[gi]
     say(f"sap f32 {dims} sap_block={sb} link_prec={link_prec}")
     m0 = -0.2
@@ -296,8 +297,8 @@ def test_edge_cases(c1):
     del torch
 
 
-def test_little_solve_fp32_and_reproducible(c1):
-    say("little solve reproducibility / FP32 inner")
+def test_little_solve_reproducible(c1):
+    say("little solve reproducibility")
     torch = pytest.importorskip("torch")
     S = _c1_solver(c1)
     dims, b = c1["dims"], (4, 4, 4, 4)
@@ -338,11 +339,12 @@ def test_solve_reproducible_and_history(c1):
 
 
 @pytest.mark.parametrize("gi,sap_prec,link_prec,tol", [(0, F64, F64, 1e-12), (0, F32, F32, 1e-4), (1, F32, F32, 1e-4),
-                                                        (3, F32, F32, 1e-4), (1, F32, BF16, 3e-2)])
+                                                        (3, F32, F32, 1e-4), (1, F32, BF16, 3e-2),
+                                                        (2, F32, F32, 1e-4), (2, F32, BF16, 3e-2)])
 def test_sap_multi_rhs(gi, sap_prec, link_prec, tol):
     # one Schwarz launch per sweep for three fields equals the per-field oracle;
     # in FP32 the several-field kernel (third link rows in LDS) on 256-, 60-
-    # and 4-site blocks
+    # and 4-site blocks, the generic kernel on 512-site (8 x 4^3) blocks
     dims, b, sb = GEOMS[gi]
     say(f"sap multi-rhs {dims} sap_block={sb} prec={sap_prec} links={link_prec}")
     m0 = -0.2
@@ -567,4 +569,30 @@ def test_little_operator_column_kernels(Ns, nkv):
     Phi = oracle.block_gram_schmidt(init, dims, b)
     assert rel(S.unpack(S.basis()), Phi) < 1e-12
     assert rel(S.little_operator(), oracle.little_operator(U, Phi, -0.2, dims, b)) < 1e-10
+    S.close()
+
+
+def test_graph_solve_after_new_setup(c1):
+    # graphs on, FP64 little solves (even-odd with global-mode deflation):
+    # setup, solve, a second setup on another gauge field, solve. The captured
+    # steps of the first subspace must not be replayed against the second, so
+    # each graph solve equals the direct solve on the same subspace bit for bit
+    say("graph solve after a new setup")
+    dims = c1["dims"]
+    U2 = latgen.make_links(dims, 0.45, 1011)
+    S = _c1_solver(c1, tol=1e-10, nkv=6)
+    ed = S.pack(c1["eta"])
+    S.use_graphs(True)
+    for U in (c1["U"], U2, c1["U"]):
+        S.set_gauge(U)
+        S.setup(S.pack(c1["init"]))
+        got, info = S.solve(ed)
+        got = S.unpack(got)
+        S.use_graphs(False)
+        ref, info_ref = S.solve(ed)
+        assert info.status == 0 and info.n_gcr == info_ref.n_gcr
+        assert np.array_equal(got, S.unpack(ref))
+        r = c1["eta"] - oracle.dirac(U, got[0], c1["m0"], dims)
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(c1["eta"])
+        S.use_graphs(True)
     S.close()

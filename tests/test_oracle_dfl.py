@@ -293,3 +293,35 @@ def test_inverse_iteration_lowers_rayleigh_bound():
         f = oracle.inverse_iteration(U, init, m0, dims, b, 5, 4, n)
         ratios.append(max(np.linalg.norm(oracle.dirac(U, g, m0, dims)) / np.linalg.norm(g) for g in f))
     assert ratios[0] > ratios[1] > ratios[2]
+
+
+def test_inverse_iteration_is_normalised_inverse_power():
+    # eq. (5.1) with the Schwarz procedure replaced by its limit: at a heavy
+    # setup mass, with many cycles and MR steps, M_sap is D^-1 to rounding, so
+    # n steps of the relaxed inverse iteration give D^-n psi_0 / ||D^-n psi_0||
+    # (psi_0 normalised first, each step normalised); the dense D comes from
+    # the oracle's stencil at the setup mass, not at another mass
+    dims, b = (4, 4, 2, 2), (2, 2, 1, 1)
+    V = int(np.prod(dims))
+    m_setup = 1.0
+    U = latgen.make_links(dims, 0.4, 1101)
+    init = latgen.make_init_fields(dims, 2, 1102)
+    D = dense_from(lambda f: oracle.dirac(U, f, m_setup, dims), V)
+    D_other = dense_from(lambda f: oracle.dirac(U, f, 0.3, dims), V)
+    for n in (1, 2):
+        got = oracle.inverse_iteration(U, 7.0 * init, m_setup, dims, b, 30, 30, n)
+        for l in range(2):
+            assert abs(np.linalg.norm(got[l]) - 1.0) < 1e-13
+            want = init[l].reshape(-1)
+            other = want.copy()
+            for _ in range(n):
+                want = np.linalg.solve(D, want)
+                other = np.linalg.solve(D_other, other)
+            want /= np.linalg.norm(want)
+            other /= np.linalg.norm(other)
+            assert np.abs(got[l].reshape(-1) - want).max() < 1e-10
+            assert np.abs(got[l].reshape(-1) - other).max() > 1e-3
+    # zero steps: the normalised start fields
+    got0 = oracle.inverse_iteration(U, 3.0 * init, m_setup, dims, b, 30, 30, 0)
+    for l in range(2):
+        assert np.abs(got0[l] - init[l] / np.linalg.norm(init[l])).max() < 1e-15
