@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "lib", "num_threads", "gamma", "dirac", "dirac_blockdiag", "hop_cross", "dirac_sites",
     "mr_block", "sap", "block_counts", "to_blocks", "from_blocks", "block_colours",
-    "block_neighbour", "block_gram_schmidt", "restrict", "prolong", "proj_P",
+    "block_neighbour", "clover_site", "block_gram_schmidt", "restrict", "prolong", "proj_P",
     "little_operator", "little_apply", "little_dense", "little_solve", "little_gcr",
     "Deflation", "gcr", "inverse_iteration", "setup", "solve", "deficit", "dot", "norm",
     "LITTLE_DIRS",
@@ -40,16 +40,18 @@ def lib():
             build_oracle()
         L = ctypes.CDLL(path)
         vp = ctypes.c_void_p
-        L.orc_dirac.argtypes = [vp, ctypes.c_double, vp, vp, vp]
-        L.orc_dirac_blockdiag.argtypes = [vp, vp, ctypes.c_double, vp, vp, vp]
-        L.orc_hop_cross.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int]
-        L.orc_dirac_sites.argtypes = [vp, ctypes.c_double, vp, vp, vp, ctypes.c_long, vp]
-        L.orc_mr_block.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.c_long, vp, ctypes.c_int, vp]
-        L.orc_sap.argtypes = [vp, vp, ctypes.c_double, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+        d, i = ctypes.c_double, ctypes.c_int
+        L.orc_dirac.argtypes = [vp, d, d, i, vp, vp, vp]
+        L.orc_dirac_blockdiag.argtypes = [vp, vp, d, d, i, vp, vp, vp]
+        L.orc_hop_cross.argtypes = [vp, vp, i, vp, vp, vp, i, i]
+        L.orc_dirac_sites.argtypes = [vp, d, d, i, vp, vp, vp, ctypes.c_long, vp]
+        L.orc_mr_block.argtypes = [vp, vp, d, d, i, vp, ctypes.c_long, vp, i, vp]
+        L.orc_sap.argtypes = [vp, vp, d, d, i, vp, vp, i, i, vp]
+        L.orc_clover_site.argtypes = [vp, vp, d, ctypes.c_long, vp]
         L.orc_gamma.argtypes = [vp]
         L.orc_num_threads.restype = ctypes.c_int
         for f in (L.orc_dirac, L.orc_dirac_blockdiag, L.orc_hop_cross, L.orc_dirac_sites,
-                  L.orc_mr_block, L.orc_sap, L.orc_gamma):
+                  L.orc_mr_block, L.orc_sap, L.orc_gamma, L.orc_clover_site):
             f.restype = None
         _LIB = L
     return _LIB
@@ -101,39 +103,46 @@ def gamma() -> np.ndarray:
 
 # --------------------------------------------------------------- operators
 
-def dirac(U, psi, m0: float, dims) -> np.ndarray:
-    """D psi, eq. (3.9)'s operator (plain Wilson, periodic)."""
+def _bc0(antiperiodic: bool) -> int:
+    return -1 if antiperiodic else 1
+
+
+def dirac(U, psi, m0: float, dims, *, csw: float = 0.0, antiperiodic: bool = False) -> np.ndarray:
+    """D psi, eq. (3.9)'s operator: Wilson plus the clover term csw (i/4) sigma.F
+    (section 2.1's O(a) improvement; csw = 0 is plain Wilson); periodic in
+    space, periodic or antiperiodic in time (direction 0)."""
     d, V = _dims(dims)
     U = _cgauge(U, V)
     psi = _cfield(psi, V)
     out = np.empty_like(psi)
-    lib().orc_dirac(_ptr(np.array(d, dtype=np.int32)), float(m0), _ptr(U), _ptr(psi), _ptr(out))
+    lib().orc_dirac(_ptr(np.array(d, dtype=np.int32)), float(m0), float(csw), _bc0(antiperiodic), _ptr(U),
+                    _ptr(psi), _ptr(out))
     return out
 
 
-def dirac_blockdiag(U, psi, m0: float, dims, b) -> np.ndarray:
+def dirac_blockdiag(U, psi, m0: float, dims, b, *, csw: float = 0.0, antiperiodic: bool = False) -> np.ndarray:
     """(direct sum of D_Lambda) psi: D with every hop across a block face dropped."""
     d, V = _dims(dims)
     U = _cgauge(U, V)
     psi = _cfield(psi, V)
     out = np.empty_like(psi)
     lib().orc_dirac_blockdiag(_ptr(np.array(d, dtype=np.int32)), _ptr(np.array(b, dtype=np.int32)),
-                              float(m0), _ptr(U), _ptr(psi), _ptr(out))
+                              float(m0), float(csw), _bc0(antiperiodic), _ptr(U), _ptr(psi), _ptr(out))
     return out
 
 
-def hop_cross(U, psi, dims, b, mu: int, direction: int) -> np.ndarray:
+def hop_cross(U, psi, dims, b, mu: int, direction: int, *, antiperiodic: bool = False) -> np.ndarray:
     """The hop terms of D in direction mu (+1 forward, -1 backward) that cross a block face."""
     d, V = _dims(dims)
     U = _cgauge(U, V)
     psi = _cfield(psi, V)
     out = np.empty_like(psi)
     lib().orc_hop_cross(_ptr(np.array(d, dtype=np.int32)), _ptr(np.array(b, dtype=np.int32)),
-                        _ptr(U), _ptr(psi), _ptr(out), int(mu), int(direction))
+                        _bc0(antiperiodic), _ptr(U), _ptr(psi), _ptr(out), int(mu), int(direction))
     return out
 
 
-def dirac_sites(U, psi, m0: float, dims, sites) -> np.ndarray:
+def dirac_sites(U, psi, m0: float, dims, sites, *, csw: float = 0.0, antiperiodic: bool = False) -> np.ndarray:
     """(D psi)(x) for the listed sites only, shape (len(sites), 12)."""
     d, V = _dims(dims)
     U = _cgauge(U, V)
@@ -142,12 +151,23 @@ def dirac_sites(U, psi, m0: float, dims, sites) -> np.ndarray:
     if s.size and (s.min() < 0 or s.max() >= V):
         raise ValueError("site index out of range")
     out = np.empty((s.size, 12), dtype=np.complex128)
-    lib().orc_dirac_sites(_ptr(np.array(d, dtype=np.int32)), float(m0), _ptr(U), _ptr(psi),
-                          _ptr(s), s.size, _ptr(out))
+    lib().orc_dirac_sites(_ptr(np.array(d, dtype=np.int32)), float(m0), float(csw), _bc0(antiperiodic), _ptr(U),
+                          _ptr(psi), _ptr(s), s.size, _ptr(out))
     return out
 
 
-def mr_block(U, rhs, m0: float, dims, b, blk: int, nmr: int) -> np.ndarray:
+def clover_site(U, dims, csw: float, site: int) -> np.ndarray:
+    """The clover matrix csw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x) of one site, (12, 12)
+    in the spin-colour index 3 alpha + a."""
+    d, V = _dims(dims)
+    U = _cgauge(U, V)
+    out = np.empty((12, 12), dtype=np.complex128)
+    lib().orc_clover_site(_ptr(np.array(d, dtype=np.int32)), _ptr(U), float(csw), int(site), _ptr(out))
+    return out
+
+
+def mr_block(U, rhs, m0: float, dims, b, blk: int, nmr: int, *, csw: float = 0.0,
+             antiperiodic: bool = False) -> np.ndarray:
     """nmr minimal-residual steps for D_Lambda x = rhs|_Lambda on block blk.
 
     Returns a full-size field that holds x on the block and zero elsewhere.
@@ -157,11 +177,11 @@ def mr_block(U, rhs, m0: float, dims, b, blk: int, nmr: int) -> np.ndarray:
     rhs = _cfield(rhs, V)
     x = np.zeros_like(rhs)
     lib().orc_mr_block(_ptr(np.array(d, dtype=np.int32)), _ptr(np.array(b, dtype=np.int32)),
-                       float(m0), _ptr(U), int(blk), _ptr(rhs), int(nmr), _ptr(x))
+                       float(m0), float(csw), _bc0(antiperiodic), _ptr(U), int(blk), _ptr(rhs), int(nmr), _ptr(x))
     return x
 
 
-def sap(U, rho, m0: float, dims, b, ncy: int, nmr: int) -> np.ndarray:
+def sap(U, rho, m0: float, dims, b, ncy: int, nmr: int, *, csw: float = 0.0, antiperiodic: bool = False) -> np.ndarray:
     """psi = M_sap rho: the Schwarz alternating procedure (preconditioner of eq. (6.2)).
 
     Reading (the paper defers the definition to its ref. on Schwarz
@@ -176,7 +196,7 @@ def sap(U, rho, m0: float, dims, b, ncy: int, nmr: int) -> np.ndarray:
     rho = _cfield(rho, V)
     psi = np.empty_like(rho)
     lib().orc_sap(_ptr(np.array(d, dtype=np.int32)), _ptr(np.array(b, dtype=np.int32)),
-                  float(m0), _ptr(U), _ptr(rho), int(ncy), int(nmr), _ptr(psi))
+                  float(m0), float(csw), _bc0(antiperiodic), _ptr(U), _ptr(rho), int(ncy), int(nmr), _ptr(psi))
     return psi
 
 
@@ -291,7 +311,7 @@ def deficit(Phi, psi, dims, b) -> float:
 LITTLE_DIRS = [(None, 0)] + [(mu, s) for mu in range(4) for s in (+1, -1)]
 
 
-def little_operator(U, Phi, m0: float, dims, b) -> np.ndarray:
+def little_operator(U, Phi, m0: float, dims, b, *, csw: float = 0.0, antiperiodic: bool = False) -> np.ndarray:
     """Block matrices of the little Dirac operator, eq. (A.1): shape (Nb, 9, Ns, Ns).
 
     A[Lambda, 0][k, l] = (phi^Lambda_k, D phi^Lambda_l) = (phi^Lambda_k, D_Lambda phi^Lambda_l);
@@ -308,11 +328,11 @@ def little_operator(U, Phi, m0: float, dims, b) -> np.ndarray:
     A = np.zeros((Nb, 9, Ns, Ns), dtype=np.complex128)
     for l in range(Ns):
         Fl = Phi[l]
-        y = to_blocks(dirac_blockdiag(U, Fl, m0, dims, b), dims, b)
+        y = to_blocks(dirac_blockdiag(U, Fl, m0, dims, b, csw=csw, antiperiodic=antiperiodic), dims, b)
         A[:, 0, :, l] = np.einsum("kbi,bi->bk", Pb.conj(), y)
         for d in range(1, 9):
             mu, s = LITTLE_DIRS[d]
-            y = to_blocks(hop_cross(U, Fl, dims, b, mu, s), dims, b)
+            y = to_blocks(hop_cross(U, Fl, dims, b, mu, s, antiperiodic=antiperiodic), dims, b)
             A[:, d, :, l] = np.einsum("kbi,bi->bk", Pb.conj(), y)
     return A
 
@@ -372,8 +392,10 @@ class Deflation:
     to ``little_tol``.
     """
 
-    def __init__(self, U, Phi, A, m0, dims, b, little_tol: float = 1e-13):
+    def __init__(self, U, Phi, A, m0, dims, b, little_tol: float = 1e-13, *, csw: float = 0.0,
+                 antiperiodic: bool = False):
         self.U, self.Phi, self.A = U, np.asarray(Phi), A
+        self.csw, self.antiperiodic = float(csw), bool(antiperiodic)
         self.m0, self.dims, self.b = float(m0), list(dims), list(b)
         self.little_tol = little_tol
         Nb, _, Ns, _ = A.shape
@@ -389,7 +411,7 @@ class Deflation:
         return little_gcr(self.A, w, self.dims, self.b, tol=self.little_tol)[0]
 
     def D(self, psi):
-        return dirac(self.U, psi, self.m0, self.dims)
+        return dirac(self.U, psi, self.m0, self.dims, csw=self.csw, antiperiodic=self.antiperiodic)
 
     def coarse(self, y):
         return prolong(self.Phi, self.little_inverse(restrict(self.Phi, y, self.dims, self.b)),
@@ -472,7 +494,8 @@ def gcr(apply_op, eta, precond=None, project=None, tol: float = 1e-10, nkv: int 
         rho = Pj(eta - apply_op(psi)).reshape(shape)
 
 
-def inverse_iteration(U, init, m0: float, dims, sap_block, ncy: int, nmr: int, n_iter: int):
+def inverse_iteration(U, init, m0: float, dims, sap_block, ncy: int, nmr: int, n_iter: int, *, csw: float = 0.0,
+                      antiperiodic: bool = False):
     """Relaxed inverse iteration of eq. (5.1): psi_l <- M_sap psi_l, normalised.
 
     The start fields are normalised first; each step applies one Schwarz
@@ -482,21 +505,23 @@ def inverse_iteration(U, init, m0: float, dims, sap_block, ncy: int, nmr: int, n
     fields = [np.asarray(f, dtype=np.complex128).reshape(-1, 12) for f in init]
     fields = [f / norm(f) for f in fields]
     for _ in range(int(n_iter)):
-        fields = [sap(U, f, m0, dims, sap_block, ncy, nmr) for f in fields]
+        fields = [sap(U, f, m0, dims, sap_block, ncy, nmr, csw=csw, antiperiodic=antiperiodic) for f in fields]
         fields = [f / norm(f) for f in fields]
     return np.stack(fields)
 
 
-def setup(U, init, m0: float, dims, sap_block, dfl_block, ncy: int, nmr: int, n_iter: int):
+def setup(U, init, m0: float, dims, sap_block, dfl_block, ncy: int, nmr: int, n_iter: int, *, csw: float = 0.0,
+          antiperiodic: bool = False):
     """Subspace generation (section 5.3) + eq. (4.2) + eq. (A.1): returns (Phi, A)."""
-    fields = inverse_iteration(U, init, m0, dims, sap_block, ncy, nmr, n_iter)
+    fields = inverse_iteration(U, init, m0, dims, sap_block, ncy, nmr, n_iter, csw=csw, antiperiodic=antiperiodic)
     Phi = block_gram_schmidt(fields, dims, dfl_block)
-    A = little_operator(U, Phi, m0, dims, dfl_block)
+    A = little_operator(U, Phi, m0, dims, dfl_block, csw=csw, antiperiodic=antiperiodic)
     return Phi, A
 
 
 def solve(U, eta, m0: float, dims, *, sap_block=None, ncy=5, nmr=4, dfl=None,
-          tol: float = 1e-10, nkv: int = 16, maxiter: int = 1000, history=None):
+          tol: float = 1e-10, nkv: int = 16, maxiter: int = 1000, history=None, csw: float = 0.0,
+          antiperiodic: bool = False):
     """Solve D psi = eta (eq. (3.9)) to ||eta - D psi|| <= tol ||eta||.
 
     dfl = Deflation or None; sap_block = SAP block shape or None (no
@@ -505,10 +530,10 @@ def solve(U, eta, m0: float, dims, *, sap_block=None, ncy=5, nmr=4, dfl=None,
     i.e. P_R applied to the GCR iterate plus the coarse part.
     Returns (psi, iterations, converged).
     """
-    op = lambda x: dirac(U, x, m0, dims)
+    op = lambda x: dirac(U, x, m0, dims, csw=csw, antiperiodic=antiperiodic)
     M = None
     if sap_block is not None:
-        M = lambda r: sap(U, r, m0, dims, sap_block, ncy, nmr)
+        M = lambda r: sap(U, r, m0, dims, sap_block, ncy, nmr, csw=csw, antiperiodic=antiperiodic)
     Pj = dfl.PL if dfl is not None else None
     psi, it, ok = gcr(op, eta, precond=M, project=Pj, tol=tol, nkv=nkv, maxiter=maxiter,
                       history=history)
