@@ -1,32 +1,41 @@
 """Benchmark of the deflated SAP-GCR solver on one MI355X.
 
-Workload (one "step"): the 16^4 lattice at two gauge roughnesses (eps 0.4 and
-0.6, seeds 2001/2002). Per gauge field one subspace setup (Ns = 20 fields,
-3 inverse-iteration steps, 4^4 blocks) is reused for the three masses
-m0 = -0.2, -0.3, -0.35, each solved to ||eta - D psi|| <= 1e-10 ||eta|| with
-FP64 flexible GCR (16 Krylov vectors), FP32 Schwarz block solves (4^4 blocks,
-5 cycles, 4 MR steps, FP32 two-row links) and FP64 little solves (1e-6 inside
-cycles, 1e-12 at restarts). value = solves per second over the whole step,
-setups included; all inputs are resident in HBM before the timed region.
+Headline workload (one "step"): the 64 x 32^3 lattice (2,097,152 sites) with
+the link field U = exp(i 0.5 H) of seed 5100 and a Gaussian source (seed
+5200), bare mass m0 = -0.56 (near the critical mass of this gauge
+roughness). A step is one subspace setup (Ns = 24 random start fields, seed
+5300, 3 inverse-iteration steps, 4^4 deflation blocks, block Gram-Schmidt and
+little-operator assembly) followed by one solve to ||eta - D psi|| <= 1e-10
+||eta|| with FP64 flexible GCR (16 Krylov vectors), FP32 Schwarz block solves
+(4^4 blocks, 5 cycles, 4 MR steps, FP32 two-row links), FP32 little solves
+inside GCR cycles and FP64 ones (1e-12) at restarts and for the final
+correction. value = steps per second (one setup plus one solve each); the
+setup and solve times are reported apart. All inputs are resident in HBM
+before the timed region; the true residual of every timed solve is recomputed
+in FP64.
 
 Also reported (outside the timed region):
-* the dominant kernel's roofline: one extra step with the library's event
-  timers on; algorithmic flops or bytes per launch over the measured launch
-  duration;
-* dirac_apply GFLOP/s and algorithmic GB/s on 64 x 32^3 (FP64, FP32 and
-  BF16 two-row links), a working set well above the 256 MB MALL;
-* undeflated SAP+GCR and plain FP64 GCR on the same fields;
-* 32 x 16^3 in mixed precision (BF16 two-row links, FP32 Schwarz and inner
-  little solves, Schwarz block shape picked by the autotuner) with the error
-  of each result against FP64 references;
+* the dominant kernel's roofline: one extra step with the library's
+  kernel-class event timers on; algorithmic flops or bytes per launch over
+  the measured launch duration, with the rocprofv3 counter traffic when the
+  committed counter summary matches the kernel source;
+* dirac_apply GFLOP/s and GB/s on 64 x 32^3 (FP64, FP32 and BF16 two-row
+  links) and with 12 sources on 48 x 24^3;
+* on the headline field: undeflated SAP+GCR, plain FP64 GCR, the deflated
+  solver with FP64 inner little solves, with the oblique global-mode deflation
+  of the little system (appendix A.3 as written) and with a bootstrapped setup
+  (section 5.3);
+* 32 x 16^3 in mixed precision (BF16 two-row links; Schwarz block shape from
+  the autotuner) against the all-FP64 deflated solver and plain FP64 GCR, with
+  errors against FP64 references;
+* 12 point sources on 48 x 24^3 and 6 on 32 x 16^3 (Ns = 24) as one batch per
+  lattice with graph replay, against one-by-one solves and plain FP64 GCR;
 * the learned start fields: the network trained on 16^4 fields (eps 0.5),
-  then on held-out 64 x 32^3 fields the GCR iterations and times of the
-  deflated solve with network start fields against random ones at equal
-  inverse-iteration steps;
-* 12 point sources on 48 x 24^3 and 6 on 32 x 16^3 (Ns = 24) solved as one
-  batch per lattice with graph replay, against one-by-one solves, and the
-  12-source dirac_apply rate;
-* the FP64 CPU oracle timed on a bounded sample of the same workload.
+  then on 5 held-out 64 x 32^3 fields the setup and solve times against
+  random start fields and plain FP64 GCR;
+* the 16^4 workload (two gauge fields x three masses) against undeflated
+  solvers;
+* the FP64 CPU oracle timed on a bounded sample, scaled to the headline step.
 """
 from __future__ import annotations
 
@@ -36,6 +45,7 @@ import json
 import os
 import platform
 import re
+import subprocess
 import sys
 import time
 
@@ -51,14 +61,19 @@ FLOPS_PER_SITE = 1368            # Wilson stencil per site per right-hand side (
 # links are stored as two rows of the SU(3) matrix in every precision (the third row is rebuilt)
 BYTES_PER_SITE = {"f64_tworow": 768, "f32_tworow": 384, "bf16_tworow": 288}
 
-DIMS = (16, 16, 16, 16)
+# headline workload
+DIMS = (64, 32, 32, 32)
 BLOCK = (4, 4, 4, 4)
-FIELDS = [(0.4, 2001), (0.6, 2002)]
-MASSES = [-0.2, -0.3, -0.35]
-NS, NCY, NMR, NKV, NINV = 20, 5, 4, 16, 3
+EPS, SEED, M0 = 0.5, 5100, -0.56
+NS, NCY, NMR, NKV, NINV = 24, 5, 4, 16, 3
 TOL = 1e-10
 V = int(np.prod(DIMS))
 NB = V // int(np.prod(BLOCK))
+
+# the 16^4 workload
+C2_DIMS = (16, 16, 16, 16)
+C2_FIELDS = [(0.4, 2001), (0.6, 2002)]
+C2_MASSES = [-0.2, -0.3, -0.35]
 
 
 def sap_flops_per_site(nmr):
@@ -71,36 +86,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_inputs():
-    import latgen
-    fields = []
-    for eps, seed in FIELDS:
-        U = latgen.make_links(DIMS, eps, seed)
-        eta = latgen.make_source(DIMS, seed + 100)
-        init = latgen.make_init_fields(DIMS, NS, seed + 200)
-        fields.append(dict(eps=eps, seed=seed, U=U, eta=eta, init=init))
-    return fields
-
-
-def solver_params(**kw):
+def params(**kw):
     from paper_0706_2298_amd import F32, F64
     p = dict(dfl_block=BLOCK, sap_block=BLOCK, Ns=NS, ncy=NCY, nmr=NMR, nkv=NKV, n_inviter=NINV,
-             m0=MASSES[0], m0_setup=min(MASSES), tol=TOL, sap_prec=F32, link_prec=F32, little_prec=F64,
+             m0=M0, m0_setup=M0, tol=TOL, sap_prec=F32, link_prec=F32, little_prec=F32,
              little_tol_in=1e-6, little_tol_out=1e-12, maxiter=4000)
     p.update(kw)
     return p
 
 
-def run_step(ctxs, stats=None):
-    for c in ctxs:
-        c["S"].setup(c["init"])
-        for m in MASSES:
-            c["S"].set_mass(m)
-            _, info = c["S"].solve(c["eta"])
-            if stats is not None:
-                stats.append(dict(eps=c["eps"], m0=m, **info.as_dict()))
-            if info.status != 0:
-                raise RuntimeError(f"solve failed: {info.as_dict()}")
+def timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
 
 
 def time_events(torch, fn, reps):
@@ -116,23 +116,32 @@ def time_events(torch, fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def profiled_step(ctxs):
-    """One more step with the library's kernel-class timers on."""
+def headline_inputs():
+    import latgen
+    U = latgen.make_links(DIMS, EPS, SEED)
+    eta = latgen.make_source(DIMS, SEED + 100)
+    init = latgen.make_init_fields(DIMS, NS, SEED + 200)
+    return U, eta, init
+
+
+def step(torch, S, eta, init):
+    """One setup + one solve; (t_setup, t_solve, info)."""
+    _, t_setup = timed(torch, lambda: S.setup(init))
+    (_, info), t_solve = timed(torch, lambda: S.solve(eta))
+    if info.status != 0:
+        raise RuntimeError(f"solve failed: {info.as_dict()}")
+    return t_setup, t_solve, info
+
+
+def profiled(S, fn):
+    """Run fn with the library's kernel-class timers on; {class: (s, launches)} and little iterations."""
     from paper_0706_2298_amd import binding
-    for c in ctxs:
-        binding.dfl_profile_read(c["S"].ctx)          # reset
-        binding.dfl_profile_enable(c["S"].ctx, True)
-    run_step(ctxs)
-    tot = {k: [0.0, 0] for k in binding.PROF_CLASSES}
-    little_it = 0
-    for c in ctxs:
-        p = binding.dfl_profile_read(c["S"].ctx)
-        binding.dfl_profile_enable(c["S"].ctx, False)
-        for k in binding.PROF_CLASSES:
-            tot[k][0] += p[k][0]
-            tot[k][1] += p[k][1]
-        little_it += p["little_iterations"]
-    return tot, little_it
+    binding.dfl_profile_read(S.ctx)
+    binding.dfl_profile_enable(S.ctx, True)
+    fn()
+    p = binding.dfl_profile_read(S.ctx)
+    binding.dfl_profile_enable(S.ctx, False)
+    return p
 
 
 def source_digest(*names):
@@ -143,42 +152,52 @@ def source_digest(*names):
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = {"sap": ("sap.hip", "hop.h", "common.h"), "little": ("little.hip", "common.h"),
-                  "dirac": ("dirac.hip", "hop.h", "common.h"), "project": ("dfl.hip", "common.h")}
+KERNEL_SOURCES = {"sap": ("sap.hip", "hop.h", "common.h"), "setup_sap": ("sap.hip", "hop.h", "common.h"),
+                  "little": ("little.hip", "common.h"), "dirac": ("dirac.hip", "hop.h", "common.h"),
+                  "project": ("dfl.hip", "common.h")}
 
 
-def counter_traffic(cls, launches_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of this
-    kernel, if it was taken on the current source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{cls}_counters.md")
+def counter_traffic(name, digest_of):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    profiles/<name>_counters.md, if it was taken on the current source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{name}_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"source digest:\s*([0-9a-f]+)", txt)
     b = re.search(r"hbm bytes per launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != source_digest(*KERNEL_SOURCES[cls]):
+    if not m or not b or m.group(1) != source_digest(*KERNEL_SOURCES[digest_of]):
         return None
     return float(b.group(1))
 
 
-def roofline(prof, little_it):
-    """Roofline object for the class that took the most time in the profiled step."""
-    cls = max(("sap", "little", "dirac", "project"), key=lambda k: prof[k][0])
+def roofline(prof):
+    """Roofline object for the kernel class that took the most time in the profiled step
+    (the setup's block Gram-Schmidt and assembly class is a mix of kernels and is left out)."""
+    cls = max(("sap", "setup_sap", "little", "dirac", "project"), key=lambda k: prof[k][0])
     sec, n = prof[cls]
     dur = sec / max(n, 1)
-    if cls == "sap":
-        flops = sap_flops_per_site(NMR) * (V // 2)          # one colour sweep visits half the sites
+    half = V // 2   # one colour sweep visits half the sites
+    if cls in ("sap", "setup_sap"):
+        nf = 1 if cls == "sap" else NS
+        flops = sap_flops_per_site(NMR) * half * nf
         ach = flops / dur / 1e12
-        r = dict(kernel="k_sap_pair<Links32> (Schwarz colour sweep of one field, FP32, 4^4 blocks, two lanes per site)", bound="alu", achieved=ach,
-                 peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / FP32_VECTOR_PEAK_TFLOPS,
-                 per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {V // 2} sites")
+        kern = ("k_sap_pair<Links32> (Schwarz colour sweep of one field, FP32, 4^4 blocks, two lanes per site)"
+                if cls == "sap" else
+                f"k_sap_rl<Links32> (Schwarz colour sweep of the {NS} inverse-iteration fields, FP32, 4^4 blocks)")
+        r = dict(kernel=kern, bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                 frac=ach / FP32_VECTOR_PEAK_TFLOPS,
+                 per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {half} sites x {nf} fields")
     elif cls == "little":
-        per_it = 16 * NB * (9 * NS * NS + 4 * NS)
-        byts = per_it * little_it / max(n, 1)
+        it = prof["little_iterations"] / max(n, 1)
+        # even-odd step: the eight neighbour blocks of D^-1 A over all blocks
+        # (two half-applies) in FP32, plus four vectors
+        per_it = NB * (8 * NS * NS * 8 + 4 * NS * 8)
+        byts = per_it * it
         ach = byts / dur / 1e9
-        r = dict(kernel="k_little_gcr<double, true> (even-odd little GCR, one launch per little solve)", bound="hbm", achieved=ach,
-                 peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                 per_launch=f"{byts:.4g} B = {little_it / max(n, 1):.1f} iterations x {per_it} B (A + 4 vectors)")
+        r = dict(kernel="k_little_gcr<float, true> (even-odd little GCR, FP32, one launch per little solve)",
+                 bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                 per_launch=f"{byts:.4g} B = {it:.1f} iterations x {per_it} B (D^-1 A blocks + 4 vectors, FP32)")
     elif cls == "dirac":
         byts = BYTES_PER_SITE["f64_tworow"] * V
         ach = byts / dur / 1e9
@@ -187,81 +206,92 @@ def roofline(prof, little_it):
     else:
         byts = 192 * (NS + 1) * V
         ach = byts / dur / 1e9
-        r = dict(kernel="k_restrict / k_prolong", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                 frac=ach / HBM_PEAK_GBS, per_launch=f"{byts} B = (Ns + 1) fields x 192 B/site")
+        r = dict(kernel="k_restrict_kg / k_prolong (FP64)", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
+                 unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                 per_launch=f"{byts} B = (Ns + 1) fields x 192 B/site x {V}")
+    r["class"] = cls
     r["avg_launch_us"] = dur * 1e6
     r["launches_per_step"] = n
-    r["traffic"] = counter_traffic(cls, None)
-    return r, {k: dict(seconds=v[0], launches=v[1]) for k, v in prof.items()}
+    r["traffic"] = counter_traffic(cls, cls)
+    return r
 
 
 def dirac_rates(torch):
-    """dirac_apply on 64 x 32^3: FP64 arithmetic with FP64 two-row links, FP32 with FP32 and BF16 two-row links."""
+    """dirac_apply on 64 x 32^3: FP64 arithmetic with FP64 two-row links, FP32 with FP32 and BF16
+    two-row links (a working set well above the 256 MB MALL), with the counter traffic."""
     import latgen
     from paper_0706_2298_amd import BF16, F32, F64, Solver, binding
-    dims = (64, 32, 32, 32)
-    vol = int(np.prod(dims))
-    U = latgen.make_links(dims, 0.4, 4101)
-    psi = latgen.make_source(dims, 4102)
+    U = latgen.make_links(DIMS, 0.4, 4101)
+    psi = latgen.make_source(DIMS, 4102)
     out = {}
     for name, lp, prec in [("f64_tworow", F64, F64), ("f32_tworow", F32, F32), ("bf16_tworow", BF16, F32)]:
         sp = F64 if lp == F64 else F32
-        S = Solver(dims, Ns=1, nkv=1, little_nkv=1, m0=-0.2, link_prec=lp, sap_prec=sp)
+        S = Solver(DIMS, Ns=1, nkv=1, little_nkv=1, m0=-0.2, link_prec=lp, sap_prec=sp)
         S.set_gauge(U)
         x = S.pack(psi, prec=prec)
         y = S.field(1, prec)
         t = time_events(torch, lambda: binding.dirac_apply(S.ctx, x, y, 1, prec), 40)
-        gbs = BYTES_PER_SITE[name] * vol / t / 1e9
-        out[name] = dict(ms=t * 1e3, gflops=FLOPS_PER_SITE * vol / t / 1e9, gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
+        gbs = BYTES_PER_SITE[name] * V / t / 1e9
+        out[name] = dict(us=t * 1e6, gflops=FLOPS_PER_SITE * V / t / 1e9, gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
         S.close()
         del x, y
     torch.cuda.empty_cache()
-    return dict(lattice=list(dims), bytes_per_site=BYTES_PER_SITE, flops_per_site=FLOPS_PER_SITE, **out)
+    tr = counter_traffic("dirac64", "dirac")
+    if tr is not None:
+        out["f64_tworow"]["counter_bytes_per_launch"] = tr
+        out["f64_tworow"]["counter_gbs"] = tr / (out["f64_tworow"]["us"] * 1e-6) / 1e9
+    return dict(lattice=list(DIMS), bytes_per_site=BYTES_PER_SITE, flops_per_site=FLOPS_PER_SITE, **out)
 
 
-def undeflated(torch, fields):
-    from paper_0706_2298_amd import SOLVER_GCR, SOLVER_SAP_GCR, Solver
-    rows = []
-    for f in fields:
-        for solver, nkv, name in [(SOLVER_SAP_GCR, 32, "sap_gcr"), (SOLVER_GCR, 32, "gcr_f64")]:
-            S = Solver(DIMS, **solver_params(solver=solver, nkv=nkv, Ns=1, maxiter=20000))
-            S.set_gauge(f["U"])
-            eta = S.pack(f["eta"])
-            for m in MASSES:
-                S.set_mass(m)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, info = S.solve(eta)
-                torch.cuda.synchronize()
-                rows.append(dict(solver=name, eps=f["eps"], m0=m, n_gcr=info.n_gcr, status=info.status,
-                                 rel_residual=info.rel_residual, seconds=time.perf_counter() - t0))
-            S.close()
+def comparisons(torch, U, eta, init):
+    """Other solvers and variants on the headline field (time to solution, iterations)."""
+    from paper_0706_2298_amd import F64, SOLVER_GCR, SOLVER_SAP_GCR, Solver
+    rows = {}
+    for name, kw in [("sap_gcr", dict(solver=SOLVER_SAP_GCR, nkv=32, Ns=1, maxiter=20000)),
+                     ("gcr_f64", dict(solver=SOLVER_GCR, nkv=32, Ns=1, maxiter=20000))]:
+        S = Solver(DIMS, **params(**kw))
+        S.set_gauge(U)
+        ed = S.pack(eta)
+        (_, info), t = timed(torch, lambda: S.solve(ed))
+        rows[name] = dict(t_solve=t, n_gcr=info.n_gcr, status=info.status, rel_residual=info.rel_residual)
+        S.close()
+        del ed
+        torch.cuda.empty_cache()
+        log(f"{name}: {info.n_gcr} iterations, {t:.3f} s")
+    for name, kw in [("dfl_little_f64", dict(little_prec=F64)),
+                     ("dfl_oblique_little_deflation", dict(little_gdefl=2)),
+                     ("dfl_bootstrap_1", dict(n_boot=1)),
+                     ("dfl_bootstrap_2_ninv2", dict(n_boot=1, n_inviter=2))]:
+        S = Solver(DIMS, **params(**kw))
+        S.set_gauge(U)
+        ed, fi = S.pack(eta), S.pack(init)
+        step(torch, S, ed, fi)                       # warm
+        ts, tv, info = step(torch, S, ed, fi)
+        rows[name] = dict(t_setup=ts, t_solve=tv, n_gcr=info.n_gcr, n_little=info.n_little,
+                          n_little_solves=info.n_little_solves, rel_residual=info.rel_residual)
+        S.close()
+        del ed, fi
+        torch.cuda.empty_cache()
+        log(f"{name}: setup {ts:.3f} s, {info.n_gcr} iterations, solve {tv:.3f} s")
     return rows
-
-
-def timed(torch, fn):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = fn()
-    torch.cuda.synchronize()
-    return out, time.perf_counter() - t0
 
 
 def mixed_precision_32x16(torch):
     """32 x 16^3, eps 0.4 (seed 3001), m0 = -0.3, Gaussian source (seed 3002):
     BF16 two-row links, FP32 Schwarz and inner little solves, FP64 GCR and
     projector; Schwarz block 4^4 or 8 x 4^3 chosen by the autotuner on
-    setup + solve time. Errors: dirac_apply and one Schwarz application against
-    the FP64 oracle; the solution against an all-FP64 solve to 1e-12 on the
-    GPU, and its true residual recomputed by the oracle's D."""
+    setup + solve time. Time to solution against the all-FP64 deflated solver
+    and plain FP64 GCR on the same field. Errors: dirac_apply and one Schwarz
+    application against the FP64 oracle; the solution against the all-FP64
+    solve to 1e-12, and its true residual recomputed by the oracle's D."""
     import latgen
     import oracle
-    from paper_0706_2298_amd import BF16, F32, F64, Solver, autotune, binding
+    from paper_0706_2298_amd import BF16, F32, F64, SOLVER_GCR, Solver, autotune, binding
     dims, m0 = (32, 16, 16, 16), -0.3
     U = latgen.make_links(dims, 0.4, 3001)
     eta = latgen.make_source(dims, 3002)
-    init = latgen.make_init_fields(dims, NS, 3003)
-    base = solver_params(m0=m0, m0_setup=m0, link_prec=BF16, sap_prec=F32, little_prec=F32)
+    init = latgen.make_init_fields(dims, 20, 3003)
+    base = params(Ns=20, m0=m0, m0_setup=m0, link_prec=BF16, sap_prec=F32, little_prec=F32)
     base.pop("sap_block")
     cands = [dict(sap_block=sb, nmr=NMR, graph=False) for sb in [(4, 4, 4, 4), (8, 4, 4, 4)]]
     tuned = autotune.tune(dims, U, eta[None], init=init, params=base, cands=cands, cache=None, solves_per_setup=1,
@@ -269,50 +299,72 @@ def mixed_precision_32x16(torch):
     S = Solver(dims, sap_block=tuned["sap_block"], **base)
     S.set_gauge(U)
     ed, initd = S.pack(eta), S.pack(init)
+    S.setup(initd)
+    S.solve(ed)
     _, t_setup = timed(torch, lambda: S.setup(initd))
     (psi, info), t_solve = timed(torch, lambda: S.solve(ed))
     psi = S.unpack(psi)[0]
-    # stencil and one Schwarz application in reduced precision against the oracle
     x = S.pack(eta, prec=F32)
     y = S.field(1, F32)
     binding.dirac_apply(S.ctx, x, y, 1, F32)
-    d_err = float(np.linalg.norm(S.unpack(y, prec=F32)[0] - oracle.dirac(U, eta, m0, dims)) /
-                  np.linalg.norm(oracle.dirac(U, eta, m0, dims)))
+    dref = oracle.dirac(U, eta, m0, dims)
+    d_err = float(np.linalg.norm(S.unpack(y, prec=F32)[0] - dref) / np.linalg.norm(dref))
     sap_gpu = S.unpack(S.sap(ed))[0]
     sap_ref = oracle.sap(U, eta, m0, dims, tuple(tuned["sap_block"]), NCY, NMR)
     s_err = float(np.linalg.norm(sap_gpu - sap_ref) / np.linalg.norm(sap_ref))
     S.close()
-    R = Solver(dims, **solver_params(m0=m0, m0_setup=m0, sap_prec=F64, link_prec=F64, little_prec=F64, tol=1e-12,
-                                     sap_block=tuned["sap_block"]))
+    out = dict(lattice=list(dims), m0=m0, autotune=dict(sap_block=list(tuned["sap_block"]), seconds=tuned["seconds"]),
+               mixed=dict(t_setup=t_setup, t_solve=t_solve, n_gcr=info.n_gcr, n_little=info.n_little))
+    # all-FP64 deflated solver on the same field and block shape (to 1e-10 for the
+    # time, to 1e-12 for the reference solution)
+    R = Solver(dims, **params(Ns=20, m0=m0, m0_setup=m0, sap_prec=F64, link_prec=F64, little_prec=F64,
+                              sap_block=tuned["sap_block"]))
+    R.set_gauge(U)
+    ed, initd = R.pack(eta), R.pack(init)
+    R.setup(initd)
+    R.solve(ed)
+    _, t_setup64 = timed(torch, lambda: R.setup(initd))
+    (_, info64), t_solve64 = timed(torch, lambda: R.solve(ed))
+    out["all_f64_dfl"] = dict(t_setup=t_setup64, t_solve=t_solve64, n_gcr=info64.n_gcr)
+    R.close()
+    R = Solver(dims, **params(Ns=20, m0=m0, m0_setup=m0, sap_prec=F64, link_prec=F64, little_prec=F64, tol=1e-12,
+                              sap_block=tuned["sap_block"]))
     R.set_gauge(U)
     R.setup(R.pack(init))
     ref, _ = R.solve(R.pack(eta))
     ref = R.unpack(ref)[0]
     R.close()
+    G = Solver(dims, **params(Ns=1, m0=m0, solver=SOLVER_GCR, nkv=32, maxiter=20000, sap_prec=F64, link_prec=F64))
+    G.set_gauge(U)
+    ed = G.pack(eta)
+    (_, infog), t_gcr = timed(torch, lambda: G.solve(ed))
+    out["gcr_f64"] = dict(t_solve=t_gcr, n_gcr=infog.n_gcr)
+    G.close()
+    del ed
     torch.cuda.empty_cache()
     res = float(np.linalg.norm(eta - oracle.dirac(U, psi, m0, dims)) / np.linalg.norm(eta))
-    return dict(lattice=list(dims), m0=m0, autotune=dict(sap_block=list(tuned["sap_block"]),
-                                                         seconds=tuned["seconds"]),
-                t_setup=t_setup, t_solve=t_solve, n_gcr=info.n_gcr, n_little=info.n_little,
-                rel_residual_oracle_D=res,
-                err_solution_vs_fp64_solve=float(np.linalg.norm(psi - ref) / np.linalg.norm(ref)),
-                err_dirac_bf16_links_vs_oracle=d_err, err_sap_fp32_bf16_vs_oracle=s_err)
+    out.update(rel_residual_oracle_D=res, err_solution_vs_fp64_solve=float(np.linalg.norm(psi - ref) /
+                                                                           np.linalg.norm(ref)),
+               err_dirac_bf16_links_vs_oracle=d_err, err_sap_fp32_bf16_vs_oracle=s_err,
+               speedup_vs_gcr_f64=t_gcr / (t_setup + t_solve))
+    return out
 
 
 def multi_rhs(torch):
     """12 point sources (x = 0, spin-colour 0..11) on 48 x 24^3 (seed 4001) and
     6 (spin-colour 0..5) on 32 x 16^3 (seed 4002), eps 0.4, m0 = -0.3, Ns = 24:
     one batched solve per lattice with graph replay against one-by-one solves
-    on the same subspace; plus dirac_apply on the 12 sources in one launch."""
+    on the same subspace and plain FP64 GCR (batched); plus dirac_apply on the
+    12 sources in one launch."""
     import latgen
-    from paper_0706_2298_amd import F64, Solver, binding
+    from paper_0706_2298_amd import F64, SOLVER_GCR, Solver, binding
     out = {}
     for dims, seed, n in [((48, 24, 24, 24), 4001, 12), ((32, 16, 16, 16), 4002, 6)]:
         key = "x".join(map(str, dims))
         U = latgen.make_links(dims, 0.4, seed)
         src = latgen.point_sources(dims, range(n))
         init = latgen.make_init_fields(dims, 24, seed + 200)
-        S = Solver(dims, **solver_params(Ns=24, m0=-0.3, m0_setup=-0.3, nrhs_max=n))
+        S = Solver(dims, **params(Ns=24, m0=-0.3, m0_setup=-0.3, nrhs_max=n))
         S.set_gauge(U)
         ed = S.pack(src)
         _, t_setup = timed(torch, lambda: S.setup(S.pack(init)))
@@ -324,13 +376,6 @@ def multi_rhs(torch):
         row["max_rel_residual"] = max(i.rel_residual for i in infos)
         S.use_graphs(False)
         _, row["t_batched_direct"] = timed(torch, lambda: S.solve(ed))
-        binding.dfl_profile_read(S.ctx)
-        binding.dfl_profile_enable(S.ctx, True)
-        S.solve(ed)
-        prof = binding.dfl_profile_read(S.ctx)
-        binding.dfl_profile_enable(S.ctx, False)
-        row["kernel_time_batched"] = {k: dict(seconds=prof[k][0], launches=prof[k][1]) for k in binding.PROF_CLASSES}
-        row["little_iterations_batched"] = prof["little_iterations"]
         singles = []
         t_single = 0.0
         for j in range(n):
@@ -345,34 +390,46 @@ def multi_rhs(torch):
             y = S.field(n, F64)
             t = time_events(torch, lambda: binding.dirac_apply(S.ctx, ed, y, n, F64), 10)
             vol = int(np.prod(dims))
-            byts = (2 * 192 * n + 576) * vol  # spinors in and out per source, links once
-            row["dirac_nrhs12"] = dict(ms=t * 1e3, gflops=FLOPS_PER_SITE * vol * n / t / 1e9,
+            byts = (2 * 192 * n + 384) * vol  # spinors in and out per source, two-row links once
+            row["dirac_nrhs12"] = dict(us=t * 1e6, gflops=FLOPS_PER_SITE * vol * n / t / 1e9,
                                        gbs=byts / t / 1e9, frac_hbm=byts / t / 1e9 / HBM_PEAK_GBS,
                                        bytes_per_site_per_rhs=byts / vol / n)
             del y
         S.close()
         del ed
         torch.cuda.empty_cache()
+        G = Solver(dims, **params(Ns=1, m0=-0.3, solver=SOLVER_GCR, nkv=16, maxiter=20000, nrhs_max=n,
+                                  sap_prec=F64, link_prec=F64))
+        G.set_gauge(U)
+        ed = G.pack(src)
+        (_, infg), row["t_gcr_f64_batched"] = timed(torch, lambda: G.solve(ed))
+        row["n_gcr_f64"] = [i.n_gcr for i in infg]
+        G.close()
+        del ed
+        torch.cuda.empty_cache()
+        row["speedup_vs_gcr_f64"] = row["t_gcr_f64_batched"] / (t_setup + row["t_batched_graph"])
         out[key] = row
+        log(f"multi-rhs {key}: batched {row['t_batched_graph']:.3f} s, one by one {t_single:.3f} s, "
+            f"plain GCR {row['t_gcr_f64_batched']:.3f} s")
     return out
 
 
-def learned_subspace(torch, n_train=20, n_test=2, train_steps=300, m0=-0.56):
+def learned_subspace(torch, n_train=20, n_test=5, train_steps=300, m0=-0.56):
     """Start-field network: trained on 20 seeded 16^4 gauge fields (eps 0.5,
     seeds 5000..5019; targets = 24 inverse-iteration low modes, 3 steps, from
-    seeded random fields), tested on held-out 64 x 32^3 fields (seeds 5100..)
-    at m0 = -0.56 (near the critical mass of eps 0.5): deflated SAP-GCR
-    iterations and times with the subspace grown from (a) random fields and
-    (b) network fields, both with 3 inverse-iteration steps (equal setup
-    D-applications), and (c) network fields with 1 step. The network is local
-    (receptive field 9^4) and the links are i.i.d. per site, so a 16^4 lattice
-    has the local statistics of a 64 x 32^3 one."""
+    seeded random fields), tested on 5 held-out 64 x 32^3 fields (seeds
+    5100..5104) at m0 = -0.56: deflated SAP-GCR setup and solve times with the
+    subspace grown from (a) random fields with 3 inverse-iteration steps,
+    (b) network fields with 3 steps and (c) network fields with 1 step, and
+    plain FP64 GCR on the same field. The network is local (receptive field
+    9^4) and the links are i.i.d. per site, so a 16^4 lattice has the local
+    statistics of a 64 x 32^3 one."""
     import latgen
-    from paper_0706_2298_amd import F32, Solver, binding
+    from paper_0706_2298_amd import SOLVER_GCR, F64, Solver
     from paper_0706_2298_amd.learned import CHANNELS, StartFieldNet, make_targets
-    tdims, xdims, eps, K = (16, 16, 16, 16), (64, 32, 32, 32), 0.5, 24
-    prm = dict(Ns=24, m0=m0, m0_setup=m0, n_inviter=0, sap_prec=F32, link_prec=F32, little_prec=F32, maxiter=4000)
-    S = Solver(tdims, **solver_params(**prm))
+    tdims, eps, K = (16, 16, 16, 16), 0.5, 24
+    prm = params(m0=m0, m0_setup=m0, n_inviter=0)
+    S = Solver(tdims, **prm)
     links, targets = [], []
     t0 = time.perf_counter()
     for j in range(n_train):
@@ -395,22 +452,23 @@ def learned_subspace(torch, n_train=20, n_test=2, train_steps=300, m0=-0.56):
     S.close()
     del targets, net
     torch.cuda.empty_cache()
-    T = Solver(xdims, **solver_params(**prm))
+    T = Solver(DIMS, **prm)
     net = StartFieldNet(T, weights)
+    G = Solver(DIMS, **params(Ns=1, m0=m0, solver=SOLVER_GCR, nkv=32, maxiter=20000, sap_prec=F64, link_prec=F64))
     rows = []
     for j in range(n_test):
         seed = 5100 + j
-        U = latgen.make_links(xdims, eps, seed)
-        eta = latgen.make_source(xdims, seed + 100)
+        U = latgen.make_links(DIMS, eps, seed)
+        eta = latgen.make_source(DIMS, seed + 100)
         T.set_gauge(U)
         ed = T.pack(eta)
         row = dict(seed=seed)
-        noise = torch.tensor(latgen.net_noise(xdims, seed + 400), dtype=torch.float32, device="cuda")
+        noise = torch.tensor(latgen.net_noise(DIMS, seed + 400), dtype=torch.float32, device="cuda")
         for name, steps in [("random_k3", 3), ("learned_k3", 3), ("learned_k1", 1)]:
             # the random numbers of either start are generated and uploaded
             # before the clock starts
             if name.startswith("random"):
-                f = T.pack(latgen.make_init_fields(xdims, K, seed + 200))
+                f = T.pack(latgen.make_init_fields(DIMS, K, seed + 200))
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
             else:
@@ -425,53 +483,141 @@ def learned_subspace(torch, n_train=20, n_test=2, train_steps=300, m0=-0.56):
             row[name] = dict(n_gcr=info.n_gcr, t_setup=t_setup, t_solve=t_solve, status=info.status,
                              rel_residual=info.rel_residual, n_little=info.n_little)
             del f
-        del noise
+        G.set_gauge(U)
+        eg = G.pack(eta)
+        (_, infog), t_g = timed(torch, lambda: G.solve(eg))
+        row["gcr_f64"] = dict(n_gcr=infog.n_gcr, t_solve=t_g)
+        del noise, eg, ed
         rows.append(row)
         log(f"learned: field {seed}: " + ", ".join(f"{k} {row[k]['n_gcr']} it" for k in row if k != "seed"))
     T.close()
+    G.close()
     torch.cuda.empty_cache()
-    return dict(train_lattice=list(tdims), test_lattice=list(xdims), eps=eps, m0=m0, channels=list(CHANNELS),
+    mean = lambda k, q: float(np.mean([r[k][q] for r in rows]))
+    summary = {k: dict(n_gcr=mean(k, "n_gcr"), t_setup=mean(k, "t_setup"), t_solve=mean(k, "t_solve"))
+               for k in ("random_k3", "learned_k3", "learned_k1")}
+    summary["gcr_f64"] = dict(n_gcr=mean("gcr_f64", "n_gcr"), t_solve=mean("gcr_f64", "t_solve"))
+    return dict(train_lattice=list(tdims), test_lattice=list(DIMS), eps=eps, m0=m0, channels=list(CHANNELS),
                 n_train_fields=n_train, train_steps=train_steps, t_targets=t_targets, t_train=t_train,
-                loss_first10=float(np.mean(losses[:10])), loss_last10=float(np.mean(losses[-10:])), tests=rows)
+                loss_first10=float(np.mean(losses[:10])), loss_last10=float(np.mean(losses[-10:])), tests=rows,
+                mean_over_tests=summary)
 
 
-def cpu_baseline(fields, stats):
-    """The FP64 oracle on a bounded sample of the step, scaled to solves/s.
+def workload_16x4(torch):
+    """The 16^4 lattice at eps 0.4 and 0.6 (seeds 2001/2002), one setup
+    (Ns = 20, 3 inverse-iteration steps) per field reused for m0 = -0.2, -0.3,
+    -0.35: time per step of six solves, and the undeflated solvers."""
+    import latgen
+    from paper_0706_2298_amd import SOLVER_GCR, SOLVER_SAP_GCR, F64, Solver
+    ctx = []
+    for eps, seed in C2_FIELDS:
+        U = latgen.make_links(C2_DIMS, eps, seed)
+        S = Solver(C2_DIMS, **params(Ns=20, m0=C2_MASSES[0], m0_setup=min(C2_MASSES), little_prec=F64))
+        S.set_gauge(U)
+        ctx.append(dict(S=S, U=U, eps=eps, eta_h=latgen.make_source(C2_DIMS, seed + 100),
+                        eta=S.pack(latgen.make_source(C2_DIMS, seed + 100)),
+                        init=S.pack(latgen.make_init_fields(C2_DIMS, 20, seed + 200))))
+    stats = []
 
-    Sample: for the eps = 0.4 field, two Schwarz applications, the block
-    Gram-Schmidt and little-operator assembly on the 20 start fields, and
-    three iterations of the deflated GCR at m0 = -0.3. The step's cost is the
-    GPU run's own operation counts (setup SAP applications, GCR iterations)
-    times these unit costs.
-    """
+    def one(record):
+        for c in ctx:
+            c["S"].setup(c["init"])
+            for m in C2_MASSES:
+                c["S"].set_mass(m)
+                (_, info), t = timed(torch, lambda: c["S"].solve(c["eta"]))
+                if record:
+                    stats.append(dict(eps=c["eps"], m0=m, n_gcr=info.n_gcr, t_solve=t))
+    one(False)
+    _, dt = timed(torch, lambda: one(True))
+    rows = []
+    for c in ctx:
+        c["S"].close()
+        for solver, name in [(SOLVER_SAP_GCR, "sap_gcr"), (SOLVER_GCR, "gcr_f64")]:
+            S = Solver(C2_DIMS, **params(solver=solver, nkv=32, Ns=1, maxiter=20000))
+            S.set_gauge(c["U"])
+            ed = S.pack(c["eta_h"])
+            for m in C2_MASSES:
+                S.set_mass(m)
+                (_, info), t = timed(torch, lambda: S.solve(ed))
+                rows.append(dict(solver=name, eps=c["eps"], m0=m, n_gcr=info.n_gcr, t_solve=t))
+            S.close()
+    torch.cuda.empty_cache()
+    return dict(lattice=list(C2_DIMS), ms_per_step=dt * 1e3, solves_per_s=6 / dt, dfl_sap_gcr=stats,
+                undeflated=rows)
+
+
+def _oracle_units(threads_note=""):
+    """Oracle unit costs on the 16^4 field of eps 0.5 (one Dirac application,
+    one Schwarz application with 5 cycles, block Gram-Schmidt plus little
+    operator for 24 fields, one little-operator application, one restriction
+    plus prolongation with 24 fields)."""
+    import latgen
     import oracle
-    f = fields[0]
-    U, eta, init = f["U"], f["eta"], f["init"]
-    m0 = -0.3
+    dims = (16, 16, 16, 16)
+    U = latgen.make_links(dims, EPS, 6001)
+    eta = latgen.make_source(dims, 6002)
+    init = latgen.make_init_fields(dims, NS, 6003)
+    t = {}
     t0 = time.perf_counter()
-    for _ in range(2):
-        oracle.sap(U, eta, m0, DIMS, BLOCK, NCY, NMR)
-    t_sap = (time.perf_counter() - t0) / 2
+    oracle.dirac(U, eta, M0, dims)
+    t["dirac"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    Phi = oracle.block_gram_schmidt(init, DIMS, BLOCK)
-    A = oracle.little_operator(U, Phi, m0, DIMS, BLOCK)
-    t_subspace = time.perf_counter() - t0
-    dfl = oracle.Deflation(U, Phi, A, m0, DIMS, BLOCK)
+    oracle.sap(U, eta, M0, dims, BLOCK, NCY, NMR)
+    t["sap"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.solve(U, eta, m0, DIMS, sap_block=BLOCK, ncy=NCY, nmr=NMR, dfl=dfl, tol=1e-30, maxiter=3)
-    t_three = time.perf_counter() - t0
-    sample_s = 2 * t_sap + t_subspace + t_three
-    t_iter = t_three / 3.0
-    n_setup_sap = len(fields) * NS * NINV
-    n_iter = sum(s["n_gcr"] for s in stats)
-    est = n_setup_sap * t_sap + len(fields) * t_subspace + n_iter * t_iter
-    n_solves = len(stats)
-    return dict(value=n_solves / est, unit="solves/s", cores=oracle.num_threads(), kind="oracle",
-                sample=(f"16^4 eps=0.4 field: 2 SAP applications ({t_sap:.2f}s each), block GS + little operator "
-                        f"on 20 fields ({t_subspace:.2f}s), 3 deflated GCR iterations ({t_three:.2f}s); scaled by "
-                        f"the step's {n_setup_sap} setup SAP applications, 2 subspace builds and {n_iter} GCR "
-                        f"iterations -> {est:.1f}s per step of {n_solves} solves"),
-                sample_seconds=sample_s)
+    Phi = oracle.block_gram_schmidt(init, dims, BLOCK)
+    A = oracle.little_operator(U, Phi, M0, dims, BLOCK)
+    t["subspace"] = time.perf_counter() - t0
+    v = oracle.restrict(Phi, eta, dims, BLOCK)
+    t0 = time.perf_counter()
+    oracle.little_apply(A, v, dims, BLOCK)
+    t["little_apply"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.prolong(Phi, oracle.restrict(Phi, eta, dims, BLOCK), dims, BLOCK)
+    t["project"] = time.perf_counter() - t0
+    t["threads"] = oracle.num_threads()
+    return t
+
+
+def cpu_baseline(prof, info):
+    """The FP64 oracle on a bounded sample, scaled to the headline step.
+
+    Sample: unit costs of the oracle on a 16^4 lattice (1/32 of the headline
+    volume; every unit is linear in the volume): one Dirac application, one
+    Schwarz application, the subspace build for 24 fields, one little-operator
+    application and one restriction plus prolongation. The step's cost is the
+    GPU step's own operation counts times these units times 32: setup (3
+    inverse-iteration Schwarz applications per field, the subspace build) and
+    solve (per GCR iteration one Schwarz application, two Dirac applications
+    and two projections; per little GCR iteration two little-operator
+    applications). Also the units with one thread (a subprocess with
+    OMP_NUM_THREADS=1)."""
+    units = _oracle_units()
+    scale = V / 16 ** 4
+    n_it = info.n_gcr + info.n_restarts
+    n_little = prof["little_iterations"]
+    est_setup = scale * (NINV * NS * units["sap"] + units["subspace"])
+    est_solve = scale * (info.n_gcr * units["sap"] + 2 * n_it * units["dirac"] + 2 * n_it * units["project"]
+                         + 2 * n_little * units["little_apply"])
+    est = est_setup + est_solve
+    one = None
+    try:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        code = ("import json, bench; print(json.dumps(bench._oracle_units()))")
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                           timeout=300)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        one = None
+    return dict(value=1.0 / est, unit="steps/s", cores=units["threads"], kind="oracle",
+                sample=(f"oracle unit costs on 16^4 (eps 0.5): Dirac {units['dirac']:.3f}s, Schwarz application "
+                        f"{units['sap']:.2f}s, 24-field subspace {units['subspace']:.2f}s, little apply "
+                        f"{units['little_apply']:.4f}s, restrict+prolong {units['project']:.3f}s; x{scale:.0f} "
+                        f"volume, times the GPU step's counts ({NINV}x{NS} setup Schwarz applications, "
+                        f"{info.n_gcr} GCR iterations, {n_little} little iterations) -> {est_setup:.0f}s setup + "
+                        f"{est_solve:.0f}s solve per step"),
+                est_setup_s=est_setup, est_solve_s=est_solve, units=units, units_one_thread=one)
 
 
 def main():
@@ -483,15 +629,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dirac", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the 32x16^3 mixed-precision and multi-source runs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 32x16^3, multi-source and 16^4 runs")
     ap.add_argument("--no-learned", action="store_true", help="skip the start-field network training and tests")
-    ap.add_argument("--learned-tests", type=int, default=2, help="held-out 64x32^3 fields for the network")
+    ap.add_argument("--learned-tests", type=int, default=5, help="held-out 64x32^3 fields for the network")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (y = 1.0 * x), to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this solver build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not implemented)"}))
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (sharding over several GPUs "
+                                   "is a design note, not built)"}))
         sys.exit(2)
 
     import torch
@@ -510,32 +656,31 @@ def main():
         return
 
     log("generating inputs")
-    fields = make_inputs()
-    ctxs = []
-    for f in fields:
-        S = Solver(DIMS, **solver_params())
-        S.set_gauge(f["U"])
-        ctxs.append(dict(S=S, eps=f["eps"], eta=S.pack(f["eta"]), init=S.pack(f["init"])))
+    U, eta_h, init_h = headline_inputs()
+    S = Solver(DIMS, **params())
+    S.set_gauge(U)
+    eta, init = S.pack(eta_h), S.pack(init_h)
     torch.cuda.synchronize()
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
-        run_step(ctxs)
-    torch.cuda.synchronize()
+        step(torch, S, eta, init)
     log(f"timing {args.steps} steps")
-    stats = []
+    per = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        run_step(ctxs, stats if k == 0 else None)
+    for _ in range(args.steps):
+        per.append(step(torch, S, eta, init))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    n_solves = len(FIELDS) * len(MASSES)
-    log(f"step {dt * 1e3:.1f} ms")
+    info = per[0][2]
+    log(f"step {dt * 1e3:.1f} ms (setup {np.median([p[0] for p in per]) * 1e3:.1f} ms, "
+        f"solve {np.median([p[1] for p in per]) * 1e3:.1f} ms, {info.n_gcr} iterations)")
 
     result = {
         "metric": "dirac_apply GFLOP/s + HBM GB/s; time-to-solution @ rel. residual 1e-10",
-        "value": n_solves / dt,
-        "unit": "solves/s",
+        "value": 1.0 / dt,
+        "unit": "solves/s (one subspace setup + one solve each)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -543,43 +688,50 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32 (FP64 GCR, projector and residual; FP32 Schwarz and inner little solves)",
         "data": "synthetic",
-        "config": {"workload": "16^4 DFL+SAP+GCR: eps {0.4,0.6} x m0 {-0.2,-0.3,-0.35}, one setup per field "
-                               "(Ns 20, 3 inverse-iteration steps, 4^4 blocks), FP64 GCR + FP32 SAP, tol 1e-10",
+        "config": {"workload": "64x32^3 DFL+SAP+GCR, eps 0.5 (seed 5100), m0 -0.56: one setup (Ns 24, 3 "
+                               "inverse-iteration steps, 4^4 blocks) + one solve to 1e-10 per step",
                    "lattice": list(DIMS), "Ns": NS, "n_inviter": NINV, "ncy": NCY, "nmr": NMR, "nkv": NKV,
-                   "solves_per_step": n_solves},
-        "time_to_solution_s": {f"eps{s['eps']}_m{s['m0']}": s["t_solve"] for s in stats},
-        "solves": stats,
+                   "blocks": list(BLOCK)},
+        "time_to_solution_s": {"setup": float(np.median([p[0] for p in per])),
+                               "solve": float(np.median([p[1] for p in per])), "total": dt},
+        "solve": dict(info.as_dict()),
     }
     if not args.no_profile:
         log("profiled step")
-        prof, little_it = profiled_step(ctxs)
-        result["roofline"], result["kernel_time_per_step"] = roofline(prof, little_it)
-    for c in ctxs:
-        c["S"].close()
-    ctxs.clear()
+        prof = profiled(S, lambda: step(torch, S, eta, init))
+        result["roofline"] = roofline(prof)
+        result["kernel_time_per_step"] = {k: dict(seconds=prof[k][0], launches=prof[k][1])
+                                          for k in prof if k != "little_iterations"}
+        result["kernel_time_per_step"]["little_iterations"] = prof["little_iterations"]
+    else:
+        prof = None
+    S.close()
+    del eta, init
     torch.cuda.empty_cache()
 
     if not args.no_dirac:
         log("dirac_apply on 64x32^3")
         result["dirac_apply"] = dirac_rates(torch)
     if not args.no_compare:
-        log("undeflated comparisons")
-        result["undeflated"] = undeflated(torch, fields)
+        log("comparisons on the headline field")
+        result["comparisons"] = comparisons(torch, U, eta_h, init_h)
     if not args.no_extras:
         log("mixed precision on 32x16^3")
         result["mixed_precision_32x16^3"] = mixed_precision_32x16(torch)
         log("multi-source batches")
         result["multi_rhs"] = multi_rhs(torch)
+        log("16^4 workload")
+        result["workload_16^4"] = workload_16x4(torch)
     if not args.no_learned:
         log("learned start fields")
         result["learned_subspace"] = learned_subspace(torch, n_test=args.learned_tests)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and prof is not None:
         log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(fields, stats)
+        result["cpu_baseline"] = cpu_baseline(prof, info)
     result["host"] = {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
-    print(json.dumps(result))
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":

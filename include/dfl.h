@@ -9,12 +9,15 @@
  * built by inverse iteration (eq. (5.1)) and the little Dirac operator of
  * eqs. (3.2)/(A.1).
  *
- * Operator. D is the plain Wilson operator (the paper's operator without the
- * clover term), periodic in all four directions:
- *   (D psi)(x) = (4 + m0) psi(x) - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu)
- *                                              + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ * Operator. D is the O(a)-improved Wilson operator of section 2.1:
+ *   (D psi)(x) = (4 + m0) psi(x) + csw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x) psi(x)
+ *                - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
  * with the chiral basis g_mu = [[0, e_mu], [e_mu^+, 0]], e_0 = -1,
- * e_k = -i sigma_k (so g_5 = diag(1, 1, -1, -1)).
+ * e_k = -i sigma_k (so g_5 = diag(1, 1, -1, -1)), sigma_{mu nu} = (i/2)[g_mu, g_nu],
+ * Fhat_{mu nu}(x) = (Q_{mu nu}(x) - Q_{mu nu}(x)^+)/8 with Q_{mu nu} the sum of the
+ * four plaquettes in the (mu, nu) plane around x. csw = 0 (the default) is
+ * the plain Wilson operator. Space is periodic; time (direction 0) periodic
+ * or antiperiodic (dfl_params.antiperiodic).
  *
  * Canonical layouts (host-side convention, also accepted on the device):
  *   site s = ((x0*L1 + x1)*L2 + x2)*L3 + x3 (x0 slowest), V sites;
@@ -112,10 +115,25 @@ typedef struct {
     int little_eo;         /* 1: single-source little solves run GCR on the even-odd
                               reduced system (appendix A.2), falling back to A when a
                               diagonal block is not safely invertible */
-    int little_gdefl;      /* 1 (with little_eo and Ns <= 32): deflate the even-odd little
-                              system by the even-block parts of the global fields the
-                              subspace was built from, i.e. the inverse-iteration fields
-                              before block orthonormalisation (appendix A.3) */
+    int little_gdefl;      /* global-mode deflation of the even-odd little system
+                              (appendix A.3; with little_eo and Ns <= 32) by the
+                              even-block parts of the global fields the subspace was built
+                              from, i.e. the inverse-iteration fields before block
+                              orthonormalisation. 0: off; 1: minimal-residual form (the
+                              residue kept orthogonal to A_hat Z); 2: section 3's oblique
+                              projectors with the Ns x Ns "little little" operator
+                              Z^+ A_hat Z inverted exactly */
+    double csw;            /* coefficient of the O(a)-improvement (clover) term of section
+                              2.1, csw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x), Fhat
+                              from the four plaquettes around x; 0: plain Wilson */
+    int antiperiodic;      /* 1: antiperiodic quark boundary condition in direction 0
+                              (time), 0: periodic; space is always periodic */
+    int n_boot;            /* 0..n_inviter: the last n_boot inverse-iteration steps of
+                              dfl_setup are bootstrapped (section 5.3): the fields of the
+                              previous step span a subspace that deflates the approximate
+                              solve, psi <- P_R M_sap P_L psi + Phi A^-1 Phi^+ psi (eqs. (3.10),
+                              (3.11)), little solves to little_tol_in in little_prec;
+                              needs 2 Ns more FP64 fields of device memory */
 } dfl_params;
 
 typedef struct {
@@ -258,8 +276,9 @@ enum {
     DFL_PROF_DIRAC = 1,    /* full-lattice Dirac operator inside the solvers and dirac_apply */
     DFL_PROF_LITTLE = 2,   /* little GCR (one cooperative launch per little solve) */
     DFL_PROF_PROJECT = 3,  /* block restriction and prolongation */
-    DFL_PROF_SETUP = 4,    /* Schwarz sweeps of the inverse iteration, block Gram-Schmidt, little-operator assembly */
-    DFL_PROF_NCLASS = 5
+    DFL_PROF_SETUP = 4,    /* block Gram-Schmidt, little-operator assembly and its even-odd and global-mode preparation */
+    DFL_PROF_SETUP_SAP = 5, /* Schwarz sweeps of the inverse iteration (all Ns fields per launch) */
+    DFL_PROF_NCLASS = 6
 };
 int dfl_profile_enable(dfl_ctx *ctx, int on);
 /* seconds[DFL_PROF_NCLASS], launches[DFL_PROF_NCLASS] (host memory); little_iters

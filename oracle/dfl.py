@@ -495,25 +495,50 @@ def gcr(apply_op, eta, precond=None, project=None, tol: float = 1e-10, nkv: int 
 
 
 def inverse_iteration(U, init, m0: float, dims, sap_block, ncy: int, nmr: int, n_iter: int, *, csw: float = 0.0,
-                      antiperiodic: bool = False):
-    """Relaxed inverse iteration of eq. (5.1): psi_l <- M_sap psi_l, normalised.
+                      antiperiodic: bool = False, n_boot: int = 0, dfl_block=None):
+    """Relaxed inverse iteration of eq. (5.1): psi_l <- "D^-1" psi_l, normalised.
 
-    The start fields are normalised first; each step applies one Schwarz
-    procedure (ncy cycles) to every field and normalises it again. No
-    orthogonalisation between fields (the block Gram-Schmidt follows).
+    The start fields are normalised first; each step applies an approximate
+    inverse of D to every field and normalises it again. No orthogonalisation
+    between fields (the block Gram-Schmidt follows).
+
+    The approximate inverse is one Schwarz procedure M_sap (ncy cycles), as
+    section 5.3 proposes. With n_boot > 0 the last n_boot steps are
+    bootstrapped (the last paragraph of section 5.3): before such a step the
+    current fields span a deflation subspace (eq. (4.2) on blocks dfl_block,
+    little operator eq. (A.1) at this mass), and the step solves D chi = psi_l
+    with it the way section 6 does, stopped after the preconditioner: the
+    deflated equation P_L D chi = P_L psi (eq. (3.11)) is solved approximately
+    by chi = M_sap P_L psi, and the solution is completed by eq. (3.10),
+    psi <- P_R chi + Phi A^-1 Phi^dagger psi. (With M_sap = D^-1 this is D^-1 psi
+    exactly, since P_R D^-1 P_L = D^-1 - Phi A^-1 Phi^dagger.)
     """
+    n_iter, n_boot = int(n_iter), int(n_boot)
+    if not 0 <= n_boot <= n_iter:
+        raise ValueError("n_boot must lie in 0..n_iter")
+    if n_boot and dfl_block is None:
+        raise ValueError("a bootstrapped step needs the deflation block shape")
+    kw = dict(csw=csw, antiperiodic=antiperiodic)
     fields = [np.asarray(f, dtype=np.complex128).reshape(-1, 12) for f in init]
     fields = [f / norm(f) for f in fields]
-    for _ in range(int(n_iter)):
-        fields = [sap(U, f, m0, dims, sap_block, ncy, nmr, csw=csw, antiperiodic=antiperiodic) for f in fields]
+    for step in range(n_iter):
+        if step < n_iter - n_boot:
+            fields = [sap(U, f, m0, dims, sap_block, ncy, nmr, **kw) for f in fields]
+        else:
+            Phi = block_gram_schmidt(np.stack(fields), dims, dfl_block)
+            A = little_operator(U, Phi, m0, dims, dfl_block, **kw)
+            dfl = Deflation(U, Phi, A, m0, dims, dfl_block, **kw)
+            fields = [dfl.PR(sap(U, dfl.PL(f), m0, dims, sap_block, ncy, nmr, **kw)) + dfl.coarse(f)
+                      for f in fields]
         fields = [f / norm(f) for f in fields]
     return np.stack(fields)
 
 
 def setup(U, init, m0: float, dims, sap_block, dfl_block, ncy: int, nmr: int, n_iter: int, *, csw: float = 0.0,
-          antiperiodic: bool = False):
+          antiperiodic: bool = False, n_boot: int = 0):
     """Subspace generation (section 5.3) + eq. (4.2) + eq. (A.1): returns (Phi, A)."""
-    fields = inverse_iteration(U, init, m0, dims, sap_block, ncy, nmr, n_iter, csw=csw, antiperiodic=antiperiodic)
+    fields = inverse_iteration(U, init, m0, dims, sap_block, ncy, nmr, n_iter, csw=csw, antiperiodic=antiperiodic,
+                               n_boot=n_boot, dfl_block=dfl_block)
     Phi = block_gram_schmidt(fields, dims, dfl_block)
     A = little_operator(U, Phi, m0, dims, dfl_block, csw=csw, antiperiodic=antiperiodic)
     return Phi, A

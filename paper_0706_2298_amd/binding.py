@@ -32,7 +32,8 @@ class Params(ctypes.Structure):
         ("little_tol_in", ctypes.c_double), ("little_tol_out", ctypes.c_double),
         ("link_prec", ctypes.c_int), ("sap_prec", ctypes.c_int), ("little_prec", ctypes.c_int),
         ("little_grid", ctypes.c_int), ("little_adapt", ctypes.c_int), ("little_eo", ctypes.c_int),
-        ("little_gdefl", ctypes.c_int),
+        ("little_gdefl", ctypes.c_int), ("csw", ctypes.c_double), ("antiperiodic", ctypes.c_int),
+        ("n_boot", ctypes.c_int),
     ]
 
 
@@ -62,7 +63,7 @@ EXPORTS = [
     "dfl_inverse_iteration", "net_features", "conv4d_forward", "conv4d_backward", "net_outputs_to_fields",
     "net_fields_grad_to_outputs", "deficit_loss", "adam_update",
 ]
-PROF_CLASSES = ["sap", "dirac", "little", "project", "setup"]
+PROF_CLASSES = ["sap", "dirac", "little", "project", "setup", "setup_sap"]
 
 
 def load(path: str = LIB_PATH):

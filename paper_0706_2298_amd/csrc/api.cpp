@@ -66,7 +66,8 @@ void free_all(dfl_ctx* c)
                     c->lchi, c->lr,  c->lx,   c->lw,  c->lt,    c->lw32, c->lx32, c->red, c->dscal, c->dflag,
                     c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
                     c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol, c->Mt64, c->Mt32, c->lw1, c->lw2,
-                    c->gsR, c->gU, c->gW, c->gQ, c->gZ, c->gQ32, c->gZ32, c->gC};
+                    c->gsR, c->gU, c->gW, c->gQ, c->gZ, c->gQ32, c->gZ32, c->gC, c->Cl64, c->Cl32,
+                    c->gAinv, c->gGw, c->bootF, c->bootT};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -134,8 +135,16 @@ void validate(const dfl_params& p)
         fail(DFL_EINVAL, "FP64 SAP needs FP64 links");
     if (p.little_prec != DFL_F64 && p.little_prec != DFL_F32)
         fail(DFL_EINVAL, "little_prec must be F64 or F32");
+    if (p.little_gdefl < 0 || p.little_gdefl > 2)
+        fail(DFL_EINVAL, "little_gdefl must be 0, 1 or 2");
+    if (p.n_boot < 0 || p.n_boot > p.n_inviter)
+        fail(DFL_EINVAL, "n_boot must lie in 0..n_inviter");
     if (p.solver < DFL_SOLVER_GCR || p.solver > DFL_SOLVER_DFL_SAP_GCR)
         fail(DFL_EINVAL, "unknown solver");
+    if (!std::isfinite(p.csw))
+        fail(DFL_EINVAL, "csw must be finite");
+    if (p.antiperiodic != 0 && p.antiperiodic != 1)
+        fail(DFL_EINVAL, "antiperiodic must be 0 or 1");
 }
 
 Links64 links64(const dfl_ctx* c) { return Links64{c->U64, c->V}; }
@@ -331,7 +340,7 @@ void run_step(dfl_ctx* c, long key, const std::function<void()>& body)
 void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0, int nb = 1)
 {
     ProfScope ps(c, DFL_PROF_DIRAC);
-    launch_dirac64(c->g, links64(c), in, out, nb, m0, 0, 0, 0, c->stream);
+    launch_dirac64(c->g, links64(c), in, out, nb, m0, 0, 0, 0, c->stream, c->Cl64);
 }
 
 // out = s - D in for nb fields (the subtraction fused into the stencil); out
@@ -339,7 +348,7 @@ void dirac64(dfl_ctx* c, const c64* in, c64* out, double m0, int nb = 1)
 void dirac64_sub(dfl_ctx* c, const c64* s, const c64* in, c64* out, double m0, int nb = 1)
 {
     ProfScope ps(c, DFL_PROF_DIRAC);
-    launch_dirac64_sub(c->g, links64(c), s, in, out, nb, m0, c->stream);
+    launch_dirac64_sub(c->g, links64(c), s, in, out, nb, m0, c->stream, c->Cl64);
 }
 
 // psi = M_sap rho for nrhs fields (FP64 in and out; block solves in sap_prec).
@@ -356,7 +365,7 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1)
             for (int col = 0; col < 2; ++col) {
                 ProfScope ps(c, c->sap_prof_cls);
                 launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, nrhs, init_of(cy, col),
-                                    c->stream);
+                                    c->stream, c->Cl64);
             }
         return;
     }
@@ -369,10 +378,10 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1)
             c64* out64 = cy == ncy - 1 ? psi : nullptr;
             if (c->p.link_prec == DFL_BF16)
                 launch_sap_colour_bf16(c->g, c->sg, linksbf(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
-                                       init_of(cy, col), out64, c->stream);
+                                       init_of(cy, col), out64, c->stream, c->Cl32);
             else
                 launch_sap_colour32(c->g, c->sg, links32(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
-                                    init_of(cy, col), out64, c->stream);
+                                    init_of(cy, col), out64, c->stream, c->Cl32);
         }
 }
 
@@ -573,7 +582,8 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
         if (nb == 1)
             launch_little_gcr<double>(c->g, Ns, nkv, mi, tol, tol_dev, c->At64, c->eo_ok ? c->Mt64 : nullptr,
                                       static_cast<c64*>(c->lw1), static_cast<c64*>(c->lw2), c->gQ, c->gZ,
-                                      c->eo_ok ? c->gdefl_n : 0, w, v, static_cast<c64*>(c->lr),
+                                      c->eo_ok ? c->gdefl_n : 0, c->gdefl_oblique, c->gAinv, c->gGw, w, v,
+                                      static_cast<c64*>(c->lr),
                                       static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lstats,
                                       c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
         else
@@ -588,7 +598,8 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
             if (nb == 1)
                 launch_little_gcr<float>(c->g, Ns, nkv, mi, tol, tol_dev, c->At32, c->eo_ok ? c->Mt32 : nullptr,
                                          static_cast<c32*>(c->lw1), static_cast<c32*>(c->lw2), c->gQ32, c->gZ32,
-                                         c->eo_ok ? c->gdefl_n : 0, c->lw32, c->lx32, static_cast<c32*>(c->lr),
+                                         c->eo_ok ? c->gdefl_n : 0, c->gdefl_oblique, c->gAinv, c->gGw, c->lw32,
+                                         c->lx32, static_cast<c32*>(c->lr),
                                          static_cast<c32*>(c->lxi), static_cast<c32*>(c->lchi), c->lpart, c->lstats,
                                          c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
             else
@@ -714,11 +725,120 @@ int cholesky_inverse(std::vector<cd>& G, int n)
     return m;
 }
 
+// Dense inverse of an n x n complex matrix (row-major) by Gauss-Jordan with
+// partial pivoting; false if a pivot falls below 1e-12 of the largest entry.
+bool invert_dense(std::vector<cd>& M, int n)
+{
+    std::vector<cd> I((size_t)n * n, cd(0.0, 0.0));
+    for (int i = 0; i < n; ++i)
+        I[(size_t)i * n + i] = 1.0;
+    double big = 0.0;
+    for (const cd& z : M)
+        big = std::max(big, std::abs(z));
+    if (!(big > 0.0))
+        return false;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::abs(M[(size_t)r * n + col]) > std::abs(M[(size_t)piv * n + col]))
+                piv = r;
+        if (!(std::abs(M[(size_t)piv * n + col]) > 1e-12 * big))
+            return false;
+        if (piv != col)
+            for (int j = 0; j < n; ++j) {
+                std::swap(M[(size_t)piv * n + j], M[(size_t)col * n + j]);
+                std::swap(I[(size_t)piv * n + j], I[(size_t)col * n + j]);
+            }
+        const cd inv = 1.0 / M[(size_t)col * n + col];
+        for (int j = 0; j < n; ++j) {
+            M[(size_t)col * n + j] *= inv;
+            I[(size_t)col * n + j] *= inv;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col)
+                continue;
+            const cd f = M[(size_t)r * n + col];
+            if (f == cd(0.0, 0.0))
+                continue;
+            for (int j = 0; j < n; ++j) {
+                M[(size_t)r * n + j] -= f * M[(size_t)col * n + j];
+                I[(size_t)r * n + j] -= f * I[(size_t)col * n + j];
+            }
+        }
+    }
+    M = I;
+    return true;
+}
+
+// Section 3's projectors on the even-odd little system (appendix A.3 as the
+// paper states it): Z = the even-block global modes, orthonormalised
+// (Cholesky-QR twice), W = A_hat Z, the "little little" operator Z^+ W
+// inverted exactly on the host; the little GCR then applies
+// P_L = 1 - W (Z^+ W)^-1 Z^+ to every new Krylov image and to the residue at
+// the start and at every restart, and the solution picks up Z (Z^+ W)^-1 Z^+
+// of the residue. Synchronises; off (gdefl_n = 0) if Z^+ W is not safely
+// invertible.
+void prepare_gdefl_oblique(dfl_ctx* c)
+{
+    const int Ns = c->p.Ns;
+    const long N = (long)c->g.Nb * Ns;
+    launch_global_modes(c->g, c->gsR, Ns, c->gU, c->stream);
+    std::vector<cd> G;
+    int nq = Ns;
+    for (int pass = 0; pass < 2; ++pass) {
+        c64* X = pass == 0 ? c->gU : c->gZ;
+        c64* Xout = pass == 0 ? c->gZ : c->gU;
+        launch_gram(X, N, nq, c->gC, c->stream);
+        G.assign((size_t)nq * nq, cd(0.0, 0.0));
+        HIPCHECK(hipMemcpyAsync(G.data(), c->gC, sizeof(c64) * nq * nq, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        const int m = cholesky_inverse(G, nq);
+        if (m == 0)
+            return;
+        std::vector<cd> C((size_t)nq * m);
+        for (int k = 0; k < nq; ++k)
+            for (int l = 0; l < m; ++l)
+                C[(size_t)k * m + l] = G[(size_t)k * nq + l];
+        HIPCHECK(hipMemcpyAsync(c->gC, C.data(), sizeof(c64) * nq * m, hipMemcpyHostToDevice, c->stream));
+        launch_combine(X, N, nq, m, c->gC, Xout, c->stream);
+        sync(c);
+        nq = m;
+    }
+    std::swap(c->gZ, c->gU);  // Z (orthonormal, nq columns) now in gZ
+    // W = A_hat Z on the even blocks: odd = M_oe Z, then even = Z - M_eo (odd)
+    launch_zero<double>(c->gW, N * Ns, c->stream);
+    launch_zero<double>(c->gQ, N * Ns, c->stream);
+    launch_eo_hop(c->g, c->Mt64, Ns, c->gZ, nullptr, c->gW, nq, 1, 0.0, 1.0, c->stream);
+    launch_eo_hop(c->g, c->Mt64, Ns, c->gW, c->gZ, c->gQ, nq, 0, 1.0, -1.0, c->stream);
+    std::vector<cd> Ac((size_t)nq * nq), Gw((size_t)nq * nq);
+    launch_gram2(c->gZ, c->gQ, N, nq, c->gC, c->stream);
+    HIPCHECK(hipMemcpyAsync(Ac.data(), c->gC, sizeof(c64) * nq * nq, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    launch_gram(c->gQ, N, nq, c->gC, c->stream);
+    HIPCHECK(hipMemcpyAsync(Gw.data(), c->gC, sizeof(c64) * nq * nq, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (!invert_dense(Ac, nq))
+        return;
+    HIPCHECK(hipMemcpyAsync(c->gAinv, Ac.data(), sizeof(c64) * nq * nq, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(hipMemcpyAsync(c->gGw, Gw.data(), sizeof(c64) * nq * nq, hipMemcpyHostToDevice, c->stream));
+    launch_c64_to_c32(c->gQ, c->gQ32, N * Ns, c->stream);
+    launch_c64_to_c32(c->gZ, c->gZ32, N * Ns, c->stream);
+    HIPCHECK(hipGetLastError());
+    sync(c);  // Ac and Gw are host memory read by the copies
+    c->gdefl_n = nq;
+    c->gdefl_oblique = true;
+}
+
 void prepare_gdefl(dfl_ctx* c)
 {
     c->gdefl_n = 0;
+    c->gdefl_oblique = false;
     if (!c->p.little_gdefl || !c->eo_ok || !c->gU)
         return;
+    if (c->p.little_gdefl == 2) {
+        prepare_gdefl_oblique(c);
+        return;
+    }
     const int Ns = c->p.Ns;
     const long N = (long)c->g.Nb * Ns;
     launch_global_modes(c->g, c->gsR, Ns, c->gU, c->stream);
@@ -786,7 +906,7 @@ void inverse_iterate(dfl_ctx* c, c64* f, int n, int steps)
     // the sweeps of the inverse iteration are timed as setup work
     struct SetupSweeps {
         dfl_ctx* c;
-        explicit SetupSweeps(dfl_ctx* cc) : c(cc) { c->sap_prof_cls = DFL_PROF_SETUP; }
+        explicit SetupSweeps(dfl_ctx* cc) : c(cc) { c->sap_prof_cls = DFL_PROF_SETUP_SAP; }
         ~SetupSweeps() { c->sap_prof_cls = DFL_PROF_SAP; }
     } setup_sweeps(c);
     for (int step = 0; step < steps; ++step) {
@@ -816,6 +936,102 @@ template <typename T> T* grow(dfl_ctx* c, T* p, size_t& have, size_t need)
     T* q = alloc_dev<T>(c, need);
     have = need;
     return q;
+}
+
+// Block Gram-Schmidt (eq. (4.2)) of the Ns fields at src into Phi and the
+// little operator (eq. (A.1)) at mass mA, with the even-odd and global-mode
+// preparation. Synchronises; fails on non-finite fields or rank loss.
+void build_subspace(dfl_ctx* c, const c64* src, double mA)
+{
+    const long F = c->field_elems;
+    const int Ns = c->p.Ns;
+    if (src != c->Phi)
+        HIPCHECK(hipMemcpyAsync(c->Phi, src, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
+    ProfScope ps_setup(c, DFL_PROF_SETUP);
+    launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->gsR, c->stream);
+    // little operator, eq. (A.1): block-diagonal part and the eight face
+    // hops, applied to a chunk of basis fields per launch (the Krylov
+    // buffer is free during the setup), then the block products with Phi.
+    // Chunk of basis fields per launch: bounded by the Krylov buffer (the
+    // stencil output) and by t1 (the split partial sums, Nb*Ns*chunk entries)
+    const long part_cap = F * c->p.nrhs_max;
+    const int chunk = (int)std::max(1L, std::min({(long)Ns, (long)little_columns_max(Ns),
+                                                  (long)c->p.nkv * c->p.nrhs_max, (long)(128 - Ns),
+                                                  part_cap / ((long)c->g.Nb * Ns)}));
+    for (int l0 = 0; l0 < Ns; l0 += chunk) {
+        const int nc = std::min(chunk, Ns - l0);
+        const c64* f = c->Phi + (long)l0 * F;
+        for (int d = 0; d < 9; ++d) {
+            if (d == 0) {
+                launch_dirac64(c->g, links64(c), f, c->xi, nc, mA, 1, 0, 0, c->stream, c->Cl64);
+            } else {
+                const int mu = (d - 1) / 2;
+                const int dir = (d & 1) ? +1 : -1;
+                launch_dirac64_face(c->g, links64(c), f, c->xi, nc, mu, dir, c->stream);
+            }
+            launch_little_columns64(c->g, c->Phi, Ns, c->xi, nc, l0, d, c->A64, c->t1, part_cap, c->stream);
+        }
+    }
+    launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);
+    c->eo_ok = false;
+    c->m0_A = mA;
+    int flag[4];
+    HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (flag[0] & 1)
+        fail(DFL_ENONFINITE, "non-finite entries in the start fields");
+    if (flag[0] & 2)
+        fail(DFL_ESINGULAR, "block Gram-Schmidt lost rank: the start fields are linearly dependent on a block");
+    prepare_eo(c);
+    prepare_gdefl(c);
+}
+
+// One bootstrapped inverse-iteration step (section 5.3) on the Ns fields f,
+// with the subspace current in the context (built from f at m0_setup): each
+// field psi becomes P_R chi + Phi A^-1 Phi^+ psi (eq. (3.10)) with chi = M_sap
+// P_L psi, the approximate solution of the deflated equation P_L D chi =
+// P_L psi (eq. (3.11)) after its preconditioner, and is normalised. Little
+// solves to little_tol_in in little_prec; the Schwarz procedure runs on all
+// fields in one launch per sweep.
+void bootstrap_step(dfl_ctx* c, c64* f)
+{
+    const long F = c->field_elems;
+    const int Ns = c->p.Ns;
+    const double m = c->p.m0_setup, tol = c->p.little_tol_in;
+    const dfl_prec lp = c->p.little_prec;
+    // t_l = Phi A^-1 Phi^+ psi_l, and psi_l <- P_L psi_l = psi_l - D t_l
+    for (int l = 0; l < Ns; ++l) {
+        c64* fl = f + (long)l * F;
+        c64* tl = c->bootT + (long)l * F;
+        coarse(c, fl, tl, tol, lp);
+        dirac64_sub(c, fl, tl, c->t1, m);
+        launch_copy<double>(c->t1, fl, F, c->stream);
+    }
+    // chi = M_sap P_L psi for all fields at once
+    {
+        struct SetupSweeps {
+            dfl_ctx* c;
+            explicit SetupSweeps(dfl_ctx* cc) : c(cc) { c->sap_prof_cls = DFL_PROF_SETUP_SAP; }
+            ~SetupSweeps() { c->sap_prof_cls = DFL_PROF_SAP; }
+        } setup_sweeps(c);
+        if (c->p.sap_prec == DFL_F64) {
+            sap_apply(c, f, c->tN, m, Ns);
+            launch_copy<double>(c->tN, f, F * Ns, c->stream);
+        } else {
+            sap_apply(c, f, f, m, Ns);  // FP32 path: staged through s32a/s32b
+        }
+    }
+    // psi_l <- chi_l - Phi A^-1 Phi^+ D chi_l + t_l
+    for (int l = 0; l < Ns; ++l) {
+        c64* fl = f + (long)l * F;
+        dirac64(c, fl, c->t1, m);
+        coarse(c, c->t1, c->t2, tol, lp);
+        launch_sub<double>(fl, c->t2, fl, F, c->stream);
+        launch_add<double>(fl, c->bootT + (long)l * F, fl, F, c->stream);
+    }
+    launch_finite_check<double>(f, F * Ns, c->dflag, c->stream);
+    launch_norm2_b<double>(f, F, Ns, F, c->red, c->dnorm, 2, nullptr, c->stream);
+    launch_scale_invsqrt_b<double>(f, F, Ns, F, c->dnorm, 2, nullptr, c->stream);
 }
 
 }  // namespace
@@ -876,6 +1092,9 @@ void dfl_default_params(dfl_params* p)
     p->little_adapt = 1;
     p->little_eo = 1;
     p->little_gdefl = 1;
+    p->csw = 0.0;
+    p->antiperiodic = 0;
+    p->n_boot = 0;
 }
 
 const char* dfl_last_error(void) { return dfl::g_last_error.c_str(); }
@@ -931,6 +1150,7 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
     c->stream = static_cast<hipStream_t>(hip_stream);
     HIPCHECK(hipGetDevice(&c->device));
     c->g = make_geom(p->dims, p->dfl_block);
+    c->g.tsign = p->antiperiodic ? -1 : 1;
     c->V = c->g.V;
     c->field_elems = 12 * c->V;
     SapGeom& sg = c->sg;
@@ -950,6 +1170,10 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->U64 = alloc_dev<c64>(c, (size_t)24 * V);
         c->U32 = alloc_dev<c32>(c, (size_t)24 * V);
         c->Ubf = alloc_dev<uint32_t>(c, (size_t)24 * V);
+        if (p->csw != 0.0) {
+            c->Cl64 = alloc_dev<c64>(c, (size_t)kCloverComp * V);
+            c->Cl32 = alloc_dev<c32>(c, (size_t)kCloverComp * V);
+        }
         c->Phi = alloc_dev<c64>(c, (size_t)p->Ns * F);
         c->A64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->A32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
@@ -969,6 +1193,8 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
                 c->gQ32 = alloc_dev<c32>(c, (size_t)p->Ns * N);
                 c->gZ32 = alloc_dev<c32>(c, (size_t)p->Ns * N);
                 c->gC = alloc_dev<c64>(c, (size_t)p->Ns * p->Ns);
+                c->gAinv = alloc_dev<double>(c, (size_t)2 * p->Ns * p->Ns);
+                c->gGw = alloc_dev<double>(c, (size_t)2 * p->Ns * p->Ns);
             }
         }
         const long R = p->nrhs_max;
@@ -985,6 +1211,10 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         c->s32c = alloc_dev<c32>(c, F);
         if (p->sap_prec == DFL_F64)
             c->tN = alloc_dev<c64>(c, (size_t)p->Ns * F);
+        if (p->n_boot > 0) {
+            c->bootF = alloc_dev<c64>(c, (size_t)p->Ns * F);
+            c->bootT = alloc_dev<c64>(c, (size_t)p->Ns * F);
+        }
         c->lxi = alloc_dev<c64>(c, (size_t)p->little_nkv * R * N);
         c->lchi = alloc_dev<c64>(c, (size_t)p->little_nkv * R * N);
         c->lr = alloc_dev<c64>(c, R * N);
@@ -1128,6 +1358,10 @@ int dfl_set_gauge(dfl_ctx* c, const double* U)
     sync(c);
     if (flag)
         fail(DFL_EINVAL, "gauge field: every link must be SU(3) (third row = conj(row0 x row1) to 1e-12)");
+    if (c->Cl64) {
+        launch_clover_field(c->g, links64(c), c->p.csw, c->Cl64, c->Cl32, c->stream);
+        HIPCHECK(hipGetLastError());
+    }
     c->have_gauge = true;
     API_END
 }
@@ -1181,13 +1415,13 @@ int dirac_apply(dfl_ctx* c, const void* psi, void* out, int nrhs, dfl_prec prec)
     ProfScope ps(c, DFL_PROF_DIRAC);
     if (prec == DFL_F64)
         launch_dirac64(c->g, links64(c), static_cast<const c64*>(psi), static_cast<c64*>(out), nrhs, c->p.m0, 0, 0,
-                       0, c->stream);
+                       0, c->stream, c->Cl64);
     else if (prec == DFL_F32 && c->p.link_prec == DFL_BF16)
         launch_dirac_bf16(c->g, linksbf(c), static_cast<const c32*>(psi), static_cast<c32*>(out), nrhs,
-                          (float)c->p.m0, c->stream);
+                          (float)c->p.m0, c->stream, c->Cl32);
     else if (prec == DFL_F32)
         launch_dirac32(c->g, links32(c), static_cast<const c32*>(psi), static_cast<c32*>(out), nrhs, (float)c->p.m0,
-                       c->stream);
+                       c->stream, c->Cl32);
     else
         fail(DFL_EINVAL, "dirac_apply precision must be F64 or F32");
     HIPCHECK(hipGetLastError());
@@ -1219,56 +1453,27 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
         fail(DFL_EINVAL, "n_init must equal Ns");
     const long F = c->field_elems;
     const int Ns = c->p.Ns;
+    const int nb = c->p.n_boot;
     // captured GCR steps keep the even-odd and global-deflation state (and
     // the buffers of Q and Z) of the subspace they were recorded with
     sync(c);
     drop_graphs(c);
     c->have_subspace = false;
-    HIPCHECK(hipMemcpyAsync(c->Phi, init, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
+    // the fields are relaxed in Phi itself, or (bootstrapped iteration) kept
+    // apart from the intermediate subspaces built from them
+    c64* fields = nb > 0 ? c->bootF : c->Phi;
+    HIPCHECK(hipMemcpyAsync(fields, init, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
     // inverse iteration, eq. (5.1): psi_l <- M_sap psi_l, normalised; the
     // Schwarz sweeps relax all Ns fields in one launch each
-    inverse_iterate(c, c->Phi, Ns, c->p.n_inviter);
-    // block restriction and Gram-Schmidt, eq. (4.2)
-    ProfScope ps_setup(c, DFL_PROF_SETUP);
-    launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->gsR, c->stream);
-    // little operator, eq. (A.1): block-diagonal part and the eight face
-    // hops, applied to a chunk of basis fields per launch (the Krylov
-    // buffer is free during the setup), then the block products with Phi
-    const long nA = (long)c->g.Nb * 9 * Ns * Ns;
-    // chunk of basis fields per launch: bounded by the Krylov buffer (the
-    // stencil output) and by t1 (the split partial sums, Nb*Ns*chunk entries)
-    const long part_cap = F * c->p.nrhs_max;
-    const int chunk = (int)std::max(1L, std::min({(long)Ns, (long)little_columns_max(Ns),
-                                                  (long)c->p.nkv * c->p.nrhs_max, (long)(128 - Ns),
-                                                  part_cap / ((long)c->g.Nb * Ns)}));
-    for (int l0 = 0; l0 < Ns; l0 += chunk) {
-        const int nc = std::min(chunk, Ns - l0);
-        const c64* f = c->Phi + (long)l0 * F;
-        for (int d = 0; d < 9; ++d) {
-            if (d == 0) {
-                launch_dirac64(c->g, links64(c), f, c->xi, nc, c->p.m0, 1, 0, 0, c->stream);
-            } else {
-                const int mu = (d - 1) / 2;
-                const int dir = (d & 1) ? +1 : -1;
-                launch_dirac64_face(c->g, links64(c), f, c->xi, nc, mu, dir, c->stream);
-            }
-            launch_little_columns64(c->g, c->Phi, Ns, c->xi, nc, l0, d, c->A64, c->t1, part_cap, c->stream);
-        }
+    inverse_iterate(c, fields, Ns, c->p.n_inviter - nb);
+    // bootstrapped steps (section 5.3): the current fields deflate the
+    // approximate solve of the next step
+    for (int b = 0; b < nb; ++b) {
+        build_subspace(c, fields, c->p.m0_setup);
+        bootstrap_step(c, fields);
     }
-    launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);
-    (void)nA;
-    c->eo_ok = false;
-    c->m0_A = c->p.m0;
-    int flag[4];
-    HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
-    sync(c);
-    if (flag[0] & 1)
-        fail(DFL_ENONFINITE, "non-finite entries in the start fields");
-    if (flag[0] & 2)
-        fail(DFL_ESINGULAR, "block Gram-Schmidt lost rank: the start fields are linearly dependent on a block");
-    prepare_eo(c);
-    prepare_gdefl(c);
+    build_subspace(c, fields, c->p.m0);
     c->have_subspace = true;
     API_END
 }

@@ -144,6 +144,7 @@ struct Geom {
     int Vb;       // sites per block
     int Nb;       // number of blocks
     long V;       // sites
+    int tsign;    // quark boundary condition in direction 0: +1 periodic, -1 antiperiodic
 };
 
 __host__ inline Geom make_geom(const int L[4], const int b[4])
@@ -163,6 +164,7 @@ __host__ inline Geom make_geom(const int L[4], const int b[4])
     g.Vb = b[0] * b[1] * b[2] * b[3];
     g.Nb = g.nb[0] * g.nb[1] * g.nb[2] * g.nb[3];
     g.V = (long)g.Vb * g.Nb;
+    g.tsign = 1;
     return g;
 }
 
@@ -207,6 +209,16 @@ __host__ __device__ inline long site_step(const Geom& g, long s, const int n[4],
     }
     long dy = (step > 0) ? -(long)(g.b[mu] - 1) * g.lstr[mu] : (long)(g.b[mu] - 1) * g.lstr[mu];
     return s + (long)dn * g.bstr[mu] * g.Vb + dy;
+}
+
+// whether the hop from a site with block/in-block coordinates (n, y) in
+// direction mu, orientation step, crosses the time boundary x0 = L0-1 <-> 0
+// (where an antiperiodic quark field picks up a factor -1)
+__host__ __device__ inline bool crosses_time(const Geom& g, const int n[4], const int y[4], int mu, int step)
+{
+    if (mu != 0 || g.tsign > 0)
+        return false;
+    return step > 0 ? (n[0] == g.nb[0] - 1 && y[0] == g.b[0] - 1) : (n[0] == 0 && y[0] == 0);
 }
 
 // canonical site index from global coordinates

@@ -840,6 +840,26 @@ __global__ __launch_bounds__(256) void k_gram(const c64* __restrict__ X, long n,
         G[blockIdx.x] = c64{re, im};
 }
 
+// G[k][l] = (X_k, Y_l) for nv vectors each
+__global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ X, const c64* __restrict__ Y, long n, int nv,
+                                               c64* __restrict__ G)
+{
+    __shared__ double sh[16];
+    const int k = blockIdx.x / nv, l = blockIdx.x % nv;
+    const c64* a = X + (long)k * n;
+    const c64* b = Y + (long)l * n;
+    double re = 0.0, im = 0.0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) {
+        const c64 u = a[i], v = b[i];
+        re += u.re * v.re + u.im * v.im;
+        im += u.re * v.im - u.im * v.re;
+    }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (threadIdx.x == 0)
+        G[blockIdx.x] = c64{re, im};
+}
+
 // Y_l = sum_k X_k C[k][l], l < m, for nv vectors of n entries (C complex nv x m, device)
 __global__ void k_combine(const c64* __restrict__ X, long n, int nv, int m, const c64* __restrict__ C,
                           c64* __restrict__ Y)
@@ -999,6 +1019,10 @@ void launch_eo_hop(const Geom& g, const c64* Mt, int Ns, const c64* in, const c6
 void launch_gram(const c64* X, long n, int nv, c64* G, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gram, dim3(nv * nv), dim3(256), 0, s, X, n, nv, G);
+}
+void launch_gram2(const c64* X, const c64* Y, long n, int nv, c64* G, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gram2, dim3(nv * nv), dim3(256), 0, s, X, Y, n, nv, G);
 }
 void launch_combine(const c64* X, long n, int nv, int m, const c64* C, c64* Y, hipStream_t s)
 {

@@ -6,7 +6,10 @@
 // neighbour; they come from L2/MALL, not HBM), and writes one spinor. The
 // workgroup numbering is XCD-aware (common.h): each XCD sweeps a contiguous
 // range of sites so that neighbour reuse stays inside one L2.
+#include <complex>
+
 #include "hop.h"
+
 
 namespace dfl {
 
@@ -36,6 +39,8 @@ __device__ inline void hops_all(const Geom& g, const L& U, const cpx<T>* __restr
             continue;
         long t = site_step(g, s, n, y, mu, step);
         spinor<T> p = load_spinor(f, g.V, t);
+        if (crosses_time(g, n, y, mu, step))
+            negate(p);
         if (step > 0)
             hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
         else
@@ -46,10 +51,11 @@ __device__ inline void hops_all(const Geom& g, const L& U, const cpx<T>* __restr
 // Workgroup id -> (site chunk, right-hand side): XCD k sweeps its contiguous
 // range of chunks, and for each chunk all right-hand sides back to back, so
 // the chunk's links are read from HBM once and from L2 for the other RHS.
-template <int MODE, typename T, typename L>
+template <int MODE, typename T, typename L, bool CLV>
 __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __restrict__ psi,
                                                cpx<T>* __restrict__ out, T diag, int hop_mu, int hop_dir,
-                                               int chunks_padded, int nrhs, const cpx<T>* __restrict__ sub)
+                                               int chunks_padded, int nrhs, const cpx<T>* __restrict__ sub,
+                                               Clover<T> C)
 {
     const int per = chunks_padded / kNumXcd;
     const int local = blockIdx.x / kNumXcd;
@@ -71,7 +77,10 @@ __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __rest
         zero(z);
         o = finish(z, acc, T(0));
     } else {
-        o = finish(load_spinor(f, g.V, s), acc, diag);
+        const spinor<T> self = load_spinor(f, g.V, s);
+        o = finish(self, acc, diag);
+        if constexpr (CLV)
+            clover_add(C, s, self, o);
     }
     if (sub) {
         const spinor<T> a = load_spinor(sub + off, g.V, s);
@@ -87,10 +96,10 @@ __global__ __launch_bounds__(256) void k_dirac(Geom g, L U, const cpx<T>* __rest
 // that stay inside the block read the neighbour from LDS (three quarters of
 // them for 4^4 blocks), the others and all links come from global memory.
 // The output is written with non-temporal stores (it is not re-read here).
-template <typename T, typename L>
-__global__ __launch_bounds__(256) void k_dirac_blk(Geom g, L U, const cpx<T>* __restrict__ psi,
+template <typename T, typename L, bool CLV>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_dirac_blk(Geom g, L U, const cpx<T>* __restrict__ psi,
                                                    cpx<T>* __restrict__ out, T diag, int chunks_padded, int nrhs,
-                                                   const cpx<T>* __restrict__ sub)
+                                                   const cpx<T>* __restrict__ sub, Clover<T> C)
 {
     __shared__ cpx<T> sp[12][256];
     const int per = chunks_padded / kNumXcd;
@@ -127,6 +136,8 @@ __global__ __launch_bounds__(256) void k_dirac_blk(Geom g, L U, const cpx<T>* __
                     p.s[al].c[a] = sp[3 * al + a][tl];
         } else {
             p = load_spinor(f, g.V, t);
+            if (crosses_time(g, n, y, mu, step))
+                negate(p);
         }
         if (step > 0)
             hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
@@ -140,6 +151,8 @@ __global__ __launch_bounds__(256) void k_dirac_blk(Geom g, L U, const cpx<T>* __
         for (int a = 0; a < 3; ++a)
             self.s[al].c[a] = sp[3 * al + a][t0];
     spinor<T> o = finish(self, acc, diag);
+    if constexpr (CLV)
+        clover_add(C, s, self, o);
     if (sub) {
         const spinor<T> a = load_spinor(sub + off, g.V, s);
 #pragma unroll
@@ -190,6 +203,8 @@ __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* _
     if (g.nb[mu] > 1) {
         const long t = site_step(g, s, n, y, mu, dir);
         spinor<T> p = load_spinor(psi + off, g.V, t);
+        if (crosses_time(g, n, y, mu, dir))
+            negate(p);
         if (dir > 0)
             hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
         else
@@ -200,40 +215,53 @@ __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* _
     store_spinor(out + off, g.V, s, finish(z, acc, T(0)));
 }
 
-// sub (MODE 0, may be null): out = sub - D psi
+// sub (MODE 0, may be null): out = sub - D psi; clov (may be null): the
+// clover term, added in modes 0 and 1
+template <typename X> struct same {
+    using type = X;
+};
 template <int MODE, typename T, typename L>
 void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, int mu, int dir, hipStream_t s,
-            const cpx<T>* sub = nullptr)
+            const typename same<cpx<T>>::type* sub, const typename same<cpx<T>>::type* clov)
 {
+    const Clover<T> C{MODE == 2 ? nullptr : clov};
     if (MODE == 0 && g.Vb == 256) {
         const int gp = pad_grid(g.Nb);
-        hipLaunchKernelGGL((k_dirac_blk<T, L>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, gp,
-                           nrhs, sub);
+        if (C.c)
+            hipLaunchKernelGGL((k_dirac_blk<T, L, true>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out,
+                               T(4) + m0, gp, nrhs, sub, C);
+        else
+            hipLaunchKernelGGL((k_dirac_blk<T, L, false>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out,
+                               T(4) + m0, gp, nrhs, sub, C);
         return;
     }
     long nwg = (g.V + 255) / 256;
     int gp = pad_grid(nwg);
-    hipLaunchKernelGGL((k_dirac<MODE, T, L>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0, mu, dir,
-                       gp, nrhs, MODE == 0 ? sub : nullptr);
+    if (MODE != 2 && C.c)
+        hipLaunchKernelGGL((k_dirac<MODE, T, L, true>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out, T(4) + m0,
+                           mu, dir, gp, nrhs, MODE == 0 ? sub : nullptr, C);
+    else
+        hipLaunchKernelGGL((k_dirac<MODE, T, L, false>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi, out,
+                           T(4) + m0, mu, dir, gp, nrhs, MODE == 0 ? sub : nullptr, C);
 }
 
 }  // namespace
 
 void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, double m0, int mode, int mu,
-                    int dir, hipStream_t s)
+                    int dir, hipStream_t s, const c64* clov)
 {
     if (mode == 0)
-        launch<0>(g, U, psi, out, nrhs, m0, mu, dir, s);
+        launch<0>(g, U, psi, out, nrhs, m0, mu, dir, s, nullptr, clov);
     else if (mode == 1)
-        launch<1>(g, U, psi, out, nrhs, m0, mu, dir, s);
+        launch<1>(g, U, psi, out, nrhs, m0, mu, dir, s, nullptr, clov);
     else
-        launch<2>(g, U, psi, out, nrhs, m0, mu, dir, s);
+        launch<2>(g, U, psi, out, nrhs, m0, mu, dir, s, nullptr, nullptr);
 }
 
 void launch_dirac64_sub(const Geom& g, Links64 U, const c64* sub, const c64* psi, c64* out, int nrhs, double m0,
-                        hipStream_t s)
+                        hipStream_t s, const c64* clov)
 {
-    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s, sub);
+    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s, sub, clov);
 }
 
 void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s)
@@ -244,14 +272,196 @@ void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int
                        U, psi, out, mu, dir, nface);
 }
 
-void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s)
+void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,
+                    const c32* clov)
 {
-    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s);
+    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s, nullptr, clov);
 }
 
-void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s)
+void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,
+                       const c32* clov)
 {
-    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s);
+    launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s, nullptr, clov);
+}
+
+}  // namespace dfl
+
+// ------------------------------------------------------------ clover term
+
+namespace dfl {
+
+namespace {
+
+// sigma_{mu nu} restricted to one chirality (2 x 2), for the six planes mu < nu
+struct SigmaBlocks {
+    c64 s[6][2][2][2];  // [plane][chirality][row][col]
+};
+
+__device__ inline su3<double> mat_mul(const su3<double>& a, const su3<double>& b)
+{
+    su3<double> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            c.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
+    return c;
+}
+
+__device__ inline su3<double> dag(const su3<double>& a)
+{
+    su3<double> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            c.m[i][j] = conjg(a.m[j][i]);
+    return c;
+}
+
+// native index of the site x + step * mu
+__device__ inline long shifted(const Geom& g, long s, int mu, int step)
+{
+    int n[4], y[4];
+    site_decompose(g, s, n, y);
+    return site_step(g, s, n, y, mu, step);
+}
+
+// Fhat_{mu nu}(x) = (Q - Q^+) / 8, Q = sum of the four plaquette leaves in
+// the (mu, nu) plane that start and end at x (counter-clockwise from the
+// mu direction)
+__device__ inline su3<double> field_tensor(const Geom& g, const Links64& U, long x, int mu, int nu)
+{
+    const long xpm = shifted(g, x, mu, +1), xpn = shifted(g, x, nu, +1);
+    const long xmm = shifted(g, x, mu, -1), xmn = shifted(g, x, nu, -1);
+    const long xmm_pn = shifted(g, xmm, nu, +1), xmm_mn = shifted(g, xmm, nu, -1);
+    const long xmn_pm = shifted(g, xmn, mu, +1);
+    su3<double> Q = mat_mul(mat_mul(load_link(U, mu, x), load_link(U, nu, xpm)),
+                            mat_mul(dag(load_link(U, mu, xpn)), dag(load_link(U, nu, x))));
+    su3<double> l = mat_mul(mat_mul(load_link(U, nu, x), dag(load_link(U, mu, xmm_pn))),
+                            mat_mul(dag(load_link(U, nu, xmm)), load_link(U, mu, xmm)));
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Q.m[i][j] += l.m[i][j];
+    l = mat_mul(mat_mul(dag(load_link(U, mu, xmm)), dag(load_link(U, nu, xmm_mn))),
+                mat_mul(load_link(U, mu, xmm_mn), load_link(U, nu, xmn)));
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Q.m[i][j] += l.m[i][j];
+    l = mat_mul(mat_mul(dag(load_link(U, nu, xmn)), load_link(U, mu, xmn)),
+                mat_mul(load_link(U, nu, xmn_pm), dag(load_link(U, mu, x))));
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Q.m[i][j] += l.m[i][j];
+    su3<double> F;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const c64 a = Q.m[i][j], b = conjg(Q.m[j][i]);
+            F.m[i][j] = c64{0.125 * (a.re - b.re), 0.125 * (a.im - b.im)};
+        }
+    return F;
+}
+
+// One thread per site: C_h = csw (i/2) sum_{mu < nu} sigma^h_{mu nu} (x) Fhat_{mu nu}
+// for both chiralities h, written in the packed hermitian form of hop.h.
+__global__ __launch_bounds__(256) void k_clover_field(Geom g, Links64 U, double csw, SigmaBlocks sig,
+                                                      c64* __restrict__ C64, c32* __restrict__ C32)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V)
+        return;
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        // one chirality at a time (Fhat is recomputed for the second): the
+        // 6 x 6 block stays in registers
+        c64 C[6][6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                C[i][j] = c64{0.0, 0.0};
+        int plane = 0;
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll 1
+            for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
+                const su3<double> F = field_tensor(g, U, s, mu, nu);
+#pragma unroll
+                for (int al = 0; al < 2; ++al)
+#pragma unroll
+                    for (int be = 0; be < 2; ++be) {
+                        // csw (i/2) sigma_{al be}
+                        const c64 sg = sig.s[plane][h][al][be];
+                        const c64 f = c64{-0.5 * csw * sg.im, 0.5 * csw * sg.re};
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+#pragma unroll
+                            for (int b = 0; b < 3; ++b)
+                                C[3 * al + a][3 * be + b] += f * F.m[a][b];
+                    }
+            }
+        c64 e[18];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            e[q] = c64{C[2 * q][2 * q].re, C[2 * q + 1][2 * q + 1].re};
+        int q = 3;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j, ++q)
+                e[q] = C[i][j];
+#pragma unroll
+        for (int q2 = 0; q2 < 18; ++q2) {
+            st(C64, toff<c64>(s, 18 * h + q2, kCloverComp), e[q2]);
+            if (C32)
+                st(C32, toff<c32>(s, 18 * h + q2, kCloverComp), c32{(float)e[q2].re, (float)e[q2].im});
+        }
+    }
+}
+
+}  // namespace
+
+void launch_clover_field(const Geom& g, Links64 U, double csw, c64* C64, c32* C32, hipStream_t s)
+{
+    // sigma_{mu nu} = (i/2) [g_mu, g_nu] is block diagonal in the chiral basis:
+    // (i/2)(e_mu e_nu^+ - e_nu e_mu^+) on spins 0, 1 and
+    // (i/2)(e_mu^+ e_nu - e_nu^+ e_mu) on spins 2, 3
+    using cd = std::complex<double>;
+    const cd I(0.0, 1.0);
+    cd e[4][2][2] = {{{-1.0, 0.0}, {0.0, -1.0}},
+                     {{0.0, -I}, {-I, 0.0}},
+                     {{0.0, -1.0}, {1.0, 0.0}},
+                     {{-I, 0.0}, {0.0, I}}};
+    auto prod = [&](int a, bool da, int b, bool db, int i, int j) {
+        cd t = 0.0;
+        for (int k = 0; k < 2; ++k) {
+            cd x = da ? std::conj(e[a][k][i]) : e[a][i][k];
+            cd y = db ? std::conj(e[b][j][k]) : e[b][k][j];
+            t += x * y;
+        }
+        return t;
+    };
+    SigmaBlocks sig;
+    int plane = 0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu, ++plane)
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    cd up = 0.5 * I * (prod(mu, false, nu, true, i, j) - prod(nu, false, mu, true, i, j));
+                    cd lo = 0.5 * I * (prod(mu, true, nu, false, i, j) - prod(nu, true, mu, false, i, j));
+                    sig.s[plane][0][i][j] = c64{up.real(), up.imag()};
+                    sig.s[plane][1][i][j] = c64{lo.real(), lo.imag()};
+                }
+    const unsigned nwg = (unsigned)((g.V + 255) / 256);
+    hipLaunchKernelGGL(k_clover_field, dim3(nwg), dim3(256), 0, s, g, U, csw, sig, C64, C32);
 }
 
 }  // namespace dfl

@@ -136,9 +136,11 @@ __device__ inline void hop_fwd(const su3<T>& u, const spinor<T>& p, spinor<T>& a
     }
 }
 
-// acc += (1 + g_mu) U^+ psi_bwd   (u is the link U_mu(x - mu))
+// The backward hop in two halves: the spin-projected colour vectors
+// v = U^+ k of (1 + g_mu) U^+ psi_bwd, and their reconstruction into the four
+// spin components (bwd_add).
 template <int MU, typename T>
-__device__ inline void hop_bwd(const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+__device__ inline void bwd_project(const su3<T>& u, const spinor<T>& p, cvec3<T>& v0, cvec3<T>& v1)
 {
     cvec3<T> k0, k1;
     if (MU == 0) {
@@ -154,8 +156,12 @@ __device__ inline void hop_bwd(const su3<T>& u, const spinor<T>& p, spinor<T>& a
         k0 = p.s[0] + vmi(p.s[2]);
         k1 = p.s[1] + vi(p.s[3]);
     }
-    cvec3<T> v0 = mul_dag(u, k0);
-    cvec3<T> v1 = mul_dag(u, k1);
+    v0 = mul_dag(u, k0);
+    v1 = mul_dag(u, k1);
+}
+
+template <int MU, typename T> __device__ inline void bwd_add(const cvec3<T>& v0, const cvec3<T>& v1, spinor<T>& acc)
+{
     acc.s[0] += v0;
     acc.s[1] += v1;
     if (MU == 0) {
@@ -171,6 +177,15 @@ __device__ inline void hop_bwd(const su3<T>& u, const spinor<T>& p, spinor<T>& a
         acc.s[2] += vi(v0);
         acc.s[3] += vmi(v1);
     }
+}
+
+// acc += (1 + g_mu) U^+ psi_bwd   (u is the link U_mu(x - mu))
+template <int MU, typename T>
+__device__ inline void hop_bwd(const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+{
+    cvec3<T> v0, v1;
+    bwd_project<MU>(u, p, v0, v1);
+    bwd_add<MU>(v0, v1, acc);
 }
 
 // runtime-direction forms (uniform branch on mu)
@@ -192,6 +207,57 @@ __device__ inline void hop_bwd_rt(int mu, const su3<T>& u, const spinor<T>& p, s
     case 1: hop_bwd<1>(u, p, acc); break;
     case 2: hop_bwd<2>(u, p, acc); break;
     default: hop_bwd<3>(u, p, acc); break;
+    }
+}
+
+// -p (the neighbour of a hop across the time boundary of an antiperiodic field)
+template <typename T> __device__ inline void negate(spinor<T>& p)
+{
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+        p.s[al] = cvec3<T>{{-p.s[al].c[0], -p.s[al].c[1], -p.s[al].c[2]}};
+}
+
+// The clover term of the O(a)-improved operator (section 2.1): per site a
+// hermitian 12 x 12 matrix that commutes with gamma_5, i.e. two hermitian
+// 6 x 6 blocks, one per chirality (spins 0, 1 and spins 2, 3; index
+// 3 * (spin % 2) + colour inside a block). Each block is stored as 18 complex
+// entries: slots 0..2 hold the six real diagonal entries as (d0, d1), (d2, d3),
+// (d4, d5), slots 3..17 the entries (i, j), i < j, row by row. 36 entries per
+// site in the 64-site tiling (kCloverComp). c == nullptr: no clover term.
+template <typename T> struct Clover {
+    const cpx<T>* c;
+};
+
+// o += C(x) p for site s
+template <typename T> __device__ inline void clover_add(const Clover<T>& C, long s, const spinor<T>& p, spinor<T>& o)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cpx<T> e[18];
+#pragma unroll
+        for (int q = 0; q < 18; ++q)
+            e[q] = ld(C.c, toff<cpx<T>>(s, 18 * h + q, kCloverComp));
+        cpx<T> v[6], w[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            v[i] = p.s[2 * h + i / 3].c[i % 3];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const T d = (i & 1) ? e[i / 2].im : e[i / 2].re;
+            w[i] = cpx<T>{d * v[i].re, d * v[i].im};
+        }
+        int q = 3;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j, ++q) {
+                w[i] += e[q] * v[j];               // C_ij v_j
+                w[j] += cmul_conj(e[q], v[i]);     // C_ji v_i = conj(C_ij) v_i
+            }
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            o.s[2 * h + i / 3].c[i % 3] += w[i];
     }
 }
 

@@ -62,9 +62,10 @@ constexpr int kRedBlocks = 480;   // fixed grid of the partial-sum kernels (dete
 constexpr int kRedThreads = 256;
 constexpr int kMaxDot = 64;       // most vectors in one multi-dot
 constexpr int kMaxLittleNkv = 32; // most Krylov vectors of the little GCR
-constexpr int kLittleMaxGrid = 128;  // workgroups of the cooperative little GCR
+constexpr int kLittleMaxGrid = 256;  // workgroups of the cooperative little GCR (one per CU)
 constexpr int kMaxLittleRhs = 16;    // right-hand sides of one batched little solve
 constexpr int kMaxLittleDefl = 32;   // global deflation directions of the little system
+constexpr int kCloverComp = 36;         // complex entries of the clover term per site (two packed 6 x 6 blocks)
 constexpr int kLittleMaxGridMulti = 256;  // workgroups of the batched little GCR (one per CU)
 
 }  // namespace dfl
@@ -82,6 +83,8 @@ struct dfl_ctx {
     dfl::c64* U64 = nullptr;
     dfl::c32* U32 = nullptr;
     uint32_t* Ubf = nullptr;
+    dfl::c64* Cl64 = nullptr;  // clover term (csw != 0), FP64 and FP32, 36 complex per site
+    dfl::c32* Cl32 = nullptr;
     bool have_gauge = false;
 
     // deflation subspace
@@ -102,7 +105,10 @@ struct dfl_ctx {
     dfl::c32* gQ32 = nullptr;
     dfl::c32* gZ32 = nullptr;
     dfl::c64* gC = nullptr;    // Ns x Ns scratch (Gram matrix, transform)
+    double* gAinv = nullptr;   // oblique form: (Z^+ A_hat Z)^-1 and W^+ W, Ns x Ns complex each
+    double* gGw = nullptr;
     int gdefl_n = 0;           // deflation directions in use (0: none)
+    bool gdefl_oblique = false;
     double m0_A = 0.0;
     bool have_subspace = false;
 
@@ -119,6 +125,8 @@ struct dfl_ctx {
     dfl::c32* s32b = nullptr;
     dfl::c32* s32c = nullptr;
     dfl::c64* tN = nullptr;    // Ns FP64 fields: FP64 inverse-iteration output
+    dfl::c64* bootF = nullptr; // bootstrapped inverse iteration: the Ns fields and
+    dfl::c64* bootT = nullptr; //   their coarse parts Phi A^-1 Phi^+ psi
     // little-system workspaces (max(FP64) size; reused for FP32)
     void* lxi = nullptr;
     void* lchi = nullptr;
@@ -191,27 +199,37 @@ void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s);
 // out = D psi (nrhs fields, each 12 V). mode 0: full D; 1: block-diagonal part
 // (hops leaving a layout block dropped); 2: block-crossing hop in direction
 // mu, orientation dir (no mass term).
+// clov (may be null): the clover term (36 complex per site, see hop.h), in modes 0 and 1
 void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, double m0,
-                    int mode, int mu, int dir, hipStream_t s);
+                    int mode, int mu, int dir, hipStream_t s, const c64* clov);
 // out = sub - D psi (full operator, FP64) for nrhs fields; out aliases neither sub nor psi
 void launch_dirac64_sub(const Geom& g, Links64 U, const c64* sub, const c64* psi, c64* out, int nrhs, double m0,
-                        hipStream_t s);
+                        hipStream_t s, const c64* clov);
 // MODE 2 on the face sites only (other sites of out untouched)
 void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s);
-void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s);
-void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s);
+void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,
+                    const c32* clov);
+void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,
+                       const c32* clov);
+// clover term of the O(a)-improved operator from the FP64 links: csw (i/4)
+// sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x), stored per chirality block (hop.h)
+// in FP64 (C64) and FP32 (C32, may be null)
+void launch_clover_field(const Geom& g, Links64 U, double csw, c64* C64, c32* C32, hipStream_t s);
 
 // ------------------------------------------------------------------- sap.hip
 // one colour sweep for nrhs fields (each 12 V entries, back to back)
 // init: 0 = general psi, 1 = psi zero on the sweep's own blocks, 2 = psi
 // zero everywhere (the two sweeps of the first cycle); out64 (FP32 sweeps,
 // may be null): the blocks' new psi also written there in FP64
+// clov (may be null): the clover term in the sweep's precision
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi,
-                         double m0, int nmr, int colour, int nrhs, int init, hipStream_t s);
+                         double m0, int nmr, int colour, int nrhs, int init, hipStream_t s, const c64* clov);
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi,
-                         float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s);
+                         float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s,
+                         const c32* clov);
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi,
-                            float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s);
+                            float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s,
+                            const c32* clov);
 
 // ------------------------------------------------------------------ blas.hip
 template <typename T> void launch_zero(cpx<T>* x, long n, hipStream_t s);
@@ -280,6 +298,8 @@ void launch_eo_hop(const Geom& g, const c64* Mt, int Ns, const c64* in, const c6
                    double alpha, double beta, hipStream_t s);
 // G[k][l] = (X_k, X_l); Y_l = sum_k X_k C[k][l] for l < m (C is nv x m)
 void launch_gram(const c64* X, long n, int nv, c64* G, hipStream_t s);
+// G[k][l] = (X_k, Y_l) for k, l < nv
+void launch_gram2(const c64* X, const c64* Y, long n, int nv, c64* G, hipStream_t s);
 void launch_combine(const c64* X, long n, int nv, int m, const c64* C, c64* Y, hipStream_t s);
 // A[blk][d][k][l0 + j] = (Phi_k, Y_j) over each block for k < Ns, j < nc
 // (nc <= little_columns_max(Ns), nc + Ns <= 128); part: scratch of part_cap
@@ -349,10 +369,13 @@ bool little_eo_fits(const Geom& g, int grid);
 // the grid (at most kLittleMaxGrid workgroups, one per compute unit) is then
 // resident by construction when nothing else runs on the device, and the
 // barriers' bounded polling reports a failure rather than hang otherwise.
+// oblique = 1: section 3's projectors on the even-odd system instead (Q holds
+// W = A_hat Z, Z orthonormal, Ainv = (Z^+ W)^-1 and Gw = W^+ W, nq x nq
+// complex row-major on the device).
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev,
                        const cpx<T>* At, const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* Q, const cpx<T>* Z,
-                       int nq, const cpx<T>* w,
+                       int nq, int oblique, const double* Ainv, const double* Gw, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                        unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative = true);
 

@@ -40,8 +40,8 @@ constexpr int SB = 2 * NK + 2 + NQ;   // second pass, same layout
 constexpr int SC = 2 * SB;            // ||r||^2 inside a cycle
 constexpr int SR = SC + 1;            // ||r||^2 after a restart
 constexpr int SW = SC + 2;            // ||w||^2
-constexpr int SQ = SC + 3;            // (Q_l, r) at the start and after a restart
-constexpr int NSLOT = SQ + NQ;
+constexpr int SQ = SC + 3;            // (Q_l, r), or (Z_l, r) then (W_l, r), at the start and after a restart
+constexpr int NSLOT = SQ + 2 * NQ;
 static_assert(NK + NQ <= 64, "the coefficient step gives each projection one lane of a wavefront");
 
 template <typename T> struct LittleArgs {
@@ -58,9 +58,13 @@ template <typename T> struct LittleArgs {
     cpx<T>* chi;           // nkv * N
     cpx<T>* w1;            // even-odd workspaces (N each)
     cpx<T>* w2;
-    const cpx<T>* Q;       // global deflation (appendix A.3): nq orthonormal images Q = A_hat Z
-    const cpx<T>* Z;       //   and their preimages, little vectors (even blocks)
+    const cpx<T>* Q;       // global deflation (appendix A.3), minimal-residual form: nq orthonormal
+    const cpx<T>* Z;       //   images Q = A_hat Z and their preimages Z, little vectors (even blocks);
+                           //   oblique form: Q holds W = A_hat Z, Z is orthonormal
     int nq;
+    int oblique;           // 1: the oblique projectors of section 3 on the even-odd system, with
+    const double* Ainv;    //   Ainv = (Z^+ W)^-1 (nq x nq complex, row-major) and
+    const double* Gw;      //   Gw = W^+ W (nq x nq complex)
     double* part;          // NSLOT * G complex partial sums
     int* stats;            // [0] += iterations, [1] += solves, [2] |= 1 not converged, |= 4 barrier timeout
     unsigned* bar_count;   // grid barrier: arrivals (0 between barriers)
@@ -213,7 +217,10 @@ __device__ inline void reduce_slots(const double* __restrict__ part, int G, int 
 // (block, d, k) forms one term of row k (Ns multiply-adds over l, reading Mat
 // coalesced in k); the terms of a row are summed from LDS in a fixed order.
 // Blocks are processed LT1 / ((d1 - d0) Ns) at a time; lds holds 2 LT1 doubles.
-constexpr int kApplyChunk = 10;
+#ifndef DFL_LITTLE_APPLY_CHUNK
+#define DFL_LITTLE_APPLY_CHUNK 10
+#endif
+constexpr int kApplyChunk = DFL_LITTLE_APPLY_CHUNK;
 template <typename T>
 __device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int nlist, const cpx<T>* __restrict__ Mat,
                                     int d0, int d1, const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ s,
@@ -306,11 +313,11 @@ __device__ inline void partial_norm2(const LittleCtx<T>& c, const cpx<T>* __rest
 // part[slot0 ...][g].
 template <typename T>
 __device__ inline void partial_pass(const LittleCtx<T>& c, const cpx<T>* chi, int k, const cpx<T>* __restrict__ y,
-                                    const cpx<T>* __restrict__ r, int slot0)
+                                    const cpx<T>* __restrict__ r, int slot0, int nqg)
 {
     constexpr int NW = LT1 / 64;
     const int lane = c.t & 63, w = c.t >> 6;
-    const int ns = 2 * k + 2 + c.a.nq;
+    const int ns = 2 * k + 2 + nqg;
     const int R = c.R();
     // kSlotUnroll slots per wavefront at a time, their loads in flight together
     for (int sb = w; sb < ns; sb += NW * kSlotUnroll) {
@@ -368,8 +375,12 @@ __device__ inline void partial_norm2_q(const LittleCtx<T>& c, const cpx<T>* __re
 {
     const int lane = c.t & 63, w = c.t >> 6;
     const int R = c.R();
-    for (int s = w; s < 1 + c.a.nq; s += LT1 / 64) {
-        const cpx<T>* u = s == 0 ? v : c.a.Q + (long)(s - 1) * c.N;
+    // minimal-residual form: (Q_l, v); oblique form: (Z_l, v) and (W_l, v)
+    const int nd = c.a.oblique ? 2 * c.a.nq : c.a.nq;
+    for (int s = w; s < 1 + nd; s += LT1 / 64) {
+        const cpx<T>* u = s == 0 ? v
+                          : (c.a.oblique && s <= c.a.nq) ? c.a.Z + (long)(s - 1) * c.N
+                                                          : c.a.Q + (long)((s - 1) % c.a.nq) * c.N;
         double2 acc = make_double2(0.0, 0.0);
         for (int e = lane; e < R; e += 64) {
             long i = c.entry(e);
@@ -379,9 +390,32 @@ __device__ inline void partial_norm2_q(const LittleCtx<T>& c, const cpx<T>* __re
         acc.x = wave_sum(acc.x);
         acc.y = wave_sum(acc.y);
         if (lane == 0) {
-            const int slot = s == 0 ? sn : SQ + s - 1;
+            const int slot = s == 0 ? sn : SQ + s - 1;  // (W_l, v) follow the nq (Z_l, v)
             c.a.part[((long)slot * c.G + c.g) * 2] = acc.x;
             c.a.part[((long)slot * c.G + c.g) * 2 + 1] = acc.y;
+        }
+    }
+}
+
+// (Z_l, y), l < nq, into slots SQ + l (oblique deflation of a new Krylov image)
+template <typename T>
+__device__ inline void partial_zdots(const LittleCtx<T>& c, const cpx<T>* __restrict__ y)
+{
+    const int lane = c.t & 63, w = c.t >> 6;
+    const int R = c.R();
+    for (int s = w; s < c.a.nq; s += LT1 / 64) {
+        const cpx<T>* u = c.a.Z + (long)s * c.N;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int e = lane; e < R; e += 64) {
+            long i = c.entry(e);
+            cpx<T> p = u[i], q = y[i];
+            acc = cfma_conj(acc, (double)p.re, (double)p.im, (double)q.re, (double)q.im);
+        }
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
+        if (lane == 0) {
+            c.a.part[((long)(SQ + s) * c.G + c.g) * 2] = acc.x;
+            c.a.part[((long)(SQ + s) * c.G + c.g) * 2 + 1] = acc.y;
         }
     }
 }
@@ -460,6 +494,8 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
     __shared__ double acoef[NK][NK][2];
     __shared__ double qcoef[NQ][NK][2];  // components of each direction's image along Q
     __shared__ double zc[NQ][2];
+    __shared__ double cq_s[NQ][2];       // coefficients of the current projection along W (or Q) and Z
+    __shared__ double pn2_s;             // ||r||^2 after a projection
     __shared__ double bcoef[NK];
     __shared__ double ccoef[NK][2];
     __shared__ double alpha[NK][2];
@@ -516,9 +552,56 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
     }
 
     const int nq = a.nq;
-    // r -= Q c, x += Z c with c = red[0..2nq) (the residue leaves span Q: global deflation)
+    const bool obl = a.oblique && nq > 0;
+    const int nqg = obl ? 0 : nq;  // deflation directions inside the Gram-Schmidt pass (minimal-residual form)
+    // Coefficients of the projection of a vector v whose dots sit in red
+    // ((Q_l, v) or (Z_l, v) at 0.., (W_l, v) at 2 nq.. in the oblique form):
+    // c = (Q_l, v) (Q orthonormal), or c = Ainv Z^+ v (section 3's P_L on the
+    // even-odd system, Ainv the inverse of the little little operator Z^+ A_hat Z).
+    // Returns ||v - Q c||^2 given ||v||^2 (thread 0's value is authoritative).
+    auto proj_coef = [&](double vn2) {
+        if (c.t < nq) {
+            double cr = red[2 * c.t], ci = red[2 * c.t + 1];
+            if (obl) {
+                cr = 0.0;
+                ci = 0.0;
+                for (int m = 0; m < nq; ++m) {
+                    const double ar = a.Ainv[2 * (c.t * nq + m)], ai = a.Ainv[2 * (c.t * nq + m) + 1];
+                    cr += ar * red[2 * m] - ai * red[2 * m + 1];
+                    ci += ar * red[2 * m + 1] + ai * red[2 * m];
+                }
+            }
+            cq_s[c.t][0] = cr;
+            cq_s[c.t][1] = ci;
+        }
+        __syncthreads();
+        double rn = vn2;
+        if (c.t == 0) {
+            if (!obl) {
+                for (int l = 0; l < nq; ++l)
+                    rn -= cq_s[l][0] * cq_s[l][0] + cq_s[l][1] * cq_s[l][1];
+            } else {
+                // ||v - W c||^2 = ||v||^2 - 2 Re sum conj(c_l) (W_l, v) + c^+ Gw c
+                for (int l = 0; l < nq; ++l) {
+                    const double cr = cq_s[l][0], ci = cq_s[l][1];
+                    const double wr = red[2 * (nq + l)], wi = red[2 * (nq + l) + 1];
+                    rn -= 2.0 * (cr * wr + ci * wi);
+                    for (int m = 0; m < nq; ++m) {
+                        const double gr = a.Gw[2 * (l * nq + m)], gi = a.Gw[2 * (l * nq + m) + 1];
+                        const double dr = cq_s[m][0], di = cq_s[m][1];
+                        // conj(c_l) G_lm c_m
+                        const double tr = gr * dr - gi * di, ti = gr * di + gi * dr;
+                        rn += cr * tr + ci * ti;
+                    }
+                }
+            }
+        }
+        return rn;
+    };
+    // r -= Q c (or W c), x += Z c with c = cq_s: the residue leaves span Q (minimal-residual
+    // form) or range(A_hat Z) along the oblique projector (section 3)
     auto project_q = [&]() {
-        auto cq = [&](int l) { return make_double2(red[2 * l], red[2 * l + 1]); };
+        auto cq = [&](int l) { return make_double2(cq_s[l][0], cq_s[l][1]); };
         combine_terms(c, nq, cq, [&](int l) { return a.Q + (long)l * N; }, lds, [&](int, long i, double sr, double si) {
             a.r[i] = cpx<T>{(T)((double)a.r[i].re - sr), (T)((double)a.r[i].im - si)};
         });
@@ -540,11 +623,10 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
         wn2_s = red[0];
     __syncthreads();
     const double wn2 = wn2_s;
-    double rn2_0 = wn2;  // ||r||^2 after the projection below (Q orthonormal)
+    double rn2_0 = wn2;  // ||r||^2 after the projection below (thread 0)
     if (nq > 0) {
-        reduce_slots(a.part, c.G, SQ, nq, red);
-        for (int l = 0; l < nq; ++l)
-            rn2_0 -= red[2 * l] * red[2 * l] + red[2 * l + 1] * red[2 * l + 1];
+        reduce_slots(a.part, c.G, SQ, obl ? 2 * nq : nq, red);
+        rn2_0 = proj_coef(wn2);
         project_q();
     }
     if (c.t == 0)
@@ -598,20 +680,38 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                 }
             }
             op(xk, ck);
+            if (obl) {
+                // oblique form: chi_k = P_L A_hat xi_k = A_hat xi_k - W Ainv Z^+ A_hat xi_k
+                // before the Gram-Schmidt pass (one more reduction); the
+                // preimage of chi_k is xi_k - Z c_k
+                __syncthreads();
+                partial_zdots(c, ck);
+                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+                reduce_slots(a.part, c.G, SQ, nq, red);
+                proj_coef(0.0);
+                if (c.t < nq) {
+                    qcoef[c.t][k][0] = cq_s[c.t][0];
+                    qcoef[c.t][k][1] = cq_s[c.t][1];
+                }
+                combine_terms(c, nq, [&](int l) { return make_double2(cq_s[l][0], cq_s[l][1]); },
+                              [&](int l) { return a.Q + (long)l * N; }, lds, [&](int, long i, double sr, double si) {
+                                  ck[i] = cpx<T>{(T)((double)ck[i].re - sr), (T)((double)ck[i].im - si)};
+                              });
+            }
             // one Gram-Schmidt pass: everything needed for chi_k, c_k and the new r
-            partial_pass(c, a.chi, k, ck, a.r, SA);
+            partial_pass(c, a.chi, k, ck, a.r, SA, nqg);
             grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
-            reduce_slots(a.part, c.G, SA, 2 * k + 2 + nq, red);
+            reduce_slots(a.part, c.G, SA, 2 * k + 2 + nqg, red);
             // red: [0,k) a_j; [k,2k) (chi_j, r); 2k: ||chi_k||^2; 2k+1: (chi_k, r); [2k+2, 2k+2+nq) (Q_l, chi_k)
             const int q0 = 2 * k + 2;
             // the k + nq <= 64 projections are spread over the lanes of wavefront 0
             if (c.t < 64) {
                 const int ri = c.t < k ? 2 * c.t : 2 * (q0 + c.t - k);
-                const double m2 = c.t < k + nq ? red[ri] * red[ri] + red[ri + 1] * red[ri + 1] : 0.0;
+                const double m2 = c.t < k + nqg ? red[ri] * red[ri] + red[ri + 1] * red[ri + 1] : 0.0;
                 const double p2 = wave_sum(m2);
                 if (c.t == 0) {
                     const double n2 = red[4 * k];
-                    second_s = ((k > 0 || nq > 0) && !(n2 - p2 >= 0.01 * n2)) ? 1 : 0;
+                    second_s = ((k > 0 || nqg > 0) && !(n2 - p2 >= 0.01 * n2)) ? 1 : 0;
                 }
             }
             __syncthreads();
@@ -626,7 +726,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                         yr -= red[2 * j] * (double)z.re - red[2 * j + 1] * (double)z.im;
                         yi -= red[2 * j] * (double)z.im + red[2 * j + 1] * (double)z.re;
                     }
-                    for (int l = 0; l < nq; ++l) {
+                    for (int l = 0; l < nqg; ++l) {
                         const double qr = red[2 * (q0 + l)], qi = red[2 * (q0 + l) + 1];
                         const cpx<T> z = a.Q[(long)l * N + i];
                         yr -= qr * (double)z.re - qi * (double)z.im;
@@ -638,20 +738,20 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                     acoef[c.t][k][0] = red[2 * c.t];
                     acoef[c.t][k][1] = red[2 * c.t + 1];
                 }
-                if (c.t < nq) {
+                if (c.t < nqg) {
                     qcoef[c.t][k][0] = red[2 * (q0 + c.t)];
                     qcoef[c.t][k][1] = red[2 * (q0 + c.t) + 1];
                 }
                 __syncthreads();
-                partial_pass(c, a.chi, k, ck, a.r, SB);
+                partial_pass(c, a.chi, k, ck, a.r, SB, nqg);
                 grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S3
-                reduce_slots(a.part, c.G, SB, 2 * k + 2 + nq, red);
+                reduce_slots(a.part, c.G, SB, 2 * k + 2 + nqg, red);
             } else {
                 if (c.t < k) {
                     acoef[c.t][k][0] = 0.0;
                     acoef[c.t][k][1] = 0.0;
                 }
-                if (c.t < nq) {
+                if (c.t < nqg) {
                     qcoef[c.t][k][0] = 0.0;
                     qcoef[c.t][k][1] = 0.0;
                 }
@@ -670,7 +770,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                     di = ar * qi - ai * qr;
                     acoef[j][k][0] += ar;
                     acoef[j][k][1] += ai;
-                } else if (c.t < k + nq) {
+                } else if (c.t < k + nqg) {
                     const int l = c.t - k;
                     const double qr = red[2 * (q0 + l)], qi = red[2 * (q0 + l) + 1];
                     m2 = qr * qr + qi * qi;
@@ -700,7 +800,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
             const double inv = 1.0 / b, cr0 = ccoef[k][0], ci0 = ccoef[k][1];
             // chi_k -= sum_j a_j chi_j + sum_l q_l Q_l, then normalise; r -= c_k chi_k
             combine_terms(
-                c, k + nq,
+                c, k + nqg,
                 [&](int j) {
                     const int ri = j < k ? 2 * j : 2 * (q0 + j - k);
                     return make_double2(red[ri], red[ri + 1]);
@@ -776,12 +876,14 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
         __syncthreads();
         double rn2 = rn2_s;
         if (nq > 0) {
-            // remove the residue's component in span Q (x moves along Z): ||r||^2 drops by |c|^2
-            reduce_slots(a.part, c.G, SQ, nq, red);
-            for (int l = 0; l < nq; ++l)
-                rn2 -= red[2 * l] * red[2 * l] + red[2 * l + 1] * red[2 * l + 1];
+            // project the residue (x moves along Z); ||r||^2 as it is afterwards
+            reduce_slots(a.part, c.G, SQ, obl ? 2 * nq : nq, red);
+            rn2 = proj_coef(rn2);
+            if (c.t == 0)
+                pn2_s = rn2;  // thread 0's value, shared below
             project_q();
             __syncthreads();
+            rn2 = pn2_s;
         }
         converged = rn2 <= tol2 * wn2;
         __syncthreads();  // every thread has read rn2_s
@@ -1335,7 +1437,8 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
 
 template <typename T>
 void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,
-                 const cpx<T>* Mt, const cpx<T>* Q, const cpx<T>* Z, int nq, const cpx<T>* w, cpx<T>* x, cpx<T>* r,
+                 const cpx<T>* Mt, const cpx<T>* Q, const cpx<T>* Z, int nq, int oblique, const double* Ainv,
+                 const double* Gw, const cpx<T>* w, cpx<T>* x, cpx<T>* r,
                  cpx<T>* xi, cpx<T>* chi, cpx<T>* w1, cpx<T>* w2, double* part, int* stats, unsigned* bar_count,
                  unsigned long long* bar_gen, int grid_size, hipStream_t s, bool cooperative)
 {
@@ -1358,6 +1461,11 @@ void launch_impl(const Geom& g, int Ns, int nkv, int maxiter, double tol, const 
     a.Q = Mt ? Q : nullptr;
     a.Z = Mt ? Z : nullptr;
     a.nq = (Mt && Q && Z) ? nq : 0;
+    a.oblique = oblique && a.nq > 0 && Ainv && Gw;
+    a.Ainv = Ainv;
+    a.Gw = Gw;
+    if (oblique && a.nq > 0 && !a.oblique)
+        fail(DFL_EINVAL, "oblique little deflation needs the inverse and Gram matrices");
     a.part = part;
     a.stats = stats;
     a.bar_count = bar_count;
@@ -1440,12 +1548,13 @@ size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * grid_s
 
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,
-                       const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* Q, const cpx<T>* Z, int nq, const cpx<T>* w,
+                       const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2, const cpx<T>* Q, const cpx<T>* Z, int nq, int oblique,
+                       const double* Ainv, const double* Gw, const cpx<T>* w,
                        cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, int* stats, unsigned* bar_count,
                        unsigned long long* bar_gen, int grid, hipStream_t s, bool cooperative)
 {
-    launch_impl<T>(g, Ns, nkv, maxiter, tol, tol_dev, At, Mt, Q, Z, nq, w, x, r, xi, chi, w1, w2, part, stats, bar_count,
-                   bar_gen, grid, s, cooperative);
+    launch_impl<T>(g, Ns, nkv, maxiter, tol, tol_dev, At, Mt, Q, Z, nq, oblique, Ainv, Gw, w, x, r, xi, chi, w1, w2, part,
+                   stats, bar_count, bar_gen, grid, s, cooperative);
 }
 
 template <typename T>
@@ -1502,10 +1611,12 @@ INST_MULTI(float)
 #undef INST_MULTI
 
 template void launch_little_gcr<double>(const Geom&, int, int, int, double, const double*, const c64*, const c64*,
-                                        c64*, c64*, const c64*, const c64*, int, const c64*, c64*, c64*, c64*,
-                                        c64*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
+                                        c64*, c64*, const c64*, const c64*, int, int, const double*, const double*,
+                                        const c64*, c64*, c64*, c64*, c64*, double*, int*, unsigned*,
+                                        unsigned long long*, int, hipStream_t, bool);
 template void launch_little_gcr<float>(const Geom&, int, int, int, double, const double*, const c32*, const c32*,
-                                       c32*, c32*, const c32*, const c32*, int, const c32*, c32*, c32*, c32*,
-                                       c32*, double*, int*, unsigned*, unsigned long long*, int, hipStream_t, bool);
+                                       c32*, c32*, const c32*, const c32*, int, int, const double*, const double*,
+                                       const c32*, c32*, c32*, c32*, c32*, double*, int*, unsigned*,
+                                       unsigned long long*, int, hipStream_t, bool);
 
 }  // namespace dfl

@@ -80,6 +80,8 @@ __device__ inline void full_hops(const Geom& g, const SapGeom& sg, const L& U, c
             continue;
         long tn = site_step(g, s, n, y, mu, step);
         spinor<T> p = load_spinor(psi, g.V, tn);
+        if (crosses_time(g, n, y, mu, step))
+            negate(p);
         if (step > 0)
             hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
         else
@@ -87,10 +89,10 @@ __device__ inline void full_hops(const Geom& g, const SapGeom& sg, const L& U, c
     }
 }
 
-template <typename T, typename L>
+template <typename T, typename L, bool CLV>
 __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<T>* __restrict__ rho,
                                              cpx<T>* __restrict__ psi, T diag, int nmr, int colour, int nrhs, int init,
-                                             c64* __restrict__ out64)
+                                             c64* __restrict__ out64, Clover<T> C)
 {
     // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
     rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
@@ -149,6 +151,9 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
         if (init == 0)
             self = load_spinor(psi, g.V, s);
         spinor<T> d = finish(self, acc, diag);
+        if constexpr (CLV)
+            if (init == 0)
+                clover_add(C, s, self, d);
         spinor<T> b = load_spinor(rho, g.V, s);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
@@ -172,6 +177,8 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
             zero(acc);
             block_hops(g, sg, U, lr, t, yl, s, n, y, acc);
             q = finish(r, acc, diag);
+            if constexpr (CLV)
+                clover_add(C, s, r, q);
 #pragma unroll
             for (int al = 0; al < 4; ++al)
 #pragma unroll
@@ -720,7 +727,7 @@ __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, co
 
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            int nrhs, int init, c64* out64, hipStream_t s);
+            int nrhs, int init, c64* out64, hipStream_t s, const cpx<T>* clov);
 
 // Blocks of up to 256 sites: links in registers. One field: lane pairs, one
 // block per CU at two wavefronts per SIMD (the blocks of one colour leave CUs
@@ -728,13 +735,13 @@ void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* ps
 // fields: one lane per site, two blocks per CU (16 fields on 16^4: 12% faster
 // than the generic kernel at three blocks per CU, which re-reads the links
 // every MR step, and 28% faster than lane pairs at one block per CU).
-// Larger blocks: the generic kernel.
+// Larger blocks, the clover term and antiperiodic time: the generic kernel.
 template <typename L>
 void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
-               int nrhs, int init, c64* out64, hipStream_t s)
+               int nrhs, int init, c64* out64, hipStream_t s, const c32* clov)
 {
-    if (sg.Vsb > 256) {
-        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
+    if (sg.Vsb > 256 || clov || g.tsign < 0) {
+        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
         return;
     }
     size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
@@ -754,32 +761,40 @@ void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, 
 
 template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            int nrhs, int init, c64* out64, hipStream_t s)
+            int nrhs, int init, c64* out64, hipStream_t s, const cpx<T>* clov)
 {
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(cpx<T>);
-    static std::once_flag attr;  // one per kernel instantiation
-    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap<T, L>), 160 * 1024 - 1024);
-    hipLaunchKernelGGL((k_sap<T, L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
-                       T(4) + m0, nmr, colour, nrhs, init, out64);
+    const Clover<T> C{clov};
+    if (clov) {
+        static std::once_flag attr;  // one per kernel instantiation
+        set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap<T, L, true>), 160 * 1024 - 1024);
+        hipLaunchKernelGGL((k_sap<T, L, true>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho,
+                           psi, T(4) + m0, nmr, colour, nrhs, init, out64, C);
+    } else {
+        static std::once_flag attr;
+        set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap<T, L, false>), 160 * 1024 - 1024);
+        hipLaunchKernelGGL((k_sap<T, L, false>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho,
+                           psi, T(4) + m0, nmr, colour, nrhs, init, out64, C);
+    }
 }
 
 }  // namespace
 
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi, double m0, int nmr,
-                         int colour, int nrhs, int init, hipStream_t s)
+                         int colour, int nrhs, int init, hipStream_t s, const c64* clov)
 {
-    launch(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, (c64*)nullptr, s);
+    launch(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, (c64*)nullptr, s, clov);
 }
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi, float m0, int nmr,
-                         int colour, int nrhs, int init, c64* out64, hipStream_t s)
+                         int colour, int nrhs, int init, c64* out64, hipStream_t s, const c32* clov)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
 }
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi, float m0,
-                            int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s)
+                            int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s, const c32* clov)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s);
+    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
 }
 
 }  // namespace dfl

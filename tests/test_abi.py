@@ -1,6 +1,7 @@
 """The C ABI library loads, exports every symbol the header declares, and rejects
 bad parameters on the host (no GPU call is made for these)."""
 import ctypes
+import subprocess
 import os
 import re
 
@@ -70,7 +71,20 @@ def test_null_context_is_einval():
     assert L.dfl_field_bytes(None, 0) == -1
 
 
-def test_params_struct_layout_matches_c():
-    # the ctypes mirror must have the C struct size: 3 int[4] + 10 int + 5 double + 3 enum + 4 int + padding
-    assert ctypes.sizeof(binding.Params) == 160
-    assert ctypes.sizeof(binding.Info) == 40
+def test_params_struct_layout_matches_c(tmp_path):
+    # the ctypes mirrors must have the C structs' sizes and field offsets, as
+    # the C compiler lays out include/dfl.h
+    fields = [f for f, _ in binding.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dfl.h"\nint main(void) {\n'
+                   '  printf("%zu %zu\\n", sizeof(dfl_params), sizeof(dfl_info));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(dfl_params, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(binding.Params)
+    assert int(out[1]) == ctypes.sizeof(binding.Info)
+    for f, off in zip(fields, out[2:]):
+        assert getattr(binding.Params, f).offset == int(off), f

@@ -460,14 +460,15 @@ def test_graph_solve_equals_direct(c1, nrhs):
 
 
 def test_little_solve_even_odd_vs_plain(c1):
-    # GCR on the even-odd reduced system with global-mode deflation (default),
-    # without the deflation, and on A itself all reach the dense solution; each
+    # GCR on the even-odd reduced system with global-mode deflation in the
+    # minimal-residual form (default) and in section 3's oblique form, without
+    # the deflation, and on A itself all reach the dense solution; each
     # refinement needs no more iterations than the plainer form
-    say("little solve: deflated even-odd, even-odd, plain")
+    say("little solve: deflated even-odd (both forms), even-odd, plain")
     torch = pytest.importorskip("torch")
     dims, b = c1["dims"], (4, 4, 4, 4)
     its = {}
-    for eo, gd in [(1, 1), (1, 0), (0, 0)]:
+    for eo, gd in [(1, 2), (1, 1), (1, 0), (0, 0)]:
         S = _c1_solver(c1, little_eo=eo, little_gdefl=gd)
         Nb, Ns = S.Nb, S.Ns
         v = latgen.random_field((Nb, 1, 1, 1), 52).reshape(-1)[: Nb * Ns]
@@ -482,6 +483,21 @@ def test_little_solve_even_odd_vs_plain(c1):
     print("[little iterations]", its, flush=True)
     for tol in (1e-12, 1e-6):
         assert its[(1, 1, tol)] <= its[(1, 0, tol)] <= its[(0, 0, tol)]
+        assert its[(1, 2, tol)] <= its[(1, 0, tol)]
+
+
+@pytest.mark.parametrize("little_prec", [F64, F32])
+def test_solve_oblique_little_deflation(c1, little_prec):
+    # the deflated solver with section 3's oblique global-mode deflation of the
+    # little system (FP64 and FP32 inner little solves) meets the criterion
+    say(f"solve with oblique little deflation, little_prec={little_prec}")
+    dims = c1["dims"]
+    S = _c1_solver(c1, tol=1e-10, little_gdefl=2, little_prec=little_prec, sap_prec=F32, link_prec=F32)
+    psi, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 0, info.as_dict()
+    r = c1["eta"] - oracle.dirac(c1["U"], S.unpack(psi)[0], c1["m0"], dims)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(c1["eta"])
+    S.close()
 
 
 def test_set_gauge_requires_su3():
@@ -595,4 +611,134 @@ def test_graph_solve_after_new_setup(c1):
         r = c1["eta"] - oracle.dirac(U, got[0], c1["m0"], dims)
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(c1["eta"])
         S.use_graphs(True)
+    S.close()
+
+
+# ---------------------------------------------- O(a)-improved operator (section 2.1)
+
+CSW = 1.90952
+
+
+@pytest.mark.parametrize("gi", [0, 1, 2])
+def test_dirac_clover_antiperiodic(gi):
+    # the clover term and the antiperiodic time boundary in the stencil: FP64
+    # on 4^4 layout blocks of 8^4 and 16 x 8^3 lattices (LDS kernel) and on
+    # ragged 60-site blocks (generic kernel); FP32 and BF16 links
+    dims, b, sb = GEOMS[gi]
+    say(f"dirac clover antiperiodic {dims}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.5, 111)
+    psi = latgen.random_field(dims, 112, n=2)
+    kw = dict(csw=CSW, antiperiodic=True)
+    S = make_solver(dims, b, sb, m0=m0, nrhs_max=2, **kw)
+    S.set_gauge(U)
+    out = S.unpack(S.dirac(S.pack(psi)))
+    for r in range(2):
+        ref = oracle.dirac(U, psi[r], m0, dims, **kw)
+        assert rel(out[r], ref) < 1e-13
+        assert rel(out[r], oracle.dirac(U, psi[r], m0, dims)) > 1e-3   # the terms are really there
+    S.close()
+    if gi == 0:
+        for link_prec, tol in [(F32, 1e-5), (BF16, 1e-2)]:
+            S = make_solver(dims, b, sb, m0=m0, link_prec=link_prec, sap_prec=F32, **kw)
+            S.set_gauge(U)
+            got = S.unpack(S.dirac(S.pack(psi[0], prec=F32), prec=F32), prec=F32)[0]
+            assert rel(got, oracle.dirac(U, psi[0], m0, dims, **kw)) < tol
+            S.close()
+
+
+@pytest.mark.parametrize("gi,sap_prec,link_prec,nrhs,tol", [(0, F64, F64, 1, 1e-12), (2, F64, F64, 2, 1e-12),
+                                                             (0, F32, F32, 1, 1e-4), (0, F32, BF16, 2, 3e-2),
+                                                             (2, F32, F32, 2, 1e-4)])
+def test_sap_clover_antiperiodic(gi, sap_prec, link_prec, nrhs, tol):
+    # Schwarz sweeps with the clover term in the block operator and the
+    # antiperiodic boundary in the residual (generic kernel), 256- and
+    # 512-site blocks, one and two fields
+    dims, b, sb = GEOMS[gi]
+    say(f"sap clover {dims} sap_block={sb} prec={sap_prec} links={link_prec} nrhs={nrhs}")
+    m0 = -0.2
+    kw = dict(csw=CSW, antiperiodic=True)
+    U = latgen.make_links(dims, 0.4, 121)
+    rho = latgen.random_field(dims, 122, n=nrhs)
+    S = make_solver(dims, b, sb, m0=m0, ncy=3, nmr=4, nrhs_max=nrhs, sap_prec=sap_prec, link_prec=link_prec, **kw)
+    S.set_gauge(U)
+    got = S.unpack(S.sap(S.pack(rho)))
+    for r in range(nrhs):
+        e = rel(got[r], oracle.sap(U, rho[r], m0, dims, sb, 3, 4, **kw))
+        assert e < tol, (r, e)
+    S.close()
+
+
+def test_setup_and_solve_clover_antiperiodic():
+    # subspace, little operator (eq. (A.1) with the clover term in the block
+    # operator and the boundary sign on the x0 faces), projectors and the
+    # deflated solve of the O(a)-improved operator against the oracle
+    say("setup and solve, clover + antiperiodic")
+    dims, b = (8, 8, 8, 8), (4, 4, 4, 4)
+    kw = dict(csw=CSW, antiperiodic=True)
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.4, 131)
+    eta = latgen.make_source(dims, 132)
+    init = latgen.make_init_fields(dims, 8, 133)
+    # no inverse-iteration steps: the basis is the block Gram-Schmidt of the start fields
+    S = Solver(dims, m0=m0, m0_setup=m0, ncy=5, nmr=4, Ns=8, n_inviter=0, tol=1e-12, **kw)
+    S.set_gauge(U)
+    S.setup(S.pack(init))
+    Phi = oracle.block_gram_schmidt(init, dims, b)
+    assert rel(S.unpack(S.basis()), Phi) < 1e-12
+    A = oracle.little_operator(U, Phi, m0, dims, b, **kw)
+    assert rel(S.little_operator(), A) < 1e-10
+    dfl = oracle.Deflation(U, Phi, A, m0, dims, b, **kw)
+    y = latgen.make_source(dims, 134)
+    yd = S.pack(y)
+    for which, ref in [(PROJ_COARSE, dfl.coarse(y)), (PROJ_PL, dfl.PL(y)), (PROJ_PR, dfl.PR(y))]:
+        assert rel(S.unpack(S.project(which, yd))[0], ref) < 1e-9, which
+    psi, info = S.solve(S.pack(eta))
+    assert info.status == 0, info.as_dict()
+    psi = S.unpack(psi)[0]
+    r = eta - oracle.dirac(U, psi, m0, dims, **kw)
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(eta)
+    ref, _, ok = oracle.solve(U, eta, m0, dims, sap_block=b, dfl=dfl, tol=1e-12, **kw)
+    assert ok and np.linalg.norm(psi - ref) <= 1e-9 * np.linalg.norm(ref)
+    # a mass shift keeps the subspace (the clover term does not depend on m0)
+    S.set_mass(-0.25)
+    assert rel(S.little_operator(), oracle.little_operator(U, Phi, -0.25, dims, b, **kw)) < 1e-10
+    S.close()
+    # mixed precision with the clover term still reaches the FP64 criterion
+    S = Solver(dims, m0=m0, m0_setup=m0, ncy=5, nmr=4, Ns=8, n_inviter=2, tol=1e-10, sap_prec=F32,
+               link_prec=BF16, little_prec=F32, **kw)
+    S.set_gauge(U)
+    S.setup(S.pack(init))
+    psi, info = S.solve(S.pack(eta))
+    assert info.status == 0
+    r = eta - oracle.dirac(U, S.unpack(psi)[0], m0, dims, **kw)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(eta)
+    S.close()
+
+
+@pytest.mark.parametrize("n_boot", [1, 2])
+def test_bootstrapped_setup(c1, n_boot):
+    # section 5.3's bootstrapped inverse iteration: with exact little solves
+    # (FP64 to 1e-13) the basis and the little operator equal the oracle's,
+    # whose bootstrapped steps use dense LU; with the default inner tolerance
+    # the deflated solve on that subspace meets the criterion
+    say(f"bootstrapped setup n_boot={n_boot}")
+    dims, b = c1["dims"], (4, 4, 4, 4)
+    m0, m_setup = c1["m0"], -0.25
+    Phi, A = oracle.setup(c1["U"], c1["init"], m_setup, dims, b, b, 5, 4, 3, n_boot=n_boot)
+    S = Solver(dims, m0=m_setup, m0_setup=m_setup, ncy=5, nmr=4, Ns=8, n_inviter=3, n_boot=n_boot,
+               little_tol_in=1e-13, tol=1e-10)
+    S.set_gauge(c1["U"])
+    S.setup(S.pack(c1["init"]))
+    assert rel(S.unpack(S.basis()), Phi) < 1e-9
+    assert rel(S.little_operator(), A) < 1e-9
+    S.close()
+    S = Solver(dims, m0=m0, m0_setup=m_setup, ncy=5, nmr=4, Ns=8, n_inviter=3, n_boot=n_boot, tol=1e-10,
+               sap_prec=F32, link_prec=F32, little_prec=F32)
+    S.set_gauge(c1["U"])
+    S.setup(S.pack(c1["init"]))
+    psi, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 0
+    r = c1["eta"] - oracle.dirac(c1["U"], S.unpack(psi)[0], m0, dims)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(c1["eta"])
     S.close()

@@ -325,3 +325,54 @@ def test_inverse_iteration_is_normalised_inverse_power():
     got0 = oracle.inverse_iteration(U, 3.0 * init, m_setup, dims, b, 30, 30, 0)
     for l in range(2):
         assert np.abs(got0[l] - init[l] / np.linalg.norm(init[l])).max() < 1e-15
+
+
+def test_bootstrapped_inverse_iteration_exact_limit():
+    # with M_sap -> D^-1 (heavy setup mass, many cycles and MR steps) the
+    # bootstrapped step P_R M_sap P_L + Phi A^-1 Phi^dagger is D^-1 itself, so n
+    # steps with any number of bootstrapped ones give the normalised D^-n psi_0
+    dims, b = (4, 4, 2, 2), (2, 2, 1, 1)
+    V = int(np.prod(dims))
+    m_setup = 1.0
+    U = latgen.make_links(dims, 0.4, 1101)
+    init = latgen.make_init_fields(dims, 2, 1102)
+    D = dense_from(lambda f: oracle.dirac(U, f, m_setup, dims), V)
+    for n, nb in ((1, 1), (2, 1), (2, 2)):
+        got = oracle.inverse_iteration(U, 3.0 * init, m_setup, dims, b, 30, 30, n, n_boot=nb, dfl_block=b)
+        for l in range(2):
+            want = init[l].reshape(-1)
+            for _ in range(n):
+                want = np.linalg.solve(D, want)
+            want /= np.linalg.norm(want)
+            assert abs(np.linalg.norm(got[l]) - 1.0) < 1e-13
+            assert np.abs(got[l].reshape(-1) - want).max() < 1e-10
+
+
+def test_bootstrapped_inverse_iteration_lowers_bound_5_2():
+    # at a light mass with the standard Schwarz parameters, deflating the last
+    # steps with the current fields (section 5.3) gives fields with a smaller
+    # bound M of eq. (5.2) than plain inverse iteration with the same steps,
+    # and a subspace that is no worse for the lowest modes of D^dagger D
+    # (deficits eq. (3.15) of the 8 lowest right singular vectors of the dense D)
+    dims, b = (4, 4, 4, 4), (2, 2, 2, 2)
+    V = int(np.prod(dims))
+    m0 = -0.3
+    U = latgen.make_links(dims, 0.4, 1201)
+    init = latgen.make_init_fields(dims, 6, 1202)
+    D = dense_from(lambda f: oracle.dirac(U, f, m0, dims), V)
+    low = np.linalg.svd(D)[2][-8:].conj()
+
+    def stats(n_iter, n_boot):
+        f = oracle.inverse_iteration(U, init, m0, dims, b, 5, 4, n_iter, n_boot=n_boot, dfl_block=b)
+        Phi = oracle.block_gram_schmidt(f, dims, b)
+        dfc = np.mean([oracle.deficit(Phi, low[k].reshape(V, 12), dims, b) for k in range(8)])
+        ray = np.mean([np.linalg.norm(oracle.dirac(U, g, m0, dims)) / np.linalg.norm(g) for g in f])
+        return ray, dfc
+
+    r_plain, d_plain = stats(3, 0)
+    r_boot, d_boot = stats(3, 1)
+    assert r_boot < 0.75 * r_plain
+    assert d_boot <= d_plain + 1e-3
+    r_plain4, d_plain4 = stats(4, 0)
+    r_boot4, d_boot4 = stats(4, 2)
+    assert r_boot4 < 0.75 * r_plain4 and d_boot4 <= d_plain4 + 1e-3
