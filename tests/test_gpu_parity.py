@@ -518,30 +518,30 @@ def test_set_gauge_requires_su3():
 
 
 def test_bench_workload_16x4():
-    # The benchmark's solve workload at full size, in the configuration bench.py
-    # times (16^4, Ns = 20, 4^4 blocks, FP32 Schwarz with FP32 two-row links,
-    # FP64 GCR and little solves, tol 1e-10), checked by what the oracle computes
-    # at this size: the basis is orthonormal on every block, the little operator
-    # equals Phi^+ D Phi of the oracle on the same basis, and each solution meets
-    # the stopping criterion with the oracle's FP64 operator.
+    # The benchmark's 16^4 workload at full size, in the configuration bench.py
+    # times (Ns = 20, 4^4 blocks, FP32 Schwarz with FP32 two-row links, FP64
+    # GCR and little solves, tol 1e-10), checked by what the oracle computes
+    # at this size: the basis is orthonormal on every block, the little
+    # operator equals Phi^+ D Phi of the oracle on the same basis, and each
+    # solution meets the stopping criterion with the oracle's FP64 operator.
     import bench
     say("bench workload 16^4")
-    dims, b = bench.DIMS, bench.BLOCK
-    eps, seed = bench.FIELDS[0]
+    dims, b = bench.C2_DIMS, bench.BLOCK
+    eps, seed = bench.C2_FIELDS[0]
     U = latgen.make_links(dims, eps, seed)
     eta = latgen.make_source(dims, seed + 100)
-    init = latgen.make_init_fields(dims, bench.NS, seed + 200)
-    prm = bench.solver_params()
+    init = latgen.make_init_fields(dims, 20, seed + 200)
+    prm = bench.params(Ns=20, m0=bench.C2_MASSES[0], m0_setup=min(bench.C2_MASSES), little_prec=F64)
     S = Solver(dims, **prm)
     S.set_gauge(U)
     S.setup(S.pack(init))
     Phi = S.unpack(S.basis())
     Pb = oracle.to_blocks(Phi, dims, b)                      # (Ns, Nb, 12 Vb)
     G = np.einsum("kbi,lbi->bkl", Pb.conj(), Pb)
-    assert np.abs(G - np.eye(bench.NS)[None]).max() < 1e-12
+    assert np.abs(G - np.eye(20)[None]).max() < 1e-12
     A = S.little_operator()
     assert rel(A, oracle.little_operator(U, Phi, prm["m0"], dims, b)) < 1e-11
-    for m0 in bench.MASSES:
+    for m0 in bench.C2_MASSES:
         S.set_mass(m0)
         psi, info = S.solve(S.pack(eta))
         assert info.status == 0
@@ -549,6 +549,26 @@ def test_bench_workload_16x4():
         true_rel = oracle.norm(res) / oracle.norm(eta)
         assert true_rel <= bench.TOL, (m0, info.as_dict())
         assert abs(info.rel_residual - true_rel) < 1e-12
+    S.close()
+
+
+def test_bench_headline_64x32():
+    # The benchmark's headline step at full size, exactly as bench.py times
+    # it (64 x 32^3, Ns = 24, FP32 Schwarz and inner little solves): the
+    # solution meets the stopping criterion with the oracle's FP64 operator
+    # on the whole lattice, and the reported residual is that one
+    import bench
+    say("bench headline 64x32^3")
+    U, eta, init = bench.headline_inputs()
+    S = Solver(bench.DIMS, **bench.params())
+    S.set_gauge(U)
+    S.setup(S.pack(init))
+    psi, info = S.solve(S.pack(eta))
+    assert info.status == 0, info.as_dict()
+    res = eta - oracle.dirac(U, S.unpack(psi)[0], bench.M0, bench.DIMS)
+    true_rel = oracle.norm(res) / oracle.norm(eta)
+    assert true_rel <= bench.TOL
+    assert abs(info.rel_residual - true_rel) < 1e-12
     S.close()
 
 
