@@ -56,6 +56,20 @@ int conv4d_forward(dfl_ctx *ctx, const float *in_dev, int cin, const float *W_de
 int conv4d_backward(dfl_ctx *ctx, const float *in_dev, int cin, const float *W_dev, int cout, const float *g_dev,
                     float *dW_dev, float *db_dev, float *din_dev, const float *z_in_dev);
 
+/* conv4d_backward without any allocation, for callers that cannot allocate
+ * device memory (code under graph capture, serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, results and errors as conv4d_backward,
+ * except that the weight-gradient partial sums live in a fixed device array of
+ * 64 MiB that the library holds on every device it runs on until the process
+ * ends (conv4d_backward grows a context buffer instead); when the default
+ * chunking over the sites needs more, fewer and longer chunks are summed, so
+ * dW may differ from conv4d_backward's by FP32 rounding. No call allocates.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents: calls that overlap on one device (several streams, contexts or
+ * threads) race and must be serialised by the caller. */
+int conv4d_backward_noalloc(dfl_ctx *ctx, const float *in_dev, int cin, const float *W_dev, int cout,
+                            const float *g_dev, float *dW_dev, float *db_dev, float *din_dev, const float *z_in_dev);
+
 /* Ns native FP64 fields from the last layer's planes out [24*Ns][V]:
  * component c of field l is out[(l*12 + c)*2] + i out[(l*12 + c)*2 + 1]. */
 int net_outputs_to_fields(dfl_ctx *ctx, const float *out_dev, int Ns, void *fields_dev);

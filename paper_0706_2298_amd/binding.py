@@ -60,7 +60,8 @@ EXPORTS = [
     "dfl_set_gauge", "dfl_pack", "dfl_unpack", "dirac_apply", "sap_precond", "dfl_setup", "dfl_get_basis",
     "dfl_get_little", "little_dirac_apply", "little_solve", "deflate_project", "solve", "dfl_residual_history",
     "dfl_profile_enable", "dfl_profile_read", "dfl_last_error", "dfl_use_graphs", "dfl_graph_replays",
-    "dfl_inverse_iteration", "net_features", "conv4d_forward", "conv4d_backward", "net_outputs_to_fields",
+    "dfl_inverse_iteration", "net_features", "conv4d_forward", "conv4d_backward", "conv4d_backward_noalloc",
+    "net_outputs_to_fields",
     "net_fields_grad_to_outputs", "deficit_loss", "adam_update",
 ]
 PROF_CLASSES = ["sap", "dirac", "little", "project", "setup", "setup_sap"]
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
         "net_features": (i, [vp, vp, vp]),
         "conv4d_forward": (i, [vp, vp, i, vp, vp, i, vp, vp]),
         "conv4d_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp, vp]),
+        "conv4d_backward_noalloc": (i, [vp, vp, i, vp, i, vp, vp, vp, vp, vp]),
         "net_outputs_to_fields": (i, [vp, vp, i, vp]),
         "net_fields_grad_to_outputs": (i, [vp, vp, i, vp]),
         "deficit_loss": (i, [vp, vp, i, vp, i, P(d), vp]),
@@ -243,6 +245,11 @@ def conv4d_forward(ctx, x, cin, W, b, cout, z, a=None):
 def conv4d_backward(ctx, x, cin, W, cout, g, dW, db, din=None, z_in=None):
     _check(load().conv4d_backward(ctx, _ptr(x), cin, _ptr(W), cout, _ptr(g), _ptr(dW), _ptr(db), _ptr(din),
                                   _ptr(z_in)))
+
+
+def conv4d_backward_noalloc(ctx, x, cin, W, cout, g, dW, db, din=None, z_in=None):
+    _check(load().conv4d_backward_noalloc(ctx, _ptr(x), cin, _ptr(W), cout, _ptr(g), _ptr(dW), _ptr(db), _ptr(din),
+                                          _ptr(z_in)))
 
 
 def net_outputs_to_fields(ctx, out, Ns, fields):

@@ -1773,6 +1773,31 @@ int conv4d_backward(dfl_ctx* c, const float* in, int cin, const float* W, int co
     API_END
 }
 
+int conv4d_backward_noalloc(dfl_ctx* c, const float* in, int cin, const float* W, int cout, const float* g,
+                            float* dW, float* db, float* din, const float* z_in)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(in, "in");
+    need_ptr(W, "W");
+    need_ptr(g, "g");
+    need_ptr(dW, "dW");
+    need_ptr(db, "db");
+    if (cin < 1 || cin > kNetMaxCin || cout < 1 || cout > kNetMaxCout)
+        fail(DFL_EINVAL, "channels: 1 <= cin <= 96, 1 <= cout <= 576");
+    if (din && (din == g || din == in))
+        fail(DFL_EINVAL, "din must not overlap g or in");
+    long chunk = 0;
+    int nchunk = 0;
+    if (!conv_wgrad_chunk_fit(c->g, cin, cout, kNoAllocFloats, &chunk, &nchunk))
+        fail(DFL_EINVAL, "conv4d_backward_noalloc: one chunk of the weight-gradient partial sums (81 cin cout "
+                         "floats) exceeds the 64 MiB scratch");
+    float* part = noalloc_scratch();
+    launch_conv_backward(c->g, in, cin, W, cout, g, dW, db, din, z_in, part, chunk, nchunk, c->stream);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
 int net_outputs_to_fields(dfl_ctx* c, const float* out, int Ns, void* fields)
 {
     API_BEGIN

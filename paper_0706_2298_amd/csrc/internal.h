@@ -341,6 +341,13 @@ void launch_deficit_grad(const Geom& g, const c64* Psi, int Ns, const c64* T, in
                          c64* grad, hipStream_t s);
 void launch_adam(float* th, const float* gr, float* m, float* v, long n, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t s);
+// allocation-free weight gradient: floats of the device scratch array (64 MiB
+// per device), its device address on the current device, and a chunking of
+// the partial sums that fits cap floats (false if one chunk does not fit)
+constexpr size_t kNoAllocFloats = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+float* noalloc_scratch();
+bool conv_wgrad_chunk_fit(const Geom& g, int cin, int cout, size_t cap, long* chunk, int* nchunk);
 constexpr int kNetMaxCin = 96;     // input channels of a convolution (weight gradient bound)
 constexpr int kNetMaxCout = 576;   // output channels (input-gradient staging bound)
 constexpr int kLossMaxN = 32;      // fields and targets of the deficit loss

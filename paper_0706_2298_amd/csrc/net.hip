@@ -7,6 +7,8 @@
 // so a tap's neighbour is a fixed shift of the site index up to the periodic
 // wrap. Weights are [81][Cin][Cout], tap t = sum_mu (o_mu + 1) 3^(3 - mu) for
 // the offset o in {-1,0,1}^4. Quark fields are native FP64 fields (common.h).
+#include <mutex>
+
 #include "internal.h"
 
 namespace dfl {
@@ -635,6 +637,51 @@ size_t conv_wgrad_chunk_floats(const Geom& g, int cin, int cout, long* chunk, in
     *chunk = c;
     *nchunk = (int)((g.V + c - 1) / c);
     return (size_t)(*nchunk) * 81 * cin * cout;
+}
+
+// ------------------------------------- allocation-free weight gradient
+//
+// Partial sums of the weight gradient for callers that cannot allocate
+// (conv4d_backward_noalloc): a file-scope device array of kNoAllocFloats
+// floats, which every device the library runs on holds until the process
+// ends. Host code takes its device address from hipGetSymbolAddress, once per
+// device, and passes that to the kernels (the array's name is no device
+// address on the host). Every call overwrites the part it uses before reading
+// it; calls that overlap on one device race on it.
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+float* noalloc_scratch()
+{
+    static std::mutex mu;
+    static float* ptr[kMaxDevices] = {};
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        fail(DFL_EINVAL, "device index beyond the allocation-free scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            fail(DFL_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        ptr[dev] = static_cast<float*>(p);
+    }
+    return ptr[dev];
+}
+
+bool conv_wgrad_chunk_fit(const Geom& g, int cin, int cout, size_t cap, long* chunk, int* nchunk)
+{
+    const size_t per = (size_t)81 * cin * cout;
+    if (conv_wgrad_chunk_floats(g, cin, cout, chunk, nchunk) <= cap)
+        return true;
+    const long most = (long)(cap / per);
+    if (most < 1)
+        return false;
+    long c = (g.V + most - 1) / most;
+    c = ((c + kWS - 1) / kWS) * kWS;
+    *chunk = c;
+    *nchunk = (int)((g.V + c - 1) / c);
+    return (size_t)(*nchunk) * per <= cap;
 }
 
 void launch_net_features(const Geom& g, const c64* U64, const float* noise, float* x, hipStream_t s)
