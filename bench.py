@@ -634,6 +634,7 @@ def main():
     ap.add_argument("--learned-tests", type=int, default=5, help="held-out 64x32^3 fields for the network")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (y = 1.0 * x), to scale HBM byte counters")
+    ap.add_argument("--dirac-only", action="store_true", help="only the dirac_apply rates on 64x32^3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (sharding over several GPUs "
@@ -653,6 +654,10 @@ def main():
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         print(json.dumps({"copy_read_bytes": x.numel() * 8, "copy_write_bytes": y.numel() * 8, "dispatches": 5}))
+        return
+
+    if args.dirac_only:
+        print(json.dumps(dirac_rates(torch)), flush=True)
         return
 
     log("generating inputs")

@@ -635,19 +635,27 @@ void read_little_stats(dfl_ctx* c, int out[3])
     }
 }
 
-// out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term) for nb fields; out may not alias in
+// out = Phi A^{-1} Phi^+ in  (eq. (3.10)'s coarse term) for nb fields; out may not alias in.
+// Inexact (FP32) inner projections read the FP32 copy of the basis.
 void coarse(dfl_ctx* c, const c64* in, c64* out, double tol, dfl_prec prec, int nb = 1,
             const double* tol_dev = nullptr)
 {
     c64* w = static_cast<c64*>(c->lw);
     c64* x = static_cast<c64*>(c->lx);
+    const bool b32 = prec == DFL_F32 && c->Phi32;
     {
         ProfScope ps(c, DFL_PROF_PROJECT);
-        launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, nb, c->stream);
+        if (b32)
+            launch_restrict_b32(c->g, c->Phi32, c->p.Ns, in, w, nb, c->stream);
+        else
+            launch_restrict64(c->g, c->Phi, c->p.Ns, in, w, nb, c->stream);
     }
     little_solve_impl(c, w, x, tol, prec, nb, tol_dev);
     ProfScope ps(c, DFL_PROF_PROJECT);
-    launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, nb, c->stream);
+    if (b32)
+        launch_prolong_b32(c->g, c->Phi32, c->p.Ns, x, out, nb, c->stream);
+    else
+        launch_prolong64(c->g, c->Phi, c->p.Ns, x, out, nb, c->stream);
 }
 
 // out = P_L in = in - D coarse(in)   (eq. (3.3)) for nb fields
@@ -973,6 +981,8 @@ void build_subspace(dfl_ctx* c, const c64* src, double mA)
         }
     }
     launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);
+    if (c->Phi32)
+        launch_f64_to_f32(c->Phi, c->Phi32, F * Ns, c->stream);
     c->eo_ok = false;
     c->m0_A = mA;
     int flag[4];
@@ -1175,6 +1185,8 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
             c->Cl32 = alloc_dev<c32>(c, (size_t)kCloverComp * V);
         }
         c->Phi = alloc_dev<c64>(c, (size_t)p->Ns * F);
+        if (p->little_prec == DFL_F32)
+            c->Phi32 = alloc_dev<c32>(c, (size_t)p->Ns * F);
         c->A64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->A32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
         c->At64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);

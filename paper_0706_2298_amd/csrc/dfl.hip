@@ -28,8 +28,8 @@ __device__ inline long block_elem(const Geom& g, int blk, int e)
 // Phi_k entries are read once per chunk of RB right-hand sides (one pass
 // over eight right-hand sides has nine loads per entry in flight). A single
 // field uses k_restrict_kg below.
-template <int RB>
-__global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict__ Phi, int Ns,
+template <int RB, typename P>
+__global__ __launch_bounds__(kBT) void k_restrict(Geom g, const P* __restrict__ Phi, int Ns,
                                                   const c64* __restrict__ psi, c64* __restrict__ w, int nrhs,
                                                   int grid_padded)
 {
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
     const int blk = q / Ns, k = q - blk * Ns;
     const long fs = 12 * g.V;
     const long nw = (long)g.Nb * Ns;
-    const c64* ph = Phi + (long)k * fs;
+    const P* ph = Phi + (long)k * fs;
     const int ne = 12 * g.Vb;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int b0 = 0; b0 < nrhs; b0 += RB) {
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
             re[j] = im[j] = 0.0;
         for (int e = threadIdx.x; e < ne; e += kBT) {
             const long i = block_elem(g, blk, e);
-            const c64 a = ph[i];
+            const c64 a = c64{(double)ph[i].re, (double)ph[i].im};
 #pragma unroll
             for (int j = 0; j < RB; ++j)
                 if (b0 + j < nrhs) {
@@ -82,8 +82,8 @@ __global__ __launch_bounds__(kBT) void k_restrict(Geom g, const c64* __restrict_
 // Single field, KG basis fields per workgroup: one workgroup per (block,
 // group of KG consecutive k); each entry of psi is loaded once for the KG
 // products (the block of psi is fetched Ns / KG times instead of Ns).
-template <int KG>
-__global__ __launch_bounds__(kBT) void k_restrict_kg(Geom g, const c64* __restrict__ Phi, int Ns,
+template <int KG, typename P>
+__global__ __launch_bounds__(kBT) void k_restrict_kg(Geom g, const P* __restrict__ Phi, int Ns,
                                                      const c64* __restrict__ psi, c64* __restrict__ w, int ngrp,
                                                      int grid_padded)
 {
@@ -101,7 +101,8 @@ __global__ __launch_bounds__(kBT) void k_restrict_kg(Geom g, const c64* __restri
         re[j] = im[j] = 0.0;
     constexpr int RU = 4;
     for (int e0 = threadIdx.x; e0 < ne; e0 += RU * kBT) {
-        c64 bv[RU], av[RU][KG];
+        c64 bv[RU];
+        P av[RU][KG];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const long i = block_elem(g, blk, min(e0 + u * kBT, ne - 1));
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(kBT) void k_restrict_kg(Geom g, const c64* __restri
             if (e0 + u * kBT < ne) {
 #pragma unroll
                 for (int j = 0; j < KG; ++j) {
-                    const c64 a = av[u][j], b = bv[u];
+                    const c64 a = c64{(double)av[u][j].re, (double)av[u][j].im}, b = bv[u];
                     re[j] += a.re * b.re + a.im * b.im;
                     im[j] += a.re * b.im - a.im * b.re;
                 }
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(kBT) void k_restrict_kg(Geom g, const c64* __restri
 }
 
 // psi_b(i) = sum_k Phi_k(i) v_b[blk(i)*Ns + k], one thread per field entry
-__global__ __launch_bounds__(256) void k_prolong(Geom g, const c64* __restrict__ Phi, int Ns,
+template <typename P>
+__global__ __launch_bounds__(256) void k_prolong(Geom g, const P* __restrict__ Phi, int Ns,
                                                  const c64* __restrict__ v, c64* __restrict__ psi, int nrhs)
 {
     const long fs = 12 * g.V;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geom g, const c64* __restrict__
         for (int j = 0; j < kRB; ++j)
             acc[j] = c64{0.0, 0.0};
         for (int k = 0; k < Ns; ++k) {
-            const c64 a = Phi[(long)k * fs + i];
+            const c64 a = c64{(double)Phi[(long)k * fs + i].re, (double)Phi[(long)k * fs + i].im};
 #pragma unroll
             for (int j = 0; j < kRB; ++j)
                 if (b0 + j < nrhs)
@@ -446,13 +448,13 @@ __global__ __launch_bounds__(256) void k_little_columns(Geom g, const c64* __res
     }
 }
 
-// Register-tiled form for Ns <= 20 and nc <= 16: the (k, j) pairs form 16
-// tiles of 5 x 4, one per 16-lane row of the workgroup; the 16 lanes of a
-// row take every 16th staged entry, read 5 + 4 values from LDS per entry for
-// 20 products (the kernel above reads 2 per product), and combine their sums
-// with in-row DPP moves at the end. Same partial-sum layout as above.
-constexpr int kRtK = 5, kRtJ = 4, kRtCE = 64;
-constexpr int kRtLd = (4 * kRtK + 4 * kRtJ + 3) / 4;  // staged rows per thread (Ns + nc <= 36 rows / 4 waves)
+// Register-tiled form for Ns <= 4 TK and nc <= 16: the (k, j) pairs form 16
+// tiles of TK x 4, one per 16-lane row of the workgroup; the 16 lanes of a
+// row take every 16th staged entry, read TK + 4 values from LDS per entry for
+// 4 TK products (the kernel above reads 2 per product), and combine their
+// sums with in-row DPP moves at the end. Same partial-sum layout as above.
+// TK = 5 serves Ns <= 20, TK = 6 Ns <= 24.
+constexpr int kRtJ = 4, kRtCE = 64;
 
 __device__ inline double row16_sum(double v)
 {
@@ -464,10 +466,13 @@ __device__ inline double row16_sum(double v)
     return v;
 }
 
+template <int TK>
 __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __restrict__ Phi, int Ns,
                                                            const c64* __restrict__ Y, int nc, int nsplit, int fmu,
                                                            int fy, int nface, c64* __restrict__ part)
 {
+    constexpr int kRtK = TK;
+    constexpr int kRtLd = (4 * kRtK + 4 * kRtJ + 3) / 4;  // staged rows per thread (Ns + nc rows over 4 waves)
     extern __shared__ c64 st[];  // [Ns + nc][kRtCE]
     const int blk = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
     const long F = 12 * g.V;
@@ -909,22 +914,40 @@ __global__ void k_c64_to_c32(const c64* a, c32* b, long n)
 
 }  // namespace
 
-void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
+template <typename P>
+void restrict_any(const Geom& g, const P* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
 {
     const int gp = pad_grid((long)g.Nb * Ns);
     if (nrhs == 1) {
         constexpr int KG = 4;  // measured: five fields per workgroup are no faster
         const int ngrp = (Ns + KG - 1) / KG;
         const int gk = pad_grid((long)g.Nb * ngrp);
-        hipLaunchKernelGGL(k_restrict_kg<KG>, dim3(gk), dim3(kBT), 0, s, g, Phi, Ns, psi, w, ngrp, gk);
+        hipLaunchKernelGGL((k_restrict_kg<KG, P>), dim3(gk), dim3(kBT), 0, s, g, Phi, Ns, psi, w, ngrp, gk);
     }
     else
-        hipLaunchKernelGGL(k_restrict<kRB>, dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
+        hipLaunchKernelGGL((k_restrict<kRB, P>), dim3(gp), dim3(kBT), 0, s, g, Phi, Ns, psi, w, nrhs, gp);
+}
+template <typename P>
+void prolong_any(const Geom& g, const P* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s)
+{
+    const long n = 12 * g.V;
+    hipLaunchKernelGGL(k_prolong<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi, nrhs);
+}
+void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
+{
+    restrict_any(g, Phi, Ns, psi, w, nrhs, s);
 }
 void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s)
 {
-    const long n = 12 * g.V;
-    hipLaunchKernelGGL(k_prolong, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi, nrhs);
+    prolong_any(g, Phi, Ns, v, psi, nrhs, s);
+}
+void launch_restrict_b32(const Geom& g, const c32* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
+{
+    restrict_any(g, Phi, Ns, psi, w, nrhs, s);
+}
+void launch_prolong_b32(const Geom& g, const c32* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s)
+{
+    prolong_any(g, Phi, Ns, v, psi, nrhs, s);
 }
 void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s)
 {
@@ -962,9 +985,12 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
         nsplit = 1;
     if ((long)nsplit * g.Nb * Ns * nc > part_cap)
         fail(DFL_EINVAL, "little-operator assembly: scratch too small for the column chunk");
-    if (Ns <= 4 * kRtK && nc <= 4 * kRtJ) {
-        hipLaunchKernelGGL(k_little_columns_rt, dim3(g.Nb * nsplit), dim3(256), sizeof(c64) * (Ns + nc) * kRtCE, s, g,
-                           Phi, Ns, Y, nc, nsplit, fmu, fy, nface, part);
+    if (Ns <= 20 && nc <= 4 * kRtJ) {
+        hipLaunchKernelGGL(k_little_columns_rt<5>, dim3(g.Nb * nsplit), dim3(256), sizeof(c64) * (Ns + nc) * kRtCE, s,
+                           g, Phi, Ns, Y, nc, nsplit, fmu, fy, nface, part);
+    } else if (Ns <= 24 && nc <= 4 * kRtJ) {
+        hipLaunchKernelGGL(k_little_columns_rt<6>, dim3(g.Nb * nsplit), dim3(256), sizeof(c64) * (Ns + nc) * kRtCE, s,
+                           g, Phi, Ns, Y, nc, nsplit, fmu, fy, nface, part);
     } else {
         static std::once_flag attr;
         set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_columns),

@@ -288,6 +288,9 @@ template <typename T> void launch_finite_check(const cpx<T>* x, long n, int* fla
 void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s);
 // psi_b = sum_k Phi_k v_b[blk][k]
 void launch_prolong64(const Geom& g, const c64* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s);
+// the same with an FP32 copy of the basis (FP64 fields, FP64 arithmetic)
+void launch_restrict_b32(const Geom& g, const c32* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s);
+void launch_prolong_b32(const Geom& g, const c32* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s);
 // block Gram-Schmidt in place on Ns fields (modified GS, order l = 0..Ns-1);
 // R (may be null): [Nb][Ns][Ns] coefficients, field l = sum_k R[k][l] basis k
 void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s);

@@ -588,11 +588,12 @@ def test_block_gram_schmidt_block_sizes(dims, b):
     S.close()
 
 
-@pytest.mark.parametrize("Ns,nkv", [(24, 8), (20, 16), (12, 5)])
+@pytest.mark.parametrize("Ns,nkv", [(28, 8), (24, 16), (24, 8), (20, 16), (12, 5)])
 def test_little_operator_column_kernels(Ns, nkv):
-    # eq. (A.1) assembled over chunks of min(Ns, nkv) basis fields: Ns <= 20
-    # with chunks <= 16 runs the register-tiled block products (chunks 16 + 4
-    # and 5 + 5 + 2 here), Ns = 24 the one-pair-per-thread kernel; without
+    # eq. (A.1) assembled over chunks of min(Ns, nkv) basis fields: chunks of
+    # at most 16 run the register-tiled block products, 5 x 4 tiles for
+    # Ns <= 20 (chunks 16 + 4 and 5 + 5 + 2 here) and 6 x 4 for Ns <= 24
+    # (16 + 8 and 8 + 8 + 8), Ns = 28 the one-pair-per-thread kernel; without
     # inverse-iteration steps the basis is the block Gram-Schmidt of the start
     # fields, so the oracle needs no solver
     say(f"little operator Ns={Ns} chunk={min(Ns, nkv)}")
