@@ -279,8 +279,8 @@ def comparisons(torch, U, eta, init):
 def mixed_precision_32x16(torch):
     """32 x 16^3, eps 0.4 (seed 3001), m0 = -0.3, Gaussian source (seed 3002):
     BF16 two-row links, FP32 Schwarz and inner little solves, FP64 GCR and
-    projector; Schwarz block 4^4 or 8 x 4^3 chosen by the autotuner on
-    setup + solve time. Time to solution against the all-FP64 deflated solver
+    projector; Schwarz block 4^4 or 8 x 4^3, then the little solver's grid,
+    chosen by the autotuner on setup + solve time. Time to solution against the all-FP64 deflated solver
     and plain FP64 GCR on the same field. Errors: dirac_apply and one Schwarz
     application against the FP64 oracle; the solution against the all-FP64
     solve to 1e-12, and its true residual recomputed by the oracle's D."""
@@ -296,7 +296,7 @@ def mixed_precision_32x16(torch):
     cands = [dict(sap_block=sb, nmr=NMR, graph=False) for sb in [(4, 4, 4, 4), (8, 4, 4, 4)]]
     tuned = autotune.tune(dims, U, eta[None], init=init, params=base, cands=cands, cache=None, solves_per_setup=1,
                           reps=1)
-    S = Solver(dims, sap_block=tuned["sap_block"], **base)
+    S = Solver(dims, sap_block=tuned["sap_block"], little_grid=tuned["little_grid"], **base)
     S.set_gauge(U)
     ed, initd = S.pack(eta), S.pack(init)
     S.setup(initd)
@@ -313,7 +313,8 @@ def mixed_precision_32x16(torch):
     sap_ref = oracle.sap(U, eta, m0, dims, tuple(tuned["sap_block"]), NCY, NMR)
     s_err = float(np.linalg.norm(sap_gpu - sap_ref) / np.linalg.norm(sap_ref))
     S.close()
-    out = dict(lattice=list(dims), m0=m0, autotune=dict(sap_block=list(tuned["sap_block"]), seconds=tuned["seconds"]),
+    out = dict(lattice=list(dims), m0=m0, autotune=dict(sap_block=list(tuned["sap_block"]), little_grid=tuned["little_grid"],
+                                                         seconds=tuned["seconds"]),
                mixed=dict(t_setup=t_setup, t_solve=t_solve, n_gcr=info.n_gcr, n_little=info.n_little))
     # all-FP64 deflated solver on the same field and block shape (to 1e-10 for the
     # time, to 1e-12 for the reference solution)

@@ -109,7 +109,8 @@ typedef struct {
     dfl_prec sap_prec;     /* arithmetic of the SAP block solves: F64 or F32 */
     dfl_prec little_prec;  /* arithmetic of the little solves inside cycles: F64 or F32 */
     int little_grid;       /* workgroups of the little solver (0: a quarter of the block
-                              count; at most 128 and the block count) */
+                              count); clamped to the block count, to 256 and to the
+                              number of workgroups the device holds at once */
     int little_adapt;      /* 1: inside a cycle, relax the little-solve tolerance in
                               proportion to the fall of the residue (appendix A.5) */
     int little_eo;         /* 1: single-source little solves run GCR on the even-odd

@@ -5,9 +5,12 @@ algorithm (section 6: the preconditioner, hence the iteration counts and the
 inverse-iteration subspace), so candidates are ranked by measured wall time of
 one subspace setup plus ``solves_per_setup`` solves on the caller's gauge
 field, not by kernel time alone. Graph replay of the GCR steps is a third
-axis. The winner is cached in a JSON file keyed by device architecture and
-problem (lattice, deflation blocks, Ns, precisions, number of sources), so a
-second call with the same key measures nothing.
+axis. A second stage then tries, for the winner, the workgroup count of the
+little solver (the grid of its one-launch GCR: more workgroups add apply
+bandwidth and cost more per grid barrier, so the best count depends on the
+block count and Ns). The winner is cached in a JSON file keyed by device
+architecture and problem (lattice, deflation blocks, Ns, precisions, number of
+sources), so a second call with the same key measures nothing.
 
 Every measurement goes through the library's C ABI (Solver); nothing here
 computes any part of the method.
@@ -29,6 +32,9 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_0706_2298
 SAP_SHAPES = [(4, 4, 4, 4), (8, 4, 4, 4), (4, 8, 4, 4), (4, 4, 8, 4), (4, 4, 4, 8)]
 NMR_CHOICES = (3, 4, 5)
 GRAPH_CHOICES = (False, True)
+# workgroups of the little solver (0: the library's default, a quarter of the
+# block count); the library clamps to the block count and to 256
+LITTLE_GRID_CHOICES = (0, 32, 64, 128, 256)
 
 
 def valid_sap_block(dims, sb) -> bool:
@@ -48,6 +54,20 @@ def candidates(dims, shapes: Iterable = SAP_SHAPES, nmr: Iterable = NMR_CHOICES,
     for sb, m, g in itertools.product(shapes, nmr, graphs):
         if valid_sap_block(dims, sb):
             out.append(dict(sap_block=tuple(sb), nmr=int(m), graph=bool(g)))
+    return out
+
+
+def little_grid_candidates(dims, dfl_block=(4, 4, 4, 4), choices: Iterable = LITTLE_GRID_CHOICES) -> list[int]:
+    """Distinct effective little-solver grids for the lattice: 0 (the default,
+    Nb / 4) first, then every explicit count below the block count Nb that
+    differs from the default."""
+    nb = int(np.prod([L // b for L, b in zip(dims, dfl_block)]))
+    default = max(1, min(nb // 4, 256, nb))
+    out = [0]
+    for g in choices:
+        g = int(g)
+        if g > 0 and g <= nb and g != default and g not in out:
+            out.append(g)
     return out
 
 
@@ -83,6 +103,7 @@ def measure_solver(dims, U, eta, init, params: dict, cand: dict, solves_per_setu
     kw = dict(params)
     kw["sap_block"] = cand["sap_block"]
     kw["nmr"] = cand["nmr"]
+    kw["little_grid"] = int(cand.get("little_grid", kw.get("little_grid", 0)))
     nrhs = eta.shape[0] if eta.ndim == 3 else 1
     kw["nrhs_max"] = max(kw.get("nrhs_max", 1), nrhs)
     S = Solver(dims, **kw)
@@ -114,9 +135,12 @@ def measure_solver(dims, U, eta, init, params: dict, cand: dict, solves_per_setu
 
 def tune(dims, U, eta, init=None, params: dict | None = None, cands: list[dict] | None = None,
          cache: str | None = DEFAULT_CACHE, arch: str | None = None, solves_per_setup: int = 3, reps: int = 2,
-         measure: Callable | None = None, verbose: bool = False) -> dict:
-    """Pick the fastest candidate for this problem; returns {sap_block, nmr, graph, seconds, cached}.
+         measure: Callable | None = None, verbose: bool = False, little_grids: Iterable | None = None) -> dict:
+    """Pick the fastest candidate for this problem; returns {sap_block, nmr, graph, little_grid, seconds, cached}.
 
+    Stage 1 ranks ``cands`` (Schwarz block, MR steps, graphs) at the default
+    little-solver grid; stage 2 tries ``little_grids`` (default: every
+    distinct grid of ``little_grid_candidates``) for the stage-1 winner.
     ``measure(cand) -> seconds`` replaces the GPU measurement when given
     (used by the host-side tests of the selection and cache logic).
     """
@@ -146,7 +170,20 @@ def tune(dims, U, eta, init=None, params: dict | None = None, cands: list[dict] 
     t_best, best = min(timings, key=lambda tc: tc[0])
     if not np.isfinite(t_best):
         raise RuntimeError("autotune: no candidate converged")
-    out = dict(sap_block=list(best["sap_block"]), nmr=best["nmr"], graph=best["graph"], seconds=t_best)
+    best = dict(best, little_grid=int(best.get("little_grid", params.get("little_grid", 0))))
+    grids = list(little_grids) if little_grids is not None else little_grid_candidates(
+        dims, params.get("dfl_block", (4, 4, 4, 4)))
+    for lg in grids:
+        if int(lg) == best["little_grid"]:
+            continue
+        c = dict(best, little_grid=int(lg))
+        t = float(measure(c))
+        if verbose:
+            print(f"[autotune] {c} -> {t * 1e3:.2f} ms", flush=True)
+        if t < t_best:
+            t_best, best = t, c
+    out = dict(sap_block=list(best["sap_block"]), nmr=best["nmr"], graph=best["graph"],
+               little_grid=best["little_grid"], seconds=t_best)
     if cache:
         data = _load(cache)
         data[key] = out

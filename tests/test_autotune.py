@@ -30,14 +30,14 @@ def test_tune_picks_fastest_and_caches(tmp_path):
     calls = []
 
     def measure(c):
-        i = cands.index(c)
+        i = cands.index({k: c[k] for k in ("sap_block", "nmr", "graph")})
         calls.append(i)
         return table[i]
 
     eta = np.zeros((1, 4, 12))
     best = autotune.tune(dims, None, eta, params=dict(Ns=20), cands=cands, cache=cache, arch="gfx950",
-                         measure=measure)
-    assert best["cached"] is False and best["seconds"] == 0.5
+                         measure=measure, little_grids=())
+    assert best["cached"] is False and best["seconds"] == 0.5 and best["little_grid"] == 0
     assert (best["sap_block"], best["nmr"], best["graph"]) == (cands[3]["sap_block"], cands[3]["nmr"],
                                                              cands[3]["graph"])
     assert sorted(calls) == list(range(len(cands)))
@@ -51,6 +51,39 @@ def test_tune_picks_fastest_and_caches(tmp_path):
     autotune.tune(dims, None, eta, params=dict(Ns=24), cands=cands, cache=cache, arch="gfx950", measure=measure)
     autotune.tune(dims, None, eta, params=dict(Ns=20), cands=cands, cache=cache, arch="gfx942", measure=measure)
     assert len(json.load(open(cache))) == 3
+
+
+def test_little_grid_candidates():
+    # 32 x 16^3 with 4^4 deflation blocks: Nb = 512, default grid 128
+    assert autotune.little_grid_candidates((32, 16, 16, 16)) == [0, 32, 64, 256]
+    # 8^4: Nb = 16 blocks, default 4; every explicit choice exceeds Nb
+    assert autotune.little_grid_candidates((8, 8, 8, 8)) == [0]
+    # 64 x 32^3: Nb = 8192, default clamped to 256
+    assert autotune.little_grid_candidates((64, 32, 32, 32)) == [0, 32, 64, 128]
+
+
+def test_tune_second_stage_little_grid(tmp_path):
+    cache = str(tmp_path / "tune.json")
+    dims = (32, 16, 16, 16)
+    cands = autotune.candidates(dims, nmr=(4,), graphs=(False,))
+    seen = []
+
+    def measure(c):
+        seen.append(dict(c))
+        t = 1.0 + 0.01 * cands.index({k: c[k] for k in ("sap_block", "nmr", "graph")})
+        return t - (0.3 if c.get("little_grid") == 64 else 0.0)
+
+    best = autotune.tune(dims, None, np.zeros((1, 4, 12)), params=dict(Ns=20), cands=cands, cache=cache,
+                         arch="gfx950", measure=measure)
+    # stage 1 at the default grid, stage 2 over the other grids for the winner (cands[0])
+    assert [c.get("little_grid", 0) for c in seen[:len(cands)]] == [0] * len(cands)
+    stage2 = seen[len(cands):]
+    assert [c["little_grid"] for c in stage2] == [32, 64, 256]
+    assert all(c["sap_block"] == cands[0]["sap_block"] for c in stage2)
+    assert best["little_grid"] == 64 and abs(best["seconds"] - 0.7) < 1e-12
+    hit = autotune.tune(dims, None, np.zeros((1, 4, 12)), params=dict(Ns=20), cands=cands, cache=cache,
+                        arch="gfx950", measure=measure)
+    assert hit["cached"] is True and hit["little_grid"] == 64
 
 
 def test_tune_rejects_all_failed(tmp_path):
@@ -72,5 +105,5 @@ def test_tune_on_gpu(tmp_path):
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(dims, U, eta, init=init, params=params, cands=cands, cache=cache, solves_per_setup=2,
                          reps=1)
-    assert best["cached"] is False and np.isfinite(best["seconds"])
+    assert best["cached"] is False and np.isfinite(best["seconds"]) and best["little_grid"] == 0
     assert autotune.tune(dims, U, eta, init=init, params=params, cands=cands, cache=cache)["cached"] is True
