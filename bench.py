@@ -25,14 +25,15 @@ Also reported (outside the timed region):
   solver with FP64 inner little solves, with the oblique global-mode deflation
   of the little system (appendix A.3 as written) and with a bootstrapped setup
   (section 5.3);
-* 32 x 16^3 in mixed precision (BF16 two-row links; Schwarz block shape from
-  the autotuner) against the all-FP64 deflated solver and plain FP64 GCR, with
+* 32 x 16^3 in mixed precision (BF16 two-row links; Schwarz block shape and
+  little-solver grid from the autotuner) against the all-FP64 deflated solver and plain FP64 GCR, with
   errors against FP64 references;
 * 12 point sources on 48 x 24^3 and 6 on 32 x 16^3 (Ns = 24) as one batch per
   lattice with graph replay, against one-by-one solves and plain FP64 GCR;
 * the learned start fields: the network trained on 16^4 fields (eps 0.5),
   then on 5 held-out 64 x 32^3 fields the setup and solve times against
-  random start fields and plain FP64 GCR;
+  random start fields and plain FP64 GCR, with the forward pass in FP32 and
+  with BF16 operands;
 * the 16^4 workload (two gauge fields x three masses) against undeflated
   solvers;
 * the FP64 CPU oracle timed on a bounded sample, scaled to the headline step.
@@ -421,7 +422,8 @@ def learned_subspace(torch, n_train=20, n_test=5, train_steps=300, m0=-0.56):
     seeded random fields), tested on 5 held-out 64 x 32^3 fields (seeds
     5100..5104) at m0 = -0.56: deflated SAP-GCR setup and solve times with the
     subspace grown from (a) random fields with 3 inverse-iteration steps,
-    (b) network fields with 3 steps and (c) network fields with 1 step, and
+    (b) network fields with 3 steps and (c) with 1 step, (d) network fields
+    from the BF16-operand forward pass with 1 step and (e) with none, and
     plain FP64 GCR on the same field. The network is local (receptive field
     9^4) and the links are i.i.d. per site, so a 16^4 lattice has the local
     statistics of a 64 x 32^3 one."""
@@ -455,6 +457,12 @@ def learned_subspace(torch, n_train=20, n_test=5, train_steps=300, m0=-0.56):
     torch.cuda.empty_cache()
     T = Solver(DIMS, **prm)
     net = StartFieldNet(T, weights)
+    # the BF16 forward keeps a BF16 copy of the weights, allocated on first use
+    T.set_gauge(latgen.make_links(DIMS, eps, 5100))
+    net.forward(torch.zeros(V * 24, dtype=torch.float32, device="cuda"), bf16=True)
+    torch.cuda.synchronize()
+    variants = [("random_k3", 3, None), ("learned_k3", 3, False), ("learned_k1", 1, False),
+                ("learned_bf16_k1", 1, True), ("learned_bf16_k0", 0, True)]
     G = Solver(DIMS, **params(Ns=1, m0=m0, solver=SOLVER_GCR, nkv=32, maxiter=20000, sap_prec=F64, link_prec=F64))
     rows = []
     for j in range(n_test):
@@ -465,17 +473,17 @@ def learned_subspace(torch, n_train=20, n_test=5, train_steps=300, m0=-0.56):
         ed = T.pack(eta)
         row = dict(seed=seed)
         noise = torch.tensor(latgen.net_noise(DIMS, seed + 400), dtype=torch.float32, device="cuda")
-        for name, steps in [("random_k3", 3), ("learned_k3", 3), ("learned_k1", 1)]:
+        for name, steps, bf16 in variants:
             # the random numbers of either start are generated and uploaded
             # before the clock starts
-            if name.startswith("random"):
+            if bf16 is None:
                 f = T.pack(latgen.make_init_fields(DIMS, K, seed + 200))
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
             else:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                f = net.forward(noise)
+                f = net.forward(noise, bf16=bf16)
             make_targets(T, f, steps)
             T.setup(f)
             torch.cuda.synchronize()
@@ -496,7 +504,7 @@ def learned_subspace(torch, n_train=20, n_test=5, train_steps=300, m0=-0.56):
     torch.cuda.empty_cache()
     mean = lambda k, q: float(np.mean([r[k][q] for r in rows]))
     summary = {k: dict(n_gcr=mean(k, "n_gcr"), t_setup=mean(k, "t_setup"), t_solve=mean(k, "t_solve"))
-               for k in ("random_k3", "learned_k3", "learned_k1")}
+               for k, _, _ in variants}
     summary["gcr_f64"] = dict(n_gcr=mean("gcr_f64", "n_gcr"), t_solve=mean("gcr_f64", "t_solve"))
     return dict(train_lattice=list(tdims), test_lattice=list(DIMS), eps=eps, m0=m0, channels=list(CHANNELS),
                 n_train_fields=n_train, train_steps=train_steps, t_targets=t_targets, t_train=t_train,

@@ -47,6 +47,18 @@ int net_features(dfl_ctx *ctx, const float *noise_dev, float *x_dev);
 int conv4d_forward(dfl_ctx *ctx, const float *in_dev, int cin, const float *W_dev, const float *b_dev, int cout,
                    float *z_dev, float *a_dev);
 
+/* conv4d_forward with BF16 operands: every input value and weight is rounded
+ * to BF16 (nearest even) and the products are summed in FP32 on the matrix
+ * cores; bias and activation in FP32. Per output, |z - z_exact| is at most
+ * about 2^-7 sum_o sum_ci |W| |in| (two roundings of 2^-8 relative each).
+ * For inference (the start fields of section 5.3); training uses the FP32
+ * map. Needs L3 % 32 == 0 and L2 % 4 == 0 (DFL_EINVAL otherwise); the
+ * context keeps a BF16 copy of the weights (at most 81 x 96 x 576 entries),
+ * grown on first use (synchronises then). Channel limits and overlap rules
+ * as conv4d_forward. */
+int conv4d_forward_bf16(dfl_ctx *ctx, const float *in_dev, int cin, const float *W_dev, const float *b_dev,
+                        int cout, float *z_dev, float *a_dev);
+
 /* Backward of conv4d_forward for the gradient g [cout][V] of a loss with
  * respect to z: dW[t][ci][co] = sum_x in[ci][x + o_t] g[co][x] and
  * db[co] = sum_x g[co][x] (both overwritten, summed in a fixed order), and,

@@ -60,7 +60,7 @@ EXPORTS = [
     "dfl_set_gauge", "dfl_pack", "dfl_unpack", "dirac_apply", "sap_precond", "dfl_setup", "dfl_get_basis",
     "dfl_get_little", "little_dirac_apply", "little_solve", "deflate_project", "solve", "dfl_residual_history",
     "dfl_profile_enable", "dfl_profile_read", "dfl_last_error", "dfl_use_graphs", "dfl_graph_replays",
-    "dfl_inverse_iteration", "net_features", "conv4d_forward", "conv4d_backward", "conv4d_backward_noalloc",
+    "dfl_inverse_iteration", "net_features", "conv4d_forward", "conv4d_forward_bf16", "conv4d_backward", "conv4d_backward_noalloc",
     "net_outputs_to_fields",
     "net_fields_grad_to_outputs", "deficit_loss", "adam_update",
 ]
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "dfl_inverse_iteration": (i, [vp, vp, i, i]),
         "net_features": (i, [vp, vp, vp]),
         "conv4d_forward": (i, [vp, vp, i, vp, vp, i, vp, vp]),
+        "conv4d_forward_bf16": (i, [vp, vp, i, vp, vp, i, vp, vp]),
         "conv4d_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp, vp]),
         "conv4d_backward_noalloc": (i, [vp, vp, i, vp, i, vp, vp, vp, vp, vp]),
         "net_outputs_to_fields": (i, [vp, vp, i, vp]),
@@ -240,6 +241,10 @@ def net_features(ctx, noise, x):
 
 def conv4d_forward(ctx, x, cin, W, b, cout, z, a=None):
     _check(load().conv4d_forward(ctx, _ptr(x), cin, _ptr(W), _ptr(b), cout, _ptr(z), _ptr(a)))
+
+
+def conv4d_forward_bf16(ctx, x, cin, W, b, cout, z, a=None):
+    _check(load().conv4d_forward_bf16(ctx, _ptr(x), cin, _ptr(W), _ptr(b), cout, _ptr(z), _ptr(a)))
 
 
 def conv4d_backward(ctx, x, cin, W, cout, g, dW, db, din=None, z_in=None):

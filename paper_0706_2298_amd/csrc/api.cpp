@@ -67,7 +67,7 @@ void free_all(dfl_ctx* c)
                     c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
                     c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol, c->Mt64, c->Mt32, c->lw1, c->lw2,
                     c->gsR, c->gU, c->gW, c->gQ, c->gZ, c->gQ32, c->gZ32, c->gC, c->Cl64, c->Cl32,
-                    c->gAinv, c->gGw, c->bootF, c->bootT};
+                    c->gAinv, c->gGw, c->bootF, c->bootT, c->net_wbf};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -1758,6 +1758,26 @@ int conv4d_forward(dfl_ctx* c, const float* in, int cin, const float* W, const f
     if (z == in || a == in)
         fail(DFL_EINVAL, "outputs must not overlap the input");
     launch_conv_forward(c->g, in, cin, W, b, cout, z, a, c->stream);
+    HIPCHECK(hipGetLastError());
+    API_END
+}
+
+int conv4d_forward_bf16(dfl_ctx* c, const float* in, int cin, const float* W, const float* b, int cout, float* z,
+                        float* a)
+{
+    API_BEGIN
+    need_ctx(c);
+    need_ptr(in, "in");
+    need_ptr(W, "W");
+    need_ptr(z, "z");
+    if (cin < 1 || cin > kNetMaxCin || cout < 1 || cout > kNetMaxCout)
+        fail(DFL_EINVAL, "channels: 1 <= cin <= 96, 1 <= cout <= 576");
+    if (z == in || a == in)
+        fail(DFL_EINVAL, "outputs must not overlap the input");
+    if (!conv_bf16_fits(c->g))
+        fail(DFL_EINVAL, "the BF16 convolution needs L3 % 32 == 0 and L2 % 4 == 0");
+    c->net_wbf = grow<uint16_t>(c, c->net_wbf, c->net_wbf_n, conv_bf16_weight_elems(cin, cout));
+    launch_conv_forward_bf16(c->g, in, cin, W, b, cout, z, a, c->net_wbf, c->stream);
     HIPCHECK(hipGetLastError());
     API_END
 }

@@ -162,6 +162,8 @@ struct dfl_ctx {
     // start-field network scratch (grown on demand)
     float* net_part = nullptr;   // weight-gradient partial sums
     size_t net_part_n = 0;
+    uint16_t* net_wbf = nullptr; // BF16 weights of the BF16 forward
+    size_t net_wbf_n = 0;
     dfl::c64* loss_Y = nullptr;  // deficit loss: per-block G^-1 Psi^+ T
     double* loss_buf = nullptr;  // [Nb][K] block norms, [Nb][K] projections, [K] weights
     double* loss_host = nullptr;
@@ -333,6 +335,12 @@ void launch_net_features(const Geom& g, const c64* U64, const float* noise, floa
 void launch_conv_forward(const Geom& g, const float* in, int cin, const float* W, const float* b, int cout, float* z,
                          float* a, hipStream_t s);
 size_t conv_wgrad_chunk_floats(const Geom& g, int cin, int cout, long* chunk, int* nchunk);
+// BF16-operand forward (FP32 sums) for lattices with L3 % 32 == 0 and L2 % 4 == 0
+// (conv_bf16_fits); Wb holds conv_bf16_weight_elems(cin, cout) BF16 entries
+bool conv_bf16_fits(const Geom& g);
+size_t conv_bf16_weight_elems(int cin, int cout);
+void launch_conv_forward_bf16(const Geom& g, const float* in, int cin, const float* W, const float* b, int cout,
+                              float* z, float* a, uint16_t* Wb, hipStream_t s);
 void launch_conv_backward(const Geom& g, const float* in, int cin, const float* W, int cout, const float* gr,
                           float* dW, float* db, float* din, const float* zprev, float* part, long chunk, int nchunk,
                           hipStream_t s);

@@ -234,6 +234,137 @@ __global__ __launch_bounds__(256) void k_conv_mfma(Lat lt, const float* __restri
     }
 }
 
+// Forward map with BF16 operands on the matrix cores: inputs and weights
+// rounded to BF16 (nearest even), products summed in FP32
+// (v_mfma_f32_16x16x32_bf16), bias and activation in FP32. The weights come
+// pre-converted as Wb[t][oc][ic] (ic padded to a multiple of 32 and oc to
+// the channel tile with zeros), so a tap's 32-channel chunk is a straight
+// 16-byte copy into LDS. Workgroup: kBNL consecutive x2 lines of kBTS sites
+// along x3 (one line per wavefront) and 16 OT output channels; every
+// wavefront keeps OT x 2 tiles of 16 x 16 accumulators, so one staged
+// operand row feeds two (weights) or OT (inputs) instructions. For each of
+// the 27 neighbour line offsets (o0, o1, o2) and each 32-channel chunk the
+// four lines' segments with their +-1 halo along x3 and the three taps'
+// weights (o3 = -1, 0, 1) are staged; the taps read the segments at shifts
+// of one site. Lane l supplies A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j < 8 (the contraction index is summed, so
+// only its being the same for A and B matters) and holds
+// C[4 (l / 16) + i][l % 16], i < 4.
+constexpr int kBTS = 32;       // sites per line segment
+constexpr int kBNL = 4;        // x2 lines per workgroup (one per wavefront)
+constexpr int kBK = 32;        // input channels per chunk (the instruction's K)
+constexpr int kBRow = kBK + 8; // LDS row stride in BF16 elements (80 bytes)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+template <int OT>
+__global__ __launch_bounds__(256) void k_conv_bf16(Lat lt, const float* __restrict__ in, int cin, int cinP,
+                                                   const uint16_t* __restrict__ Wb, int coutP,
+                                                   const float* __restrict__ bias, int cout, float* __restrict__ out,
+                                                   float* __restrict__ act)
+{
+    constexpr int OCT = 16 * OT;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[kBNL][kBTS + 2][kBRow];
+    __shared__ __attribute__((aligned(16))) uint16_t ws[3][OCT][kBRow];
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const long V = lt.V;
+    const int n_oct = coutP / OCT;
+    const long grp = blockIdx.x / n_oct;  // channel tiles of one site group are adjacent
+    const int oc0 = (int)(blockIdx.x - grp * n_oct) * OCT;
+    const int nseg = lt.L[3] / kBTS, ngx2 = lt.L[2] / kBNL;
+    long r = grp;
+    const int seg = (int)(r % nseg);
+    r /= nseg;
+    const int x2g = (int)(r % ngx2) * kBNL;
+    r /= ngx2;
+    const int x1 = (int)(r % lt.L[1]);
+    const int x0 = (int)(r / lt.L[1]);
+    const int x3_0 = seg * kBTS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kr = lane >> 4, kc = lane & 15;
+    f4 acc[OT][2];
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot)
+        acc[ot][0] = acc[ot][1] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int l = 0; l < 27; ++l) {
+        const int o0 = l / 9 - 1, o1 = (l / 3) % 3 - 1, o2 = l % 3 - 1;
+        int y0 = x0 + o0, y1 = x1 + o1;
+        y0 = y0 < 0 ? y0 + lt.L[0] : (y0 >= lt.L[0] ? y0 - lt.L[0] : y0);
+        y1 = y1 < 0 ? y1 + lt.L[1] : (y1 >= lt.L[1] ? y1 - lt.L[1] : y1);
+        const long base01 = (long)y0 * lt.str[0] + (long)y1 * lt.str[1];
+        for (int c0 = 0; c0 < cinP; c0 += kBK) {
+            __syncthreads();  // the previous chunk's operands are consumed
+            for (int e = threadIdx.x; e < kBNL * kBK * (kBTS + 2); e += 256) {
+                const int j = e % (kBTS + 2);
+                const int rest = e / (kBTS + 2);
+                const int ic = rest % kBK, ln = rest / kBK;
+                int y2 = x2g + ln + o2;
+                y2 = y2 < 0 ? y2 + lt.L[2] : (y2 >= lt.L[2] ? y2 - lt.L[2] : y2);
+                int y3 = x3_0 - 1 + j;
+                y3 = y3 < 0 ? y3 + lt.L[3] : (y3 >= lt.L[3] ? y3 - lt.L[3] : y3);
+                const float v = c0 + ic < cin ? in[(long)(c0 + ic) * V + base01 + (long)y2 * lt.str[2] + y3] : 0.f;
+                xs[ln][j][ic] = (uint16_t)bf16_bits(v);
+            }
+            for (int e = threadIdx.x; e < 3 * OCT * (kBK / 8); e += 256) {
+                const int v8 = e % (kBK / 8);
+                const int rest = e / (kBK / 8);
+                const int oc = rest % OCT, q = rest / OCT;
+                const long t = l * 3 + q;  // tap of (o0, o1, o2, o3 = q - 1)
+                *reinterpret_cast<u16x8*>(&ws[q][oc][8 * v8]) =
+                    *reinterpret_cast<const u16x8*>(Wb + (t * coutP + oc0 + oc) * cinP + c0 + 8 * v8);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                // the neighbour x3 + (q - 1) of segment site i sits in staged column i + q
+                bf16x8 b[2];
+#pragma unroll
+                for (int st = 0; st < 2; ++st)
+                    b[st] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&xs[w][st * 16 + kc + q][8 * kr]));
+#pragma unroll
+                for (int ot = 0; ot < OT; ++ot) {
+                    const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&ws[q][ot * 16 + kc][8 * kr]));
+#pragma unroll
+                    for (int st = 0; st < 2; ++st)
+                        acc[ot][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[st], acc[ot][st], 0, 0, 0);
+                }
+            }
+        }
+    }
+    const long line = ((long)x0 * lt.L[1] + x1) * lt.L[2] + x2g + w;
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot)
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const long site = base_site(lt, line, x3_0 + st * 16 + kc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int oc = oc0 + ot * 16 + 4 * kr + i;
+                if (oc >= cout)
+                    continue;
+                const float v = acc[ot][st][i] + (bias ? bias[oc] : 0.f);
+                out[(long)oc * V + site] = v;
+                if (act)
+                    act[(long)oc * V + site] = silu_f(v);
+            }
+        }
+}
+
+// Wb[t][oc][ic] = bf16(W[t][ic][oc]) on the padded [81][coutP][cinP] grid (zeros outside)
+__global__ __launch_bounds__(256) void k_weights_bf16(const float* __restrict__ W, int cin, int cout, int cinP,
+                                                      int coutP, uint16_t* __restrict__ Wb)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 81L * coutP * cinP)
+        return;
+    const int ic = (int)(e % cinP);
+    const long rest = e / cinP;
+    const int oc = (int)(rest % coutP);
+    const long t = rest / coutP;
+    const float v = (ic < cin && oc < cout) ? W[(t * cin + ic) * cout + oc] : 0.f;
+    Wb[e] = (uint16_t)bf16_bits(v);
+}
+
 // Weight gradient, partial over a chunk of sites:
 // part[chunk][t][ci][co] = sum_{y in chunk} in[ci][y + o_t] g[co][y].
 // Workgroup (t, co tile of kWT, site chunk); thread (ci group, co), the
@@ -699,6 +830,32 @@ void launch_conv_forward(const Geom& g, const float* in, int cin, const float* W
     else
         hipLaunchKernelGGL(k_conv<false>, dim3(site_blocks(g.V), (cout + kCO - 1) / kCO), dim3(256), 0, s, lt, in,
                            cin, W, cin, cout, b, cout, z, a, nullptr);
+}
+
+bool conv_bf16_fits(const Geom& g) { return g.L[3] % kBTS == 0 && g.L[2] % kBNL == 0; }
+
+size_t conv_bf16_weight_elems(int cin, int cout)
+{
+    const int ot = cout <= 32 ? 2 : 4;
+    const int cinP = (cin + kBK - 1) / kBK * kBK, coutP = (cout + 16 * ot - 1) / (16 * ot) * (16 * ot);
+    return 81ul * (size_t)cinP * (size_t)coutP;
+}
+
+void launch_conv_forward_bf16(const Geom& g, const float* in, int cin, const float* W, const float* b, int cout,
+                              float* z, float* a, uint16_t* Wb, hipStream_t s)
+{
+    const Lat lt = make_lat(g);
+    const int ot = cout <= 32 ? 2 : 4;
+    const int cinP = (cin + kBK - 1) / kBK * kBK, coutP = (cout + 16 * ot - 1) / (16 * ot) * (16 * ot);
+    const long nw = 81L * cinP * coutP;
+    hipLaunchKernelGGL(k_weights_bf16, dim3(site_blocks(nw)), dim3(256), 0, s, W, cin, cout, cinP, coutP, Wb);
+    const unsigned ngrp = (unsigned)(g.V / (kBTS * kBNL));
+    if (ot == 2)
+        hipLaunchKernelGGL(k_conv_bf16<2>, dim3(ngrp * (unsigned)(coutP / 32)), dim3(256), 0, s, lt, in, cin, cinP,
+                           Wb, coutP, b, cout, z, a);
+    else
+        hipLaunchKernelGGL(k_conv_bf16<4>, dim3(ngrp * (unsigned)(coutP / 64)), dim3(256), 0, s, lt, in, cin, cinP,
+                           Wb, coutP, b, cout, z, a);
 }
 
 void launch_conv_backward(const Geom& g, const float* in, int cin, const float* W, int cout, const float* gr,

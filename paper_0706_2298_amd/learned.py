@@ -62,10 +62,12 @@ class StartFieldNet:
                         b.cpu().numpy().astype(np.float64)))
         return out
 
-    def forward(self, noise):
+    def forward(self, noise, bf16=False):
         """Start fields (Ns native FP64 fields) for the solver's current gauge field.
 
-        noise: (V, 24) canonical-order array or device tensor.
+        noise: (V, 24) canonical-order array or device tensor. bf16: run the
+        convolutions with BF16 operands and FP32 sums (inference only; needs
+        L3 % 32 == 0 and L2 % 4 == 0).
         """
         torch = self.torch
         if isinstance(noise, np.ndarray):
@@ -79,7 +81,8 @@ class StartFieldNet:
             cin, cout = self.channels[i], self.channels[i + 1]
             z = self._planes(cout)
             a = self._planes(cout) if i < n - 1 else None
-            binding.conv4d_forward(ctx, acts[-1], cin, self.W[i], self.b[i], cout, z, a)
+            conv = binding.conv4d_forward_bf16 if bf16 else binding.conv4d_forward
+            conv(ctx, acts[-1], cin, self.W[i], self.b[i], cout, z, a)
             zs.append(z)
             acts.append(a if a is not None else z)
         fields = self.S.field(self.Ns, F64)

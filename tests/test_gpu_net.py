@@ -230,3 +230,60 @@ def test_conv_both_paths(dims, blk, cin, cout):
     dxr, _, _ = onet.conv4d_backward(x, W, g, dims)
     assert rel(din.cpu().numpy().reshape(cin, V).T, dxr * onet.silu_grad(zin)) < 2e-5
     s.close()
+
+
+def bf16_round(a):
+    """Round to BF16 (nearest even) through FP32, as the device does with FP32 inputs."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("dims,blk", [((4, 4, 8, 32), (2, 2, 2, 4)), ((4, 4, 4, 64), (2, 2, 2, 4))])
+@pytest.mark.parametrize("cin,cout", [(5, 7), (96, 37), (32, 576), (32, 32), (8, 33)])
+def test_conv_forward_bf16(dims, blk, cin, cout):
+    # BF16 operands, FP32 sums. Two checks per output:
+    #  (1) against the exact FP64 map: |z - z_exact| <= (2u + u^2 + n 2^-24) sum|W||x| + 2^-24 |z|,
+    #      u = 2^-8 the BF16 unit roundoff, n = 81 cin products (rounding of both operands,
+    #      then FP32 summation in any order, then the FP32 bias add);
+    #  (2) against the FP64 map of the BF16-rounded operands: only the FP32 summation error.
+    say(f"conv bf16 {dims} {cin}->{cout}")
+    s = Solver(dims, dfl_block=blk, sap_block=blk, Ns=2, nkv=2, little_nkv=2, m0=-0.2, nrhs_max=1)
+    try:
+        torch = s.torch
+        V = int(np.prod(dims))
+        rng = np.random.default_rng(cin * 11 + cout + dims[3])
+        x = rng.standard_normal((V, cin))
+        W = rng.standard_normal((3, 3, 3, 3, cin, cout)) / np.sqrt(81 * cin)
+        b = rng.standard_normal(cout)
+        xd, Wd, bd = dev(x.T, torch), dev(W.reshape(81, cin, cout), torch), dev(b, torch)
+        z = torch.empty(cout * V, dtype=torch.float32, device="cuda")
+        a = torch.empty_like(z)
+        binding.conv4d_forward_bf16(s.ctx, xd, cin, Wd, bd, cout, z, a)
+        zg = z.cpu().numpy().reshape(cout, V).T.astype(np.float64)
+        ag = a.cpu().numpy().reshape(cout, V).T.astype(np.float64)
+        x32, W32, b32 = (np.float32(v).astype(np.float64) for v in (x, W, b))
+        n = 81 * cin
+        scale = onet.conv4d(np.abs(x32), np.abs(W32), np.zeros(cout), dims)
+        u = 2.0 ** -8
+        exact = onet.conv4d(x32, W32, b32, dims)
+        bound = (2 * u + u * u + n * 2.0 ** -24) * scale + 2.0 ** -24 * np.abs(exact) + 1e-30
+        assert np.all(np.abs(zg - exact) <= bound), float(np.max(np.abs(zg - exact) / bound))
+        rounded = onet.conv4d(bf16_round(x32), bf16_round(W32), b32, dims)
+        tight = n * 2.0 ** -24 * scale * (1 + 2 * u) + 2.0 ** -24 * np.abs(rounded) + 1e-30
+        assert np.all(np.abs(zg - rounded) <= tight), float(np.max(np.abs(zg - rounded) / tight))
+        # the operands really are rounded (not an FP32 path)
+        assert np.max(np.abs(zg - exact)) > 1e-5 * np.max(np.abs(exact))
+        assert rel(ag, onet.silu(zg)) < 1e-6
+    finally:
+        s.close()
+
+
+def test_conv_forward_bf16_refuses_other_lattices(S):
+    say("conv bf16 lattice check")
+    torch = S.torch
+    x = torch.zeros(4 * V, dtype=torch.float32, device="cuda")
+    W = torch.zeros(81 * 4 * 4, dtype=torch.float32, device="cuda")
+    z = torch.empty(4 * V, dtype=torch.float32, device="cuda")
+    with pytest.raises(binding.DflError):
+        binding.conv4d_forward_bf16(S.ctx, x, 4, W, None, 4, z, None)  # L3 = 8
