@@ -14,15 +14,6 @@ template <typename T> struct cpx {
     T re, im;
 };
 
-// round-to-nearest-even float -> bfloat16 bits (finite inputs)
-__device__ inline uint32_t bf16_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7fffu + lsb;
-    return u >> 16;
-}
-
 template <typename T> __host__ __device__ inline cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
 template <typename T> __device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T> __device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }

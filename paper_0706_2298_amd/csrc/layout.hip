@@ -55,6 +55,15 @@ __global__ __launch_bounds__(256) void k_unpack_field(Geom g, const cpx<T>* __re
     }
 }
 
+// round-to-nearest-even float -> bfloat16 bits (finite inputs)
+__device__ inline uint32_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return u >> 16;
+}
+
 // Links in two-row form ([4][6] entries per site) in FP64, FP32 and BF16; the
 // third row is rebuilt as conj(row0 x row1) wherever a link is used. flag |= 1
 // where the given third row differs from that (the link is not SU(3)).

@@ -212,79 +212,103 @@ __device__ inline void reduce_slots(const double* __restrict__ part, int G, int 
 }
 
 // y_blk = alpha s_blk + beta sum_{d0 <= d < d1} Mat[blk][d] u_{nbr_d(blk)} for
-// the blocks at the listed owned positions (list null: positions 0..nlist-1). Mat is
-// stored transposed, Mat[blk][d][l][k] = (block d of blk)[k][l]. Task
-// (block, d, k) forms one term of row k (Ns multiply-adds over l, reading Mat
-// coalesced in k); the terms of a row are summed from LDS in a fixed order.
-// Blocks are processed LT1 / ((d1 - d0) Ns) at a time; lds holds 2 LT1 doubles.
-constexpr int kApplyChunk = 10;  // measured: 12 no faster on 64 x 32^3, 24 spills
+// the blocks at the listed owned positions (list null: positions 0..nlist-1).
+// Mat is stored transposed, Mat[blk][d][l][k] = (block d of blk)[k][l], so
+// the threads of a block's rows k read Mat coalesced in k (the vector entry
+// u_{nbr_d}[l] is the same address for all of them). A thread sums all
+// terms of one row (or, when the rows do not fill the workgroup, those of a
+// contiguous range of d, the ranges meeting in lds in a fixed order), with
+// kApplyChunk matrix and vector loads of kApplyD neighbour blocks in flight
+// at a time, and writes its row without waiting for the others: y may alias
+// u where the rows written and the entries read lie on different blocks (the
+// even-odd updates). Ends with a workgroup barrier.
+constexpr int kApplyChunk = 8;
 template <typename T>
 __device__ inline void apply_blocks(const LittleCtx<T>& c, const int* list, int nlist, const cpx<T>* __restrict__ Mat,
-                                    int d0, int d1, const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ s,
-                                    double alpha, double beta, cpx<T>* __restrict__ y, double* lds)
+                                    int d0, int d1, const cpx<T>* u, const cpx<T>* s, double alpha, double beta,
+                                    cpx<T>* y, double* lds)
 {
+    constexpr int kApplyD = 2;
     const Geom& g = c.a.g;
     const int Ns = c.a.Ns;
     const int nd = d1 - d0;
-    const int per = nd * Ns;
-    const int bpr = per <= LT1 ? LT1 / per : 1;
-    for (int i0 = 0; i0 < nlist; i0 += bpr) {
-        {
-            const int task = c.t;
-            const int ib = task / per;
-            const int rem = task - ib * per;
-            const int d = d0 + rem / Ns;
-            const int k = rem - (d - d0) * Ns;
-            if (ib < bpr && i0 + ib < nlist) {
-                const int own = list ? list[i0 + ib] : i0 + ib;
-                const int blk = c.g + own * c.G;
-                const int nbr = d == 0 ? blk : (c.nbr ? c.nbr[8 * own + d - 1] : nbr_block(g, blk, d));
-                const cpx<T>* M = Mat + ((long)blk * 9 + d) * Ns * Ns + k;
-                const cpx<T>* vv = u + (long)nbr * Ns;
-                double re = 0.0, im = 0.0;
-                // kApplyChunk loads of M and of u are issued before their
-                // multiply-adds, so the chunk costs one memory round trip
+    const int rows = nlist * Ns;
+    const int ng = rows > 0 ? max(1, min(LT1 / rows, nd)) : 1;
+    const int per = (nd + ng - 1) / ng;
+    for (int t0 = 0; t0 < ng * rows; t0 += LT1) {
+        const int task = t0 + c.t;
+        if (task < ng * rows) {
+            const int gq = task / rows, row = task - gq * rows;
+            const int ib = row / Ns, k = row - ib * Ns;
+            const int own = list ? list[ib] : ib;
+            const int blk = c.g + own * c.G;
+            const int da = d0 + gq * per, dz = min(d1, da + per);
+            double re = 0.0, im = 0.0;
+            for (int db = da; db < dz; db += kApplyD) {
+                const cpx<T>* M[kApplyD];
+                const cpx<T>* uu[kApplyD];
+#pragma unroll
+                for (int v = 0; v < kApplyD; ++v) {
+                    const int d = min(db + v, dz - 1);  // past dz: a valid block, dropped below
+                    const int nb = d == 0 ? blk : (c.nbr ? c.nbr[8 * own + d - 1] : nbr_block(g, blk, d));
+                    M[v] = Mat + ((long)blk * 9 + d) * Ns * Ns + k;
+                    uu[v] = u + (long)nb * Ns;
+                }
                 for (int l0 = 0; l0 < Ns; l0 += kApplyChunk) {
-                    cpx<T> mv[kApplyChunk], uv[kApplyChunk];
+                    cpx<T> mv[kApplyD][kApplyChunk], uv[kApplyD][kApplyChunk];
 #pragma unroll
-                    for (int q = 0; q < kApplyChunk; ++q)
-                        if (l0 + q < Ns) {
-                            mv[q] = M[(long)(l0 + q) * Ns];
-                            uv[q] = vv[l0 + q];
+                    for (int v = 0; v < kApplyD; ++v)
+#pragma unroll
+                        for (int q = 0; q < kApplyChunk; ++q) {
+                            const int l = min(l0 + q, Ns - 1);  // past Ns: re-read, dropped below
+                            mv[v][q] = M[v][(long)l * Ns];
+                            uv[v][q] = uu[v][l];
                         }
 #pragma unroll
-                    for (int q = 0; q < kApplyChunk; ++q)
-                        if (l0 + q < Ns) {
-                            const cpx<T> p = mv[q], w = uv[q];
-                            re += (double)p.re * (double)w.re - (double)p.im * (double)w.im;
-                            im += (double)p.re * (double)w.im + (double)p.im * (double)w.re;
-                        }
+                    for (int v = 0; v < kApplyD; ++v)
+#pragma unroll
+                        for (int q = 0; q < kApplyChunk; ++q)
+                            if (db + v < dz && l0 + q < Ns) {
+                                const cpx<T> p = mv[v][q], w = uv[v][q];
+                                re += (double)p.re * (double)w.re - (double)p.im * (double)w.im;
+                                im += (double)p.re * (double)w.im + (double)p.im * (double)w.re;
+                            }
                 }
-                lds[2 * task] = re;
-                lds[2 * task + 1] = im;
             }
-        }
-        __syncthreads();
-        for (int q = c.t; q < bpr * Ns; q += LT1) {
-            const int jb = q / Ns, kk = q - jb * Ns;
-            if (i0 + jb < nlist) {
-                double sr = 0.0, si = 0.0;
-                for (int dd = 0; dd < nd; ++dd) {
-                    sr += lds[2 * (jb * per + dd * Ns + kk)];
-                    si += lds[2 * (jb * per + dd * Ns + kk) + 1];
-                }
-                const int blk = c.g + (list ? list[i0 + jb] : i0 + jb) * c.G;
-                const long i = (long)blk * Ns + kk;
-                double yr = beta * sr, yi = beta * si;
+            if (ng == 1) {
+                const long i = (long)blk * Ns + k;
+                double yr = beta * re, yi = beta * im;
                 if (alpha != 0.0) {
                     yr += alpha * (double)s[i].re;
                     yi += alpha * (double)s[i].im;
                 }
                 y[i] = cpx<T>{(T)yr, (T)yi};
+            } else {
+                lds[2 * task] = re;
+                lds[2 * task + 1] = im;
             }
         }
-        __syncthreads();
     }
+    if (ng > 1) {
+        __syncthreads();
+        for (int row = c.t; row < rows; row += LT1) {
+            double sr = 0.0, si = 0.0;
+            for (int gq = 0; gq < ng; ++gq) {
+                sr += lds[2 * (gq * rows + row)];
+                si += lds[2 * (gq * rows + row) + 1];
+            }
+            const int ib = row / Ns, k = row - ib * Ns;
+            const int blk = c.g + (list ? list[ib] : ib) * c.G;
+            const long i = (long)blk * Ns + k;
+            double yr = beta * sr, yi = beta * si;
+            if (alpha != 0.0) {
+                yr += alpha * (double)s[i].re;
+                yi += alpha * (double)s[i].im;
+            }
+            y[i] = cpx<T>{(T)yr, (T)yi};
+        }
+    }
+    __syncthreads();
 }
 
 // ||v||^2 over the workgroup's vector entries -> part[slot][g]

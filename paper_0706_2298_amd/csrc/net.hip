@@ -250,6 +250,14 @@ __global__ __launch_bounds__(256) void k_conv_mfma(Lat lt, const float* __restri
 // B[8 (l / 16) + j][l % 16], j < 8 (the contraction index is summed, so
 // only its being the same for A and B matters) and holds
 // C[4 (l / 16) + i][l % 16], i < 4.
+// round-to-nearest-even float -> bfloat16 bits (finite inputs)
+__device__ inline uint32_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
 constexpr int kBTS = 32;       // sites per line segment
 constexpr int kBNL = 4;        // x2 lines per workgroup (one per wavefront)
 constexpr int kBK = 32;        // input channels per chunk (the instruction's K)
