@@ -40,6 +40,8 @@ struct SapGeom {
     int lstr[4];  // in-block strides (lexicographic, y3 fastest)
     int Vsb;      // sites per SAP block
     int n_per_colour;
+    int one_rl;   // one field: 1 = one lane per site, two blocks per CU (many blocks per colour),
+                  // 0 = lane pairs, one block per CU
 };
 
 // links, two rows per matrix (the third is conj(row0 x row1)): FP64, FP32 and
@@ -195,6 +197,8 @@ void launch_unpack_field32(const Geom& g, const c32* nat, c64* canon, int nrhs, 
 // flag |= 1 if some link's third row is not conj(row0 x row1)
 void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, int* flag, hipStream_t s);
 void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s);
+// nb fields of n entries: out_b = in_b / sqrt(nrm2[b * cstride]) in FP32
+void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s);
 void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s);
 
 // ----------------------------------------------------------------- dirac.hip

@@ -5,6 +5,8 @@
 // order (common.h). Links: FP64, FP32 and BF16 store the first two rows only
 // (24 entries per site), the third row being rebuilt as conj(row0 x row1),
 // which is exact for SU(3) matrices.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace dfl {
@@ -113,6 +115,20 @@ __global__ __launch_bounds__(256) void k_f64_to_f32(const c64* __restrict__ in, 
         out[i] = c32{(float)in[i].re, (float)in[i].im};
 }
 
+// out_b = in_b / sqrt(nrm2[b * cstride]) rounded to FP32 (the scale in FP64),
+// field b of n entries at b * n; blockIdx.y = field
+__global__ __launch_bounds__(256) void k_f64_to_f32_scaled(const c64* __restrict__ in, c32* __restrict__ out, long n,
+                                                           const double* __restrict__ nrm2, int cstride)
+{
+    const int b = blockIdx.y;
+    const double q = nrm2[(long)b * cstride];
+    const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    in += (long)b * n;
+    out += (long)b * n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = c32{(float)(in[i].re * f), (float)(in[i].im * f)};
+}
+
 __global__ __launch_bounds__(256) void k_f32_to_f64(const c32* __restrict__ in, c64* __restrict__ out, long n)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -148,6 +164,14 @@ void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s)
 {
     if (n > 0)
         hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+}
+void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s)
+{
+    if (n > 0 && nb > 0) {
+        const long blocks = std::min<long>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_f64_to_f32_scaled, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
+                           nrm2, cstride);
+    }
 }
 void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s)
 {

@@ -729,12 +729,14 @@ template <typename T, typename L>
 void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
             int nrhs, int init, c64* out64, hipStream_t s, const cpx<T>* clov);
 
-// Blocks of up to 256 sites: links in registers. One field: lane pairs, one
-// block per CU at two wavefronts per SIMD (the blocks of one colour leave CUs
-// free; 16^4 with 4^4 blocks: 5% faster than one lane per site); several
-// fields: one lane per site, two blocks per CU (16 fields on 16^4: 12% faster
-// than the generic kernel at three blocks per CU, which re-reads the links
-// every MR step, and 28% faster than lane pairs at one block per CU).
+// Blocks of up to 256 sites: links in registers. One field on lattices whose
+// colours hold few blocks per CU (sg.one_rl == 0): lane pairs, one block per
+// CU at two wavefronts per SIMD (16^4 and 32 x 16^3 with 4^4 blocks: 11%
+// faster than one lane per site); several fields, or one field with many
+// blocks per colour: one lane per site, two blocks per CU (16 fields on 16^4:
+// 12% faster than the generic kernel at three blocks per CU, which re-reads
+// the links every MR step, and 28% faster than lane pairs; one field on
+// 64 x 32^3: 346 against 475 us per sweep with lane pairs).
 // Larger blocks, the clover term and antiperiodic time: the generic kernel.
 template <typename L>
 void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
@@ -745,7 +747,7 @@ void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, 
         return;
     }
     size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
-    if (nrhs == 1) {
+    if (nrhs == 1 && !sg.one_rl) {
         int threads = ((2 * sg.Vsb + 63) / 64) * 64;
         hipLaunchKernelGGL((k_sap_pair<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
                            4.0f + m0, nmr, colour, nrhs, init, out64);
