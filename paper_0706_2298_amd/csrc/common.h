@@ -10,7 +10,7 @@ namespace dfl {
 
 // ------------------------------------------------------------ complex
 
-template <typename T> struct cpx {
+template <typename T> struct alignas(2 * sizeof(T)) cpx {
     T re, im;
 };
 
@@ -83,12 +83,41 @@ template <typename T> struct su3 {
 };
 
 // U v
+// fused multiply-add a * b + c (one rounding)
+template <typename T> __device__ inline T fmadd(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == sizeof(double))
+        return __builtin_fma(a, b, c);
+    else
+        return __builtin_fmaf(a, b, c);
+}
+
+// c + a * b as four fused multiply-adds
+template <typename T> __device__ inline cpx<T> cfma(cpx<T> a, cpx<T> b, cpx<T> c)
+{
+    return {fmadd(-a.im, b.im, fmadd(a.re, b.re, c.re)), fmadd(a.im, b.re, fmadd(a.re, b.im, c.im))};
+}
+
+// Row sums of three complex products as one chain of fused multiply-adds per
+// real part (a sum of products written with complex operators compiles to a
+// multiply, a multiply-add and an add per product and component instead).
 template <typename T> __device__ inline cvec3<T> mul(const su3<T>& u, const cvec3<T>& v)
 {
     cvec3<T> r;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-        r.c[a] = u.m[a][0] * v.c[0] + u.m[a][1] * v.c[1] + u.m[a][2] * v.c[2];
+    for (int a = 0; a < 3; ++a) {
+        T re = u.m[a][0].re * v.c[0].re, im = u.m[a][0].re * v.c[0].im;
+        re = fmadd(-u.m[a][0].im, v.c[0].im, re);
+        im = fmadd(u.m[a][0].im, v.c[0].re, im);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+            re = fmadd(u.m[a][b].re, v.c[b].re, re);
+            re = fmadd(-u.m[a][b].im, v.c[b].im, re);
+            im = fmadd(u.m[a][b].re, v.c[b].im, im);
+            im = fmadd(u.m[a][b].im, v.c[b].re, im);
+        }
+        r.c[a] = cpx<T>{re, im};
+    }
     return r;
 }
 // U^dagger v
@@ -96,16 +125,38 @@ template <typename T> __device__ inline cvec3<T> mul_dag(const su3<T>& u, const 
 {
     cvec3<T> r;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-        r.c[a] = cmul_conj(u.m[0][a], v.c[0]) + cmul_conj(u.m[1][a], v.c[1]) + cmul_conj(u.m[2][a], v.c[2]);
+    for (int a = 0; a < 3; ++a) {
+        T re = u.m[0][a].re * v.c[0].re, im = u.m[0][a].re * v.c[0].im;
+        re = fmadd(u.m[0][a].im, v.c[0].im, re);
+        im = fmadd(-u.m[0][a].im, v.c[0].re, im);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+            re = fmadd(u.m[b][a].re, v.c[b].re, re);
+            re = fmadd(u.m[b][a].im, v.c[b].im, re);
+            im = fmadd(u.m[b][a].re, v.c[b].im, im);
+            im = fmadd(-u.m[b][a].im, v.c[b].re, im);
+        }
+        r.c[a] = cpx<T>{re, im};
+    }
     return r;
 }
 // third row of an SU(3) matrix from the first two: conj(row0 x row1)
 template <typename T> __device__ inline void complete_third_row(su3<T>& u)
 {
-    u.m[2][0] = conjg(u.m[0][1] * u.m[1][2] - u.m[0][2] * u.m[1][1]);
-    u.m[2][1] = conjg(u.m[0][2] * u.m[1][0] - u.m[0][0] * u.m[1][2]);
-    u.m[2][2] = conjg(u.m[0][0] * u.m[1][1] - u.m[0][1] * u.m[1][0]);
+    // conj(a b - c d) with one fused chain per real part
+    auto cross = [](cpx<T> a, cpx<T> b, cpx<T> c, cpx<T> d) {
+        T re = a.re * b.re, im = a.re * b.im;
+        re = fmadd(-a.im, b.im, re);
+        im = fmadd(a.im, b.re, im);
+        re = fmadd(-c.re, d.re, re);
+        im = fmadd(-c.re, d.im, im);
+        re = fmadd(c.im, d.im, re);
+        im = fmadd(-c.im, d.re, im);
+        return cpx<T>{re, -im};
+    };
+    u.m[2][0] = cross(u.m[0][1], u.m[1][2], u.m[0][2], u.m[1][1]);
+    u.m[2][1] = cross(u.m[0][2], u.m[1][0], u.m[0][0], u.m[1][2]);
+    u.m[2][2] = cross(u.m[0][0], u.m[1][1], u.m[0][1], u.m[1][0]);
 }
 
 // quark field value at one site: 4 spins x 3 colours

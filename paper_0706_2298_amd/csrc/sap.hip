@@ -285,11 +285,21 @@ template <typename L> __device__ inline su3<float> expand_lds(const Link2<L>& l,
     return u;
 }
 
-template <typename L>
+// B4: 4^4 blocks, whose extents, in-block strides and LDS plane size are
+// compile-time constants (every LDS access of a hop is then an immediate
+// offset from the thread's own address).
+template <typename L, bool B4>
 __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
                                                c32* __restrict__ psi, float diag, int nmr, int colour, int nrhs,
                                                int init, c64* __restrict__ out64)
 {
+    const int Vsb = B4 ? 256 : sg.Vsb;
+    int sbl[4], lst[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        sbl[mu] = B4 ? 4 : sg.sb[mu];
+        lst[mu] = B4 ? (64 >> (2 * mu)) : sg.lstr[mu];
+    }
     // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
     rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
     psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
@@ -297,11 +307,11 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
         out64 += (long)(blockIdx.x % nrhs) * 12 * g.V;
     extern __shared__ char smem_raw[];
     c32* lr = reinterpret_cast<c32*>(smem_raw);
-    c32* l3 = lr + 12 * sg.Vsb;  // third link rows: entry (3 h + b) * Vsb + site
+    c32* l3 = lr + 12 * Vsb;  // third link rows: entry (3 h + b) * Vsb + site
     __shared__ double red[3][8];
 
     const int t = threadIdx.x;
-    const bool active = t < sg.Vsb;
+    const bool active = t < Vsb;
     const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
 
     int k = blockIdx.x / nrhs;
@@ -320,14 +330,14 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
     long s = 0;
     if (active) {
         int tt = t;
-        yl[3] = tt % sg.sb[3];
-        tt /= sg.sb[3];
-        yl[2] = tt % sg.sb[2];
-        tt /= sg.sb[2];
-        yl[1] = tt % sg.sb[1];
-        yl[0] = tt / sg.sb[1];
+        yl[3] = tt % sbl[3];
+        tt /= sbl[3];
+        yl[2] = tt % sbl[2];
+        tt /= sbl[2];
+        yl[1] = tt % sbl[1];
+        yl[0] = tt / sbl[1];
         for (int mu = 0; mu < 4; ++mu) {
-            int x = m[mu] * sg.sb[mu] + yl[mu];
+            int x = m[mu] * sbl[mu] + yl[mu];
             n[mu] = x / g.b[mu];
             y[mu] = x - n[mu] * g.b[mu];
         }
@@ -352,8 +362,8 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
             const su3<float> u = expand(lk[h]);
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                l3[(3 * h + b) * sg.Vsb + t] = u.m[2][b];
-            const bool inside = step > 0 ? yl[mu] + 1 < sg.sb[mu] : yl[mu] > 0;
+                l3[(3 * h + b) * Vsb + t] = u.m[2][b];
+            const bool inside = step > 0 ? yl[mu] + 1 < sbl[mu] : yl[mu] > 0;
             if (init == 0 || (init == 1 && !inside)) {
                 spinor<float> p = load_spinor(psi, g.V, tn);
                 if (step > 0)
@@ -379,29 +389,33 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
             for (int al = 0; al < 4; ++al)
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
-                    lr[(3 * al + a) * sg.Vsb + t] = r.s[al].c[a];
+                    lr[(3 * al + a) * Vsb + t] = r.s[al].c[a];
         }
         __syncthreads();
-        spinor<float> q;
-        zero(q);
+        // acc = -2 D_Lambda r: it starts at -2 diag r and collects the inside
+        // hops, so the MR coefficient follows from it without forming D_Lambda r
+        spinor<float> acc;
         // the lane's products summed in FP32, the block sums in FP64
         float fr_re = 0.0f, fr_im = 0.0f, fqq = 0.0f;
         if (active) {
-            spinor<float> acc;
-            zero(acc);
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    acc.s[al].c[a] = cpx<float>{-2.0f * diag * r.s[al].c[a].re, -2.0f * diag * r.s[al].c[a].im};
 #pragma unroll
             for (int h = 0; h < 8; ++h) {
                 const int mu = h >> 1;
                 const int step = (h & 1) ? -1 : +1;
-                if (step > 0 ? yl[mu] + 1 < sg.sb[mu] : yl[mu] > 0) {
-                    const int tn = t + step * sg.lstr[mu];
+                if (step > 0 ? yl[mu] + 1 < sbl[mu] : yl[mu] > 0) {
+                    const int tn = t + step * lst[mu];
                     spinor<float> p;
 #pragma unroll
                     for (int al = 0; al < 4; ++al)
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
-                            p.s[al].c[a] = lr[(3 * al + a) * sg.Vsb + tn];
-                    const su3<float> u = expand_lds(lk[h], l3 + 3 * h * sg.Vsb + t, sg.Vsb);
+                            p.s[al].c[a] = lr[(3 * al + a) * Vsb + tn];
+                    const su3<float> u = expand_lds(lk[h], l3 + 3 * h * Vsb + t, Vsb);
                     if (step > 0)
                         hop_fwd_rt(mu, u, p, acc);
                     else
@@ -410,16 +424,15 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
                 if (h & 1)
                     asm volatile("" ::: "memory");
             }
-            q = finish(r, acc, diag);
 #pragma unroll
             for (int al = 0; al < 4; ++al)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const float qa = q.s[al].c[a].re, qb = q.s[al].c[a].im;
+                    const float qa = acc.s[al].c[a].re, qb = acc.s[al].c[a].im;
                     const float ra = r.s[al].c[a].re, rb = r.s[al].c[a].im;
-                    fr_re += qa * ra + qb * rb;
-                    fr_im += qa * rb - qb * ra;
-                    fqq += qa * qa + qb * qb;
+                    fr_re = fmadd(qb, rb, fmadd(qa, ra, fr_re));
+                    fr_im = fmadd(-qb, ra, fmadd(qa, rb, fr_im));
+                    fqq = fmadd(qb, qb, fmadd(qa, qa, fqq));
                 }
         }
         const double qr_re = wave_sum((double)fr_re);
@@ -439,13 +452,16 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
         }
         if (!(sqq > 0.0))
             break;  // zero residue on this block: uniform across the workgroup
-        c32 alpha{(float)(sre / sqq), (float)(sim / sqq)};
+        // with q = D_Lambda r = -acc / 2: alpha = (q, r) / ||q||^2 = -2 (acc, r) / ||acc||^2,
+        // x += alpha r, r -= alpha q = r + (alpha / 2) acc
+        const c32 alpha{(float)(-2.0 * sre / sqq), (float)(-2.0 * sim / sqq)};
+        const c32 half{0.5f * alpha.re, 0.5f * alpha.im};
 #pragma unroll
         for (int al = 0; al < 4; ++al)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                xs.s[al].c[a] += alpha * r.s[al].c[a];
-                r.s[al].c[a] -= alpha * q.s[al].c[a];
+                xs.s[al].c[a] = cfma(alpha, r.s[al].c[a], xs.s[al].c[a]);
+                r.s[al].c[a] = cfma(half, acc.s[al].c[a], r.s[al].c[a]);
             }
     }
 
@@ -683,9 +699,9 @@ __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, co
             q[i] = c32{diag * r[i].re - 0.5f * ao.re, diag * r[i].im - 0.5f * ao.im};
             const float qa = q[i].re, qb = q[i].im;
             const float ra = r[i].re, rb = r[i].im;
-            fr_re += qa * ra + qb * rb;
-            fr_im += qa * rb - qb * ra;
-            fqq += qa * qa + qb * qb;
+            fr_re = fmadd(qb, rb, fmadd(qa, ra, fr_re));
+            fr_im = fmadd(-qb, ra, fmadd(qa, rb, fr_im));
+            fqq = fmadd(qb, qb, fmadd(qa, qa, fqq));
         }
         const double qr_re = wave_sum((double)fr_re);
         const double qr_im = wave_sum((double)fr_im);
@@ -707,8 +723,8 @@ __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, co
         c32 alpha{(float)(sre / sqq), (float)(sim / sqq)};
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            xs[i] += alpha * r[i];
-            r[i] -= alpha * q[i];
+            xs[i] = cfma(alpha, r[i], xs[i]);
+            r[i] = cfma(-alpha, q[i], r[i]);
         }
     }
 
@@ -756,9 +772,17 @@ void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, 
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds_rl = (size_t)36 * sg.Vsb * sizeof(c32);
     static std::once_flag attr;  // one per link type
-    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap_rl<L>), 80 * 1024);
-    hipLaunchKernelGGL((k_sap_rl<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds_rl, s, g, sg, U, rho, psi,
-                       4.0f + m0, nmr, colour, nrhs, init, out64);
+    static std::once_flag attr4;
+    const bool b4 = sg.sb[0] == 4 && sg.sb[1] == 4 && sg.sb[2] == 4 && sg.sb[3] == 4;
+    if (b4) {
+        set_max_lds_once(attr4, reinterpret_cast<const void*>(&k_sap_rl<L, true>), 80 * 1024);
+        hipLaunchKernelGGL((k_sap_rl<L, true>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds_rl, s, g, sg, U,
+                           rho, psi, 4.0f + m0, nmr, colour, nrhs, init, out64);
+    } else {
+        set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap_rl<L, false>), 80 * 1024);
+        hipLaunchKernelGGL((k_sap_rl<L, false>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds_rl, s, g, sg, U,
+                           rho, psi, 4.0f + m0, nmr, colour, nrhs, init, out64);
+    }
 }
 
 template <typename T, typename L>
