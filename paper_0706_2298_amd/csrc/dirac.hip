@@ -172,12 +172,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_dirac_blk(Geom 
 
 // The block-crossing hop (hop_mu, hop_dir) of MODE 2 on the sites it reaches
 // only: one thread per site of the face {y_mu = b_mu - 1} (dir = +1) or
-// {y_mu = 0} (dir = -1) of every layout block, blockIdx.y = right-hand side.
-// The other sites of out are left untouched (the little-operator assembly
-// reads the face only).
+// {y_mu = 0} (dir = -1) of every layout block, for the nrhs fields in turn
+// (the link is loaded once and serves them all). The other sites of out are
+// left untouched (the little-operator assembly reads the face only).
 template <typename T, typename L>
 __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* __restrict__ psi,
-                                                    cpx<T>* __restrict__ out, int mu, int dir, int nface)
+                                                    cpx<T>* __restrict__ out, int mu, int dir, int nface, int nrhs)
 {
     const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= (long)g.Nb * nface)
@@ -197,22 +197,29 @@ __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* _
         }
     }
     const long s = site_compose(g, n, y);
-    const long off = (long)blockIdx.y * 12 * g.V;
-    spinor<T> acc;
-    zero(acc);
-    if (g.nb[mu] > 1) {
-        const long t = site_step(g, s, n, y, mu, dir);
-        spinor<T> p = load_spinor(psi + off, g.V, t);
-        if (crosses_time(g, n, y, mu, dir))
-            negate(p);
-        if (dir > 0)
-            hop_fwd_rt(mu, load_link(U, mu, s), p, acc);
-        else
-            hop_bwd_rt(mu, load_link(U, mu, t), p, acc);
-    }
+    const long fs = 12 * g.V;  // field stride
     spinor<T> z;
     zero(z);
-    store_spinor(out + off, g.V, s, finish(z, acc, T(0)));
+    if (g.nb[mu] <= 1) {
+        for (int q = 0; q < nrhs; ++q)
+            store_spinor(out + q * fs, g.V, s, z);
+        return;
+    }
+    const long t = site_step(g, s, n, y, mu, dir);
+    const bool neg = crosses_time(g, n, y, mu, dir);
+    const su3<T> u = load_link(U, mu, dir > 0 ? s : t);
+    for (int q = 0; q < nrhs; ++q) {
+        spinor<T> p0 = load_spinor(psi + q * fs, g.V, t);
+        if (neg)
+            negate(p0);
+        spinor<T> a0;
+        zero(a0);
+        if (dir > 0)
+            hop_fwd_rt(mu, u, p0, a0);
+        else
+            hop_bwd_rt(mu, u, p0, a0);
+        store_spinor(out + q * fs, g.V, s, finish(z, a0, T(0)));
+    }
 }
 
 // sub (MODE 0, may be null): out = sub - D psi; clov (may be null): the
@@ -268,8 +275,8 @@ void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int
 {
     const int nface = (int)(g.Vb / g.b[mu]);
     const long n = (long)g.Nb * nface;
-    hipLaunchKernelGGL((k_dirac_face<double, Links64>), dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, g,
-                       U, psi, out, mu, dir, nface);
+    hipLaunchKernelGGL((k_dirac_face<double, Links64>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, U, psi,
+                       out, mu, dir, nface, nrhs);
 }
 
 void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,
