@@ -902,42 +902,52 @@ void prepare_gdefl(dfl_ctx* c)
     c->gdefl_n = nq;
 }
 
-// Relaxed inverse iteration of eq. (5.1) on n native FP64 fields in place:
-// normalise, then `steps` times psi <- M_sap psi at m0_setup and normalise.
+// Relaxed inverse iteration of eq. (5.1) on n native FP64 fields: from the
+// fields at src (read only) into dst (src == dst: in place), normalise, then
+// `steps` times psi <- M_sap psi at m0_setup and normalise. With
+// normalise_out false the last normalisation is left out (for callers that
+// only use the span of each field, e.g. the block Gram-Schmidt of the
+// subspace setup, which is invariant under positive scale factors).
 // Sets c->dflag bit 0 on non-finite input.
-void inverse_iterate(dfl_ctx* c, c64* f, int n, int steps)
+void inverse_iterate(dfl_ctx* c, const c64* src, c64* dst, int n, int steps, bool normalise_out = true)
 {
     const long F = c->field_elems;
     // the n fields (back to back) are checked and normalised one launch per kernel
     auto normalise = [&]() {
         // a reduction writes a complex pair per field: stride 2
-        launch_norm2_b<double>(f, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
-        launch_scale_invsqrt_b<double>(f, F, n, F, c->dnorm, 2, nullptr, c->stream);
+        launch_norm2_b<double>(dst, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
+        launch_scale_invsqrt_b<double>(dst, F, n, F, c->dnorm, 2, nullptr, c->stream);
     };
-    launch_finite_check<double>(f, F * n, c->dflag, c->stream);
+    launch_finite_check<double>(src, F * n, c->dflag, c->stream);
     // the sweeps of the inverse iteration are timed as setup work
     struct SetupSweeps {
         dfl_ctx* c;
         explicit SetupSweeps(dfl_ctx* cc) : c(cc) { c->sap_prof_cls = DFL_PROF_SETUP_SAP; }
         ~SetupSweeps() { c->sap_prof_cls = DFL_PROF_SAP; }
     } setup_sweeps(c);
-    if (c->p.sap_prec == DFL_F64) {
-        normalise();
+    if (c->p.sap_prec == DFL_F64 || steps == 0) {
+        if (src != dst)
+            HIPCHECK(hipMemcpyAsync(dst, src, sizeof(c64) * F * n, hipMemcpyDeviceToDevice, c->stream));
         for (int step = 0; step < steps; ++step) {
-            sap_apply(c, f, c->tN, c->p.m0_setup, n);
-            launch_copy<double>(c->tN, f, F * n, c->stream);
             normalise();
+            sap_apply(c, dst, c->tN, c->p.m0_setup, n);
+            launch_copy<double>(c->tN, dst, F * n, c->stream);
         }
+        if (normalise_out || steps == 0)
+            normalise();
         return;
     }
     // FP32 block solves: each normalisation before a step is the scale of the
     // step's rounding to FP32 (M_sap is linear, so the step maps the
-    // normalised field), and only the last one rewrites the fields
+    // normalised field), the first step reads src and writes dst, and only a
+    // final normalisation rewrites the fields
     for (int step = 0; step < steps; ++step) {
-        launch_norm2_b<double>(f, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
-        sap_apply(c, f, f, c->p.m0_setup, n, c->dnorm);  // staged through s32a/s32b
+        const c64* in = step == 0 ? src : dst;
+        launch_norm2_b<double>(in, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
+        sap_apply(c, in, dst, c->p.m0_setup, n, c->dnorm);  // staged through s32a/s32b
     }
-    normalise();
+    if (normalise_out)
+        normalise();
 }
 
 int max_multi_fields(const dfl_ctx* c)
@@ -1495,11 +1505,14 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     // the fields are relaxed in Phi itself, or (bootstrapped iteration) kept
     // apart from the intermediate subspaces built from them
     c64* fields = nb > 0 ? c->bootF : c->Phi;
-    HIPCHECK(hipMemcpyAsync(fields, init, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
     // inverse iteration, eq. (5.1): psi_l <- M_sap psi_l, normalised; the
-    // Schwarz sweeps relax all Ns fields in one launch each
-    inverse_iterate(c, fields, Ns, c->p.n_inviter - nb);
+    // Schwarz sweeps relax all Ns fields in one launch each. The first step
+    // reads the caller's fields; the last normalisation is left out, since
+    // everything built from the fields (their block Gram-Schmidt, the
+    // global deflation modes, a bootstrapped step) depends only on each
+    // field's direction.
+    inverse_iterate(c, static_cast<const c64*>(init), fields, Ns, c->p.n_inviter - nb, false);
     // bootstrapped steps (section 5.3): the current fields deflate the
     // approximate solve of the next step
     for (int b = 0; b < nb; ++b) {
@@ -1746,7 +1759,7 @@ int dfl_inverse_iteration(dfl_ctx* c, void* fields, int n, int steps)
     if (steps < 0)
         fail(DFL_EINVAL, "steps must be >= 0");
     HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int) * 4, c->stream));
-    inverse_iterate(c, static_cast<c64*>(fields), n, steps);
+    inverse_iterate(c, static_cast<c64*>(fields), static_cast<c64*>(fields), n, steps);
     int flag[4];
     HIPCHECK(hipMemcpyAsync(flag, c->dflag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
     sync(c);
