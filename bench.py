@@ -183,9 +183,9 @@ def roofline(prof):
         nf = 1 if cls == "sap" else NS
         flops = sap_flops_per_site(NMR) * half * nf
         ach = flops / dur / 1e12
-        kern = ("k_sap_pair<Links32> (Schwarz colour sweep of one field, FP32, 4^4 blocks, two lanes per site)"
+        kern = ("k_sap_rl<Links32, 4^4> (Schwarz colour sweep of one field, FP32, one lane per site)"
                 if cls == "sap" else
-                f"k_sap_rl<Links32> (Schwarz colour sweep of the {NS} inverse-iteration fields, FP32, 4^4 blocks)")
+                f"k_sap_rl<Links32, 4^4> (Schwarz colour sweep of the {NS} inverse-iteration fields, FP32)")
         r = dict(kernel=kern, bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                  frac=ach / FP32_VECTOR_PEAK_TFLOPS,
                  per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {half} sites x {nf} fields")
