@@ -67,7 +67,7 @@ void free_all(dfl_ctx* c)
                     c->At64, c->At32, c->lpart, c->lstats, c->lbar_count, c->lbar_gen, c->tN,
                     c->lfin, c->lacoef, c->dact, c->net_part, c->loss_Y, c->loss_buf, c->dtol, c->Mt64, c->Mt32, c->lw1, c->lw2,
                     c->gsR, c->gU, c->gW, c->gQ, c->gZ, c->gQ32, c->gZ32, c->gC, c->Cl64, c->Cl32,
-                    c->gAinv, c->gGw, c->bootF, c->bootT, c->net_wbf};
+                    c->gAinv, c->gGw, c->bootF, c->bootT, c->net_wbf, c->PhiT};
     for (void* p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -988,18 +988,26 @@ void build_subspace(dfl_ctx* c, const c64* src, double mA)
     const int chunk = (int)std::max(1L, std::min({(long)Ns, (long)little_columns_max(Ns),
                                                   (long)c->p.nkv * c->p.nrhs_max, (long)(128 - Ns),
                                                   part_cap / ((long)c->g.Nb * Ns)}));
+    // The faces along x2 and x3 are scattered in the native in-block order
+    // (x3 fastest); their hops and block products read a copy of the basis in
+    // the transposed order, where those faces are whole tiles or long runs.
+    const bool tl = little_columns_transposable(Ns, chunk);
+    if (tl) {
+        c->PhiT = grow<c64>(c, c->PhiT, c->PhiT_n, (size_t)F * Ns);
+        launch_to_transposed(c->g, c->Phi, c->PhiT, Ns, c->stream);
+    }
     for (int l0 = 0; l0 < Ns; l0 += chunk) {
         const int nc = std::min(chunk, Ns - l0);
-        const c64* f = c->Phi + (long)l0 * F;
         for (int d = 0; d < 9; ++d) {
-            if (d == 0) {
+            const int mu = d == 0 ? -1 : (d - 1) / 2;
+            const bool t = tl && mu >= 2;
+            const c64* basis = t ? c->PhiT : c->Phi;
+            const c64* f = basis + (long)l0 * F;
+            if (d == 0)
                 launch_dirac64(c->g, links64(c), f, c->xi, nc, mA, 1, 0, 0, c->stream, c->Cl64);
-            } else {
-                const int mu = (d - 1) / 2;
-                const int dir = (d & 1) ? +1 : -1;
-                launch_dirac64_face(c->g, links64(c), f, c->xi, nc, mu, dir, c->stream);
-            }
-            launch_little_columns64(c->g, c->Phi, Ns, c->xi, nc, l0, d, c->A64, c->t1, part_cap, c->stream);
+            else
+                launch_dirac64_face(c->g, links64(c), f, c->xi, nc, mu, (d & 1) ? +1 : -1, c->stream, t);
+            launch_little_columns64(c->g, basis, Ns, c->xi, nc, l0, d, c->A64, c->t1, part_cap, c->stream, t);
         }
     }
     launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);

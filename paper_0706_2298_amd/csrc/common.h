@@ -244,6 +244,17 @@ __host__ __device__ inline long site_compose(const Geom& g, const int n[4], cons
     return blk * g.Vb + loc;
 }
 
+// The same site in the transposed in-block order (y0 fastest, y3 slowest),
+// blocks in the native order: a copy of a field in this order holds the faces
+// {y_3 = const} of a 4^4 block as whole 64-site tiles and the faces
+// {y_2 = const} as runs of 16 sites, which the native order scatters.
+__host__ __device__ inline long site_compose_t(const Geom& g, const int n[4], const int y[4])
+{
+    long blk = ((long)(n[0] * g.nb[1] + n[1]) * g.nb[2] + n[2]) * g.nb[3] + n[3];
+    long loc = ((long)(y[3] * g.b[2] + y[2]) * g.b[1] + y[1]) * g.b[0] + y[0];
+    return blk * g.Vb + loc;
+}
+
 // native index of the neighbour s + step*mu (step = +1 or -1), periodic
 __host__ __device__ inline long site_step(const Geom& g, long s, const int n[4], const int y[4], int mu, int step)
 {

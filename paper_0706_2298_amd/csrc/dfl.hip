@@ -389,6 +389,25 @@ __device__ inline long face_elem(const Geom& g, int blk, int e, int fmu, int fy,
     return tidx((long)blk * g.Vb + t, c, 12);
 }
 
+// The same for fields stored in the transposed in-block order (y0 fastest;
+// site_compose_t), the face sites enumerated in that order.
+__device__ inline long face_elem_t(const Geom& g, int blk, int e, int fmu, int fy, int nface)
+{
+    const int c = e / nface;
+    int r = e - c * nface, y[4];
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == fmu) {
+            y[nu] = fy;
+        } else {
+            y[nu] = r % g.b[nu];
+            r /= g.b[nu];
+        }
+    }
+    const int t = ((y[3] * g.b[2] + y[2]) * g.b[1] + y[1]) * g.b[0] + y[0];
+    return tidx((long)blk * g.Vb + t, c, 12);
+}
+
 // A block hop (eq. (A.1) with D restricted to the hops from block Lambda + mu
 // into Lambda) is non-zero only on the sites of Lambda's face towards
 // Lambda + mu: for those columns only that face's entries are summed.
@@ -466,7 +485,7 @@ __device__ inline double row16_sum(double v)
     return v;
 }
 
-template <int TK>
+template <int TK, bool TL>
 __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __restrict__ Phi, int Ns,
                                                            const c64* __restrict__ Y, int nc, int nsplit, int fmu,
                                                            int fy, int nface, c64* __restrict__ part)
@@ -495,7 +514,9 @@ __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __
     // during the current stage's products
     c64 v[kRtLd];
     auto load = [&](int e0) {
-        const long i = e0 + lane < e_hi ? face_elem(g, blk, e0 + lane, fmu, fy, nface) : -1;
+        const long i = e0 + lane >= e_hi ? -1
+                       : (TL ? face_elem_t(g, blk, e0 + lane, fmu, fy, nface)
+                             : face_elem(g, blk, e0 + lane, fmu, fy, nface));
 #pragma unroll
         for (int m = 0; m < kRtLd; ++m) {
             const int r = wid + 4 * m;
@@ -967,9 +988,13 @@ int little_columns_max(int Ns)
     return nc < 1 ? 1 : nc;
 }
 
+bool little_columns_transposable(int Ns, int nc) { return Ns <= 24 && nc <= 4 * kRtJ; }
+
 void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y, int nc, int l0, int d, c64* A,
-                             c64* part, long part_cap, hipStream_t s)
+                             c64* part, long part_cap, hipStream_t s, bool transposed)
 {
+    if (transposed && (d == 0 || !little_columns_transposable(Ns, nc)))
+        fail(DFL_EINVAL, "little-operator assembly: transposed order only for face columns of the tiled kernels");
     const size_t lds = sizeof(c64) * (Ns + nc) * (kCE + 1);
     // columns of a block hop: only the face towards the neighbour (see k_little_columns)
     const int fmu = d == 0 ? -1 : (d - 1) / 2;
@@ -985,12 +1010,21 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
         nsplit = 1;
     if ((long)nsplit * g.Nb * Ns * nc > part_cap)
         fail(DFL_EINVAL, "little-operator assembly: scratch too small for the column chunk");
+    const size_t lds_rt = sizeof(c64) * (Ns + nc) * kRtCE;
     if (Ns <= 20 && nc <= 4 * kRtJ) {
-        hipLaunchKernelGGL(k_little_columns_rt<5>, dim3(g.Nb * nsplit), dim3(256), sizeof(c64) * (Ns + nc) * kRtCE, s,
-                           g, Phi, Ns, Y, nc, nsplit, fmu, fy, nface, part);
+        if (transposed)
+            hipLaunchKernelGGL((k_little_columns_rt<5, true>), dim3(g.Nb * nsplit), dim3(256), lds_rt, s, g, Phi, Ns, Y,
+                               nc, nsplit, fmu, fy, nface, part);
+        else
+            hipLaunchKernelGGL((k_little_columns_rt<5, false>), dim3(g.Nb * nsplit), dim3(256), lds_rt, s, g, Phi, Ns,
+                               Y, nc, nsplit, fmu, fy, nface, part);
     } else if (Ns <= 24 && nc <= 4 * kRtJ) {
-        hipLaunchKernelGGL(k_little_columns_rt<6>, dim3(g.Nb * nsplit), dim3(256), sizeof(c64) * (Ns + nc) * kRtCE, s,
-                           g, Phi, Ns, Y, nc, nsplit, fmu, fy, nface, part);
+        if (transposed)
+            hipLaunchKernelGGL((k_little_columns_rt<6, true>), dim3(g.Nb * nsplit), dim3(256), lds_rt, s, g, Phi, Ns, Y,
+                               nc, nsplit, fmu, fy, nface, part);
+        else
+            hipLaunchKernelGGL((k_little_columns_rt<6, false>), dim3(g.Nb * nsplit), dim3(256), lds_rt, s, g, Phi, Ns,
+                               Y, nc, nsplit, fmu, fy, nface, part);
     } else {
         static std::once_flag attr;
         set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_columns),

@@ -174,8 +174,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_dirac_blk(Geom 
 // only: one thread per site of the face {y_mu = b_mu - 1} (dir = +1) or
 // {y_mu = 0} (dir = -1) of every layout block, for the nrhs fields in turn
 // (the link is loaded once and serves them all). The other sites of out are
-// left untouched (the little-operator assembly reads the face only).
-template <typename T, typename L>
+// left untouched (the little-operator assembly reads the face only). TL: psi
+// and out in the transposed in-block order (site_compose_t), the face sites
+// enumerated in that order (links always in the native one).
+template <typename T, typename L, bool TL>
 __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* __restrict__ psi,
                                                     cpx<T>* __restrict__ out, int mu, int dir, int nface, int nrhs)
 {
@@ -189,6 +191,10 @@ __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* _
     for (int nu = 3; nu >= 0; --nu) {
         n[nu] = rb % g.nb[nu];
         rb /= g.nb[nu];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int nu = TL ? q : 3 - q;  // fastest in-block coordinate first
         if (nu == mu) {
             y[nu] = dir > 0 ? g.b[nu] - 1 : 0;
         } else {
@@ -197,19 +203,27 @@ __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* _
         }
     }
     const long s = site_compose(g, n, y);
+    const long so = TL ? site_compose_t(g, n, y) : s;
     const long fs = 12 * g.V;  // field stride
     spinor<T> z;
     zero(z);
     if (g.nb[mu] <= 1) {
         for (int q = 0; q < nrhs; ++q)
-            store_spinor(out + q * fs, g.V, s, z);
+            store_spinor(out + q * fs, g.V, so, z);
         return;
     }
     const long t = site_step(g, s, n, y, mu, dir);
+    long ti = t;
+    if (TL) {
+        int nn[4] = {n[0], n[1], n[2], n[3]}, yn[4] = {y[0], y[1], y[2], y[3]};
+        yn[mu] = dir > 0 ? 0 : g.b[mu] - 1;  // the face hop always leaves the block
+        nn[mu] = (n[mu] + dir + g.nb[mu]) % g.nb[mu];
+        ti = site_compose_t(g, nn, yn);
+    }
     const bool neg = crosses_time(g, n, y, mu, dir);
     const su3<T> u = load_link(U, mu, dir > 0 ? s : t);
     for (int q = 0; q < nrhs; ++q) {
-        spinor<T> p0 = load_spinor(psi + q * fs, g.V, t);
+        spinor<T> p0 = load_spinor(psi + q * fs, g.V, ti);
         if (neg)
             negate(p0);
         spinor<T> a0;
@@ -218,8 +232,21 @@ __global__ __launch_bounds__(256) void k_dirac_face(Geom g, L U, const cpx<T>* _
             hop_fwd_rt(mu, u, p0, a0);
         else
             hop_bwd_rt(mu, u, p0, a0);
-        store_spinor(out + q * fs, g.V, s, finish(z, a0, T(0)));
+        store_spinor(out + q * fs, g.V, so, finish(z, a0, T(0)));
     }
+}
+
+// dst = src with every block's sites in the transposed in-block order, for
+// nf fields; one thread per (site, field)
+__global__ __launch_bounds__(256) void k_to_transposed(Geom g, const c64* __restrict__ src, c64* __restrict__ dst)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V)
+        return;
+    const long off = (long)blockIdx.y * 12 * g.V;
+    int n[4], y[4];
+    site_decompose(g, s, n, y);
+    store_spinor(dst + off, g.V, site_compose_t(g, n, y), load_spinor(src + off, g.V, s));
 }
 
 // sub (MODE 0, may be null): out = sub - D psi; clov (may be null): the
@@ -271,12 +298,22 @@ void launch_dirac64_sub(const Geom& g, Links64 U, const c64* sub, const c64* psi
     launch<0>(g, U, psi, out, nrhs, m0, 0, 0, s, sub, clov);
 }
 
-void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s)
+void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s,
+                         bool transposed)
 {
     const int nface = (int)(g.Vb / g.b[mu]);
     const long n = (long)g.Nb * nface;
-    hipLaunchKernelGGL((k_dirac_face<double, Links64>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, U, psi,
-                       out, mu, dir, nface, nrhs);
+    if (transposed)
+        hipLaunchKernelGGL((k_dirac_face<double, Links64, true>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           g, U, psi, out, mu, dir, nface, nrhs);
+    else
+        hipLaunchKernelGGL((k_dirac_face<double, Links64, false>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           g, U, psi, out, mu, dir, nface, nrhs);
+}
+
+void launch_to_transposed(const Geom& g, const c64* src, c64* dst, int nf, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_transposed, dim3((unsigned)((g.V + 255) / 256), nf), dim3(256), 0, s, g, src, dst);
 }
 
 void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,

@@ -166,6 +166,8 @@ struct dfl_ctx {
     size_t net_part_n = 0;
     uint16_t* net_wbf = nullptr; // BF16 weights of the BF16 forward
     size_t net_wbf_n = 0;
+    dfl::c64* PhiT = nullptr;    // the basis in the transposed in-block order (assembly of the
+    size_t PhiT_n = 0;           // face columns along x2 and x3)
     dfl::c64* loss_Y = nullptr;  // deficit loss: per-block G^-1 Psi^+ T
     double* loss_buf = nullptr;  // [Nb][K] block norms, [Nb][K] projections, [K] weights
     double* loss_host = nullptr;
@@ -212,7 +214,11 @@ void launch_dirac64(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs
 void launch_dirac64_sub(const Geom& g, Links64 U, const c64* sub, const c64* psi, c64* out, int nrhs, double m0,
                         hipStream_t s, const c64* clov);
 // MODE 2 on the face sites only (other sites of out untouched)
-void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s);
+// transposed: psi and out in the transposed in-block order (site_compose_t)
+void launch_dirac64_face(const Geom& g, Links64 U, const c64* psi, c64* out, int nrhs, int mu, int dir, hipStream_t s,
+                         bool transposed = false);
+// dst = src with every block's sites in the transposed in-block order (nf FP64 fields)
+void launch_to_transposed(const Geom& g, const c64* src, c64* dst, int nf, hipStream_t s);
 void launch_dirac32(const Geom& g, Links32 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,
                     const c32* clov);
 void launch_dirac_bf16(const Geom& g, LinksBF16 U, const c32* psi, c32* out, int nrhs, float m0, hipStream_t s,
@@ -312,10 +318,13 @@ void launch_gram2(const c64* X, const c64* Y, long n, int nv, c64* G, hipStream_
 void launch_combine(const c64* X, long n, int nv, int m, const c64* C, c64* Y, hipStream_t s);
 // A[blk][d][k][l0 + j] = (Phi_k, Y_j) over each block for k < Ns, j < nc
 // (nc <= little_columns_max(Ns), nc + Ns <= 128); part: scratch of part_cap
-// complex entries for the split partial sums (at least Nb*Ns*nc)
+// complex entries for the split partial sums (at least Nb*Ns*nc). transposed
+// (face columns d > 0 with little_columns_transposable only): Phi and Y in
+// the transposed in-block order (site_compose_t).
 int little_columns_max(int Ns);
+bool little_columns_transposable(int Ns, int nc);
 void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y, int nc, int l0, int d, c64* A,
-                             c64* part, long part_cap, hipStream_t s);
+                             c64* part, long part_cap, hipStream_t s, bool transposed = false);
 // w_b = A v_b (9-point block stencil) for nrhs little vectors
 template <typename T>
 void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, int nrhs, hipStream_t s);
