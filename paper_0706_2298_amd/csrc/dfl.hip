@@ -276,6 +276,152 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
     }
 }
 
+// The same modified Gram-Schmidt with the fields taken in pairs (l, l + 1),
+// NT threads of E entries each:
+// both are held in registers and projected against each earlier basis field
+// in one pass (one load of that field and one reduction of both products
+// for two projections), then l + 1 against the new l. Each field sees the
+// same sequence of projections as in k_block_gs, so the results are equal.
+template <int E, int NT>
+__global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
+                                                   int* __restrict__ flag, c64* __restrict__ R)
+{
+    __shared__ double2 sh[2][NT / 64];
+    const int blk = blockIdx.x;
+    const long fs = 12 * g.V;
+    const int ne = 12 * g.Vb;
+    // sums over the workgroup of two complex values at once (as two block_sum2)
+    auto sum2x2 = [&](double2& a, double2& b) {
+        a.x = wave_sum(a.x);
+        a.y = wave_sum(a.y);
+        b.x = wave_sum(b.x);
+        b.y = wave_sum(b.y);
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        if (lane == 0) {
+            sh[0][wid] = a;
+            sh[1][wid] = b;
+        }
+        __syncthreads();
+        double2 ta = make_double2(0.0, 0.0), tb = make_double2(0.0, 0.0);
+        for (int q = 0; q < nw; ++q) {
+            ta.x += sh[0][q].x;
+            ta.y += sh[0][q].y;
+            tb.x += sh[1][q].x;
+            tb.y += sh[1][q].y;
+        }
+        __syncthreads();
+        a = ta;
+        b = tb;
+    };
+    auto load_field = [&](int k, c64* w) {
+        const c64* fk = F + (long)k * fs;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int e = threadIdx.x + j * NT;
+            w[j] = e < ne ? fk[block_elem(g, blk, e)] : c64{0.0, 0.0};
+        }
+    };
+    // normalise v (field l, input norm n0), store it, record the diagonal of R
+    auto finish = [&](int l, c64* v, double n0, double nv2) {
+        double nv = sqrt(nv2);
+        n0 = sqrt(n0);
+        if (R && threadIdx.x == 0) {
+            R[((long)blk * Ns + l) * Ns + l] = c64{nv, 0.0};
+            for (int k = l + 1; k < Ns; ++k)
+                R[((long)blk * Ns + k) * Ns + l] = c64{0.0, 0.0};
+        }
+        if (!(nv > rank_tol * n0) || !(n0 > 0.0)) {
+            if (threadIdx.x == 0)
+                atomicOr(flag, 2);
+            nv = 1.0;
+        }
+        const double inv = 1.0 / nv;
+        c64* fl = F + (long)l * fs;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            v[j] = c64{v[j].re * inv, v[j].im * inv};
+            const int e = threadIdx.x + j * NT;
+            if (e < ne)
+                fl[block_elem(g, blk, e)] = v[j];
+        }
+    };
+    for (int l = 0; l < Ns; l += 2) {
+        const bool two = l + 1 < Ns;
+        c64 va[E], vb[E];
+        load_field(l, va);
+        if (two)
+            load_field(l + 1, vb);
+        else
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+                vb[j] = c64{0.0, 0.0};
+        double2 na = make_double2(0.0, 0.0), nb = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            na.x += va[j].re * va[j].re + va[j].im * va[j].im;
+            nb.x += vb[j].re * vb[j].re + vb[j].im * vb[j].im;
+        }
+        sum2x2(na, nb);
+        c64 un[E];
+        if (l > 0)
+            load_field(0, un);
+        for (int k = 0; k < l; ++k) {
+            c64 u[E];
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+                u[j] = un[j];
+            if (k + 1 < l)
+                load_field(k + 1, un);
+            double2 da = make_double2(0.0, 0.0), db = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                da.x += u[j].re * va[j].re + u[j].im * va[j].im;
+                da.y += u[j].re * va[j].im - u[j].im * va[j].re;
+                db.x += u[j].re * vb[j].re + u[j].im * vb[j].im;
+                db.y += u[j].re * vb[j].im - u[j].im * vb[j].re;
+            }
+            sum2x2(da, db);
+            const c64 ca{da.x, da.y}, cb{db.x, db.y};
+            if (R && threadIdx.x == 0) {
+                R[((long)blk * Ns + k) * Ns + l] = ca;
+                if (two)
+                    R[((long)blk * Ns + k) * Ns + l + 1] = cb;
+            }
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                va[j] -= ca * u[j];
+                vb[j] -= cb * u[j];
+            }
+        }
+        // field l is complete: its norm; field l + 1 continues against it
+        double2 nva = make_double2(0.0, 0.0), dummy = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            nva.x += va[j].re * va[j].re + va[j].im * va[j].im;
+        sum2x2(nva, dummy);
+        finish(l, va, na.x, nva.x);
+        if (!two)
+            break;
+        double2 d = make_double2(0.0, 0.0), nvb = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            d.x += va[j].re * vb[j].re + va[j].im * vb[j].im;
+            d.y += va[j].re * vb[j].im - va[j].im * vb[j].re;
+        }
+        sum2x2(d, dummy);
+        const c64 c{d.x, d.y};
+        if (R && threadIdx.x == 0)
+            R[((long)blk * Ns + l) * Ns + l + 1] = c;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            vb[j] -= c * va[j];
+            nvb.x += vb[j].re * vb[j].re + vb[j].im * vb[j].im;
+        }
+        sum2x2(nvb, dummy);
+        finish(l + 1, vb, nb.x, nvb.x);
+    }
+}
+
 // The same Gram-Schmidt for blocks of any size, both fields streamed through memory.
 __global__ __launch_bounds__(kBT) void k_block_gs_stream(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
                                                   int* __restrict__ flag, c64* __restrict__ R)
@@ -975,8 +1121,8 @@ void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag
     const int e = (12 * (int)g.Vb + kBT - 1) / kBT;  // entries per thread
     if (e <= 6)
         hipLaunchKernelGGL(k_block_gs<6>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
-    else if (e <= 12)
-        hipLaunchKernelGGL(k_block_gs<12>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
+    else if (e <= 12)  // two fields at a time, 512 threads: six entries of each per thread
+        hipLaunchKernelGGL((k_block_gs2<6, 512>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R);
     else if (e <= 24)
         hipLaunchKernelGGL(k_block_gs<24>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
     else
