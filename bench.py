@@ -237,6 +237,36 @@ def dirac_rates(torch):
         S.close()
         del x, y
     torch.cuda.empty_cache()
+    # achievable HBM rate for reference: a device-to-device copy of one FP64 64 x 32^3 field (402 MB)
+    a = torch.ones(24 * V, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    t = time_events(torch, lambda: b.copy_(a), 20)
+    out["copy_gbs"] = 2 * a.numel() * 8 / t / 1e9
+    del a, b
+    # 12 fields in one launch on 48 x 24^3 against one field (per field and site: FP64 384 B of
+    # spinors, FP32 192 B; the two-row links, 384 / 192 B per site, once per launch)
+    dims12 = (48, 24, 24, 24)
+    v12 = int(np.prod(dims12))
+    U12 = latgen.make_links(dims12, 0.4, 4001)
+    src = latgen.random_field(dims12, 4003, n=12)
+    multi = {}
+    for name, lp, prec, sb, lb in [("f64", F64, F64, 384, 384), ("f32", F32, F32, 192, 192)]:
+        S = Solver(dims12, Ns=1, nkv=1, little_nkv=1, m0=-0.3, link_prec=lp, sap_prec=prec, nrhs_max=12)
+        S.set_gauge(U12)
+        x = S.pack(src, prec=prec)
+        y = S.field(12, prec)
+        x1 = S.pack(src[0], prec=prec)
+        y1 = S.field(1, prec)
+        t12 = time_events(torch, lambda: binding.dirac_apply(S.ctx, x, y, 12, prec), 10)
+        t1 = time_events(torch, lambda: binding.dirac_apply(S.ctx, x1, y1, 1, prec), 20)
+        gbs = (12 * sb + lb) * v12 / t12 / 1e9
+        multi[name] = dict(us_12=t12 * 1e6, us_1=t1 * 1e6, per_field_speedup=12 * t1 / t12,
+                           gflops_12=FLOPS_PER_SITE * v12 * 12 / t12 / 1e9, gbs_12=gbs,
+                           frac_hbm_12=gbs / HBM_PEAK_GBS)
+        S.close()
+        del x, y, x1, y1
+        torch.cuda.empty_cache()
+    out["multi_field_48x24"] = multi
     tr = counter_traffic("dirac64", "dirac")
     if tr is not None:
         out["f64_tworow"]["counter_bytes_per_launch"] = tr

@@ -7,6 +7,7 @@
 // workgroup numbering is XCD-aware (common.h): each XCD sweeps a contiguous
 // range of sites so that neighbour reuse stays inside one L2.
 #include <complex>
+#include <type_traits>
 
 #include "hop.h"
 
@@ -120,9 +121,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_dirac_blk(Geom 
     site_decompose(g, s, n, y);
     spinor<T> acc;
     zero(acc);
+    // x3 and x2 hops first: their neighbours across the block faces are
+    // scattered partial lines of the neighbouring blocks, which run at the
+    // same time on the same XCD and have just fetched those lines
 #pragma unroll 1
     for (int h = 0; h < 8; ++h) {
-        const int mu = h >> 1;
+        const int mu = 3 - (h >> 1);
         const int step = (h & 1) ? -1 : +1;
         const bool inside = step > 0 ? y[mu] + 1 < g.b[mu] : y[mu] > 0;
         const long t = site_step(g, s, n, y, mu, step);
@@ -168,6 +172,275 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_dirac_blk(Geom 
             __builtin_nontemporal_store(o.s[al].c[a].re, &q->re);
             __builtin_nontemporal_store(o.s[al].c[a].im, &q->im);
         }
+}
+
+// ------------------------------------------------- 4^4 layout blocks
+//
+// Faces of a 4^4 block: face f = 2 (3 - mu) + (dir < 0), i.e. f = 0, 1 the
+// forward and backward faces normal to x3, ..., f = 6, 7 those normal to x0.
+// Each holds 64 sites, numbered by the other three in-block coordinates
+// (ascending directions, the highest fastest). The kernels below load the
+// neighbour spinors across the first NF faces in the same burst as the block's
+// own spinors, spin-project them ((1 - g_mu) psi across a forward face,
+// (1 + g_mu) psi across a backward one) and keep the two colour vectors in
+// LDS, where the face sites' hops read them. In the native site order the
+// neighbours across the x3 and x2 faces are every fourth site or runs of four
+// sites of the neighbouring block, i.e. parts of its cache lines; that block
+// runs at the same time on the same XCD, so a fetch in the same burst as its
+// own loads is mostly an L2 hit instead of a second fetch later on.
+
+constexpr int kFaceSites = 64;
+
+__device__ inline int face_pos(const int y[4], int mu)
+{
+    int r = 0;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu)
+        if (nu != mu)
+            r = r * 4 + y[nu];
+    return r;
+}
+
+// thread t0 loads the neighbour across face (t0 / 64) + 4 k at face position
+// t0 % 64, for k < NF / 4
+template <int NF, typename T>
+__device__ inline void face_load(const Geom& g, const cpx<T>* __restrict__ f, const int n[4], int t0,
+                                 spinor<T> (&hp)[NF / 4])
+{
+#pragma unroll
+    for (int k = 0; k < NF / 4; ++k) {
+        const int fi = (t0 >> 6) + 4 * k;
+        const int mu = 3 - (fi >> 1);
+        const int step = (fi & 1) ? -1 : +1;
+        int yy[4], nn[4];
+        int rr = t0 & (kFaceSites - 1);
+#pragma unroll
+        for (int nu = 3; nu >= 0; --nu) {
+            nn[nu] = n[nu];
+            if (nu != mu) {
+                yy[nu] = rr & 3;
+                rr >>= 2;
+            }
+        }
+        yy[mu] = step > 0 ? 0 : 3;
+        nn[mu] = n[mu] + step;
+        nn[mu] += nn[mu] < 0 ? g.nb[mu] : (nn[mu] >= g.nb[mu] ? -g.nb[mu] : 0);
+        hp[k] = load_spinor(f, g.V, site_compose(g, nn, yy));
+    }
+}
+
+// projects the loaded neighbours (with the antiperiodic sign of a hop across
+// x0 = L0 - 1 <-> 0) into the face arrays
+template <int NF, typename T>
+__device__ inline void face_store(const Geom& g, const int n[4], int t0, spinor<T> (&hp)[NF / 4],
+                                  cpx<T> (*hal)[6][kFaceSites])
+{
+#pragma unroll
+    for (int k = 0; k < NF / 4; ++k) {
+        const int fi = (t0 >> 6) + 4 * k;
+        const int mu = 3 - (fi >> 1);
+        const int step = (fi & 1) ? -1 : +1;
+        if (mu == 0 && g.tsign < 0 && (step > 0 ? n[0] == g.nb[0] - 1 : n[0] == 0))
+            negate(hp[k]);
+        cvec3<T> a, b;
+        proj_rt(mu, step, hp[k], a, b);
+        const int r = t0 & (kFaceSites - 1);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            hal[fi][q][r] = a.c[q];
+            hal[fi][3 + q][r] = b.c[q];
+        }
+    }
+}
+
+// hop H (order x3+, x3-, x2+, ..., x0-) of site s: the neighbour from the
+// block's spinors in LDS, from the face arrays, or (faces >= NF) from memory
+template <int H, int NF, typename T, typename L>
+__device__ inline void hop4(const Geom& g, const cpx<T>* __restrict__ f, const cpx<T> (*sp)[256],
+                            const cpx<T> (*hal)[6][kFaceSites], const LinkRows<L>& u, int t0, long s, const int n[4],
+                            const int y[4], spinor<T>& acc)
+{
+    constexpr int MU = 3 - (H >> 1);
+    constexpr int STEP = (H & 1) ? -1 : +1;
+    constexpr int FI = H;
+    constexpr int LSTR = MU == 3 ? 1 : MU == 2 ? 4 : MU == 1 ? 16 : 64;
+    const bool inside = STEP > 0 ? y[MU] < 3 : y[MU] > 0;
+    cvec3<T> a, b;
+    if (inside) {
+        spinor<T> p;
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                p.s[al].c[c] = sp[3 * al + c][t0 + STEP * LSTR];
+        if (STEP > 0)
+            proj_fwd<MU>(p, a, b);
+        else
+            proj_bwd<MU>(p, a, b);
+    } else if (FI < NF) {
+        const int r = face_pos(y, MU);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            a.c[q] = hal[FI][q][r];
+            b.c[q] = hal[FI][3 + q][r];
+        }
+    } else {
+        spinor<T> p = load_spinor(f, g.V, site_step(g, s, n, y, MU, STEP));
+        if (crosses_time(g, n, y, MU, STEP))
+            negate(p);
+        if (STEP > 0)
+            proj_fwd<MU>(p, a, b);
+        else
+            proj_bwd<MU>(p, a, b);
+    }
+    hop_add<MU, STEP>(to_link(u), a, b, acc);
+}
+
+// out (+ off) = diag psi - 1/2 acc (+ clover) at site s, or sub - that;
+// non-temporal stores (the result is not re-read by this kernel)
+template <typename T, bool CLV>
+__device__ inline void finish_store(const cpx<T> (*sp)[256], int t0, long s, const spinor<T>& acc, T diag,
+                                    const Clover<T>& C, const cpx<T>* __restrict__ sub, cpx<T>* __restrict__ dst)
+{
+    spinor<T> self;
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            self.s[al].c[a] = sp[3 * al + a][t0];
+    spinor<T> o = finish(self, acc, diag);
+    if constexpr (CLV)
+        clover_add(C, s, self, o);
+    if (sub) {
+        const spinor<T> a = load_spinor(sub, 0, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+            o.s[al] = a.s[al] - o.s[al];
+    }
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cpx<T>* q = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(dst) + toff<cpx<T>>(s, 3 * al + a, 12));
+            __builtin_nontemporal_store(o.s[al].c[a].re, &q->re);
+            __builtin_nontemporal_store(o.s[al].c[a].im, &q->im);
+        }
+}
+
+// FP32 spinors with FP32 links: one workgroup per (4^4 block, field); own
+// spinors and all eight faces staged at the start, together with all eight
+// links of every site (two rows each). Consecutive workgroups take the same
+// block for the different fields, so that after the first field the links
+// come from L2.
+template <typename T, typename L, bool CLV>
+__global__ __launch_bounds__(256, 2) void k_dirac_f4(Geom g, L U, const cpx<T>* __restrict__ psi,
+                                                     cpx<T>* __restrict__ out, T diag, int chunks_padded, int nrhs,
+                                                     const cpx<T>* __restrict__ sub, Clover<T> C)
+{
+    __shared__ cpx<T> sp[12][256];
+    __shared__ cpx<T> hal[8][6][kFaceSites];
+    const int per = chunks_padded / kNumXcd;
+    const int local = blockIdx.x / kNumXcd;
+    const int blk = (blockIdx.x % kNumXcd) * per + local / nrhs;
+    const int rhs = local % nrhs;
+    if (blk >= g.Nb)
+        return;
+    const int t0 = threadIdx.x;
+    const long s = (long)blk * 256 + t0;
+    const long off = (long)rhs * 12 * g.V;
+    const cpx<T>* f = psi + off;
+    int n[4], y[4];
+    site_decompose(g, s, n, y);
+    const spinor<T> own = load_spinor(f, g.V, s);
+    spinor<T> hp[2];
+    face_load<8>(g, f, n, t0, hp);
+    LinkRows<L> uf[4], ub[4];
+#pragma unroll
+    for (int mu = 3; mu >= 0; --mu) {
+        uf[mu] = load_rows(U, mu, s);
+        ub[mu] = load_rows(U, mu, site_step(g, s, n, y, mu, -1));
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+        sp[c][t0] = own.s[c / 3].c[c % 3];
+    face_store<8>(g, n, t0, hp, hal);
+    __syncthreads();
+    spinor<T> acc;
+    zero(acc);
+    hop4<0, 8>(g, f, sp, hal, uf[3], t0, s, n, y, acc);
+    hop4<1, 8>(g, f, sp, hal, ub[3], t0, s, n, y, acc);
+    hop4<2, 8>(g, f, sp, hal, uf[2], t0, s, n, y, acc);
+    hop4<3, 8>(g, f, sp, hal, ub[2], t0, s, n, y, acc);
+    hop4<4, 8>(g, f, sp, hal, uf[1], t0, s, n, y, acc);
+    hop4<5, 8>(g, f, sp, hal, ub[1], t0, s, n, y, acc);
+    hop4<6, 8>(g, f, sp, hal, uf[0], t0, s, n, y, acc);
+    hop4<7, 8>(g, f, sp, hal, ub[0], t0, s, n, y, acc);
+    finish_store<T, CLV>(sp, t0, s, acc, diag, C, sub ? sub + off : nullptr, out + off);
+}
+
+// As k_dirac_f4 for BF16 links: the hop loop kept rolled and each hop's link
+// loaded one hop ahead (three workgroups per CU).
+template <typename T, typename L, bool CLV>
+__global__ __launch_bounds__(256, 3) void k_dirac_f4p(Geom g, L U, const cpx<T>* __restrict__ psi,
+                                                      cpx<T>* __restrict__ out, T diag, int chunks_padded, int nrhs,
+                                                      const cpx<T>* __restrict__ sub, Clover<T> C)
+{
+    __shared__ cpx<T> sp[12][256];
+    __shared__ cpx<T> hal[8][6][kFaceSites];
+    const int per = chunks_padded / kNumXcd;
+    const int local = blockIdx.x / kNumXcd;
+    const int blk = (blockIdx.x % kNumXcd) * per + local / nrhs;
+    const int rhs = local % nrhs;
+    if (blk >= g.Nb)
+        return;
+    const int t0 = threadIdx.x;
+    const long s = (long)blk * 256 + t0;
+    const long off = (long)rhs * 12 * g.V;
+    const cpx<T>* f = psi + off;
+    int n[4], y[4];
+    site_decompose(g, s, n, y);
+    const spinor<T> own = load_spinor(f, g.V, s);
+    spinor<T> hp[2];
+    face_load<8>(g, f, n, t0, hp);
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+        sp[c][t0] = own.s[c / 3].c[c % 3];
+    face_store<8>(g, n, t0, hp, hal);
+    __syncthreads();
+    spinor<T> acc;
+    zero(acc);
+    LinkRows<L> next = load_rows(U, 3, s);
+#pragma unroll 1
+    for (int h = 0; h < 8; ++h) {
+        const int mu = 3 - (h >> 1);
+        const int step = (h & 1) ? -1 : +1;
+        const LinkRows<L> cur = next;
+        if (h < 7) {
+            const int mu2 = 3 - ((h + 1) >> 1);
+            next = load_rows(U, mu2, ((h + 1) & 1) ? site_step(g, s, n, y, mu2, -1) : s);
+        }
+        const bool inside = step > 0 ? y[mu] < 3 : y[mu] > 0;
+        cvec3<T> a, b;
+        if (inside) {
+            spinor<T> p;
+            const int tl = t0 + step * g.lstr[mu];
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    p.s[al].c[c] = sp[3 * al + c][tl];
+            proj_rt(mu, step, p, a, b);
+        } else {
+            const int r = face_pos(y, mu);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                a.c[q] = hal[h][q][r];
+                b.c[q] = hal[h][3 + q][r];
+            }
+        }
+        hop_add_rt(mu, step, to_link(cur), a, b, acc);
+    }
+    finish_store<T, CLV>(sp, t0, s, acc, diag, C, sub ? sub + off : nullptr, out + off);
 }
 
 // The block-crossing hop (hop_mu, hop_dir) of MODE 2 on the sites it reaches
@@ -259,6 +532,28 @@ void launch(const Geom& g, L U, const cpx<T>* psi, cpx<T>* out, int nrhs, T m0, 
             const typename same<cpx<T>>::type* sub, const typename same<cpx<T>>::type* clov)
 {
     const Clover<T> C{MODE == 2 ? nullptr : clov};
+    const bool b4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
+    if constexpr (MODE == 0 && sizeof(T) == 4) {
+        if (b4) {
+            const int gp = pad_grid(g.Nb);
+            if constexpr (std::is_same<L, LinksBF16>::value) {
+                if (C.c)
+                    hipLaunchKernelGGL((k_dirac_f4p<T, L, true>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi,
+                                       out, T(4) + m0, gp, nrhs, sub, C);
+                else
+                    hipLaunchKernelGGL((k_dirac_f4p<T, L, false>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi,
+                                       out, T(4) + m0, gp, nrhs, sub, C);
+            } else {
+                if (C.c)
+                    hipLaunchKernelGGL((k_dirac_f4<T, L, true>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi,
+                                       out, T(4) + m0, gp, nrhs, sub, C);
+                else
+                    hipLaunchKernelGGL((k_dirac_f4<T, L, false>), dim3(gp * nrhs), dim3(256), 0, s, g, U, psi,
+                                       out, T(4) + m0, gp, nrhs, sub, C);
+            }
+            return;
+        }
+    }
     if (MODE == 0 && g.Vb == 256) {
         const int gp = pad_grid(g.Nb);
         if (C.c)

@@ -68,6 +68,71 @@ __device__ inline su3<float> load_link(const LinksBF16& L, int mu, long s)
     return u;
 }
 
+// The two stored rows of a link, loaded ahead of their use (the third row is
+// completed only when the matrix is needed, so that a load in flight holds 12
+// instead of 18 values).
+template <typename L> struct LinkRows;
+template <> struct LinkRows<Links64> {
+    c64 e[6];
+};
+template <> struct LinkRows<Links32> {
+    c32 e[6];
+};
+template <> struct LinkRows<LinksBF16> {
+    uint32_t e[6];
+};
+__device__ inline LinkRows<Links64> load_rows(const Links64& L, int mu, long s)
+{
+    LinkRows<Links64> r;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        r.e[q] = ld(L.u, toff<c64>(s, mu * 6 + q, 24));
+    return r;
+}
+__device__ inline LinkRows<Links32> load_rows(const Links32& L, int mu, long s)
+{
+    LinkRows<Links32> r;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        r.e[q] = ld(L.u, toff<c32>(s, mu * 6 + q, 24));
+    return r;
+}
+__device__ inline LinkRows<LinksBF16> load_rows(const LinksBF16& L, int mu, long s)
+{
+    LinkRows<LinksBF16> r;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        r.e[q] = ld(L.u, toff<uint32_t>(s, mu * 6 + q, 24));
+    return r;
+}
+__device__ inline su3<double> to_link(const LinkRows<Links64>& r)
+{
+    su3<double> u;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        u.m[q / 3][q % 3] = r.e[q];
+    complete_third_row(u);
+    return u;
+}
+__device__ inline su3<float> to_link(const LinkRows<Links32>& r)
+{
+    su3<float> u;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        u.m[q / 3][q % 3] = r.e[q];
+    complete_third_row(u);
+    return u;
+}
+__device__ inline su3<float> to_link(const LinkRows<LinksBF16>& r)
+{
+    su3<float> u;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        u.m[q / 3][q % 3] = c32{bf16_to_f(r.e[q] & 0xffffu), bf16_to_f(r.e[q] >> 16)};
+    complete_third_row(u);
+    return u;
+}
+
 template <typename T> __device__ inline spinor<T> load_spinor(const cpx<T>* __restrict__ f, long V, long s)
 {
     (void)V;
@@ -99,11 +164,11 @@ template <typename T> __device__ inline void zero(spinor<T>& p)
             p.s[al].c[a] = cpx<T>{0, 0};
 }
 
-// acc += (1 - g_mu) U psi_fwd
-template <int MU, typename T>
-__device__ inline void hop_fwd(const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+// The spin projections of the two hops: (1 - g_mu) psi = [h0, h1; ...] for the
+// forward hop and (1 + g_mu) psi = [k0, k1; ...] for the backward one; the
+// lower two spin components follow from the upper ones (fwd_add, bwd_add).
+template <int MU, typename T> __device__ inline void proj_fwd(const spinor<T>& p, cvec3<T>& h0, cvec3<T>& h1)
 {
-    cvec3<T> h0, h1;
     if (MU == 0) {
         h0 = p.s[0] + p.s[2];
         h1 = p.s[1] + p.s[3];
@@ -117,8 +182,27 @@ __device__ inline void hop_fwd(const su3<T>& u, const spinor<T>& p, spinor<T>& a
         h0 = p.s[0] + vi(p.s[2]);
         h1 = p.s[1] - vi(p.s[3]);
     }
-    cvec3<T> u0 = mul(u, h0);
-    cvec3<T> u1 = mul(u, h1);
+}
+template <int MU, typename T> __device__ inline void proj_bwd(const spinor<T>& p, cvec3<T>& k0, cvec3<T>& k1)
+{
+    if (MU == 0) {
+        k0 = p.s[0] - p.s[2];
+        k1 = p.s[1] - p.s[3];
+    } else if (MU == 1) {
+        k0 = p.s[0] + vmi(p.s[3]);
+        k1 = p.s[1] + vmi(p.s[2]);
+    } else if (MU == 2) {
+        k0 = p.s[0] - p.s[3];
+        k1 = p.s[1] + p.s[2];
+    } else {
+        k0 = p.s[0] + vmi(p.s[2]);
+        k1 = p.s[1] + vi(p.s[3]);
+    }
+}
+
+// acc += the four spin components of (1 - g_mu) U psi_fwd from u0 = U h0, u1 = U h1
+template <int MU, typename T> __device__ inline void fwd_add(const cvec3<T>& u0, const cvec3<T>& u1, spinor<T>& acc)
+{
     acc.s[0] += u0;
     acc.s[1] += u1;
     if (MU == 0) {
@@ -136,6 +220,15 @@ __device__ inline void hop_fwd(const su3<T>& u, const spinor<T>& p, spinor<T>& a
     }
 }
 
+// acc += (1 - g_mu) U psi_fwd
+template <int MU, typename T>
+__device__ inline void hop_fwd(const su3<T>& u, const spinor<T>& p, spinor<T>& acc)
+{
+    cvec3<T> h0, h1;
+    proj_fwd<MU>(p, h0, h1);
+    fwd_add<MU>(mul(u, h0), mul(u, h1), acc);
+}
+
 // The backward hop in two halves: the spin-projected colour vectors
 // v = U^+ k of (1 + g_mu) U^+ psi_bwd, and their reconstruction into the four
 // spin components (bwd_add).
@@ -143,19 +236,7 @@ template <int MU, typename T>
 __device__ inline void bwd_project(const su3<T>& u, const spinor<T>& p, cvec3<T>& v0, cvec3<T>& v1)
 {
     cvec3<T> k0, k1;
-    if (MU == 0) {
-        k0 = p.s[0] - p.s[2];
-        k1 = p.s[1] - p.s[3];
-    } else if (MU == 1) {
-        k0 = p.s[0] + vmi(p.s[3]);
-        k1 = p.s[1] + vmi(p.s[2]);
-    } else if (MU == 2) {
-        k0 = p.s[0] - p.s[3];
-        k1 = p.s[1] + p.s[2];
-    } else {
-        k0 = p.s[0] + vmi(p.s[2]);
-        k1 = p.s[1] + vi(p.s[3]);
-    }
+    proj_bwd<MU>(p, k0, k1);
     v0 = mul_dag(u, k0);
     v1 = mul_dag(u, k1);
 }
@@ -207,6 +288,57 @@ __device__ inline void hop_bwd_rt(int mu, const su3<T>& u, const spinor<T>& p, s
     case 1: hop_bwd<1>(u, p, acc); break;
     case 2: hop_bwd<2>(u, p, acc); break;
     default: hop_bwd<3>(u, p, acc); break;
+    }
+}
+
+// runtime-direction projection (a = h0 or k0, b = h1 or k1) and accumulation
+// of the projected neighbour multiplied by the link (U for step > 0, U^+ for
+// step < 0)
+template <typename T>
+__device__ inline void proj_rt(int mu, int step, const spinor<T>& p, cvec3<T>& a, cvec3<T>& b)
+{
+    if (step > 0) {
+        switch (mu) {
+        case 0: proj_fwd<0>(p, a, b); break;
+        case 1: proj_fwd<1>(p, a, b); break;
+        case 2: proj_fwd<2>(p, a, b); break;
+        default: proj_fwd<3>(p, a, b); break;
+        }
+    } else {
+        switch (mu) {
+        case 0: proj_bwd<0>(p, a, b); break;
+        case 1: proj_bwd<1>(p, a, b); break;
+        case 2: proj_bwd<2>(p, a, b); break;
+        default: proj_bwd<3>(p, a, b); break;
+        }
+    }
+}
+template <int MU, int STEP, typename T>
+__device__ inline void hop_add(const su3<T>& u, const cvec3<T>& a, const cvec3<T>& b, spinor<T>& acc)
+{
+    if (STEP > 0)
+        fwd_add<MU>(mul(u, a), mul(u, b), acc);
+    else
+        bwd_add<MU>(mul_dag(u, a), mul_dag(u, b), acc);
+}
+template <typename T>
+__device__ inline void hop_add_rt(int mu, int step, const su3<T>& u, const cvec3<T>& a, const cvec3<T>& b,
+                                  spinor<T>& acc)
+{
+    if (step > 0) {
+        switch (mu) {
+        case 0: hop_add<0, 1>(u, a, b, acc); break;
+        case 1: hop_add<1, 1>(u, a, b, acc); break;
+        case 2: hop_add<2, 1>(u, a, b, acc); break;
+        default: hop_add<3, 1>(u, a, b, acc); break;
+        }
+    } else {
+        switch (mu) {
+        case 0: hop_add<0, -1>(u, a, b, acc); break;
+        case 1: hop_add<1, -1>(u, a, b, acc); break;
+        case 2: hop_add<2, -1>(u, a, b, acc); break;
+        default: hop_add<3, -1>(u, a, b, acc); break;
+        }
     }
 }
 

@@ -65,7 +65,7 @@ template <typename T> struct LittleArgs {
     int oblique;           // 1: the oblique projectors of section 3 on the even-odd system, with
     const double* Ainv;    //   Ainv = (Z^+ W)^-1 (nq x nq complex, row-major) and
     const double* Gw;      //   Gw = W^+ W (nq x nq complex)
-    double* part;          // NSLOT * G complex partial sums
+    double* part;          // NSLOT * G complex partial sums, then NSLOT published sums
     int* stats;            // [0] += iterations, [1] += solves, [2] |= 1 not converged, |= 4 barrier timeout
     unsigned* bar_count;   // grid barrier: arrivals (0 between barriers)
     unsigned long long* bar_gen;  // grid barrier: generation, increases across launches
@@ -208,6 +208,61 @@ __device__ inline void reduce_slots(const double* __restrict__ part, int G, int 
             }
         }
     }
+    __syncthreads();
+}
+
+// Grid barrier that also reduces the partial-sum slots [s0, s0 + ns) over the
+// G workgroups: the workgroup that arrives last sums them (reduce_slots, the
+// same fixed order whichever workgroup it is, so the result is
+// bit-reproducible), writes the ns complex sums to pub and only then publishes
+// the next generation; the others wait for it and read the ns sums instead of
+// all G ns partial sums. One workgroup thus reads the partials once, instead
+// of every workgroup reading all of them from the other XCDs' L2. red: 2 ns
+// doubles in LDS; last_s: an int in LDS. pub is not overwritten before every
+// workgroup has read it (the next such barrier needs every workgroup's
+// arrival first).
+__device__ inline void grid_barrier_reduce(unsigned* count, unsigned long long* gen, unsigned long long& target,
+                                           int* stats, const double* __restrict__ part, double* pub, int G, int s0,
+                                           int ns, double* red, int* last_s)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ++target;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int last = old == gridDim.x - 1;
+        if (last)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *last_s = last;
+    }
+    __syncthreads();
+    if (*last_s) {
+        reduce_slots(part, G, s0, ns, red);
+        for (int q = threadIdx.x; q < 2 * ns; q += blockDim.x)
+            pub[q] = red[q];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        return;
+    }
+    if (threadIdx.x == 0) {
+        long spin = 0;
+        while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spin > kSpinLimit) {
+                atomicOr(&stats[2], 4);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * ns; q += blockDim.x)
+        red[q] = pub[q];
     __syncthreads();
 }
 
@@ -523,6 +578,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
     __shared__ double sh[16];
     __shared__ double wn2_s, rn2_s;
     __shared__ int second_s;
+    __shared__ int last_s;
     __shared__ double lds[2 * LT1];
     __shared__ int l_even[EO ? kMaxOwned : 1], l_odd[EO ? kMaxOwned : 1];  // owned positions by colour
     __shared__ int n_even_s, n_odd_s;
@@ -563,6 +619,19 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
         } else {
             apply_blocks(c, (const int*)nullptr, nbg, a.At, 0, 9, u, (const cpx<T>*)nullptr, 0.0, 1.0, y, lds);
         }
+    };
+    // a grid barrier whose last arrival reduces slots [s0, s0 + ns) into red for everyone
+    double* const pub = a.part + (long)NSLOT * G * 2;
+    auto barrier_reduce = [&](int s0, int ns) {
+        grid_barrier_reduce(a.bar_count, a.bar_gen, bar_target, a.stats, a.part, pub, G, s0, ns, red, &last_s);
+    };
+    // red[q] = red[from + q], q < n (then a workgroup barrier)
+    auto shift_red = [&](int from, int n) {
+        const double v = c.t < n ? red[from + c.t] : 0.0;
+        __syncthreads();
+        if (c.t < n)
+            red[c.t] = v;
+        __syncthreads();
     };
     const cpx<T>* rhs = a.w;
     if (EO) {
@@ -638,15 +707,15 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
         a.r[i] = rhs[i];
     }
     partial_norm2_q(c, rhs, SW);
-    grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
-    reduce_slots(a.part, c.G, SW, 1, red);
+    // SW and the SQ slots are adjacent: one reduction, then the (Q_l, rhs) moved to red[0..]
+    const int nqd = nq > 0 ? (obl ? 2 * nq : nq) : 0;
+    barrier_reduce(SW, 1 + nqd);
     if (c.t == 0)
         wn2_s = red[0];
-    __syncthreads();
+    shift_red(2, 2 * nqd);
     const double wn2 = wn2_s;
     double rn2_0 = wn2;  // ||r||^2 after the projection below (thread 0)
     if (nq > 0) {
-        reduce_slots(a.part, c.G, SQ, obl ? 2 * nq : nq, red);
         rn2_0 = proj_coef(wn2);
         project_q();
     }
@@ -690,8 +759,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                     xk[i] = a.r[i];
                 }
                 partial_norm2(c, a.r, SC, sh);
-                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S1: r complete everywhere
-                reduce_slots(a.part, c.G, SC, 1, red);
+                barrier_reduce(SC, 1);  // S1: r complete everywhere
                 if (c.t == 0)
                     rn2_s = red[0];
                 __syncthreads();
@@ -707,8 +775,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                 // preimage of chi_k is xi_k - Z c_k
                 __syncthreads();
                 partial_zdots(c, ck);
-                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
-                reduce_slots(a.part, c.G, SQ, nq, red);
+                barrier_reduce(SQ, nq);
                 proj_coef(0.0);
                 if (c.t < nq) {
                     qcoef[c.t][k][0] = cq_s[c.t][0];
@@ -721,8 +788,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
             }
             // one Gram-Schmidt pass: everything needed for chi_k, c_k and the new r
             partial_pass(c, a.chi, k, ck, a.r, SA, nqg);
-            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
-            reduce_slots(a.part, c.G, SA, 2 * k + 2 + nqg, red);
+            barrier_reduce(SA, 2 * k + 2 + nqg);  // S2
             // red: [0,k) a_j; [k,2k) (chi_j, r); 2k: ||chi_k||^2; 2k+1: (chi_k, r); [2k+2, 2k+2+nq) (Q_l, chi_k)
             const int q0 = 2 * k + 2;
             // the k + nq <= 64 projections are spread over the lanes of wavefront 0
@@ -765,8 +831,7 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
                 }
                 __syncthreads();
                 partial_pass(c, a.chi, k, ck, a.r, SB, nqg);
-                grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S3
-                reduce_slots(a.part, c.G, SB, 2 * k + 2 + nqg, red);
+                barrier_reduce(SB, 2 * k + 2 + nqg);  // S3
             } else {
                 if (c.t < k) {
                     acoef[c.t][k][0] = 0.0;
@@ -890,15 +955,14 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
         // partial_norm2_q reads each entry from another thread than the one that wrote it
         __syncthreads();
         partial_norm2_q(c, a.r, SR);
-        grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
-        reduce_slots(a.part, c.G, SR, 1, red);
+        // slots SR, SW (not used here) and SQ.. in one reduction; the (Q_l, r) then moved to red[0..]
+        barrier_reduce(SR, 2 + nqd);
         if (c.t == 0)
             rn2_s = red[0];
-        __syncthreads();
+        shift_red(4, 2 * nqd);
         double rn2 = rn2_s;
         if (nq > 0) {
             // project the residue (x moves along Z); ||r||^2 as it is afterwards
-            reduce_slots(a.part, c.G, SQ, obl ? 2 * nq : nq, red);
             rn2 = proj_coef(rn2);
             if (c.t == 0)
                 pn2_s = rn2;  // thread 0's value, shared below
@@ -1565,7 +1629,7 @@ bool little_eo_fits(const Geom& g, int grid)
     return (g.Nb + grid - 1) / grid <= kMaxOwned;
 }
 
-size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * grid_size * 2; }
+size_t little_gcr_partial_doubles(int grid_size) { return (size_t)NSLOT * (grid_size + 1) * 2; }
 
 template <typename T>
 void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, const cpx<T>* At,

@@ -98,6 +98,29 @@ def test_dirac_f32_links(link_prec, tol):
     S.close()
 
 
+@pytest.mark.parametrize("gi", [0, 2])
+@pytest.mark.parametrize("link_prec,tol", [(F32, 1e-5), (BF16, 1e-2)])
+@pytest.mark.parametrize("nrhs,kw", [(1, {}), (3, {}), (1, dict(csw=1.90952, antiperiodic=True)),
+                                     (3, dict(csw=1.90952, antiperiodic=True))])
+def test_dirac_f32_fields_4x4_blocks(gi, link_prec, tol, nrhs, kw):
+    # FP32 spinors on 4^4 layout blocks: one field (halo faces staged in LDS)
+    # and several fields (links held in registers across the fields, the next
+    # field's spinors loaded during the current one) against the oracle, per
+    # field; 8^4 (two blocks per direction) and 16 x 8^3
+    dims, b, sb = GEOMS[gi]
+    say(f"dirac f32 fields {dims} link_prec={link_prec} nrhs={nrhs} {kw}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.5, 31)
+    psi = latgen.random_field(dims, 32, n=nrhs)
+    S = make_solver(dims, b, sb, m0=m0, link_prec=link_prec, sap_prec=F32, nrhs_max=nrhs, **kw)
+    S.set_gauge(U)
+    out = S.unpack(S.dirac(S.pack(psi, prec=F32), prec=F32), prec=F32)
+    for r in range(nrhs):
+        e = rel(out[r], oracle.dirac(U, psi[r], m0, dims, **kw))
+        assert 1e-9 < e < tol, (r, e)
+    S.close()
+
+
 def test_dirac_full_size_sampled():
     # the benchmark's stencil workload, 64 x 32^3, checked on sampled sites
     dims = (64, 32, 32, 32)
