@@ -237,11 +237,14 @@ def dirac_rates(torch):
         S.close()
         del x, y
     torch.cuda.empty_cache()
-    # achievable HBM rate for reference: a device-to-device copy of one FP64 64 x 32^3 field (402 MB)
+    # achievable HBM rate for reference: a device-to-device copy of one FP64 64 x 32^3 field (402 MB);
+    # each stencil rate is also given as a fraction of it
     a = torch.ones(24 * V, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     t = time_events(torch, lambda: b.copy_(a), 20)
     out["copy_gbs"] = 2 * a.numel() * 8 / t / 1e9
+    for name in BYTES_PER_SITE:
+        out[name]["frac_copy"] = out[name]["gbs"] / out["copy_gbs"]
     del a, b
     # 12 fields in one launch on 48 x 24^3 against one field (per field and site: FP64 384 B of
     # spinors, FP32 192 B; the two-row links, 384 / 192 B per site, once per launch)
@@ -267,10 +270,11 @@ def dirac_rates(torch):
         del x, y, x1, y1
         torch.cuda.empty_cache()
     out["multi_field_48x24"] = multi
-    tr = counter_traffic("dirac64", "dirac")
-    if tr is not None:
-        out["f64_tworow"]["counter_bytes_per_launch"] = tr
-        out["f64_tworow"]["counter_gbs"] = tr / (out["f64_tworow"]["us"] * 1e-6) / 1e9
+    for name, summary in [("f64_tworow", "dirac64"), ("f32_tworow", "dirac32"), ("bf16_tworow", "diracbf16")]:
+        tr = counter_traffic(summary, "dirac")
+        if tr is not None:
+            out[name]["counter_bytes_per_launch"] = tr
+            out[name]["counter_gbs"] = tr / (out[name]["us"] * 1e-6) / 1e9
     return dict(lattice=list(DIMS), bytes_per_site=BYTES_PER_SITE, flops_per_site=FLOPS_PER_SITE, **out)
 
 
