@@ -354,8 +354,12 @@ void dirac64_sub(dfl_ctx* c, const c64* s, const c64* in, c64* out, double m0, i
 // psi = M_sap rho for nrhs fields (FP64 in and out; block solves in sap_prec).
 // One launch per colour sweep covers all nrhs fields. rho_nrm2 (FP32 block
 // solves only, may be null): rho_b enters divided by sqrt(rho_nrm2[2 b]), the
-// scale applied while rho is rounded to FP32 (M_sap is linear).
-void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, const double* rho_nrm2 = nullptr)
+// scale applied while rho is rounded to FP32 (M_sap is linear). FP32 block
+// solves leave the result in FP32 in s32b as well; rho_from_s32b: rho is that
+// FP32 result of the previous call (rho is then not read, rho_nrm2 required),
+// and psi may be null (no FP64 result written).
+void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, const double* rho_nrm2 = nullptr,
+               bool rho_from_s32b = false)
 {
     const long n = c->field_elems * nrhs;
     const int ncy = c->p.ncy;
@@ -373,7 +377,9 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, co
     }
     // FP32 block solves on FP32 copies; the last cycle's sweeps also write
     // their blocks' result to psi in FP64 (every block has one of the colours)
-    if (rho_nrm2)
+    if (rho_from_s32b)
+        launch_f32_scaled(c->s32b, c->s32a, c->field_elems, nrhs, rho_nrm2, 2, c->stream);
+    else if (rho_nrm2)
         launch_f64_to_f32_scaled(rho, c->s32a, c->field_elems, nrhs, rho_nrm2, 2, c->stream);
     else
         launch_f64_to_f32(rho, c->s32a, n, c->stream);
@@ -939,12 +945,17 @@ void inverse_iterate(dfl_ctx* c, const c64* src, c64* dst, int n, int steps, boo
     }
     // FP32 block solves: each normalisation before a step is the scale of the
     // step's rounding to FP32 (M_sap is linear, so the step maps the
-    // normalised field), the first step reads src and writes dst, and only a
-    // final normalisation rewrites the fields
+    // normalised field). The first step reads src; the later ones read the
+    // previous step's FP32 result (its FP64 copy would hold the same values,
+    // so the norms and the scaled roundings are the same bits), and only the
+    // last step writes dst in FP64; a final normalisation rewrites the fields
     for (int step = 0; step < steps; ++step) {
-        const c64* in = step == 0 ? src : dst;
-        launch_norm2_b<double>(in, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
-        sap_apply(c, in, dst, c->p.m0_setup, n, c->dnorm);  // staged through s32a/s32b
+        const bool last = step == steps - 1;
+        if (step == 0)
+            launch_norm2_b<double>(src, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
+        else
+            launch_norm2_b<float>(c->s32b, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
+        sap_apply(c, src, last ? dst : nullptr, c->p.m0_setup, n, c->dnorm, step > 0);  // through s32a/s32b
     }
     if (normalise_out)
         normalise();

@@ -115,10 +115,12 @@ __global__ __launch_bounds__(256) void k_f64_to_f32(const c64* __restrict__ in, 
         out[i] = c32{(float)in[i].re, (float)in[i].im};
 }
 
-// out_b = in_b / sqrt(nrm2[b * cstride]) rounded to FP32 (the scale in FP64),
-// field b of n entries at b * n; blockIdx.y = field
-__global__ __launch_bounds__(256) void k_f64_to_f32_scaled(const c64* __restrict__ in, c32* __restrict__ out, long n,
-                                                           const double* __restrict__ nrm2, int cstride)
+// out_b = in_b / sqrt(nrm2[b * cstride]) rounded to FP32 (the product in FP64, so
+// an FP32 input gives the same bits as its exact FP64 copy), field b of n
+// entries at b * n; blockIdx.y = field
+template <typename TI>
+__global__ __launch_bounds__(256) void k_to_f32_scaled(const cpx<TI>* __restrict__ in, c32* __restrict__ out, long n,
+                                                       const double* __restrict__ nrm2, int cstride)
 {
     const int b = blockIdx.y;
     const double q = nrm2[(long)b * cstride];
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(256) void k_f64_to_f32_scaled(const c64* __restrict
     in += (long)b * n;
     out += (long)b * n;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        out[i] = c32{(float)(in[i].re * f), (float)(in[i].im * f)};
+        out[i] = c32{(float)((double)in[i].re * f), (float)((double)in[i].im * f)};
 }
 
 __global__ __launch_bounds__(256) void k_f32_to_f64(const c32* __restrict__ in, c64* __restrict__ out, long n)
@@ -169,7 +171,15 @@ void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const dou
 {
     if (n > 0 && nb > 0) {
         const long blocks = std::min<long>((n + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_f64_to_f32_scaled, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
+        hipLaunchKernelGGL(k_to_f32_scaled<double>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
+                           nrm2, cstride);
+    }
+}
+void launch_f32_scaled(const c32* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s)
+{
+    if (n > 0 && nb > 0) {
+        const long blocks = std::min<long>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_to_f32_scaled<float>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
                            nrm2, cstride);
     }
 }
