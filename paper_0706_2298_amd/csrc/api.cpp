@@ -989,7 +989,6 @@ void build_subspace(dfl_ctx* c, const c64* src, double mA)
     if (src != c->Phi)
         HIPCHECK(hipMemcpyAsync(c->Phi, src, sizeof(c64) * F * Ns, hipMemcpyDeviceToDevice, c->stream));
     ProfScope ps_setup(c, DFL_PROF_SETUP);
-    launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->gsR, c->stream);
     // little operator, eq. (A.1): block-diagonal part and the eight face
     // hops, applied to a chunk of basis fields per launch (the Krylov
     // buffer is free during the setup), then the block products with Phi.
@@ -1003,10 +1002,14 @@ void build_subspace(dfl_ctx* c, const c64* src, double mA)
     // (x3 fastest); their hops and block products read a copy of the basis in
     // the transposed order, where those faces are whole tiles or long runs.
     const bool tl = little_columns_transposable(Ns, chunk);
-    if (tl) {
+    if (tl)
         c->PhiT = grow<c64>(c, c->PhiT, c->PhiT_n, (size_t)F * Ns);
+    // block Gram-Schmidt (eq. (4.2)); the 256-site block kernel also writes the
+    // transposed copy and the FP32 copy of the basis
+    const bool copies = launch_block_gs64(c->g, c->Phi, Ns, 1e-10, c->dflag, c->gsR, c->stream,
+                                          tl ? c->PhiT : nullptr, c->Phi32);
+    if (tl && !copies)
         launch_to_transposed(c->g, c->Phi, c->PhiT, Ns, c->stream);
-    }
     for (int l0 = 0; l0 < Ns; l0 += chunk) {
         const int nc = std::min(chunk, Ns - l0);
         for (int d = 0; d < 9; ++d) {
@@ -1022,7 +1025,7 @@ void build_subspace(dfl_ctx* c, const c64* src, double mA)
         }
     }
     launch_little_copies(c->A64, c->A32, c->At64, c->At32, (long)c->g.Nb * 9, Ns, c->stream);
-    if (c->Phi32)
+    if (c->Phi32 && !copies)
         launch_f64_to_f32(c->Phi, c->Phi32, F * Ns, c->stream);
     c->eo_ok = false;
     c->m0_A = mA;

@@ -171,6 +171,46 @@ __global__ __launch_bounds__(256) void k_prolong(Geom g, const P* __restrict__ P
     }
 }
 
+// The same when every 64-site tile lies in one block (Vb a multiple of 64):
+// a workgroup's 256 entries are a third of one tile, so the block and its
+// coefficients are uniform across the workgroup (scalar loads), and eight
+// basis fields' loads are issued together.
+template <typename P>
+__global__ __launch_bounds__(256) void k_prolong_tile(Geom g, const P* __restrict__ Phi, int Ns,
+                                                      const c64* __restrict__ v, c64* __restrict__ psi, int nrhs)
+{
+    constexpr int KU = 8;
+    const long fs = 12 * g.V;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long blk = (long)(blockIdx.x / 3) * kTile / g.Vb;
+    const long nw = (long)g.Nb * Ns;
+    for (int b0 = 0; b0 < nrhs; b0 += kRB) {
+        c64 acc[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j)
+            acc[j] = c64{0.0, 0.0};
+        for (int k0 = 0; k0 < Ns; k0 += KU) {
+            c64 a[KU];
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int k = min(k0 + u, Ns - 1);  // past Ns: a valid field, weight dropped below
+                a[u] = c64{(double)Phi[(long)k * fs + i].re, (double)Phi[(long)k * fs + i].im};
+            }
+#pragma unroll
+            for (int u = 0; u < KU; ++u)
+                if (k0 + u < Ns)
+#pragma unroll
+                    for (int j = 0; j < kRB; ++j)
+                        if (b0 + j < nrhs)
+                            acc[j] += a[u] * v[(long)(b0 + j) * nw + blk * Ns + k0 + u];
+        }
+#pragma unroll
+        for (int j = 0; j < kRB; ++j)
+            if (b0 + j < nrhs)
+                psi[(long)(b0 + j) * fs + i] = acc[j];
+    }
+}
+
 // Modified Gram-Schmidt per block, in place, order l = 0..Ns-1 (eq. (4.2)).
 // flag is set to 1 if a block loses rank; R (may be null) receives the
 // triangular factor. One workgroup per block; the field being orthogonalised
@@ -284,7 +324,8 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
 // same sequence of projections as in k_block_gs, so the results are equal.
 template <int E, int NT>
 __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
-                                                   int* __restrict__ flag, c64* __restrict__ R)
+                                                   int* __restrict__ flag, c64* __restrict__ R, c64* __restrict__ FT,
+                                                   c32* __restrict__ F32)
 {
     __shared__ double2 sh[2][NT / 64];
     const int blk = blockIdx.x;
@@ -341,8 +382,19 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
         for (int j = 0; j < E; ++j) {
             v[j] = c64{v[j].re * inv, v[j].im * inv};
             const int e = threadIdx.x + j * NT;
-            if (e < ne)
-                fl[block_elem(g, blk, e)] = v[j];
+            if (e < ne) {
+                const long i = block_elem(g, blk, e);
+                fl[i] = v[j];
+                if (F32)
+                    F32[(long)l * fs + i] = c32{(float)v[j].re, (float)v[j].im};
+                if (FT) {
+                    // the same entry in the transposed in-block order
+                    const long st = (i / (12 * kTile)) * kTile + (i & (kTile - 1));
+                    int n[4], y[4];
+                    site_decompose(g, st, n, y);
+                    FT[(long)l * fs + tidx(site_compose_t(g, n, y), (int)((i / kTile) % 12), 12)] = v[j];
+                }
+            }
         }
     };
     for (int l = 0; l < Ns; l += 2) {
@@ -1098,7 +1150,11 @@ template <typename P>
 void prolong_any(const Geom& g, const P* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s)
 {
     const long n = 12 * g.V;
-    hipLaunchKernelGGL(k_prolong<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi, nrhs);
+    if (g.Vb % kTile == 0)  // then n is a multiple of 3 * 256
+        hipLaunchKernelGGL(k_prolong_tile<P>, dim3((unsigned)(n / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi, nrhs);
+    else
+        hipLaunchKernelGGL(k_prolong<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, Phi, Ns, v, psi,
+                           nrhs);
 }
 void launch_restrict64(const Geom& g, const c64* Phi, int Ns, const c64* psi, c64* w, int nrhs, hipStream_t s)
 {
@@ -1116,17 +1172,23 @@ void launch_prolong_b32(const Geom& g, const c32* Phi, int Ns, const c64* v, c64
 {
     prolong_any(g, Phi, Ns, v, psi, nrhs, s);
 }
-void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s)
+bool launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s, c64* FT,
+                       c32* F32)
 {
     const int e = (12 * (int)g.Vb + kBT - 1) / kBT;  // entries per thread
     if (e <= 6)
         hipLaunchKernelGGL(k_block_gs<6>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
-    else if (e <= 12)  // two fields at a time, 512 threads: six entries of each per thread
-        hipLaunchKernelGGL((k_block_gs2<6, 512>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R);
+    else if (e <= 12 && g.Vb % kTile == 0) {  // two fields at a time, 512 threads: six entries of each per thread
+        hipLaunchKernelGGL((k_block_gs2<6, 512>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R, FT, F32);
+        return true;
+    } else if (e <= 12)
+        hipLaunchKernelGGL((k_block_gs2<6, 512>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R, nullptr,
+                           nullptr);
     else if (e <= 24)
         hipLaunchKernelGGL(k_block_gs<24>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
     else
         hipLaunchKernelGGL(k_block_gs_stream, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
+    return FT == nullptr && F32 == nullptr;
 }
 int little_columns_max(int Ns)
 {

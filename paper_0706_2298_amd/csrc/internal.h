@@ -307,7 +307,11 @@ void launch_restrict_b32(const Geom& g, const c32* Phi, int Ns, const c64* psi, 
 void launch_prolong_b32(const Geom& g, const c32* Phi, int Ns, const c64* v, c64* psi, int nrhs, hipStream_t s);
 // block Gram-Schmidt in place on Ns fields (modified GS, order l = 0..Ns-1);
 // R (may be null): [Nb][Ns][Ns] coefficients, field l = sum_k R[k][l] basis k
-void launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s);
+// FT, F32 (may be null): the result also in the transposed in-block order
+// (site_compose_t) and in FP32; returns whether those copies were written (the
+// 256-site block kernel writes them, the caller makes them otherwise)
+bool launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag, c64* R, hipStream_t s,
+                       c64* FT = nullptr, c32* F32 = nullptr);
 // global modes of the little system from R: Ns little vectors, even blocks only
 void launch_global_modes(const Geom& g, const c64* R, int Ns, c64* U, hipStream_t s);
 // on blocks of the given parity: out = alpha sv + beta sum_{d>=1} (D^-1 A_d) in_{nbr} (nv vectors)

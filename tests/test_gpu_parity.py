@@ -228,6 +228,31 @@ def test_projectors(c1):
     S.close()
 
 
+@pytest.mark.parametrize("gi", [1, 2])
+def test_projectors_block_shapes(gi):
+    # restriction and prolongation on 60-site blocks (a 64-site tile spans
+    # several blocks: the general prolongation kernel) and on 4^4 blocks of a
+    # 16 x 8^3 lattice (the tile kernel); without inverse-iteration steps the
+    # basis is the block Gram-Schmidt of the start fields
+    dims, b, sb = GEOMS[gi]
+    say(f"projectors {dims} blocks {b}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.4, 91)
+    init = latgen.make_init_fields(dims, 3, 92)
+    S = make_solver(dims, b, sb, Ns=3, n_inviter=0, m0=m0, m0_setup=m0)
+    S.set_gauge(U)
+    S.setup(S.pack(init))
+    Phi = oracle.block_gram_schmidt(init, dims, b)
+    A = oracle.little_operator(U, Phi, m0, dims, b)
+    dfl = oracle.Deflation(U, Phi, A, m0, dims, b)
+    y = latgen.make_source(dims, 93)
+    yd = S.pack(y)
+    for which, ref in [(PROJ_P, dfl.P(y)), (PROJ_COARSE, dfl.coarse(y)), (PROJ_PL, dfl.PL(y)), (PROJ_PR, dfl.PR(y))]:
+        got = S.unpack(S.project(which, yd))[0]
+        assert rel(got, ref) < 1e-9, which
+    S.close()
+
+
 def test_solve_dfl_sap_gcr_c1(c1):
     say("solve DFL+SAP+GCR c1")
     dims = c1["dims"]
