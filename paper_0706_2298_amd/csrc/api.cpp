@@ -1516,7 +1516,6 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
     need_gauge(c);
     if (n_init != c->p.Ns)
         fail(DFL_EINVAL, "n_init must equal Ns");
-    const long F = c->field_elems;
     const int Ns = c->p.Ns;
     const int nb = c->p.n_boot;
     // captured GCR steps keep the even-odd and global-deflation state (and
@@ -1925,7 +1924,6 @@ int deficit_loss(dfl_ctx* c, const void* fields, int Ns, const void* targets, in
         fail(DFL_EINVAL, "Ns exceeds the dimension of a block");
     const long Nb = c->g.Nb;
     const size_t nY = (size_t)Nb * Ns * K;
-    const size_t nbuf = (size_t)Nb * K * 2 + K;
     if (nY > c->loss_n || !c->loss_buf) {
         sync(c);
         if (c->loss_Y)
