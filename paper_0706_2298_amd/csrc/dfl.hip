@@ -331,6 +331,7 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
     const int blk = blockIdx.x;
     const long fs = 12 * g.V;
     const int ne = 12 * g.Vb;
+    const bool b4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
     // sums over the workgroup of two complex values at once (as two block_sum2)
     auto sum2x2 = [&](double2& a, double2& b) {
         a.x = wave_sum(a.x);
@@ -389,10 +390,20 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
                     F32[(long)l * fs + i] = c32{(float)v[j].re, (float)v[j].im};
                 if (FT) {
                     // the same entry in the transposed in-block order
-                    const long st = (i / (12 * kTile)) * kTile + (i & (kTile - 1));
-                    int n[4], y[4];
-                    site_decompose(g, st, n, y);
-                    FT[(long)l * fs + tidx(site_compose_t(g, n, y), (int)((i / kTile) % 12), 12)] = v[j];
+                    long it;
+                    if (b4) {
+                        // 4^4 block, entry e = 768 y0 + 64 c + 16 y1 + 4 y2 + y3: the transposed
+                        // site has tile y3 and lane 16 y2 + 4 y1 + y0
+                        const int y0 = e / (12 * kTile), ln = e & (kTile - 1), c = (e >> 6) % 12;
+                        it = (long)blk * ne + (ln & 3) * (12 * kTile) + c * kTile + ((ln >> 2) & 3) * 16 +
+                             (ln >> 4) * 4 + y0;
+                    } else {
+                        const long st = (i / (12 * kTile)) * kTile + (i & (kTile - 1));
+                        int n[4], y[4];
+                        site_decompose(g, st, n, y);
+                        it = tidx(site_compose_t(g, n, y), (int)((i / kTile) % 12), 12);
+                    }
+                    FT[(long)l * fs + it] = v[j];
                 }
             }
         }
