@@ -145,6 +145,12 @@ typedef struct {
     int n_little_solves; /* number of little solves */
     double rel_residual; /* ||eta - D psi|| / ||eta||, recomputed in FP64 at the end */
     double t_solve;      /* seconds from entry to return */
+    double t_setup;      /* seconds of the last dfl_setup on this context (entry to return;
+                            0 before the first) */
+    double t_sap;        /* kernel seconds of this solve in the Schwarz sweeps, the stencil, */
+    double t_dirac;      /* the restriction and prolongation and the little solves, from the */
+    double t_proj;       /* library's event timers while dfl_profile_enable(ctx, 1) is on; */
+    double t_little;     /* -1 when it is off (the timers cost a few us per launch) */
 } dfl_info;
 
 /* Fill *p with defaults: 4^4 blocks, Ns = 20, ncy = 5, nmr = 4, nkv = 16,

@@ -42,6 +42,8 @@ class Info(ctypes.Structure):
         ("status", ctypes.c_int), ("n_gcr", ctypes.c_int), ("n_restarts", ctypes.c_int),
         ("n_little", ctypes.c_int), ("n_little_solves", ctypes.c_int),
         ("rel_residual", ctypes.c_double), ("t_solve", ctypes.c_double),
+        ("t_setup", ctypes.c_double), ("t_sap", ctypes.c_double), ("t_dirac", ctypes.c_double),
+        ("t_proj", ctypes.c_double), ("t_little", ctypes.c_double),
     ]
 
     def as_dict(self):

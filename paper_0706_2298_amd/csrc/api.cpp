@@ -1511,6 +1511,7 @@ int sap_precond(dfl_ctx* c, const void* rho, void* psi, int nrhs)
 int dfl_setup(dfl_ctx* c, const void* init, int n_init)
 {
     API_BEGIN
+    const auto ts0 = std::chrono::steady_clock::now();
     need_ctx(c);
     need_ptr(init, "init fields (the caller draws the random start fields)");
     need_gauge(c);
@@ -1540,8 +1541,9 @@ int dfl_setup(dfl_ctx* c, const void* init, int n_init)
         build_subspace(c, fields, c->p.m0_setup);
         bootstrap_step(c, fields);
     }
-    build_subspace(c, fields, c->p.m0);
+    build_subspace(c, fields, c->p.m0);  // synchronises
     c->have_subspace = true;
+    c->t_setup_last = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts0).count();
     API_END
 }
 
@@ -1672,6 +1674,13 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
     const double m0 = c->p.m0;
     const int nb = nrhs;
     auto t0 = std::chrono::steady_clock::now();
+    // per-class kernel seconds of this solve (event timers, profiling on)
+    double prof0[DFL_PROF_NCLASS] = {0};
+    if (c->prof_on) {
+        prof_collect(c);
+        for (int k = 0; k < DFL_PROF_NCLASS; ++k)
+            prof0[k] = c->prof_t[k];
+    }
     const c64* eta = static_cast<const c64*>(eta_v);
     c64* psi = static_cast<c64*>(psi_v);
     HIPCHECK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
@@ -1740,6 +1749,8 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
     dirac64_sub(c, eta, psi, c->t2, m0, nb);
     std::vector<double> rr = host_norm2_b(c, c->t2, F, nb);
     auto t1 = std::chrono::steady_clock::now();
+    if (c->prof_on)
+        prof_collect(c);
     int ls[3] = {0, 0, 0};
     read_little_stats(c, ls);
     for (int b = 0; b < nb; ++b) {
@@ -1758,6 +1769,14 @@ int solve(dfl_ctx* c, const void* eta_v, void* psi_v, int nrhs, dfl_info* info)
             q.n_little_solves = ls[1];
             q.rel_residual = rel;
             q.t_solve = std::chrono::duration<double>(t1 - t0).count();
+            q.t_setup = c->t_setup_last;
+            q.t_sap = q.t_dirac = q.t_proj = q.t_little = -1.0;
+            if (c->prof_on) {
+                q.t_sap = c->prof_t[DFL_PROF_SAP] - prof0[DFL_PROF_SAP];
+                q.t_dirac = c->prof_t[DFL_PROF_DIRAC] - prof0[DFL_PROF_DIRAC];
+                q.t_proj = c->prof_t[DFL_PROF_PROJECT] - prof0[DFL_PROF_PROJECT];
+                q.t_little = c->prof_t[DFL_PROF_LITTLE] - prof0[DFL_PROF_LITTLE];
+            }
         }
     }
     if (worst != DFL_OK) {

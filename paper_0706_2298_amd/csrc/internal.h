@@ -180,6 +180,7 @@ struct dfl_ctx {
     std::vector<std::pair<long, hipGraphExec_t>> graphs;
     long graph_replays = 0;
     // kernel-class timers
+    double t_setup_last = 0.0;  // seconds of the last dfl_setup
     bool prof_on = false;
     int sap_prof_cls = DFL_PROF_SAP;  // class the Schwarz sweeps are timed in (setup during inverse iteration)
     std::vector<hipEvent_t> ev_pool;                 // free events

@@ -121,6 +121,27 @@ def test_dirac_f32_fields_4x4_blocks(gi, link_prec, tol, nrhs, kw):
     S.close()
 
 
+@pytest.mark.parametrize("geom", [GEOMS[1], ((16, 8, 8, 8), (8, 4, 4, 2), (4, 4, 4, 4))])
+@pytest.mark.parametrize("link_prec,tol", [(F32, 1e-5), (BF16, 1e-2)])
+@pytest.mark.parametrize("kw", [{}, dict(csw=1.90952, antiperiodic=True)])
+def test_dirac_f32_fields_other_blocks(geom, link_prec, tol, kw):
+    # FP32 spinors on layout blocks other than 4^4: 60-site blocks (the
+    # generic one-thread-per-site kernel) and 8x4x4x2 blocks (256 sites: the
+    # block kernel with the spinors in LDS), two fields
+    dims, b, sb = geom
+    say(f"dirac f32 other blocks {dims} {b} link_prec={link_prec} {kw}")
+    m0 = -0.2
+    U = latgen.make_links(dims, 0.5, 41)
+    psi = latgen.random_field(dims, 42, n=2)
+    S = make_solver(dims, b, sb, m0=m0, link_prec=link_prec, sap_prec=F32, nrhs_max=2, **kw)
+    S.set_gauge(U)
+    out = S.unpack(S.dirac(S.pack(psi, prec=F32), prec=F32), prec=F32)
+    for r in range(2):
+        e = rel(out[r], oracle.dirac(U, psi[r], m0, dims, **kw))
+        assert 1e-9 < e < tol, (r, e)
+    S.close()
+
+
 def test_dirac_full_size_sampled():
     # the benchmark's stencil workload, 64 x 32^3, checked on sampled sites
     dims = (64, 32, 32, 32)
@@ -273,6 +294,24 @@ def test_solve_dfl_sap_gcr_c1(c1):
     ref, _, ok = oracle.solve(c1["U"], c1["eta"], c1["m0"], dims, sap_block=(4, 4, 4, 4), dfl=dfl, tol=1e-12)
     assert ok
     assert np.linalg.norm(psi - ref) <= 1e-9 * np.linalg.norm(ref)
+    S.close()
+
+
+def test_solve_info_times(c1):
+    # dfl_info carries the last setup's time and, with the event timers on, the
+    # solve's kernel seconds per class; without them those read -1
+    from paper_0706_2298_amd import binding
+    say("solve info times c1")
+    S = _c1_solver(c1, tol=1e-10)
+    _, info = S.solve(S.pack(c1["eta"]))
+    assert info.status == 0 and info.t_setup > 0.0
+    assert info.t_sap == info.t_dirac == info.t_proj == info.t_little == -1.0
+    binding.dfl_profile_enable(S.ctx, 1)
+    _, info = S.solve(S.pack(c1["eta"]))
+    parts = [info.t_sap, info.t_dirac, info.t_proj, info.t_little]
+    assert all(t > 0.0 for t in parts), info.as_dict()
+    assert sum(parts) <= info.t_solve, info.as_dict()
+    binding.dfl_profile_enable(S.ctx, 0)
     S.close()
 
 
