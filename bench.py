@@ -58,6 +58,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_NONPACKED_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # 78.6: one (non-packed) FP32 FMA per lane and cycle
 FLOPS_PER_SITE = 1368            # Wilson stencil per site per right-hand side (1320 hop + 48 diagonal)
 # links are stored as two rows of the SU(3) matrix in every precision (the third row is rebuilt)
 BYTES_PER_SITE = {"f64_tworow": 768, "f32_tworow": 384, "bf16_tworow": 288}
@@ -188,7 +189,10 @@ def roofline(prof):
                 f"k_sap_rl<Links32, 4^4> (Schwarz colour sweep of the {NS} inverse-iteration fields, FP32)")
         r = dict(kernel=kern, bound="alu", achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                  frac=ach / FP32_VECTOR_PEAK_TFLOPS,
-                 per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {half} sites x {nf} fields")
+                 per_launch=f"{flops:.4g} flop = {sap_flops_per_site(NMR)} flop/site x {half} sites x {nf} fields",
+                 # the library is built without packed FP32 instructions: one FP32 FMA per lane and cycle,
+                 # 256 CUs x 64 lanes x 2 flop x 2.4 GHz
+                 peak_nonpacked=FP32_NONPACKED_PEAK_TFLOPS, frac_nonpacked=ach / FP32_NONPACKED_PEAK_TFLOPS)
     elif cls == "little":
         it = prof["little_iterations"] / max(n, 1)
         # even-odd step: the eight neighbour blocks of D^-1 A over all blocks
