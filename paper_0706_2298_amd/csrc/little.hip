@@ -1060,6 +1060,7 @@ template <> struct Mfma<double> {
     static __device__ inline int row(int kq, int i) { return 4 * i + kq; }
 };
 
+constexpr int kMfmaBatch = 6;  // MFMA steps whose operands are in flight together (2 Ns = 48: two batches)
 template <typename T>
 __device__ inline void apply_multi_mfma(const MultiCtx<T>& c, const cpx<T>* __restrict__ v, long vstride,
                                         cpx<T>* __restrict__ y, long ystride, const int* list, int nlist)
@@ -1076,25 +1077,38 @@ __device__ inline void apply_multi_mfma(const MultiCtx<T>& c, const cpx<T>* __re
         const int rr = 16 * tt + n;
         const int m = rr >> 1, cr = rr & 1;
         typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll 1
         for (int d = 0; d < 9; ++d) {
             const int nbr = nbr_block(g, blk, d);
             const cpx<T>* Ad = c.a.At + ((long)blk * 9 + d) * Ns * Ns;
             const cpx<T>* vb = v + b_n * vstride + (long)nbr * Ns;
-            for (int kc = 0; kc < 2 * Ns; kc += 4) {
-                const int kk = kc + kq;
-                const int l = kk >> 1, ck = kk & 1;
-                T a = 0, bv = 0;
-                if (kk < 2 * Ns) {
-                    if (m < Ns) {
-                        const cpx<T> z = Ad[(long)l * Ns + m];
-                        a = cr == 0 ? (ck == 0 ? z.re : -z.im) : (ck == 0 ? z.im : z.re);
-                    }
-                    if (n < nlist) {
-                        const cpx<T> q = vb[l];
-                        bv = ck == 0 ? q.re : q.im;
-                    }
+            // the operands of kMfmaBatch steps loaded together, then their products
+#pragma unroll 1
+            for (int kc0 = 0; kc0 < 2 * Ns; kc0 += 4 * kMfmaBatch) {
+                T av[kMfmaBatch], bw[kMfmaBatch];
+                // clamped indices: every load is issued (no branch between them), the
+                // out-of-range operands are zeroed afterwards
+                cpx<T> za[kMfmaBatch], qa[kMfmaBatch];
+#pragma unroll
+                for (int st = 0; st < kMfmaBatch; ++st) {
+                    const int kk = min(kc0 + 4 * st + kq, 2 * Ns - 1);
+                    const int l = kk >> 1;
+                    za[st] = Ad[(long)l * Ns + min(m, Ns - 1)];
+                    qa[st] = vb[l];
                 }
-                acc = Mfma<T>::step(a, bv, acc);
+#pragma unroll
+                for (int st = 0; st < kMfmaBatch; ++st) {
+                    const int kk = kc0 + 4 * st + kq;
+                    const int ck = kk & 1;
+                    const bool in = kk < 2 * Ns;
+                    const cpx<T> z = za[st], q = qa[st];
+                    av[st] = (in && m < Ns) ? (cr == 0 ? (ck == 0 ? z.re : -z.im) : (ck == 0 ? z.im : z.re)) : T(0);
+                    bw[st] = (in && n < nlist) ? (ck == 0 ? q.re : q.im) : T(0);
+                }
+#pragma unroll
+                for (int st = 0; st < kMfmaBatch; ++st)
+                    if (kc0 + 4 * st < 2 * Ns)
+                        acc = Mfma<T>::step(av[st], bw[st], acc);
             }
         }
         if (n < nlist) {
