@@ -113,9 +113,9 @@ typedef struct {
                               number of workgroups the device holds at once */
     int little_adapt;      /* 1: inside a cycle, relax the little-solve tolerance in
                               proportion to the fall of the residue (appendix A.5) */
-    int little_eo;         /* 1: single-source little solves run GCR on the even-odd
-                              reduced system (appendix A.2), falling back to A when a
-                              diagonal block is not safely invertible */
+    int little_eo;         /* 1: little solves (single-source and batched) run GCR on the
+                              even-odd reduced system (appendix A.2), falling back to A
+                              when a diagonal block is not safely invertible */
     int little_gdefl;      /* global-mode deflation of the even-odd little system
                               (appendix A.3; with little_eo and Ns <= 32) by the
                               even-block parts of the global fields the subspace was built

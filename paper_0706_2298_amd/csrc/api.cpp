@@ -588,6 +588,7 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
 {
     const long n = (long)c->g.Nb * c->p.Ns;
     const int Ns = c->p.Ns, nkv = c->p.little_nkv, mi = c->p.little_maxiter;
+    const bool eo_multi = nb > 1 && c->eo_ok && little_eo_fits(c->g, c->lgrid_multi);
     if (prec == DFL_F64) {
         ProfScope ps(c, DFL_PROF_LITTLE);
         if (nb == 1)
@@ -598,7 +599,9 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
                                       static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lstats,
                                       c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
         else
-            launch_little_gcr_multi<double>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At64, w, v, static_cast<c64*>(c->lr),
+            launch_little_gcr_multi<double>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At64, eo_multi ? c->Mt64 : nullptr,
+                                            static_cast<c64*>(c->lw1), static_cast<c64*>(c->lw2), w, v,
+                                            static_cast<c64*>(c->lr),
                                             static_cast<c64*>(c->lxi), static_cast<c64*>(c->lchi), c->lpart, c->lfin,
                                             c->lacoef, c->lstats, c->lbar_count, c->lbar_gen,
                                             c->lgrid_multi, c->stream, !c->capturing);
@@ -614,7 +617,9 @@ void little_solve_impl(dfl_ctx* c, const c64* w, c64* v, double tol, dfl_prec pr
                                          static_cast<c32*>(c->lxi), static_cast<c32*>(c->lchi), c->lpart, c->lstats,
                                          c->lbar_count, c->lbar_gen, c->lgrid, c->stream, !c->capturing);
             else
-                launch_little_gcr_multi<float>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At32, c->lw32, c->lx32,
+                launch_little_gcr_multi<float>(c->g, Ns, nkv, mi, tol, tol_dev, nb, c->At32,
+                                               eo_multi ? c->Mt32 : nullptr, static_cast<c32*>(c->lw1),
+                                               static_cast<c32*>(c->lw2), c->lw32, c->lx32,
                                                static_cast<c32*>(c->lr), static_cast<c32*>(c->lxi),
                                                static_cast<c32*>(c->lchi), c->lpart, c->lfin, c->lacoef, c->lstats,
                                                c->lbar_count, c->lbar_gen, c->lgrid_multi, c->stream, !c->capturing);
@@ -1247,8 +1252,8 @@ int dfl_create(dfl_ctx** out, const dfl_params* p, void* hip_stream)
         if (p->little_eo) {
             c->Mt64 = alloc_dev<c64>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
             c->Mt32 = alloc_dev<c32>(c, (size_t)c->g.Nb * 9 * p->Ns * p->Ns);
-            c->lw1 = alloc_dev<c64>(c, N);
-            c->lw2 = alloc_dev<c64>(c, N);
+            c->lw1 = alloc_dev<c64>(c, (size_t)p->nrhs_max * N);  // one vector per source
+            c->lw2 = alloc_dev<c64>(c, (size_t)p->nrhs_max * N);
             if (p->little_gdefl && p->Ns <= kMaxLittleDefl) {
                 c->gsR = alloc_dev<c64>(c, (size_t)c->g.Nb * p->Ns * p->Ns);
                 c->gU = alloc_dev<c64>(c, (size_t)p->Ns * N);

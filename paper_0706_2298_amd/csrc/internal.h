@@ -419,11 +419,14 @@ void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, 
 
 // The same for nrhs systems at once (nrhs <= kMaxLittleRhs): w, x, r hold
 // nrhs little vectors back to back, xi and chi nkv * nrhs. Sizes of part,
-// fin and acoef (doubles) come from little_gcr_multi_doubles.
+// fin and acoef (doubles) come from little_gcr_multi_doubles. With Mt
+// non-null each system is solved in its even-odd reduced form (appendix A.2;
+// w1 and w2 hold nrhs vectors each, little_eo_fits must hold for the grid);
+// global-mode deflation is not applied here.
 size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef);
 template <typename T>
 void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, int nrhs,
-                             const cpx<T>* At,
+                             const cpx<T>* At, const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2,
                              const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
                              double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, int grid,
                              hipStream_t s, bool cooperative = true);

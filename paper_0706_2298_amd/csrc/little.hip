@@ -1011,6 +1011,9 @@ template <typename T> struct LittleMultiArgs {
     double tol2;
     const double* tol_dev;
     const cpx<T>* At;
+    const cpx<T>* Mt;  // even-odd matrices (even-odd kernel only)
+    cpx<T>* w1;        // M_0 w, nrhs vectors (even-odd kernel only)
+    cpx<T>* w2;        // the reduced right-hand sides on even blocks, the odd-block intermediate of the operator
     const cpx<T>* w;
     cpx<T>* x;
     cpx<T>* r;
@@ -1028,23 +1031,26 @@ template <typename T> struct MultiCtx {
     const LittleMultiArgs<T>& a;
     int G, g, t, nbg, R;
     long N;
+    const int* vb;  // positions of the blocks the vectors live on (even-odd: the even ones), null: all owned
     __device__ long entry(int e) const
     {
         int i = e / a.Ns;
         int k = e - i * a.Ns;
-        return (long)(g + i * G) * a.Ns + k;
+        return (long)(g + (vb ? vb[i] : i) * G) * a.Ns + k;
     }
     __device__ double* pslot(int slot, int b) const { return a.part + (((long)slot * a.nrhs + b) * G + g) * 2; }
 };
 
-// y_b = A v_b on the owned rows for the listed sources, on the matrix cores:
-// for an owned block the nine terms
-// sum_d A_d V_d (V_d: the listed sources' entries on the d-th neighbour, Ns x
-// nlist) form one real GEMM of the 2Ns x 18Ns matrix [[ar, -ai], [ai, ar]]
-// (rows and columns interleaved re/im) with the 18Ns x nlist matrix of the
-// V_d entries read as reals, in 16x16x4 tiles (FP32 or FP64 MFMA). Wave w
+// y_b = alpha s_b + beta sum_{d0 <= d < d1} M_d v_b on owned blocks for the
+// listed sources, on the matrix cores: for an owned block the terms
+// sum_d M_d V_d (V_d: the listed sources' entries on the d-th neighbour, Ns x
+// nlist) form one real GEMM of the 2Ns x 2(d1-d0)Ns matrix [[ar, -ai], [ai, ar]]
+// (rows and columns interleaved re/im) with the 2(d1-d0)Ns x nlist matrix of
+// the V_d entries read as reals, in 16x16x4 tiles (FP32 or FP64 MFMA). Wave w
 // takes (block, row tile) tasks w, w + 16, ...; the sources (<= 16) are the
-// 16 columns. A is read from the transposed blocks At, coalesced in the row.
+// 16 columns. M (A or the even-odd matrices) is read from transposed blocks,
+// coalesced in the row. pos lists the npos owned positions to apply on (null:
+// positions 0..npos-1); s is read only when alpha is not zero.
 template <typename T> struct Mfma;
 // Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result
 // element i of lane l is D[row(l / 16, i)][l % 16], with the row order of
@@ -1062,8 +1068,9 @@ template <> struct Mfma<double> {
 
 constexpr int kMfmaBatch = 6;  // MFMA steps whose operands are in flight together (2 Ns = 48: two batches)
 template <typename T>
-__device__ inline void apply_multi_mfma(const MultiCtx<T>& c, const cpx<T>* __restrict__ v, long vstride,
-                                        cpx<T>* __restrict__ y, long ystride, const int* list, int nlist)
+__device__ inline void apply_multi_mfma(const MultiCtx<T>& c, const cpx<T>* __restrict__ Mat, int d0, int d1,
+                                        const int* pos, int npos, const cpx<T>* __restrict__ v, const cpx<T>* s,
+                                        double alpha, double beta, cpx<T>* y, const int* list, int nlist)
 {
     const Geom& g = c.a.g;
     const int Ns = c.a.Ns;
@@ -1071,17 +1078,17 @@ __device__ inline void apply_multi_mfma(const MultiCtx<T>& c, const cpx<T>* __re
     const int lane = c.t & 63, wave = c.t >> 6;
     const int n = lane & 15, kq = lane >> 4;
     const int b_n = n < nlist ? list[n] : 0;
-    for (int task = wave; task < c.nbg * mt; task += LT / 64) {
+    for (int task = wave; task < npos * mt; task += LT / 64) {
         const int ib = task / mt, tt = task - ib * mt;
-        const int blk = c.g + ib * c.G;
+        const int blk = c.g + (pos ? pos[ib] : ib) * c.G;
         const int rr = 16 * tt + n;
         const int m = rr >> 1, cr = rr & 1;
         typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
 #pragma unroll 1
-        for (int d = 0; d < 9; ++d) {
+        for (int d = d0; d < d1; ++d) {
             const int nbr = nbr_block(g, blk, d);
-            const cpx<T>* Ad = c.a.At + ((long)blk * 9 + d) * Ns * Ns;
-            const cpx<T>* vb = v + b_n * vstride + (long)nbr * Ns;
+            const cpx<T>* Ad = Mat + ((long)blk * 9 + d) * Ns * Ns;
+            const cpx<T>* vb = v + b_n * c.N + (long)nbr * Ns;
             // the operands of kMfmaBatch steps loaded together, then their products
 #pragma unroll 1
             for (int kc0 = 0; kc0 < 2 * Ns; kc0 += 4 * kMfmaBatch) {
@@ -1112,12 +1119,17 @@ __device__ inline void apply_multi_mfma(const MultiCtx<T>& c, const cpx<T>* __re
             }
         }
         if (n < nlist) {
-            T* yb = reinterpret_cast<T*>(y + b_n * ystride + (long)blk * Ns);
+            const long o = b_n * c.N + (long)blk * Ns;
+            T* yb = reinterpret_cast<T*>(y + o);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int ro = 16 * tt + Mfma<T>::row(kq, i);
-                if (ro < 2 * Ns)
-                    yb[ro] = acc[i];
+                if (ro < 2 * Ns) {
+                    double val = beta * (double)acc[i];
+                    if (alpha != 0.0)
+                        val += alpha * (double)reinterpret_cast<const T*>(s + o)[ro];
+                    yb[ro] = (T)val;
+                }
             }
         }
     }
@@ -1246,7 +1258,7 @@ __device__ inline void multi_fin(const double* part, double* fin, int nrhs, int 
     }
 }
 
-template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(LittleMultiArgs<T> a)
+template <typename T, bool EO> __global__ __launch_bounds__(LT) void k_little_gcr_multi(LittleMultiArgs<T> a)
 {
     __shared__ double red[kMaxLittleRhs][2 * RS];
     __shared__ double bcoef[kMaxLittleRhs][NK];
@@ -1256,9 +1268,10 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
     __shared__ int act[kMaxLittleRhs], stop[kMaxLittleRhs], conv[kMaxLittleRhs], kb[kMaxLittleRhs];
     __shared__ int second[kMaxLittleRhs];
     __shared__ int list[kMaxLittleRhs], nlist_s, list2[kMaxLittleRhs], nlist2_s;
-    
+    __shared__ int l_even[EO ? kMaxOwned : 1], l_odd[EO ? kMaxOwned : 1];  // owned positions by colour
+    __shared__ int n_even_s, n_odd_s;
 
-    MultiCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns};
+    MultiCtx<T> c{a, (int)gridDim.x, (int)blockIdx.x, (int)threadIdx.x, 0, 0, (long)a.g.Nb * a.Ns, nullptr};
     const double tol2 = a.tol_dev ? (*a.tol_dev) * (*a.tol_dev) : a.tol2;
     const int nr = a.nrhs;
     const long N = c.N;
@@ -1266,23 +1279,60 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
     if (c.t == 0)
         bar_target = __hip_atomic_load(a.bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     c.nbg = (a.g.Nb - c.g + c.G - 1) / c.G;
-    c.R = c.nbg * a.Ns;
-    double* acoef = a.acoef + (long)c.g * nr * NK * NK * 2;
-    auto AC = [&](int b, int i, int j) -> double* { return acoef + (((long)b * NK + i) * NK + j) * 2; };
-
-    // x = 0, r = w, ||w_b||^2
-    for (long q = c.t; q < (long)c.R * nr; q += LT) {
-        const int b = (int)(q / c.R), e = (int)(q - (long)b * c.R);
-        const long i = c.entry(e) + b * N;
-        a.x[i] = cpx<T>{0, 0};
-        a.r[i] = a.w[i];
+    if (EO && c.t == 0) {
+        int ne = 0, no = 0;
+        for (int i = 0; i < c.nbg; ++i) {
+            if (block_colour(a.g, c.g + i * c.G))
+                l_odd[no++] = i;
+            else
+                l_even[ne++] = i;
+        }
+        n_even_s = ne;
+        n_odd_s = no;
     }
     if (c.t < nr)
         list[c.t] = c.t;
     if (c.t == 0)
         nlist_s = nr;
     __syncthreads();
-    multi_norm2(c, a.w, list, nr, SW);
+    const int n_even = EO ? n_even_s : 0, n_odd = EO ? n_odd_s : 0;
+    if (EO)
+        c.vb = l_even;
+    c.R = (EO ? n_even : c.nbg) * a.Ns;
+    double* acoef = a.acoef + (long)c.g * nr * NK * NK * 2;
+    auto AC = [&](int b, int i, int j) -> double* { return acoef + (((long)b * NK + i) * NK + j) * 2; };
+    // y = A u (plain) or y = u - M_eo M_oe u on even blocks, the odd-block
+    // intermediate in w2 (one more grid barrier), for the listed sources
+    auto op = [&](const cpx<T>* u, cpx<T>* y, const int* lst, int nl) {
+        if (EO) {
+            apply_multi_mfma(c, a.Mt, 1, 9, l_odd, n_odd, u, (const cpx<T>*)nullptr, 0.0, 1.0, a.w2, lst, nl);
+            grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+            apply_multi_mfma(c, a.Mt, 1, 9, l_even, n_even, (const cpx<T>*)a.w2, u, 1.0, -1.0, y, lst, nl);
+        } else {
+            apply_multi_mfma(c, a.At, 0, 9, (const int*)nullptr, c.nbg, u, (const cpx<T>*)nullptr, 0.0, 1.0, y, lst,
+                             nl);
+        }
+    };
+    // the system's right-hand sides: w, or w1_e - M_eo w1_o (w1 = M_0 w) on even blocks
+    const cpx<T>* rhs = a.w;
+    if (EO) {
+        apply_multi_mfma(c, a.Mt, 0, 1, (const int*)nullptr, c.nbg, a.w, (const cpx<T>*)nullptr, 0.0, 1.0, a.w1,
+                         list, nr);
+        grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
+        apply_multi_mfma(c, a.Mt, 1, 9, l_even, n_even, (const cpx<T>*)a.w1, (const cpx<T>*)a.w1, 1.0, -1.0, a.w2,
+                         list, nr);
+        rhs = a.w2;
+    }
+
+    // x = 0, r = rhs, ||rhs_b||^2
+    for (long q = c.t; q < (long)c.R * nr; q += LT) {
+        const int b = (int)(q / c.R), e = (int)(q - (long)b * c.R);
+        const long i = c.entry(e) + b * N;
+        a.x[i] = cpx<T>{0, 0};
+        a.r[i] = rhs[i];
+    }
+    __syncthreads();
+    multi_norm2(c, rhs, list, nr, SW);
     grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
     multi_reduce_real(a.part, nr, c.G, SW, list, nr, wn2);
     if (c.t < nr) {
@@ -1335,7 +1385,7 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
             const int na = nlist_s;
             if (na == 0)
                 break;
-            apply_multi_mfma(c, a.xi + (long)k * nr * N, N, a.chi + (long)k * nr * N, N, list, na);
+            op(a.xi + (long)k * nr * N, a.chi + (long)k * nr * N, list, na);
             multi_pass(c, k, list, na, SA);
             grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);  // S2
             multi_fin(a.part, a.fin, nr, c.G, c.g, SA, 2 * k + 2, list, na);
@@ -1502,12 +1552,12 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
         }
         // recompute r_b = w_b - A x_b for those RHS
         grid_barrier(a.bar_count, a.bar_gen, bar_target, a.stats);
-        apply_multi_mfma(c, a.x, N, a.r, N, list, nx);
+        op(a.x, a.r, list, nx);
         for (long q = c.t; q < (long)c.R * nx; q += LT) {
             const int bi = (int)(q / c.R), e = (int)(q - (long)bi * c.R);
             const int b = list[bi];
             const long i = c.entry(e) + b * N;
-            a.r[i] = cpx<T>{(T)((double)a.w[i].re - (double)a.r[i].re), (T)((double)a.w[i].im - (double)a.r[i].im)};
+            a.r[i] = cpx<T>{(T)((double)rhs[i].re - (double)a.r[i].re), (T)((double)rhs[i].im - (double)a.r[i].im)};
         }
         __syncthreads();
         multi_norm2(c, a.r, list, nx, SR);
@@ -1522,6 +1572,17 @@ template <typename T> __global__ __launch_bounds__(LT) void k_little_gcr_multi(L
         __syncthreads();
         if (nx == 0)
             break;  // no RHS made progress: all stopped
+    }
+    if (EO) {
+        // x_o = w1_o - M_oe x_e for every source: a grid barrier followed the
+        // last update of x_e (the zero start or the update before the residue
+        // recomputation), so the neighbours' entries are complete
+        __syncthreads();
+        if (c.t < nr)
+            list[c.t] = c.t;
+        __syncthreads();
+        apply_multi_mfma(c, a.Mt, 1, 9, l_odd, n_odd, (const cpx<T>*)a.x, (const cpx<T>*)a.w1, 1.0, -1.0, a.x, list,
+                         nr);
     }
     if (c.g == 0 && c.t == 0) {
         int nc = 0;
@@ -1627,8 +1688,10 @@ int little_gcr_resident_limit(bool multi)
         per_cu = n < per_cu ? n : per_cu;
     };
     if (multi) {
-        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<double>), LT);
-        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<float>), LT);
+        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<double, false>), LT);
+        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<float, false>), LT);
+        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<double, true>), LT);
+        occ(reinterpret_cast<const void*>(&k_little_gcr_multi<float, true>), LT);
     } else {
         occ(reinterpret_cast<const void*>(&k_little_gcr<double, true>), LT1);
         occ(reinterpret_cast<const void*>(&k_little_gcr<double, false>), LT1);
@@ -1658,11 +1721,13 @@ void launch_little_gcr(const Geom& g, int Ns, int nkv, int maxiter, double tol, 
 
 template <typename T>
 void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double tol, const double* tol_dev, int nrhs,
-                             const cpx<T>* At,
+                             const cpx<T>* At, const cpx<T>* Mt, cpx<T>* w1, cpx<T>* w2,
                              const cpx<T>* w, cpx<T>* x, cpx<T>* r, cpx<T>* xi, cpx<T>* chi, double* part, double* fin,
                              double* acoef, int* stats, unsigned* bar_count, unsigned long long* bar_gen, int grid,
                              hipStream_t s, bool cooperative)
 {
+    if (Mt && !(w1 && w2 && little_eo_fits(g, grid)))
+        fail(DFL_EINVAL, "even-odd little solve: missing work vectors or too many blocks per workgroup");
     LittleMultiArgs<T> a;
     a.g = g;
     a.Ns = Ns;
@@ -1672,6 +1737,9 @@ void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double
     a.tol2 = tol * tol;
     a.tol_dev = tol_dev;
     a.At = At;
+    a.Mt = Mt;
+    a.w1 = w1;
+    a.w2 = w2;
     a.w = w;
     a.x = x;
     a.r = r;
@@ -1684,13 +1752,17 @@ void launch_little_gcr_multi(const Geom& g, int Ns, int nkv, int maxiter, double
     a.bar_count = bar_count;
     a.bar_gen = bar_gen;
     if (!cooperative) {
-        hipLaunchKernelGGL(k_little_gcr_multi<T>, dim3(grid), dim3(LT), 0, s, a);
+        if (Mt)
+            hipLaunchKernelGGL((k_little_gcr_multi<T, true>), dim3(grid), dim3(LT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_little_gcr_multi<T, false>), dim3(grid), dim3(LT), 0, s, a);
         HIPCHECK(hipGetLastError());
         return;
     }
     void* args[] = {&a};
-    HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_little_gcr_multi<T>),
-                                        dim3(grid), dim3(LT), args, 0, s));
+    const void* fn = Mt ? reinterpret_cast<const void*>(&k_little_gcr_multi<T, true>)
+                        : reinterpret_cast<const void*>(&k_little_gcr_multi<T, false>);
+    HIPCHECK(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(LT), args, 0, s));
 }
 
 size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* acoef)
@@ -1702,7 +1774,7 @@ size_t little_gcr_multi_doubles(int grid_size, int nrhs, size_t* fin, size_t* ac
 
 #define INST_MULTI(T)                                                                                               \
     template void launch_little_gcr_multi<T>(const Geom&, int, int, int, double, const double*, int, const cpx<T>*,  \
-                                             const cpx<T>*,                                                         \
+                                             const cpx<T>*, cpx<T>*, cpx<T>*, const cpx<T>*,                        \
                                              cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*, double*, double*, double*, int*,    \
                                              unsigned*, unsigned long long*, int, hipStream_t, bool);
 INST_MULTI(double)

@@ -465,11 +465,13 @@ def test_little_apply_multi_rhs(c1):
     S.close()
 
 
-def test_projectors_multi_rhs(c1):
+@pytest.mark.parametrize("eo", [1, 0])
+def test_projectors_multi_rhs(c1, eo):
     # batched restriction, little solve (one cooperative launch for all
-    # sources) and prolongation against the oracle field by field
-    say("projectors multi-rhs c1")
-    S = _c1_solver(c1, nrhs_max=3)
+    # sources; on the even-odd reduced systems or on A itself) and
+    # prolongation against the oracle field by field
+    say(f"projectors multi-rhs c1 little_eo={eo}")
+    S = _c1_solver(c1, nrhs_max=3, little_eo=eo)
     dims, b = c1["dims"], (4, 4, 4, 4)
     dfl = oracle.Deflation(c1["U"], c1["Phi"], c1["A"], c1["m0"], dims, b)
     y = latgen.random_field(dims, 62, n=3)
