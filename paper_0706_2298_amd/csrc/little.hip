@@ -1001,7 +1001,12 @@ template <typename T, bool EO> __global__ __launch_bounds__(LT1) void k_little_g
 // Reductions over the workgroups are two-level: partial sums, a barrier,
 // workgroup g sums the slots t = g mod G into fin, a barrier, everyone reads
 // fin. A RHS leaves the cycle when it converges or its new direction falls
-// in the span; the cycle ends when no RHS is left in it.
+// in the span; the cycle ends when no RHS is left in it. With EO the systems
+// are the even-odd reduced ones of appendix A.2, as in the single-source
+// solver: the Krylov vectors live on the even blocks, w1 = M_0 w holds each
+// source's block-diagonally scaled right-hand side, w2 the reduced one on the
+// even blocks and the operator's intermediate on the odd ones, and the odd
+// part of each solution follows from the even part at the end.
 
 constexpr int RS = 2 * NK + 2;  // slots of one pass per RHS
 
