@@ -1000,13 +1000,16 @@ void build_subspace(dfl_ctx* c, const c64* src, double mA)
     // Chunk of basis fields per launch: bounded by the Krylov buffer (the
     // stencil output) and by t1 (the split partial sums, Nb*Ns*chunk entries)
     const long part_cap = F * c->p.nrhs_max;
-    const int chunk = (int)std::max(1L, std::min({(long)Ns, (long)little_columns_max(Ns),
-                                                  (long)c->p.nkv * c->p.nrhs_max, (long)(128 - Ns),
+    const long kcap = (long)c->p.nkv * c->p.nrhs_max;  // fields of each Krylov buffer
+    const int chunk = (int)std::max(1L, std::min({(long)Ns, (long)little_columns_max(Ns), kcap, (long)(128 - Ns),
                                                   part_cap / ((long)c->g.Nb * Ns)}));
+    // All Ns columns of a direction in one matrix-core launch when the two
+    // Krylov buffers hold them (each basis block then read once per direction)
+    const bool all = little_columns_all_ok(Ns, part_cap, c->g.Nb) && Ns <= 2 * kcap;
     // The faces along x2 and x3 are scattered in the native in-block order
     // (x3 fastest); their hops and block products read a copy of the basis in
     // the transposed order, where those faces are whole tiles or long runs.
-    const bool tl = little_columns_transposable(Ns, chunk);
+    const bool tl = all || little_columns_transposable(Ns, chunk);
     if (tl)
         c->PhiT = grow<c64>(c, c->PhiT, c->PhiT_n, (size_t)F * Ns);
     // block Gram-Schmidt (eq. (4.2)); the 256-site block kernel also writes the
@@ -1015,7 +1018,25 @@ void build_subspace(dfl_ctx* c, const c64* src, double mA)
                                           tl ? c->PhiT : nullptr, c->Phi32);
     if (tl && !copies)
         launch_to_transposed(c->g, c->Phi, c->PhiT, Ns, c->stream);
-    for (int l0 = 0; l0 < Ns; l0 += chunk) {
+    for (int d = 0; all && d < 9; ++d) {
+        const int mu = d == 0 ? -1 : (d - 1) / 2;
+        const bool t = mu >= 2;
+        const c64* basis = t ? c->PhiT : c->Phi;
+        const int n1 = (int)std::min<long>(Ns, kcap);
+        for (int h = 0; h < 2; ++h) {
+            const int l0 = h == 0 ? 0 : n1, nc = h == 0 ? n1 : Ns - n1;
+            c64* y = h == 0 ? c->xi : c->chi;
+            if (nc == 0)
+                continue;
+            if (d == 0)
+                launch_dirac64(c->g, links64(c), basis + (long)l0 * F, y, nc, mA, 1, 0, 0, c->stream, c->Cl64);
+            else
+                launch_dirac64_face(c->g, links64(c), basis + (long)l0 * F, y, nc, mu, (d & 1) ? +1 : -1, c->stream,
+                                    t);
+        }
+        launch_little_columns64_all(c->g, basis, Ns, c->xi, n1, c->chi, d, c->A64, c->t1, part_cap, c->stream, t);
+    }
+    for (int l0 = 0; !all && l0 < Ns; l0 += chunk) {
         const int nc = std::min(chunk, Ns - l0);
         for (int d = 0; d < 9; ++d) {
             const int mu = d == 0 ? -1 : (d - 1) / 2;

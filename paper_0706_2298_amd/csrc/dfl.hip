@@ -775,6 +775,132 @@ __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __
         }
 }
 
+// Matrix-core form for all Ns columns of a direction at once (Ns <= 32), so
+// that the block of every basis field is read once per direction. The
+// complex products C[k][j] = sum_e conj(Phi_k(e)) Y_j(e) are the real
+// product P Q over two real K indices per entry (the parts of Y_j(e) it
+// multiplies): P[2k][.] = (Re Phi_k, Im Phi_k), P[2k+1][.] = (-Im Phi_k,
+// Re Phi_k), Q[.][j] = (Re Y_j, Im Y_j). It runs as 16x16x4 FP64 MFMA tiles,
+// RT = ceil(2Ns / 16) row tiles by CT = ceil(Ns / 16) column tiles; a pair of
+// MFMA steps covers four entries, lane (n, q) supplying Phi_{k(n)}(e0 + q) and
+// Y_{j(n)}(e0 + q), their real parts in the first step and their imaginary
+// parts in the second. Entries are staged through LDS 64 at a time (rows
+// padded to 65 entries); each of the four wavefronts takes 16 of them, and
+// the wavefronts' tiles are summed through LDS at the end. Columns
+// j < n1 are read from Y1, the others from Y2 (two column buffers). Same
+// partial-sum layout as above with nc = Ns.
+using f64x4 = __attribute__((ext_vector_type(4))) double;
+constexpr int kMfCE = 64;       // entries per stage
+constexpr int kMfRow = kMfCE + 1;  // staged row stride (entries)
+
+template <int RT, int CT, bool TL>
+__global__ __launch_bounds__(256) void k_little_columns_mfma(Geom g, const c64* __restrict__ Phi, int Ns,
+                                                             const c64* __restrict__ Y1, int n1,
+                                                             const c64* __restrict__ Y2, int nsplit, int fmu, int fy,
+                                                             int nface, c64* __restrict__ part)
+{
+    constexpr int kLd = (16 * RT + 3) / 4;  // staged rows per thread: 2 Ns <= 16 RT rows over 4 wavefronts
+    extern __shared__ c64 st[];             // [2 Ns][kMfRow], then the wavefronts' tiles
+    const int blk = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+    const long F = 12 * g.V;
+    const int ne = 12 * nface;
+    const int per = ((ne + nsplit - 1) / nsplit + kMfCE - 1) / kMfCE * kMfCE;
+    const int e_lo = split * per;
+    const int e_hi = e_lo + per < ne ? e_lo + per : ne;
+    const int nr = 2 * Ns;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int n = lane & 15, q = lane >> 4;
+    f64x4 acc[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+            acc[t][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+    c64 v[kLd];
+    auto load = [&](int e0) {
+        const long i = e0 + lane >= e_hi ? -1
+                       : (TL ? face_elem_t(g, blk, e0 + lane, fmu, fy, nface)
+                             : face_elem(g, blk, e0 + lane, fmu, fy, nface));
+#pragma unroll
+        for (int m = 0; m < kLd; ++m) {
+            const int r = wid + 4 * m;
+            v[m] = c64{0.0, 0.0};
+            if (i >= 0 && r < nr) {
+                const int j = r - Ns;
+                v[m] = r < Ns ? Phi[(long)r * F + i] : (j < n1 ? Y1[(long)j * F + i] : Y2[(long)(j - n1) * F + i]);
+            }
+        }
+    };
+    if (e_lo < e_hi)
+        load(e_lo);
+    for (int e0 = e_lo; e0 < e_hi; e0 += kMfCE) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kLd; ++m) {
+            const int r = wid + 4 * m;
+            if (r < nr)
+                st[r * kMfRow + lane] = v[m];
+        }
+        __syncthreads();
+        if (e0 + kMfCE < e_hi)
+            load(e0 + kMfCE);
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const int e = 16 * wid + 4 * g4 + q;
+            c64 a[RT], b[CT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int k = 8 * t + (n >> 1);
+                a[t] = k < Ns ? st[k * kMfRow + e] : c64{0.0, 0.0};
+            }
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int j = 16 * c + n;
+                b[c] = j < Ns ? st[(Ns + j) * kMfRow + e] : c64{0.0, 0.0};
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                // rows 2k (real part of the product) and 2k + 1 (imaginary part)
+                const double p1 = (n & 1) ? -a[t].im : a[t].re;
+                const double p2 = (n & 1) ? a[t].re : a[t].im;
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(p1, b[c].re, acc[t][c], 0, 0, 0);
+                    acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(p2, b[c].im, acc[t][c], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // the four wavefronts' tiles, summed in a fixed order: tile element i of
+    // lane (n, q) is row 16 t + 4 i + q, column 16 c + n
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(st);  // [wave][t][c][i][lane]
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                red[(((wid * RT + t) * CT + c) * 4 + i) * 64 + lane] = acc[t][c][i];
+    __syncthreads();
+    const int np = Ns * Ns;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const int k = p / Ns, j = p - k * Ns;
+        double z[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = 2 * k + h;
+            const int t = row >> 4, i = (row & 15) >> 2, qq = row & 3;
+            const int c = j >> 4, ln = qq * 16 + (j & 15);
+            double sum = 0.0;
+            for (int w = 0; w < 4; ++w)
+                sum += red[(((w * RT + t) * CT + c) * 4 + i) * 64 + ln];
+            z[h] = sum;
+        }
+        part[((long)split * g.Nb + blk) * np + p] = c64{z[0], z[1]};
+    }
+}
+
 // A[blk][d][k][l0 + j] = sum over splits of part (fixed order)
 __global__ __launch_bounds__(256) void k_little_columns_sum(Geom g, const c64* __restrict__ part, int Ns, int nc,
                                                             int nsplit, int l0, int d, c64* __restrict__ A)
@@ -1254,6 +1380,59 @@ void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y
     const long n = (long)g.Nb * Ns * nc;
     hipLaunchKernelGGL(k_little_columns_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, part, Ns, nc,
                        nsplit, l0, d, A);
+}
+
+bool little_columns_all_ok(int Ns, long part_cap, long Nb) { return Ns >= 1 && Ns <= 32 && part_cap >= Nb * Ns * Ns; }
+
+// dynamic LDS of k_little_columns_mfma: the staged rows or the wavefronts' tiles
+size_t columns_mfma_lds(int Ns, int RT, int CT)
+{
+    return std::max(sizeof(c64) * 2 * Ns * kMfRow, sizeof(double) * 4 * RT * CT * 4 * 64);
+}
+
+template <int RT, int CT, bool TL>
+void launch_columns_mfma(const Geom& g, const c64* Phi, int Ns, const c64* Y1, int n1, const c64* Y2, int nsplit,
+                         int fmu, int fy, int nface, c64* part, hipStream_t s)
+{
+    static std::once_flag attr;  // the limit for the largest Ns of this tile count
+    set_max_lds_once(attr, reinterpret_cast<const void*>(&k_little_columns_mfma<RT, CT, TL>),
+                     (int)columns_mfma_lds(8 * RT, RT, CT));
+    hipLaunchKernelGGL((k_little_columns_mfma<RT, CT, TL>), dim3(g.Nb * nsplit), dim3(256),
+                       columns_mfma_lds(Ns, RT, CT), s, g, Phi, Ns, Y1, n1, Y2, nsplit, fmu, fy, nface, part);
+}
+
+void launch_little_columns64_all(const Geom& g, const c64* Phi, int Ns, const c64* Y1, int n1, const c64* Y2, int d,
+                                 c64* A, c64* part, long part_cap, hipStream_t s, bool transposed)
+{
+    if (!little_columns_all_ok(Ns, part_cap, g.Nb) || n1 < 0 || n1 > Ns || (n1 < Ns && !Y2))
+        fail(DFL_EINVAL, "little-operator assembly: all-column products need Ns <= 32 and Nb Ns^2 scratch entries");
+    if (transposed && d == 0)
+        fail(DFL_EINVAL, "little-operator assembly: transposed order only for face columns");
+    const int fmu = d == 0 ? -1 : (d - 1) / 2;
+    const int fy = d == 0 ? 0 : ((d & 1) ? g.b[fmu] - 1 : 0);
+    const int nface = fmu < 0 ? g.Vb : g.Vb / g.b[fmu];
+    const int ne = 12 * nface;
+    int nsplit = ne / (8 * kCE);
+    if (nsplit > 8)
+        nsplit = 8;
+    while (nsplit > 1 && (long)nsplit * g.Nb * Ns * Ns > part_cap)
+        --nsplit;
+    if (nsplit < 1)
+        nsplit = 1;
+    const int RT = (Ns + 7) / 8;  // CT = (Ns + 15) / 16 follows from RT
+#define COLS_MFMA(R, C)                                                                                          \
+    (transposed ? launch_columns_mfma<R, C, true>(g, Phi, Ns, Y1, n1, Y2, nsplit, fmu, fy, nface, part, s)      \
+                : launch_columns_mfma<R, C, false>(g, Phi, Ns, Y1, n1, Y2, nsplit, fmu, fy, nface, part, s))
+    switch (RT) {
+    case 1: COLS_MFMA(1, 1); break;
+    case 2: COLS_MFMA(2, 1); break;
+    case 3: COLS_MFMA(3, 2); break;
+    default: COLS_MFMA(4, 2); break;
+    }
+#undef COLS_MFMA
+    const long n = (long)g.Nb * Ns * Ns;
+    hipLaunchKernelGGL(k_little_columns_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, part, Ns, Ns,
+                       nsplit, 0, d, A);
 }
 
 template <typename T>

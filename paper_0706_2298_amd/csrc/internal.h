@@ -332,6 +332,12 @@ int little_columns_max(int Ns);
 bool little_columns_transposable(int Ns, int nc);
 void launch_little_columns64(const Geom& g, const c64* Phi, int Ns, const c64* Y, int nc, int l0, int d, c64* A,
                              c64* part, long part_cap, hipStream_t s, bool transposed = false);
+// All Ns columns of direction d in one launch on the matrix cores (Ns <= 32,
+// part_cap >= Nb Ns^2): columns j < n1 of Y1, the others of Y2 (Ns - n1
+// fields); transposed as for launch_little_columns64 (face columns only).
+bool little_columns_all_ok(int Ns, long part_cap, long Nb);
+void launch_little_columns64_all(const Geom& g, const c64* Phi, int Ns, const c64* Y1, int n1, const c64* Y2, int d,
+                                 c64* A, c64* part, long part_cap, hipStream_t s, bool transposed);
 // w_b = A v_b (9-point block stencil) for nrhs little vectors
 template <typename T>
 void launch_little_apply(const Geom& g, const cpx<T>* A, int Ns, const cpx<T>* v, cpx<T>* w, int nrhs, hipStream_t s);

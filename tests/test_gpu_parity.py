@@ -677,14 +677,18 @@ def test_block_gram_schmidt_block_sizes(dims, b):
     S.close()
 
 
-@pytest.mark.parametrize("Ns,nkv", [(28, 8), (24, 16), (24, 8), (20, 16), (12, 5)])
+@pytest.mark.parametrize("Ns,nkv", [(28, 8), (24, 16), (24, 8), (20, 16), (12, 5), (8, 16), (16, 8), (28, 16),
+                                    (32, 16)])
 def test_little_operator_column_kernels(Ns, nkv):
-    # eq. (A.1) assembled over chunks of min(Ns, nkv) basis fields: chunks of
-    # at most 16 run the register-tiled block products, 5 x 4 tiles for
-    # Ns <= 20 (chunks 16 + 4 and 5 + 5 + 2 here) and 6 x 4 for Ns <= 24
-    # (16 + 8 and 8 + 8 + 8), Ns = 28 the one-pair-per-thread kernel; without
-    # inverse-iteration steps the basis is the block Gram-Schmidt of the start
-    # fields, so the oracle needs no solver
+    # eq. (A.1): when the two Krylov buffers (nkv fields each) hold all Ns
+    # columns, one matrix-core launch per direction takes them all (row x
+    # column tiles 1 x 1 for Ns = 8, 2 x 1 for 16, 3 x 2 for 20 and 24, 4 x 2
+    # for 28 and 32; the columns split over the two buffers 16 + 8, 16 + 4,
+    # 8 + 8, 16 + 12, 16 + 16). Otherwise chunks of min(Ns, nkv) basis fields:
+    # 6 x 4 register tiles for Ns = 24 (8 + 8 + 8), 5 x 4 for Ns = 12
+    # (5 + 5 + 2), the one-pair-per-thread kernel for Ns = 28 in chunks of 8.
+    # Without inverse-iteration steps the basis is the block Gram-Schmidt of
+    # the start fields, so the oracle needs no solver
     say(f"little operator Ns={Ns} chunk={min(Ns, nkv)}")
     dims, b = (8, 8, 8, 8), (4, 4, 4, 4)
     U = latgen.make_links(dims, 0.4, 81)
