@@ -321,18 +321,24 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
 // both are held in registers and projected against each earlier basis field
 // in one pass (one load of that field and one reduction of both products
 // for two projections), then l + 1 against the new l. Each field sees the
-// same sequence of projections as in k_block_gs, so the results are equal.
+// same sequence of projections as in k_block_gs; the product of l + 1 with
+// the new l is summed with the norm of l, before l is scaled (the results
+// agree up to that rounding).
 template <int E, int NT>
 __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
                                                    int* __restrict__ flag, c64* __restrict__ R, c64* __restrict__ FT,
                                                    c32* __restrict__ F32)
 {
-    __shared__ double2 sh[2][NT / 64];
+    __shared__ double2 sh[2][2][NT / 64];
     const int blk = blockIdx.x;
     const long fs = 12 * g.V;
     const int ne = 12 * g.Vb;
     const bool b4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
-    // sums over the workgroup of two complex values at once (as two block_sum2)
+    // sums over the workgroup of two complex values at once (as two
+    // block_sum2). Consecutive sums use alternate LDS slots, so one barrier
+    // each suffices: a slot is written again only after the barrier of the
+    // next sum, which every thread passes after reading it.
+    int par = 0;
     auto sum2x2 = [&](double2& a, double2& b) {
         a.x = wave_sum(a.x);
         a.y = wave_sum(a.y);
@@ -340,18 +346,18 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
         b.y = wave_sum(b.y);
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
         if (lane == 0) {
-            sh[0][wid] = a;
-            sh[1][wid] = b;
+            sh[par][0][wid] = a;
+            sh[par][1][wid] = b;
         }
         __syncthreads();
         double2 ta = make_double2(0.0, 0.0), tb = make_double2(0.0, 0.0);
         for (int q = 0; q < nw; ++q) {
-            ta.x += sh[0][q].x;
-            ta.y += sh[0][q].y;
-            tb.x += sh[1][q].x;
-            tb.y += sh[1][q].y;
+            ta.x += sh[par][0][q].x;
+            ta.y += sh[par][0][q].y;
+            tb.x += sh[par][1][q].x;
+            tb.y += sh[par][1][q].y;
         }
-        __syncthreads();
+        par ^= 1;
         a = ta;
         b = tb;
     };
@@ -363,8 +369,9 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
             w[j] = e < ne ? fk[block_elem(g, blk, e)] : c64{0.0, 0.0};
         }
     };
-    // normalise v (field l, input norm n0), store it, record the diagonal of R
-    auto finish = [&](int l, c64* v, double n0, double nv2) {
+    // normalise v (field l, input norm n0), store it, record the diagonal of
+    // R; returns the factor applied
+    auto finish = [&](int l, c64* v, double n0, double nv2) -> double {
         double nv = sqrt(nv2);
         n0 = sqrt(n0);
         if (R && threadIdx.x == 0) {
@@ -407,6 +414,7 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
                 }
             }
         }
+        return inv;
     };
     for (int l = 0; l < Ns; l += 2) {
         const bool two = l + 1 < Ns;
@@ -456,25 +464,24 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
                 vb[j] -= cb * u[j];
             }
         }
-        // field l is complete: its norm; field l + 1 continues against it
-        double2 nva = make_double2(0.0, 0.0), dummy = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < E; ++j)
-            nva.x += va[j].re * va[j].re + va[j].im * va[j].im;
-        sum2x2(nva, dummy);
-        finish(l, va, na.x, nva.x);
-        if (!two)
-            break;
-        double2 d = make_double2(0.0, 0.0), nvb = make_double2(0.0, 0.0);
+        // field l is complete: its norm and, in the same sum, its product
+        // with field l + 1, which then continues against the normalised l:
+        // (v_l / |v_l|, v_{l+1}) = (v_l, v_{l+1}) / |v_l|
+        double2 nva = make_double2(0.0, 0.0), d = make_double2(0.0, 0.0);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
+            nva.x += va[j].re * va[j].re + va[j].im * va[j].im;
             d.x += va[j].re * vb[j].re + va[j].im * vb[j].im;
             d.y += va[j].re * vb[j].im - va[j].im * vb[j].re;
         }
-        sum2x2(d, dummy);
-        const c64 c{d.x, d.y};
+        sum2x2(nva, d);
+        const double inv_a = finish(l, va, na.x, nva.x);
+        if (!two)
+            break;
+        const c64 c{d.x * inv_a, d.y * inv_a};
         if (R && threadIdx.x == 0)
             R[((long)blk * Ns + l) * Ns + l + 1] = c;
+        double2 nvb = make_double2(0.0, 0.0), dummy = make_double2(0.0, 0.0);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             vb[j] -= c * va[j];
