@@ -357,9 +357,10 @@ void dirac64_sub(dfl_ctx* c, const c64* s, const c64* in, c64* out, double m0, i
 // scale applied while rho is rounded to FP32 (M_sap is linear). FP32 block
 // solves leave the result in FP32 in s32b as well; rho_from_s32b: rho is that
 // FP32 result of the previous call (rho is then not read, rho_nrm2 required),
-// and psi may be null (no FP64 result written).
+// and psi may be null (no FP64 result written). finite_flag (FP32 block solves
+// with rho_nrm2 only): bit 1 set there if an entry of rho is not finite.
 void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, const double* rho_nrm2 = nullptr,
-               bool rho_from_s32b = false)
+               bool rho_from_s32b = false, int* finite_flag = nullptr)
 {
     const long n = c->field_elems * nrhs;
     const int ncy = c->p.ncy;
@@ -380,7 +381,7 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, co
     if (rho_from_s32b)
         launch_f32_scaled(c->s32b, c->s32a, c->field_elems, nrhs, rho_nrm2, 2, c->stream);
     else if (rho_nrm2)
-        launch_f64_to_f32_scaled(rho, c->s32a, c->field_elems, nrhs, rho_nrm2, 2, c->stream);
+        launch_f64_to_f32_scaled(rho, c->s32a, c->field_elems, nrhs, rho_nrm2, 2, c->stream, finite_flag);
     else
         launch_f64_to_f32(rho, c->s32a, n, c->stream);
     for (int cy = 0; cy < ncy; ++cy)
@@ -929,14 +930,17 @@ void inverse_iterate(dfl_ctx* c, const c64* src, c64* dst, int n, int steps, boo
         launch_norm2_b<double>(dst, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
         launch_scale_invsqrt_b<double>(dst, F, n, F, c->dnorm, 2, nullptr, c->stream);
     };
-    launch_finite_check<double>(src, F * n, c->dflag, c->stream);
+    const bool fp32 = c->p.sap_prec != DFL_F64 && steps > 0;
+    // (the FP32 path checks src while its first step rounds it to FP32)
+    if (!fp32)
+        launch_finite_check<double>(src, F * n, c->dflag, c->stream);
     // the sweeps of the inverse iteration are timed as setup work
     struct SetupSweeps {
         dfl_ctx* c;
         explicit SetupSweeps(dfl_ctx* cc) : c(cc) { c->sap_prof_cls = DFL_PROF_SETUP_SAP; }
         ~SetupSweeps() { c->sap_prof_cls = DFL_PROF_SAP; }
     } setup_sweeps(c);
-    if (c->p.sap_prec == DFL_F64 || steps == 0) {
+    if (!fp32) {
         if (src != dst)
             HIPCHECK(hipMemcpyAsync(dst, src, sizeof(c64) * F * n, hipMemcpyDeviceToDevice, c->stream));
         for (int step = 0; step < steps; ++step) {
@@ -960,7 +964,8 @@ void inverse_iterate(dfl_ctx* c, const c64* src, c64* dst, int n, int steps, boo
             launch_norm2_b<double>(src, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
         else
             launch_norm2_b<float>(c->s32b, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
-        sap_apply(c, src, last ? dst : nullptr, c->p.m0_setup, n, c->dnorm, step > 0);  // through s32a/s32b
+        sap_apply(c, src, last ? dst : nullptr, c->p.m0_setup, n, c->dnorm, step > 0,
+                  step == 0 ? c->dflag : nullptr);  // through s32a/s32b
     }
     if (normalise_out)
         normalise();

@@ -201,7 +201,9 @@ void launch_unpack_field32(const Geom& g, const c32* nat, c64* canon, int nrhs, 
 void launch_pack_gauge(const Geom& g, const c64* canon, c64* U64, c32* U32, uint32_t* Ubf, int* flag, hipStream_t s);
 void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s);
 // nb fields of n entries: out_b = in_b / sqrt(nrm2[b * cstride]) in FP32
-void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s);
+// (finite_flag non-null: bit 1 set there if an input entry is not finite)
+void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s,
+                              int* finite_flag = nullptr);
 // the same from FP32 fields (out must not alias in)
 void launch_f32_scaled(const c32* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s);
 void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s);

@@ -117,18 +117,25 @@ __global__ __launch_bounds__(256) void k_f64_to_f32(const c64* __restrict__ in, 
 
 // out_b = in_b / sqrt(nrm2[b * cstride]) rounded to FP32 (the product in FP64, so
 // an FP32 input gives the same bits as its exact FP64 copy), field b of n
-// entries at b * n; blockIdx.y = field
+// entries at b * n; blockIdx.y = field. With flag non-null, bit 1 of *flag is
+// set if an input entry is not finite.
 template <typename TI>
 __global__ __launch_bounds__(256) void k_to_f32_scaled(const cpx<TI>* __restrict__ in, c32* __restrict__ out, long n,
-                                                       const double* __restrict__ nrm2, int cstride)
+                                                       const double* __restrict__ nrm2, int cstride, int* flag)
 {
     const int b = blockIdx.y;
     const double q = nrm2[(long)b * cstride];
     const double f = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
     in += (long)b * n;
     out += (long)b * n;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        out[i] = c32{(float)((double)in[i].re * f), (float)((double)in[i].im * f)};
+    bool bad = false;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const cpx<TI> z = in[i];
+        bad |= !isfinite((double)z.re) || !isfinite((double)z.im);
+        out[i] = c32{(float)((double)z.re * f), (float)((double)z.im * f)};
+    }
+    if (flag && bad)
+        atomicOr(flag, 1);
 }
 
 __global__ __launch_bounds__(256) void k_f32_to_f64(const c32* __restrict__ in, c64* __restrict__ out, long n)
@@ -167,12 +174,13 @@ void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s)
     if (n > 0)
         hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
 }
-void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s)
+void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s,
+                              int* finite_flag)
 {
     if (n > 0 && nb > 0) {
         const long blocks = std::min<long>((n + 255) / 256, 4096);
         hipLaunchKernelGGL(k_to_f32_scaled<double>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
-                           nrm2, cstride);
+                           nrm2, cstride, finite_flag);
     }
 }
 void launch_f32_scaled(const c32* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s)
@@ -180,7 +188,7 @@ void launch_f32_scaled(const c32* in, c32* out, long n, int nb, const double* nr
     if (n > 0 && nb > 0) {
         const long blocks = std::min<long>((n + 255) / 256, 4096);
         hipLaunchKernelGGL(k_to_f32_scaled<float>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
-                           nrm2, cstride);
+                           nrm2, cstride, (int*)nullptr);
     }
 }
 void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s)

@@ -341,6 +341,23 @@ def test_solve_mixed_precision(c1):
     S.close()
 
 
+@pytest.mark.parametrize("sap_prec", [F64, F32])
+def test_setup_non_finite_start_fields(c1, sap_prec):
+    # a NaN in the start fields is reported as non-finite input (FP32 Schwarz
+    # sweeps: found while the first inverse-iteration step rounds the fields)
+    say(f"setup non-finite start fields sap_prec={sap_prec}")
+    S = Solver(c1["dims"], Ns=8, n_inviter=2, m0=c1["m0"], m0_setup=c1["m0"], sap_prec=sap_prec,
+               link_prec=sap_prec)
+    S.set_gauge(c1["U"])
+    bad = S.pack(c1["init"])
+    bad.view(-1)[bad.numel() // 2 + 17] = complex(float("nan"), 0.0)
+    with pytest.raises(DflError) as e:
+        S.setup(bad)
+    assert e.value.code == -5
+    S.setup(S.pack(c1["init"]))  # the context stays usable
+    S.close()
+
+
 def test_edge_cases(c1):
     say("edge cases")
     torch = pytest.importorskip("torch")
