@@ -355,12 +355,15 @@ void dirac64_sub(dfl_ctx* c, const c64* s, const c64* in, c64* out, double m0, i
 // One launch per colour sweep covers all nrhs fields. rho_nrm2 (FP32 block
 // solves only, may be null): rho_b enters divided by sqrt(rho_nrm2[2 b]), the
 // scale applied while rho is rounded to FP32 (M_sap is linear). FP32 block
-// solves leave the result in FP32 in s32b as well; rho_from_s32b: rho is that
-// FP32 result of the previous call (rho is then not read, rho_nrm2 required),
-// and psi may be null (no FP64 result written). finite_flag (FP32 block solves
-// with rho_nrm2 only): bit 1 set there if an entry of rho is not finite.
-void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, const double* rho_nrm2 = nullptr,
-               bool rho_from_s32b = false, int* finite_flag = nullptr)
+// solves leave the result in FP32 as well, in s32b or s32a: the pointer
+// returned (null for FP64 block solves). rho32 (FP32 block solves, rho_nrm2
+// required): rho is the FP32 result of an earlier call, s32a or s32b, which
+// the sweeps read directly, scaled as they read it, writing into the other
+// of the two (rho is then not read, and psi may be null: no FP64 result
+// written). finite_flag (FP32 block solves with rho_nrm2 only): bit 1 set
+// there if an entry of rho is not finite.
+c32* sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, const double* rho_nrm2 = nullptr,
+               const c32* rho32 = nullptr, int* finite_flag = nullptr)
 {
     const long n = c->field_elems * nrhs;
     const int ncy = c->p.ncy;
@@ -374,13 +377,20 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, co
                 launch_sap_colour64(c->g, c->sg, links64(c), rho, psi, m0, c->p.nmr, col, nrhs, init_of(cy, col),
                                     c->stream, c->Cl64);
             }
-        return;
+        return nullptr;
     }
     // FP32 block solves on FP32 copies; the last cycle's sweeps also write
     // their blocks' result to psi in FP64 (every block has one of the colours)
-    if (rho_from_s32b)
-        launch_f32_scaled(c->s32b, c->s32a, c->field_elems, nrhs, rho_nrm2, 2, c->stream);
-    else if (rho_nrm2)
+    const c32* in32 = c->s32a;
+    c32* out32 = c->s32b;
+    const double* scale_on_read = nullptr;
+    if (rho32) {
+        if (!rho_nrm2 || (rho32 != c->s32a && rho32 != c->s32b))
+            fail(DFL_EINVAL, "Schwarz application: an FP32 input must be a staged result with its norms");
+        in32 = rho32;
+        out32 = rho32 == c->s32b ? c->s32a : c->s32b;
+        scale_on_read = rho_nrm2;
+    } else if (rho_nrm2)
         launch_f64_to_f32_scaled(rho, c->s32a, c->field_elems, nrhs, rho_nrm2, 2, c->stream, finite_flag);
     else
         launch_f64_to_f32(rho, c->s32a, n, c->stream);
@@ -389,12 +399,13 @@ void sap_apply(dfl_ctx* c, const c64* rho, c64* psi, double m0, int nrhs = 1, co
             ProfScope ps(c, c->sap_prof_cls);
             c64* out64 = cy == ncy - 1 ? psi : nullptr;
             if (c->p.link_prec == DFL_BF16)
-                launch_sap_colour_bf16(c->g, c->sg, linksbf(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
-                                       init_of(cy, col), out64, c->stream, c->Cl32);
+                launch_sap_colour_bf16(c->g, c->sg, linksbf(c), in32, out32, (float)m0, c->p.nmr, col, nrhs,
+                                       init_of(cy, col), out64, c->stream, c->Cl32, scale_on_read);
             else
-                launch_sap_colour32(c->g, c->sg, links32(c), c->s32a, c->s32b, (float)m0, c->p.nmr, col, nrhs,
-                                    init_of(cy, col), out64, c->stream, c->Cl32);
+                launch_sap_colour32(c->g, c->sg, links32(c), in32, out32, (float)m0, c->p.nmr, col, nrhs,
+                                    init_of(cy, col), out64, c->stream, c->Cl32, scale_on_read);
         }
+    return out32;
 }
 
 // ------------------------------------------------------------------ GCR
@@ -953,19 +964,20 @@ void inverse_iterate(dfl_ctx* c, const c64* src, c64* dst, int n, int steps, boo
         return;
     }
     // FP32 block solves: each normalisation before a step is the scale of the
-    // step's rounding to FP32 (M_sap is linear, so the step maps the
-    // normalised field). The first step reads src; the later ones read the
-    // previous step's FP32 result (its FP64 copy would hold the same values,
-    // so the norms and the scaled roundings are the same bits), and only the
-    // last step writes dst in FP64; a final normalisation rewrites the fields
+    // step's input (M_sap is linear, so the step maps the normalised field).
+    // The first step rounds src to FP32 with that scale; the later ones read
+    // the previous step's FP32 result in place, scaling it as the sweeps read
+    // it, and write into the other FP32 buffer. Only the last step writes dst
+    // in FP64; a final normalisation rewrites the fields
+    const c32* cur = nullptr;
     for (int step = 0; step < steps; ++step) {
         const bool last = step == steps - 1;
         if (step == 0)
             launch_norm2_b<double>(src, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
         else
-            launch_norm2_b<float>(c->s32b, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
-        sap_apply(c, src, last ? dst : nullptr, c->p.m0_setup, n, c->dnorm, step > 0,
-                  step == 0 ? c->dflag : nullptr);  // through s32a/s32b
+            launch_norm2_b<float>(cur, F, n, F, c->red, c->dnorm, 2, nullptr, c->stream);
+        cur = sap_apply(c, src, last ? dst : nullptr, c->p.m0_setup, n, c->dnorm, cur,
+                        step == 0 ? c->dflag : nullptr);
     }
     if (normalise_out)
         normalise();

@@ -204,8 +204,6 @@ void launch_f64_to_f32(const c64* in, c32* out, long n, hipStream_t s);
 // (finite_flag non-null: bit 1 set there if an input entry is not finite)
 void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s,
                               int* finite_flag = nullptr);
-// the same from FP32 fields (out must not alias in)
-void launch_f32_scaled(const c32* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s);
 void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s);
 
 // ----------------------------------------------------------------- dirac.hip
@@ -241,12 +239,13 @@ void launch_clover_field(const Geom& g, Links64 U, double csw, c64* C64, c32* C3
 // clov (may be null): the clover term in the sweep's precision
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi,
                          double m0, int nmr, int colour, int nrhs, int init, hipStream_t s, const c64* clov);
+// rho_nrm2 (may be null): field b of rho enters divided by sqrt(rho_nrm2[2 b])
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi,
                          float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s,
-                         const c32* clov);
+                         const c32* clov, const double* rho_nrm2 = nullptr);
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi,
                             float m0, int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s,
-                            const c32* clov);
+                            const c32* clov, const double* rho_nrm2 = nullptr);
 
 // ------------------------------------------------------------------ blas.hip
 template <typename T> void launch_zero(cpx<T>* x, long n, hipStream_t s);

@@ -115,12 +115,10 @@ __global__ __launch_bounds__(256) void k_f64_to_f32(const c64* __restrict__ in, 
         out[i] = c32{(float)in[i].re, (float)in[i].im};
 }
 
-// out_b = in_b / sqrt(nrm2[b * cstride]) rounded to FP32 (the product in FP64, so
-// an FP32 input gives the same bits as its exact FP64 copy), field b of n
-// entries at b * n; blockIdx.y = field. With flag non-null, bit 1 of *flag is
-// set if an input entry is not finite.
-template <typename TI>
-__global__ __launch_bounds__(256) void k_to_f32_scaled(const cpx<TI>* __restrict__ in, c32* __restrict__ out, long n,
+// out_b = in_b / sqrt(nrm2[b * cstride]) rounded to FP32 (the product in FP64),
+// field b of n entries at b * n; blockIdx.y = field. With flag non-null, bit 1
+// of *flag is set if an input entry is not finite.
+__global__ __launch_bounds__(256) void k_to_f32_scaled(const c64* __restrict__ in, c32* __restrict__ out, long n,
                                                        const double* __restrict__ nrm2, int cstride, int* flag)
 {
     const int b = blockIdx.y;
@@ -130,9 +128,9 @@ __global__ __launch_bounds__(256) void k_to_f32_scaled(const cpx<TI>* __restrict
     out += (long)b * n;
     bool bad = false;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const cpx<TI> z = in[i];
-        bad |= !isfinite((double)z.re) || !isfinite((double)z.im);
-        out[i] = c32{(float)((double)z.re * f), (float)((double)z.im * f)};
+        const c64 z = in[i];
+        bad |= !isfinite(z.re) || !isfinite(z.im);
+        out[i] = c32{(float)(z.re * f), (float)(z.im * f)};
     }
     if (flag && bad)
         atomicOr(flag, 1);
@@ -179,16 +177,8 @@ void launch_f64_to_f32_scaled(const c64* in, c32* out, long n, int nb, const dou
 {
     if (n > 0 && nb > 0) {
         const long blocks = std::min<long>((n + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_to_f32_scaled<double>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
+        hipLaunchKernelGGL(k_to_f32_scaled, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
                            nrm2, cstride, finite_flag);
-    }
-}
-void launch_f32_scaled(const c32* in, c32* out, long n, int nb, const double* nrm2, int cstride, hipStream_t s)
-{
-    if (n > 0 && nb > 0) {
-        const long blocks = std::min<long>((n + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_to_f32_scaled<float>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, in, out, n,
-                           nrm2, cstride, (int*)nullptr);
     }
 }
 void launch_f32_to_f64(const c32* in, c64* out, long n, hipStream_t s)

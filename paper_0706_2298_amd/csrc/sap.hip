@@ -27,6 +27,24 @@ namespace dfl {
 
 namespace {
 
+// factor of field b's rho when it enters scaled: 1 / sqrt(nrm2[2 b]) (0 for
+// a zero field), 1 without nrm2
+template <typename T> __device__ inline T rho_scale(const double* nrm2, int b)
+{
+    if (!nrm2)
+        return T(1);
+    const double q = nrm2[2 * b];
+    return q > 0.0 ? (T)(1.0 / sqrt(q)) : T(0);
+}
+template <typename T> __device__ inline void scale_spinor(spinor<T>& p, T f)
+{
+#pragma unroll
+    for (int al = 0; al < 4; ++al)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            p.s[al].c[a] = cpx<T>{p.s[al].c[a].re * f, p.s[al].c[a].im * f};
+}
+
 template <typename T> __device__ inline void store_spinor_f64(c64* __restrict__ f, long V, long s, const spinor<T>& p)
 {
     spinor<double> d;
@@ -91,10 +109,12 @@ __device__ inline void full_hops(const Geom& g, const SapGeom& sg, const L& U, c
 
 template <typename T, typename L, bool CLV>
 __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<T>* __restrict__ rho,
-                                             cpx<T>* __restrict__ psi, T diag, int nmr, int colour, int nrhs, int init,
-                                             c64* __restrict__ out64, Clover<T> C)
+                                             const double* __restrict__ rho_nrm2, cpx<T>* __restrict__ psi, T diag,
+                                             int nmr, int colour, int nrhs, int init, c64* __restrict__ out64,
+                                             Clover<T> C)
 {
     // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
+    const T rs = rho_scale<T>(rho_nrm2, blockIdx.x % nrhs);
     rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
     psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
     if (out64)
@@ -155,6 +175,8 @@ __global__ __launch_bounds__(512) void k_sap(Geom g, SapGeom sg, L U, const cpx<
             if (init == 0)
                 clover_add(C, s, self, d);
         spinor<T> b = load_spinor(rho, g.V, s);
+        if (rho_nrm2)
+            scale_spinor(b, rs);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
             r.s[al] = b.s[al] - d.s[al];
@@ -290,8 +312,9 @@ template <typename L> __device__ inline su3<float> expand_lds(const Link2<L>& l,
 // offset from the thread's own address).
 template <typename L, bool B4>
 __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
-                                               c32* __restrict__ psi, float diag, int nmr, int colour, int nrhs,
-                                               int init, c64* __restrict__ out64)
+                                               const double* __restrict__ rho_nrm2, c32* __restrict__ psi,
+                                               float diag, int nmr, int colour, int nrhs, int init,
+                                               c64* __restrict__ out64)
 {
     const int Vsb = B4 ? 256 : sg.Vsb;
     int sbl[4], lst[4];
@@ -301,6 +324,7 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
         lst[mu] = B4 ? (64 >> (2 * mu)) : sg.lstr[mu];
     }
     // workgroup -> (block of this colour, right-hand side), right-hand sides fastest
+    const float rs = rho_scale<float>(rho_nrm2, blockIdx.x % nrhs);
     rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
     psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
     if (out64)
@@ -378,6 +402,8 @@ __global__ __launch_bounds__(256, 2) void k_sap_rl(Geom g, SapGeom sg, L U, cons
             self = load_spinor(psi, g.V, s);
         spinor<float> d = finish(self, acc, diag);
         spinor<float> b = load_spinor(rho, g.V, s);
+        if (rho_nrm2)
+            scale_spinor(b, rs);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
             r.s[al] = b.s[al] - d.s[al];
@@ -566,9 +592,11 @@ template <typename L> __device__ inline su3<float> pair_link(const L& U, int mu,
 
 template <typename L>
 __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, const c32* __restrict__ rho,
-                                                     c32* __restrict__ psi, float diag, int nmr, int colour,
-                                                     int nrhs, int init, c64* __restrict__ out64)
+                                                     const double* __restrict__ rho_nrm2, c32* __restrict__ psi,
+                                                     float diag, int nmr, int colour, int nrhs, int init,
+                                                     c64* __restrict__ out64)
 {
+    const float rs = rho_scale<float>(rho_nrm2, blockIdx.x % nrhs);
     rho += (long)(blockIdx.x % nrhs) * 12 * g.V;
     psi += (long)(blockIdx.x % nrhs) * 12 * g.V;
     if (out64)
@@ -654,7 +682,9 @@ __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, co
             c32 self = c32{0.0f, 0.0f};
             if (init == 0)
                 self = ld(psi, toff<c32>(s, c0 + i, 12));
-            const c32 b = ld(rho, toff<c32>(s, c0 + i, 12));
+            c32 b = ld(rho, toff<c32>(s, c0 + i, 12));
+            if (rho_nrm2)
+                b = c32{b.re * rs, b.im * rs};
             r[i] = c32{b.re - (diag * self.re - 0.5f * ao.re), b.im - (diag * self.im - 0.5f * ao.im)};
         }
     }
@@ -742,8 +772,8 @@ __global__ __launch_bounds__(512, 1) void k_sap_pair(Geom g, SapGeom sg, L U, co
 }
 
 template <typename T, typename L>
-void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            int nrhs, int init, c64* out64, hipStream_t s, const cpx<T>* clov);
+void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, const double* rho_nrm2, cpx<T>* psi, T m0,
+            int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s, const cpx<T>* clov);
 
 // Blocks of up to 256 sites: links in registers. One field on lattices whose
 // colours hold few blocks per CU (sg.one_rl == 0): lane pairs, one block per
@@ -755,18 +785,18 @@ void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* ps
 // 64 x 32^3: 346 against 475 us per sweep with lane pairs).
 // Larger blocks, the clover term and antiperiodic time: the generic kernel.
 template <typename L>
-void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, float m0, int nmr, int colour,
-               int nrhs, int init, c64* out64, hipStream_t s, const c32* clov)
+void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, const double* rho_nrm2, c32* psi, float m0,
+               int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s, const c32* clov)
 {
     if (sg.Vsb > 256 || clov || g.tsign < 0) {
-        launch<float, L>(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
+        launch<float, L>(g, sg, U, rho, rho_nrm2, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
         return;
     }
     size_t lds = (size_t)12 * sg.Vsb * sizeof(c32);
     if (nrhs == 1 && !sg.one_rl) {
         int threads = ((2 * sg.Vsb + 63) / 64) * 64;
-        hipLaunchKernelGGL((k_sap_pair<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho, psi,
-                           4.0f + m0, nmr, colour, nrhs, init, out64);
+        hipLaunchKernelGGL((k_sap_pair<L>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho,
+                           rho_nrm2, psi, 4.0f + m0, nmr, colour, nrhs, init, out64);
         return;
     }
     int threads = ((sg.Vsb + 63) / 64) * 64;
@@ -777,17 +807,17 @@ void launch_rl(const Geom& g, const SapGeom& sg, L U, const c32* rho, c32* psi, 
     if (b4) {
         set_max_lds_once(attr4, reinterpret_cast<const void*>(&k_sap_rl<L, true>), 80 * 1024);
         hipLaunchKernelGGL((k_sap_rl<L, true>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds_rl, s, g, sg, U,
-                           rho, psi, 4.0f + m0, nmr, colour, nrhs, init, out64);
+                           rho, rho_nrm2, psi, 4.0f + m0, nmr, colour, nrhs, init, out64);
     } else {
         set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap_rl<L, false>), 80 * 1024);
         hipLaunchKernelGGL((k_sap_rl<L, false>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds_rl, s, g, sg, U,
-                           rho, psi, 4.0f + m0, nmr, colour, nrhs, init, out64);
+                           rho, rho_nrm2, psi, 4.0f + m0, nmr, colour, nrhs, init, out64);
     }
 }
 
 template <typename T, typename L>
-void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* psi, T m0, int nmr, int colour,
-            int nrhs, int init, c64* out64, hipStream_t s, const cpx<T>* clov)
+void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, const double* rho_nrm2, cpx<T>* psi, T m0,
+            int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s, const cpx<T>* clov)
 {
     int threads = ((sg.Vsb + 63) / 64) * 64;
     size_t lds = (size_t)12 * sg.Vsb * sizeof(cpx<T>);
@@ -796,12 +826,12 @@ void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* ps
         static std::once_flag attr;  // one per kernel instantiation
         set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap<T, L, true>), 160 * 1024 - 1024);
         hipLaunchKernelGGL((k_sap<T, L, true>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho,
-                           psi, T(4) + m0, nmr, colour, nrhs, init, out64, C);
+                           rho_nrm2, psi, T(4) + m0, nmr, colour, nrhs, init, out64, C);
     } else {
         static std::once_flag attr;
         set_max_lds_once(attr, reinterpret_cast<const void*>(&k_sap<T, L, false>), 160 * 1024 - 1024);
         hipLaunchKernelGGL((k_sap<T, L, false>), dim3(sg.n_per_colour * nrhs), dim3(threads), lds, s, g, sg, U, rho,
-                           psi, T(4) + m0, nmr, colour, nrhs, init, out64, C);
+                           rho_nrm2, psi, T(4) + m0, nmr, colour, nrhs, init, out64, C);
     }
 }
 
@@ -810,17 +840,19 @@ void launch(const Geom& g, const SapGeom& sg, L U, const cpx<T>* rho, cpx<T>* ps
 void launch_sap_colour64(const Geom& g, const SapGeom& sg, Links64 U, const c64* rho, c64* psi, double m0, int nmr,
                          int colour, int nrhs, int init, hipStream_t s, const c64* clov)
 {
-    launch(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, (c64*)nullptr, s, clov);
+    launch(g, sg, U, rho, (const double*)nullptr, psi, m0, nmr, colour, nrhs, init, (c64*)nullptr, s, clov);
 }
 void launch_sap_colour32(const Geom& g, const SapGeom& sg, Links32 U, const c32* rho, c32* psi, float m0, int nmr,
-                         int colour, int nrhs, int init, c64* out64, hipStream_t s, const c32* clov)
+                         int colour, int nrhs, int init, c64* out64, hipStream_t s, const c32* clov,
+                         const double* rho_nrm2)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
+    launch_rl(g, sg, U, rho, rho_nrm2, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
 }
 void launch_sap_colour_bf16(const Geom& g, const SapGeom& sg, LinksBF16 U, const c32* rho, c32* psi, float m0,
-                            int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s, const c32* clov)
+                            int nmr, int colour, int nrhs, int init, c64* out64, hipStream_t s, const c32* clov,
+                            const double* rho_nrm2)
 {
-    launch_rl(g, sg, U, rho, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
+    launch_rl(g, sg, U, rho, rho_nrm2, psi, m0, nmr, colour, nrhs, init, out64, s, clov);
 }
 
 }  // namespace dfl
