@@ -316,50 +316,52 @@ __global__ __launch_bounds__(kBT) void k_block_gs(Geom g, c64* __restrict__ F, i
     }
 }
 
-// The same modified Gram-Schmidt with the fields taken in pairs (l, l + 1),
-// NT threads of E entries each:
-// both are held in registers and projected against each earlier basis field
-// in one pass (one load of that field and one reduction of both products
-// for two projections), then l + 1 against the new l. Each field sees the
-// same sequence of projections as in k_block_gs; the product of l + 1 with
-// the new l is summed with the norm of l, before l is scaled (the results
-// agree up to that rounding).
-template <int E, int NT>
-__global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
+// The same modified Gram-Schmidt with the fields taken G at a time, NT
+// threads of E entries each: the G fields of a group are held in registers
+// and projected against each earlier basis field in one pass (one load of
+// that field and one workgroup sum of the G products), then against each
+// other in order. Each field sees the same sequence of projections as in
+// k_block_gs; the products of field l with the later fields of its group are
+// summed with the norm of l, before l is scaled (the results agree up to that
+// rounding). Every earlier basis field is read once per group.
+constexpr int kGsGroup = 4;  // fields per group of k_block_gsg on blocks of up to 512 sites
+template <int E, int NT, int G>
+__global__ __launch_bounds__(NT) void k_block_gsg(Geom g, c64* __restrict__ F, int Ns, double rank_tol,
                                                    int* __restrict__ flag, c64* __restrict__ R, c64* __restrict__ FT,
                                                    c32* __restrict__ F32)
 {
-    __shared__ double2 sh[2][2][NT / 64];
+    __shared__ double2 sh[2][G][NT / 64];
     const int blk = blockIdx.x;
     const long fs = 12 * g.V;
     const int ne = 12 * g.Vb;
     const bool b4 = g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && g.b[3] == 4;
-    // sums over the workgroup of two complex values at once (as two
-    // block_sum2). Consecutive sums use alternate LDS slots, so one barrier
-    // each suffices: a slot is written again only after the barrier of the
-    // next sum, which every thread passes after reading it.
+    // workgroup sums of the first nv (<= G) complex values of v, the same in
+    // every thread afterwards. Consecutive sums use alternate LDS slots, so
+    // one barrier each suffices: a slot is written again only after the
+    // barrier of the next sum, which every thread passes after reading it.
     int par = 0;
-    auto sum2x2 = [&](double2& a, double2& b) {
-        a.x = wave_sum(a.x);
-        a.y = wave_sum(a.y);
-        b.x = wave_sum(b.x);
-        b.y = wave_sum(b.y);
+    auto sumN = [&](double2* v, int nv) {
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        if (lane == 0) {
-            sh[par][0][wid] = a;
-            sh[par][1][wid] = b;
-        }
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if (q < nv) {
+                v[q].x = wave_sum(v[q].x);
+                v[q].y = wave_sum(v[q].y);
+                if (lane == 0)
+                    sh[par][q][wid] = v[q];
+            }
         __syncthreads();
-        double2 ta = make_double2(0.0, 0.0), tb = make_double2(0.0, 0.0);
-        for (int q = 0; q < nw; ++q) {
-            ta.x += sh[par][0][q].x;
-            ta.y += sh[par][0][q].y;
-            tb.x += sh[par][1][q].x;
-            tb.y += sh[par][1][q].y;
-        }
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if (q < nv) {
+                double2 t = make_double2(0.0, 0.0);
+                for (int w = 0; w < nw; ++w) {
+                    t.x += sh[par][q][w].x;
+                    t.y += sh[par][q][w].y;
+                }
+                v[q] = t;
+            }
         par ^= 1;
-        a = ta;
-        b = tb;
     };
     auto load_field = [&](int k, c64* w) {
         const c64* fk = F + (long)k * fs;
@@ -416,79 +418,103 @@ __global__ __launch_bounds__(NT) void k_block_gs2(Geom g, c64* __restrict__ F, i
         }
         return inv;
     };
-    for (int l = 0; l < Ns; l += 2) {
-        const bool two = l + 1 < Ns;
-        c64 va[E], vb[E];
-        load_field(l, va);
-        if (two)
-            load_field(l + 1, vb);
-        else
+    for (int l0 = 0; l0 < Ns; l0 += G) {
+        const int cnt = min(G, Ns - l0);
+        c64 v[G][E];
+        double2 s[G];
+#pragma unroll
+        for (int f = 0; f < G; ++f) {
+            if (f < cnt)
+                load_field(l0 + f, v[f]);
+            else
+#pragma unroll
+                for (int j = 0; j < E; ++j)
+                    v[f][j] = c64{0.0, 0.0};
+        }
+        // input norms (the reference of the rank test)
+#pragma unroll
+        for (int f = 0; f < G; ++f) {
+            s[f] = make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < E; ++j)
-                vb[j] = c64{0.0, 0.0};
-        double2 na = make_double2(0.0, 0.0), nb = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            na.x += va[j].re * va[j].re + va[j].im * va[j].im;
-            nb.x += vb[j].re * vb[j].re + vb[j].im * vb[j].im;
+                s[f].x += v[f][j].re * v[f][j].re + v[f][j].im * v[f][j].im;
         }
-        sum2x2(na, nb);
+        sumN(s, G);
+        double n0[G];
+#pragma unroll
+        for (int f = 0; f < G; ++f)
+            n0[f] = s[f].x;
+        // against the earlier basis fields, the next one's load issued ahead
         c64 un[E];
-        if (l > 0)
+        if (l0 > 0)
             load_field(0, un);
-        for (int k = 0; k < l; ++k) {
+        for (int k = 0; k < l0; ++k) {
             c64 u[E];
 #pragma unroll
             for (int j = 0; j < E; ++j)
                 u[j] = un[j];
-            if (k + 1 < l)
+            if (k + 1 < l0)
                 load_field(k + 1, un);
-            double2 da = make_double2(0.0, 0.0), db = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int j = 0; j < E; ++j) {
-                da.x += u[j].re * va[j].re + u[j].im * va[j].im;
-                da.y += u[j].re * va[j].im - u[j].im * va[j].re;
-                db.x += u[j].re * vb[j].re + u[j].im * vb[j].im;
-                db.y += u[j].re * vb[j].im - u[j].im * vb[j].re;
+            for (int f = 0; f < G; ++f) {
+                s[f] = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    s[f].x += u[j].re * v[f][j].re + u[j].im * v[f][j].im;
+                    s[f].y += u[j].re * v[f][j].im - u[j].im * v[f][j].re;
+                }
             }
-            sum2x2(da, db);
-            const c64 ca{da.x, da.y}, cb{db.x, db.y};
+            sumN(s, G);
             if (R && threadIdx.x == 0) {
-                R[((long)blk * Ns + k) * Ns + l] = ca;
-                if (two)
-                    R[((long)blk * Ns + k) * Ns + l + 1] = cb;
+#pragma unroll
+                for (int f = 0; f < G; ++f)
+                    if (f < cnt)
+                        R[((long)blk * Ns + k) * Ns + l0 + f] = c64{s[f].x, s[f].y};
             }
 #pragma unroll
-            for (int j = 0; j < E; ++j) {
-                va[j] -= ca * u[j];
-                vb[j] -= cb * u[j];
+            for (int f = 0; f < G; ++f) {
+                const c64 c{s[f].x, s[f].y};
+#pragma unroll
+                for (int j = 0; j < E; ++j)
+                    v[f][j] -= c * u[j];
             }
         }
-        // field l is complete: its norm and, in the same sum, its product
-        // with field l + 1, which then continues against the normalised l:
-        // (v_l / |v_l|, v_{l+1}) = (v_l, v_{l+1}) / |v_l|
-        double2 nva = make_double2(0.0, 0.0), d = make_double2(0.0, 0.0);
+        // within the group, in order: the norm of field f and its products
+        // with the later fields in one sum, then f is scaled and stored and
+        // the later fields continue against it
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
-            nva.x += va[j].re * va[j].re + va[j].im * va[j].im;
-            d.x += va[j].re * vb[j].re + va[j].im * vb[j].im;
-            d.y += va[j].re * vb[j].im - va[j].im * vb[j].re;
-        }
-        sum2x2(nva, d);
-        const double inv_a = finish(l, va, na.x, nva.x);
-        if (!two)
-            break;
-        const c64 c{d.x * inv_a, d.y * inv_a};
-        if (R && threadIdx.x == 0)
-            R[((long)blk * Ns + l) * Ns + l + 1] = c;
-        double2 nvb = make_double2(0.0, 0.0), dummy = make_double2(0.0, 0.0);
+        for (int f = 0; f < G; ++f) {
+            if (f >= cnt)
+                break;
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
-            vb[j] -= c * va[j];
-            nvb.x += vb[j].re * vb[j].re + vb[j].im * vb[j].im;
+            for (int h = 0; h < G; ++h) {
+                s[h] = make_double2(0.0, 0.0);
+                if (h == 0) {
+#pragma unroll
+                    for (int j = 0; j < E; ++j)
+                        s[0].x += v[f][j].re * v[f][j].re + v[f][j].im * v[f][j].im;
+                } else if (f + h < G) {
+#pragma unroll
+                    for (int j = 0; j < E; ++j) {
+                        s[h].x += v[f][j].re * v[f + h][j].re + v[f][j].im * v[f + h][j].im;
+                        s[h].y += v[f][j].re * v[f + h][j].im - v[f][j].im * v[f + h][j].re;
+                    }
+                }
+            }
+            sumN(s, cnt - f);
+            const double inv = finish(l0 + f, v[f], n0[f], s[0].x);
+#pragma unroll
+            for (int h = 1; h < G; ++h) {
+                if (f + h < cnt) {
+                    const c64 c{s[h].x * inv, s[h].y * inv};
+                    if (R && threadIdx.x == 0)
+                        R[((long)blk * Ns + l0 + f) * Ns + l0 + f + h] = c;
+#pragma unroll
+                    for (int j = 0; j < E; ++j)
+                        v[f + h][j] -= c * v[f][j];
+                }
+            }
         }
-        sum2x2(nvb, dummy);
-        finish(l + 1, vb, nb.x, nvb.x);
     }
 }
 
@@ -1322,12 +1348,13 @@ bool launch_block_gs64(const Geom& g, c64* F, int Ns, double rank_tol, int* flag
     const int e = (12 * (int)g.Vb + kBT - 1) / kBT;  // entries per thread
     if (e <= 6)
         hipLaunchKernelGGL(k_block_gs<6>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
-    else if (e <= 12 && g.Vb % kTile == 0) {  // two fields at a time, 512 threads: six entries of each per thread
-        hipLaunchKernelGGL((k_block_gs2<6, 512>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R, FT, F32);
+    else if (e <= 12 && g.Vb % kTile == 0) {  // kGsGroup fields at a time, 512 threads: six entries of each per thread
+        hipLaunchKernelGGL((k_block_gsg<6, 512, kGsGroup>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R,
+                           FT, F32);
         return true;
     } else if (e <= 12)
-        hipLaunchKernelGGL((k_block_gs2<6, 512>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R, nullptr,
-                           nullptr);
+        hipLaunchKernelGGL((k_block_gsg<6, 512, kGsGroup>), dim3(g.Nb), dim3(512), 0, s, g, F, Ns, rank_tol, flag, R,
+                           nullptr, nullptr);
     else if (e <= 24)
         hipLaunchKernelGGL(k_block_gs<24>, dim3(g.Nb), dim3(kBT), 0, s, g, F, Ns, rank_tol, flag, R);
     else
