@@ -824,6 +824,7 @@ __global__ __launch_bounds__(256) void k_little_columns_rt(Geom g, const c64* __
 // partial-sum layout as above with nc = Ns.
 using f64x4 = __attribute__((ext_vector_type(4))) double;
 constexpr int kMfCE = 64;       // entries per stage
+constexpr int kColsMinGrid = 2048;  // workgroups of a launch below which a block's entries are split
 constexpr int kMfRow = kMfCE + 1;  // staged row stride (entries)
 
 template <int RT, int CT, bool TL>
@@ -1446,13 +1447,14 @@ void launch_little_columns64_all(const Geom& g, const c64* Phi, int Ns, const c6
     const int fy = d == 0 ? 0 : ((d & 1) ? g.b[fmu] - 1 : 0);
     const int nface = fmu < 0 ? g.Vb : g.Vb / g.b[fmu];
     const int ne = 12 * nface;
-    int nsplit = ne / (8 * kCE);
-    if (nsplit > 8)
-        nsplit = 8;
+    // the entries of a block split over workgroups only when the blocks alone
+    // give fewer than about eight workgroups per CU (on 64x32^3 one workgroup
+    // per block and direction was 2 ms per setup faster than three or five
+    // splits), each split at least four staged tiles
+    int nsplit = (kColsMinGrid + g.Nb - 1) / g.Nb;
+    nsplit = std::min({nsplit, 8, std::max(1, ne / (4 * kMfCE))});
     while (nsplit > 1 && (long)nsplit * g.Nb * Ns * Ns > part_cap)
         --nsplit;
-    if (nsplit < 1)
-        nsplit = 1;
     const int RT = (Ns + 7) / 8;  // CT = (Ns + 15) / 16 follows from RT
 #define COLS_MFMA(R, C)                                                                                          \
     (transposed ? launch_columns_mfma<R, C, true>(g, Phi, Ns, Y1, n1, Y2, nsplit, fmu, fy, nface, part, s)      \
